@@ -1,0 +1,171 @@
+/*
+ * pcdn.h -- C ABI of the MI355X (gfx950) PCDN library.
+ *
+ * Parallel Coordinate Descent Newton (Bian, Li, Liu, Yang, arXiv:1306.4080)
+ * for L1-regularised loss minimisation (Sec. 2, eq. (1)):
+ *
+ *     min_w  F(w) = C * sum_{i<n} phi(w; x_i, y_i) + ||w||_1,   w in R^p,
+ *
+ * with the logistic loss phi = log(1 + exp(-y w^T x)) (eq. (2)) or the L2 hinge
+ * loss phi = max(0, 1 - y w^T x)^2 (eq. (3)).  The paper writes s samples and
+ * n features; this interface writes n samples and p features.
+ *
+ * Conventions shared by every entry point:
+ *  - Return codes: PCDN_OK (0) on success, PCDN_NOT_CONVERGED (1) when a solve
+ *    stopped at max_outer, a negative PCDN_E_* code on error.  After an error
+ *    pcdn_last_error() describes it; the context stays usable unless the code
+ *    is PCDN_E_DEVICE.
+ *  - No exception crosses the ABI.  A context is not thread-safe: use one per
+ *    host thread.  All work runs on the context's HIP stream; every entry point
+ *    that returns host data synchronises that stream before returning.
+ *  - Host arrays are borrowed for the duration of the call only.  The library
+ *    owns every device buffer it allocates and frees them in pcdn_destroy().
+ *  - Layouts: X is compressed sparse column (CSC).  Column j holds rows
+ *    row_idx[col_ptr[j] .. col_ptr[j+1]) in strictly increasing order with
+ *    values val[...]; labels y[i] are +1 or -1.
+ */
+#ifndef PCDN_H
+#define PCDN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcdn_ctx pcdn_ctx;
+
+/* Loss selector: eq. (2) or eq. (3). */
+typedef enum { PCDN_LOSS_LOGISTIC = 0, PCDN_LOSS_L2SVM = 1 } pcdn_loss;
+
+enum {
+  PCDN_OK = 0,
+  PCDN_NOT_CONVERGED = 1,
+  PCDN_E_ARG = -1,     /* invalid argument (sizes, C, P, eps, loss, bundle) */
+  PCDN_E_CSC = -2,     /* malformed CSC, non-finite value or label not +-1  */
+  PCDN_E_OOM = -3,     /* device allocation failed                          */
+  PCDN_E_DEVICE = -4,  /* HIP runtime error                                 */
+  PCDN_E_STATE = -5,   /* call out of order (no data loaded, no state set)  */
+  PCDN_E_NUMERIC = -6  /* NaN reached the objective                         */
+};
+
+/* Options.  A zero-filled struct (or NULL) selects the paper's settings:
+ * sigma = 0.01, beta = 0.5, gamma = 0 (Sec. 5.1), nu = 1e-12 (Hessian floor,
+ * proof of Lemma 1(b)), max_outer = 1000, max_ls = 30, seed = 0, w0 = 0
+ * (Algorithm 3 starts from zero). */
+typedef struct {
+  uint64_t seed;        /* seeds the per-outer-iteration feature partition  */
+  int32_t max_outer;    /* outer iterations at most (0: 1000)               */
+  int32_t max_ls;       /* backtracking steps q = 0..max_ls-1 (0: 30; <=32) */
+  double sigma;         /* Armijo sigma in (0,1) (0: 0.01)                  */
+  double beta;          /* backtracking factor in (0,1) (0: 0.5)            */
+  double gamma;         /* Delta's Hessian weight in [0,1) (0 is valid)     */
+  double nu;            /* floor added to a Hessian entry <= 0 (0: 1e-12)   */
+  const double* w0;     /* host, p entries, warm start; NULL: zeros         */
+} pcdn_opts;
+
+/* Per-solve report. */
+typedef struct {
+  int32_t outer_iters;  /* outer iterations run                             */
+  int32_t converged;    /* 1 if the stopping rule held                      */
+  int64_t bundles;      /* inner iterations (bundles) run                   */
+  int64_t ls_steps;     /* line-search candidates tested, q+1 per bundle    */
+  int64_t ls_fail;      /* bundles whose search found no step (w unchanged) */
+  int64_t nnz_swept;    /* sum over bundles of the bundle's nonzeros        */
+  double objective;     /* F(w) at exit, from the retained quantities       */
+  double subgrad;       /* ||grad^S F(w)||_1 at exit                        */
+  double subgrad0;      /* ||grad^S F(0)||_1, the stopping reference        */
+  double alg_bytes;     /* algorithmic HBM bytes of the kernels run         */
+  double seconds;       /* wall time of the solve (stream-synchronised)     */
+} pcdn_info;
+
+/* Per-inner-iteration report of pcdn_step(). */
+typedef struct {
+  double alpha;   /* accepted step beta^q, 0 when no q < max_ls passed      */
+  double delta;   /* Delta of the Armijo rule (eq. (7))                     */
+  double dF;      /* F(w + alpha d) - F(w) from retained quantities, eq. (10) */
+  int32_t q;      /* accepted backtracking index, -1 if none                */
+  int32_t pad;
+} pcdn_step_info;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * run on (borrowed; it must outlive the context) or NULL for a stream the
+ * library creates.  *out receives the context, or NULL on error. */
+int pcdn_create(pcdn_ctx** out, int device, void* hip_stream);
+
+/* Load (copy) the design matrix and labels, replacing any previous data.
+ * n, p >= 1 and < 2^31; nnz >= 0.  ptr_kind 0: the four arrays are host
+ * pointers; 1: device pointers on the context's device.  The CSC is validated
+ * (col_ptr[0] = 0, non-decreasing, col_ptr[p] = nnz, rows in range and
+ * strictly increasing per column, finite values, y in {-1,+1}); on failure
+ * nothing is replaced and PCDN_E_CSC is returned. */
+int pcdn_load_csc(pcdn_ctx* ctx, int64_t n, int64_t p, int64_t nnz,
+                  const int64_t* col_ptr, const int32_t* row_idx,
+                  const float* val, const int8_t* y, int ptr_kind);
+
+/* Algorithm 3 (PCDN) with Algorithm 4's line search on the loaded data:
+ * for outer iteration k the features are split by a seeded uniform random
+ * permutation into ceil(p/P) bundles of P (the last may be smaller), each
+ * bundle takes one P-dimensional approximate Newton step with Armijo
+ * backtracking.  Stops after the outer iteration at which
+ * ||grad^S F(w)||_1 <= eps * ||grad^S F(0)||_1 (the paper fixes only that its
+ * rule resembles newGLMNET's outer test) or at max_outer.  C > 0,
+ * 1 <= P <= p, eps >= 0.  w_out (host, p doubles, nullable) receives w;
+ * info (nullable) the report.  Returns PCDN_OK or PCDN_NOT_CONVERGED.  The
+ * final state stays on the device for pcdn_get_w() and pcdn_step(). */
+int pcdn_solve(pcdn_ctx* ctx, double C, int64_t P, double eps, int loss,
+               const pcdn_opts* opts, double* w_out, pcdn_info* info);
+
+/* Set the device state to (loss, C, w): w (host, p doubles) or zeros if NULL;
+ * the retained e^{w^T x_i} (logistic) or b_i = 1 - y_i w^T x_i (SVM) are
+ * recomputed from w in FP64 (Sec. 3.1). */
+int pcdn_reset(pcdn_ctx* ctx, int loss, double C, const double* w);
+
+/* One inner iteration of Algorithm 3 on an explicit bundle (host array of P
+ * distinct feature indices in [0, p)), from the current device state; updates
+ * w and the retained quantities.  opts supplies sigma, beta, gamma, nu and
+ * max_ls (NULL: defaults).  Optional host outputs (NULL to skip): g, h, d
+ * (P doubles each, bundle order): gradient, Hessian diagonal (eq. (11); SVM:
+ * generalised Hessian) and the direction (eq. (5)); dtx (n doubles): d^T x_i
+ * before any backtracking scaling. */
+int pcdn_step(pcdn_ctx* ctx, const int32_t* bundle, int64_t P, const pcdn_opts* opts,
+              pcdn_step_info* out, double* g, double* h, double* d, double* dtx);
+
+/* The feature permutation of outer iteration k for `seed` (host, p int32):
+ * features sorted by the upper 32 bits of output j of the SplitMix64 stream
+ * whose seed is output k of the SplitMix64 stream seeded with `seed`, ties by
+ * index.  Bundle t of that iteration is perm[tP, min((t+1)P, p)). */
+int pcdn_permutation(pcdn_ctx* ctx, uint64_t seed, int64_t k, int32_t* perm_out);
+
+/* Copy the current w (host, p doubles). */
+int pcdn_get_w(pcdn_ctx* ctx, double* w_out);
+
+/* Copy the retained per-sample quantities (host, n doubles). */
+int pcdn_get_cache(pcdn_ctx* ctx, double* cache_out);
+
+/* F(w) (eq. (1)) and ||grad^S F(w)||_1 at the current state (either pointer
+ * may be NULL). */
+int pcdn_evaluate(pcdn_ctx* ctx, double* objective, double* subgrad);
+
+/* Kernel timing.  pcdn_profile(ctx, 1) brackets every launch of the bundle
+ * sweep kernels with HIP events on the context's stream; pcdn_profile_read()
+ * returns, for kernel class `which` (0: gradient/direction sweep, 1: d^T x
+ * scatter of split columns, 2: line search, 3: apply, 4: stopping sweep), the
+ * summed event time in ms, the launch count and the algorithmic bytes those
+ * launches moved, accumulated since the last pcdn_profile(ctx, 1). */
+int pcdn_profile(pcdn_ctx* ctx, int enable);
+int pcdn_profile_read(pcdn_ctx* ctx, int which, double* ms, int64_t* launches,
+                      double* alg_bytes);
+
+/* Description of the last error on ctx (or of a failed pcdn_create when ctx
+ * is NULL); valid until the next call on ctx. */
+const char* pcdn_last_error(const pcdn_ctx* ctx);
+
+/* Release the context and its device memory.  NULL is accepted. */
+int pcdn_destroy(pcdn_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCDN_H */

@@ -1,0 +1,290 @@
+"""ctypes binding of ``libpcdn.so`` (declared in ``include/pcdn.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+There is no fallback: if the library is missing or does not load, every entry
+point raises.  The functions carry the C names; ``Solver`` is a small owner of
+one context.
+
+Device arrays may be passed as torch tensors (their ``data_ptr()`` is handed
+over with ``ptr_kind = 1``); host arrays as numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import sys
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcdn.so")
+
+PCDN_LOSS_LOGISTIC = 0
+PCDN_LOSS_L2SVM = 1
+PCDN_OK = 0
+PCDN_NOT_CONVERGED = 1
+ERRORS = {-1: "PCDN_E_ARG", -2: "PCDN_E_CSC", -3: "PCDN_E_OOM", -4: "PCDN_E_DEVICE",
+          -5: "PCDN_E_STATE", -6: "PCDN_E_NUMERIC"}
+LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
+          "svm": PCDN_LOSS_L2SVM, "l2svm": PCDN_LOSS_L2SVM}
+
+# entry points declared in include/pcdn.h
+SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
+           "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
+           "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy")
+
+
+class PcdnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class pcdn_opts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("max_outer", ctypes.c_int32),
+                ("max_ls", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("nu", ctypes.c_double), ("w0", ctypes.c_void_p)]
+
+
+class pcdn_info(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("bundles", ctypes.c_int64), ("ls_steps", ctypes.c_int64),
+                ("ls_fail", ctypes.c_int64), ("nnz_swept", ctypes.c_int64),
+                ("objective", ctypes.c_double), ("subgrad", ctypes.c_double),
+                ("subgrad0", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+class pcdn_step_info(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("delta", ctypes.c_double),
+                ("dF", ctypes.c_double), ("q", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpcdn.so (after torch, if torch is importable, so that one HIP
+    runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"PCDN HIP library not built: {path} is missing "
+                           "(run `python -m paper_1306_4080_amd.build`)")
+    if "torch" not in sys.modules:
+        try:
+            import torch  # noqa: F401  (shares its HIP runtime with the library)
+        except Exception:
+            pass
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                              ctypes.c_uint64, ctypes.c_double)
+    L.pcdn_create.argtypes = [ctypes.POINTER(vp), i32, vp]
+    L.pcdn_load_csc.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i32]
+    L.pcdn_solve.argtypes = [vp, dbl, i64, dbl, i32, ctypes.POINTER(pcdn_opts), vp,
+                             ctypes.POINTER(pcdn_info)]
+    L.pcdn_reset.argtypes = [vp, i32, dbl, vp]
+    L.pcdn_step.argtypes = [vp, vp, i64, ctypes.POINTER(pcdn_opts),
+                            ctypes.POINTER(pcdn_step_info), vp, vp, vp, vp]
+    L.pcdn_permutation.argtypes = [vp, u64, i64, vp]
+    L.pcdn_get_w.argtypes = [vp, vp]
+    L.pcdn_get_cache.argtypes = [vp, vp]
+    L.pcdn_evaluate.argtypes = [vp, vp, vp]
+    L.pcdn_profile.argtypes = [vp, i32]
+    L.pcdn_profile_read.argtypes = [vp, i32, vp, vp, vp]
+    L.pcdn_last_error.argtypes = [vp]
+    L.pcdn_last_error.restype = ctypes.c_char_p
+    L.pcdn_destroy.argtypes = [vp]
+    for s in SYMBOLS:
+        if s != "pcdn_last_error":
+            getattr(L, s).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a) -> int:
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _check(ctx, rc, allow=(PCDN_OK,)):
+    if rc in allow:
+        return rc
+    msg = load_library().pcdn_last_error(ctx)
+    raise PcdnError(rc, msg.decode() if msg else "")
+
+
+def _opts(seed=0, max_outer=0, max_ls=0, sigma=0.0, beta=0.0, gamma=0.0, nu=0.0, w0=None):
+    o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None)
+    keep = None
+    if w0 is not None:
+        keep = np.ascontiguousarray(w0, dtype=np.float64)
+        o.w0 = keep.ctypes.data
+    return o, keep
+
+
+# --------------------------------------------------------------------------
+# entry points with the C names
+# --------------------------------------------------------------------------
+def pcdn_create(device: int = 0, hip_stream: int | None = None):
+    L = load_library()
+    h = ctypes.c_void_p()
+    rc = L.pcdn_create(ctypes.byref(h), int(device), hip_stream)
+    _check(None, rc)
+    return h
+
+
+def pcdn_destroy(ctx) -> None:
+    load_library().pcdn_destroy(ctx)
+
+
+def pcdn_last_error(ctx) -> str:
+    m = load_library().pcdn_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def pcdn_load_csc(ctx, n, p, col_ptr, row_idx, val, y) -> None:
+    """Load X (CSC) and y; numpy arrays (host) or torch CUDA tensors (device)."""
+    on_device = hasattr(col_ptr, "is_cuda") and col_ptr.is_cuda
+    if not on_device:
+        col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.int8)
+    nnz = int(col_ptr[-1])
+    rc = load_library().pcdn_load_csc(ctx, int(n), int(p), nnz, _ptr(col_ptr), _ptr(row_idx),
+                                      _ptr(val), _ptr(y), 1 if on_device else 0)
+    _check(ctx, rc)
+
+
+def pcdn_solve(ctx, C, P, eps, loss, p, **opts):
+    """Returns (status, w, info dict)."""
+    loss = LOSSES.get(loss, loss)
+    o, keep = _opts(**opts)
+    w = np.empty(int(p), dtype=np.float64)
+    info = pcdn_info()
+    rc = load_library().pcdn_solve(ctx, float(C), int(P), float(eps), int(loss),
+                                   ctypes.byref(o), w.ctypes.data, ctypes.byref(info))
+    _check(ctx, rc, (PCDN_OK, PCDN_NOT_CONVERGED))
+    d = {f: getattr(info, f) for f, _ in pcdn_info._fields_}
+    return rc, w, d
+
+
+def pcdn_reset(ctx, loss, C, w=None) -> None:
+    loss = LOSSES.get(loss, loss)
+    keep = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    rc = load_library().pcdn_reset(ctx, int(loss), float(C),
+                                   None if keep is None else keep.ctypes.data)
+    _check(ctx, rc)
+
+
+def pcdn_step(ctx, bundle, n, want=("g", "h", "d", "dtx"), **opts):
+    bundle = np.ascontiguousarray(bundle, dtype=np.int32)
+    P = len(bundle)
+    o, _ = _opts(**opts)
+    out = {k: np.empty(P if k != "dtx" else int(n)) for k in want}
+    si = pcdn_step_info()
+    rc = load_library().pcdn_step(ctx, bundle.ctypes.data, P, ctypes.byref(o), ctypes.byref(si),
+                                  *[(_ptr(out[k]) if k in out else None)
+                                    for k in ("g", "h", "d", "dtx")])
+    _check(ctx, rc)
+    out.update(alpha=si.alpha, delta=si.delta, dF=si.dF, q=si.q)
+    return out
+
+
+def pcdn_permutation(ctx, seed, k, p) -> np.ndarray:
+    out = np.empty(int(p), dtype=np.int32)
+    _check(ctx, load_library().pcdn_permutation(ctx, int(seed), int(k), out.ctypes.data))
+    return out
+
+
+def pcdn_get_w(ctx, p) -> np.ndarray:
+    out = np.empty(int(p))
+    _check(ctx, load_library().pcdn_get_w(ctx, out.ctypes.data))
+    return out
+
+
+def pcdn_get_cache(ctx, n) -> np.ndarray:
+    out = np.empty(int(n))
+    _check(ctx, load_library().pcdn_get_cache(ctx, out.ctypes.data))
+    return out
+
+
+def pcdn_evaluate(ctx):
+    F = ctypes.c_double()
+    G = ctypes.c_double()
+    _check(ctx, load_library().pcdn_evaluate(ctx, ctypes.byref(F), ctypes.byref(G)))
+    return F.value, G.value
+
+
+def pcdn_profile(ctx, enable: bool) -> None:
+    _check(ctx, load_library().pcdn_profile(ctx, 1 if enable else 0))
+
+
+def pcdn_profile_read(ctx, which: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    b = ctypes.c_double()
+    _check(ctx, load_library().pcdn_profile_read(ctx, int(which), ctypes.byref(ms),
+                                                 ctypes.byref(n), ctypes.byref(b)))
+    return ms.value, n.value, b.value
+
+
+# --------------------------------------------------------------------------
+# convenience owner
+# --------------------------------------------------------------------------
+@dataclass
+class Solver:
+    """One library context holding one loaded problem."""
+    device: int = 0
+    hip_stream: int | None = None
+
+    def __post_init__(self):
+        self.ctx = pcdn_create(self.device, self.hip_stream)
+        self.n = self.p = None
+
+    def load(self, n, p, col_ptr, row_idx, val, y):
+        pcdn_load_csc(self.ctx, n, p, col_ptr, row_idx, val, y)
+        self.n, self.p = int(n), int(p)
+        return self
+
+    def load_data(self, d):
+        return self.load(d.n, d.p, d.col_ptr, d.row_idx, d.val, d.y)
+
+    def solve(self, C, P, eps, loss, **opts):
+        return pcdn_solve(self.ctx, C, P, eps, loss, self.p, **opts)
+
+    def reset(self, loss, C, w=None):
+        pcdn_reset(self.ctx, loss, C, w)
+
+    def step(self, bundle, **opts):
+        return pcdn_step(self.ctx, bundle, self.n, **opts)
+
+    def permutation(self, seed, k):
+        return pcdn_permutation(self.ctx, seed, k, self.p)
+
+    def w(self):
+        return pcdn_get_w(self.ctx, self.p)
+
+    def cache(self):
+        return pcdn_get_cache(self.ctx, self.n)
+
+    def evaluate(self):
+        return pcdn_evaluate(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            pcdn_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,863 @@
+// C ABI of the PCDN library: context, data validation and upload, and the host
+// driver of Algorithm 3 (outer loop over random partitions, inner loop over
+// bundles).  All arithmetic of the method runs in the kernels of
+// pcdn_kernels.hip; this file only sizes launches, orders them on the
+// context's stream and reads back scalars.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pcdn.h"
+#include "pcdn_device.h"
+
+using namespace pcdn;
+
+namespace {
+
+constexpr int kProfClasses = 5;  // sweep, split scatter, line search, apply, stopping sweep
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[kProfClasses] = {0, 0, 0, 0, 0};
+  int64_t launches[kProfClasses] = {0, 0, 0, 0, 0};
+};
+
+// Algorithmic bytes per unit (what the method must move; see the design doc's model).
+constexpr double kBytesPerNnzSweep = 17.0;    // row idx 4 + value 4 + retained gather 8 + label 1
+constexpr double kBytesPerSlotSweep = 60.0;   // col_ptr pair 16 + perm 4 + w 8 + g,h,d,dterm 32
+constexpr double kBytesPerNnzScatter = 24.0;  // row idx 4 + value 4 + FP64 read-modify-write 16
+constexpr double kBytesPerRowLs = 17.0;       // d^T x 8 + retained 8 + label 1
+constexpr double kBytesPerSlotLs = 28.0;      // perm 4 + w 8 + d 8 + dterm 8
+constexpr double kBytesPerRowApply = 33.0;    // d^T x 8 + retained RMW 16 + label 1 + clear 8
+constexpr double kBytesPerSlotApply = 28.0;   // perm 4 + d 8 + w RMW 16
+constexpr double kBytesPerNnzStop = 17.0;
+constexpr double kBytesPerFeatStop = 32.0;    // col_ptr pair 16 + w 8 + |grad^S| 8
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct pcdn_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // data
+  int64_t n = 0, p = 0, nnz = 0;
+  bool loaded = false;
+  int64_t* cp = nullptr;
+  int32_t* ri = nullptr;
+  float* v = nullptr;
+  int8_t* y = nullptr;
+
+  // state
+  int loss = -1;
+  double C = 0.0;
+  bool has_state = false;
+  double* w = nullptr;
+  double* cache = nullptr;
+  double* dtx = nullptr;
+  double* tmp_n = nullptr;
+  double* tmp_p = nullptr;
+  double* g = nullptr;
+  double* h = nullptr;
+  double* d = nullptr;
+  double* dterm = nullptr;
+
+  // partition and chunk bookkeeping
+  uint32_t* keys0 = nullptr;
+  uint32_t* keys1 = nullptr;
+  int32_t* idx0 = nullptr;
+  int32_t* idx1 = nullptr;
+  int32_t* hist = nullptr;
+  int32_t* scan_tmp = nullptr;
+  int32_t* nch = nullptr;
+  int32_t* cstart = nullptr;
+  int32_t* chunk_slot = nullptr;
+  int32_t* id_cstart = nullptr;
+  int32_t* id_slot = nullptr;
+  int32_t* step_perm = nullptr;
+  int64_t max_chunks = 0;
+  double2* part = nullptr;
+  unsigned* cnt = nullptr;
+
+  // reductions and small device records
+  double* ls_part = nullptr;
+  unsigned* counters = nullptr;  // [0] line search, [1] sums
+  StepState* st = nullptr;
+  Stats* stats = nullptr;
+  double* scal = nullptr;        // [0] stopping norm, [1] loss sum, [2] l1 sum
+  double* sum_part = nullptr;
+
+  // pinned host mirrors
+  double* hscal = nullptr;
+  Stats* hstats = nullptr;
+  StepState* hst = nullptr;
+
+  Profiler prof;
+  Stats prof_base{};
+};
+
+namespace {
+
+constexpr int kLsGridMax = 1024;
+
+int fail(pcdn_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((ctx), PCDN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define ALLOC(ctx, ptr, count)                                                         \
+  do {                                                                                 \
+    if (dalloc(&(ptr), (size_t)(count)) != hipSuccess) {                               \
+      (void)hipGetLastError();                                                         \
+      return fail((ctx), PCDN_E_OOM, "device allocation failed for " #ptr);            \
+    }                                                                                  \
+  } while (0)
+
+template <class T>
+void dfree(T*& ptr) {
+  if (ptr) (void)hipFree((void*)ptr);
+  ptr = nullptr;
+}
+
+void free_data(pcdn_ctx* c) {
+  dfree(c->cp); dfree(c->ri); dfree(c->v); dfree(c->y);
+  dfree(c->w); dfree(c->cache); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
+  dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
+  dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
+  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunk_slot);
+  dfree(c->id_cstart); dfree(c->id_slot); dfree(c->step_perm);
+  dfree(c->part); dfree(c->cnt); dfree(c->ls_part);
+  c->loaded = false;
+  c->has_state = false;
+  c->n = c->p = c->nnz = 0;
+}
+
+struct Opts {
+  uint64_t seed;
+  int max_outer, max_ls;
+  double sigma, beta, gamma, nu;
+  const double* w0;
+};
+
+int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
+  r->seed = o ? o->seed : 0;
+  r->max_outer = (o && o->max_outer) ? o->max_outer : 1000;
+  r->max_ls = (o && o->max_ls) ? o->max_ls : 30;
+  r->sigma = (o && o->sigma != 0.0) ? o->sigma : 0.01;
+  r->beta = (o && o->beta != 0.0) ? o->beta : 0.5;
+  r->gamma = o ? o->gamma : 0.0;
+  r->nu = (o && o->nu != 0.0) ? o->nu : 1e-12;
+  r->w0 = o ? o->w0 : nullptr;
+  if (r->max_outer < 0) return fail(c, PCDN_E_ARG, "max_outer must be >= 0");
+  if (r->max_ls < 1 || r->max_ls > kQMax) return fail(c, PCDN_E_ARG, "max_ls must lie in [1, 32]");
+  if (!(r->sigma > 0.0 && r->sigma < 1.0)) return fail(c, PCDN_E_ARG, "sigma must lie in (0, 1)");
+  if (!(r->beta > 0.0 && r->beta < 1.0)) return fail(c, PCDN_E_ARG, "beta must lie in (0, 1)");
+  if (!(r->gamma >= 0.0 && r->gamma < 1.0)) return fail(c, PCDN_E_ARG, "gamma must lie in [0, 1)");
+  if (!(r->nu > 0.0) || !std::isfinite(r->nu)) return fail(c, PCDN_E_ARG, "nu must be > 0");
+  return PCDN_OK;
+}
+
+int check_loss(pcdn_ctx* c, int loss) {
+  if (loss != PCDN_LOSS_LOGISTIC && loss != PCDN_LOSS_L2SVM)
+    return fail(c, PCDN_E_ARG, "unknown loss");
+  return PCDN_OK;
+}
+
+// --- profiling -----------------------------------------------------------
+hipEvent_t prof_event(pcdn_ctx* c) {
+  if (!c->prof.pool.empty()) {
+    hipEvent_t e = c->prof.pool.back();
+    c->prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Harvest finished event pairs (the stream has been synchronised).
+void prof_harvest(pcdn_ctx* c) {
+  for (auto& pe : c->prof.pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess)
+      c->prof.ms[pe.first] += ms;
+    c->prof.launches[pe.first] += 1;
+    c->prof.pool.push_back(pe.second.first);
+    c->prof.pool.push_back(pe.second.second);
+  }
+  c->prof.pending.clear();
+}
+
+struct ProfScope {
+  pcdn_ctx* c;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(pcdn_ctx* c_, int cls_) : c(c_), cls(cls_) {
+    if (c->prof.on) {
+      if (c->prof.pending.size() > 8192) {
+        (void)hipStreamSynchronize(c->stream);
+        prof_harvest(c);
+      }
+      a = prof_event(c);
+      b = prof_event(c);
+      if (a) (void)hipEventRecord(a, c->stream);
+    }
+  }
+  ~ProfScope() {
+    if (a && b) {
+      (void)hipEventRecord(b, c->stream);
+      c->prof.pending.push_back({cls, {a, b}});
+    }
+  }
+};
+
+// --- kernel sequences -------------------------------------------------------
+int sweep_grid(int64_t slots) {
+  int64_t g = (slots + kWavesPerBlock - 1) / kWavesPerBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+int row_grid(int64_t items, int cap) {
+  int64_t g = (items + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
+  SweepArgs a{};
+  a.cp = c->cp;
+  a.ri = c->ri;
+  a.v = c->v;
+  a.y = c->y;
+  a.cache = c->cache;
+  a.w = c->w;
+  a.g = c->g;
+  a.h = c->h;
+  a.d = c->d;
+  a.dterm = c->dterm;
+  a.sg = c->tmp_p;
+  a.part = c->part;
+  a.cnt = c->cnt;
+  a.dtx = c->dtx;
+  a.stats = c->stats;
+  a.C = c->C;
+  a.gamma = o.gamma;
+  a.nu = o.nu;
+  return a;
+}
+
+// One inner iteration of Algorithm 3 on slots [lo, hi) of `perm` (whose chunk
+// bookkeeping is in c->cstart / c->chunk_slot).
+int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+  SweepArgs a = sweep_args(c, o);
+  a.perm = perm;
+  a.cstart = c->cstart;
+  a.chunk_slot = c->chunk_slot;
+  a.slot_lo = lo;
+  a.slot_hi = hi;
+  const int64_t Pt = hi - lo;
+  const int sg = sweep_grid(Pt);
+  {
+    ProfScope ps(c, 0);
+    HIPCHK(c, launch_sweep(c->loss, 0, a, sg, c->stream));
+  }
+  {
+    ProfScope ps(c, 1);
+    HIPCHK(c, launch_scatter_split(a, sg, c->stream));
+  }
+  LsArgs l{};
+  l.dtx = c->dtx;
+  l.cache = c->cache;
+  l.y = c->y;
+  l.n = c->n;
+  l.w = c->w;
+  l.perm = perm;
+  l.slot_lo = lo;
+  l.slot_hi = hi;
+  l.d = c->d;
+  l.dterm = c->dterm;
+  l.part = c->ls_part;
+  l.counter = c->counters;
+  l.st = c->st;
+  l.stats = c->stats;
+  l.C = c->C;
+  l.sigma = o.sigma;
+  l.beta = o.beta;
+  l.q0 = 0;
+  l.Q = o.max_ls;
+  l.max_ls = o.max_ls;
+  {
+    ProfScope ps(c, 2);
+    HIPCHK(c, launch_linesearch(c->loss, l, row_grid(std::max(c->n, Pt), kLsGridMax), c->stream));
+  }
+  ApplyArgs ap{};
+  ap.dtx = c->dtx;
+  ap.cache = c->cache;
+  ap.y = c->y;
+  ap.n = c->n;
+  ap.w = c->w;
+  ap.perm = perm;
+  ap.slot_lo = lo;
+  ap.slot_hi = hi;
+  ap.d = c->d;
+  ap.st = c->st;
+  ap.beta = o.beta;
+  {
+    ProfScope ps(c, 3);
+    HIPCHK(c, launch_apply(c->loss, ap, row_grid(std::max(c->n, Pt), 4096), c->stream));
+  }
+  return PCDN_OK;
+}
+
+// ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0).
+int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w) {
+  SweepArgs a = sweep_args(c, o);
+  a.w = w;
+  a.perm = nullptr;
+  a.cstart = c->id_cstart;
+  a.chunk_slot = c->id_slot;
+  a.slot_lo = 0;
+  a.slot_hi = c->p;
+  {
+    ProfScope ps(c, 4);
+    HIPCHK(c, launch_sweep(c->loss, 1, a, sweep_grid(c->p), c->stream));
+  }
+  HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->counters + 1, c->scal, c->stream));
+  return PCDN_OK;
+}
+
+int read_scalar(pcdn_ctx* c, int idx, double* out) {
+  HIPCHK(c, hipMemcpyAsync(c->hscal + idx, c->scal + idx, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->prof.on) prof_harvest(c);
+  *out = c->hscal[idx];
+  return PCDN_OK;
+}
+
+int stopping_norm(pcdn_ctx* c, const Opts& o, const double* w, double* G) {
+  int rc = launch_stopping(c, o, w);
+  if (rc) return rc;
+  return read_scalar(c, 0, G);
+}
+
+int objective(pcdn_ctx* c, double* F) {
+  HIPCHK(c, launch_loss_terms(c->loss, c->cache, c->y, c->n, c->tmp_n, c->stream));
+  HIPCHK(c, launch_sum(c->tmp_n, c->n, c->sum_part, c->counters + 1, c->scal + 1, c->stream));
+  HIPCHK(c, launch_abs(c->w, c->p, c->tmp_p, c->stream));
+  HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->counters + 1, c->scal + 2, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hscal + 1, c->scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *F = c->hscal[2] + c->C * c->hscal[1];
+  return PCDN_OK;
+}
+
+// Retained quantities from w (device): z = X w, then e^z or 1 - y z.
+int cache_from_w(pcdn_ctx* c, bool w_is_zero) {
+  if (w_is_zero) {
+    HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));  // e^0 = 1, b = 1
+    return PCDN_OK;
+  }
+  HIPCHK(c, launch_fill(c->cache, 0.0, c->n, c->stream));
+  HIPCHK(c, launch_margins(c->cp, c->ri, c->v, c->w, c->id_cstart, c->id_slot, c->p, c->cache,
+                           sweep_grid(c->p), c->stream));
+  HIPCHK(c, launch_cache_from_z(c->loss, c->cache, c->y, c->n, c->stream));
+  return PCDN_OK;
+}
+
+int set_w(pcdn_ctx* c, const double* w_host) {
+  if (w_host) {
+    for (int64_t j = 0; j < c->p; ++j)
+      if (!std::isfinite(w_host[j])) return fail(c, PCDN_E_ARG, "w contains a non-finite value");
+    HIPCHK(c, hipMemcpyAsync(c->w, w_host, c->p * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+  } else {
+    HIPCHK(c, launch_fill(c->w, 0.0, c->p, c->stream));
+  }
+  return cache_from_w(c, w_host == nullptr);
+}
+
+int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k) {
+  // stream seed of outer iteration k: output k of the generator seeded with `seed`
+  uint64_t z = seed + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  HIPCHK(c, launch_perm_keys(z, c->p, c->keys0, c->idx0, c->stream));
+  HIPCHK(c, launch_radix_sort(c->keys0, c->idx0, c->keys1, c->idx1, c->p, c->hist, c->scan_tmp,
+                              c->stream));
+  return PCDN_OK;
+}
+
+int read_stats(pcdn_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->hstats, c->stats, sizeof(Stats), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PCDN_OK;
+}
+
+double alg_bytes_of(const Stats& s, const Stats& b, int cls, int64_t p) {
+  const double d_nnz_gh = (double)(s.nnz_gh - b.nnz_gh);
+  const double d_slots = (double)(s.slots - b.slots);
+  const double d_fused = (double)(s.nnz_scat_fused - b.nnz_scat_fused);
+  const double d_split = (double)(s.nnz_scat_split - b.nnz_scat_split);
+  const double d_rows = (double)(s.rows_touched - b.rows_touched);
+  const double d_stop = (double)(s.nnz_stop - b.nnz_stop);
+  const double d_sweeps = (double)(s.stop_sweeps - b.stop_sweeps);
+  switch (cls) {
+    case 0: return kBytesPerNnzSweep * d_nnz_gh + kBytesPerSlotSweep * d_slots +
+                   kBytesPerNnzScatter * d_fused;
+    case 1: return kBytesPerNnzScatter * d_split;
+    case 2: return kBytesPerRowLs * d_rows + kBytesPerSlotLs * d_slots;
+    case 3: return kBytesPerRowApply * d_rows + kBytesPerSlotApply * d_slots;
+    case 4: return kBytesPerNnzStop * d_stop + kBytesPerFeatStop * (double)p * d_sweeps;
+    default: return 0.0;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+static thread_local std::string g_create_error;
+
+extern "C" int pcdn_create(pcdn_ctx** out, int device, void* hip_stream) {
+  if (!out) return PCDN_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    g_create_error = "no HIP device available";
+    return PCDN_E_DEVICE;
+  }
+  if (device < 0 || device >= ndev) {
+    g_create_error = "device index out of range";
+    return PCDN_E_ARG;
+  }
+  pcdn_ctx* c = new (std::nothrow) pcdn_ctx();
+  if (!c) return PCDN_E_OOM;
+  c->device = device;
+  auto bail = [&](int code, const char* msg) {
+    g_create_error = msg;
+    pcdn_destroy(c);
+    return code;
+  };
+  if (hipSetDevice(device) != hipSuccess) return bail(PCDN_E_DEVICE, "hipSetDevice failed");
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(PCDN_E_DEVICE, "hipStreamCreate failed");
+    c->own_stream = true;
+  }
+  if (dalloc(&c->counters, 4) != hipSuccess || dalloc(&c->st, 1) != hipSuccess ||
+      dalloc(&c->stats, 1) != hipSuccess || dalloc(&c->scal, 8) != hipSuccess ||
+      dalloc(&c->sum_part, kSumGrid) != hipSuccess)
+    return bail(PCDN_E_OOM, "device allocation failed");
+  if (hipHostMalloc((void**)&c->hscal, 8 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hstats, sizeof(Stats)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hst, sizeof(StepState)) != hipSuccess)
+    return bail(PCDN_E_OOM, "pinned host allocation failed");
+  if (hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->stats, 0, sizeof(Stats), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(PCDN_E_DEVICE, "initialisation failed");
+  *out = c;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_destroy(pcdn_ctx* c) {
+  if (!c) return PCDN_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_data(c);
+  dfree(c->counters); dfree(c->st); dfree(c->stats); dfree(c->scal); dfree(c->sum_part);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  if (c->hstats) (void)hipHostFree(c->hstats);
+  if (c->hst) (void)hipHostFree(c->hst);
+  for (auto& pe : c->prof.pending) {
+    (void)hipEventDestroy(pe.second.first);
+    (void)hipEventDestroy(pe.second.second);
+  }
+  for (auto e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return PCDN_OK;
+}
+
+extern "C" const char* pcdn_last_error(const pcdn_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
+                             const int64_t* col_ptr, const int32_t* row_idx, const float* val,
+                             const int8_t* y, int ptr_kind) {
+  if (!c) return PCDN_E_ARG;
+  if (n < 1 || p < 1 || n >= (int64_t)1 << 31 || p >= (int64_t)1 << 31 || nnz < 0)
+    return fail(c, PCDN_E_ARG, "sizes out of range (need 1 <= n, p < 2^31, nnz >= 0)");
+  if (!col_ptr || !y || (nnz > 0 && (!row_idx || !val)))
+    return fail(c, PCDN_E_ARG, "null array");
+  if (ptr_kind != 0 && ptr_kind != 1) return fail(c, PCDN_E_ARG, "ptr_kind must be 0 or 1");
+  const int64_t max_chunks = p + (nnz + kChunk - 1) / kChunk + 1;
+  if (max_chunks >= ((int64_t)1 << 31) - 1) return fail(c, PCDN_E_ARG, "matrix too large");
+  HIPCHK(c, hipSetDevice(c->device));
+
+  // host view for validation (device input is copied down once)
+  std::vector<int64_t> hcp;
+  std::vector<int32_t> hri;
+  std::vector<float> hv;
+  std::vector<int8_t> hy;
+  const int64_t* Hcp = col_ptr;
+  const int32_t* Hri = row_idx;
+  const float* Hv = val;
+  const int8_t* Hy = y;
+  if (ptr_kind == 1) {
+    hcp.resize(p + 1);
+    hri.resize(nnz);
+    hv.resize(nnz);
+    hy.resize(n);
+    HIPCHK(c, hipMemcpy(hcp.data(), col_ptr, (p + 1) * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (nnz) {
+      HIPCHK(c, hipMemcpy(hri.data(), row_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(hv.data(), val, nnz * sizeof(float), hipMemcpyDeviceToHost));
+    }
+    HIPCHK(c, hipMemcpy(hy.data(), y, n, hipMemcpyDeviceToHost));
+    Hcp = hcp.data();
+    Hri = hri.data();
+    Hv = hv.data();
+    Hy = hy.data();
+  }
+  if (Hcp[0] != 0 || Hcp[p] != nnz) return fail(c, PCDN_E_CSC, "col_ptr must start at 0 and end at nnz");
+  for (int64_t j = 0; j < p; ++j) {
+    const int64_t lo = Hcp[j], hi = Hcp[j + 1];
+    if (hi < lo) return fail(c, PCDN_E_CSC, "col_ptr is decreasing at column " + std::to_string(j));
+    for (int64_t k = lo; k < hi; ++k) {
+      const int32_t r = Hri[k];
+      if (r < 0 || r >= n) return fail(c, PCDN_E_CSC, "row index out of range in column " + std::to_string(j));
+      if (k > lo && r <= Hri[k - 1])
+        return fail(c, PCDN_E_CSC, "rows not strictly increasing in column " + std::to_string(j));
+      if (!std::isfinite(Hv[k])) return fail(c, PCDN_E_CSC, "non-finite value in column " + std::to_string(j));
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (Hy[i] != 1 && Hy[i] != -1) return fail(c, PCDN_E_CSC, "label not +1/-1 at row " + std::to_string(i));
+
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  free_data(c);
+  c->n = n;
+  c->p = p;
+  c->nnz = nnz;
+  c->max_chunks = max_chunks;
+  const int64_t ntiles = (p + 4095) / 4096;
+  const int64_t hist_m = 256 * ntiles;
+  ALLOC(c, c->cp, p + 1);
+  ALLOC(c, c->ri, nnz);
+  ALLOC(c, c->v, nnz);
+  ALLOC(c, c->y, n);
+  ALLOC(c, c->w, p);
+  ALLOC(c, c->cache, n);
+  ALLOC(c, c->dtx, n);
+  ALLOC(c, c->tmp_n, n);
+  ALLOC(c, c->tmp_p, p);
+  ALLOC(c, c->g, p);
+  ALLOC(c, c->h, p);
+  ALLOC(c, c->d, p);
+  ALLOC(c, c->dterm, p);
+  ALLOC(c, c->keys0, p);
+  ALLOC(c, c->keys1, p);
+  ALLOC(c, c->idx0, p);
+  ALLOC(c, c->idx1, p);
+  ALLOC(c, c->hist, hist_m + 1);
+  ALLOC(c, c->scan_tmp, std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)) + 1);
+  ALLOC(c, c->nch, p);
+  ALLOC(c, c->cstart, p + 1);
+  ALLOC(c, c->chunk_slot, max_chunks);
+  ALLOC(c, c->id_cstart, p + 1);
+  ALLOC(c, c->id_slot, max_chunks);
+  ALLOC(c, c->step_perm, p);
+  ALLOC(c, c->part, max_chunks);
+  ALLOC(c, c->cnt, p);
+  ALLOC(c, c->ls_part, (size_t)kLsGridMax * (2 * kQMax + 1));
+  const hipMemcpyKind kind = ptr_kind == 1 ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIPCHK(c, hipMemcpyAsync(c->cp, col_ptr, (p + 1) * sizeof(int64_t), kind, c->stream));
+  if (nnz) {
+    HIPCHK(c, hipMemcpyAsync(c->ri, row_idx, nnz * sizeof(int32_t), kind, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->v, val, nnz * sizeof(float), kind, c->stream));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->y, y, n, kind, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->dtx, 0, n * sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->cnt, 0, p * sizeof(unsigned), c->stream));
+  HIPCHK(c, launch_chunks(nullptr, c->cp, p, c->nch, c->id_cstart, c->id_slot, c->scan_tmp,
+                          c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->loaded = true;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_reset(pcdn_ctx* c, int loss, double C, const double* w) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
+  int rc = check_loss(c, loss);
+  if (rc) return rc;
+  if (!(C > 0.0) || !std::isfinite(C)) return fail(c, PCDN_E_ARG, "C must be a finite positive number");
+  HIPCHK(c, hipSetDevice(c->device));
+  c->loss = loss;
+  c->C = C;
+  rc = set_w(c, w);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_state = true;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pcdn_opts* opts,
+                         pcdn_step_info* out, double* g, double* h, double* d, double* dtx) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded || !c->has_state) return fail(c, PCDN_E_STATE, "call pcdn_reset or pcdn_solve first");
+  if (!bundle || P < 1 || P > c->p) return fail(c, PCDN_E_ARG, "bundle size must lie in [1, p]");
+  Opts o;
+  int rc = resolve_opts(c, opts, &o);
+  if (rc) return rc;
+  std::vector<unsigned char> seen(c->p, 0);
+  for (int64_t t = 0; t < P; ++t) {
+    const int32_t j = bundle[t];
+    if (j < 0 || j >= c->p) return fail(c, PCDN_E_ARG, "bundle index out of range");
+    if (seen[j]) return fail(c, PCDN_E_ARG, "bundle indices must be distinct");
+    seen[j] = 1;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpyAsync(c->step_perm, bundle, P * sizeof(int32_t), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, c->nch, c->cstart, c->chunk_slot, c->scan_tmp,
+                          c->stream));
+  // run the bundle; keep d^T x before the apply kernel clears it
+  SweepArgs a = sweep_args(c, o);
+  a.perm = c->step_perm;
+  a.cstart = c->cstart;
+  a.chunk_slot = c->chunk_slot;
+  a.slot_lo = 0;
+  a.slot_hi = P;
+  const int sg = sweep_grid(P);
+  HIPCHK(c, launch_sweep(c->loss, 0, a, sg, c->stream));
+  HIPCHK(c, launch_scatter_split(a, sg, c->stream));
+  if (dtx)
+    HIPCHK(c, hipMemcpyAsync(c->tmp_n, c->dtx, c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  LsArgs l{};
+  l.dtx = c->dtx; l.cache = c->cache; l.y = c->y; l.n = c->n; l.w = c->w;
+  l.perm = c->step_perm; l.slot_lo = 0; l.slot_hi = P; l.d = c->d; l.dterm = c->dterm;
+  l.part = c->ls_part; l.counter = c->counters; l.st = c->st; l.stats = c->stats;
+  l.C = c->C; l.sigma = o.sigma; l.beta = o.beta; l.q0 = 0; l.Q = o.max_ls; l.max_ls = o.max_ls;
+  HIPCHK(c, launch_linesearch(c->loss, l, row_grid(std::max(c->n, P), kLsGridMax), c->stream));
+  if (g) HIPCHK(c, hipMemcpyAsync(g, c->g, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (h) HIPCHK(c, hipMemcpyAsync(h, c->h, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (d) HIPCHK(c, hipMemcpyAsync(d, c->d, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  ApplyArgs ap{};
+  ap.dtx = c->dtx; ap.cache = c->cache; ap.y = c->y; ap.n = c->n; ap.w = c->w;
+  ap.perm = c->step_perm; ap.slot_lo = 0; ap.slot_hi = P; ap.d = c->d; ap.st = c->st;
+  ap.beta = o.beta;
+  HIPCHK(c, launch_apply(c->loss, ap, row_grid(std::max(c->n, P), 4096), c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->hst, c->st, sizeof(StepState), hipMemcpyDeviceToHost, c->stream));
+  if (dtx)
+    HIPCHK(c, hipMemcpyAsync(dtx, c->tmp_n, c->n * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (out) {
+    out->alpha = c->hst->alpha;
+    out->delta = c->hst->delta;
+    out->dF = c->hst->dF;
+    out->q = c->hst->q;
+    out->pad = 0;
+  }
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, int32_t* perm_out) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
+  if (!perm_out || k < 0) return fail(c, PCDN_E_ARG, "bad argument");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = device_permutation(c, seed, k);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(perm_out, c->idx0, c->p * sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss,
+                          const pcdn_opts* opts, double* w_out, pcdn_info* info) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
+  int rc = check_loss(c, loss);
+  if (rc) return rc;
+  if (!(C > 0.0) || !std::isfinite(C)) return fail(c, PCDN_E_ARG, "C must be a finite positive number");
+  if (P < 1 || P > c->p) return fail(c, PCDN_E_ARG, "bundle size P must lie in [1, p]");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, PCDN_E_ARG, "eps must be finite and >= 0");
+  Opts o;
+  rc = resolve_opts(c, opts, &o);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  rc = read_stats(c);
+  if (rc) return rc;
+  const Stats base = *c->hstats;
+  c->loss = loss;
+  c->C = C;
+
+  // reference norm at w = 0 (retained quantities all one)
+  HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));
+  double G0 = 0.0, G = 0.0;
+  rc = stopping_norm(c, o, nullptr, &G0);
+  if (rc) return rc;
+  if (!std::isfinite(G0)) return fail(c, PCDN_E_NUMERIC, "non-finite gradient at w = 0");
+  bool converged = false;
+  if (G0 == 0.0) {
+    rc = set_w(c, nullptr);
+    if (rc) return rc;
+    converged = true;
+  } else {
+    rc = set_w(c, o.w0);
+    if (rc) return rc;
+    if (o.w0) {
+      rc = stopping_norm(c, o, c->w, &G);
+      if (rc) return rc;
+    } else {
+      G = G0;
+    }
+    converged = G <= eps * G0;
+  }
+  c->has_state = true;
+  int outer = 0;
+  const int64_t nb = (c->p + P - 1) / P;
+  while (!converged && outer < o.max_outer) {
+    rc = device_permutation(c, o.seed, outer);
+    if (rc) return rc;
+    HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunk_slot, c->scan_tmp,
+                            c->stream));
+    for (int64_t t = 0; t < nb; ++t) {
+      const int64_t lo = t * P, hi = std::min(lo + P, c->p);
+      rc = run_bundle(c, o, c->idx0, lo, hi);
+      if (rc) return rc;
+    }
+    ++outer;
+    rc = stopping_norm(c, o, c->w, &G);
+    if (rc) return rc;
+    if (!std::isfinite(G)) return fail(c, PCDN_E_NUMERIC, "non-finite subgradient norm");
+    converged = G <= eps * G0;
+  }
+  double F = 0.0;
+  rc = objective(c, &F);
+  if (rc) return rc;
+  if (std::isnan(F)) return fail(c, PCDN_E_NUMERIC, "objective is NaN");
+  if (w_out)
+    HIPCHK(c, hipMemcpyAsync(w_out, c->w, c->p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  rc = read_stats(c);
+  if (rc) return rc;
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    const Stats& s = *c->hstats;
+    info->outer_iters = outer;
+    info->converged = converged ? 1 : 0;
+    info->bundles = (int64_t)(s.bundles - base.bundles);
+    info->ls_steps = (int64_t)(s.ls_steps - base.ls_steps);
+    info->ls_fail = (int64_t)(s.ls_fail - base.ls_fail);
+    info->nnz_swept = (int64_t)(s.nnz_gh - base.nnz_gh);
+    info->objective = F;
+    info->subgrad = G0 == 0.0 ? 0.0 : G;
+    info->subgrad0 = G0;
+    double bytes = 0.0;
+    for (int k = 0; k < kProfClasses; ++k) bytes += alg_bytes_of(s, base, k, c->p);
+    info->alg_bytes = bytes;
+    info->seconds = std::chrono::duration<double>(t1 - t0).count();
+  }
+  return converged ? PCDN_OK : PCDN_NOT_CONVERGED;
+}
+
+extern "C" int pcdn_get_w(pcdn_ctx* c, double* w_out) {
+  if (!c || !w_out) return c ? fail(c, PCDN_E_ARG, "null output") : PCDN_E_ARG;
+  if (!c->loaded || !c->has_state) return fail(c, PCDN_E_STATE, "no state");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpyAsync(w_out, c->w, c->p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_get_cache(pcdn_ctx* c, double* out) {
+  if (!c || !out) return c ? fail(c, PCDN_E_ARG, "null output") : PCDN_E_ARG;
+  if (!c->loaded || !c->has_state) return fail(c, PCDN_E_STATE, "no state");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipMemcpyAsync(out, c->cache, c->n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_evaluate(pcdn_ctx* c, double* F, double* G) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded || !c->has_state) return fail(c, PCDN_E_STATE, "no state");
+  HIPCHK(c, hipSetDevice(c->device));
+  Opts o;
+  int rc = resolve_opts(c, nullptr, &o);
+  if (rc) return rc;
+  if (G) {
+    rc = stopping_norm(c, o, c->w, G);
+    if (rc) return rc;
+  }
+  if (F) {
+    rc = objective(c, F);
+    if (rc) return rc;
+  }
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_profile(pcdn_ctx* c, int enable) {
+  if (!c) return PCDN_E_ARG;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_harvest(c);
+  for (int k = 0; k < kProfClasses; ++k) {
+    c->prof.ms[k] = 0.0;
+    c->prof.launches[k] = 0;
+  }
+  c->prof.on = enable != 0;
+  int rc = read_stats(c);
+  if (rc) return rc;
+  c->prof_base = *c->hstats;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_profile_read(pcdn_ctx* c, int which, double* ms, int64_t* launches,
+                                 double* alg_bytes) {
+  if (!c) return PCDN_E_ARG;
+  if (which < 0 || which >= kProfClasses) return fail(c, PCDN_E_ARG, "unknown kernel class");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_harvest(c);
+  int rc = read_stats(c);
+  if (rc) return rc;
+  if (ms) *ms = c->prof.ms[which];
+  if (launches) *launches = c->prof.launches[which];
+  if (alg_bytes) *alg_bytes = alg_bytes_of(*c->hstats, c->prof_base, which, c->p);
+  return PCDN_OK;
+}

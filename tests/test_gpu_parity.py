@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (the build's target): g, h, d, d^T x at 1e-6 relative with the
+absolute floors 1e-6 * C * sum_i |x_ij| for g_j and 1e-6 * max|.| for d and
+d^T x; the accepted step alpha and index q exactly (powers of two); final
+objective at 1e-6 relative.  The permutation is integer work: bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pc():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_4080_amd as pc
+    pc.ensure_built()
+    return pc
+
+
+def _solver(pc, d):
+    return pc.Solver(device=0).load_data(d)
+
+
+def _colabs(d):
+    return np.array([np.abs(d.val[d.col_ptr[j]:d.col_ptr[j + 1]].astype(float)).sum()
+                     for j in range(d.p)])
+
+
+def _compare_step(d, s_gpu, s_orc, bundle, C):
+    colabs = _colabs(d)[bundle]
+    g_floor = RTOL * C * colabs + 1e-300
+    np.testing.assert_array_less(np.abs(s_gpu["g"] - s_orc["g"]), RTOL * np.abs(s_orc["g"]) + g_floor + 1e-15)
+    np.testing.assert_allclose(s_gpu["h"], s_orc["h"], rtol=RTOL, atol=1e-15)
+    dmax = np.max(np.abs(s_orc["d"])) if len(bundle) else 0.0
+    np.testing.assert_allclose(s_gpu["d"], s_orc["d"], rtol=RTOL, atol=RTOL * dmax + 1e-300)
+    xmax = np.max(np.abs(s_orc["dtx"]))
+    np.testing.assert_allclose(s_gpu["dtx"], s_orc["dtx"], rtol=RTOL, atol=RTOL * xmax + 1e-300)
+    assert s_gpu["q"] == s_orc["q"], (s_gpu["q"], s_orc["q"], s_gpu["dF"], s_orc["dF"])
+    assert s_gpu["alpha"] == s_orc["alpha"]
+    assert s_gpu["delta"] == pytest.approx(s_orc["delta"], rel=RTOL, abs=1e-12)
+    assert s_gpu["dF"] == pytest.approx(s_orc["dF"], rel=RTOL, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# a1: the partition
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("p", [1, 7, 4096, 4097, 50000, 1000000])
+def test_permutation_bitexact(pc, p):
+    d = synth.tiny(1, n=3, p=p, density=0.0) if p < 100 else None
+    if d is None:
+        # a matrix with p columns is needed only to size the context
+        col_ptr = np.zeros(p + 1, dtype=np.int64)
+        d = synth.Data(n=1, p=p, col_ptr=col_ptr, row_idx=np.zeros(0, np.int32),
+                       val=np.zeros(0, np.float32), y=np.ones(1, np.int8))
+    s = _solver(pc, d)
+    for seed, k in ((0, 0), (20130616, 3), (2**64 - 1, 11)):
+        assert np.array_equal(s.permutation(seed, k), oracle.permutation(seed, k, p)), (seed, k)
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# a2-a6: one inner iteration on the same w and bundle
+# --------------------------------------------------------------------------
+def _random_w(rng, p, frac=0.5, scale=0.3):
+    return rng.normal(0, scale, p) * (rng.random(p) < frac)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_step_parity_c1(pc, loss):
+    d = synth.c1()
+    prob = oracle.Problem.from_data(d)
+    C = 1.0
+    par = oracle.Params(loss=loss, C=C)
+    s = _solver(pc, d)
+    rng = np.random.default_rng(5)
+    for trial in range(6):
+        w = _random_w(rng, d.p) if trial else np.zeros(d.p)
+        s.reset(loss, C, w)
+        cache = oracle.cache_from_w(prob, loss, w)
+        np.testing.assert_allclose(s.cache(), cache, rtol=1e-12)
+        perm = oracle.permutation(3, trial, d.p)
+        P = [32, 1, 500, 77, 32, 250][trial]
+        bundle = perm[:P]
+        w_o = w.copy()
+        s_orc = oracle.step(prob, par, w_o, cache, bundle)
+        s_gpu = s.step(bundle)
+        _compare_step(d, s_gpu, s_orc, bundle, C)
+        np.testing.assert_allclose(s.w(), w_o, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(s.cache(), cache, rtol=1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_step_parity_long_columns_c2(pc, loss):
+    """C2 has columns of up to 20,000 nonzeros (split over many wavefronts)."""
+    d = synth.c2()
+    prob = oracle.Problem.from_data(d)
+    C = 4.0
+    par = oracle.Params(loss=loss, C=C)
+    s = _solver(pc, d)
+    rng = np.random.default_rng(8)
+    lens = d.col_lengths()
+    heavy = np.argsort(lens)[::-1][:40]
+    for trial in range(3):
+        w = _random_w(rng, d.p, frac=0.05, scale=0.2) if trial else np.zeros(d.p)
+        s.reset(loss, C, w)
+        cache = oracle.cache_from_w(prob, loss, w)
+        perm = oracle.permutation(9, trial, d.p)
+        bundle = np.concatenate([heavy[trial::3], perm[:1024]])
+        bundle = bundle[np.sort(np.unique(bundle, return_index=True)[1])]
+        w_o = w.copy()
+        s_orc = oracle.step(prob, par, w_o, cache, bundle)
+        s_gpu = s.step(bundle)
+        _compare_step(d, s_gpu, s_orc, bundle, C)
+        np.testing.assert_allclose(s.w(), w_o, rtol=1e-12, atol=1e-15)
+    s.close()
+
+
+def test_step_backtracking_and_failure(pc):
+    """Duplicated columns force q > 0; max_ls = 1 forces a failed search."""
+    base = synth.tiny(12, n=40, p=4, density=0.8)
+    X = base.dense()
+    X = np.hstack([X, X[:, :2], 0.5 * X[:, 2:3]])
+    d = synth.from_dense(X, base.y)
+    prob = oracle.Problem.from_data(d)
+    s = _solver(pc, d)
+    for loss in ("lr", "svm"):
+        for max_ls in (30, 1):
+            par = oracle.Params(loss=loss, C=3.0, max_ls=max_ls)
+            w = np.zeros(d.p)
+            s.reset(loss, 3.0, w)
+            cache = oracle.cache_from_w(prob, loss, w)
+            qs = []
+            for k in range(5):
+                B = oracle.permutation(77, k, d.p)
+                s_orc = oracle.step(prob, par, w, cache, B)
+                s_gpu = s.step(B, max_ls=max_ls)
+                _compare_step(d, s_gpu, s_orc, B, 3.0)
+                np.testing.assert_allclose(s.w(), w, rtol=1e-12, atol=1e-15)
+                qs.append(s_orc["q"])
+            assert (max(qs) > 0) if max_ls == 30 else (min(qs) == -1)
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# whole solves: final objective
+# --------------------------------------------------------------------------
+def _solve_both(pc, d, loss, C, P, eps, seed=1, max_outer=1000, w0=None, s=None):
+    prob = oracle.Problem.from_data(d)
+    w_o, info_o, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C), P=P, eps=eps, seed=seed,
+                                  max_outer=max_outer, w0=w0)
+    own = s is None
+    if own:
+        s = _solver(pc, d)
+    rc, w_g, info_g = s.solve(C, P, eps, loss, seed=seed, max_outer=max_outer, w0=w0)
+    if own:
+        s.close()
+    return (rc, w_g, info_g), (w_o, info_o)
+
+
+def _assert_solve_parity(g, o):
+    rc, w_g, ig = g
+    w_o, io = o
+    print(f"F_gpu={ig['objective']:.15g} F_orc={io['objective']:.15g} outer={ig['outer_iters']}/"
+          f"{io['outer_iters']} ls={ig['ls_steps']}/{io['ls_steps']}", flush=True)
+    assert ig["objective"] == pytest.approx(io["objective"], rel=RTOL)
+    assert ig["outer_iters"] == io["outer_iters"]
+    assert ig["converged"] == io["converged"]
+    assert ig["subgrad0"] == pytest.approx(io["subgrad0"], rel=1e-12)
+    assert ig["nnz_swept"] == io["nnz_swept"]
+    assert ig["bundles"] == io["bundles"]
+    assert ig["ls_fail"] == io["ls_fail"]
+
+
+def test_solve_parity_c1(pc):
+    d = synth.c1()
+    g, o = _solve_both(pc, d, "lr", 1.0, 32, 1e-4)
+    _assert_solve_parity(g, o)
+    assert g[0] == 0
+
+
+@pytest.mark.parametrize("C,P", [(0.5, 64), (0.5, 1024), (0.5, 8192),
+                                 (4.0, 64), (4.0, 1024), (4.0, 8192)])
+def test_solve_parity_c2(pc, C, P):
+    d = _c2_cached()
+    g, o = _solve_both(pc, d, "lr", C, P, 1e-4)
+    _assert_solve_parity(g, o)
+
+
+_C2 = {}
+
+
+def _c2_cached():
+    if "d" not in _C2:
+        _C2["d"] = synth.c2()
+    return _C2["d"]
+
+
+def test_solve_parity_c3(pc):
+    """Full-size SVM configuration (100,000 x 1,000,000, 12M nonzeros)."""
+    d = synth.c3()
+    g, o = _solve_both(pc, d, "svm", 1.0, 16384, 1e-3)
+    _assert_solve_parity(g, o)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_solve_edge_cases(pc, loss):
+    # empty columns, P = 1, P = p, ragged last bundle
+    d = synth.tiny(70, n=50, p=13, density=0.3, empty_cols=(0, 5))
+    for P in (1, 4, 13):
+        g, o = _solve_both(pc, d, loss, 1.0, P, 1e-8, max_outer=500)
+        _assert_solve_parity(g, o)
+    # one sample, one feature
+    d1 = synth.from_dense(np.array([[2.0]]), np.array([1], np.int8))
+    g, o = _solve_both(pc, d1, loss, 1.0, 1, 1e-10)
+    _assert_solve_parity(g, o)
+    # all-empty matrix: w = 0 is optimal
+    d0 = synth.Data(n=3, p=4, col_ptr=np.zeros(5, np.int64), row_idx=np.zeros(0, np.int32),
+                    val=np.zeros(0, np.float32), y=np.array([1, -1, 1], np.int8))
+    g, o = _solve_both(pc, d0, loss, 1.0, 2, 1e-6)
+    _assert_solve_parity(g, o)
+    assert g[2]["outer_iters"] == 0 and np.all(g[1] == 0)
+
+
+def test_warm_start_and_max_outer(pc):
+    d = synth.c1()
+    prob = oracle.Problem.from_data(d)
+    s = _solver(pc, d)
+    # hitting max_outer returns PCDN_NOT_CONVERGED with the same state as the oracle
+    g, o = _solve_both(pc, d, "lr", 1.0, 32, 1e-12, max_outer=3, s=s)
+    _assert_solve_parity(g, o)
+    assert g[0] == 1
+    # warm start from that point
+    g2, o2 = _solve_both(pc, d, "lr", 2.0, 32, 1e-4, w0=o[0], s=s)
+    _assert_solve_parity(g2, o2)
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# boundary error handling
+# --------------------------------------------------------------------------
+def test_abi_errors(pc):
+    from paper_1306_4080_amd import PcdnError
+    d = synth.tiny(3, n=10, p=5, density=0.5)
+    s = pc.Solver(device=0)
+    with pytest.raises(PcdnError, match="E_STATE"):
+        s.p = 5
+        s.solve(1.0, 2, 1e-3, "lr")
+    bad = d.row_idx.copy()
+    j = int(np.flatnonzero(np.diff(d.col_ptr) >= 2)[0])
+    lo = d.col_ptr[j]
+    bad[lo], bad[lo + 1] = bad[lo + 1], bad[lo]
+    with pytest.raises(PcdnError, match="E_CSC"):
+        s.load(d.n, d.p, d.col_ptr, bad, d.val, d.y)
+    bad = d.row_idx.copy()
+    bad[0] = d.n
+    with pytest.raises(PcdnError, match="E_CSC"):
+        s.load(d.n, d.p, d.col_ptr, bad, d.val, d.y)
+    v = d.val.copy()
+    v[0] = np.nan
+    with pytest.raises(PcdnError, match="E_CSC"):
+        s.load(d.n, d.p, d.col_ptr, d.row_idx, v, d.y)
+    y = d.y.copy()
+    y[0] = 0
+    with pytest.raises(PcdnError, match="E_CSC"):
+        s.load(d.n, d.p, d.col_ptr, d.row_idx, d.val, y)
+    s.load_data(d)
+    for args in ((0.0, 2, 1e-3, "lr"), (1.0, 0, 1e-3, "lr"), (1.0, 6, 1e-3, "lr"),
+                 (1.0, 2, -1.0, "lr"), (1.0, 2, 1e-3, 7)):
+        with pytest.raises(PcdnError, match="E_ARG"):
+            s.solve(*args)
+    with pytest.raises(PcdnError, match="E_ARG"):
+        s.solve(1.0, 2, 1e-3, "lr", max_ls=33)
+    s.reset("lr", 1.0)
+    with pytest.raises(PcdnError, match="E_ARG"):
+        s.step(np.array([0, 0], np.int32))
+    with pytest.raises(PcdnError, match="E_ARG"):
+        s.step(np.array([5], np.int32))
+    # the context stays usable after errors
+    rc, w, info = s.solve(1.0, 2, 1e-3, "lr")
+    assert rc == 0
+    s.close()
