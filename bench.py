@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""PCDN bundle-sweep benchmark on one MI355X.
+
+Workload: the text-like L1-regularised logistic-regression problem
+(n = 20,000 samples, p = 50,000 features, ~1.6M fp32 nonzeros, Zipf(1.1) column
+frequencies, row-normalised lognormal values) at its six settings
+C in {0.5, 4} x P in {64, 1024, 8192}; synthetic, seeded, generated in-process.
+
+A step is one pass of the whole hot path for each of the six settings: one outer
+iteration of Algorithm 3 (seeded partition, every bundle's gradient/Hessian
+sweep, direction, d^T x scatter, line search and apply, then the full-gradient
+stopping test), continuing each setting's trajectory from w = 0 (the warmup
+steps are the first iterations).  value = bundle-sweep nonzeros processed per
+second over the timed steps.
+
+The timed region (A) replays the library's captured HIP graphs without
+instrumentation.  A second region (B) runs the next `steps` outer iterations
+with every kernel launch bracketed by HIP events on the library's stream; the
+roofline object reports the kernel class with the most time there
+(algorithmic bytes per launch / average launch duration).
+The FP64 CPU oracle is timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "bundle-sweep nnz/s (HBM GB/s %peak); batched solves/s + p99 latency vs plain"
+HBM_PEAK_GBS = 8000.0
+KERNEL_CLASSES = ("sweep", "split_columns", "linesearch", "apply", "stopping_sweep")
+KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep, direction, fused d^T x scatter)",
+                "k_split (split-column finish and scatter)",
+                "k_linesearch (per-candidate loss-change partial sums)",
+                "k_apply (Armijo decision, w and retained-quantity update)",
+                "k_sweep+k_split stopping mode (full-gradient subgradient norm)")
+SETTINGS = [(0.5, 64), (0.5, 1024), (0.5, 8192), (4.0, 64), (4.0, 1024), (4.0, 8192)]
+SEED = 1
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time budget of the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("pcdn_kernels.hip", "pcdn_device.h"):
+        with open(os.path.join(ROOT, "paper_1306_4080_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_class: str):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_class}_c2_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(d, budget_s: float) -> dict:
+    """The FP64 oracle (single-threaded C) on a bounded sample: the first outer
+    iterations of each of the six settings, round-robin until the budget."""
+    import oracle
+    prob = oracle.Problem.from_data(d)
+    done_nnz = 0
+    # run each setting for m outer iterations, m chosen from a one-iteration probe
+    t_probe = time.perf_counter()
+    for C, P in SETTINGS:
+        par = oracle.Params(loss="lr", C=C)
+        oracle.solve(prob, par, P=P, eps=0.0, seed=SEED, max_outer=1)
+    probe = time.perf_counter() - t_probe
+    m = max(1, int(budget_s / max(probe, 1e-3)))
+    t0 = time.perf_counter()
+    for C, P in SETTINGS:
+        par = oracle.Params(loss="lr", C=C)
+        w, info, _ = oracle.solve(prob, par, P=P, eps=0.0, seed=SEED, max_outer=m)
+        done_nnz += info["nnz_swept"]
+    dt = time.perf_counter() - t0
+    return {"value": done_nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} outer iterations of each of the six (C, P) settings "
+                      f"from w = 0 ({done_nnz} bundle nonzeros, {dt:.1f} s, single thread)"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU PCDN is a design "
+              "(row sharding with two all-reduces per bundle), not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_1306_4080_amd as pc
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    pc.ensure_built()
+    d = synth.c2()
+    solvers = []
+    for C, P in SETTINGS:
+        s = pc.Solver(device=0).load_data(d)
+        s.reset("lr", C)
+        solvers.append((s, C, P))
+
+    # warmup: the first outer iterations of each trajectory
+    for k in range(args.warmup):
+        for s, C, P in solvers:
+            s.iterate(P, k, 1, want_subgrad=True, seed=SEED)
+    torch.cuda.synchronize()
+
+    # timed region A: graph replays, no instrumentation
+    per_setting = {f"C={C},P={P}": 0.0 for _, C, P in solvers}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        for s, C, P in solvers:
+            ts = time.perf_counter()
+            s.iterate(P, args.warmup + step, 1, want_subgrad=True, seed=SEED)
+            per_setting[f"C={C},P={P}"] += time.perf_counter() - ts
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    nnz_total = d.nnz * len(SETTINGS) * args.steps
+    value = nnz_total / elapsed
+
+    # timed region B: the next `steps` outer iterations with every kernel class
+    # bracketed by HIP events on the library's stream (launched directly, not
+    # from a graph, so events can bracket each kernel); the roofline is taken
+    # for the class with the most kernel time
+    for s, _, _ in solvers:
+        pc.pcdn_profile(s.ctx, (1 << len(KERNEL_CLASSES)) - 1)
+    tb0 = time.perf_counter()
+    for step in range(args.steps):
+        for s, C, P in solvers:
+            s.iterate(P, args.warmup + args.steps + step, 1, want_subgrad=True, seed=SEED)
+    tb1 = time.perf_counter()
+    kernels = {}
+    totals = {}
+    for cls, name in enumerate(KERNEL_CLASSES):
+        ms = n = b = 0.0
+        for s, _, _ in solvers:
+            a_ms, a_n, a_b = pc.pcdn_profile_read(s.ctx, cls)
+            ms += a_ms
+            n += a_n
+            b += a_b
+        totals[cls] = (ms, n, b)
+        kernels[name] = {"launches": int(n), "ms_total": round(ms, 4),
+                         "us_per_launch": round(1e3 * ms / max(n, 1), 3),
+                         "alg_GBps": round(b / (ms / 1e3) / 1e9, 1) if ms > 0 else None}
+    dominant = max(totals, key=lambda k: totals[k][0])
+    dom_ms, dom_n, dom_bytes = totals[dominant]
+    avg_launch_s = dom_ms / 1e3 / max(dom_n, 1)
+    bytes_per_launch = dom_bytes / max(dom_n, 1)
+    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    traffic = measured_traffic(KERNEL_CLASSES[dominant])
+    F = {f"C={C},P={P}": s.evaluate()[0] for s, C, P in solvers}
+    for s, _, _ in solvers:
+        s.close()
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "text-like L1-LR 20000x50000, Zipf(1.1) columns, "
+                               "C in {0.5,4} x P in {64,1024,8192}",
+                   "n": d.n, "p": d.p, "nnz": d.nnz, "loss": "logistic", "seed": SEED,
+                   "settings": [f"C={C},P={P}" for C, P in SETTINGS]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": KERNEL_NAMES[dominant],
+                     "alg_bytes_per_launch": bytes_per_launch,
+                     "avg_launch_us": avg_launch_s * 1e6, "launches": int(dom_n),
+                     "measured": "HIP events in timed region B (the next steps after region A)",
+                     "region_b_ms_per_step": 1e3 * (tb1 - tb0) / args.steps},
+        "per_setting_ms_per_iter": {k: 1e3 * v / args.steps for k, v in per_setting.items()},
+        "kernels": kernels,
+        "objective_after": F,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,7 +62,16 @@ typedef struct {
   double gamma;         /* Delta's Hessian weight in [0,1) (0 is valid)     */
   double nu;            /* floor added to a Hessian entry <= 0 (0: 1e-12)   */
   const double* w0;     /* host, p entries, warm start; NULL: zeros         */
+  int32_t schedule;     /* PCDN_SCHED_*: how bundles map onto the GPU       */
+  int32_t reserved;     /* must be 0                                        */
 } pcdn_opts;
+
+/* Bundle schedules (same arithmetic, different launch structure):
+ *  WIDE:   every bundle is four kernels over the whole GPU (many nonzeros);
+ *  NARROW: one workgroup runs all bundles of an outer iteration (small
+ *          bundles, where kernel-boundary latency would dominate);
+ *  AUTO:   NARROW when the average bundle holds few nonzeros, else WIDE. */
+enum { PCDN_SCHED_AUTO = 0, PCDN_SCHED_WIDE = 1, PCDN_SCHED_NARROW = 2 };
 
 /* Per-solve report. */
 typedef struct {
@@ -131,6 +140,16 @@ int pcdn_reset(pcdn_ctx* ctx, int loss, double C, const double* w);
 int pcdn_step(pcdn_ctx* ctx, const int32_t* bundle, int64_t P, const pcdn_opts* opts,
               pcdn_step_info* out, double* g, double* h, double* d, double* dtx);
 
+/* Run `count` outer iterations of Algorithm 3, iterations k_first ..
+ * k_first+count-1 of the partition sequence of opts->seed, from the current
+ * device state (left by pcdn_reset, pcdn_solve or an earlier call) with that
+ * state's loss and C.  Each outer iteration draws its partition, runs every
+ * bundle, then the full-gradient stopping sweep.  subgrad (nullable)
+ * receives ||grad^S F(w)||_1 after the last iteration.  1 <= P <= p,
+ * k_first >= 0, count >= 0. */
+int pcdn_iterate(pcdn_ctx* ctx, int64_t P, int64_t k_first, int64_t count,
+                 const pcdn_opts* opts, double* subgrad);
+
 /* The feature permutation of outer iteration k for `seed` (host, p int32):
  * features sorted by the upper 32 bits of output j of the SplitMix64 stream
  * whose seed is output k of the SplitMix64 stream seeded with `seed`, ties by
@@ -147,13 +166,15 @@ int pcdn_get_cache(pcdn_ctx* ctx, double* cache_out);
  * may be NULL). */
 int pcdn_evaluate(pcdn_ctx* ctx, double* objective, double* subgrad);
 
-/* Kernel timing.  pcdn_profile(ctx, 1) brackets every launch of the bundle
- * sweep kernels with HIP events on the context's stream; pcdn_profile_read()
- * returns, for kernel class `which` (0: gradient/direction sweep, 1: d^T x
- * scatter of split columns, 2: line search, 3: apply, 4: stopping sweep), the
- * summed event time in ms, the launch count and the algorithmic bytes those
- * launches moved, accumulated since the last pcdn_profile(ctx, 1). */
-int pcdn_profile(pcdn_ctx* ctx, int enable);
+/* Kernel timing.  Kernel classes: 0 gradient/direction sweep (with the fused
+ * d^T x scatter), 1 d^T x scatter of split columns, 2 line search, 3 apply,
+ * 4 stopping sweep.  pcdn_profile(ctx, mask) brackets every launch of each
+ * class whose bit (1 << class) is set in mask with HIP events on the
+ * context's stream (mask 0: off) and restarts the accumulators;
+ * pcdn_profile_read() returns for class `which` the summed event time in ms
+ * and the launch count since then (bracketed classes only), and the
+ * algorithmic bytes all launches of that class moved since then. */
+int pcdn_profile(pcdn_ctx* ctx, int mask);
 int pcdn_profile_read(pcdn_ctx* ctx, int which, double* ms, int64_t* launches,
                       double* alg_bytes);
 

@@ -31,6 +31,7 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
 
 # entry points declared in include/pcdn.h
 SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
+           "pcdn_iterate",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
            "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy")
 
@@ -45,7 +46,8 @@ class pcdn_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("max_outer", ctypes.c_int32),
                 ("max_ls", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("nu", ctypes.c_double), ("w0", ctypes.c_void_p)]
+                ("nu", ctypes.c_double), ("w0", ctypes.c_void_p),
+                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class pcdn_info(ctypes.Structure):
@@ -89,6 +91,7 @@ def load_library(path: str = LIB_PATH):
     L.pcdn_reset.argtypes = [vp, i32, dbl, vp]
     L.pcdn_step.argtypes = [vp, vp, i64, ctypes.POINTER(pcdn_opts),
                             ctypes.POINTER(pcdn_step_info), vp, vp, vp, vp]
+    L.pcdn_iterate.argtypes = [vp, i64, i64, i64, ctypes.POINTER(pcdn_opts), vp]
     L.pcdn_permutation.argtypes = [vp, u64, i64, vp]
     L.pcdn_get_w.argtypes = [vp, vp]
     L.pcdn_get_cache.argtypes = [vp, vp]
@@ -120,8 +123,13 @@ def _check(ctx, rc, allow=(PCDN_OK,)):
     raise PcdnError(rc, msg.decode() if msg else "")
 
 
-def _opts(seed=0, max_outer=0, max_ls=0, sigma=0.0, beta=0.0, gamma=0.0, nu=0.0, w0=None):
-    o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None)
+SCHEDULES = {"auto": 0, "wide": 1, "narrow": 2}
+
+
+def _opts(seed=0, max_outer=0, max_ls=0, sigma=0.0, beta=0.0, gamma=0.0, nu=0.0, w0=None,
+          schedule="auto"):
+    schedule = SCHEDULES.get(schedule, schedule)
+    o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None, int(schedule), 0)
     keep = None
     if w0 is not None:
         keep = np.ascontiguousarray(w0, dtype=np.float64)
@@ -198,6 +206,17 @@ def pcdn_step(ctx, bundle, n, want=("g", "h", "d", "dtx"), **opts):
     return out
 
 
+def pcdn_iterate(ctx, P, k_first, count, want_subgrad=True, **opts):
+    """Run outer iterations from the current device state; returns the
+    stopping norm after the last one (or None)."""
+    o, _ = _opts(**opts)
+    G = ctypes.c_double()
+    rc = load_library().pcdn_iterate(ctx, int(P), int(k_first), int(count), ctypes.byref(o),
+                                     ctypes.byref(G) if want_subgrad else None)
+    _check(ctx, rc)
+    return G.value if want_subgrad else None
+
+
 def pcdn_permutation(ctx, seed, k, p) -> np.ndarray:
     out = np.empty(int(p), dtype=np.int32)
     _check(ctx, load_library().pcdn_permutation(ctx, int(seed), int(k), out.ctypes.data))
@@ -223,8 +242,9 @@ def pcdn_evaluate(ctx):
     return F.value, G.value
 
 
-def pcdn_profile(ctx, enable: bool) -> None:
-    _check(ctx, load_library().pcdn_profile(ctx, 1 if enable else 0))
+def pcdn_profile(ctx, mask: int) -> None:
+    """mask: bit k brackets kernel class k with HIP events (0: off)."""
+    _check(ctx, load_library().pcdn_profile(ctx, int(mask)))
 
 
 def pcdn_profile_read(ctx, which: int):
@@ -265,6 +285,9 @@ class Solver:
 
     def step(self, bundle, **opts):
         return pcdn_step(self.ctx, bundle, self.n, **opts)
+
+    def iterate(self, P, k_first, count, want_subgrad=True, **opts):
+        return pcdn_iterate(self.ctx, P, k_first, count, want_subgrad, **opts)
 
     def permutation(self, seed, k):
         return pcdn_permutation(self.ctx, seed, k, self.p)

@@ -22,7 +22,7 @@ namespace {
 constexpr int kProfClasses = 5;  // sweep, split scatter, line search, apply, stopping sweep
 
 struct Profiler {
-  bool on = false;
+  int mask = 0;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   double ms[kProfClasses] = {0, 0, 0, 0, 0};
@@ -72,6 +72,7 @@ struct pcdn_ctx {
   double* dtx = nullptr;
   double* tmp_n = nullptr;
   double* tmp_p = nullptr;
+  unsigned* rowflag = nullptr;
   double* g = nullptr;
   double* h = nullptr;
   double* d = nullptr;
@@ -86,17 +87,17 @@ struct pcdn_ctx {
   int32_t* scan_tmp = nullptr;
   int32_t* nch = nullptr;
   int32_t* cstart = nullptr;
-  int32_t* chunk_slot = nullptr;
+  Chunk* chunks = nullptr;
   int32_t* id_cstart = nullptr;
-  int32_t* id_slot = nullptr;
+  Chunk* id_chunks = nullptr;
+  int64_t id_total_chunks = 0;
   int32_t* step_perm = nullptr;
   int64_t max_chunks = 0;
   double2* part = nullptr;
-  unsigned* cnt = nullptr;
 
   // reductions and small device records
   double* ls_part = nullptr;
-  unsigned* counters = nullptr;  // [0] line search, [1] sums
+  IterState* iter = nullptr;
   StepState* st = nullptr;
   Stats* stats = nullptr;
   double* scal = nullptr;        // [0] stopping norm, [1] loss sum, [2] l1 sum
@@ -106,6 +107,28 @@ struct pcdn_ctx {
   double* hscal = nullptr;
   Stats* hstats = nullptr;
   StepState* hst = nullptr;
+  IterState* hiter = nullptr;
+
+  // replayable outer iteration (HIP graph) and the key it was captured for
+  hipGraphExec_t graph = nullptr;
+  bool use_graphs = true;
+  struct GraphKey {
+    int64_t P = -1;
+    int loss = -1;
+    double C = 0, sigma = 0, beta = 0, gamma = 0, nu = 0;
+    int max_ls = 0;
+    int schedule = -1;
+    bool operator==(const GraphKey& o) const {
+      return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
+             gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule;
+    }
+  } graph_key;
+
+  // counters known on the host (launch structure): sweep and stopping work
+  struct HostCounts {
+    double nnz_gh = 0, slots = 0, nnz_stop = 0, stop_sweeps = 0;
+  } hc, prof_hc;
+  std::vector<int64_t> h_cp;  // host copy of col_ptr
 
   Profiler prof;
   Stats prof_base{};
@@ -113,7 +136,6 @@ struct pcdn_ctx {
 
 namespace {
 
-constexpr int kLsGridMax = 1024;
 
 int fail(pcdn_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -135,6 +157,12 @@ int fail(pcdn_ctx* c, int code, const std::string& msg) {
     }                                                                                  \
   } while (0)
 
+void drop_graph(pcdn_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_key = pcdn_ctx::GraphKey();
+}
+
 template <class T>
 void dfree(T*& ptr) {
   if (ptr) (void)hipFree((void*)ptr);
@@ -144,11 +172,13 @@ void dfree(T*& ptr) {
 void free_data(pcdn_ctx* c) {
   dfree(c->cp); dfree(c->ri); dfree(c->v); dfree(c->y);
   dfree(c->w); dfree(c->cache); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
+  dfree(c->rowflag);
   dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
-  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunk_slot);
-  dfree(c->id_cstart); dfree(c->id_slot); dfree(c->step_perm);
-  dfree(c->part); dfree(c->cnt); dfree(c->ls_part);
+  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
+  dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
+  dfree(c->part); dfree(c->ls_part);
+  drop_graph(c);
   c->loaded = false;
   c->has_state = false;
   c->n = c->p = c->nnz = 0;
@@ -159,7 +189,11 @@ struct Opts {
   int max_outer, max_ls;
   double sigma, beta, gamma, nu;
   const double* w0;
+  int schedule;
 };
+
+// Average nonzeros per bundle up to which one workgroup runs the bundles.
+constexpr double kNarrowMaxBundleNnz = 8192.0;
 
 int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
   r->seed = o ? o->seed : 0;
@@ -170,6 +204,10 @@ int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
   r->gamma = o ? o->gamma : 0.0;
   r->nu = (o && o->nu != 0.0) ? o->nu : 1e-12;
   r->w0 = o ? o->w0 : nullptr;
+  r->schedule = o ? o->schedule : PCDN_SCHED_AUTO;
+  if (r->schedule < PCDN_SCHED_AUTO || r->schedule > PCDN_SCHED_NARROW)
+    return fail(c, PCDN_E_ARG, "unknown schedule");
+  if (o && o->reserved != 0) return fail(c, PCDN_E_ARG, "reserved option field must be 0");
   if (r->max_outer < 0) return fail(c, PCDN_E_ARG, "max_outer must be >= 0");
   if (r->max_ls < 1 || r->max_ls > kQMax) return fail(c, PCDN_E_ARG, "max_ls must lie in [1, 32]");
   if (!(r->sigma > 0.0 && r->sigma < 1.0)) return fail(c, PCDN_E_ARG, "sigma must lie in (0, 1)");
@@ -201,9 +239,12 @@ hipEvent_t prof_event(pcdn_ctx* c) {
 void prof_harvest(pcdn_ctx* c) {
   for (auto& pe : c->prof.pending) {
     float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess)
+    if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
       c->prof.ms[pe.first] += ms;
-    c->prof.launches[pe.first] += 1;
+      c->prof.launches[pe.first] += 1;
+    } else {
+      (void)hipGetLastError();  // do not leave the failure for the next launch check
+    }
     c->prof.pool.push_back(pe.second.first);
     c->prof.pool.push_back(pe.second.second);
   }
@@ -215,14 +256,17 @@ struct ProfScope {
   int cls;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(pcdn_ctx* c_, int cls_) : c(c_), cls(cls_) {
-    if (c->prof.on) {
+    if (c->prof.mask & (1 << cls)) {
       if (c->prof.pending.size() > 8192) {
         (void)hipStreamSynchronize(c->stream);
         prof_harvest(c);
       }
       a = prof_event(c);
       b = prof_event(c);
-      if (a) (void)hipEventRecord(a, c->stream);
+      if (a && hipEventRecord(a, c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        a = nullptr;
+      }
     }
   }
   ~ProfScope() {
@@ -234,19 +278,8 @@ struct ProfScope {
 };
 
 // --- kernel sequences -------------------------------------------------------
-int sweep_grid(int64_t slots) {
-  int64_t g = (slots + kWavesPerBlock - 1) / kWavesPerBlock;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
-}
-
-int row_grid(int64_t items, int cap) {
-  int64_t g = (items + kBlock - 1) / kBlock;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
-}
-
 SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   SweepArgs a{};
-  a.cp = c->cp;
   a.ri = c->ri;
   a.v = c->v;
   a.y = c->y;
@@ -258,7 +291,6 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   a.dterm = c->dterm;
   a.sg = c->tmp_p;
   a.part = c->part;
-  a.cnt = c->cnt;
   a.dtx = c->dtx;
   a.stats = c->stats;
   a.C = c->C;
@@ -267,25 +299,29 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   return a;
 }
 
-// One inner iteration of Algorithm 3 on slots [lo, hi) of `perm` (whose chunk
-// bookkeeping is in c->cstart / c->chunk_slot).
-int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+// Inner iteration of Algorithm 3 on slots [lo, hi) of `perm` whose chunk
+// descriptors are c->chunks / c->cstart, first half: sweep (g, h, d, fused
+// d^T x) and split columns.
+int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
   SweepArgs a = sweep_args(c, o);
-  a.perm = perm;
+  a.chunks = c->chunks;
   a.cstart = c->cstart;
-  a.chunk_slot = c->chunk_slot;
   a.slot_lo = lo;
   a.slot_hi = hi;
-  const int64_t Pt = hi - lo;
-  const int sg = sweep_grid(Pt);
   {
     ProfScope ps(c, 0);
-    HIPCHK(c, launch_sweep(c->loss, 0, a, sg, c->stream));
+    HIPCHK(c, launch_sweep(c->loss, false, a, c->stream));
   }
   {
     ProfScope ps(c, 1);
-    HIPCHK(c, launch_scatter_split(a, sg, c->stream));
+    HIPCHK(c, launch_split(c->loss, false, a, c->stream));
   }
+  return PCDN_OK;
+}
+
+// Second half: line-search partials, then decision + apply.  With the first
+// half, four kernel boundaries are the only synchronisation of a bundle.
+int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
   LsArgs l{};
   l.dtx = c->dtx;
   l.cache = c->cache;
@@ -298,18 +334,12 @@ int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
   l.d = c->d;
   l.dterm = c->dterm;
   l.part = c->ls_part;
-  l.counter = c->counters;
-  l.st = c->st;
   l.stats = c->stats;
-  l.C = c->C;
-  l.sigma = o.sigma;
   l.beta = o.beta;
-  l.q0 = 0;
   l.Q = o.max_ls;
-  l.max_ls = o.max_ls;
   {
     ProfScope ps(c, 2);
-    HIPCHK(c, launch_linesearch(c->loss, l, row_grid(std::max(c->n, Pt), kLsGridMax), c->stream));
+    HIPCHK(c, launch_linesearch(c->loss, l, c->stream));
   }
   ApplyArgs ap{};
   ap.dtx = c->dtx;
@@ -321,29 +351,43 @@ int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
   ap.slot_lo = lo;
   ap.slot_hi = hi;
   ap.d = c->d;
+  ap.part = c->ls_part;
+  ap.ls_blocks = ls_grid(c->n);
   ap.st = c->st;
+  ap.stats = c->stats;
+  ap.C = c->C;
+  ap.sigma = o.sigma;
   ap.beta = o.beta;
+  ap.Q = o.max_ls;
+  ap.max_ls = o.max_ls;
   {
     ProfScope ps(c, 3);
-    HIPCHK(c, launch_apply(c->loss, ap, row_grid(std::max(c->n, Pt), 4096), c->stream));
+    HIPCHK(c, launch_apply(c->loss, ap, c->stream));
   }
   return PCDN_OK;
 }
 
-// ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0).
-int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w) {
+int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+  int rc = bundle_sweep(c, o, lo, hi);
+  if (rc) return rc;
+  return bundle_ls_apply(c, o, perm, lo, hi);
+}
+
+// ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0);
+// `it` (nullable) is advanced by the final reduction.
+int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) {
   SweepArgs a = sweep_args(c, o);
   a.w = w;
-  a.perm = nullptr;
+  a.chunks = c->id_chunks;
   a.cstart = c->id_cstart;
-  a.chunk_slot = c->id_slot;
   a.slot_lo = 0;
   a.slot_hi = c->p;
   {
     ProfScope ps(c, 4);
-    HIPCHK(c, launch_sweep(c->loss, 1, a, sweep_grid(c->p), c->stream));
+    HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
+    HIPCHK(c, launch_split(c->loss, true, a, c->stream));
   }
-  HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->counters + 1, c->scal, c->stream));
+  HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->scal, it, c->stream));
   return PCDN_OK;
 }
 
@@ -351,22 +395,24 @@ int read_scalar(pcdn_ctx* c, int idx, double* out) {
   HIPCHK(c, hipMemcpyAsync(c->hscal + idx, c->scal + idx, sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (c->prof.on) prof_harvest(c);
+  if (c->prof.mask) prof_harvest(c);
   *out = c->hscal[idx];
   return PCDN_OK;
 }
 
 int stopping_norm(pcdn_ctx* c, const Opts& o, const double* w, double* G) {
-  int rc = launch_stopping(c, o, w);
+  int rc = launch_stopping(c, o, w, nullptr);
   if (rc) return rc;
+  c->hc.nnz_stop += (double)c->nnz;
+  c->hc.stop_sweeps += 1;
   return read_scalar(c, 0, G);
 }
 
 int objective(pcdn_ctx* c, double* F) {
   HIPCHK(c, launch_loss_terms(c->loss, c->cache, c->y, c->n, c->tmp_n, c->stream));
-  HIPCHK(c, launch_sum(c->tmp_n, c->n, c->sum_part, c->counters + 1, c->scal + 1, c->stream));
+  HIPCHK(c, launch_sum(c->tmp_n, c->n, c->sum_part, c->scal + 1, nullptr, c->stream));
   HIPCHK(c, launch_abs(c->w, c->p, c->tmp_p, c->stream));
-  HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->counters + 1, c->scal + 2, c->stream));
+  HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->scal + 2, nullptr, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->hscal + 1, c->scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -381,8 +427,8 @@ int cache_from_w(pcdn_ctx* c, bool w_is_zero) {
     return PCDN_OK;
   }
   HIPCHK(c, launch_fill(c->cache, 0.0, c->n, c->stream));
-  HIPCHK(c, launch_margins(c->cp, c->ri, c->v, c->w, c->id_cstart, c->id_slot, c->p, c->cache,
-                           sweep_grid(c->p), c->stream));
+  HIPCHK(c, launch_margins(c->ri, c->v, c->w, c->id_chunks, c->id_total_chunks, c->cache,
+                           c->stream));
   HIPCHK(c, launch_cache_from_z(c->loss, c->cache, c->y, c->n, c->stream));
   return PCDN_OK;
 }
@@ -399,15 +445,132 @@ int set_w(pcdn_ctx* c, const double* w_host) {
   return cache_from_w(c, w_host == nullptr);
 }
 
-int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k) {
-  // stream seed of outer iteration k: output k of the generator seeded with `seed`
-  uint64_t z = seed + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  HIPCHK(c, launch_perm_keys(z, c->p, c->keys0, c->idx0, c->stream));
+// Partition of outer iteration k (it != null: k and seed read on the device).
+int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, const IterState* it) {
+  HIPCHK(c, launch_perm_keys(it, seed, k, c->p, c->keys0, c->idx0, c->stream));
   HIPCHK(c, launch_radix_sort(c->keys0, c->idx0, c->keys1, c->idx1, c->p, c->hist, c->scan_tmp,
                               c->stream));
+  return PCDN_OK;
+}
+
+bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P) {
+  if (o.schedule == PCDN_SCHED_NARROW) return true;
+  if (o.schedule == PCDN_SCHED_WIDE) return false;
+  return (double)c->nnz * (double)P / (double)c->p <= kNarrowMaxBundleNnz;
+}
+
+// Bundles [t_begin, t_end) of size P over the order `perm` (descriptors in
+// c->chunks / c->cstart) in one workgroup.
+int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
+                          int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
+  NarrowArgs na{};
+  na.sw = sweep_args(c, o);
+  na.sw.chunks = c->chunks;
+  na.sw.cstart = c->cstart;
+  na.cache = c->cache;
+  na.w = c->w;
+  na.rowflag = c->rowflag;
+  na.perm = perm;
+  na.n = c->n;
+  na.p = p_slots;
+  na.P = P;
+  na.t_begin = t_begin;
+  na.t_end = t_end;
+  na.st = c->st;
+  na.stats = c->stats;
+  na.C = c->C;
+  na.sigma = o.sigma;
+  na.beta = o.beta;
+  na.max_ls = o.max_ls;
+  na.dtx_copy = dtx_copy;
+  ProfScope ps(c, 0);
+  HIPCHK(c, launch_narrow(c->loss, na, c->stream));
+  return PCDN_OK;
+}
+
+// One outer iteration k of Algorithm 3: partition, every bundle, then the
+// stopping sweep (result in c->scal[0]).  it != null: k is read from and
+// advanced on the device (graph replays).
+int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
+  int rc = device_permutation(c, o.seed, k, it);
+  if (rc) return rc;
+  HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunks, c->scan_tmp,
+                          c->stream));
+  const int64_t nb = (c->p + P - 1) / P;
+  if (use_narrow(c, o, P)) {
+    rc = launch_narrow_bundles(c, o, c->idx0, c->p, P, 0, nb, nullptr);
+    if (rc) return rc;
+  } else {
+    for (int64_t t = 0; t < nb; ++t) {
+      const int64_t lo = t * P, hi = std::min(lo + P, c->p);
+      rc = run_bundle(c, o, c->idx0, lo, hi);
+      if (rc) return rc;
+    }
+  }
+  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, c->stats, c->stream));
+  return launch_stopping(c, o, c->w, it);
+}
+
+// Capture (once per key) the outer iteration as a HIP graph.
+int ensure_graph(pcdn_ctx* c, const Opts& o, int64_t P) {
+  pcdn_ctx::GraphKey key;
+  key.P = P;
+  key.loss = c->loss;
+  key.C = c->C;
+  key.sigma = o.sigma;
+  key.beta = o.beta;
+  key.gamma = o.gamma;
+  key.nu = o.nu;
+  key.max_ls = o.max_ls;
+  key.schedule = o.schedule;
+  if (c->graph && c->graph_key == key) return PCDN_OK;
+  drop_graph(c);
+  hipGraph_t g = nullptr;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_outer(c, o, P, 0, c->iter);
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(c, PCDN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph = nullptr;
+    return fail(c, PCDN_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  }
+  c->graph_key = key;
+  return PCDN_OK;
+}
+
+// Outer iterations k_first .. k_first+count-1; the last stopping norm stays in
+// c->scal[0].  Replays a captured graph unless kernel profiling is on.
+int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t count) {
+  if (count <= 0) return PCDN_OK;
+  // every outer iteration sweeps each feature once in a bundle and once more
+  // in the stopping test
+  c->hc.nnz_gh += (double)c->nnz * count;
+  c->hc.slots += (double)c->p * count;
+  c->hc.nnz_stop += (double)c->nnz * count;
+  c->hc.stop_sweeps += (double)count;
+  // kernel profiling brackets launches with events: launch directly then
+  if (c->use_graphs && c->prof.mask == 0) {
+    int rc = ensure_graph(c, o, P);
+    if (rc) return rc;
+    c->hiter->seed = o.seed;
+    c->hiter->k = k_first;
+    HIPCHK(c, hipMemcpyAsync(c->iter, c->hiter, sizeof(IterState), hipMemcpyHostToDevice,
+                             c->stream));
+    for (int64_t k = 0; k < count; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
+    // the pinned source may be reused only after the copy ran
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PCDN_OK;
+  }
+  for (int64_t k = k_first; k < k_first + count; ++k) {
+    int rc = enqueue_outer(c, o, P, k, nullptr);
+    if (rc) return rc;
+  }
   return PCDN_OK;
 }
 
@@ -417,14 +580,15 @@ int read_stats(pcdn_ctx* c) {
   return PCDN_OK;
 }
 
-double alg_bytes_of(const Stats& s, const Stats& b, int cls, int64_t p) {
-  const double d_nnz_gh = (double)(s.nnz_gh - b.nnz_gh);
-  const double d_slots = (double)(s.slots - b.slots);
+double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& h,
+                    const pcdn_ctx::HostCounts& hb, int cls, int64_t p) {
+  const double d_nnz_gh = h.nnz_gh - hb.nnz_gh;
+  const double d_slots = h.slots - hb.slots;
   const double d_fused = (double)(s.nnz_scat_fused - b.nnz_scat_fused);
   const double d_split = (double)(s.nnz_scat_split - b.nnz_scat_split);
   const double d_rows = (double)(s.rows_touched - b.rows_touched);
-  const double d_stop = (double)(s.nnz_stop - b.nnz_stop);
-  const double d_sweeps = (double)(s.stop_sweeps - b.stop_sweeps);
+  const double d_stop = h.nnz_stop - hb.nnz_stop;
+  const double d_sweeps = h.stop_sweeps - hb.stop_sweeps;
   switch (cls) {
     case 0: return kBytesPerNnzSweep * d_nnz_gh + kBytesPerSlotSweep * d_slots +
                    kBytesPerNnzScatter * d_fused;
@@ -471,15 +635,16 @@ extern "C" int pcdn_create(pcdn_ctx** out, int device, void* hip_stream) {
       return bail(PCDN_E_DEVICE, "hipStreamCreate failed");
     c->own_stream = true;
   }
-  if (dalloc(&c->counters, 4) != hipSuccess || dalloc(&c->st, 1) != hipSuccess ||
+  if (dalloc(&c->iter, 1) != hipSuccess || dalloc(&c->st, 1) != hipSuccess ||
       dalloc(&c->stats, 1) != hipSuccess || dalloc(&c->scal, 8) != hipSuccess ||
       dalloc(&c->sum_part, kSumGrid) != hipSuccess)
     return bail(PCDN_E_OOM, "device allocation failed");
   if (hipHostMalloc((void**)&c->hscal, 8 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&c->hstats, sizeof(Stats)) != hipSuccess ||
-      hipHostMalloc((void**)&c->hst, sizeof(StepState)) != hipSuccess)
+      hipHostMalloc((void**)&c->hst, sizeof(StepState)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hiter, sizeof(IterState)) != hipSuccess)
     return bail(PCDN_E_OOM, "pinned host allocation failed");
-  if (hipMemsetAsync(c->counters, 0, 4 * sizeof(unsigned), c->stream) != hipSuccess ||
+  if (hipMemsetAsync(c->iter, 0, sizeof(IterState), c->stream) != hipSuccess ||
       hipMemsetAsync(c->stats, 0, sizeof(Stats), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(PCDN_E_DEVICE, "initialisation failed");
@@ -492,10 +657,11 @@ extern "C" int pcdn_destroy(pcdn_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_data(c);
-  dfree(c->counters); dfree(c->st); dfree(c->stats); dfree(c->scal); dfree(c->sum_part);
+  dfree(c->iter); dfree(c->st); dfree(c->stats); dfree(c->scal); dfree(c->sum_part);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->hstats) (void)hipHostFree(c->hstats);
   if (c->hst) (void)hipHostFree(c->hst);
+  if (c->hiter) (void)hipHostFree(c->hiter);
   for (auto& pe : c->prof.pending) {
     (void)hipEventDestroy(pe.second.first);
     (void)hipEventDestroy(pe.second.second);
@@ -565,12 +731,12 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
 
   HIPCHK(c, hipStreamSynchronize(c->stream));
   free_data(c);
+  c->h_cp.assign(Hcp, Hcp + p + 1);
   c->n = n;
   c->p = p;
   c->nnz = nnz;
   c->max_chunks = max_chunks;
-  const int64_t ntiles = (p + 4095) / 4096;
-  const int64_t hist_m = 256 * ntiles;
+  const int64_t hist_m = radix_hist_ints(p);
   ALLOC(c, c->cp, p + 1);
   ALLOC(c, c->ri, nnz);
   ALLOC(c, c->v, nnz);
@@ -580,6 +746,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->dtx, n);
   ALLOC(c, c->tmp_n, n);
   ALLOC(c, c->tmp_p, p);
+  ALLOC(c, c->rowflag, n);
   ALLOC(c, c->g, p);
   ALLOC(c, c->h, p);
   ALLOC(c, c->d, p);
@@ -588,17 +755,16 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->keys1, p);
   ALLOC(c, c->idx0, p);
   ALLOC(c, c->idx1, p);
-  ALLOC(c, c->hist, hist_m + 1);
+  ALLOC(c, c->hist, hist_m);
   ALLOC(c, c->scan_tmp, std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)) + 1);
   ALLOC(c, c->nch, p);
   ALLOC(c, c->cstart, p + 1);
-  ALLOC(c, c->chunk_slot, max_chunks);
+  ALLOC(c, c->chunks, max_chunks);
   ALLOC(c, c->id_cstart, p + 1);
-  ALLOC(c, c->id_slot, max_chunks);
+  ALLOC(c, c->id_chunks, max_chunks);
   ALLOC(c, c->step_perm, p);
   ALLOC(c, c->part, max_chunks);
-  ALLOC(c, c->cnt, p);
-  ALLOC(c, c->ls_part, (size_t)kLsGridMax * (2 * kQMax + 1));
+  ALLOC(c, c->ls_part, (size_t)kLsGrid * (2 * kQMax + 2));
   const hipMemcpyKind kind = ptr_kind == 1 ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIPCHK(c, hipMemcpyAsync(c->cp, col_ptr, (p + 1) * sizeof(int64_t), kind, c->stream));
   if (nnz) {
@@ -607,10 +773,14 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   }
   HIPCHK(c, hipMemcpyAsync(c->y, y, n, kind, c->stream));
   HIPCHK(c, hipMemsetAsync(c->dtx, 0, n * sizeof(double), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->cnt, 0, p * sizeof(unsigned), c->stream));
-  HIPCHK(c, launch_chunks(nullptr, c->cp, p, c->nch, c->id_cstart, c->id_slot, c->scan_tmp,
+  HIPCHK(c, hipMemsetAsync(c->rowflag, 0, n * sizeof(unsigned), c->stream));
+  HIPCHK(c, launch_chunks(nullptr, c->cp, p, c->nch, c->id_cstart, c->id_chunks, c->scan_tmp,
                           c->stream));
+  int32_t total = 0;
+  HIPCHK(c, hipMemcpyAsync(&total, c->id_cstart + p, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->id_total_chunks = total;
   c->loaded = true;
   return PCDN_OK;
 }
@@ -649,35 +819,27 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipMemcpyAsync(c->step_perm, bundle, P * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream));
-  HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, c->nch, c->cstart, c->chunk_slot, c->scan_tmp,
+  HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, c->nch, c->cstart, c->chunks, c->scan_tmp,
                           c->stream));
-  // run the bundle; keep d^T x before the apply kernel clears it
-  SweepArgs a = sweep_args(c, o);
-  a.perm = c->step_perm;
-  a.cstart = c->cstart;
-  a.chunk_slot = c->chunk_slot;
-  a.slot_lo = 0;
-  a.slot_hi = P;
-  const int sg = sweep_grid(P);
-  HIPCHK(c, launch_sweep(c->loss, 0, a, sg, c->stream));
-  HIPCHK(c, launch_scatter_split(a, sg, c->stream));
-  if (dtx)
-    HIPCHK(c, hipMemcpyAsync(c->tmp_n, c->dtx, c->n * sizeof(double), hipMemcpyDeviceToDevice,
-                             c->stream));
-  LsArgs l{};
-  l.dtx = c->dtx; l.cache = c->cache; l.y = c->y; l.n = c->n; l.w = c->w;
-  l.perm = c->step_perm; l.slot_lo = 0; l.slot_hi = P; l.d = c->d; l.dterm = c->dterm;
-  l.part = c->ls_part; l.counter = c->counters; l.st = c->st; l.stats = c->stats;
-  l.C = c->C; l.sigma = o.sigma; l.beta = o.beta; l.q0 = 0; l.Q = o.max_ls; l.max_ls = o.max_ls;
-  HIPCHK(c, launch_linesearch(c->loss, l, row_grid(std::max(c->n, P), kLsGridMax), c->stream));
+  // run the bundle; keep d^T x before it is cleared
+  if (use_narrow(c, o, P)) {
+    rc = launch_narrow_bundles(c, o, c->step_perm, P, P, 0, 1, dtx ? c->tmp_n : nullptr);
+    if (rc) return rc;
+  } else {
+    rc = bundle_sweep(c, o, 0, P);
+    if (rc) return rc;
+    if (dtx)
+      HIPCHK(c, hipMemcpyAsync(c->tmp_n, c->dtx, c->n * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+    rc = bundle_ls_apply(c, o, c->step_perm, 0, P);
+    if (rc) return rc;
+  }
+  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, c->stats, c->stream));
+  for (int64_t t = 0; t < P; ++t) c->hc.nnz_gh += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
+  c->hc.slots += (double)P;
   if (g) HIPCHK(c, hipMemcpyAsync(g, c->g, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (h) HIPCHK(c, hipMemcpyAsync(h, c->h, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (d) HIPCHK(c, hipMemcpyAsync(d, c->d, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  ApplyArgs ap{};
-  ap.dtx = c->dtx; ap.cache = c->cache; ap.y = c->y; ap.n = c->n; ap.w = c->w;
-  ap.perm = c->step_perm; ap.slot_lo = 0; ap.slot_hi = P; ap.d = c->d; ap.st = c->st;
-  ap.beta = o.beta;
-  HIPCHK(c, launch_apply(c->loss, ap, row_grid(std::max(c->n, P), 4096), c->stream));
   HIPCHK(c, hipMemcpyAsync(c->hst, c->st, sizeof(StepState), hipMemcpyDeviceToHost, c->stream));
   if (dtx)
     HIPCHK(c, hipMemcpyAsync(dtx, c->tmp_n, c->n * sizeof(double), hipMemcpyDeviceToHost,
@@ -698,7 +860,7 @@ extern "C" int pcdn_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, int32_t* 
   if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
   if (!perm_out || k < 0) return fail(c, PCDN_E_ARG, "bad argument");
   HIPCHK(c, hipSetDevice(c->device));
-  int rc = device_permutation(c, seed, k);
+  int rc = device_permutation(c, seed, k, nullptr);
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(perm_out, c->idx0, c->p * sizeof(int32_t), hipMemcpyDeviceToHost,
                            c->stream));
@@ -723,6 +885,7 @@ extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss
   rc = read_stats(c);
   if (rc) return rc;
   const Stats base = *c->hstats;
+  const pcdn_ctx::HostCounts hbase = c->hc;
   c->loss = loss;
   c->C = C;
 
@@ -750,19 +913,11 @@ extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss
   }
   c->has_state = true;
   int outer = 0;
-  const int64_t nb = (c->p + P - 1) / P;
   while (!converged && outer < o.max_outer) {
-    rc = device_permutation(c, o.seed, outer);
+    rc = run_outer(c, o, P, outer, 1);
     if (rc) return rc;
-    HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunk_slot, c->scan_tmp,
-                            c->stream));
-    for (int64_t t = 0; t < nb; ++t) {
-      const int64_t lo = t * P, hi = std::min(lo + P, c->p);
-      rc = run_bundle(c, o, c->idx0, lo, hi);
-      if (rc) return rc;
-    }
     ++outer;
-    rc = stopping_norm(c, o, c->w, &G);
+    rc = read_scalar(c, 0, &G);
     if (rc) return rc;
     if (!std::isfinite(G)) return fail(c, PCDN_E_NUMERIC, "non-finite subgradient norm");
     converged = G <= eps * G0;
@@ -783,16 +938,42 @@ extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss
     info->bundles = (int64_t)(s.bundles - base.bundles);
     info->ls_steps = (int64_t)(s.ls_steps - base.ls_steps);
     info->ls_fail = (int64_t)(s.ls_fail - base.ls_fail);
-    info->nnz_swept = (int64_t)(s.nnz_gh - base.nnz_gh);
+    info->nnz_swept = (int64_t)(c->hc.nnz_gh - hbase.nnz_gh);
     info->objective = F;
     info->subgrad = G0 == 0.0 ? 0.0 : G;
     info->subgrad0 = G0;
     double bytes = 0.0;
-    for (int k = 0; k < kProfClasses; ++k) bytes += alg_bytes_of(s, base, k, c->p);
+    for (int k = 0; k < kProfClasses; ++k) bytes += alg_bytes_of(s, base, c->hc, hbase, k, c->p);
     info->alg_bytes = bytes;
     info->seconds = std::chrono::duration<double>(t1 - t0).count();
   }
   return converged ? PCDN_OK : PCDN_NOT_CONVERGED;
+}
+
+extern "C" int pcdn_iterate(pcdn_ctx* c, int64_t P, int64_t k_first, int64_t count,
+                            const pcdn_opts* opts, double* subgrad) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded || !c->has_state) return fail(c, PCDN_E_STATE, "call pcdn_reset or pcdn_solve first");
+  if (P < 1 || P > c->p) return fail(c, PCDN_E_ARG, "bundle size P must lie in [1, p]");
+  if (k_first < 0 || count < 0) return fail(c, PCDN_E_ARG, "k_first and count must be >= 0");
+  Opts o;
+  int rc = resolve_opts(c, opts, &o);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  rc = run_outer(c, o, P, k_first, count);
+  if (rc) return rc;
+  if (subgrad) {
+    if (count == 0) {
+      rc = launch_stopping(c, o, c->w, nullptr);
+      if (rc) return rc;
+    }
+    rc = read_scalar(c, 0, subgrad);
+    if (rc) return rc;
+  } else {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->prof.mask) prof_harvest(c);
+  }
+  return PCDN_OK;
 }
 
 extern "C" int pcdn_get_w(pcdn_ctx* c, double* w_out) {
@@ -831,7 +1012,7 @@ extern "C" int pcdn_evaluate(pcdn_ctx* c, double* F, double* G) {
   return PCDN_OK;
 }
 
-extern "C" int pcdn_profile(pcdn_ctx* c, int enable) {
+extern "C" int pcdn_profile(pcdn_ctx* c, int mask) {
   if (!c) return PCDN_E_ARG;
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -840,10 +1021,11 @@ extern "C" int pcdn_profile(pcdn_ctx* c, int enable) {
     c->prof.ms[k] = 0.0;
     c->prof.launches[k] = 0;
   }
-  c->prof.on = enable != 0;
+  c->prof.mask = mask & ((1 << kProfClasses) - 1);
   int rc = read_stats(c);
   if (rc) return rc;
   c->prof_base = *c->hstats;
+  c->prof_hc = c->hc;
   return PCDN_OK;
 }
 
@@ -858,6 +1040,7 @@ extern "C" int pcdn_profile_read(pcdn_ctx* c, int which, double* ms, int64_t* la
   if (rc) return rc;
   if (ms) *ms = c->prof.ms[which];
   if (launches) *launches = c->prof.launches[which];
-  if (alg_bytes) *alg_bytes = alg_bytes_of(*c->hstats, c->prof_base, which, c->p);
+  if (alg_bytes)
+    *alg_bytes = alg_bytes_of(*c->hstats, c->prof_base, c->hc, c->prof_hc, which, c->p);
   return PCDN_OK;
 }

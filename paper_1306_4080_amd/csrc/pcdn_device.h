@@ -5,10 +5,15 @@
 //   state   : w fp64[p], cache fp64[n] (e^{w^T x_i} or b_i), dtx fp64[n]
 //             (kept all-zero between inner iterations)
 //   bundle  : perm int32[p] (slot -> feature), per-slot g, h, d, dterm fp64
-//   chunks  : every feature owns ceil(nnz_j / kChunk) >= 1 work chunks;
-//             cstart int32[p+1] is the exclusive scan of chunk counts in slot
-//             order and chunk_slot int32[] maps a chunk back to its slot, so a
-//             wavefront takes one chunk regardless of column length.
+//   chunks  : every feature owns ceil(nnz_j / kChunk) >= 1 work chunks.  For
+//             the slot order of one outer iteration, Chunk descriptors list
+//             them slot after slot (cstart int32[p+1] = first chunk of each
+//             slot), so a wavefront takes one chunk regardless of column length
+//             and reaches its nonzeros through one descriptor load.
+//
+// Synchronisation model: on gfx950 a device-scope fence or grid barrier costs
+// far more than a kernel boundary, so every global dependency of the bundle
+// sweep is a kernel boundary and no kernel waits on another block.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,22 +26,33 @@ constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kChunk = 1024;   // nonzeros per wavefront work item
 constexpr int kQMax = 32;      // line-search candidates evaluated per pass
+constexpr int kQGroup = 4;     // candidates per line-search thread (grid y covers the rest)
+constexpr int kLsGrid = 256;   // blocks of the line-search kernel (at most)
+constexpr int kSumGrid = 256;  // blocks of the first reduction level
 constexpr int kLogistic = 0;
 constexpr int kL2Svm = 1;
 
+struct Chunk {
+  int64_t klo;   // first nonzero of the chunk
+  int32_t len;   // nonzeros in the chunk (0 for an empty column)
+  int32_t slot;  // slot of the feature in the order
+  int32_t c0;    // first chunk of the feature
+  int32_t nch;   // chunks of the feature
+  int32_t feat;  // feature index
+  int32_t pad;
+};
+
 // Cumulative device-side counters (read back by the host at sync points).
+// Data-dependent counters, updated by one thread per block (never per
+// wavefront: same-address atomics from thousands of waves serialise).
 struct Stats {
   unsigned long long bundles;        // inner iterations
   unsigned long long ls_steps;       // candidates tested (q + 1, or max_ls on failure)
   unsigned long long ls_fail;        // inner iterations without an accepted step
-  unsigned long long nnz_gh;         // nonzeros read by the gradient sweep (bundles)
   unsigned long long nnz_scat_fused; // nonzeros scattered into d^T x by the sweep kernel
   unsigned long long nnz_scat_split; // nonzeros scattered by the split-column kernel
   unsigned long long rows_touched;   // rows with d^T x_i != 0, summed over bundles
-  unsigned long long slots;          // features swept (bundles)
-  unsigned long long nnz_stop;       // nonzeros read by stopping sweeps
-  unsigned long long stop_sweeps;    // stopping sweeps run
-  unsigned long long pad[6];
+  unsigned long long pad[10];
 };
 
 // Result of the line search of the current inner iteration.
@@ -48,24 +64,29 @@ struct StepState {
   int32_t pad;
 };
 
+// Outer-iteration counter used by graph replays: the partition of iteration
+// k is keyed by SplitMix64 output k of `seed`; the final reduction of every
+// stopping sweep advances k.
+struct IterState {
+  uint64_t seed;
+  int64_t k;
+};
+
 struct SweepArgs {
-  const int64_t* cp;
   const int32_t* ri;
   const float* v;
   const int8_t* y;
   const double* cache;
   const double* w;            // nullable: treated as zero
-  const int32_t* perm;        // slot -> feature
+  const Chunk* chunks;        // chunk descriptors of the order
   const int32_t* cstart;      // slot -> first chunk, p+1 entries
-  const int32_t* chunk_slot;  // chunk -> slot
   int64_t slot_lo, slot_hi;   // this launch covers slots [slot_lo, slot_hi)
-  double* g;                  // outputs indexed by slot - slot_lo
+  double* g;                  // per-slot outputs, indexed by the absolute slot
   double* h;
   double* d;
   double* dterm;              // g d + gamma h d^2 + |w + d| - |w|
   double* sg;                 // stopping mode: |grad^S_j F|
   double2* part;              // split-column partial sums, per chunk
-  unsigned* cnt;              // split-column arrival counters, per slot
   double* dtx;                // d^T x accumulator
   Stats* stats;
   double C, gamma, nu;
@@ -77,16 +98,14 @@ struct LsArgs {
   const int8_t* y;
   int64_t n;
   const double* w;
-  const int32_t* perm;
+  const int32_t* perm;        // slot -> feature
   int64_t slot_lo, slot_hi;
   const double* d;
   const double* dterm;
-  double* part;        // per block: kQMax line-loss sums, kQMax l1 sums, Delta
-  unsigned* counter;   // last-block ticket
-  StepState* st;
+  double* part;        // [value][block]: Q loss sums, Q l1 sums, Delta, touched rows
   Stats* stats;
-  double C, sigma, beta;
-  int q0, Q, max_ls;
+  double beta;
+  int Q;
 };
 
 struct ApplyArgs {
@@ -95,45 +114,72 @@ struct ApplyArgs {
   const int8_t* y;
   int64_t n;
   double* w;
-  const int32_t* perm;
+  const int32_t* perm;        // slot -> feature
   int64_t slot_lo, slot_hi;
   const double* d;
-  const StepState* st;
-  double beta;
+  const double* part;  // line-search partials
+  int ls_blocks;       // blocks that wrote them
+  StepState* st;
+  Stats* stats;
+  double C, sigma, beta;
+  int Q, max_ls;
+};
+
+// Single-workgroup schedule: bundles t_begin .. t_end-1 of one outer iteration
+// (bundle t = slots [tP, min((t+1)P, p)) of the order described by sw.chunks).
+struct NarrowArgs {
+  SweepArgs sw;
+  double* cache;       // the same arrays as sw.cache / sw.w, writable
+  double* w;
+  unsigned* rowflag;   // per-row "touched" flags, all zero between bundles
+  const int32_t* perm;
+  int64_t n, p, P;
+  int64_t t_begin, t_end;
+  StepState* st;       // record of the last bundle
+  Stats* stats;
+  double* dtx_copy;    // nullable: receives d^T x of the (last) bundle
+  double C, sigma, beta;
+  int max_ls;
 };
 
 // ---- host-callable launchers (pcdn_kernels.hip) -------------------------
 hipError_t launch_fill(double* a, double v, int64_t n, hipStream_t s);
-hipError_t launch_perm_keys(uint64_t stream_seed, int64_t p, uint32_t* keys, int32_t* idx,
-                            hipStream_t s);
+// Keys of the partition of outer iteration it->k (or of the given k if it is
+// null): upper 32 bits of SplitMix64 output j of the stream seeded with output
+// k of the stream seeded with `seed`.
+hipError_t launch_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
+                            uint32_t* keys, int32_t* idx, hipStream_t s);
 // Stable LSD radix sort of (keys, idx) by the 32-bit keys; results end in keys0/idx0.
-// hist needs 256 * ceil(p / 4096) + 1 ints, scan_tmp scan_tmp_ints(256 * ceil(p/4096) + 1).
 hipError_t launch_radix_sort(uint32_t* keys0, int32_t* idx0, uint32_t* keys1, int32_t* idx1,
                              int64_t p, int32_t* hist, int32_t* scan_tmp, hipStream_t s);
 int64_t scan_tmp_ints(int64_t m);
+int64_t radix_hist_ints(int64_t p);
 // Exclusive scan of in[0..m) into out[0..m], out[m] = total (int32).
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s);
-// Chunk bookkeeping for a slot order: nch[r] = max(1, ceil(len(perm[r]) / kChunk)),
-// cstart = scan(nch), chunk_slot filled.
+// Chunk descriptors for a slot order (perm null: identity).
 hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* nch,
-                         int32_t* cstart, int32_t* chunk_slot, int32_t* tmp, hipStream_t s);
-hipError_t launch_sweep(int loss, int stopping_mode, const SweepArgs& a, int grid, hipStream_t s);
-hipError_t launch_scatter_split(const SweepArgs& a, int grid, hipStream_t s);
-hipError_t launch_linesearch(int loss, const LsArgs& a, int grid, hipStream_t s);
-hipError_t launch_apply(int loss, const ApplyArgs& a, int grid, hipStream_t s);
-// Deterministic sum of a[0..m) into *out (two levels, fixed grid).
-hipError_t launch_sum(const double* a, int64_t m, double* part, unsigned* counter, double* out,
+                         int32_t* cstart, Chunk* chunks, int32_t* tmp, hipStream_t s);
+int sweep_grid(int64_t slots);
+hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
+hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
+int ls_grid(int64_t n);
+hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s);
+hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s);
+hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
+// Nonzeros of the features with d != 0 (slots 0..p of perm) into stats.
+hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
+                                int64_t p, Stats* stats, hipStream_t s);
+// Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
+hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s);
 hipError_t launch_loss_terms(int loss, const double* cache, const int8_t* y, int64_t n,
                              double* out, hipStream_t s);
 hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s);
-// z = X w by scattering every column (atomics), then the retained quantities.
-hipError_t launch_margins(const int64_t* cp, const int32_t* ri, const float* v, const double* w,
-                          const int32_t* id_cstart, const int32_t* id_slot, int64_t p, double* z,
-                          int grid, hipStream_t s);
+// z = X w by scattering every column (atomics) over identity-order chunks.
+hipError_t launch_margins(const int32_t* ri, const float* v, const double* w,
+                          const Chunk* id_chunks, int64_t total_chunks, double* z,
+                          hipStream_t s);
 hipError_t launch_cache_from_z(int loss, double* z_to_cache, const int8_t* y, int64_t n,
                                hipStream_t s);
-
-constexpr int kSumGrid = 256;
 
 }  // namespace pcdn

@@ -25,15 +25,21 @@ __device__ inline double wave_sum(double v) {
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ inline int wave_in_block() { return threadIdx.x / kWave; }
 
-// Sum over a 256-thread block; result valid in thread 0.  Fixed order.
+// Sum over a 256-thread block in a fixed order; every thread gets the result.
 __device__ inline double block_sum(double v, double* lds4) {
   v = wave_sum(v);
   if (lane_id() == 0) lds4[wave_in_block()] = v;
   __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0) r = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+  const double r = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
   __syncthreads();
   return r;
+}
+
+// Wave-uniform value as a scalar (lets descriptor loads become scalar loads).
+__device__ inline int64_t uniform(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // ---------------------------------------------------------------------------
@@ -75,8 +81,9 @@ __device__ inline void grad_hess_term(double c, int yi, double x, double& gs, do
   }
 }
 
-// log(A + B e^t) for A, B >= 0, A + B = 1, t <= 0.
-__device__ inline double log_blend(double A, double B, double t) {
+// log(A + B e^t) for A, B >= 0, A + B = 1, t <= 0.  Kept out of line: its
+// FP64 expm1/log1p bodies would otherwise be inlined at every call site.
+__device__ __attribute__((noinline)) double log_blend(double A, double B, double t) {
   const double u = B * expm1(t);
   return u >= -0.5 ? log1p(u) : log(A + B * exp(t));
 }
@@ -130,10 +137,17 @@ __global__ void k_fill(double* a, double v, int64_t n) {
     a[i] = v;
 }
 
-__global__ void k_perm_keys(uint64_t stream_seed, int64_t p, uint32_t* keys, int32_t* idx) {
+__global__ void k_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
+                            uint32_t* keys, int32_t* idx) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (it) {
+    seed = it->seed;
+    k = it->k;
+  }
+  // stream of outer iteration k: output k of the generator seeded with `seed`
+  const uint64_t stream = splitmix_out(seed + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull);
   if (j < p) {
-    const uint64_t state = stream_seed + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
+    const uint64_t state = stream + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
     keys[j] = (uint32_t)(splitmix_out(state) >> 32);
     idx[j] = (int32_t)j;
   }
@@ -291,7 +305,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------------------
-// chunk bookkeeping
+// chunk bookkeeping: nch = chunks per slot, cstart = exclusive scan, then one
+// descriptor per chunk
 // ---------------------------------------------------------------------------
 __global__ void k_chunk_count(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* nch) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -303,24 +318,40 @@ __global__ void k_chunk_count(const int32_t* perm, const int64_t* cp, int64_t p,
   }
 }
 
-__global__ void k_chunk_fill(const int32_t* cstart, int64_t p, int32_t* chunk_slot) {
+__global__ void k_chunk_fill(const int32_t* perm, const int64_t* cp, const int32_t* cstart,
+                             int64_t p, Chunk* chunks) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r < p)
-    for (int32_t c = cstart[r]; c < cstart[r + 1]; ++c) chunk_slot[c] = (int32_t)r;
+  if (r < p) {
+    const int32_t j = perm ? perm[r] : (int32_t)r;
+    const int64_t k0 = cp[j], len = cp[j + 1] - k0;
+    const int32_t c0 = cstart[r], nch = cstart[r + 1] - c0;
+    for (int32_t q = 0; q < nch; ++q) {
+      Chunk ch;
+      ch.klo = k0 + (int64_t)q * kChunk;
+      const int64_t rem = len - (int64_t)q * kChunk;
+      ch.len = (int32_t)(rem < kChunk ? (rem > 0 ? rem : 0) : kChunk);
+      ch.slot = (int32_t)r;
+      ch.c0 = c0;
+      ch.nch = nch;
+      ch.feat = j;
+      ch.pad = 0;
+      chunks[c0 + q] = ch;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// gradient / Hessian sweep over a bundle's columns (one wavefront per chunk).
-// Bundle mode: per-feature g, h, direction d and the Delta term; a feature
-// whose column fits one chunk also scatters d_j x^j into d^T x right away
-// (the second read of x^j comes from L2).  Split columns leave partial sums;
-// the last wavefront to finish a feature combines them in chunk order.
-// Stopping mode: |grad^S_j F| per feature, no direction, no scatter.
+// gradient / Hessian sweep over a bundle's columns, one wavefront per chunk.
+// Bundle mode: per-feature g, h, the direction d (eq. (5)) and its Delta
+// term; a feature whose column fits one chunk also scatters d_j x^j into
+// d^T x right away (the second read of x^j, Sec. 3.1, served from L2).  Split
+// columns only leave their partial sums; k_split finishes them after the
+// kernel boundary.  Stopping mode: |grad^S_j F| per feature, no direction.
 // ---------------------------------------------------------------------------
 constexpr int kUnroll = 4;
 
 template <int LOSS>
-__device__ inline void sweep_chunk(const SweepArgs& a, int64_t klo, int64_t khi, int lane,
+__device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi, int lane,
                                    double& gs, double& hs) {
   for (int64_t k = klo + lane; k < khi; k += (int64_t)kWave * kUnroll) {
     int32_t row[kUnroll];
@@ -345,7 +376,7 @@ __device__ inline void sweep_chunk(const SweepArgs& a, int64_t klo, int64_t khi,
   }
 }
 
-__device__ inline void scatter_chunk(const SweepArgs& a, int64_t klo, int64_t khi, int lane,
+__device__ inline void scatter_range(const SweepArgs& a, int64_t klo, int64_t khi, int lane,
                                      double dj) {
   for (int64_t k = klo + lane; k < khi; k += kWave) {
     const int32_t row = a.ri[k];
@@ -353,254 +384,250 @@ __device__ inline void scatter_chunk(const SweepArgs& a, int64_t klo, int64_t kh
   }
 }
 
+// g, h from the summed column terms; writes the per-feature outputs (lane 0)
+// and returns the direction (0 in stopping mode).
+template <int LOSS, bool STOP>
+__device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, double gs,
+                                        double hs, bool writer) {
+  double g, h;
+  if (LOSS == kLogistic) {
+    g = a.C * gs;
+    h = a.C * hs;
+  } else {
+    g = -2.0 * a.C * gs;
+    h = 2.0 * a.C * hs;
+  }
+  if (h <= 0.0) h += a.nu;
+  const double wj = a.w ? a.w[ch.feat] : 0.0;
+  const int64_t o = ch.slot;
+  if (STOP) {
+    if (writer) a.sg[o] = fabs(min_norm_subgradient(g, wj));
+    return 0.0;
+  }
+  const double dj = newton_dir(g, h, wj);
+  if (writer) {
+    a.g[o] = g;
+    a.h[o] = h;
+    a.d[o] = dj;
+    a.dterm[o] = g * dj + a.gamma * h * dj * dj + (fabs(wj + dj) - fabs(wj));
+  }
+  return dj;
+}
+
 template <int LOSS, bool STOP>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   const int lane = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t c_lo = a.cstart[a.slot_lo];
   const int32_t c_hi = a.cstart[a.slot_hi];
-  unsigned long long nnz_local = 0, nnz_scat = 0;
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
-    const int32_t r = a.chunk_slot[c];
-    const int32_t j = a.perm ? a.perm[r] : r;
-    const int64_t k0 = a.cp[j], k1 = a.cp[j + 1];
-    const int32_t c0 = a.cstart[r];
-    const int32_t nch = a.cstart[r + 1] - c0;
-    const int64_t klo = k0 + (int64_t)(c - c0) * kChunk;
-    const int64_t khi = klo + kChunk < k1 ? klo + kChunk : k1;
+    const Chunk ch = a.chunks[c];
+    const int64_t khi = ch.klo + ch.len;
     double gs = 0.0, hs = 0.0;
-    sweep_chunk<LOSS>(a, klo, khi, lane, gs, hs);
+    sweep_range<LOSS>(a, ch.klo, khi, lane, gs, hs);
     gs = wave_sum(gs);
     hs = wave_sum(hs);
-    nnz_local += (unsigned long long)(khi - klo);
-    if (nch > 1) {
+    if (ch.nch > 1) {
       if (lane == 0) a.part[c] = make_double2(gs, hs);
-      __threadfence();
-      unsigned ticket = 0;
-      if (lane == 0) ticket = atomicAdd(&a.cnt[r], 1u);
-      ticket = __shfl(ticket, 0, kWave);
-      if (ticket != (unsigned)(nch - 1)) continue;
-      __threadfence();
-      gs = 0.0;
-      hs = 0.0;
-      for (int32_t q = lane; q < nch; q += kWave) {
-        const double2 pq = a.part[c0 + q];
-        gs += pq.x;
-        hs += pq.y;
-      }
-      gs = wave_sum(gs);
-      hs = wave_sum(hs);
-      if (lane == 0) a.cnt[r] = 0u;
+      continue;
     }
-    double g, h;
-    if (LOSS == kLogistic) {
-      g = a.C * gs;
-      h = a.C * hs;
-    } else {
-      g = -2.0 * a.C * gs;
-      h = 2.0 * a.C * hs;
-    }
-    if (h <= 0.0) h += a.nu;
-    const double wj = a.w ? a.w[j] : 0.0;
-    const int64_t o = r - a.slot_lo;
-    if (STOP) {
-      if (lane == 0) a.sg[o] = fabs(min_norm_subgradient(g, wj));
-    } else {
-      const double dj = newton_dir(g, h, wj);
-      if (lane == 0) {
-        a.g[o] = g;
-        a.h[o] = h;
-        a.d[o] = dj;
-        a.dterm[o] = g * dj + a.gamma * h * dj * dj + (fabs(wj + dj) - fabs(wj));
-      }
-      if (nch == 1 && dj != 0.0) {
-        scatter_chunk(a, klo, khi, lane, dj);
-        nnz_scat += (unsigned long long)(khi - klo);
-      }
-    }
-  }
-  if (STOP && a.stats && blockIdx.x == 0 && threadIdx.x == 0)
-    atomicAdd(&a.stats->stop_sweeps, 1ull);
-  if (lane == 0 && a.stats) {
-    if (STOP) {
-      atomicAdd(&a.stats->nnz_stop, nnz_local);
-    } else {
-      atomicAdd(&a.stats->nnz_gh, nnz_local);
-      if (nnz_scat) atomicAdd(&a.stats->nnz_scat_fused, nnz_scat);
-    }
+    const double dj = finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0);
+    if (!STOP && dj != 0.0) scatter_range(a, ch.klo, khi, lane, dj);
   }
 }
 
-// d^T x scatter for columns split over several chunks (their direction is only
-// known once every chunk has been summed).
-__global__ __launch_bounds__(kBlock) void k_scatter_split(SweepArgs a) {
+// Split columns: every wavefront of a split feature sums all of its chunk
+// partials in chunk order (so all of them agree bit for bit), finishes the
+// feature, and scatters its own chunk.
+template <int LOSS, bool STOP>
+__global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
   const int lane = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
   const int32_t c_lo = a.cstart[a.slot_lo];
   const int32_t c_hi = a.cstart[a.slot_hi];
-  unsigned long long nnz_scat = 0;
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
-    const int32_t r = a.chunk_slot[c];
-    const int32_t c0 = a.cstart[r];
-    const int32_t nch = a.cstart[r + 1] - c0;
-    if (nch == 1) continue;
-    const double dj = a.d[r - a.slot_lo];
-    if (dj == 0.0) continue;
-    const int32_t j = a.perm ? a.perm[r] : r;
-    const int64_t k0 = a.cp[j], k1 = a.cp[j + 1];
-    const int64_t klo = k0 + (int64_t)(c - c0) * kChunk;
-    const int64_t khi = klo + kChunk < k1 ? klo + kChunk : k1;
-    scatter_chunk(a, klo, khi, lane, dj);
-    nnz_scat += (unsigned long long)(khi - klo);
+    const Chunk ch = a.chunks[c];
+    if (ch.nch == 1) continue;
+    double gs = 0.0, hs = 0.0;
+    for (int32_t q = lane; q < ch.nch; q += kWave) {
+      const double2 pq = a.part[ch.c0 + q];
+      gs += pq.x;
+      hs += pq.y;
+    }
+    gs = wave_sum(gs);
+    hs = wave_sum(hs);
+    const double dj = finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0 && c == ch.c0);
+    if (!STOP && dj != 0.0) scatter_range(a, ch.klo, ch.klo + ch.len, lane, dj);
   }
-  if (lane == 0 && nnz_scat && a.stats) atomicAdd(&a.stats->nnz_scat_split, nnz_scat);
+}
+
+// Nonzeros scattered into d^T x during one outer iteration (features with
+// d_j != 0; split columns counted apart), one atomic per block.
+__global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const int32_t* perm,
+                                                          const int64_t* cp, int64_t p,
+                                                          Stats* stats) {
+  __shared__ double lds4[kWavesPerBlock];
+  double fused = 0.0, split = 0.0;
+  for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < p;
+       r += (int64_t)gridDim.x * kBlock) {
+    if (d[r] == 0.0) continue;
+    const int32_t j = perm[r];
+    const double len = (double)(cp[j + 1] - cp[j]);
+    if (len > kChunk)
+      split += len;
+    else
+      fused += len;
+  }
+  fused = block_sum(fused, lds4);
+  split = block_sum(split, lds4);
+  if (threadIdx.x == 0) {
+    if (fused > 0.0) atomicAdd(&stats->nnz_scat_fused, (unsigned long long)fused);
+    if (split > 0.0) atomicAdd(&stats->nnz_scat_split, (unsigned long long)split);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// P-dimensional line search (Algorithm 4 with eq. (10)): every candidate
-// q0 .. q0+Q-1 in one pass over the samples.  The per-sample argument is
-// d^T x_i scaled by beta once per rejected candidate, as Algorithm 4 scales
-// its retained d^T x_i.  The last block to finish reduces the block partials
-// in block order and applies the Armijo test in increasing q.
+// P-dimensional line search (Algorithm 4 with eq. (10)): per block, partial
+// sums over the samples of the loss change for every candidate q < Q (the
+// per-sample argument is d^T x_i scaled by beta once per rejected candidate,
+// as Algorithm 4 scales its retained d^T x_i), of the l1 change of the bundle
+// coordinates, and of Delta.  Layout: part[v * gridDim.x + block].
 // ---------------------------------------------------------------------------
 template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
-  __shared__ double red[kWavesPerBlock][kQMax];
+  __shared__ double red[kWavesPerBlock][kQGroup];
   __shared__ double lds4[kWavesPerBlock];
-  __shared__ bool is_last;
   const int lane = lane_id(), wv = wave_in_block();
-  const int stride_blk = 2 * kQMax + 1;
-  double acc[kQMax];
+  const int G = gridDim.x;
+  const int q_lo = blockIdx.y * kQGroup;
+  const int nq = a.Q - q_lo < kQGroup ? a.Q - q_lo : kQGroup;
+  double beta_lo = 1.0;
+  for (int t = 0; t < q_lo; ++t) beta_lo *= a.beta;
+  double acc[kQGroup];
 #pragma unroll
-  for (int q = 0; q < kQMax; ++q) acc[q] = 0.0;
-  unsigned long long touched = 0;
+  for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
+  double touched = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n;
-       i += (int64_t)gridDim.x * kBlock) {
+       i += (int64_t)G * kBlock) {
     const double dl = a.dtx[i];
     if (dl == 0.0) continue;
-    ++touched;
+    touched += 1.0;
     const double c = a.cache[i];
     const int yi = a.y[i];
+    // d^T x_i scaled by beta once per rejected candidate before q_lo
     double s = dl;
-    for (int t = 0; t < a.q0; ++t) s *= a.beta;
+    for (int t = 0; t < q_lo; ++t) s *= a.beta;
 #pragma unroll
-    for (int q = 0; q < kQMax; ++q) {
-      if (q < a.Q) {
+    for (int q = 0; q < kQGroup; ++q) {
+      if (q < nq) {
         acc[q] += loss_delta<LOSS>(c, yi, s);
         s *= a.beta;
       }
     }
   }
-  // block partials of the loss sums
 #pragma unroll
-  for (int q = 0; q < kQMax; ++q) {
+  for (int q = 0; q < kQGroup; ++q) {
     const double v = wave_sum(acc[q]);
     if (lane == 0) red[wv][q] = v;
   }
   __syncthreads();
-  double* mine = a.part + (int64_t)blockIdx.x * stride_blk;
-  if (threadIdx.x < kQMax)
-    mine[threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                        red[3][threadIdx.x];
+  if (threadIdx.x < nq)
+    a.part[(int64_t)(q_lo + threadIdx.x) * G + blockIdx.x] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
   __syncthreads();
-  // l1 change of the bundle coordinates per candidate, and Delta
+  // l1 change of the bundle coordinates for these candidates
   double del = 0.0;
 #pragma unroll
-  for (int q = 0; q < kQMax; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
   const int64_t Pt = a.slot_hi - a.slot_lo;
   for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < Pt;
-       r += (int64_t)gridDim.x * kBlock) {
-    const double wj = a.w[a.perm[a.slot_lo + r]];
-    const double dj = a.d[r];
-    del += a.dterm[r];
-    double al = 1.0;
-    for (int t = 0; t < a.q0; ++t) al *= a.beta;
+       r += (int64_t)G * kBlock) {
+    const int64_t slot = a.slot_lo + r;
+    const double wj = a.w[a.perm[slot]];
+    const double dj = a.d[slot];
+    del += a.dterm[slot];
+    double al = beta_lo;
 #pragma unroll
-    for (int q = 0; q < kQMax; ++q) {
-      if (q < a.Q) {
+    for (int q = 0; q < kQGroup; ++q) {
+      if (q < nq) {
         acc[q] += fabs(wj + al * dj) - fabs(wj);
         al *= a.beta;
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < kQMax; ++q) {
+  for (int q = 0; q < kQGroup; ++q) {
     const double v = wave_sum(acc[q]);
     if (lane == 0) red[wv][q] = v;
   }
   __syncthreads();
-  if (threadIdx.x < kQMax)
-    mine[kQMax + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) +
-                                 red[2][threadIdx.x]) + red[3][threadIdx.x];
-  const double dsum = block_sum(del, lds4);
-  if (threadIdx.x == 0) mine[2 * kQMax] = dsum;
-  double tsum = block_sum((double)touched, lds4);
-  if (threadIdx.x == 0 && tsum > 0.0)
-    atomicAdd(&a.stats->rows_touched, (unsigned long long)tsum);
-  // last block decides
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(a.counter, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  __shared__ double tot[2 * kQMax + 1];
-  if (threadIdx.x < 2 * kQMax + 1) {
-    double s = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) s += a.part[(int64_t)b * stride_blk + threadIdx.x];
-    tot[threadIdx.x] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double Delta = tot[2 * kQMax];
-    double Dq = Delta, al = 1.0;
-    for (int t = 0; t < a.q0; ++t) {
-      Dq *= a.beta;
-      al *= a.beta;
+  if (threadIdx.x < nq)
+    a.part[(int64_t)(a.Q + q_lo + threadIdx.x) * G + blockIdx.x] =
+        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+  if (blockIdx.y == 0) {
+    const double dsum = block_sum(del, lds4);
+    const double tsum = block_sum(touched, lds4);
+    if (threadIdx.x == 0) {
+      a.part[(int64_t)(2 * a.Q) * G + blockIdx.x] = dsum;
+      a.part[(int64_t)(2 * a.Q + 1) * G + blockIdx.x] = tsum;
     }
-    int accepted = -1;
-    double dF = 0.0;
-    for (int q = 0; q < a.Q; ++q) {
-      const double f = tot[kQMax + q] + a.C * tot[q];
-      if (f <= a.sigma * Dq) {
-        accepted = a.q0 + q;
-        dF = f;
-        break;
-      }
-      Dq *= a.beta;
-      al *= a.beta;
-    }
-    a.st->q = accepted;
-    a.st->alpha = accepted >= 0 ? al : 0.0;
-    a.st->dF = dF;
-    a.st->delta = Delta;
-    atomicAdd(&a.stats->bundles, 1ull);
-    atomicAdd(&a.stats->ls_steps,
-              (unsigned long long)(accepted >= 0 ? accepted + 1 : a.max_ls));
-    if (accepted < 0) atomicAdd(&a.stats->ls_fail, 1ull);
-    atomicAdd(&a.stats->slots, (unsigned long long)Pt);
-    *a.counter = 0u;
   }
 }
 
+// Sum of row v of the line-search partials, same order in every block.
+__device__ inline double ls_total(const double* part, int v, int G, double* lds4) {
+  double x = 0.0;
+  for (int b = threadIdx.x; b < G; b += kBlock) x += part[(int64_t)v * G + b];
+  return block_sum(x, lds4);
+}
+
 // ---------------------------------------------------------------------------
-// accept: w_B += alpha d_B, retained quantities updated on the rows the bundle
-// touches (e^{w^T x} multiplicatively, Algorithm 4; b_i -= y_i alpha d^T x_i),
-// and d^T x cleared for the next inner iteration.
+// Armijo decision and accept.  Every block takes the decision itself from the
+// line-search partials (increasing q, eq. (6)'s test with Delta scaled by beta
+// per rejection, as in Algorithm 4), identically, so no block waits for
+// another.  Then w_B += alpha d_B and the retained quantities of the touched
+// rows are updated (e^{w^T x} multiplicatively, Algorithm 4; b_i -= y_i alpha
+// d^T x_i), and d^T x is cleared for the next inner iteration.
 // ---------------------------------------------------------------------------
 template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
-  const int q = a.st->q;
+  __shared__ double lds4[kWavesPerBlock];
+  const double Delta = ls_total(a.part, 2 * a.Q, a.ls_blocks, lds4);
+  double Dq = Delta, al = 1.0, dF = 0.0;
+  int q_acc = -1;
+  for (int q = 0; q < a.Q; ++q) {
+    const double sL = ls_total(a.part, q, a.ls_blocks, lds4);
+    const double l1 = ls_total(a.part, a.Q + q, a.ls_blocks, lds4);
+    const double f = l1 + a.C * sL;
+    if (f <= a.sigma * Dq) {
+      q_acc = q;
+      dF = f;
+      break;
+    }
+    Dq *= a.beta;
+    al *= a.beta;
+  }
+  const double touched = ls_total(a.part, 2 * a.Q + 1, a.ls_blocks, lds4);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.st->q = q_acc;
+    a.st->alpha = q_acc >= 0 ? al : 0.0;
+    a.st->dF = dF;
+    a.st->delta = Delta;
+    atomicAdd(&a.stats->bundles, 1ull);
+    atomicAdd(&a.stats->ls_steps, (unsigned long long)(q_acc >= 0 ? q_acc + 1 : a.max_ls));
+    if (q_acc < 0) atomicAdd(&a.stats->ls_fail, 1ull);
+    atomicAdd(&a.stats->rows_touched, (unsigned long long)touched);
+  }
   const int64_t tid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
   const int64_t nthr = (int64_t)gridDim.x * kBlock;
   for (int64_t i = tid; i < a.n; i += nthr) {
     const double dl = a.dtx[i];
     if (dl == 0.0) continue;
-    if (q >= 0) {
+    if (q_acc >= 0) {
       double s = dl;
-      for (int t = 0; t < q; ++t) s *= a.beta;
+      for (int t = 0; t < q_acc; ++t) s *= a.beta;
       if (LOSS == kLogistic)
         a.cache[i] *= exp(s);
       else
@@ -608,40 +635,312 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
     }
     a.dtx[i] = 0.0;
   }
-  if (q >= 0) {
-    const double alpha = a.st->alpha;
-    const int64_t Pt = a.slot_hi - a.slot_lo;
-    for (int64_t r = tid; r < Pt; r += nthr) {
-      const int32_t j = a.perm[a.slot_lo + r];
-      a.w[j] += alpha * a.d[r];
-    }
+  if (q_acc >= 0) {
+    for (int64_t r = a.slot_lo + tid; r < a.slot_hi; r += nthr) a.w[a.perm[r]] += al * a.d[r];
   }
 }
 
 // ---------------------------------------------------------------------------
-// deterministic sum, loss terms, margins
+// Single-workgroup schedule: one 1024-thread workgroup runs every bundle of an
+// outer iteration of one problem, phase after phase, with workgroup barriers
+// as the only synchronisation (no kernel boundary per bundle).  Same
+// arithmetic as the multi-kernel path.  Latency, not bandwidth, bounds small
+// bundles, so the phases are arranged to keep many independent loads in
+// flight:
+//  - columns of at most kShortCol nonzeros (most of a Zipf-distributed bundle)
+//    are swept by 8-lane groups, 128 chunks at once; longer chunks go to an
+//    LDS list that whole wavefronts take;
+//  - the scatter records every row it touches once (per-row flags) in an LDS
+//    list that also caches d^T x_i, so the line search and the apply visit
+//    only the touched rows;
+//  - candidates are tested one pass at a time in increasing q (Algorithm 4's
+//    order), so an accepted unit step costs a single pass.
+// d^T x is built with atomics (performed in L2) and read back with
+// L2-coherent atomic loads.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sum(const double* x, int64_t m, double* part,
-                                                unsigned* counter, double* out) {
+constexpr int kNarrowBlock = 1024;
+constexpr int kNarrowWaves = kNarrowBlock / kWave;
+constexpr int kGroup = 8;                          // lanes per short-column group
+constexpr int kGroups = kNarrowBlock / kGroup;
+constexpr int kShortCol = 16;                      // nonzeros of a "short" chunk
+constexpr int kLongCap = 2048;                     // long chunks listed per bundle
+constexpr int kTouchCap = 8192;                    // touched rows listed per bundle
+
+__device__ inline double block_sum16(double v, double* lds16) {
+  v = wave_sum(v);
+  if (lane_id() == 0) lds16[wave_in_block()] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < kNarrowWaves; ++k) r += lds16[k];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int m = kGroup / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+__device__ inline double load_l2(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct NarrowLds {
+  double lds16[kNarrowWaves];
+  int32_t n_long, n_touch;
+  int32_t long_list[kLongCap];
+  int32_t touch_row[kTouchCap];
+  double touch_dtx[kTouchCap];
+};
+
+// d_j x^j into d^T x; the first visit of a row appends it to the touched list.
+__device__ inline void scatter_flagged(const SweepArgs& a, unsigned* rowflag, NarrowLds& L,
+                                       int64_t k, double dj) {
+  const int32_t row = a.ri[k];
+  unsafeAtomicAdd(&a.dtx[row], dj * (double)a.v[k]);
+  if (atomicExch(&rowflag[row], 1u) == 0u) {
+    const int32_t slot = atomicAdd(&L.n_touch, 1);
+    if (slot < kTouchCap) L.touch_row[slot] = row;
+  }
+}
+
+template <int LOSS>
+__global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
+  __shared__ NarrowLds L;
+  SweepArgs a = na.sw;
+  const int lane = lane_id();
+  const int wave = (int)uniform(wave_in_block());
+  const int glane = threadIdx.x & (kGroup - 1);
+  const int group = threadIdx.x / kGroup;
+  double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0;
+  for (int64_t t = na.t_begin; t < na.t_end; ++t) {
+    const int64_t lo = t * na.P;
+    const int64_t hi = lo + na.P < na.p ? lo + na.P : na.p;
+    a.slot_lo = lo;
+    a.slot_hi = hi;
+    if (threadIdx.x == 0) {
+      L.n_long = 0;
+      L.n_touch = 0;
+    }
+    __syncthreads();
+    const int32_t c_lo = a.cstart[lo], c_hi = a.cstart[hi];
+    // 1a. short single-chunk columns, one 8-lane group each
+    for (int64_t c = c_lo + group; c < c_hi; c += kGroups) {
+      const Chunk ch = a.chunks[c];
+      if (ch.nch > 1 || ch.len > kShortCol) {
+        if (glane == 0) {
+          const int32_t s = atomicAdd(&L.n_long, 1);
+          if (s < kLongCap) L.long_list[s] = (int32_t)c;
+        }
+        continue;
+      }
+      double gs = 0.0, hs = 0.0;
+      for (int64_t k = ch.klo + glane; k < ch.klo + ch.len; k += kGroup) {
+        const int32_t row = a.ri[k];
+        grad_hess_term<LOSS>(a.cache[row], (int)a.y[row], (double)a.v[k], gs, hs);
+      }
+      gs = group_sum(gs);
+      hs = group_sum(hs);
+      const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, glane == 0);
+      if (dj != 0.0)
+        for (int64_t k = ch.klo + glane; k < ch.klo + ch.len; k += kGroup)
+          scatter_flagged(a, na.rowflag, L, k, dj);
+    }
+    __syncthreads();
+    // 1b. long chunks, one wavefront each (split columns leave partials)
+    const int32_t n_long = L.n_long;
+    bool any_split = false;
+    if (n_long > kLongCap) {
+      // more long chunks than the list holds: every wavefront walks all chunks
+      for (int64_t c = c_lo + wave; c < c_hi; c += kNarrowWaves) {
+        const Chunk ch = a.chunks[c];
+        if (ch.nch == 1 && ch.len <= kShortCol) continue;
+        double gs = 0.0, hs = 0.0;
+        sweep_range<LOSS>(a, ch.klo, ch.klo + ch.len, lane, gs, hs);
+        gs = wave_sum(gs);
+        hs = wave_sum(hs);
+        if (ch.nch > 1) {
+          if (lane == 0) a.part[c] = make_double2(gs, hs);
+          any_split = true;
+          continue;
+        }
+        const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, lane == 0);
+        if (dj != 0.0)
+          for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
+            scatter_flagged(a, na.rowflag, L, k, dj);
+      }
+    } else {
+      for (int32_t e = wave; e < n_long; e += kNarrowWaves) {
+        const int64_t c = L.long_list[e];
+        const Chunk ch = a.chunks[c];
+        double gs = 0.0, hs = 0.0;
+        sweep_range<LOSS>(a, ch.klo, ch.klo + ch.len, lane, gs, hs);
+        gs = wave_sum(gs);
+        hs = wave_sum(hs);
+        if (ch.nch > 1) {
+          if (lane == 0) a.part[c] = make_double2(gs, hs);
+          any_split = true;
+          continue;
+        }
+        const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, lane == 0);
+        if (dj != 0.0)
+          for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
+            scatter_flagged(a, na.rowflag, L, k, dj);
+      }
+    }
+    // 2. split columns: every wavefront of a split feature sums its partials
+    //    in chunk order, finishes the feature and scatters its own chunk
+    if (__syncthreads_or(any_split)) {
+      for (int64_t c = c_lo + wave; c < c_hi; c += kNarrowWaves) {
+        const Chunk ch = a.chunks[c];
+        if (ch.nch == 1) continue;
+        double gs = 0.0, hs = 0.0;
+        for (int32_t q = lane; q < ch.nch; q += kWave) {
+          const double2 pq = a.part[ch.c0 + q];
+          gs += pq.x;
+          hs += pq.y;
+        }
+        gs = wave_sum(gs);
+        hs = wave_sum(hs);
+        const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, lane == 0 && c == ch.c0);
+        if (dj != 0.0)
+          for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
+            scatter_flagged(a, na.rowflag, L, k, dj);
+      }
+    }
+    __syncthreads();
+    // touched rows: the LDS list (or every row if it overflowed)
+    const int32_t n_touch = L.n_touch;
+    const bool listed = n_touch <= kTouchCap;
+    if (listed)
+      for (int32_t e = threadIdx.x; e < n_touch; e += kNarrowBlock)
+        L.touch_dtx[e] = load_l2(&a.dtx[L.touch_row[e]]);
+    // 3. Delta, then candidates q = 0, 1, ... until the Armijo test holds
+    double del = 0.0;
+    for (int64_t r = lo + threadIdx.x; r < hi; r += kNarrowBlock) del += a.dterm[r];
+    const double Delta = block_sum16(del, L.lds16);
+    double Dq = Delta, al = 1.0, dF = 0.0;
+    int q_acc = -1;
+    for (int q = 0; q < na.max_ls; ++q) {
+      double sl = 0.0, l1 = 0.0, touched = 0.0;
+      if (listed) {
+        for (int32_t e = threadIdx.x; e < n_touch; e += kNarrowBlock) {
+          const double dl = L.touch_dtx[e];
+          if (dl == 0.0) continue;
+          touched += 1.0;
+          const int32_t i = L.touch_row[e];
+          double s = dl;
+          for (int u = 0; u < q; ++u) s *= na.beta;
+          sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], s);
+        }
+      } else {
+        for (int64_t i = threadIdx.x; i < na.n; i += kNarrowBlock) {
+          const double dl = load_l2(&a.dtx[i]);
+          if (dl == 0.0) continue;
+          touched += 1.0;
+          double s = dl;
+          for (int u = 0; u < q; ++u) s *= na.beta;
+          sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], s);
+        }
+      }
+      for (int64_t r = lo + threadIdx.x; r < hi; r += kNarrowBlock) {
+        const double wj = a.w[na.perm[r]];
+        l1 += fabs(wj + al * a.d[r]) - fabs(wj);
+      }
+      const double sL = block_sum16(sl, L.lds16);
+      const double L1 = block_sum16(l1, L.lds16);
+      if (q == 0) n_touched += block_sum16(touched, L.lds16);
+      const double f = L1 + na.C * sL;
+      if (f <= na.sigma * Dq) {
+        q_acc = q;
+        dF = f;
+        break;
+      }
+      Dq *= na.beta;
+      al *= na.beta;
+    }
+    n_bundles += 1.0;
+    n_ls += q_acc >= 0 ? q_acc + 1 : na.max_ls;
+    n_fail += q_acc < 0 ? 1.0 : 0.0;
+    // 4. accept: w, retained quantities, clear d^T x and the row flags
+    if (na.dtx_copy) {
+      for (int64_t i = threadIdx.x; i < na.n; i += kNarrowBlock)
+        na.dtx_copy[i] = load_l2(&a.dtx[i]);
+      __syncthreads();  // copied before any thread clears d^T x below
+    }
+    if (listed) {
+      for (int32_t e = threadIdx.x; e < n_touch; e += kNarrowBlock) {
+        const int32_t i = L.touch_row[e];
+        const double dl = L.touch_dtx[e];
+        if (q_acc >= 0 && dl != 0.0) {
+          double s = dl;
+          for (int u = 0; u < q_acc; ++u) s *= na.beta;
+          if (LOSS == kLogistic)
+            na.cache[i] *= exp(s);
+          else
+            na.cache[i] -= a.y[i] > 0 ? s : -s;
+        }
+        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        na.rowflag[i] = 0u;
+      }
+    } else {
+      for (int64_t i = threadIdx.x; i < na.n; i += kNarrowBlock) {
+        const double dl = load_l2(&a.dtx[i]);
+        if (q_acc >= 0 && dl != 0.0) {
+          double s = dl;
+          for (int u = 0; u < q_acc; ++u) s *= na.beta;
+          if (LOSS == kLogistic)
+            na.cache[i] *= exp(s);
+          else
+            na.cache[i] -= a.y[i] > 0 ? s : -s;
+        }
+        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        na.rowflag[i] = 0u;
+      }
+    }
+    if (q_acc >= 0)
+      for (int64_t r = lo + threadIdx.x; r < hi; r += kNarrowBlock) na.w[na.perm[r]] += al * a.d[r];
+    if (threadIdx.x == 0 && t == na.t_end - 1) {
+      na.st->q = q_acc;
+      na.st->alpha = q_acc >= 0 ? al : 0.0;
+      na.st->dF = dF;
+      na.st->delta = Delta;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && na.stats) {
+    atomicAdd(&na.stats->bundles, (unsigned long long)n_bundles);
+    atomicAdd(&na.stats->ls_steps, (unsigned long long)n_ls);
+    if (n_fail > 0.0) atomicAdd(&na.stats->ls_fail, (unsigned long long)n_fail);
+    atomicAdd(&na.stats->rows_touched, (unsigned long long)n_touched);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic sum (two kernels), loss terms, margins
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sum_partial(const double* x, int64_t m,
+                                                        double* part) {
   __shared__ double lds4[kWavesPerBlock];
-  __shared__ bool is_last;
   double s = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < m;
        i += (int64_t)gridDim.x * kBlock)
     s += x[i];
   s = block_sum(s, lds4);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_final(const double* part, int nb, double* out,
+                                                      IterState* it) {
+  __shared__ double lds4[kWavesPerBlock];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += part[b];
+  s = block_sum(s, lds4);
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int b = 0; b < (int)gridDim.x; ++b) t += part[b];
-    *out = t;
-    *counter = 0u;
+    *out = s;
+    if (it) it->k += 1;
   }
 }
 
@@ -664,22 +963,17 @@ __global__ void k_abs(const double* w, int64_t p, double* out) {
   if (j < p) out[j] = fabs(w[j]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_margins(const int64_t* cp, const int32_t* ri,
-                                                    const float* v, const double* w,
-                                                    const int32_t* cstart,
-                                                    const int32_t* chunk_slot, int64_t p,
-                                                    double* z) {
+__global__ __launch_bounds__(kBlock) void k_margins(const int32_t* ri, const float* v,
+                                                    const double* w, const Chunk* chunks,
+                                                    int64_t total, double* z) {
   const int lane = lane_id();
-  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  const int32_t c_hi = cstart[p];
-  for (int64_t c = wave; c < c_hi; c += nwaves) {
-    const int32_t j = chunk_slot[c];
-    const double wj = w[j];
+  for (int64_t c = wave; c < total; c += nwaves) {
+    const Chunk ch = chunks[c];
+    const double wj = w[ch.feat];
     if (wj == 0.0) continue;
-    const int64_t klo = cp[j] + (int64_t)(c - cstart[j]) * kChunk;
-    const int64_t khi = klo + kChunk < cp[j + 1] ? klo + kChunk : cp[j + 1];
-    for (int64_t k = klo + lane; k < khi; k += kWave)
+    for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
       unsafeAtomicAdd(&z[ri[k]], wj * (double)v[k]);
   }
 }
@@ -710,14 +1004,15 @@ hipError_t launch_fill(double* a, double v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_perm_keys(uint64_t stream_seed, int64_t p, uint32_t* keys, int32_t* idx,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s,
-                     stream_seed, p, keys, idx);
+hipError_t launch_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
+                            uint32_t* keys, int32_t* idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, it,
+                     seed, k, p, keys, idx);
   return hipGetLastError();
 }
 
 int64_t scan_tmp_ints(int64_t m) { return (m + kScanTile - 1) / kScanTile + 1; }
+int64_t radix_hist_ints(int64_t p) { return 256 * ((p + kSortTile - 1) / kSortTile) + 1; }
 
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s) {
   const int64_t nb = (m + kScanTile - 1) / kScanTile;
@@ -761,56 +1056,91 @@ hipError_t launch_radix_sort(uint32_t* keys0, int32_t* idx0, uint32_t* keys1, in
 }
 
 hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* nch,
-                         int32_t* cstart, int32_t* chunk_slot, int32_t* tmp, hipStream_t s) {
+                         int32_t* cstart, Chunk* chunks, int32_t* tmp, hipStream_t s) {
   hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
                      cp, p, nch);
   hipError_t e = launch_scan(nch, cstart, p, tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s,
-                     cstart, p, chunk_slot);
+  hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
+                     cp, cstart, p, chunks);
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(int loss, int stopping_mode, const SweepArgs& a, int grid,
-                        hipStream_t s) {
+int sweep_grid(int64_t slots) { return grid_for(slots, kWavesPerBlock, 8192); }
+
+hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s) {
+  const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
   if (loss == kLogistic) {
-    if (stopping_mode)
-      hipLaunchKernelGGL((k_sweep<kLogistic, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (stopping)
+      hipLaunchKernelGGL((k_sweep<kLogistic, true>), g, dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_sweep<kLogistic, false>), dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sweep<kLogistic, false>), g, dim3(kBlock), 0, s, a);
   } else {
-    if (stopping_mode)
-      hipLaunchKernelGGL((k_sweep<kL2Svm, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (stopping)
+      hipLaunchKernelGGL((k_sweep<kL2Svm, true>), g, dim3(kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_sweep<kL2Svm, false>), dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_sweep<kL2Svm, false>), g, dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_split(const SweepArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_split, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s) {
+  const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
+  if (loss == kLogistic) {
+    if (stopping)
+      hipLaunchKernelGGL((k_split<kLogistic, true>), g, dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_split<kLogistic, false>), g, dim3(kBlock), 0, s, a);
+  } else {
+    if (stopping)
+      hipLaunchKernelGGL((k_split<kL2Svm, true>), g, dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_split<kL2Svm, false>), g, dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_linesearch(int loss, const LsArgs& a, int grid, hipStream_t s) {
+int ls_grid(int64_t n) { return grid_for(n, kBlock, kLsGrid); }
+
+hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s) {
+  const dim3 g(ls_grid(a.n), (a.Q + kQGroup - 1) / kQGroup);
   if (loss == kLogistic)
-    hipLaunchKernelGGL(k_linesearch<kLogistic>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_linesearch<kLogistic>, g, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(k_linesearch<kL2Svm>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_linesearch<kL2Svm>, g, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_apply(int loss, const ApplyArgs& a, int grid, hipStream_t s) {
+hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s) {
+  const int64_t items = a.n > a.slot_hi - a.slot_lo ? a.n : a.slot_hi - a.slot_lo;
+  const dim3 g(grid_for(items, kBlock, 512));
   if (loss == kLogistic)
-    hipLaunchKernelGGL(k_apply<kLogistic>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_apply<kLogistic>, g, dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(k_apply<kL2Svm>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_apply<kL2Svm>, g, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_sum(const double* a, int64_t m, double* part, unsigned* counter, double* out,
+hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s) {
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_narrow<kLogistic>, dim3(1), dim3(kNarrowBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_narrow<kL2Svm>, dim3(1), dim3(kNarrowBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
+                                int64_t p, Stats* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_count, dim3(grid_for(p, kBlock, 64)), dim3(kBlock), 0, s, d, perm,
+                     cp, p, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_sum, dim3(kSumGrid), dim3(kBlock), 0, s, a, m, part, counter, out);
+  const int nb = grid_for(m, kBlock, kSumGrid);
+  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(kBlock), 0, s, x, m, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, out, it);
   return hipGetLastError();
 }
 
@@ -829,11 +1159,11 @@ hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_margins(const int64_t* cp, const int32_t* ri, const float* v, const double* w,
-                          const int32_t* id_cstart, const int32_t* id_slot, int64_t p, double* z,
-                          int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_margins, dim3(grid), dim3(kBlock), 0, s, cp, ri, v, w, id_cstart, id_slot,
-                     p, z);
+hipError_t launch_margins(const int32_t* ri, const float* v, const double* w,
+                          const Chunk* id_chunks, int64_t total_chunks, double* z,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_margins, dim3(grid_for(total_chunks, kWavesPerBlock, 8192)), dim3(kBlock),
+                     0, s, ri, v, w, id_chunks, total_chunks, z);
   return hipGetLastError();
 }
 
