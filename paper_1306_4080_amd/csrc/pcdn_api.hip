@@ -94,6 +94,12 @@ struct pcdn_ctx {
   int32_t* step_perm = nullptr;
   int64_t max_chunks = 0;
   double2* part = nullptr;
+  int64_t part_len = 0;
+  // X in partition order (single-workgroup schedule)
+  int32_t* pri = nullptr;
+  float* pv = nullptr;
+  int64_t* poff = nullptr;
+  int32_t* off32 = nullptr;
 
   // reductions and small device records
   double* ls_part = nullptr;
@@ -178,6 +184,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
   dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
   dfree(c->part); dfree(c->ls_part);
+  dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32);
   drop_graph(c);
   c->loaded = false;
   c->has_state = false;
@@ -454,23 +461,29 @@ int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, const IterState* i
 }
 
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P) {
+  if (P > kNarrowMaxP || c->nnz >= ((int64_t)1 << 31)) return false;
   if (o.schedule == PCDN_SCHED_NARROW) return true;
   if (o.schedule == PCDN_SCHED_WIDE) return false;
   return (double)c->nnz * (double)P / (double)c->p <= kNarrowMaxBundleNnz;
 }
 
 // Bundles [t_begin, t_end) of size P over the order `perm` (descriptors in
-// c->chunks / c->cstart) in one workgroup.
+// c->chunks / c->cstart, p_slots slots) in one workgroup, after copying X into
+// that order.
 int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
                           int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
+  HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
+                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->stream));
   NarrowArgs na{};
   na.sw = sweep_args(c, o);
-  na.sw.chunks = c->chunks;
-  na.sw.cstart = c->cstart;
   na.cache = c->cache;
   na.w = c->w;
   na.rowflag = c->rowflag;
   na.perm = perm;
+  na.poff = c->poff;
+  na.pri = c->pri;
+  na.pv = c->pv;
+  na.part = c->part;
   na.n = c->n;
   na.p = p_slots;
   na.P = P;
@@ -763,7 +776,12 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->id_cstart, p + 1);
   ALLOC(c, c->id_chunks, max_chunks);
   ALLOC(c, c->step_perm, p);
-  ALLOC(c, c->part, max_chunks);
+  c->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
+  ALLOC(c, c->part, c->part_len);
+  ALLOC(c, c->pri, nnz);
+  ALLOC(c, c->pv, nnz);
+  ALLOC(c, c->poff, p + 1);
+  ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->ls_part, (size_t)kLsGrid * (2 * kQMax + 2));
   const hipMemcpyKind kind = ptr_kind == 1 ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIPCHK(c, hipMemcpyAsync(c->cp, col_ptr, (p + 1) * sizeof(int64_t), kind, c->stream));

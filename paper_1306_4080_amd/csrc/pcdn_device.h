@@ -126,13 +126,19 @@ struct ApplyArgs {
 };
 
 // Single-workgroup schedule: bundles t_begin .. t_end-1 of one outer iteration
-// (bundle t = slots [tP, min((t+1)P, p)) of the order described by sw.chunks).
+// (bundle t = slots [tP, min((t+1)P, p))), with X in partition order: the
+// nonzeros of slot r are pri/pv[poff[r] .. poff[r+1]).  P <= kNarrowMaxP.
+constexpr int kNarrowMaxP = 1024;
 struct NarrowArgs {
-  SweepArgs sw;
+  SweepArgs sw;        // ri/v unused; cache, y, g, h, d, dtx, C, gamma, nu used
   double* cache;       // the same arrays as sw.cache / sw.w, writable
   double* w;
   unsigned* rowflag;   // per-row "touched" flags, all zero between bundles
   const int32_t* perm;
+  const int64_t* poff; // p+1 partition-order offsets
+  const int32_t* pri;
+  const float* pv;
+  double2* part;       // global chunk partials when a bundle has > 32768 nonzeros
   int64_t n, p, P;
   int64_t t_begin, t_end;
   StepState* st;       // record of the last bundle
@@ -166,6 +172,12 @@ int ls_grid(int64_t n);
 hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s);
 hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s);
 hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
+// X in partition order for the single-workgroup schedule (needs nnz < 2^31).
+// `chunks`/`cstart` are the chunk descriptors of the same slot order.
+hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
+                          const float* v, const Chunk* chunks, const int32_t* cstart,
+                          int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
+                          int32_t* pri, float* pv, hipStream_t s);
 // Nonzeros of the features with d != 0 (slots 0..p of perm) into stats.
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
                                 int64_t p, Stats* stats, hipStream_t s);

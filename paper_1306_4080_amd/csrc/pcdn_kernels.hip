@@ -644,27 +644,26 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
 // Single-workgroup schedule: one 1024-thread workgroup runs every bundle of an
 // outer iteration of one problem, phase after phase, with workgroup barriers
 // as the only synchronisation (no kernel boundary per bundle).  Same
-// arithmetic as the multi-kernel path.  Latency, not bandwidth, bounds small
-// bundles, so the phases are arranged to keep many independent loads in
-// flight:
-//  - columns of at most kShortCol nonzeros (most of a Zipf-distributed bundle)
-//    are swept by 8-lane groups, 128 chunks at once; longer chunks go to an
-//    LDS list that whole wavefronts take;
-//  - the scatter records every row it touches once (per-row flags) in an LDS
-//    list that also caches d^T x_i, so the line search and the apply visit
-//    only the touched rows;
+// arithmetic as the multi-kernel path.  Small bundles are bound by the
+// latency of dependent memory accesses, so a bundle is arranged to need few:
+//  - X has been copied into partition order (k_permute), so a bundle's
+//    nonzeros are one contiguous range: thread v takes nonzero v, and a
+//    segmented wavefront scan (keys = slot) sums g_j, h_j; slots that cross a
+//    64-nonzero chunk are completed from LDS partials in chunk order, so the
+//    sums are deterministic;
+//  - the thread that first touches a row in the scatter (per-row flag) stores
+//    the row's retained quantity and label, already in its registers, in an
+//    LDS list; the line search and the apply then run from LDS, and the only
+//    reads after the scatter are the d^T x values (built with L2 atomics);
 //  - candidates are tested one pass at a time in increasing q (Algorithm 4's
 //    order), so an accepted unit step costs a single pass.
-// d^T x is built with atomics (performed in L2) and read back with
-// L2-coherent atomic loads.
+// Overflowing any LDS list falls back to global-memory passes (correct, slower).
 // ---------------------------------------------------------------------------
 constexpr int kNarrowBlock = 1024;
 constexpr int kNarrowWaves = kNarrowBlock / kWave;
-constexpr int kGroup = 8;                          // lanes per short-column group
-constexpr int kGroups = kNarrowBlock / kGroup;
-constexpr int kShortCol = 16;                      // nonzeros of a "short" chunk
-constexpr int kLongCap = 2048;                     // long chunks listed per bundle
-constexpr int kTouchCap = 8192;                    // touched rows listed per bundle
+constexpr int kNarrowRegRounds = 2;    // rounds of nonzeros kept in registers
+constexpr int kNarrowChunkCap = 512;   // 64-nonzero chunks with LDS partials
+constexpr int kTouchCap = 4096;        // touched rows listed per bundle
 
 __device__ inline double block_sum16(double v, double* lds16) {
   v = wave_sum(v);
@@ -677,178 +676,226 @@ __device__ inline double block_sum16(double v, double* lds16) {
   return r;
 }
 
-__device__ inline double group_sum(double v) {
-#pragma unroll
-  for (int m = kGroup / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
-}
-
 __device__ inline double load_l2(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __attribute__((noinline)) double exp_out_of_line(double x) { return exp(x); }
+
 struct NarrowLds {
   double lds16[kNarrowWaves];
-  int32_t n_long, n_touch;
-  int32_t long_list[kLongCap];
-  int32_t touch_row[kTouchCap];
-  double touch_dtx[kTouchCap];
+  int32_t n_touch;
+  int32_t off[kNarrowMaxP + 1];        // nonzero offsets of the bundle's slots
+  int32_t feat[kNarrowMaxP];
+  double w[kNarrowMaxP];
+  double d[kNarrowMaxP];
+  double2 acc[kNarrowMaxP];            // (sum g terms, sum h terms) per slot
+  double2 pf[kNarrowChunkCap];         // first segment of each 64-nonzero chunk
+  double2 pl[kNarrowChunkCap];         // last segment of each chunk
+  int32_t t_row[kTouchCap];
+  int8_t t_y[kTouchCap];
+  double t_c[kTouchCap];
+  double t_dtx[kTouchCap];
 };
 
-// d_j x^j into d^T x; the first visit of a row appends it to the touched list.
-__device__ inline void scatter_flagged(const SweepArgs& a, unsigned* rowflag, NarrowLds& L,
-                                       int64_t k, double dj) {
-  const int32_t row = a.ri[k];
-  unsafeAtomicAdd(&a.dtx[row], dj * (double)a.v[k]);
+// slot of bundle nonzero v: the largest s with off[s] <= v
+__device__ inline int32_t slot_of(const int32_t* off, int32_t nslots, int32_t v) {
+  int32_t lo = 0, hi = nslots;  // off[lo] <= v < off[hi]
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ inline void touch_row(NarrowLds& L, unsigned* rowflag, int32_t row, double c, int yi) {
   if (atomicExch(&rowflag[row], 1u) == 0u) {
-    const int32_t slot = atomicAdd(&L.n_touch, 1);
-    if (slot < kTouchCap) L.touch_row[slot] = row;
+    const int32_t e = atomicAdd(&L.n_touch, 1);
+    if (e < kTouchCap) {
+      L.t_row[e] = row;
+      L.t_c[e] = c;
+      L.t_y[e] = (int8_t)yi;
+    }
   }
 }
 
 template <int LOSS>
 __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
   __shared__ NarrowLds L;
-  SweepArgs a = na.sw;
+  const SweepArgs& a = na.sw;
   const int lane = lane_id();
-  const int wave = (int)uniform(wave_in_block());
-  const int glane = threadIdx.x & (kGroup - 1);
-  const int group = threadIdx.x / kGroup;
+  const int tid = threadIdx.x;
   double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0;
   for (int64_t t = na.t_begin; t < na.t_end; ++t) {
     const int64_t lo = t * na.P;
     const int64_t hi = lo + na.P < na.p ? lo + na.P : na.p;
-    a.slot_lo = lo;
-    a.slot_hi = hi;
-    if (threadIdx.x == 0) {
-      L.n_long = 0;
-      L.n_touch = 0;
+    const int32_t ns = (int32_t)(hi - lo);
+    const int64_t base = na.poff[lo];
+    // bundle metadata into LDS; clear the per-slot sums
+    for (int32_t s = tid; s <= ns; s += kNarrowBlock) L.off[s] = (int32_t)(na.poff[lo + s] - base);
+    for (int32_t s = tid; s < ns; s += kNarrowBlock) {
+      const int32_t j = na.perm[lo + s];
+      L.feat[s] = j;
+      L.w[s] = na.w[j];
+      L.acc[s] = make_double2(0.0, 0.0);
     }
+    if (tid == 0) L.n_touch = 0;
     __syncthreads();
-    const int32_t c_lo = a.cstart[lo], c_hi = a.cstart[hi];
-    // 1a. short single-chunk columns, one 8-lane group each
-    for (int64_t c = c_lo + group; c < c_hi; c += kGroups) {
-      const Chunk ch = a.chunks[c];
-      if (ch.nch > 1 || ch.len > kShortCol) {
-        if (glane == 0) {
-          const int32_t s = atomicAdd(&L.n_long, 1);
-          if (s < kLongCap) L.long_list[s] = (int32_t)c;
-        }
-        continue;
+    const int32_t nb = L.off[ns];
+    const int32_t nchunks = (nb + kWave - 1) / kWave;
+    double2* pf = nchunks <= kNarrowChunkCap ? L.pf : na.part;
+    double2* pl = nchunks <= kNarrowChunkCap ? L.pl : na.part + nchunks;
+    // 1. sweep: nonzero v = r0 + tid; segmented wavefront sums per slot
+    int32_t rrow[kNarrowRegRounds];
+    float rx[kNarrowRegRounds];
+    double rc[kNarrowRegRounds];
+    int ry[kNarrowRegRounds];
+    int32_t rs[kNarrowRegRounds];
+    int round = 0;
+    for (int32_t r0 = 0; r0 < nb; r0 += kNarrowBlock, ++round) {
+      const int32_t v = r0 + tid;
+      const bool valid = v < nb;
+      int32_t row = 0, s = -1;
+      float x = 0.0f;
+      double c = 0.0;
+      int yi = 0;
+      if (valid) {
+        row = na.pri[base + v];
+        x = na.pv[base + v];
+        s = slot_of(L.off, ns, v);
+        c = a.cache[row];
+        yi = (int)a.y[row];
       }
-      double gs = 0.0, hs = 0.0;
-      for (int64_t k = ch.klo + glane; k < ch.klo + ch.len; k += kGroup) {
-        const int32_t row = a.ri[k];
-        grad_hess_term<LOSS>(a.cache[row], (int)a.y[row], (double)a.v[k], gs, hs);
+      if (round < kNarrowRegRounds) {
+        rrow[round] = row;
+        rx[round] = x;
+        rc[round] = c;
+        ry[round] = yi;
+        rs[round] = s;
       }
-      gs = group_sum(gs);
-      hs = group_sum(hs);
-      const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, glane == 0);
-      if (dj != 0.0)
-        for (int64_t k = ch.klo + glane; k < ch.klo + ch.len; k += kGroup)
-          scatter_flagged(a, na.rowflag, L, k, dj);
-    }
-    __syncthreads();
-    // 1b. long chunks, one wavefront each (split columns leave partials)
-    const int32_t n_long = L.n_long;
-    bool any_split = false;
-    if (n_long > kLongCap) {
-      // more long chunks than the list holds: every wavefront walks all chunks
-      for (int64_t c = c_lo + wave; c < c_hi; c += kNarrowWaves) {
-        const Chunk ch = a.chunks[c];
-        if (ch.nch == 1 && ch.len <= kShortCol) continue;
-        double gs = 0.0, hs = 0.0;
-        sweep_range<LOSS>(a, ch.klo, ch.klo + ch.len, lane, gs, hs);
-        gs = wave_sum(gs);
-        hs = wave_sum(hs);
-        if (ch.nch > 1) {
-          if (lane == 0) a.part[c] = make_double2(gs, hs);
-          any_split = true;
-          continue;
+      double g = 0.0, h = 0.0;
+      if (valid) grad_hess_term<LOSS>(c, yi, (double)x, g, h);
+      // inclusive segmented scan over the wavefront (slots ascend along lanes)
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const double go = __shfl_up(g, o, kWave);
+        const double ho = __shfl_up(h, o, kWave);
+        const int32_t so = __shfl_up(s, o, kWave);
+        if (lane >= o && so == s) {
+          g += go;
+          h += ho;
         }
-        const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, lane == 0);
-        if (dj != 0.0)
-          for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
-            scatter_flagged(a, na.rowflag, L, k, dj);
       }
-    } else {
-      for (int32_t e = wave; e < n_long; e += kNarrowWaves) {
-        const int64_t c = L.long_list[e];
-        const Chunk ch = a.chunks[c];
-        double gs = 0.0, hs = 0.0;
-        sweep_range<LOSS>(a, ch.klo, ch.klo + ch.len, lane, gs, hs);
-        gs = wave_sum(gs);
-        hs = wave_sum(hs);
-        if (ch.nch > 1) {
-          if (lane == 0) a.part[c] = make_double2(gs, hs);
-          any_split = true;
-          continue;
-        }
-        const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, lane == 0);
-        if (dj != 0.0)
-          for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
-            scatter_flagged(a, na.rowflag, L, k, dj);
-      }
-    }
-    // 2. split columns: every wavefront of a split feature sums its partials
-    //    in chunk order, finishes the feature and scatters its own chunk
-    if (__syncthreads_or(any_split)) {
-      for (int64_t c = c_lo + wave; c < c_hi; c += kNarrowWaves) {
-        const Chunk ch = a.chunks[c];
-        if (ch.nch == 1) continue;
-        double gs = 0.0, hs = 0.0;
-        for (int32_t q = lane; q < ch.nch; q += kWave) {
-          const double2 pq = a.part[ch.c0 + q];
-          gs += pq.x;
-          hs += pq.y;
-        }
-        gs = wave_sum(gs);
-        hs = wave_sum(hs);
-        const double dj = finish_feature<LOSS, false>(a, ch, gs, hs, lane == 0 && c == ch.c0);
-        if (dj != 0.0)
-          for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
-            scatter_flagged(a, na.rowflag, L, k, dj);
+      const int32_t s_next = __shfl_down(s, 1, kWave);
+      const bool seg_end = valid && (lane == kWave - 1 || s_next != s);
+      if (seg_end) {
+        const int32_t m = v / kWave;                 // chunk of this nonzero
+        const int32_t cbeg = m * kWave, cend = cbeg + kWave - 1;
+        const bool left_open = L.off[s] < cbeg;
+        const bool right_open = L.off[s + 1] - 1 > cend;
+        if (!left_open && !right_open)
+          L.acc[s] = make_double2(g, h);             // the slot lies in this chunk
+        else if (left_open)
+          pf[m] = make_double2(g, h);                // first segment of chunk m
+        else
+          pl[m] = make_double2(g, h);                // last segment of chunk m
       }
     }
     __syncthreads();
-    // touched rows: the LDS list (or every row if it overflowed)
+    // slots spanning several chunks: head (pl) + middle chunks (pf) + tail (pf)
+    for (int32_t s = tid; s < ns; s += kNarrowBlock) {
+      const int32_t b0 = L.off[s], b1 = L.off[s + 1];
+      if (b1 - b0 == 0) continue;
+      const int32_t m1 = b0 / kWave, m2 = (b1 - 1) / kWave;
+      if (m1 == m2) continue;
+      double2 tot = pl[m1];
+      for (int32_t m = m1 + 1; m <= m2; ++m) {
+        tot.x += pf[m].x;
+        tot.y += pf[m].y;
+      }
+      L.acc[s] = tot;
+    }
+    __syncthreads();
+    // finish each slot: g, h, d (eqs. (4)-(5), (11)), Delta term
+    double del = 0.0;
+    for (int32_t s = tid; s < ns; s += kNarrowBlock) {
+      double g, h;
+      if (LOSS == kLogistic) {
+        g = na.C * L.acc[s].x;
+        h = na.C * L.acc[s].y;
+      } else {
+        g = -2.0 * na.C * L.acc[s].x;
+        h = 2.0 * na.C * L.acc[s].y;
+      }
+      if (h <= 0.0) h += a.nu;
+      const double wj = L.w[s];
+      const double dj = newton_dir(g, h, wj);
+      L.d[s] = dj;
+      del += g * dj + a.gamma * h * dj * dj + (fabs(wj + dj) - fabs(wj));
+      a.g[lo + s] = g;
+      a.h[lo + s] = h;
+      a.d[lo + s] = dj;
+    }
+    const double Delta = block_sum16(del, L.lds16);   // also publishes L.d
+    // 2. scatter d_j x_ij into d^T x; list touched rows with their retained
+    //    quantity and label
+    round = 0;
+    for (int32_t r0 = 0; r0 < nb; r0 += kNarrowBlock, ++round) {
+      const int32_t v = r0 + tid;
+      if (v >= nb) continue;
+      int32_t row, s;
+      float x;
+      double c;
+      int yi;
+      if (round < kNarrowRegRounds) {
+        row = rrow[round];
+        x = rx[round];
+        c = rc[round];
+        yi = ry[round];
+        s = rs[round];
+      } else {
+        row = na.pri[base + v];
+        x = na.pv[base + v];
+        s = slot_of(L.off, ns, v);
+        c = a.cache[row];
+        yi = (int)a.y[row];
+      }
+      const double dj = L.d[s];
+      if (dj == 0.0) continue;
+      unsafeAtomicAdd(&a.dtx[row], dj * (double)x);
+      touch_row(L, na.rowflag, row, c, yi);
+    }
+    __syncthreads();
     const int32_t n_touch = L.n_touch;
     const bool listed = n_touch <= kTouchCap;
     if (listed)
-      for (int32_t e = threadIdx.x; e < n_touch; e += kNarrowBlock)
-        L.touch_dtx[e] = load_l2(&a.dtx[L.touch_row[e]]);
-    // 3. Delta, then candidates q = 0, 1, ... until the Armijo test holds
-    double del = 0.0;
-    for (int64_t r = lo + threadIdx.x; r < hi; r += kNarrowBlock) del += a.dterm[r];
-    const double Delta = block_sum16(del, L.lds16);
+      for (int32_t e = tid; e < n_touch; e += kNarrowBlock) L.t_dtx[e] = load_l2(&a.dtx[L.t_row[e]]);
+    __syncthreads();
+    // 3. candidates q = 0, 1, ... until the Armijo test (eq. (6)) holds
     double Dq = Delta, al = 1.0, dF = 0.0;
     int q_acc = -1;
     for (int q = 0; q < na.max_ls; ++q) {
       double sl = 0.0, l1 = 0.0, touched = 0.0;
       if (listed) {
-        for (int32_t e = threadIdx.x; e < n_touch; e += kNarrowBlock) {
-          const double dl = L.touch_dtx[e];
+        for (int32_t e = tid; e < n_touch; e += kNarrowBlock) {
+          const double dl = L.t_dtx[e];
           if (dl == 0.0) continue;
           touched += 1.0;
-          const int32_t i = L.touch_row[e];
-          double s = dl;
-          for (int u = 0; u < q; ++u) s *= na.beta;
-          sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], s);
+          double sc = dl;
+          for (int u = 0; u < q; ++u) sc *= na.beta;
+          sl += loss_delta<LOSS>(L.t_c[e], (int)L.t_y[e], sc);
         }
       } else {
-        for (int64_t i = threadIdx.x; i < na.n; i += kNarrowBlock) {
+        for (int64_t i = tid; i < na.n; i += kNarrowBlock) {
           const double dl = load_l2(&a.dtx[i]);
           if (dl == 0.0) continue;
           touched += 1.0;
-          double s = dl;
-          for (int u = 0; u < q; ++u) s *= na.beta;
-          sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], s);
+          double sc = dl;
+          for (int u = 0; u < q; ++u) sc *= na.beta;
+          sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], sc);
         }
       }
-      for (int64_t r = lo + threadIdx.x; r < hi; r += kNarrowBlock) {
-        const double wj = a.w[na.perm[r]];
-        l1 += fabs(wj + al * a.d[r]) - fabs(wj);
-      }
+      for (int32_t s = tid; s < ns; s += kNarrowBlock) l1 += fabs(L.w[s] + al * L.d[s]) - fabs(L.w[s]);
       const double sL = block_sum16(sl, L.lds16);
       const double L1 = block_sum16(l1, L.lds16);
       if (q == 0) n_touched += block_sum16(touched, L.lds16);
@@ -864,45 +911,44 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
     n_bundles += 1.0;
     n_ls += q_acc >= 0 ? q_acc + 1 : na.max_ls;
     n_fail += q_acc < 0 ? 1.0 : 0.0;
-    // 4. accept: w, retained quantities, clear d^T x and the row flags
+    // 4. accept: w, retained quantities; clear d^T x and the row flags
     if (na.dtx_copy) {
-      for (int64_t i = threadIdx.x; i < na.n; i += kNarrowBlock)
-        na.dtx_copy[i] = load_l2(&a.dtx[i]);
+      for (int64_t i = tid; i < na.n; i += kNarrowBlock) na.dtx_copy[i] = load_l2(&a.dtx[i]);
       __syncthreads();  // copied before any thread clears d^T x below
     }
     if (listed) {
-      for (int32_t e = threadIdx.x; e < n_touch; e += kNarrowBlock) {
-        const int32_t i = L.touch_row[e];
-        const double dl = L.touch_dtx[e];
+      for (int32_t e = tid; e < n_touch; e += kNarrowBlock) {
+        const int32_t i = L.t_row[e];
+        const double dl = L.t_dtx[e];
         if (q_acc >= 0 && dl != 0.0) {
-          double s = dl;
-          for (int u = 0; u < q_acc; ++u) s *= na.beta;
+          double sc = dl;
+          for (int u = 0; u < q_acc; ++u) sc *= na.beta;
           if (LOSS == kLogistic)
-            na.cache[i] *= exp(s);
+            na.cache[i] = L.t_c[e] * exp_out_of_line(sc);
           else
-            na.cache[i] -= a.y[i] > 0 ? s : -s;
+            na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sc : -sc);
         }
         __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         na.rowflag[i] = 0u;
       }
     } else {
-      for (int64_t i = threadIdx.x; i < na.n; i += kNarrowBlock) {
+      for (int64_t i = tid; i < na.n; i += kNarrowBlock) {
         const double dl = load_l2(&a.dtx[i]);
         if (q_acc >= 0 && dl != 0.0) {
-          double s = dl;
-          for (int u = 0; u < q_acc; ++u) s *= na.beta;
+          double sc = dl;
+          for (int u = 0; u < q_acc; ++u) sc *= na.beta;
           if (LOSS == kLogistic)
-            na.cache[i] *= exp(s);
+            na.cache[i] *= exp_out_of_line(sc);
           else
-            na.cache[i] -= a.y[i] > 0 ? s : -s;
+            na.cache[i] -= a.y[i] > 0 ? sc : -sc;
         }
         __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         na.rowflag[i] = 0u;
       }
     }
     if (q_acc >= 0)
-      for (int64_t r = lo + threadIdx.x; r < hi; r += kNarrowBlock) na.w[na.perm[r]] += al * a.d[r];
-    if (threadIdx.x == 0 && t == na.t_end - 1) {
+      for (int32_t s = tid; s < ns; s += kNarrowBlock) na.w[L.feat[s]] = L.w[s] + al * L.d[s];
+    if (tid == 0 && t == na.t_end - 1) {
       na.st->q = q_acc;
       na.st->alpha = q_acc >= 0 ? al : 0.0;
       na.st->dF = dF;
@@ -910,12 +956,46 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && na.stats) {
+  if (tid == 0 && na.stats) {
     atomicAdd(&na.stats->bundles, (unsigned long long)n_bundles);
     atomicAdd(&na.stats->ls_steps, (unsigned long long)n_ls);
     if (n_fail > 0.0) atomicAdd(&na.stats->ls_fail, (unsigned long long)n_fail);
     atomicAdd(&na.stats->rows_touched, (unsigned long long)n_touched);
   }
+}
+
+// Copy X into partition order: the nonzeros of slot r land at
+// [poff[r], poff[r+1]) (one wavefront per chunk descriptor).
+__global__ __launch_bounds__(kBlock) void k_permute(const int32_t* ri, const float* v,
+                                                    const int64_t* cp, const Chunk* chunks,
+                                                    const int32_t* cstart, int64_t p,
+                                                    const int64_t* poff, int32_t* pri, float* pv) {
+  const int lane = lane_id();
+  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
+  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t total = cstart[p];
+  for (int64_t c = wave; c < total; c += nwaves) {
+    const Chunk ch = chunks[c];
+    const int64_t dst = poff[ch.slot] + (ch.klo - cp[ch.feat]);
+    for (int32_t e = lane; e < ch.len; e += kWave) {
+      pri[dst + e] = ri[ch.klo + e];
+      pv[dst + e] = v[ch.klo + e];
+    }
+  }
+}
+
+// Column lengths in slot order (for the partition-order offsets).
+__global__ void k_slot_len(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* len) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < p) {
+    const int32_t j = perm[r];
+    len[r] = (int32_t)(cp[j + 1] - cp[j]);
+  }
+}
+
+__global__ void k_widen(const int32_t* in, int64_t m, int64_t* out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r <= m) out[r] = in[r];
 }
 
 // ---------------------------------------------------------------------------
@@ -1118,6 +1198,21 @@ hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_apply<kLogistic>, g, dim3(kBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_apply<kL2Svm>, g, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
+                          const float* v, const Chunk* chunks, const int32_t* cstart,
+                          int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
+                          int32_t* pri, float* pv, hipStream_t s) {
+  hipLaunchKernelGGL(k_slot_len, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm, cp,
+                     p, len_tmp);
+  hipError_t e = launch_scan(len_tmp, off32, p, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(p + 1, kBlock, 1 << 30)), dim3(kBlock), 0, s, off32, p,
+                     poff);
+  hipLaunchKernelGGL(k_permute, dim3(grid_for(p, kWavesPerBlock, 8192)), dim3(kBlock), 0, s, ri, v,
+                     cp, chunks, cstart, p, poff, pri, pv);
   return hipGetLastError();
 }
 
