@@ -15,11 +15,33 @@ namespace {
 // ---------------------------------------------------------------------------
 // wavefront / block reductions
 // ---------------------------------------------------------------------------
+// One DPP step on an FP64 value (two 32-bit halves); lanes without a source
+// (outside the row, or in a masked row) read +0.0.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ inline double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  int lo = (int)(unsigned)(b & 0xffffffffull);
+  int hi = (int)(unsigned)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, BANK_MASK, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, BANK_MASK, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Sum over the 64 lanes of a wavefront, the same value in every lane, in a
+// fixed order: prefix sums inside each 16-lane row (row_shr 1, 2, 4, 8), then
+// row 0 into row 1 and row 2 into row 3 (row_bcast15), then rows 0-1 into
+// rows 2-3 (row_bcast31); lane 63 holds the total.
 __device__ inline double wave_sum(double v) {
-  // xor butterfly: every lane ends with the same bits (a + b == b + a)
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+  v += dpp_f64<0x111, 0xf, 0xf>(v);
+  v += dpp_f64<0x112, 0xf, 0xf>(v);
+  v += dpp_f64<0x114, 0xf, 0xf>(v);
+  v += dpp_f64<0x118, 0xf, 0xf>(v);
+  v += dpp_f64<0x142, 0xa, 0xf>(v);
+  v += dpp_f64<0x143, 0xc, 0xf>(v);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
@@ -60,16 +82,21 @@ __device__ inline uint64_t splitmix_out(uint64_t state) {
 // ---------------------------------------------------------------------------
 // loss pieces (Sec. 2 eqs. (2)-(3); Sec. 3.1)
 // ---------------------------------------------------------------------------
+// sigma(z) and 1 - sigma(z) from E = e^z with one division, exact at E = 0
+// and E = inf: s0 = 1 - sigma(z) = 1/(1+E), s1 = sigma(z) = E s0.
+__device__ inline void logistic_weights(double E, double& s0, double& s1) {
+  s0 = 1.0 / (1.0 + E);
+  s1 = isinf(E) ? 1.0 : E * s0;
+}
+
 // Gradient / Hessian-diagonal contribution of one nonzero x of sample i with
-// retained quantity c_i.  Logistic: with sigma(z) = 1/(1+e^{-z}) and E = e^z,
-// s1 = sigma(z) = 1/(1+1/E) and s0 = 1 - sigma(z) = 1/(1+E) (both exact at
-// E = 0 and E = inf).  For label y the misclassification weight is
-// 1 - tau(y z) = (y > 0 ? s0 : s1) and tau(1 - tau) = s0 s1.
+// retained quantity c_i.  Logistic: for label y the misclassification weight
+// 1 - tau(y z) is s0 (y = +1) or s1 (y = -1), and tau (1 - tau) = s0 s1.
 template <int LOSS>
 __device__ inline void grad_hess_term(double c, int yi, double x, double& gs, double& hs) {
   if (LOSS == kLogistic) {
-    const double s0 = 1.0 / (1.0 + c);
-    const double s1 = 1.0 / (1.0 + 1.0 / c);
+    double s0, s1;
+    logistic_weights(c, s0, s1);
     const double miss = yi > 0 ? s0 : s1;
     gs += (yi > 0 ? -miss : miss) * x;
     hs += (s0 * s1) * (x * x);
@@ -81,28 +108,34 @@ __device__ inline void grad_hess_term(double c, int yi, double x, double& gs, do
   }
 }
 
-// log(A + B e^t) for A, B >= 0, A + B = 1, t <= 0.  Kept out of line: its
-// FP64 expm1/log1p bodies would otherwise be inlined at every call site.
-__device__ __attribute__((noinline)) double log_blend(double A, double B, double t) {
-  const double u = B * expm1(t);
-  return u >= -0.5 ? log1p(u) : log(A + B * exp(t));
-}
-
 // Loss change of sample i when its margin w^T x_i grows by a (eq. (10)'s
-// summand).  Logistic: log(1+e^{-y(z+a)}) - log(1+e^{-yz}); writing
-// m = -y a and tau = tau(y z) it is log(tau + (1 - tau) e^m), evaluated as
-// m + log((1 - tau) + tau e^{-m}) when m > 0 so no exponential overflows.
+// summand).  Logistic: log(1+e^{-y(z+a)}) - log(1+e^{-yz}); with m = -y a and
+// tau = tau(y z) it is log(tau + (1 - tau) e^m), written for t = -|m| <= 0 as
+// max(m, 0) + log(A + B e^t) with (A, B) = (tau, 1 - tau) if m <= 0 and
+// (1 - tau, tau) if m > 0, so no exponential overflows.  log(A + B e^t) is
+// log1p(u), u = B expm1(t), while u >= -1/2 (log1p through log with
+// Goldberg's compensation, "What every computer scientist should know about
+// floating-point arithmetic", Theorem 4), else log of the small sum
+// A + B e^t.  One straight-line path: no divergent branches.
 // SVM: max(0, b - y a)^2 - max(0, b)^2.
 template <int LOSS>
 __device__ inline double loss_delta(double c, int yi, double a) {
   if (LOSS == kLogistic) {
-    const double s0 = 1.0 / (1.0 + c);
-    const double s1 = 1.0 / (1.0 + 1.0 / c);
+    double s0, s1;
+    logistic_weights(c, s0, s1);
     const double tau = yi > 0 ? s1 : s0;
     const double one_minus_tau = yi > 0 ? s0 : s1;
     const double m = yi > 0 ? -a : a;
-    if (m <= 0.0) return log_blend(tau, one_minus_tau, m);
-    return m + log_blend(one_minus_tau, tau, -m);
+    const bool pos = m > 0.0;
+    const double A = pos ? one_minus_tau : tau;
+    const double B = pos ? tau : one_minus_tau;
+    const double t = pos ? -m : m;
+    const double u = B * expm1(t);
+    const bool near_one = u >= -0.5;
+    const double z = near_one ? 1.0 + u : A + B * exp(t);
+    const double lz = log(z);
+    const double r = near_one ? (z == 1.0 ? u : lz * (u / (z - 1.0))) : lz;
+    return pos ? m + r : r;
   } else {
     const double bn = yi > 0 ? c - a : c + a;
     const double pn = bn > 0.0 ? bn : 0.0;
@@ -659,9 +692,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
 //    order), so an accepted unit step costs a single pass.
 // Overflowing any LDS list falls back to global-memory passes (correct, slower).
 // ---------------------------------------------------------------------------
-constexpr int kNarrowBlock = 1024;
+constexpr int kNarrowBlock = 512;      // 256 VGPRs per lane: no spills
 constexpr int kNarrowWaves = kNarrowBlock / kWave;
-constexpr int kNarrowRegRounds = 2;    // rounds of nonzeros kept in registers
+constexpr int kNarrowRegRounds = 4;    // rounds of nonzeros loaded together, kept in registers
 constexpr int kNarrowChunkCap = 512;   // 64-nonzero chunks with LDS partials
 constexpr int kTouchCap = 4096;        // touched rows listed per bundle
 
@@ -676,14 +709,35 @@ __device__ inline double block_sum16(double v, double* lds16) {
   return r;
 }
 
+// Sum of up to four per-thread values over the workgroup in a fixed order
+// (wavefront DPP sums, then the waves in index order); every thread gets the
+// totals.  Double-buffered LDS: one barrier per call suffices because a buffer
+// is rewritten only two calls later, after another barrier.
+template <int NV>
+__device__ inline void block_sums(double (&v)[NV], double (*red)[kNarrowWaves][4], int& buf) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane_id() == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[buf][wave_in_block()][i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kNarrowWaves; ++w) s += red[buf][w][i];
+    v[i] = s;
+  }
+  buf ^= 1;
+}
+
 __device__ inline double load_l2(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __attribute__((noinline)) double exp_out_of_line(double x) { return exp(x); }
-
 struct NarrowLds {
   double lds16[kNarrowWaves];
+  double red[2][kNarrowWaves][4];
   int32_t n_touch;
   int32_t off[kNarrowMaxP + 1];        // nonzero offsets of the bundle's slots
   int32_t feat[kNarrowMaxP];
@@ -745,12 +799,26 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
     const int32_t nchunks = (nb + kWave - 1) / kWave;
     double2* pf = nchunks <= kNarrowChunkCap ? L.pf : na.part;
     double2* pl = nchunks <= kNarrowChunkCap ? L.pl : na.part + nchunks;
-    // 1. sweep: nonzero v = r0 + tid; segmented wavefront sums per slot
+    // 1. sweep: nonzero v = r0 + tid; segmented wavefront sums per slot.
+    //    The first kNarrowRegRounds rounds issue all their loads together.
     int32_t rrow[kNarrowRegRounds];
     float rx[kNarrowRegRounds];
     double rc[kNarrowRegRounds];
     int ry[kNarrowRegRounds];
     int32_t rs[kNarrowRegRounds];
+#pragma unroll
+    for (int u = 0; u < kNarrowRegRounds; ++u) {
+      const int32_t v = u * kNarrowBlock + tid;
+      rrow[u] = v < nb ? na.pri[base + v] : 0;
+      rx[u] = v < nb ? na.pv[base + v] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kNarrowRegRounds; ++u) {
+      const int32_t v = u * kNarrowBlock + tid;
+      rs[u] = v < nb ? slot_of(L.off, ns, v) : -1;
+      rc[u] = v < nb ? a.cache[rrow[u]] : 0.0;
+      ry[u] = v < nb ? (int)a.y[rrow[u]] : 0;
+    }
     int round = 0;
     for (int32_t r0 = 0; r0 < nb; r0 += kNarrowBlock, ++round) {
       const int32_t v = r0 + tid;
@@ -759,19 +827,22 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
       float x = 0.0f;
       double c = 0.0;
       int yi = 0;
-      if (valid) {
+      if (round < kNarrowRegRounds) {
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u)
+          if (u == round) {
+            row = rrow[u];
+            x = rx[u];
+            c = rc[u];
+            yi = ry[u];
+            s = rs[u];
+          }
+      } else if (valid) {
         row = na.pri[base + v];
         x = na.pv[base + v];
         s = slot_of(L.off, ns, v);
         c = a.cache[row];
         yi = (int)a.y[row];
-      }
-      if (round < kNarrowRegRounds) {
-        rrow[round] = row;
-        rx[round] = x;
-        rc[round] = c;
-        ry[round] = yi;
-        rs[round] = s;
       }
       double g = 0.0, h = 0.0;
       if (valid) grad_hess_term<LOSS>(c, yi, (double)x, g, h);
@@ -836,7 +907,7 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
       a.h[lo + s] = h;
       a.d[lo + s] = dj;
     }
-    const double Delta = block_sum16(del, L.lds16);   // also publishes L.d
+    __syncthreads();  // publishes L.d; Delta's per-thread part stays in `del`
     // 2. scatter d_j x_ij into d^T x; list touched rows with their retained
     //    quantity and label
     round = 0;
@@ -848,11 +919,15 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
       double c;
       int yi;
       if (round < kNarrowRegRounds) {
-        row = rrow[round];
-        x = rx[round];
-        c = rc[round];
-        yi = ry[round];
-        s = rs[round];
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u)
+          if (u == round) {
+            row = rrow[u];
+            x = rx[u];
+            c = rc[u];
+            yi = ry[u];
+            s = rs[u];
+          }
       } else {
         row = na.pri[base + v];
         x = na.pv[base + v];
@@ -872,7 +947,8 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
       for (int32_t e = tid; e < n_touch; e += kNarrowBlock) L.t_dtx[e] = load_l2(&a.dtx[L.t_row[e]]);
     __syncthreads();
     // 3. candidates q = 0, 1, ... until the Armijo test (eq. (6)) holds
-    double Dq = Delta, al = 1.0, dF = 0.0;
+    int rbuf = 0;
+    double Delta = 0.0, Dq = 0.0, al = 1.0, dF = 0.0;
     int q_acc = -1;
     for (int q = 0; q < na.max_ls; ++q) {
       double sl = 0.0, l1 = 0.0, touched = 0.0;
@@ -896,9 +972,21 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
         }
       }
       for (int32_t s = tid; s < ns; s += kNarrowBlock) l1 += fabs(L.w[s] + al * L.d[s]) - fabs(L.w[s]);
-      const double sL = block_sum16(sl, L.lds16);
-      const double L1 = block_sum16(l1, L.lds16);
-      if (q == 0) n_touched += block_sum16(touched, L.lds16);
+      double sL, L1;
+      if (q == 0) {
+        double v4[4] = {sl, l1, del, touched};
+        block_sums<4>(v4, L.red, rbuf);
+        sL = v4[0];
+        L1 = v4[1];
+        Delta = v4[2];
+        Dq = Delta;
+        n_touched += v4[3];
+      } else {
+        double v2[2] = {sl, l1};
+        block_sums<2>(v2, L.red, rbuf);
+        sL = v2[0];
+        L1 = v2[1];
+      }
       const double f = L1 + na.C * sL;
       if (f <= na.sigma * Dq) {
         q_acc = q;
@@ -924,7 +1012,7 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
           double sc = dl;
           for (int u = 0; u < q_acc; ++u) sc *= na.beta;
           if (LOSS == kLogistic)
-            na.cache[i] = L.t_c[e] * exp_out_of_line(sc);
+            na.cache[i] = L.t_c[e] * exp(sc);
           else
             na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sc : -sc);
         }
@@ -938,7 +1026,7 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
           double sc = dl;
           for (int u = 0; u < q_acc; ++u) sc *= na.beta;
           if (LOSS == kLogistic)
-            na.cache[i] *= exp_out_of_line(sc);
+            na.cache[i] *= exp(sc);
           else
             na.cache[i] -= a.y[i] > 0 ? sc : -sc;
         }
