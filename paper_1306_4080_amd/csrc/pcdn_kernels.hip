@@ -44,6 +44,37 @@ __device__ inline double wave_sum(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// One step of a segmented inclusive scan over a wavefront whose keys do not
+// decrease along the lanes: add the source lane's running sums when it holds
+// the same key (a lane without a source reads key -1, which no valid lane has).
+template <int CTRL, int ROW_MASK>
+__device__ inline void seg_scan_step(double& g, double& h, int32_t key) {
+  const int32_t k2 = __builtin_amdgcn_update_dpp(-1, key, CTRL, ROW_MASK, 0xf, false);
+  const double g2 = dpp_f64<CTRL, ROW_MASK, 0xf>(g);
+  const double h2 = dpp_f64<CTRL, ROW_MASK, 0xf>(h);
+  if (k2 == key) {
+    g += g2;
+    h += h2;
+  }
+}
+
+// Segmented inclusive scan of (g, h) by key: the same step sequence as
+// wave_sum, each step gated on equal keys.  Keys must not decrease with the
+// lane index, so equal keys are contiguous.
+__device__ inline void seg_scan(double& g, double& h, int32_t key) {
+  seg_scan_step<0x111, 0xf>(g, h, key);
+  seg_scan_step<0x112, 0xf>(g, h, key);
+  seg_scan_step<0x114, 0xf>(g, h, key);
+  seg_scan_step<0x118, 0xf>(g, h, key);
+  seg_scan_step<0x142, 0xa>(g, h, key);
+  seg_scan_step<0x143, 0xc>(g, h, key);
+}
+
+// Key of the next lane (wave_shl1); lane 63 reads -2.
+__device__ inline int32_t next_lane_key(int32_t key) {
+  return __builtin_amdgcn_update_dpp(-2, key, 0x130, 0xf, 0xf, false);
+}
+
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 __device__ inline int wave_in_block() { return threadIdx.x / kWave; }
 
@@ -762,14 +793,14 @@ __device__ inline int32_t slot_of(const int32_t* off, int32_t nslots, int32_t v)
   return lo;
 }
 
-__device__ inline void touch_row(NarrowLds& L, unsigned* rowflag, int32_t row, double c, int yi) {
-  if (atomicExch(&rowflag[row], 1u) == 0u) {
-    const int32_t e = atomicAdd(&L.n_touch, 1);
-    if (e < kTouchCap) {
-      L.t_row[e] = row;
-      L.t_c[e] = c;
-      L.t_y[e] = (int8_t)yi;
-    }
+// Append a row, first touched by this thread, to the bundle's LDS list (the
+// count keeps growing past the capacity so that an overflow is seen).
+__device__ inline void list_row(NarrowLds& L, int32_t row, double c, int yi) {
+  const int32_t e = atomicAdd(&L.n_touch, 1);
+  if (e < kTouchCap) {
+    L.t_row[e] = row;
+    L.t_c[e] = c;
+    L.t_y[e] = (int8_t)yi;
   }
 }
 
@@ -846,19 +877,10 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
       }
       double g = 0.0, h = 0.0;
       if (valid) grad_hess_term<LOSS>(c, yi, (double)x, g, h);
-      // inclusive segmented scan over the wavefront (slots ascend along lanes)
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const double go = __shfl_up(g, o, kWave);
-        const double ho = __shfl_up(h, o, kWave);
-        const int32_t so = __shfl_up(s, o, kWave);
-        if (lane >= o && so == s) {
-          g += go;
-          h += ho;
-        }
-      }
-      const int32_t s_next = __shfl_down(s, 1, kWave);
-      const bool seg_end = valid && (lane == kWave - 1 || s_next != s);
+      // inclusive segmented scan over the wavefront (slots ascend along lanes;
+      // lanes past the end carry slot -1 and zero terms)
+      seg_scan(g, h, s);
+      const bool seg_end = valid && next_lane_key(s) != s;
       if (seg_end) {
         const int32_t m = v / kWave;                 // chunk of this nonzero
         const int32_t cbeg = m * kWave, cend = cbeg + kWave - 1;
@@ -910,35 +932,32 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
     __syncthreads();  // publishes L.d; Delta's per-thread part stays in `del`
     // 2. scatter d_j x_ij into d^T x; list touched rows with their retained
     //    quantity and label
-    round = 0;
-    for (int32_t r0 = 0; r0 < nb; r0 += kNarrowBlock, ++round) {
-      const int32_t v = r0 + tid;
-      if (v >= nb) continue;
-      int32_t row, s;
-      float x;
-      double c;
-      int yi;
-      if (round < kNarrowRegRounds) {
+    //    The register rounds issue every flag exchange before waiting on any.
+    {
+      unsigned was[kNarrowRegRounds];
 #pragma unroll
-        for (int u = 0; u < kNarrowRegRounds; ++u)
-          if (u == round) {
-            row = rrow[u];
-            x = rx[u];
-            c = rc[u];
-            yi = ry[u];
-            s = rs[u];
+      for (int u = 0; u < kNarrowRegRounds; ++u) {
+        was[u] = 1u;
+        if (u * kNarrowBlock + tid < nb) {
+          const double dj = L.d[rs[u]];
+          if (dj != 0.0) {
+            unsafeAtomicAdd(&a.dtx[rrow[u]], dj * (double)rx[u]);
+            was[u] = atomicExch(&na.rowflag[rrow[u]], 1u);
           }
-      } else {
-        row = na.pri[base + v];
-        x = na.pv[base + v];
-        s = slot_of(L.off, ns, v);
-        c = a.cache[row];
-        yi = (int)a.y[row];
+        }
       }
+#pragma unroll
+      for (int u = 0; u < kNarrowRegRounds; ++u)
+        if (was[u] == 0u) list_row(L, rrow[u], rc[u], ry[u]);
+    }
+    for (int32_t v = kNarrowRegRounds * kNarrowBlock + tid; v < nb; v += kNarrowBlock) {
+      const int32_t row = na.pri[base + v];
+      const float x = na.pv[base + v];
+      const int32_t s = slot_of(L.off, ns, v);
       const double dj = L.d[s];
       if (dj == 0.0) continue;
       unsafeAtomicAdd(&a.dtx[row], dj * (double)x);
-      touch_row(L, na.rowflag, row, c, yi);
+      if (atomicExch(&na.rowflag[row], 1u) == 0u) list_row(L, row, a.cache[row], (int)a.y[row]);
     }
     __syncthreads();
     const int32_t n_touch = L.n_touch;
