@@ -35,12 +35,13 @@ if ROOT not in sys.path:
 
 METRIC = "bundle-sweep nnz/s (HBM GB/s %peak); batched solves/s + p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_CLASSES = ("sweep", "split_columns", "linesearch", "apply", "stopping_sweep")
+KERNEL_CLASSES = ("sweep", "split_columns", "linesearch", "apply", "stopping_sweep", "narrow")
 KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep, direction, fused d^T x scatter)",
                 "k_split (split-column finish and scatter)",
                 "k_linesearch (per-candidate loss-change partial sums)",
                 "k_apply (Armijo decision, w and retained-quantity update)",
-                "k_sweep+k_split stopping mode (full-gradient subgradient norm)")
+                "k_sweep+k_split stopping mode (full-gradient subgradient norm)",
+                "k_narrow (one workgroup runs every bundle of an outer iteration)")
 SETTINGS = [(0.5, 64), (0.5, 1024), (0.5, 8192), (4.0, 64), (4.0, 1024), (4.0, 8192)]
 SEED = 1
 
@@ -53,7 +54,27 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", action="append", default=None, metavar="C,P",
+                    help="run only this (C, P) setting (repeatable); for profiling runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-mebibyte device buffer three times (the plain copy "
+                         "kernel that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hash of the kernel sources that traffic records are keyed by")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int) -> None:
+    import torch
+    nbytes = mib << 20
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}),
+          flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -78,7 +99,7 @@ def measured_traffic(kernel_class: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(d, budget_s: float) -> dict:
+def cpu_baseline(d, budget_s: float, settings) -> dict:
     """The FP64 oracle (single-threaded C) on a bounded sample: the first outer
     iterations of each of the six settings, round-robin until the budget."""
     import oracle
@@ -86,24 +107,27 @@ def cpu_baseline(d, budget_s: float) -> dict:
     done_nnz = 0
     # run each setting for m outer iterations, m chosen from a one-iteration probe
     t_probe = time.perf_counter()
-    for C, P in SETTINGS:
+    for C, P in settings:
         par = oracle.Params(loss="lr", C=C)
         oracle.solve(prob, par, P=P, eps=0.0, seed=SEED, max_outer=1)
     probe = time.perf_counter() - t_probe
     m = max(1, int(budget_s / max(probe, 1e-3)))
     t0 = time.perf_counter()
-    for C, P in SETTINGS:
+    for C, P in settings:
         par = oracle.Params(loss="lr", C=C)
         w, info, _ = oracle.solve(prob, par, P=P, eps=0.0, seed=SEED, max_outer=m)
         done_nnz += info["nnz_swept"]
     dt = time.perf_counter() - t0
     return {"value": done_nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} outer iterations of each of the six (C, P) settings "
+            "sample": f"first {m} outer iterations of each of the {len(settings)} (C, P) settings "
                       f"from w = 0 ({done_nnz} bundle nonzeros, {dt:.1f} s, single thread)"}
 
 
 def main():
     args = parse()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU PCDN is a design "
@@ -118,10 +142,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    settings = SETTINGS
+    if args.only:
+        settings = [(float(c), int(p)) for c, p in (o.split(",") for o in args.only)]
     pc.ensure_built()
     d = synth.c2()
     solvers = []
-    for C, P in SETTINGS:
+    for C, P in settings:
         s = pc.Solver(device=0).load_data(d)
         s.reset("lr", C)
         solvers.append((s, C, P))
@@ -144,7 +174,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    nnz_total = d.nnz * len(SETTINGS) * args.steps
+    nnz_total = d.nnz * len(settings) * args.steps
     value = nnz_total / elapsed
 
     # timed region B: the next `steps` outer iterations with every kernel class
@@ -197,7 +227,7 @@ def main():
         "config": {"workload": "text-like L1-LR 20000x50000, Zipf(1.1) columns, "
                                "C in {0.5,4} x P in {64,1024,8192}",
                    "n": d.n, "p": d.p, "nnz": d.nnz, "loss": "logistic", "seed": SEED,
-                   "settings": [f"C={C},P={P}" for C, P in SETTINGS]},
+                   "settings": [f"C={C},P={P}" for C, P in settings]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
@@ -211,7 +241,7 @@ def main():
         "objective_after": F,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds, settings)
     print(json.dumps(line), flush=True)
 
 

@@ -168,7 +168,8 @@ int pcdn_evaluate(pcdn_ctx* ctx, double* objective, double* subgrad);
 
 /* Kernel timing.  Kernel classes: 0 gradient/direction sweep (with the fused
  * d^T x scatter), 1 d^T x scatter of split columns, 2 line search, 3 apply,
- * 4 stopping sweep.  pcdn_profile(ctx, mask) brackets every launch of each
+ * 4 stopping sweep, 5 single-workgroup kernel (every step of every bundle of
+ * an outer iteration, PCDN_SCHED_NARROW).  pcdn_profile(ctx, mask) brackets every launch of each
  * class whose bit (1 << class) is set in mask with HIP events on the
  * context's stream (mask 0: off) and restarts the accumulators;
  * pcdn_profile_read() returns for class `which` the summed event time in ms

@@ -19,14 +19,15 @@ using namespace pcdn;
 
 namespace {
 
-constexpr int kProfClasses = 5;  // sweep, split scatter, line search, apply, stopping sweep
+// sweep, split scatter, line search, apply, stopping sweep, single-workgroup bundles
+constexpr int kProfClasses = 6;
 
 struct Profiler {
   int mask = 0;
   std::vector<hipEvent_t> pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  double ms[kProfClasses] = {0, 0, 0, 0, 0};
-  int64_t launches[kProfClasses] = {0, 0, 0, 0, 0};
+  double ms[kProfClasses] = {};
+  int64_t launches[kProfClasses] = {};
 };
 
 // Algorithmic bytes per unit (what the method must move; see the design doc's model).
@@ -131,8 +132,10 @@ struct pcdn_ctx {
   } graph_key;
 
   // counters known on the host (launch structure): sweep and stopping work
+  // (the *_narrow parts were swept by the single-workgroup kernel)
   struct HostCounts {
     double nnz_gh = 0, slots = 0, nnz_stop = 0, stop_sweeps = 0;
+    double nnz_gh_narrow = 0, slots_narrow = 0;
   } hc, prof_hc;
   std::vector<int64_t> h_cp;  // host copy of col_ptr
 
@@ -496,7 +499,7 @@ int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64
   na.beta = o.beta;
   na.max_ls = o.max_ls;
   na.dtx_copy = dtx_copy;
-  ProfScope ps(c, 0);
+  ProfScope ps(c, 5);
   HIPCHK(c, launch_narrow(c->loss, na, c->stream));
   return PCDN_OK;
 }
@@ -520,7 +523,8 @@ int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* i
       if (rc) return rc;
     }
   }
-  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, c->stats, c->stream));
+  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, use_narrow(c, o, P), c->stats,
+                                 c->stream));
   return launch_stopping(c, o, c->w, it);
 }
 
@@ -565,6 +569,10 @@ int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t co
   // in the stopping test
   c->hc.nnz_gh += (double)c->nnz * count;
   c->hc.slots += (double)c->p * count;
+  if (use_narrow(c, o, P)) {
+    c->hc.nnz_gh_narrow += (double)c->nnz * count;
+    c->hc.slots_narrow += (double)c->p * count;
+  }
   c->hc.nnz_stop += (double)c->nnz * count;
   c->hc.stop_sweeps += (double)count;
   // kernel profiling brackets launches with events: launch directly then
@@ -595,11 +603,16 @@ int read_stats(pcdn_ctx* c) {
 
 double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& h,
                     const pcdn_ctx::HostCounts& hb, int cls, int64_t p) {
-  const double d_nnz_gh = h.nnz_gh - hb.nnz_gh;
-  const double d_slots = h.slots - hb.slots;
+  // multi-kernel schedule (classes 0-3) and single-workgroup kernel (class 5)
+  const double n_nnz_gh = h.nnz_gh_narrow - hb.nnz_gh_narrow;
+  const double n_slots = h.slots_narrow - hb.slots_narrow;
+  const double n_scat = (double)(s.nnz_scat_narrow - b.nnz_scat_narrow);
+  const double n_rows = (double)(s.rows_touched_narrow - b.rows_touched_narrow);
+  const double d_nnz_gh = h.nnz_gh - hb.nnz_gh - n_nnz_gh;
+  const double d_slots = h.slots - hb.slots - n_slots;
   const double d_fused = (double)(s.nnz_scat_fused - b.nnz_scat_fused);
   const double d_split = (double)(s.nnz_scat_split - b.nnz_scat_split);
-  const double d_rows = (double)(s.rows_touched - b.rows_touched);
+  const double d_rows = (double)(s.rows_touched - b.rows_touched) - n_rows;
   const double d_stop = h.nnz_stop - hb.nnz_stop;
   const double d_sweeps = h.stop_sweeps - hb.stop_sweeps;
   switch (cls) {
@@ -609,6 +622,9 @@ double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& 
     case 2: return kBytesPerRowLs * d_rows + kBytesPerSlotLs * d_slots;
     case 3: return kBytesPerRowApply * d_rows + kBytesPerSlotApply * d_slots;
     case 4: return kBytesPerNnzStop * d_stop + kBytesPerFeatStop * (double)p * d_sweeps;
+    case 5: return kBytesPerNnzSweep * n_nnz_gh + kBytesPerSlotSweep * n_slots +
+                   kBytesPerNnzScatter * n_scat + (kBytesPerRowLs + kBytesPerRowApply) * n_rows +
+                   (kBytesPerSlotLs + kBytesPerSlotApply) * n_slots;
     default: return 0.0;
   }
 }
@@ -840,7 +856,8 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
   HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, c->nch, c->cstart, c->chunks, c->scan_tmp,
                           c->stream));
   // run the bundle; keep d^T x before it is cleared
-  if (use_narrow(c, o, P)) {
+  const bool narrow = use_narrow(c, o, P);
+  if (narrow) {
     rc = launch_narrow_bundles(c, o, c->step_perm, P, P, 0, 1, dtx ? c->tmp_n : nullptr);
     if (rc) return rc;
   } else {
@@ -852,9 +869,15 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
     rc = bundle_ls_apply(c, o, c->step_perm, 0, P);
     if (rc) return rc;
   }
-  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, c->stats, c->stream));
-  for (int64_t t = 0; t < P; ++t) c->hc.nnz_gh += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
+  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, narrow, c->stats, c->stream));
+  double swept = 0.0;
+  for (int64_t t = 0; t < P; ++t) swept += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
+  c->hc.nnz_gh += swept;
   c->hc.slots += (double)P;
+  if (narrow) {
+    c->hc.nnz_gh_narrow += swept;
+    c->hc.slots_narrow += (double)P;
+  }
   if (g) HIPCHK(c, hipMemcpyAsync(g, c->g, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (h) HIPCHK(c, hipMemcpyAsync(h, c->h, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (d) HIPCHK(c, hipMemcpyAsync(d, c->d, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -52,7 +52,9 @@ struct Stats {
   unsigned long long nnz_scat_fused; // nonzeros scattered into d^T x by the sweep kernel
   unsigned long long nnz_scat_split; // nonzeros scattered by the split-column kernel
   unsigned long long rows_touched;   // rows with d^T x_i != 0, summed over bundles
-  unsigned long long pad[10];
+  unsigned long long nnz_scat_narrow;  // nonzeros scattered by the single-workgroup kernel
+  unsigned long long rows_touched_narrow;  // part of rows_touched from that kernel
+  unsigned long long pad[8];
 };
 
 // Result of the line search of the current inner iteration.
@@ -178,9 +180,10 @@ hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, con
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, hipStream_t s);
-// Nonzeros of the features with d != 0 (slots 0..p of perm) into stats.
+// Nonzeros of the features with d != 0 (slots 0..p of perm) into stats
+// (narrow: counted for the single-workgroup kernel).
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, Stats* stats, hipStream_t s);
+                                int64_t p, bool narrow, Stats* stats, hipStream_t s);
 // Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s);

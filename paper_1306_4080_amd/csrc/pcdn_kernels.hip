@@ -531,7 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
 // d_j != 0; split columns counted apart), one atomic per block.
 __global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const int32_t* perm,
                                                           const int64_t* cp, int64_t p,
-                                                          Stats* stats) {
+                                                          bool narrow, Stats* stats) {
   __shared__ double lds4[kWavesPerBlock];
   double fused = 0.0, split = 0.0;
   for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < p;
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const
     if (d[r] == 0.0) continue;
     const int32_t j = perm[r];
     const double len = (double)(cp[j + 1] - cp[j]);
-    if (len > kChunk)
+    if (len > kChunk && !narrow)
       split += len;
     else
       fused += len;
@@ -547,7 +547,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const
   fused = block_sum(fused, lds4);
   split = block_sum(split, lds4);
   if (threadIdx.x == 0) {
-    if (fused > 0.0) atomicAdd(&stats->nnz_scat_fused, (unsigned long long)fused);
+    if (fused > 0.0)
+      atomicAdd(narrow ? &stats->nnz_scat_narrow : &stats->nnz_scat_fused, (unsigned long long)fused);
     if (split > 0.0) atomicAdd(&stats->nnz_scat_split, (unsigned long long)split);
   }
 }
@@ -1068,6 +1069,7 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
     atomicAdd(&na.stats->ls_steps, (unsigned long long)n_ls);
     if (n_fail > 0.0) atomicAdd(&na.stats->ls_fail, (unsigned long long)n_fail);
     atomicAdd(&na.stats->rows_touched, (unsigned long long)n_touched);
+    atomicAdd(&na.stats->rows_touched_narrow, (unsigned long long)n_touched);
   }
 }
 
@@ -1332,9 +1334,9 @@ hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, Stats* stats, hipStream_t s) {
+                                int64_t p, bool narrow, Stats* stats, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter_count, dim3(grid_for(p, kBlock, 64)), dim3(kBlock), 0, s, d, perm,
-                     cp, p, stats);
+                     cp, p, narrow, stats);
   return hipGetLastError();
 }
 
