@@ -125,6 +125,45 @@ int pcdn_load_csc(pcdn_ctx* ctx, int64_t n, int64_t p, int64_t nnz,
 int pcdn_solve(pcdn_ctx* ctx, double C, int64_t P, double eps, int loss,
                const pcdn_opts* opts, double* w_out, pcdn_info* info);
 
+/* One solve of a batch: the arguments of pcdn_solve for one context. */
+typedef struct {
+  pcdn_ctx* ctx;          /* loaded context; at most one job per context       */
+  double C;               /* as pcdn_solve                                     */
+  int64_t P;
+  double eps;
+  int32_t loss;
+  int32_t status;         /* out: what pcdn_solve would have returned          */
+  const pcdn_opts* opts;  /* nullable: defaults                                */
+  double* w_out;          /* nullable: host, p doubles                         */
+  pcdn_info* info;        /* nullable                                          */
+} pcdn_job;
+
+/* Independent solves together on one device (the contexts must share it).
+ * Each job follows the trajectory pcdn_solve would (same partitions, same
+ * arithmetic; Algorithm 3 per problem).  The jobs advance in rounds of one
+ * outer iteration each: the bundles of every job on the single-workgroup
+ * schedule run in one launch, one workgroup per job (their partition and
+ * stopping sweeps are replayed graphs on each context's stream); jobs on the
+ * multi-kernel schedule replay their own outer-iteration graph on their
+ * context's stream in the same round.  A job leaves the batch when its
+ * stopping rule holds or at its max_outer.  Arguments are checked for every
+ * job before any work: an invalid job makes the call return that job's error
+ * code (its context holds the message) with nothing run.  Otherwise returns
+ * PCDN_OK, with each job's PCDN_OK / PCDN_NOT_CONVERGED in jobs[i].status, or
+ * the first device error.  count = 0 is allowed.  Kernel profiling
+ * (pcdn_profile) does not bracket batch launches. */
+int pcdn_solve_batch(pcdn_job* jobs, int32_t count);
+
+/* Regularisation path: pcdn_solve for C = Cs[0], Cs[1], ... in order, each
+ * warm-started from the previous solution (the first from opts->w0, or 0),
+ * with the reference norm of the stopping rule at w = 0 for every C.  W_out
+ * (nullable, host, count x p doubles, row k = the solution for Cs[k]) and
+ * infos (nullable, count entries) receive the results.  Returns PCDN_OK if
+ * every solve converged, PCDN_NOT_CONVERGED if one stopped at max_outer, or
+ * the first error. */
+int pcdn_solve_path(pcdn_ctx* ctx, const double* Cs, int32_t count, int64_t P, double eps,
+                    int loss, const pcdn_opts* opts, double* W_out, pcdn_info* infos);
+
 /* Set the device state to (loss, C, w): w (host, p doubles) or zeros if NULL;
  * the retained e^{w^T x_i} (logistic) or b_i = 1 - y_i w^T x_i (SVM) are
  * recomputed from w in FP64 (Sec. 3.1). */

@@ -32,6 +32,7 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
 # entry points declared in include/pcdn.h
 SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
            "pcdn_iterate",
+           "pcdn_solve_batch", "pcdn_solve_path",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
            "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy")
 
@@ -64,6 +65,13 @@ class pcdn_step_info(ctypes.Structure):
                 ("dF", ctypes.c_double), ("q", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class pcdn_job(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("C", ctypes.c_double), ("P", ctypes.c_int64),
+                ("eps", ctypes.c_double), ("loss", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("opts", ctypes.POINTER(pcdn_opts)), ("w_out", ctypes.c_void_p),
+                ("info", ctypes.POINTER(pcdn_info))]
+
+
 _lib = None
 
 
@@ -92,6 +100,9 @@ def load_library(path: str = LIB_PATH):
     L.pcdn_step.argtypes = [vp, vp, i64, ctypes.POINTER(pcdn_opts),
                             ctypes.POINTER(pcdn_step_info), vp, vp, vp, vp]
     L.pcdn_iterate.argtypes = [vp, i64, i64, i64, ctypes.POINTER(pcdn_opts), vp]
+    L.pcdn_solve_batch.argtypes = [ctypes.POINTER(pcdn_job), ctypes.c_int32]
+    L.pcdn_solve_path.argtypes = [vp, ctypes.POINTER(dbl), ctypes.c_int32, i64, dbl, i32,
+                                  ctypes.POINTER(pcdn_opts), vp, ctypes.POINTER(pcdn_info)]
     L.pcdn_permutation.argtypes = [vp, u64, i64, vp]
     L.pcdn_get_w.argtypes = [vp, vp]
     L.pcdn_get_cache.argtypes = [vp, vp]
@@ -180,8 +191,53 @@ def pcdn_solve(ctx, C, P, eps, loss, p, **opts):
     rc = load_library().pcdn_solve(ctx, float(C), int(P), float(eps), int(loss),
                                    ctypes.byref(o), w.ctypes.data, ctypes.byref(info))
     _check(ctx, rc, (PCDN_OK, PCDN_NOT_CONVERGED))
-    d = {f: getattr(info, f) for f, _ in pcdn_info._fields_}
-    return rc, w, d
+    return rc, w, _info_dict(info)
+
+
+def _info_dict(info) -> dict:
+    return {f: getattr(info, f) for f, _ in pcdn_info._fields_}
+
+
+def pcdn_solve_batch(specs):
+    """specs: list of dicts with keys ctx, C, P, eps, loss, p and optional
+    opts (a dict of option keywords).  Returns a list of (status, w, info)."""
+    n = len(specs)
+    jobs = (pcdn_job * max(n, 1))()
+    infos = [pcdn_info() for _ in range(n)]
+    ws, keep = [], []
+    for i, sp in enumerate(specs):
+        o, k = _opts(**sp.get("opts", {}))
+        keep.append((o, k))
+        w = np.empty(int(sp["p"]), dtype=np.float64)
+        ws.append(w)
+        jobs[i].ctx = sp["ctx"]
+        jobs[i].C = float(sp["C"])
+        jobs[i].P = int(sp["P"])
+        jobs[i].eps = float(sp["eps"])
+        jobs[i].loss = int(LOSSES.get(sp["loss"], sp["loss"]))
+        jobs[i].opts = ctypes.pointer(o)
+        jobs[i].w_out = w.ctypes.data
+        jobs[i].info = ctypes.pointer(infos[i])
+    rc = load_library().pcdn_solve_batch(jobs, n)
+    if rc != PCDN_OK:
+        bad = next((sp["ctx"] for i, sp in enumerate(specs) if jobs[i].status == rc),
+                   specs[0]["ctx"] if specs else None)
+        _check(bad, rc)
+    return [(jobs[i].status, ws[i], _info_dict(infos[i])) for i in range(n)]
+
+
+def pcdn_solve_path(ctx, Cs, P, eps, loss, p, **opts):
+    """Returns (status, W (len(Cs) x p), list of info dicts)."""
+    loss = LOSSES.get(loss, loss)
+    Cs = np.ascontiguousarray(Cs, dtype=np.float64)
+    o, keep = _opts(**opts)
+    W = np.empty((len(Cs), int(p)), dtype=np.float64)
+    infos = (pcdn_info * max(len(Cs), 1))()
+    rc = load_library().pcdn_solve_path(ctx, Cs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        len(Cs), int(P), float(eps), int(loss), ctypes.byref(o),
+                                        W.ctypes.data, infos)
+    _check(ctx, rc, (PCDN_OK, PCDN_NOT_CONVERGED))
+    return rc, W, [_info_dict(infos[k]) for k in range(len(Cs))]
 
 
 def pcdn_reset(ctx, loss, C, w=None) -> None:
@@ -280,6 +336,14 @@ class Solver:
     def solve(self, C, P, eps, loss, **opts):
         return pcdn_solve(self.ctx, C, P, eps, loss, self.p, **opts)
 
+    def solve_path(self, Cs, P, eps, loss, **opts):
+        return pcdn_solve_path(self.ctx, Cs, P, eps, loss, self.p, **opts)
+
+    def job(self, C, P, eps, loss, **opts) -> dict:
+        """A job description for solve_batch()."""
+        return {"ctx": self.ctx, "C": C, "P": P, "eps": eps, "loss": loss, "p": self.p,
+                "opts": opts}
+
     def reset(self, loss, C, w=None):
         pcdn_reset(self.ctx, loss, C, w)
 
@@ -311,3 +375,8 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_batch(jobs):
+    """Solve the jobs (from Solver.job) together; list of (status, w, info)."""
+    return pcdn_solve_batch(jobs)

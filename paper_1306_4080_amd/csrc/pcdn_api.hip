@@ -12,25 +12,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/pcdn.h"
-#include "pcdn_device.h"
+#include "pcdn_host.h"
 
 using namespace pcdn;
 
 namespace {
 
-// sweep, split scatter, line search, apply, stopping sweep, single-workgroup bundles
-constexpr int kProfClasses = 6;
-
-struct Profiler {
-  int mask = 0;
-  std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  double ms[kProfClasses] = {};
-  int64_t launches[kProfClasses] = {};
-};
-
-// Algorithmic bytes per unit (what the method must move; see the design doc's model).
+// Algorithmic bytes per unit of work: what the method must move.
 constexpr double kBytesPerNnzSweep = 17.0;    // row idx 4 + value 4 + retained gather 8 + label 1
 constexpr double kBytesPerSlotSweep = 60.0;   // col_ptr pair 16 + perm 4 + w 8 + g,h,d,dterm 32
 constexpr double kBytesPerNnzScatter = 24.0;  // row idx 4 + value 4 + FP64 read-modify-write 16
@@ -41,135 +29,24 @@ constexpr double kBytesPerSlotApply = 28.0;   // perm 4 + d 8 + w RMW 16
 constexpr double kBytesPerNnzStop = 17.0;
 constexpr double kBytesPerFeatStop = 32.0;    // col_ptr pair 16 + w 8 + |grad^S| 8
 
-template <class T>
-hipError_t dalloc(T** p, size_t count) {
-  *p = nullptr;
-  if (count == 0) count = 1;
-  return hipMalloc((void**)p, count * sizeof(T));
-}
-
 }  // namespace
 
-struct pcdn_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-
-  // data
-  int64_t n = 0, p = 0, nnz = 0;
-  bool loaded = false;
-  int64_t* cp = nullptr;
-  int32_t* ri = nullptr;
-  float* v = nullptr;
-  int8_t* y = nullptr;
-
-  // state
-  int loss = -1;
-  double C = 0.0;
-  bool has_state = false;
-  double* w = nullptr;
-  double* cache = nullptr;
-  double* dtx = nullptr;
-  double* tmp_n = nullptr;
-  double* tmp_p = nullptr;
-  unsigned* rowflag = nullptr;
-  double* g = nullptr;
-  double* h = nullptr;
-  double* d = nullptr;
-  double* dterm = nullptr;
-
-  // partition and chunk bookkeeping
-  uint32_t* keys0 = nullptr;
-  uint32_t* keys1 = nullptr;
-  int32_t* idx0 = nullptr;
-  int32_t* idx1 = nullptr;
-  int32_t* hist = nullptr;
-  int32_t* scan_tmp = nullptr;
-  int32_t* nch = nullptr;
-  int32_t* cstart = nullptr;
-  Chunk* chunks = nullptr;
-  int32_t* id_cstart = nullptr;
-  Chunk* id_chunks = nullptr;
-  int64_t id_total_chunks = 0;
-  int32_t* step_perm = nullptr;
-  int64_t max_chunks = 0;
-  double2* part = nullptr;
-  int64_t part_len = 0;
-  // X in partition order (single-workgroup schedule)
-  int32_t* pri = nullptr;
-  float* pv = nullptr;
-  int64_t* poff = nullptr;
-  int32_t* off32 = nullptr;
-
-  // reductions and small device records
-  double* ls_part = nullptr;
-  IterState* iter = nullptr;
-  StepState* st = nullptr;
-  Stats* stats = nullptr;
-  double* scal = nullptr;        // [0] stopping norm, [1] loss sum, [2] l1 sum
-  double* sum_part = nullptr;
-
-  // pinned host mirrors
-  double* hscal = nullptr;
-  Stats* hstats = nullptr;
-  StepState* hst = nullptr;
-  IterState* hiter = nullptr;
-
-  // replayable outer iteration (HIP graph) and the key it was captured for
-  hipGraphExec_t graph = nullptr;
-  bool use_graphs = true;
-  struct GraphKey {
-    int64_t P = -1;
-    int loss = -1;
-    double C = 0, sigma = 0, beta = 0, gamma = 0, nu = 0;
-    int max_ls = 0;
-    int schedule = -1;
-    bool operator==(const GraphKey& o) const {
-      return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
-             gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule;
-    }
-  } graph_key;
-
-  // counters known on the host (launch structure): sweep and stopping work
-  // (the *_narrow parts were swept by the single-workgroup kernel)
-  struct HostCounts {
-    double nnz_gh = 0, slots = 0, nnz_stop = 0, stop_sweeps = 0;
-    double nnz_gh_narrow = 0, slots_narrow = 0;
-  } hc, prof_hc;
-  std::vector<int64_t> h_cp;  // host copy of col_ptr
-
-  Profiler prof;
-  Stats prof_base{};
-};
-
-namespace {
-
+namespace pcdn {
+namespace host {
 
 int fail(pcdn_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
 }
 
-#define HIPCHK(ctx, expr)                                                              \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail((ctx), PCDN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-  } while (0)
-
-#define ALLOC(ctx, ptr, count)                                                         \
-  do {                                                                                 \
-    if (dalloc(&(ptr), (size_t)(count)) != hipSuccess) {                               \
-      (void)hipGetLastError();                                                         \
-      return fail((ctx), PCDN_E_OOM, "device allocation failed for " #ptr);            \
-    }                                                                                  \
-  } while (0)
-
 void drop_graph(pcdn_ctx* c) {
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   c->graph = nullptr;
   c->graph_key = pcdn_ctx::GraphKey();
+  if (c->graph_pre) (void)hipGraphExecDestroy(c->graph_pre);
+  if (c->graph_post) (void)hipGraphExecDestroy(c->graph_post);
+  c->graph_pre = c->graph_post = nullptr;
+  c->split_key = pcdn_ctx::GraphKey();
 }
 
 template <class T>
@@ -193,14 +70,6 @@ void free_data(pcdn_ctx* c) {
   c->has_state = false;
   c->n = c->p = c->nnz = 0;
 }
-
-struct Opts {
-  uint64_t seed;
-  int max_outer, max_ls;
-  double sigma, beta, gamma, nu;
-  const double* w0;
-  int schedule;
-};
 
 // Average nonzeros per bundle up to which one workgroup runs the bundles.
 constexpr double kNarrowMaxBundleNnz = 8192.0;
@@ -473,10 +342,8 @@ bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P) {
 // Bundles [t_begin, t_end) of size P over the order `perm` (descriptors in
 // c->chunks / c->cstart, p_slots slots) in one workgroup, after copying X into
 // that order.
-int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
-                          int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
-  HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
-                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->stream));
+NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
+                            int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
   NarrowArgs na{};
   na.sw = sweep_args(c, o);
   na.cache = c->cache;
@@ -499,6 +366,22 @@ int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64
   na.beta = o.beta;
   na.max_ls = o.max_ls;
   na.dtx_copy = dtx_copy;
+  na.loss = c->loss;
+  return na;
+}
+
+// Copy X into the order `perm` (descriptors in c->chunks / c->cstart).
+int permute_x(pcdn_ctx* c, const int32_t* perm, int64_t p_slots) {
+  HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
+                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->stream));
+  return PCDN_OK;
+}
+
+int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
+                          int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
+  int rc = permute_x(c, perm, p_slots);
+  if (rc) return rc;
+  const NarrowArgs na = make_narrow_args(c, o, perm, p_slots, P, t_begin, t_end, dtx_copy);
   ProfScope ps(c, 5);
   HIPCHK(c, launch_narrow(c->loss, na, c->stream));
   return PCDN_OK;
@@ -507,29 +390,50 @@ int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64
 // One outer iteration k of Algorithm 3: partition, every bundle, then the
 // stopping sweep (result in c->scal[0]).  it != null: k is read from and
 // advanced on the device (graph replays).
-int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
+// The outer iteration in three parts.  Before the bundles: partition,
+// chunk descriptors, and (single-workgroup schedule) X in partition order.
+int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
   int rc = device_permutation(c, o.seed, k, it);
   if (rc) return rc;
   HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunks, c->scan_tmp,
                           c->stream));
+  if (use_narrow(c, o, P)) return permute_x(c, c->idx0, c->p);
+  return PCDN_OK;
+}
+
+// Every bundle of the partition.
+int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
   const int64_t nb = (c->p + P - 1) / P;
   if (use_narrow(c, o, P)) {
-    rc = launch_narrow_bundles(c, o, c->idx0, c->p, P, 0, nb, nullptr);
-    if (rc) return rc;
-  } else {
-    for (int64_t t = 0; t < nb; ++t) {
-      const int64_t lo = t * P, hi = std::min(lo + P, c->p);
-      rc = run_bundle(c, o, c->idx0, lo, hi);
-      if (rc) return rc;
-    }
+    const NarrowArgs na = make_narrow_args(c, o, c->idx0, c->p, P, 0, nb, nullptr);
+    ProfScope ps(c, 5);
+    HIPCHK(c, launch_narrow(c->loss, na, c->stream));
+    return PCDN_OK;
   }
+  for (int64_t t = 0; t < nb; ++t) {
+    const int64_t lo = t * P, hi = std::min(lo + P, c->p);
+    int rc = run_bundle(c, o, c->idx0, lo, hi);
+    if (rc) return rc;
+  }
+  return PCDN_OK;
+}
+
+// After the bundles: scatter counters and the stopping sweep.
+int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
   HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, use_narrow(c, o, P), c->stats,
                                  c->stream));
   return launch_stopping(c, o, c->w, it);
 }
 
-// Capture (once per key) the outer iteration as a HIP graph.
-int ensure_graph(pcdn_ctx* c, const Opts& o, int64_t P) {
+int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
+  int rc = enqueue_pre(c, o, P, k, it);
+  if (rc) return rc;
+  rc = enqueue_bundles(c, o, P);
+  if (rc) return rc;
+  return enqueue_post(c, o, P, it);
+}
+
+pcdn_ctx::GraphKey graph_key_of(const pcdn_ctx* c, const Opts& o, int64_t P) {
   pcdn_ctx::GraphKey key;
   key.P = P;
   key.loss = c->loss;
@@ -540,31 +444,59 @@ int ensure_graph(pcdn_ctx* c, const Opts& o, int64_t P) {
   key.nu = o.nu;
   key.max_ls = o.max_ls;
   key.schedule = o.schedule;
-  if (c->graph && c->graph_key == key) return PCDN_OK;
-  drop_graph(c);
+  return key;
+}
+
+// Capture what `enqueue` puts on c's stream as an executable graph.
+template <class F>
+int capture(pcdn_ctx* c, hipGraphExec_t* out, F enqueue) {
+  *out = nullptr;
   hipGraph_t g = nullptr;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  int rc = enqueue_outer(c, o, P, 0, c->iter);
+  int rc = enqueue();
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (rc) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
   }
   if (e != hipSuccess) return fail(c, PCDN_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
-    c->graph = nullptr;
+    *out = nullptr;
     return fail(c, PCDN_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
   }
+  return PCDN_OK;
+}
+
+int ensure_graph(pcdn_ctx* c, const Opts& o, int64_t P) {
+  const pcdn_ctx::GraphKey key = graph_key_of(c, o, P);
+  if (c->graph && c->graph_key == key) return PCDN_OK;
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_key = pcdn_ctx::GraphKey();
+  int rc = capture(c, &c->graph, [&] { return enqueue_outer(c, o, P, 0, c->iter); });
+  if (rc) return rc;
   c->graph_key = key;
   return PCDN_OK;
 }
 
-// Outer iterations k_first .. k_first+count-1; the last stopping norm stays in
-// c->scal[0].  Replays a captured graph unless kernel profiling is on.
-int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t count) {
-  if (count <= 0) return PCDN_OK;
+int ensure_split_graphs(pcdn_ctx* c, const Opts& o, int64_t P) {
+  const pcdn_ctx::GraphKey key = graph_key_of(c, o, P);
+  if (c->graph_pre && c->graph_post && c->split_key == key) return PCDN_OK;
+  if (c->graph_pre) (void)hipGraphExecDestroy(c->graph_pre);
+  if (c->graph_post) (void)hipGraphExecDestroy(c->graph_post);
+  c->graph_pre = c->graph_post = nullptr;
+  c->split_key = pcdn_ctx::GraphKey();
+  int rc = capture(c, &c->graph_pre, [&] { return enqueue_pre(c, o, P, 0, c->iter); });
+  if (rc) return rc;
+  rc = capture(c, &c->graph_post, [&] { return enqueue_post(c, o, P, c->iter); });
+  if (rc) return rc;
+  c->split_key = key;
+  return PCDN_OK;
+}
+
+void count_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t count) {
   // every outer iteration sweeps each feature once in a bundle and once more
   // in the stopping test
   c->hc.nnz_gh += (double)c->nnz * count;
@@ -575,17 +507,30 @@ int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t co
   }
   c->hc.nnz_stop += (double)c->nnz * count;
   c->hc.stop_sweeps += (double)count;
+}
+
+int set_iter(pcdn_ctx* c, uint64_t seed, int64_t k) {
+  c->hiter->seed = seed;
+  c->hiter->k = k;
+  HIPCHK(c, hipMemcpyAsync(c->iter, c->hiter, sizeof(IterState), hipMemcpyHostToDevice,
+                           c->stream));
+  // the pinned source may be reused only after the copy ran
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PCDN_OK;
+}
+
+// Outer iterations k_first .. k_first+count-1; the last stopping norm stays in
+// c->scal[0].  Replays a captured graph unless kernel profiling is on.
+int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t count) {
+  if (count <= 0) return PCDN_OK;
+  count_outer(c, o, P, count);
   // kernel profiling brackets launches with events: launch directly then
   if (c->use_graphs && c->prof.mask == 0) {
     int rc = ensure_graph(c, o, P);
     if (rc) return rc;
-    c->hiter->seed = o.seed;
-    c->hiter->k = k_first;
-    HIPCHK(c, hipMemcpyAsync(c->iter, c->hiter, sizeof(IterState), hipMemcpyHostToDevice,
-                             c->stream));
+    rc = set_iter(c, o.seed, k_first);
+    if (rc) return rc;
     for (int64_t k = 0; k < count; ++k) HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
-    // the pinned source may be reused only after the copy ran
-    HIPCHK(c, hipStreamSynchronize(c->stream));
     return PCDN_OK;
   }
   for (int64_t k = k_first; k < k_first + count; ++k) {
@@ -629,7 +574,101 @@ double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& 
   }
 }
 
-}  // namespace
+
+int check_solve_args(pcdn_ctx* c, double C, int64_t P, double eps, int loss,
+                     const pcdn_opts* opts, Opts* o) {
+  if (!c) return PCDN_E_ARG;
+  if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
+  int rc = check_loss(c, loss);
+  if (rc) return rc;
+  if (!(C > 0.0) || !std::isfinite(C)) return fail(c, PCDN_E_ARG, "C must be a finite positive number");
+  if (P < 1 || P > c->p) return fail(c, PCDN_E_ARG, "bundle size P must lie in [1, p]");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, PCDN_E_ARG, "eps must be finite and >= 0");
+  return resolve_opts(c, opts, o);
+}
+
+int solve_begin(SolveRun& r) {
+  pcdn_ctx* c = r.c;
+  HIPCHK(c, hipSetDevice(c->device));
+  r.t0 = std::chrono::steady_clock::now();
+  int rc = read_stats(c);
+  if (rc) return rc;
+  r.base = *c->hstats;
+  r.hbase = c->hc;
+  c->loss = r.loss;
+  c->C = r.C;
+  r.outer = 0;
+  // reference norm at w = 0 (retained quantities all one)
+  HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));
+  r.G0 = r.G = 0.0;
+  rc = stopping_norm(c, r.o, nullptr, &r.G0);
+  if (rc) return rc;
+  if (!std::isfinite(r.G0)) return fail(c, PCDN_E_NUMERIC, "non-finite gradient at w = 0");
+  if (r.G0 == 0.0) {
+    rc = set_w(c, nullptr);
+    if (rc) return rc;
+    r.converged = true;
+  } else {
+    if (r.w0_device) {
+      rc = cache_from_w(c, false);
+    } else {
+      rc = set_w(c, r.o.w0);
+    }
+    if (rc) return rc;
+    if (r.o.w0 || r.w0_device) {
+      rc = stopping_norm(c, r.o, c->w, &r.G);
+      if (rc) return rc;
+    } else {
+      r.G = r.G0;
+    }
+    r.converged = r.G <= r.eps * r.G0;
+  }
+  c->has_state = true;
+  return PCDN_OK;
+}
+
+int solve_note_outer(SolveRun& r, double G) {
+  ++r.outer;
+  r.G = G;
+  if (!std::isfinite(G)) return fail(r.c, PCDN_E_NUMERIC, "non-finite subgradient norm");
+  r.converged = G <= r.eps * r.G0;
+  return PCDN_OK;
+}
+
+int solve_end(SolveRun& r, double* w_out, pcdn_info* info) {
+  pcdn_ctx* c = r.c;
+  double F = 0.0;
+  int rc = objective(c, &F);
+  if (rc) return rc;
+  if (std::isnan(F)) return fail(c, PCDN_E_NUMERIC, "objective is NaN");
+  if (w_out)
+    HIPCHK(c, hipMemcpyAsync(w_out, c->w, c->p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  rc = read_stats(c);
+  if (rc) return rc;
+  const auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    const Stats& s = *c->hstats;
+    info->outer_iters = r.outer;
+    info->converged = r.converged ? 1 : 0;
+    info->bundles = (int64_t)(s.bundles - r.base.bundles);
+    info->ls_steps = (int64_t)(s.ls_steps - r.base.ls_steps);
+    info->ls_fail = (int64_t)(s.ls_fail - r.base.ls_fail);
+    info->nnz_swept = (int64_t)(c->hc.nnz_gh - r.hbase.nnz_gh);
+    info->objective = F;
+    info->subgrad = r.G0 == 0.0 ? 0.0 : r.G;
+    info->subgrad0 = r.G0;
+    double bytes = 0.0;
+    for (int k = 0; k < kProfClasses; ++k) bytes += alg_bytes_of(s, r.base, c->hc, r.hbase, k, c->p);
+    info->alg_bytes = bytes;
+    info->seconds = std::chrono::duration<double>(t1 - r.t0).count();
+  }
+  return r.converged ? PCDN_OK : PCDN_NOT_CONVERGED;
+}
+
+}  // namespace host
+}  // namespace pcdn
+
+using namespace pcdn::host;
 
 // ===========================================================================
 // C ABI
@@ -911,84 +950,26 @@ extern "C" int pcdn_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, int32_t* 
 
 extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss,
                           const pcdn_opts* opts, double* w_out, pcdn_info* info) {
-  if (!c) return PCDN_E_ARG;
-  if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
-  int rc = check_loss(c, loss);
+  SolveRun r;
+  int rc = check_solve_args(c, C, P, eps, loss, opts, &r.o);
   if (rc) return rc;
-  if (!(C > 0.0) || !std::isfinite(C)) return fail(c, PCDN_E_ARG, "C must be a finite positive number");
-  if (P < 1 || P > c->p) return fail(c, PCDN_E_ARG, "bundle size P must lie in [1, p]");
-  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, PCDN_E_ARG, "eps must be finite and >= 0");
-  Opts o;
-  rc = resolve_opts(c, opts, &o);
+  r.c = c;
+  r.C = C;
+  r.P = P;
+  r.eps = eps;
+  r.loss = loss;
+  rc = solve_begin(r);
   if (rc) return rc;
-  HIPCHK(c, hipSetDevice(c->device));
-  const auto t0 = std::chrono::steady_clock::now();
-  rc = read_stats(c);
-  if (rc) return rc;
-  const Stats base = *c->hstats;
-  const pcdn_ctx::HostCounts hbase = c->hc;
-  c->loss = loss;
-  c->C = C;
-
-  // reference norm at w = 0 (retained quantities all one)
-  HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));
-  double G0 = 0.0, G = 0.0;
-  rc = stopping_norm(c, o, nullptr, &G0);
-  if (rc) return rc;
-  if (!std::isfinite(G0)) return fail(c, PCDN_E_NUMERIC, "non-finite gradient at w = 0");
-  bool converged = false;
-  if (G0 == 0.0) {
-    rc = set_w(c, nullptr);
+  while (!r.converged && r.outer < r.o.max_outer) {
+    rc = run_outer(c, r.o, P, r.outer, 1);
     if (rc) return rc;
-    converged = true;
-  } else {
-    rc = set_w(c, o.w0);
-    if (rc) return rc;
-    if (o.w0) {
-      rc = stopping_norm(c, o, c->w, &G);
-      if (rc) return rc;
-    } else {
-      G = G0;
-    }
-    converged = G <= eps * G0;
-  }
-  c->has_state = true;
-  int outer = 0;
-  while (!converged && outer < o.max_outer) {
-    rc = run_outer(c, o, P, outer, 1);
-    if (rc) return rc;
-    ++outer;
+    double G = 0.0;
     rc = read_scalar(c, 0, &G);
     if (rc) return rc;
-    if (!std::isfinite(G)) return fail(c, PCDN_E_NUMERIC, "non-finite subgradient norm");
-    converged = G <= eps * G0;
+    rc = solve_note_outer(r, G);
+    if (rc) return rc;
   }
-  double F = 0.0;
-  rc = objective(c, &F);
-  if (rc) return rc;
-  if (std::isnan(F)) return fail(c, PCDN_E_NUMERIC, "objective is NaN");
-  if (w_out)
-    HIPCHK(c, hipMemcpyAsync(w_out, c->w, c->p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  rc = read_stats(c);
-  if (rc) return rc;
-  const auto t1 = std::chrono::steady_clock::now();
-  if (info) {
-    const Stats& s = *c->hstats;
-    info->outer_iters = outer;
-    info->converged = converged ? 1 : 0;
-    info->bundles = (int64_t)(s.bundles - base.bundles);
-    info->ls_steps = (int64_t)(s.ls_steps - base.ls_steps);
-    info->ls_fail = (int64_t)(s.ls_fail - base.ls_fail);
-    info->nnz_swept = (int64_t)(c->hc.nnz_gh - hbase.nnz_gh);
-    info->objective = F;
-    info->subgrad = G0 == 0.0 ? 0.0 : G;
-    info->subgrad0 = G0;
-    double bytes = 0.0;
-    for (int k = 0; k < kProfClasses; ++k) bytes += alg_bytes_of(s, base, c->hc, hbase, k, c->p);
-    info->alg_bytes = bytes;
-    info->seconds = std::chrono::duration<double>(t1 - t0).count();
-  }
-  return converged ? PCDN_OK : PCDN_NOT_CONVERGED;
+  return solve_end(r, w_out, info);
 }
 
 extern "C" int pcdn_iterate(pcdn_ctx* c, int64_t P, int64_t k_first, int64_t count,

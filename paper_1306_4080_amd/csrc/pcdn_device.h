@@ -148,6 +148,7 @@ struct NarrowArgs {
   double* dtx_copy;    // nullable: receives d^T x of the (last) bundle
   double C, sigma, beta;
   int max_ls;
+  int loss;            // kLogistic / kL2Svm (read by the multi-problem kernel)
 };
 
 // ---- host-callable launchers (pcdn_kernels.hip) -------------------------
@@ -174,6 +175,8 @@ int ls_grid(int64_t n);
 hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s);
 hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s);
 hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
+// One workgroup per entry of the device table tab[0..count).
+hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s);
 // X in partition order for the single-workgroup schedule (needs nnz < 2^31).
 // `chunks`/`cstart` are the chunk descriptors of the same slot order.
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,

@@ -1,0 +1,219 @@
+// Host-side state of a PCDN context and the internal driver functions shared
+// by the single-problem entry points (pcdn_api.hip) and the multi-problem
+// drivers (pcdn_batch.hip).  Not part of the public ABI.
+#pragma once
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/pcdn.h"
+#include "pcdn_device.h"
+
+namespace pcdn {
+namespace host {
+
+// sweep, split scatter, line search, apply, stopping sweep, single-workgroup bundles
+constexpr int kProfClasses = 6;
+
+struct Profiler {
+  int mask = 0;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[kProfClasses] = {};
+  int64_t launches[kProfClasses] = {};
+};
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+}  // namespace host
+}  // namespace pcdn
+
+using pcdn::Chunk;
+using pcdn::IterState;
+using pcdn::Stats;
+using pcdn::StepState;
+
+struct pcdn_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // data
+  int64_t n = 0, p = 0, nnz = 0;
+  bool loaded = false;
+  int64_t* cp = nullptr;
+  int32_t* ri = nullptr;
+  float* v = nullptr;
+  int8_t* y = nullptr;
+
+  // state
+  int loss = -1;
+  double C = 0.0;
+  bool has_state = false;
+  double* w = nullptr;
+  double* cache = nullptr;
+  double* dtx = nullptr;
+  double* tmp_n = nullptr;
+  double* tmp_p = nullptr;
+  unsigned* rowflag = nullptr;
+  double* g = nullptr;
+  double* h = nullptr;
+  double* d = nullptr;
+  double* dterm = nullptr;
+
+  // partition and chunk bookkeeping
+  uint32_t* keys0 = nullptr;
+  uint32_t* keys1 = nullptr;
+  int32_t* idx0 = nullptr;
+  int32_t* idx1 = nullptr;
+  int32_t* hist = nullptr;
+  int32_t* scan_tmp = nullptr;
+  int32_t* nch = nullptr;
+  int32_t* cstart = nullptr;
+  Chunk* chunks = nullptr;
+  int32_t* id_cstart = nullptr;
+  Chunk* id_chunks = nullptr;
+  int64_t id_total_chunks = 0;
+  int32_t* step_perm = nullptr;
+  int64_t max_chunks = 0;
+  double2* part = nullptr;
+  int64_t part_len = 0;
+  // X in partition order (single-workgroup schedule)
+  int32_t* pri = nullptr;
+  float* pv = nullptr;
+  int64_t* poff = nullptr;
+  int32_t* off32 = nullptr;
+
+  // reductions and small device records
+  double* ls_part = nullptr;
+  IterState* iter = nullptr;
+  StepState* st = nullptr;
+  Stats* stats = nullptr;
+  double* scal = nullptr;        // [0] stopping norm, [1] loss sum, [2] l1 sum
+  double* sum_part = nullptr;
+
+  // pinned host mirrors
+  double* hscal = nullptr;
+  Stats* hstats = nullptr;
+  StepState* hst = nullptr;
+  IterState* hiter = nullptr;
+
+  // replayable outer iteration (HIP graph) and the key it was captured for
+  hipGraphExec_t graph = nullptr;
+  bool use_graphs = true;
+  struct GraphKey {
+    int64_t P = -1;
+    int loss = -1;
+    double C = 0, sigma = 0, beta = 0, gamma = 0, nu = 0;
+    int max_ls = 0;
+    int schedule = -1;
+    bool operator==(const GraphKey& o) const {
+      return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
+             gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule;
+    }
+  } graph_key;
+  // the same outer iteration in two parts around the bundles, for drivers
+  // that run the bundles of several problems in one launch
+  hipGraphExec_t graph_pre = nullptr;   // partition, chunking, partition-order copy of X
+  hipGraphExec_t graph_post = nullptr;  // counters, stopping sweep (advances the iteration)
+  GraphKey split_key;
+
+  // counters known on the host (launch structure): sweep and stopping work
+  // (the *_narrow parts were swept by the single-workgroup kernel)
+  struct HostCounts {
+    double nnz_gh = 0, slots = 0, nnz_stop = 0, stop_sweeps = 0;
+    double nnz_gh_narrow = 0, slots_narrow = 0;
+  } hc, prof_hc;
+  std::vector<int64_t> h_cp;  // host copy of col_ptr
+
+  pcdn::host::Profiler prof;
+  Stats prof_base{};
+};
+
+namespace pcdn {
+namespace host {
+
+// Record msg as ctx's last error and return code.
+int fail(pcdn_ctx* c, int code, const std::string& msg);
+
+#define HIPCHK(ctx, expr)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((ctx), PCDN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define ALLOC(ctx, ptr, count)                                                         \
+  do {                                                                                 \
+    if (dalloc(&(ptr), (size_t)(count)) != hipSuccess) {                               \
+      (void)hipGetLastError();                                                         \
+      return fail((ctx), PCDN_E_OOM, "device allocation failed for " #ptr);            \
+    }                                                                                  \
+  } while (0)
+
+struct Opts {
+  uint64_t seed;
+  int max_outer, max_ls;
+  double sigma, beta, gamma, nu;
+  const double* w0;
+  int schedule;
+};
+
+// Options with defaults filled in and validated (o may be null).
+int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r);
+int check_loss(pcdn_ctx* c, int loss);
+// Whether outer iterations with bundle size P run in one workgroup.
+bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
+// Arguments of the single-workgroup kernel for bundles [t_begin, t_end).
+pcdn::NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm,
+                                  int64_t p_slots, int64_t P, int64_t t_begin, int64_t t_end,
+                                  double* dtx_copy);
+// Capture (once per key) the two halves of an outer iteration around the
+// single-workgroup bundles: graph_pre and graph_post (see pcdn_ctx).
+int ensure_split_graphs(pcdn_ctx* c, const Opts& o, int64_t P);
+// Capture (once per key) a whole outer iteration (graph).
+int ensure_graph(pcdn_ctx* c, const Opts& o, int64_t P);
+// Host-known work of `count` outer iterations (sweep and stopping counters).
+void count_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t count);
+// Set the device-side outer-iteration record (seed, k) read by graph replays.
+int set_iter(pcdn_ctx* c, uint64_t seed, int64_t k);
+int read_stats(pcdn_ctx* c);
+// Outer iterations k_first .. k_first+count-1 (graph replays unless profiling).
+int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t count);
+// Copy c->scal[idx] to the host (synchronises the stream).
+int read_scalar(pcdn_ctx* c, int idx, double* out);
+
+// One pcdn_solve in progress: solve_begin validates nothing (callers do),
+// computes the reference norm at w = 0 and sets up w; the caller runs outer
+// iterations until `converged` or max_outer, then solve_end reports.
+struct SolveRun {
+  pcdn_ctx* c = nullptr;
+  Opts o{};
+  double C = 0.0, eps = 0.0;
+  int64_t P = 0;
+  int loss = 0;
+  Stats base{};
+  pcdn_ctx::HostCounts hbase{};
+  double G0 = 0.0, G = 0.0;
+  bool converged = false;
+  int outer = 0;
+  bool w0_device = false;  // warm start from the w already on the device
+  std::chrono::steady_clock::time_point t0;
+};
+// Validate the arguments of a solve (as pcdn_solve does).
+int check_solve_args(pcdn_ctx* c, double C, int64_t P, double eps, int loss,
+                     const pcdn_opts* opts, Opts* o);
+int solve_begin(SolveRun& r);
+// Record a finished outer iteration whose stopping norm is G.
+int solve_note_outer(SolveRun& r, double G);
+int solve_end(SolveRun& r, double* w_out, pcdn_info* info);
+
+}  // namespace host
+}  // namespace pcdn

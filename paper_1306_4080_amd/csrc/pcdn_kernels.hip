@@ -806,10 +806,8 @@ __device__ inline void list_row(NarrowLds& L, int32_t row, double c, int yi) {
 }
 
 template <int LOSS>
-__global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
-  __shared__ NarrowLds L;
+__device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) {
   const SweepArgs& a = na.sw;
-  const int lane = lane_id();
   const int tid = threadIdx.x;
   double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0;
   for (int64_t t = na.t_begin; t < na.t_end; ++t) {
@@ -1073,6 +1071,23 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
   }
 }
 
+template <int LOSS>
+__global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
+  __shared__ NarrowLds L;
+  narrow_body<LOSS>(na, L);
+}
+
+// Independent problems in one launch: workgroup b runs the bundles of
+// problem tab[b] (each with its own loss, data and state).
+__global__ __launch_bounds__(kNarrowBlock) void k_narrow_multi(const NarrowArgs* tab) {
+  __shared__ NarrowLds L;
+  const NarrowArgs& na = tab[blockIdx.x];
+  if (na.loss == kLogistic)
+    narrow_body<kLogistic>(na, L);
+  else
+    narrow_body<kL2Svm>(na, L);
+}
+
 // Copy X into partition order: the nonzeros of slot r land at
 // [poff[r], poff[r+1]) (one wavefront per chunk descriptor).
 __global__ __launch_bounds__(kBlock) void k_permute(const int32_t* ri, const float* v,
@@ -1330,6 +1345,12 @@ hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_narrow<kLogistic>, dim3(1), dim3(kNarrowBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_narrow<kL2Svm>, dim3(1), dim3(kNarrowBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_narrow_multi, dim3(count), dim3(kNarrowBlock), 0, s, tab);
   return hipGetLastError();
 }
 

@@ -1,0 +1,182 @@
+"""Several solves per call, through the C ABI: pcdn_solve_batch (independent
+problems advanced together, the single-workgroup ones in one launch) and
+pcdn_solve_path (a regularisation path with warm starts).
+
+Bars:
+- every batched job against the same solve run alone with pcdn_solve: the
+  same outer iterations, bundles, line-search steps and failures, F within
+  1e-12 relative and w within 1e-9 (the d^T x atomics may move last bits);
+- every job and every path point against the FP64 oracle: F within 1e-6
+  relative and the same trajectory on the non-degenerate problems.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pc():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_4080_amd as pc
+    pc.ensure_built()
+    return pc
+
+
+def _empty(n, p):
+    return synth.Data(n=n, p=p, col_ptr=np.zeros(p + 1, np.int64), row_idx=np.zeros(0, np.int32),
+                      val=np.zeros(0, np.float32), y=np.where(np.arange(n) % 2, 1, -1).astype(np.int8))
+
+
+def _mixed_jobs():
+    """(name, data, loss, C, P, eps, opts, strict) of a mixed batch: both
+    losses, both schedules, sizes from 3x4 to 2,000x3,000, one job that is
+    optimal at w = 0 and one that stops at max_outer."""
+    c1 = synth.c1()
+    return [
+        ("c1-lr-narrow", c1, "lr", 1.0, 32, 1e-4, {}, True),
+        ("c1-svm-narrow", c1, "svm", 0.5, 32, 1e-4, {}, True),
+        ("c1-lr-wide", c1, "lr", 2.0, 64, 1e-4, {"schedule": "wide"}, True),
+        ("rand-lr", synth.sparse_random(11, 2000, 3000, 0.004), "lr", 1.0, 96, 1e-4, {}, True),
+        ("rand-svm-wide", synth.sparse_random(12, 800, 5000, 0.002, binary=True), "svm", 0.3, 512,
+         1e-3, {"schedule": "wide"}, True),
+        ("tiny-lr-p1", synth.tiny(70, n=50, p=13, density=0.3, empty_cols=(0, 5)), "lr", 1.0, 1,
+         1e-6, {"max_outer": 500}, False),
+        ("empty", _empty(3, 4), "svm", 1.0, 2, 1e-6, {}, False),
+        ("c1-lr-maxouter", c1, "lr", 1.0, 32, 1e-12, {"max_outer": 3}, True),
+    ]
+
+
+def _assert_same_run(a, b):
+    """Batched vs alone on the GPU: same trajectory, same result up to the
+    last bits the d^T x atomics may move."""
+    (ra, wa, ia), (rb, wb, ib) = a, b
+    assert ra == rb
+    for k in ("outer_iters", "converged", "bundles", "ls_steps", "ls_fail", "nnz_swept"):
+        assert ia[k] == ib[k], (k, ia[k], ib[k])
+    assert ia["objective"] == pytest.approx(ib["objective"], rel=1e-12)
+    np.testing.assert_allclose(wa, wb, rtol=1e-9, atol=1e-12)
+
+
+def _assert_oracle(g, o, strict):
+    rc, w_g, ig = g
+    w_o, io = o
+    assert ig["objective"] == pytest.approx(io["objective"], rel=RTOL)
+    assert ig["converged"] == io["converged"]
+    if strict:
+        for k in ("outer_iters", "bundles", "ls_steps", "ls_fail", "nnz_swept"):
+            assert ig[k] == io[k], (k, ig[k], io[k])
+
+
+def test_batch_matches_alone_and_oracle(pc):
+    jobs = _mixed_jobs()
+    solvers = [pc.Solver(device=0).load_data(d) for _, d, *_ in jobs]
+    specs = [s.job(C, P, eps, loss, seed=5, **opts)
+             for s, (_, d, loss, C, P, eps, opts, _) in zip(solvers, jobs)]
+    batched = pc.solve_batch(specs)
+    for s, (name, d, loss, C, P, eps, opts, strict), b in zip(solvers, jobs, batched):
+        print(f"{name}: status={b[0]} outer={b[2]['outer_iters']} F={b[2]['objective']:.15g}",
+              flush=True)
+        alone = s.solve(C, P, eps, loss, seed=5, **opts)
+        _assert_same_run(b, alone)
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss=loss, C=C),
+                                  P=P, eps=eps, seed=5, max_outer=opts.get("max_outer", 1000))
+        _assert_oracle(b, (w_o, io), strict)
+    assert batched[-1][0] == 1           # stopped at max_outer
+    assert batched[-2][2]["outer_iters"] == 0 and np.all(batched[-2][1] == 0)
+    for s in solvers:
+        s.close()
+
+
+def test_batch_many_small_problems(pc):
+    """32 heterogeneous LR problems (the batched recipe at small sizes) in one
+    call: every job equals its solve alone."""
+    rng = np.random.default_rng(4)
+    data = []
+    for i in range(32):
+        n = int(rng.integers(200, 1500))
+        p = int(rng.integers(300, 3000))
+        dens = float(rng.uniform(0.002, 0.02))
+        data.append(synth.sparse_random(100 + i, n, p, dens))
+    solvers = [pc.Solver(device=0).load_data(d) for d in data]
+    specs = [s.job(1.0, max(1, d.p // 20), 1e-4, "lr", seed=9) for s, d in zip(solvers, data)]
+    batched = pc.solve_batch(specs)
+    for s, d, b in zip(solvers, data, batched):
+        alone = s.solve(1.0, max(1, d.p // 20), 1e-4, "lr", seed=9)
+        _assert_same_run(b, alone)
+        assert b[0] == 0
+    # spot-check three of them against the oracle
+    for i in (0, 13, 31):
+        d = data[i]
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss="lr", C=1.0),
+                                  P=max(1, d.p // 20), eps=1e-4, seed=9)
+        _assert_oracle(batched[i], (w_o, io), True)
+    for s in solvers:
+        s.close()
+
+
+def test_batch_errors_run_nothing(pc):
+    from paper_1306_4080_amd import PcdnError
+    d = synth.c1()
+    a = pc.Solver(device=0).load_data(d)
+    b = pc.Solver(device=0).load_data(d)
+    assert pc.solve_batch([]) == []
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.solve_batch([a.job(1.0, 32, 1e-4, "lr"), b.job(-1.0, 32, 1e-4, "lr")])
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.solve_batch([a.job(1.0, 32, 1e-4, "lr"), a.job(1.0, 32, 1e-4, "lr")])
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.solve_batch([a.job(1.0, 0, 1e-4, "lr")])
+    # nothing ran: a has no state yet
+    with pytest.raises(PcdnError, match="E_STATE"):
+        a.evaluate()
+    a.close()
+    b.close()
+
+
+def test_path_matches_oracle_chain(pc):
+    """C log-spaced, ascending, each solve warm-started from the previous
+    solution; the oracle runs the same chain."""
+    d = synth.c1()
+    Cs = 2.0 ** np.linspace(-4, 2, 6)
+    s = pc.Solver(device=0).load_data(d)
+    rc, W, infos = s.solve_path(Cs, 32, 1e-4, "lr", seed=3)
+    assert rc == 0
+    prob = oracle.Problem.from_data(d)
+    w_prev = None
+    for k, C in enumerate(Cs):
+        w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=float(C)), P=32, eps=1e-4,
+                                  seed=3, w0=w_prev)
+        print(f"C={C:.4g}: outer {infos[k]['outer_iters']}/{io['outer_iters']} "
+              f"F {infos[k]['objective']:.15g}/{io['objective']:.15g}", flush=True)
+        _assert_oracle((rc, W[k], infos[k]), (w_o, io), True)
+        w_prev = w_o
+    # the path equals solves chained through the host-side warm start
+    w_prev = None
+    for k, C in enumerate(Cs):
+        r2, w2, i2 = s.solve(float(C), 32, 1e-4, "lr", seed=3, w0=w_prev)
+        _assert_same_run((rc, W[k], infos[k]), (r2, w2, i2))
+        w_prev = w2
+    s.close()
+
+
+def test_path_svm_wide(pc):
+    d = synth.sparse_random(21, 1500, 4000, 0.003, binary=True)
+    Cs = [0.05, 0.2, 0.8]
+    s = pc.Solver(device=0).load_data(d)
+    rc, W, infos = s.solve_path(Cs, 1024, 1e-3, "svm", seed=2, schedule="wide")
+    prob = oracle.Problem.from_data(d)
+    w_prev = None
+    for k, C in enumerate(Cs):
+        w_o, io, _ = oracle.solve(prob, oracle.Params(loss="svm", C=C), P=1024, eps=1e-3, seed=2,
+                                  w0=w_prev)
+        _assert_oracle((rc, W[k], infos[k]), (w_o, io), True)
+        w_prev = w_o
+    s.close()
