@@ -90,7 +90,11 @@ def test_step_parity_c1(pc, loss, schedule):
         w = _random_w(rng, d.p) if trial else np.zeros(d.p)
         s.reset(loss, C, w)
         cache = oracle.cache_from_w(prob, loss, w)
-        np.testing.assert_allclose(s.cache(), cache, rtol=1e-12)
+        # z = X w is summed with atomics in no fixed order, so the SVM slack
+        # b = 1 - y z carries a few ulps of max(1, |z|) in absolute terms
+        # (relative bounds fail where b is near 0 after the cancellation)
+        atol = 1e-13 if loss == "svm" else 0.0
+        np.testing.assert_allclose(s.cache(), cache, rtol=1e-12, atol=atol)
         perm = oracle.permutation(3, trial, d.p)
         P = [32, 1, 500, 77, 32, 250][trial]
         bundle = perm[:P]
@@ -99,7 +103,7 @@ def test_step_parity_c1(pc, loss, schedule):
         s_gpu = s.step(bundle, schedule=schedule)
         _compare_step(d, s_gpu, s_orc, bundle, C)
         np.testing.assert_allclose(s.w(), w_o, rtol=1e-12, atol=1e-15)
-        np.testing.assert_allclose(s.cache(), cache, rtol=1e-10)
+        np.testing.assert_allclose(s.cache(), cache, rtol=1e-10, atol=10 * atol)
     s.close()
 
 
