@@ -181,12 +181,17 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
 // Inner iteration of Algorithm 3 on slots [lo, hi) of `perm` whose chunk
 // descriptors are c->chunks / c->cstart, first half: sweep (g, h, d, fused
 // d^T x) and split columns.
-int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
+SweepArgs bundle_sweep_args(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
   SweepArgs a = sweep_args(c, o);
   a.chunks = c->chunks;
   a.cstart = c->cstart;
   a.slot_lo = lo;
   a.slot_hi = hi;
+  return a;
+}
+
+int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
+  const SweepArgs a = bundle_sweep_args(c, o, lo, hi);
   {
     ProfScope ps(c, 0);
     HIPCHK(c, launch_sweep(c->loss, false, a, c->stream));
@@ -200,7 +205,7 @@ int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
 
 // Second half: line-search partials, then decision + apply.  With the first
 // half, four kernel boundaries are the only synchronisation of a bundle.
-int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
   LsArgs l{};
   l.dtx = c->dtx;
   l.cache = c->cache;
@@ -216,10 +221,10 @@ int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo,
   l.stats = c->stats;
   l.beta = o.beta;
   l.Q = o.max_ls;
-  {
-    ProfScope ps(c, 2);
-    HIPCHK(c, launch_linesearch(c->loss, l, c->stream));
-  }
+  return l;
+}
+
+ApplyArgs apply_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
   ApplyArgs ap{};
   ap.dtx = c->dtx;
   ap.cache = c->cache;
@@ -239,9 +244,17 @@ int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo,
   ap.beta = o.beta;
   ap.Q = o.max_ls;
   ap.max_ls = o.max_ls;
+  return ap;
+}
+
+int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+  {
+    ProfScope ps(c, 2);
+    HIPCHK(c, launch_linesearch(c->loss, ls_args(c, o, perm, lo, hi), c->stream));
+  }
   {
     ProfScope ps(c, 3);
-    HIPCHK(c, launch_apply(c->loss, ap, c->stream));
+    HIPCHK(c, launch_apply(c->loss, apply_args(c, o, perm, lo, hi), c->stream));
   }
   return PCDN_OK;
 }
@@ -254,13 +267,18 @@ int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
 
 // ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0);
 // `it` (nullable) is advanced by the final reduction.
-int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) {
+SweepArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
   SweepArgs a = sweep_args(c, o);
   a.w = w;
   a.chunks = c->id_chunks;
   a.cstart = c->id_cstart;
   a.slot_lo = 0;
   a.slot_hi = c->p;
+  return a;
+}
+
+int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) {
+  const SweepArgs a = stop_args(c, o, w);
   {
     ProfScope ps(c, 4);
     HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
@@ -431,6 +449,52 @@ int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* i
   rc = enqueue_bundles(c, o, P);
   if (rc) return rc;
   return enqueue_post(c, o, P, it);
+}
+
+int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
+  if (use_narrow(c, o, P)) return fail(c, PCDN_E_ARG, "outer_tasks: single-workgroup schedule");
+  out.clear();
+  auto task = [&](int kind, int nblk, int gx) {
+    Task t;
+    std::memset(&t, 0, sizeof(t));
+    t.kind = kind;
+    t.loss = c->loss;
+    t.nblk = nblk;
+    t.gx = gx;
+    return t;
+  };
+  const int64_t nb = (c->p + P - 1) / P;
+  const int lsx = ls_grid(c->n), lsy = (o.max_ls + kQGroup - 1) / kQGroup;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t lo = b * P, hi = std::min(lo + P, c->p);
+    Task t = task(kTaskSweep, sweep_grid(hi - lo), 0);
+    t.u.sw = bundle_sweep_args(c, o, lo, hi);
+    out.push_back(t);
+    t.kind = kTaskSplit;
+    out.push_back(t);
+    t = task(kTaskLinesearch, lsx * lsy, lsx);
+    t.u.ls = ls_args(c, o, c->idx0, lo, hi);
+    out.push_back(t);
+    t = task(kTaskApply, apply_grid(c->n, hi - lo), 0);
+    t.u.ap = apply_args(c, o, c->idx0, lo, hi);
+    out.push_back(t);
+  }
+  Task t = task(kTaskScatterCount, scatter_count_grid(c->p), 0);
+  t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, 0, c->stats};
+  out.push_back(t);
+  t = task(kTaskSweepStop, sweep_grid(c->p), 0);
+  t.u.sw = stop_args(c, o, c->w);
+  out.push_back(t);
+  t.kind = kTaskSplitStop;
+  out.push_back(t);
+  const int sb = sum_grid(c->p);
+  t = task(kTaskSumPartial, sb, 0);
+  t.u.sum = SumArgs{c->tmp_p, c->p, c->sum_part, c->scal, c->iter, sb};
+  out.push_back(t);
+  t.kind = kTaskSumFinal;
+  t.nblk = 1;
+  out.push_back(t);
+  return PCDN_OK;
 }
 
 pcdn_ctx::GraphKey graph_key_of(const pcdn_ctx* c, const Opts& o, int64_t P) {

@@ -2,6 +2,7 @@
 // together (pcdn_solve_batch) and the warm-started regularisation path
 // (pcdn_solve_path).  Each problem follows exactly the sequence of kernels
 // pcdn_solve would run for it; only the interleaving across problems differs.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -16,27 +17,53 @@ namespace {
 // Device resources of one pcdn_solve_batch call, released on every exit.
 struct BatchRes {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t narrow_stream = nullptr;  // the multi-problem single-workgroup launch
+  hipStream_t wide_stream = nullptr;    // the executor launches
   hipEvent_t fused_done = nullptr;
   std::vector<hipEvent_t> pre_done;
-  NarrowArgs* dtab = nullptr;   // device table of the fused launch
-  NarrowArgs* htab = nullptr;   // pinned staging for it
+  NarrowArgs* dtab = nullptr;           // device table of the fused launch
+  NarrowArgs* htab = nullptr;           // pinned staging for it
+  void* dexec = nullptr;                // executor tables (tasks, block offsets, scalar sources)
+  void* hexec = nullptr;                // pinned staging for them
+  size_t exec_bytes = 0;
+  double* dG = nullptr;                 // gathered stopping norms of the multi-kernel jobs
+  double* hG = nullptr;
   ~BatchRes() {
     (void)hipSetDevice(device);
-    if (stream) (void)hipStreamSynchronize(stream);
+    if (narrow_stream) (void)hipStreamSynchronize(narrow_stream);
+    if (wide_stream) (void)hipStreamSynchronize(wide_stream);
     for (hipEvent_t e : pre_done)
       if (e) (void)hipEventDestroy(e);
     if (fused_done) (void)hipEventDestroy(fused_done);
     if (dtab) (void)hipFree(dtab);
     if (htab) (void)hipHostFree(htab);
-    if (stream) (void)hipStreamDestroy(stream);
+    if (dexec) (void)hipFree(dexec);
+    if (hexec) (void)hipHostFree(hexec);
+    if (dG) (void)hipFree(dG);
+    if (hG) (void)hipHostFree(hG);
+    if (narrow_stream) (void)hipStreamDestroy(narrow_stream);
+    if (wide_stream) (void)hipStreamDestroy(wide_stream);
   }
 };
 
 // Device error of the batch itself, reported on the first job's context.
 int batch_fail(pcdn_ctx* c, hipError_t e, const char* what) {
+  (void)hipGetLastError();
   return fail(c, PCDN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Lock-step schedule of the multi-kernel jobs of one round: launch s runs
+// task s of every job that has one (a job's tasks are the kernels of its
+// outer iteration after the partition, in order).
+struct ExecPlan {
+  std::vector<int> jobs;          // job indices, in gather order
+  std::vector<size_t> task_off;   // per launch: first task (index into the task table)
+  std::vector<size_t> first_off;  // per launch: first block offset (index into the offsets)
+  std::vector<int> count, blocks; // per launch
+  size_t n_tasks = 0, n_first = 0;
+};
 
 }  // namespace
 
@@ -68,68 +95,126 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
   BatchRes res;
   res.device = c0->device;
   HIPCHK(c0, hipSetDevice(res.device));
-  HIPCHK(c0, hipStreamCreateWithFlags(&res.stream, hipStreamNonBlocking));
+  HIPCHK(c0, hipStreamCreateWithFlags(&res.narrow_stream, hipStreamNonBlocking));
+  HIPCHK(c0, hipStreamCreateWithFlags(&res.wide_stream, hipStreamNonBlocking));
   HIPCHK(c0, hipEventCreateWithFlags(&res.fused_done, hipEventDisableTiming));
   res.pre_done.assign(count, nullptr);
   for (int32_t i = 0; i < count; ++i)
     HIPCHK(c0, hipEventCreateWithFlags(&res.pre_done[i], hipEventDisableTiming));
 
-  // set-up: reference norm and w per job, graphs, iteration record
+  // set-up: reference norm and w per job, graphs or task lists, iteration record
   std::vector<char> narrow(count, 0), active(count, 0);
+  std::vector<std::vector<Task>> tasks(count);
   int32_t n_narrow = 0;
+  size_t all_tasks = 0, all_first = 0, max_len = 0;
   for (int32_t i = 0; i < count; ++i) {
     SolveRun& r = runs[i];
     int rc = solve_begin(r);
     if (rc) return rc;
     narrow[i] = use_narrow(r.c, r.o, r.P) ? 1 : 0;
     n_narrow += narrow[i];
-    rc = narrow[i] ? ensure_split_graphs(r.c, r.o, r.P) : ensure_graph(r.c, r.o, r.P);
+    rc = ensure_split_graphs(r.c, r.o, r.P);
     if (rc) return rc;
+    if (!narrow[i]) {
+      rc = outer_tasks(r.c, r.o, r.P, tasks[i]);
+      if (rc) return rc;
+      all_tasks += tasks[i].size();
+      max_len = std::max(max_len, tasks[i].size());
+    }
     rc = set_iter(r.c, r.o.seed, 0);
     if (rc) return rc;
     active[i] = !r.converged && r.outer < r.o.max_outer;
   }
+  const int32_t n_wide = count - n_narrow;
+  // at most one block-offset entry per task plus one per launch
+  all_first = all_tasks + max_len;
   if (n_narrow > 0) {
-    hipError_t e = hipMalloc((void**)&res.dtab, sizeof(NarrowArgs) * n_narrow);
-    if (e != hipSuccess) {
+    if (dalloc(&res.dtab, n_narrow) != hipSuccess ||
+        hipHostMalloc((void**)&res.htab, sizeof(NarrowArgs) * n_narrow) != hipSuccess) {
       (void)hipGetLastError();
-      return fail(c0, PCDN_E_OOM, "device allocation failed for the batch table");
-    }
-    e = hipHostMalloc((void**)&res.htab, sizeof(NarrowArgs) * n_narrow);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c0, PCDN_E_OOM, "pinned allocation failed for the batch table");
+      return fail(c0, PCDN_E_OOM, "allocation failed for the batch table");
     }
   }
+  if (n_wide > 0) {
+    res.exec_bytes = align_up(sizeof(Task) * all_tasks) + align_up(sizeof(int32_t) * all_first) +
+                     align_up(sizeof(double*) * n_wide);
+    if (hipMalloc(&res.dexec, res.exec_bytes) != hipSuccess ||
+        hipHostMalloc(&res.hexec, res.exec_bytes) != hipSuccess ||
+        dalloc(&res.dG, n_wide) != hipSuccess ||
+        hipHostMalloc((void**)&res.hG, sizeof(double) * n_wide) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c0, PCDN_E_OOM, "allocation failed for the executor tables");
+    }
+  }
+  Task* const htasks = (Task*)res.hexec;
+  int32_t* const hfirst = (int32_t*)((char*)res.hexec + align_up(sizeof(Task) * all_tasks));
+  const double** const hsrc =
+      (const double**)((char*)hfirst + align_up(sizeof(int32_t) * all_first));
+  const Task* const dtasks = (const Task*)res.dexec;
+  const int32_t* const dfirst = (const int32_t*)((char*)res.dexec + ((char*)hfirst - (char*)res.hexec));
+  const double* const* const dsrc =
+      (const double* const*)((char*)res.dexec + ((char*)hsrc - (char*)res.hexec));
 
+  ExecPlan plan;
+  bool plan_stale = true;
   // rounds: one outer iteration of every active job
   for (;;) {
-    int32_t m = 0, live = 0;
+    int32_t live = 0;
+    for (int32_t i = 0; i < count; ++i) live += active[i];
+    if (live == 0) break;
+    // multi-kernel jobs: (re)build the lock-step tables when the set changed
+    if (plan_stale) {
+      plan = ExecPlan();
+      for (int32_t i = 0; i < count; ++i)
+        if (active[i] && !narrow[i]) plan.jobs.push_back(i);
+      size_t L = 0;
+      for (int i : plan.jobs) L = std::max(L, tasks[i].size());
+      for (size_t st = 0; st < L; ++st) {
+        plan.task_off.push_back(plan.n_tasks);
+        plan.first_off.push_back(plan.n_first);
+        int cnt = 0, blk = 0;
+        hfirst[plan.n_first++] = 0;
+        for (int i : plan.jobs) {
+          if (st >= tasks[i].size()) continue;
+          htasks[plan.n_tasks++] = tasks[i][st];
+          blk += tasks[i][st].nblk;
+          hfirst[plan.n_first++] = blk;
+          ++cnt;
+        }
+        plan.count.push_back(cnt);
+        plan.blocks.push_back(blk);
+      }
+      for (size_t k = 0; k < plan.jobs.size(); ++k) hsrc[k] = runs[plan.jobs[k]].c->scal;
+      if (!plan.jobs.empty()) {
+        const hipError_t e = hipMemcpyAsync(res.dexec, res.hexec, res.exec_bytes,
+                                            hipMemcpyHostToDevice, res.wide_stream);
+        if (e != hipSuccess) return batch_fail(c0, e, "executor table upload");
+      }
+      plan_stale = false;
+    }
+    // partitions of every active job, each on its own stream
+    int32_t m = 0;
     for (int32_t i = 0; i < count; ++i) {
       if (!active[i]) continue;
-      ++live;
       pcdn_ctx* c = runs[i].c;
+      HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
+      HIPCHK(c, hipEventRecord(res.pre_done[i], c->stream));
+      hipStream_t group = narrow[i] ? res.narrow_stream : res.wide_stream;
+      HIPCHK(c, hipStreamWaitEvent(group, res.pre_done[i], 0));
       if (narrow[i]) {
-        HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
-        HIPCHK(c, hipEventRecord(res.pre_done[i], c->stream));
-        HIPCHK(c, hipStreamWaitEvent(res.stream, res.pre_done[i], 0));
         const int64_t nb = (c->p + runs[i].P - 1) / runs[i].P;
         res.htab[m++] = make_narrow_args(c, runs[i].o, c->idx0, c->p, runs[i].P, 0, nb, nullptr);
-      } else {
-        HIPCHK(c, hipGraphLaunch(c->graph, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost,
-                                 c->stream));
       }
       count_outer(c, runs[i].o, runs[i].P, 1);
     }
-    if (live == 0) break;
+    // single-workgroup jobs: one launch, then each job's stopping sweep
     if (m > 0) {
       hipError_t e = hipMemcpyAsync(res.dtab, res.htab, sizeof(NarrowArgs) * m,
-                                    hipMemcpyHostToDevice, res.stream);
+                                    hipMemcpyHostToDevice, res.narrow_stream);
       if (e != hipSuccess) return batch_fail(c0, e, "batch table upload");
-      e = launch_narrow_multi(res.dtab, m, res.stream);
+      e = launch_narrow_multi(res.dtab, m, res.narrow_stream);
       if (e != hipSuccess) return batch_fail(c0, e, "multi-problem launch");
-      e = hipEventRecord(res.fused_done, res.stream);
+      e = hipEventRecord(res.fused_done, res.narrow_stream);
       if (e != hipSuccess) return batch_fail(c0, e, "event record");
       for (int32_t i = 0; i < count; ++i) {
         if (!active[i] || !narrow[i]) continue;
@@ -140,8 +225,24 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
                                  c->stream));
       }
     }
-    // the staging table and every pinned result are reused next round
-    HIPCHK(c0, hipStreamSynchronize(res.stream));
+    // multi-kernel jobs: every bundle and stopping sweep in lock-step launches
+    if (!plan.jobs.empty()) {
+      for (size_t st = 0; st < plan.count.size(); ++st) {
+        const hipError_t e = launch_exec(dtasks + plan.task_off[st], dfirst + plan.first_off[st],
+                                         plan.count[st], plan.blocks[st], res.wide_stream);
+        if (e != hipSuccess) return batch_fail(c0, e, "executor launch");
+      }
+      hipError_t e = launch_gather(dsrc, res.dG, (int)plan.jobs.size(), res.wide_stream);
+      if (e != hipSuccess) return batch_fail(c0, e, "gather");
+      e = hipMemcpyAsync(res.hG, res.dG, sizeof(double) * plan.jobs.size(),
+                         hipMemcpyDeviceToHost, res.wide_stream);
+      if (e != hipSuccess) return batch_fail(c0, e, "gather copy");
+    }
+    // the staging tables and every pinned result are reused next round
+    hipError_t e = hipStreamSynchronize(res.narrow_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(res.wide_stream);
+    if (e != hipSuccess) return batch_fail(c0, e, "round");
+    for (size_t k = 0; k < plan.jobs.size(); ++k) runs[plan.jobs[k]].c->hscal[0] = res.hG[k];
     for (int32_t i = 0; i < count; ++i) {
       if (!active[i]) continue;
       pcdn_ctx* c = runs[i].c;
@@ -149,6 +250,7 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
       const int rc = solve_note_outer(runs[i], c->hscal[0]);
       if (rc) return rc;
       active[i] = !runs[i].converged && runs[i].outer < runs[i].o.max_outer;
+      if (!active[i] && !narrow[i]) plan_stale = true;
     }
   }
   int first_err = PCDN_OK;

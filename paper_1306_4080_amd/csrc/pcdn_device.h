@@ -127,6 +127,52 @@ struct ApplyArgs {
   int Q, max_ls;
 };
 
+struct ScatterCountArgs {
+  const double* d;           // per-slot directions
+  const int32_t* perm;       // slot -> feature
+  const int64_t* cp;
+  int64_t p;                 // slots
+  int32_t narrow;            // count for the single-workgroup kernel
+  Stats* stats;
+};
+
+struct SumArgs {
+  const double* x;
+  int64_t m;
+  double* part;              // one partial per block of the first level
+  double* out;
+  IterState* it;             // nullable: advanced by the final level
+  int32_t nb;                // blocks of the first level
+};
+
+// One kernel invocation of one problem, as run by the multi-problem
+// executor: the kernel, its arguments, and the grid a launch of its own
+// would have (nblk blocks; the line search's grid is gx x nblk/gx).
+enum TaskKind : int32_t {
+  kTaskSweep = 0,
+  kTaskSweepStop,
+  kTaskSplit,
+  kTaskSplitStop,
+  kTaskLinesearch,
+  kTaskApply,
+  kTaskScatterCount,
+  kTaskSumPartial,
+  kTaskSumFinal,
+};
+struct Task {
+  int32_t kind;
+  int32_t loss;
+  int32_t nblk;
+  int32_t gx;
+  union {
+    SweepArgs sw;
+    LsArgs ls;
+    ApplyArgs ap;
+    ScatterCountArgs sc;
+    SumArgs sum;
+  } u;
+};
+
 // Single-workgroup schedule: bundles t_begin .. t_end-1 of one outer iteration
 // (bundle t = slots [tP, min((t+1)P, p))), with X in partition order: the
 // nonzeros of slot r are pri/pv[poff[r] .. poff[r+1]).  P <= kNarrowMaxP.
@@ -172,9 +218,18 @@ int sweep_grid(int64_t slots);
 hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
 hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
 int ls_grid(int64_t n);
+int apply_grid(int64_t n, int64_t slots);
+int scatter_count_grid(int64_t p);
+int sum_grid(int64_t m);
 hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s);
 hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s);
 hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
+// Every task of tasks[0..count) in one launch of `blocks` blocks: task i
+// takes blocks [first[i], first[i+1]) (first[count] = blocks).
+hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int blocks,
+                       hipStream_t s);
+// dst[i] = *src[i] for i < count (device pointers).
+hipError_t launch_gather(const double* const* src, double* dst, int count, hipStream_t s);
 // One workgroup per entry of the device table tab[0..count).
 hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s);
 // X in partition order for the single-workgroup schedule (needs nnz < 2^31).

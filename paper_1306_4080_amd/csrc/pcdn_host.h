@@ -175,6 +175,11 @@ bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
 pcdn::NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm,
                                   int64_t p_slots, int64_t P, int64_t t_begin, int64_t t_end,
                                   double* dtx_copy);
+// The kernels of one outer iteration after the partition (every bundle,
+// counters, stopping sweep) as tasks for the multi-problem executor, with
+// the arguments and grids the single-problem launches use (multi-kernel
+// schedule only).
+int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<pcdn::Task>& out);
 // Capture (once per key) the two halves of an outer iteration around the
 // single-workgroup bundles: graph_pre and graph_post (see pcdn_ctx).
 int ensure_split_graphs(pcdn_ctx* c, const Opts& o, int64_t P);

@@ -478,11 +478,14 @@ __device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, dou
   return dj;
 }
 
+// Kernel bodies take the block index and block count of their launch as
+// arguments, so that the multi-problem executor (k_exec) can run them on a
+// slice of its grid with exactly the work split of a launch of their own.
 template <int LOSS, bool STOP>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
-  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
+  const int64_t nwaves = nblk * kWavesPerBlock;
   const int32_t c_lo = a.cstart[a.slot_lo];
   const int32_t c_hi = a.cstart[a.slot_hi];
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
@@ -501,14 +504,19 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   }
 }
 
+template <int LOSS, bool STOP>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
+  sweep_body<LOSS, STOP>(a, blockIdx.x, gridDim.x);
+}
+
 // Split columns: every wavefront of a split feature sums all of its chunk
 // partials in chunk order (so all of them agree bit for bit), finishes the
 // feature, and scatters its own chunk.
 template <int LOSS, bool STOP>
-__global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
+__device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
-  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
+  const int64_t nwaves = nblk * kWavesPerBlock;
   const int32_t c_lo = a.cstart[a.slot_lo];
   const int32_t c_hi = a.cstart[a.slot_hi];
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
@@ -527,19 +535,22 @@ __global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
   }
 }
 
+template <int LOSS, bool STOP>
+__global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
+  split_body<LOSS, STOP>(a, blockIdx.x, gridDim.x);
+}
+
 // Nonzeros scattered into d^T x during one outer iteration (features with
 // d_j != 0; split columns counted apart), one atomic per block.
-__global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const int32_t* perm,
-                                                          const int64_t* cp, int64_t p,
-                                                          bool narrow, Stats* stats) {
+__device__ __forceinline__ void scatter_count_body(const ScatterCountArgs& a, int64_t bid,
+                                                   int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
   double fused = 0.0, split = 0.0;
-  for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < p;
-       r += (int64_t)gridDim.x * kBlock) {
-    if (d[r] == 0.0) continue;
-    const int32_t j = perm[r];
-    const double len = (double)(cp[j + 1] - cp[j]);
-    if (len > kChunk && !narrow)
+  for (int64_t r = bid * kBlock + threadIdx.x; r < a.p; r += nblk * kBlock) {
+    if (a.d[r] == 0.0) continue;
+    const int32_t j = a.perm[r];
+    const double len = (double)(a.cp[j + 1] - a.cp[j]);
+    if (len > kChunk && !a.narrow)
       split += len;
     else
       fused += len;
@@ -548,9 +559,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const
   split = block_sum(split, lds4);
   if (threadIdx.x == 0) {
     if (fused > 0.0)
-      atomicAdd(narrow ? &stats->nnz_scat_narrow : &stats->nnz_scat_fused, (unsigned long long)fused);
-    if (split > 0.0) atomicAdd(&stats->nnz_scat_split, (unsigned long long)split);
+      atomicAdd(a.narrow ? &a.stats->nnz_scat_narrow : &a.stats->nnz_scat_fused,
+                (unsigned long long)fused);
+    if (split > 0.0) atomicAdd(&a.stats->nnz_scat_split, (unsigned long long)split);
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_count(ScatterCountArgs a) {
+  scatter_count_body(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,13 +576,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_count(const double* d, const
 // as Algorithm 4 scales its retained d^T x_i), of the l1 change of the bundle
 // coordinates, and of Delta.  Layout: part[v * gridDim.x + block].
 // ---------------------------------------------------------------------------
+// bx, by: block of the (G x ceil(Q / kQGroup)) launch grid.
 template <int LOSS>
-__global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
+__device__ __forceinline__ void linesearch_body(const LsArgs& a, int bx, int by, int G) {
   __shared__ double red[kWavesPerBlock][kQGroup];
   __shared__ double lds4[kWavesPerBlock];
   const int lane = lane_id(), wv = wave_in_block();
-  const int G = gridDim.x;
-  const int q_lo = blockIdx.y * kQGroup;
+  const int q_lo = by * kQGroup;
   const int nq = a.Q - q_lo < kQGroup ? a.Q - q_lo : kQGroup;
   double beta_lo = 1.0;
   for (int t = 0; t < q_lo; ++t) beta_lo *= a.beta;
@@ -574,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
   double touched = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n;
+  for (int64_t i = bx * (int64_t)kBlock + threadIdx.x; i < a.n;
        i += (int64_t)G * kBlock) {
     const double dl = a.dtx[i];
     if (dl == 0.0) continue;
@@ -599,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
   }
   __syncthreads();
   if (threadIdx.x < nq)
-    a.part[(int64_t)(q_lo + threadIdx.x) * G + blockIdx.x] =
+    a.part[(int64_t)(q_lo + threadIdx.x) * G + bx] =
         ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
   __syncthreads();
   // l1 change of the bundle coordinates for these candidates
@@ -607,7 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
   const int64_t Pt = a.slot_hi - a.slot_lo;
-  for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < Pt;
+  for (int64_t r = bx * (int64_t)kBlock + threadIdx.x; r < Pt;
        r += (int64_t)G * kBlock) {
     const int64_t slot = a.slot_lo + r;
     const double wj = a.w[a.perm[slot]];
@@ -629,16 +645,21 @@ __global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
   }
   __syncthreads();
   if (threadIdx.x < nq)
-    a.part[(int64_t)(a.Q + q_lo + threadIdx.x) * G + blockIdx.x] =
+    a.part[(int64_t)(a.Q + q_lo + threadIdx.x) * G + bx] =
         ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-  if (blockIdx.y == 0) {
+  if (by == 0) {
     const double dsum = block_sum(del, lds4);
     const double tsum = block_sum(touched, lds4);
     if (threadIdx.x == 0) {
-      a.part[(int64_t)(2 * a.Q) * G + blockIdx.x] = dsum;
-      a.part[(int64_t)(2 * a.Q + 1) * G + blockIdx.x] = tsum;
+      a.part[(int64_t)(2 * a.Q) * G + bx] = dsum;
+      a.part[(int64_t)(2 * a.Q + 1) * G + bx] = tsum;
     }
   }
+}
+
+template <int LOSS>
+__global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
+  linesearch_body<LOSS>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // Sum of row v of the line-search partials, same order in every block.
@@ -657,7 +678,7 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
 // d^T x_i), and d^T x is cleared for the next inner iteration.
 // ---------------------------------------------------------------------------
 template <int LOSS>
-__global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
+__device__ __forceinline__ void apply_body(const ApplyArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
   const double Delta = ls_total(a.part, 2 * a.Q, a.ls_blocks, lds4);
   double Dq = Delta, al = 1.0, dF = 0.0;
@@ -675,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
     al *= a.beta;
   }
   const double touched = ls_total(a.part, 2 * a.Q + 1, a.ls_blocks, lds4);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (bid == 0 && threadIdx.x == 0) {
     a.st->q = q_acc;
     a.st->alpha = q_acc >= 0 ? al : 0.0;
     a.st->dF = dF;
@@ -685,8 +706,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
     if (q_acc < 0) atomicAdd(&a.stats->ls_fail, 1ull);
     atomicAdd(&a.stats->rows_touched, (unsigned long long)touched);
   }
-  const int64_t tid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  const int64_t nthr = (int64_t)gridDim.x * kBlock;
+  const int64_t tid = bid * kBlock + threadIdx.x;
+  const int64_t nthr = nblk * kBlock;
   for (int64_t i = tid; i < a.n; i += nthr) {
     const double dl = a.dtx[i];
     if (dl == 0.0) continue;
@@ -703,6 +724,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
   if (q_acc >= 0) {
     for (int64_t r = a.slot_lo + tid; r < a.slot_hi; r += nthr) a.w[a.perm[r]] += al * a.d[r];
   }
+}
+
+template <int LOSS>
+__global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
+  apply_body<LOSS>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,27 +1151,73 @@ __global__ void k_widen(const int32_t* in, int64_t m, int64_t* out) {
 // ---------------------------------------------------------------------------
 // deterministic sum (two kernels), loss terms, margins
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_sum_partial(const double* x, int64_t m,
-                                                        double* part) {
+__device__ __forceinline__ void sum_partial_body(const SumArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
   double s = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * kBlock)
-    s += x[i];
+  for (int64_t i = bid * kBlock + threadIdx.x; i < a.m; i += nblk * kBlock) s += a.x[i];
   s = block_sum(s, lds4);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (threadIdx.x == 0) a.part[bid] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_final(const double* part, int nb, double* out,
-                                                      IterState* it) {
+__device__ __forceinline__ void sum_final_body(const SumArgs& a) {
   __shared__ double lds4[kWavesPerBlock];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kBlock) s += part[b];
+  for (int b = threadIdx.x; b < a.nb; b += kBlock) s += a.part[b];
   s = block_sum(s, lds4);
   if (threadIdx.x == 0) {
-    *out = s;
-    if (it) it->k += 1;
+    *a.out = s;
+    if (a.it) a.it->k += 1;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partial(SumArgs a) {
+  sum_partial_body(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_final(SumArgs a) { sum_final_body(a); }
+
+// ---------------------------------------------------------------------------
+// Multi-problem executor: one launch runs one task of each of several
+// independent problems.  Block b finds its task i (first[i] <= b <
+// first[i+1]) with ballots over the block-offset table and runs the task's
+// kernel body on local block b - first[i] of nblk, i.e. with the work split
+// of a launch of its own, so every problem gets the same results as alone.
+// ---------------------------------------------------------------------------
+__device__ inline int task_of_block(const int32_t* first, int count, int b) {
+  int i = 0;
+  for (int base = 0; base < count; base += kWave) {
+    const int k = base + lane_id();
+    i += __popcll(__ballot(k < count && first[k + 1] <= b));
+  }
+  return __builtin_amdgcn_readfirstlane(i);
+}
+
+template <int LOSS>
+__device__ __forceinline__ void exec_task(const Task& t, int lb) {
+  switch (t.kind) {
+    case kTaskSweep: sweep_body<LOSS, false>(t.u.sw, lb, t.nblk); break;
+    case kTaskSweepStop: sweep_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
+    case kTaskSplit: split_body<LOSS, false>(t.u.sw, lb, t.nblk); break;
+    case kTaskSplitStop: split_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
+    case kTaskLinesearch: linesearch_body<LOSS>(t.u.ls, lb % t.gx, lb / t.gx, t.gx); break;
+    case kTaskApply: apply_body<LOSS>(t.u.ap, lb, t.nblk); break;
+    case kTaskScatterCount: scatter_count_body(t.u.sc, lb, t.nblk); break;
+    case kTaskSumPartial: sum_partial_body(t.u.sum, lb, t.nblk); break;
+    case kTaskSumFinal: sum_final_body(t.u.sum); break;
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_exec(const Task* tasks, const int32_t* first,
+                                                 int count) {
+  const int b = blockIdx.x;
+  const int i = task_of_block(first, count, b);
+  const Task& t = tasks[i];
+  const int lb = b - first[i];
+  if (t.loss == kLogistic)
+    exec_task<kLogistic>(t, lb);
+  else
+    exec_task<kL2Svm>(t, lb);
 }
 
 template <int LOSS>
@@ -1315,9 +1387,12 @@ hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+int apply_grid(int64_t n, int64_t slots) { return grid_for(n > slots ? n : slots, kBlock, 512); }
+int scatter_count_grid(int64_t p) { return grid_for(p, kBlock, 64); }
+int sum_grid(int64_t m) { return grid_for(m, kBlock, kSumGrid); }
+
 hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s) {
-  const int64_t items = a.n > a.slot_hi - a.slot_lo ? a.n : a.slot_hi - a.slot_lo;
-  const dim3 g(grid_for(items, kBlock, 512));
+  const dim3 g(apply_grid(a.n, a.slot_hi - a.slot_lo));
   if (loss == kLogistic)
     hipLaunchKernelGGL(k_apply<kLogistic>, g, dim3(kBlock), 0, s, a);
   else
@@ -1348,6 +1423,25 @@ hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int blocks,
+                       hipStream_t s) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exec, dim3(blocks), dim3(kBlock), 0, s, tasks, first, count);
+  return hipGetLastError();
+}
+
+__global__ void k_gather(const double* const* src, double* dst, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = *src[i];
+}
+
+hipError_t launch_gather(const double* const* src, double* dst, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, dst,
+                     count);
+  return hipGetLastError();
+}
+
 hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_narrow_multi, dim3(count), dim3(kNarrowBlock), 0, s, tab);
@@ -1356,16 +1450,17 @@ hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s) 
 
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
                                 int64_t p, bool narrow, Stats* stats, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter_count, dim3(grid_for(p, kBlock, 64)), dim3(kBlock), 0, s, d, perm,
-                     cp, p, narrow, stats);
+  const ScatterCountArgs a{d, perm, cp, p, narrow ? 1 : 0, stats};
+  hipLaunchKernelGGL(k_scatter_count, dim3(scatter_count_grid(p)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s) {
-  const int nb = grid_for(m, kBlock, kSumGrid);
-  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(kBlock), 0, s, x, m, part);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, part, nb, out, it);
+  const int nb = sum_grid(m);
+  const SumArgs a{x, m, part, out, it, nb};
+  hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

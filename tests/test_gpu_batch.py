@@ -97,7 +97,9 @@ def test_batch_matches_alone_and_oracle(pc):
 
 def test_batch_many_small_problems(pc):
     """32 heterogeneous LR problems (the batched recipe at small sizes) in one
-    call: every job equals its solve alone."""
+    call, every other one forced onto the multi-kernel schedule (so both the
+    single-workgroup launch and the lock-step executor carry 16 problems):
+    every job equals its solve alone."""
     rng = np.random.default_rng(4)
     data = []
     for i in range(32):
@@ -105,11 +107,13 @@ def test_batch_many_small_problems(pc):
         p = int(rng.integers(300, 3000))
         dens = float(rng.uniform(0.002, 0.02))
         data.append(synth.sparse_random(100 + i, n, p, dens))
+    sched = ["wide" if i % 2 else "auto" for i in range(32)]
     solvers = [pc.Solver(device=0).load_data(d) for d in data]
-    specs = [s.job(1.0, max(1, d.p // 20), 1e-4, "lr", seed=9) for s, d in zip(solvers, data)]
+    specs = [s.job(1.0, max(1, d.p // 20), 1e-4, "lr", seed=9, schedule=sc)
+             for s, d, sc in zip(solvers, data, sched)]
     batched = pc.solve_batch(specs)
-    for s, d, b in zip(solvers, data, batched):
-        alone = s.solve(1.0, max(1, d.p // 20), 1e-4, "lr", seed=9)
+    for s, d, b, sc in zip(solvers, data, batched, sched):
+        alone = s.solve(1.0, max(1, d.p // 20), 1e-4, "lr", seed=9, schedule=sc)
         _assert_same_run(b, alone)
         assert b[0] == 0
     # spot-check three of them against the oracle
