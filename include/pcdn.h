@@ -129,7 +129,8 @@ int pcdn_solve(pcdn_ctx* ctx, double C, int64_t P, double eps, int loss,
 typedef struct {
   pcdn_ctx* ctx;          /* loaded context; at most one job per context       */
   double C;               /* as pcdn_solve                                     */
-  int64_t P;
+  int64_t P;              /* as pcdn_solve; 0: chosen by pcdn_autotune first
+                             (and written back)                                */
   double eps;
   int32_t loss;
   int32_t status;         /* out: what pcdn_solve would have returned          */
@@ -163,6 +164,38 @@ int pcdn_solve_batch(pcdn_job* jobs, int32_t count);
  * the first error. */
 int pcdn_solve_path(pcdn_ctx* ctx, const double* Cs, int32_t count, int64_t P, double eps,
                     int loss, const pcdn_opts* opts, double* W_out, pcdn_info* infos);
+
+/* Bundle-size autotuning (pcdn_autotune). */
+typedef struct {
+  int64_t P;                /* candidate bundle size                             */
+  int32_t schedule;         /* PCDN_SCHED_WIDE or PCDN_SCHED_NARROW it ran with  */
+  int32_t outer;            /* pilot outer iterations run                        */
+  double sec_per_outer;     /* measured seconds per outer iteration              */
+  double rate;              /* measured decay of log ||grad^S F||_1 per iteration */
+  double predicted_seconds; /* predicted time to reach eps (INFINITY: no progress) */
+} pcdn_tune_point;
+
+typedef struct {
+  int64_t P;                /* chosen bundle size                                */
+  int32_t schedule;         /* chosen schedule                                   */
+  int32_t n_tried;          /* entries of tried[]                                */
+  double predicted_seconds; /* prediction for the chosen P                       */
+  pcdn_tune_point tried[8];
+} pcdn_tune;
+
+/* Choose the bundle size P (and the schedule, when opts->schedule is
+ * PCDN_SCHED_AUTO) for solving the loaded problem with (loss, C, eps), by
+ * the pilot procedure of Sec. 5.1 ("Bundle Size Choice"): candidates around
+ * the paper's starting point of about 5% of the features (P0 * 4^k,
+ * k = -3..2, clipped to [1, p]); each runs a pilot of three outer iterations
+ * from the start pcdn_solve would use; the time per outer iteration and the
+ * decay rate of the stopping norm (iterations 2-3, as eq. (15) separates the
+ * per-iteration cost from the number of iterations) predict the time to reach
+ * eps; the smallest prediction wins (a pilot that already meets eps counts
+ * with its measured time).  The context's device state afterwards is the
+ * last pilot's.  Returns PCDN_OK or an error. */
+int pcdn_autotune(pcdn_ctx* ctx, int loss, double C, double eps, const pcdn_opts* opts,
+                  pcdn_tune* out);
 
 /* Set the device state to (loss, C, w): w (host, p doubles) or zeros if NULL;
  * the retained e^{w^T x_i} (logistic) or b_i = 1 - y_i w^T x_i (SVM) are

@@ -32,7 +32,7 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
 # entry points declared in include/pcdn.h
 SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
            "pcdn_iterate",
-           "pcdn_solve_batch", "pcdn_solve_path",
+           "pcdn_solve_batch", "pcdn_solve_path", "pcdn_autotune",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
            "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy")
 
@@ -72,6 +72,17 @@ class pcdn_job(ctypes.Structure):
                 ("info", ctypes.POINTER(pcdn_info))]
 
 
+class pcdn_tune_point(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("schedule", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("sec_per_outer", ctypes.c_double), ("rate", ctypes.c_double),
+                ("predicted_seconds", ctypes.c_double)]
+
+
+class pcdn_tune(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int64), ("schedule", ctypes.c_int32), ("n_tried", ctypes.c_int32),
+                ("predicted_seconds", ctypes.c_double), ("tried", pcdn_tune_point * 8)]
+
+
 _lib = None
 
 
@@ -101,6 +112,8 @@ def load_library(path: str = LIB_PATH):
                             ctypes.POINTER(pcdn_step_info), vp, vp, vp, vp]
     L.pcdn_iterate.argtypes = [vp, i64, i64, i64, ctypes.POINTER(pcdn_opts), vp]
     L.pcdn_solve_batch.argtypes = [ctypes.POINTER(pcdn_job), ctypes.c_int32]
+    L.pcdn_autotune.argtypes = [vp, i32, dbl, dbl, ctypes.POINTER(pcdn_opts),
+                                ctypes.POINTER(pcdn_tune)]
     L.pcdn_solve_path.argtypes = [vp, ctypes.POINTER(dbl), ctypes.c_int32, i64, dbl, i32,
                                   ctypes.POINTER(pcdn_opts), vp, ctypes.POINTER(pcdn_info)]
     L.pcdn_permutation.argtypes = [vp, u64, i64, vp]
@@ -223,7 +236,25 @@ def pcdn_solve_batch(specs):
         bad = next((sp["ctx"] for i, sp in enumerate(specs) if jobs[i].status == rc),
                    specs[0]["ctx"] if specs else None)
         _check(bad, rc)
-    return [(jobs[i].status, ws[i], _info_dict(infos[i])) for i in range(n)]
+    out = []
+    for i in range(n):
+        info = _info_dict(infos[i])
+        info["P"] = jobs[i].P          # the autotuner's choice where P was 0
+        out.append((jobs[i].status, ws[i], info))
+    return out
+
+
+def pcdn_autotune(ctx, C, eps, loss, **opts) -> dict:
+    """Pilot-based bundle-size choice; returns the choice and every pilot."""
+    loss = LOSSES.get(loss, loss)
+    o, keep = _opts(**opts)
+    t = pcdn_tune()
+    _check(ctx, load_library().pcdn_autotune(ctx, int(loss), float(C), float(eps),
+                                             ctypes.byref(o), ctypes.byref(t)))
+    tried = [{f: getattr(t.tried[k], f) for f, _ in pcdn_tune_point._fields_}
+             for k in range(t.n_tried)]
+    return {"P": t.P, "schedule": t.schedule, "predicted_seconds": t.predicted_seconds,
+            "tried": tried}
 
 
 def pcdn_solve_path(ctx, Cs, P, eps, loss, p, **opts):
@@ -335,6 +366,9 @@ class Solver:
 
     def solve(self, C, P, eps, loss, **opts):
         return pcdn_solve(self.ctx, C, P, eps, loss, self.p, **opts)
+
+    def autotune(self, C, eps, loss, **opts):
+        return pcdn_autotune(self.ctx, C, eps, loss, **opts)
 
     def solve_path(self, Cs, P, eps, loss, **opts):
         return pcdn_solve_path(self.ctx, Cs, P, eps, loss, self.p, **opts)

@@ -3,7 +3,9 @@
 // (pcdn_solve_path).  Each problem follows exactly the sequence of kernels
 // pcdn_solve would run for it; only the interleaving across problems differs.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -80,7 +82,8 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
       if (jobs[k].ctx == j.ctx) return fail(j.ctx, PCDN_E_ARG, "two jobs share a context");
     if (j.ctx->device != jobs[0].ctx->device)
       return fail(j.ctx, PCDN_E_ARG, "the contexts of a batch must share one device");
-    const int rc = check_solve_args(j.ctx, j.C, j.P, j.eps, j.loss, j.opts, &runs[i].o);
+    const int rc = check_solve_args(j.ctx, j.C, j.P == 0 ? 1 : j.P, j.eps, j.loss, j.opts,
+                                    &runs[i].o);
     if (rc) {
       j.status = rc;
       return rc;
@@ -90,6 +93,18 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
     runs[i].P = j.P;
     runs[i].eps = j.eps;
     runs[i].loss = j.loss;
+  }
+  // bundle sizes left to the autotuner
+  for (int32_t i = 0; i < count; ++i) {
+    if (jobs[i].P != 0) continue;
+    pcdn_tune t;
+    const int rc = pcdn_autotune(runs[i].c, runs[i].loss, runs[i].C, runs[i].eps, jobs[i].opts, &t);
+    if (rc) {
+      jobs[i].status = rc;
+      return rc;
+    }
+    runs[i].P = t.P;
+    jobs[i].P = t.P;
   }
   pcdn_ctx* c0 = jobs[0].ctx;
   BatchRes res;
@@ -302,4 +317,90 @@ extern "C" int pcdn_solve_path(pcdn_ctx* c, const double* Cs, int32_t count, int
     if (rc == PCDN_NOT_CONVERGED) status = rc;
   }
   return status;
+}
+
+extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const pcdn_opts* opts,
+                             pcdn_tune* out) {
+  if (!c) return PCDN_E_ARG;
+  if (!out) return fail(c, PCDN_E_ARG, "null output");
+  Opts o;
+  int rc = check_solve_args(c, C, 1, eps, loss, opts, &o);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  const int64_t p = c->p;
+  // the paper's pilot start: about 5% of the features
+  const int64_t P0 = std::max<int64_t>(1, std::llround(0.05 * (double)p));
+  std::vector<int64_t> cands;
+  for (int k = -3; k <= 2; ++k) {
+    const double v = (double)P0 * std::pow(4.0, k);
+    const int64_t P = std::min<int64_t>(p, std::max<int64_t>(1, std::llround(v)));
+    if (std::find(cands.begin(), cands.end(), P) == cands.end()) cands.push_back(P);
+  }
+  // a target below the rounding floor cannot be predicted; eps = 0 tunes for 1e-12
+  const double eps_eff = std::max(eps, 1e-12);
+  constexpr int kPilot = 3;
+  using clock = std::chrono::steady_clock;
+  double best = INFINITY, best_speed = -1.0;
+  for (const int64_t P : cands) {
+    SolveRun r;
+    r.o = o;
+    r.c = c;
+    r.C = C;
+    r.P = P;
+    r.eps = eps;
+    r.loss = loss;
+    rc = solve_begin(r);
+    if (rc) return rc;
+    pcdn_tune_point& tp = out->tried[out->n_tried++];
+    tp.P = P;
+    tp.schedule = use_narrow(c, o, P) ? PCDN_SCHED_NARROW : PCDN_SCHED_WIDE;
+    if (r.converged) {  // w = 0 (or the warm start) already meets the rule
+      tp.predicted_seconds = 0.0;
+      out->P = P;
+      out->schedule = tp.schedule;
+      out->predicted_seconds = 0.0;
+      return PCDN_OK;
+    }
+    // iteration 1 pays for graph capture; iterations 2.. are timed
+    double G1 = 0.0, timed = 0.0, total = 0.0;
+    for (int k = 0; k < kPilot && !r.converged && r.outer < o.max_outer; ++k) {
+      const auto t0 = clock::now();
+      rc = run_outer(c, o, P, r.outer, 1);
+      if (rc) return rc;
+      double G = 0.0;
+      rc = read_scalar(c, 0, &G);
+      if (rc) return rc;
+      rc = solve_note_outer(r, G);
+      if (rc) return rc;
+      const double dt = std::chrono::duration<double>(clock::now() - t0).count();
+      total += dt;
+      if (k == 0)
+        G1 = G;
+      else
+        timed += dt;
+    }
+    tp.outer = r.outer;
+    tp.sec_per_outer = r.outer > 1 ? timed / (r.outer - 1) : total;
+    tp.rate = (r.outer > 1 && G1 > 0.0 && r.G > 0.0) ? (std::log(G1) - std::log(r.G)) / (r.outer - 1)
+                                                    : 0.0;
+    if (r.G <= eps_eff * r.G0) {
+      tp.predicted_seconds = total;
+    } else if (tp.rate > 0.0) {
+      const double more = std::log(r.G / (eps_eff * r.G0)) / tp.rate;
+      tp.predicted_seconds = total + more * tp.sec_per_outer;
+    } else {
+      tp.predicted_seconds = INFINITY;
+    }
+    // ties (all unpredictable) go to the fastest decay per second
+    const double speed = tp.sec_per_outer > 0.0 ? tp.rate / tp.sec_per_outer : 0.0;
+    if (tp.predicted_seconds < best ||
+        (!std::isfinite(best) && !std::isfinite(tp.predicted_seconds) && speed > best_speed)) {
+      best = tp.predicted_seconds;
+      best_speed = speed;
+      out->P = P;
+      out->schedule = tp.schedule;
+      out->predicted_seconds = tp.predicted_seconds;
+    }
+  }
+  return PCDN_OK;
 }

@@ -241,3 +241,59 @@ def sparse_random(seed: int, n: int, p: int, density: float, w_frac: float = 0.0
     s = _row_scores(n, r, c, v, w_star) + np.log(u / (1.0 - u))
     y = np.where(s >= 0, 1, -1).astype(np.int8)
     return from_triplets(n, p, r, c, v.astype(np.float32), y, w_star, dict(name="sparse_random"))
+
+
+def bernoulli_csc(seed: int, n: int, p: int, density: float, w_frac: float = 0.01) -> Data:
+    """Bernoulli(density) entries with N(0,1) values, drawn directly in
+    column-major order (no re-sort); labels y = sign(x^T w* + logistic noise)
+    with ceil(w_frac p) N(0,1) nonzeros in w*.  The recipe of the batched
+    independent problems."""
+    rng = np.random.default_rng(seed)
+    target = int(round(n * p * density))
+    # distinct flat positions j * n + i, ascending = CSC order
+    pos = np.unique(rng.integers(0, n * p, size=int(target * 1.02) + 16, dtype=np.int64))
+    if len(pos) > target:
+        keep = np.sort(rng.choice(len(pos), target, replace=False))
+        pos = pos[keep]
+    cols = pos // n
+    rows = (pos - cols * n).astype(np.int32)
+    del pos
+    val = rng.standard_normal(len(rows)).astype(np.float32)
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    np.cumsum(np.bincount(cols, minlength=p), out=col_ptr[1:])
+    w_star = np.zeros(p)
+    k = max(1, int(np.ceil(w_frac * p)))
+    w_star[rng.choice(p, k, replace=False)] = rng.standard_normal(k)
+    s = _row_scores(n, rows, cols, val, w_star)
+    u = rng.random(n)
+    s = s + np.log(u / (1.0 - u))
+    y = np.where(s >= 0, 1, -1).astype(np.int8)
+    return Data(n=n, p=p, col_ptr=col_ptr, row_idx=rows, val=val, y=y, w_star=w_star,
+                meta=dict(name="bernoulli", density=density))
+
+
+def c4_path_Cs(count: int = 32) -> np.ndarray:
+    """The regularisation path's C values: log-spaced over [2^-4, 2^6], ascending."""
+    return 2.0 ** (-4.0 + 10.0 * np.arange(count) / (count - 1))
+
+
+def c4b_shapes(seed: int = BASE_SEED + 4, count: int = 64, scale: float = 1.0):
+    """(n, p, density) of the batched independent problems: n uniform in
+    [500, 20000], p uniform in [1000, 100000], density uniform in
+    [0.001, 0.02]; `scale` < 1 shrinks n and p (not the density) for small
+    runs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(500, 20001))
+        p = int(rng.integers(1000, 100001))
+        d = float(rng.uniform(0.001, 0.02))
+        out.append((max(2, int(n * scale)), max(2, int(p * scale)), d))
+    return out
+
+
+def c4b(seed: int = BASE_SEED + 4, count: int = 64, scale: float = 1.0) -> list:
+    """The batched independent LR problems (see c4b_shapes), each drawn by
+    bernoulli_csc with its own seed."""
+    return [bernoulli_csc(seed * 1000 + i, n, p, d)
+            for i, (n, p, d) in enumerate(c4b_shapes(seed, count, scale))]

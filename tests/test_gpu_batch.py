@@ -137,7 +137,9 @@ def test_batch_errors_run_nothing(pc):
     with pytest.raises(PcdnError, match="E_ARG"):
         pc.solve_batch([a.job(1.0, 32, 1e-4, "lr"), a.job(1.0, 32, 1e-4, "lr")])
     with pytest.raises(PcdnError, match="E_ARG"):
-        pc.solve_batch([a.job(1.0, 0, 1e-4, "lr")])
+        pc.solve_batch([a.job(1.0, -1, 1e-4, "lr")])
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.solve_batch([a.job(1.0, 0, 1e-4, "lr"), b.job(1.0, d.p + 1, 1e-4, "lr")])
     # nothing ran: a has no state yet
     with pytest.raises(PcdnError, match="E_STATE"):
         a.evaluate()
@@ -184,3 +186,42 @@ def test_path_svm_wide(pc):
         _assert_oracle((rc, W[k], infos[k]), (w_o, io), True)
         w_prev = w_o
     s.close()
+
+
+def test_autotune_ladder_and_choice(pc):
+    """The candidates are the paper's pilot start (5% of the features) times
+    4^k, k = -3..2; the chosen P is one of them with the smallest
+    prediction; solving with it matches the oracle at that P."""
+    d = synth.c1()
+    s = pc.Solver(device=0).load_data(d)
+    t = s.autotune(1.0, 1e-4, "lr", seed=1)
+    P0 = round(0.05 * d.p)
+    ladder = []
+    for k in range(-3, 3):
+        P = min(d.p, max(1, int(np.floor(P0 * 4.0 ** k + 0.5))))
+        if P not in ladder:
+            ladder.append(P)
+    assert [x["P"] for x in t["tried"]] == ladder
+    preds = [x["predicted_seconds"] for x in t["tried"]]
+    assert t["P"] in ladder and t["predicted_seconds"] == min(preds)
+    assert all(x["sec_per_outer"] > 0 for x in t["tried"])
+    print("tuned:", t, flush=True)
+    g = s.solve(1.0, t["P"], 1e-4, "lr", seed=1)
+    w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss="lr", C=1.0),
+                              P=t["P"], eps=1e-4, seed=1)
+    _assert_oracle(g, (w_o, io), True)
+    s.close()
+
+
+def test_batch_autotuned_jobs(pc):
+    """P = 0 in a job: the batch tunes it first, writes it back, and the job
+    equals its solve alone at that P."""
+    data = [synth.bernoulli_csc(300 + i, 600 + 200 * i, 2000 + 500 * i, 0.01) for i in range(3)]
+    solvers = [pc.Solver(device=0).load_data(d) for d in data]
+    out = pc.solve_batch([s.job(1.0, 0, 1e-4, "lr", seed=4) for s in solvers])
+    for s, b in zip(solvers, out):
+        assert b[2]["P"] >= 1
+        alone = s.solve(1.0, b[2]["P"], 1e-4, "lr", seed=4)
+        _assert_same_run(b, alone)
+    for s in solvers:
+        s.close()

@@ -40,3 +40,23 @@ def test_c3_cap_respected_small():
     d = synth.c3(n=5000, p=40000, cap=600)
     assert d.col_lengths().max() <= 600
     assert np.all(d.val == 1.0)
+
+
+def test_bernoulli_csc_and_batched_shapes():
+    d = synth.bernoulli_csc(7, 300, 500, 0.02)
+    assert d.col_ptr[0] == 0 and d.col_ptr[-1] == d.nnz and np.all(np.diff(d.col_ptr) >= 0)
+    assert d.nnz == round(300 * 500 * 0.02)
+    for j in range(d.p):
+        r = d.row_idx[d.col_ptr[j]:d.col_ptr[j + 1]]
+        assert np.all(np.diff(r) > 0) and (len(r) == 0 or (r[0] >= 0 and r[-1] < d.n))
+    assert set(np.unique(d.y)) <= {-1, 1}
+    assert np.count_nonzero(d.w_star) == int(np.ceil(0.01 * 500))
+    again = synth.bernoulli_csc(7, 300, 500, 0.02)
+    assert np.array_equal(again.row_idx, d.row_idx) and np.array_equal(again.val, d.val)
+    shapes = synth.c4b_shapes()
+    assert len(shapes) == 64
+    for n, p, dens in shapes:
+        assert 500 <= n <= 20000 and 1000 <= p <= 100000 and 0.001 <= dens <= 0.02
+    Cs = synth.c4_path_Cs()
+    assert len(Cs) == 32 and Cs[0] == 2.0 ** -4 and abs(Cs[-1] - 2.0 ** 6) < 1e-12
+    assert np.all(np.diff(np.log2(Cs)) > 0)
