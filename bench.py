@@ -19,6 +19,14 @@ with every kernel launch bracketed by HIP events on the library's stream; the
 roofline object reports the kernel class with the most time there
 (algorithmic bytes per launch / average launch duration).
 The FP64 CPU oracle is timed on a bounded sample of the same workload.
+
+Two more objects on the same line (skipped with --no-batched):
+- "batched": 64 independent LR problems (the batched recipe: n U[500,20000],
+  p U[1000,100000], density U[0.001,0.02]) solved to eps = 1e-4 one
+  pcdn_solve after another and in one pcdn_solve_batch call, solves/s of
+  each (bundle sizes from the autotuner, tuned before timing);
+- "path": 32 C values on the text-like matrix with warm starts,
+  pcdn_solve_path against the same chain of pcdn_solve calls.
 """
 from __future__ import annotations
 
@@ -59,6 +67,10 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-mebibyte device buffer three times (the plain copy "
                          "kernel that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-solve and regularisation-path measurements")
+    ap.add_argument("--batched-scale", type=float, default=1.0,
+                    help="shrink n and p of the 64 batched problems (1.0: full size)")
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the kernel sources that traffic records are keyed by")
     return ap.parse_args()
@@ -121,6 +133,70 @@ def cpu_baseline(d, budget_s: float, settings) -> dict:
     return {"value": done_nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
             "sample": f"first {m} outer iterations of each of the {len(settings)} (C, P) settings "
                       f"from w = 0 ({done_nnz} bundle nonzeros, {dt:.1f} s, single thread)"}
+
+
+def batched_measurement(pc, synth, scale: float) -> dict:
+    """64 independent LR problems (C = 1, eps = 1e-4), bundle sizes from the
+    autotuner (not timed): one pcdn_solve after another ("plain") against one
+    pcdn_solve_batch call; both give the same results."""
+    import torch
+    data = synth.c4b(scale=scale)
+    solvers = [pc.Solver(device=0).load_data(d) for d in data]
+    t0 = time.perf_counter()
+    tunes = [s.autotune(1.0, 1e-4, "lr", seed=SEED) for s in solvers]
+    t_tune = time.perf_counter() - t0
+    Ps = [t["P"] for t in tunes]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [s.solve(1.0, P, 1e-4, "lr", seed=SEED) for s, P in zip(solvers, Ps)]
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = pc.solve_batch([s.job(1.0, P, 1e-4, "lr", seed=SEED) for s, P in zip(solvers, Ps)])
+    t_batch = time.perf_counter() - t0
+    same = all(a[2]["outer_iters"] == b[2]["outer_iters"] and
+               abs(a[2]["objective"] - b[2]["objective"]) <= 1e-12 * abs(a[2]["objective"])
+               for a, b in zip(plain, batch))
+    nnz_swept = sum(b[2]["nnz_swept"] for b in batch)
+    for s in solvers:
+        s.close()
+    n = len(data)
+    return {"workload": f"{n} independent L1-LR problems, n U[500,20000], p U[1000,100000], "
+                        f"density U[0.001,0.02] (scale {scale}), C=1, eps=1e-4, autotuned P",
+            "nnz_total": int(sum(d.nnz for d in data)),
+            "plain_solves_per_s": n / t_plain, "batched_solves_per_s": n / t_batch,
+            "speedup": t_plain / t_batch, "plain_s": t_plain, "batched_s": t_batch,
+            "batched_nnz_per_s": nnz_swept / t_batch,
+            "autotune_s": t_tune, "same_results": same,
+            "narrow_jobs": sum(t["schedule"] == 2 for t in tunes),
+            "outer_iters_total": int(sum(b[2]["outer_iters"] for b in batch))}
+
+
+def path_measurement(pc, d) -> dict:
+    """Regularisation path: 32 C values log-spaced over [2^-4, 2^6] on the
+    text-like matrix, each warm-started from the previous solution; P from
+    the autotuner at the middle C.  pcdn_solve_path against the same chain
+    of pcdn_solve calls with the warm start passed through the host."""
+    import synth
+    Cs = synth.c4_path_Cs()
+    s = pc.Solver(device=0).load_data(d)
+    P = s.autotune(float(Cs[len(Cs) // 2]), 1e-4, "lr", seed=SEED)["P"]
+    t0 = time.perf_counter()
+    rc, W, infos = s.solve_path(Cs, P, 1e-4, "lr", seed=SEED)
+    t_path = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w = None
+    outer = 0
+    for C in Cs:
+        _, w, info = s.solve(float(C), P, 1e-4, "lr", seed=SEED, w0=w)
+        outer += info["outer_iters"]
+    t_plain = time.perf_counter() - t0
+    s.close()
+    return {"workload": "32 C values 2^-4..2^6 (log-spaced, ascending) on the text-like "
+                        "L1-LR matrix, warm starts, eps=1e-4",
+            "P": int(P), "path_s": t_path, "plain_chain_s": t_plain,
+            "path_solves_per_s": len(Cs) / t_path, "plain_solves_per_s": len(Cs) / t_plain,
+            "path_outer_iters": int(sum(i["outer_iters"] for i in infos)),
+            "plain_outer_iters": int(outer)}
 
 
 def main():
@@ -240,6 +316,9 @@ def main():
         "kernels": kernels,
         "objective_after": F,
     }
+    if not args.no_batched:
+        line["batched"] = batched_measurement(pc, synth, args.batched_scale)
+        line["path"] = path_measurement(pc, d)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds, settings)
     print(json.dumps(line), flush=True)

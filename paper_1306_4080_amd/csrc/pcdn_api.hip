@@ -65,6 +65,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
   dfree(c->part); dfree(c->ls_part);
   dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32);
+  dfree(c->rp); dfree(c->rc); dfree(c->rv);
   drop_graph(c);
   c->loaded = false;
   c->has_state = false;
@@ -323,10 +324,8 @@ int cache_from_w(pcdn_ctx* c, bool w_is_zero) {
     HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));  // e^0 = 1, b = 1
     return PCDN_OK;
   }
-  HIPCHK(c, launch_fill(c->cache, 0.0, c->n, c->stream));
-  HIPCHK(c, launch_margins(c->ri, c->v, c->w, c->id_chunks, c->id_total_chunks, c->cache,
-                           c->stream));
-  HIPCHK(c, launch_cache_from_z(c->loss, c->cache, c->y, c->n, c->stream));
+  HIPCHK(c, launch_margins_rows(c->loss, c->rp, c->rc, c->rv, c->w, c->y, c->n, c->cache,
+                                c->stream));
   return PCDN_OK;
 }
 
@@ -902,6 +901,30 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->poff, p + 1);
   ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->ls_part, (size_t)kLsGrid * (2 * kQMax + 2));
+  ALLOC(c, c->rp, n + 1);
+  ALLOC(c, c->rc, nnz);
+  ALLOC(c, c->rv, nnz);
+  // CSR copy (rows in order, columns ascending within a row) for the
+  // deterministic margin computation of warm starts
+  {
+    std::vector<int64_t> hrp(n + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) ++hrp[Hri[k] + 1];
+    for (int64_t i = 0; i < n; ++i) hrp[i + 1] += hrp[i];
+    std::vector<int64_t> next(hrp.begin(), hrp.end() - 1);
+    std::vector<int32_t> hrc(nnz);
+    std::vector<float> hrv(nnz);
+    for (int64_t j = 0; j < p; ++j)
+      for (int64_t k = Hcp[j]; k < Hcp[j + 1]; ++k) {
+        const int64_t at = next[Hri[k]]++;
+        hrc[at] = (int32_t)j;
+        hrv[at] = Hv[k];
+      }
+    HIPCHK(c, hipMemcpy(c->rp, hrp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    if (nnz) {
+      HIPCHK(c, hipMemcpy(c->rc, hrc.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+      HIPCHK(c, hipMemcpy(c->rv, hrv.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
+    }
+  }
   const hipMemcpyKind kind = ptr_kind == 1 ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIPCHK(c, hipMemcpyAsync(c->cp, col_ptr, (p + 1) * sizeof(int64_t), kind, c->stream));
   if (nnz) {

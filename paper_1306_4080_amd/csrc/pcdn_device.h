@@ -248,10 +248,11 @@ hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, Ite
 hipError_t launch_loss_terms(int loss, const double* cache, const int8_t* y, int64_t n,
                              double* out, hipStream_t s);
 hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s);
-// z = X w by scattering every column (atomics) over identity-order chunks.
-hipError_t launch_margins(const int32_t* ri, const float* v, const double* w,
-                          const Chunk* id_chunks, int64_t total_chunks, double* z,
-                          hipStream_t s);
+// Retained quantities from w (e^{x_i^T w}, or 1 - y_i x_i^T w) with X in CSR
+// order (rp int64[n+1], col, v); deterministic.
+hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, const float* v,
+                               const double* w, const int8_t* y, int64_t n, double* cache,
+                               hipStream_t s);
 hipError_t launch_cache_from_z(int loss, double* z_to_cache, const int8_t* y, int64_t n,
                                hipStream_t s);
 

@@ -90,6 +90,10 @@ struct pcdn_ctx {
   float* pv = nullptr;
   int64_t* poff = nullptr;
   int32_t* off32 = nullptr;
+  // X in CSR order (warm-start margins)
+  int64_t* rp = nullptr;
+  int32_t* rc = nullptr;
+  float* rv = nullptr;
 
   // reductions and small device records
   double* ls_part = nullptr;

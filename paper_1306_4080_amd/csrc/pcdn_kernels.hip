@@ -1239,18 +1239,23 @@ __global__ void k_abs(const double* w, int64_t p, double* out) {
   if (j < p) out[j] = fabs(w[j]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_margins(const int32_t* ri, const float* v,
-                                                    const double* w, const Chunk* chunks,
-                                                    int64_t total, double* z) {
+// Retained quantities from w, one wavefront per row over X in CSR order: the
+// margin z_i = sum_j x_ij w_j is summed lane-strided, then by the fixed-order
+// wavefront sum, so it does not depend on scheduling; then e^{z_i} (logistic)
+// or b_i = 1 - y_i z_i (SVM).
+template <int LOSS>
+__global__ __launch_bounds__(kBlock) void k_margins_rows(const int64_t* rp, const int32_t* col,
+                                                         const float* v, const double* w,
+                                                         const int8_t* y, int64_t n,
+                                                         double* cache) {
   const int lane = lane_id();
   const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  for (int64_t c = wave; c < total; c += nwaves) {
-    const Chunk ch = chunks[c];
-    const double wj = w[ch.feat];
-    if (wj == 0.0) continue;
-    for (int64_t k = ch.klo + lane; k < ch.klo + ch.len; k += kWave)
-      unsafeAtomicAdd(&z[ri[k]], wj * (double)v[k]);
+  for (int64_t i = wave; i < n; i += nwaves) {
+    double z = 0.0;
+    for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kWave) z += (double)v[k] * w[col[k]];
+    z = wave_sum(z);
+    if (lane == 0) cache[i] = LOSS == kLogistic ? exp(z) : 1.0 - (y[i] > 0 ? z : -z);
   }
 }
 
@@ -1479,11 +1484,14 @@ hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_margins(const int32_t* ri, const float* v, const double* w,
-                          const Chunk* id_chunks, int64_t total_chunks, double* z,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_margins, dim3(grid_for(total_chunks, kWavesPerBlock, 8192)), dim3(kBlock),
-                     0, s, ri, v, w, id_chunks, total_chunks, z);
+hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, const float* v,
+                               const double* w, const int8_t* y, int64_t n, double* cache,
+                               hipStream_t s) {
+  const dim3 g(grid_for(n, kWavesPerBlock, 8192));
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_margins_rows<kLogistic>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n, cache);
+  else
+    hipLaunchKernelGGL(k_margins_rows<kL2Svm>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n, cache);
   return hipGetLastError();
 }
 
