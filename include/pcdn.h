@@ -155,6 +155,62 @@ typedef struct {
  * (pcdn_profile) does not bracket batch launches. */
 int pcdn_solve_batch(pcdn_job* jobs, int32_t count);
 
+/* ---- solve server: continuous batching of independent requests ---------- */
+
+/* A request: a problem as host CSC arrays (the layout and checks of
+ * pcdn_load_csc; the arrays, and opts->w0 if set, must stay valid and
+ * unchanged until the request has finished) and the arguments of pcdn_solve
+ * (P = 0: about 5% of the features, the paper's starting point). */
+typedef struct {
+  int64_t n, p, nnz;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const float* val;
+  const int8_t* y;
+  double C;
+  int64_t P;
+  double eps;
+  int32_t loss;
+  int32_t reserved;       /* must be 0                                         */
+  const pcdn_opts* opts;  /* nullable; copied at submission                    */
+} pcdn_request;
+
+typedef struct pcdn_server pcdn_server;
+
+/* A server on HIP device `device` that keeps at most hbm_budget_bytes of
+ * problem state (data, w, retained quantities, work arrays) resident. */
+int pcdn_server_create(pcdn_server** out, int device, int64_t hbm_budget_bytes);
+
+/* Queue a request (first in, first out); *id identifies it.  Cheap argument
+ * checks only (the CSC is checked at admission).  PCDN_E_OOM if its state
+ * could never fit the budget.  Does not touch the GPU. */
+int pcdn_server_submit(pcdn_server* s, const pcdn_request* r, int64_t* id);
+
+/* One scheduling step: admit queued requests in order while their state fits
+ * the budget (the data is uploaded and the solve set up on the device), run
+ * one outer iteration of every admitted solve (the rounds of
+ * pcdn_solve_batch), and finish the solves that stopped, releasing their
+ * device memory.  *finished (nullable) receives how many requests finished
+ * in this step (a request whose data fails the checks finishes with that
+ * error).  Each solve follows the trajectory pcdn_solve would take for it. */
+int pcdn_server_step(pcdn_server* s, int32_t* finished);
+
+/* Queue length, admitted solves and the device bytes they hold. */
+int pcdn_server_status(const pcdn_server* s, int32_t* waiting, int32_t* running,
+                       int64_t* bytes_in_use);
+
+/* Result of a finished request (then forgotten): w_out (nullable, p
+ * doubles), info (nullable), *status (what pcdn_solve would have returned,
+ * or the admission error).  PCDN_E_STATE if the request has not finished,
+ * PCDN_E_ARG for an unknown id. */
+int pcdn_server_take(pcdn_server* s, int64_t id, double* w_out, pcdn_info* info,
+                     int32_t* status);
+
+const char* pcdn_server_last_error(const pcdn_server* s);
+
+/* Release the server, its queue and every admitted solve.  NULL is accepted. */
+int pcdn_server_destroy(pcdn_server* s);
+
 /* Regularisation path: pcdn_solve for C = Cs[0], Cs[1], ... in order, each
  * warm-started from the previous solution (the first from opts->w0, or 0),
  * with the reference norm of the stopping rule at w = 0 for every C.  W_out

@@ -8,7 +8,7 @@ method in Python and there is no CPU fallback.
 """
 import os
 
-from .binding import (LOSSES, PCDN_LOSS_L2SVM, PCDN_LOSS_LOGISTIC, PcdnError, Solver,  # noqa: F401
+from .binding import (LOSSES, PCDN_LOSS_L2SVM, PCDN_LOSS_LOGISTIC, PcdnError, Server, Solver,  # noqa: F401
                       load_library, pcdn_create, pcdn_destroy, pcdn_evaluate, pcdn_get_cache,
                       pcdn_get_w, pcdn_iterate, pcdn_last_error, pcdn_load_csc, pcdn_permutation, pcdn_profile,
                       pcdn_autotune, pcdn_profile_read, pcdn_reset, pcdn_solve, pcdn_solve_batch,

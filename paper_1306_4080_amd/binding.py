@@ -33,6 +33,8 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
 SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
            "pcdn_iterate",
            "pcdn_solve_batch", "pcdn_solve_path", "pcdn_autotune",
+           "pcdn_server_create", "pcdn_server_submit", "pcdn_server_step", "pcdn_server_status",
+           "pcdn_server_take", "pcdn_server_last_error", "pcdn_server_destroy",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
            "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy")
 
@@ -83,6 +85,14 @@ class pcdn_tune(ctypes.Structure):
                 ("predicted_seconds", ctypes.c_double), ("tried", pcdn_tune_point * 8)]
 
 
+class pcdn_request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("p", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("col_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
+                ("val", ctypes.c_void_p), ("y", ctypes.c_void_p), ("C", ctypes.c_double),
+                ("P", ctypes.c_int64), ("eps", ctypes.c_double), ("loss", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("opts", ctypes.POINTER(pcdn_opts))]
+
+
 _lib = None
 
 
@@ -124,9 +134,19 @@ def load_library(path: str = LIB_PATH):
     L.pcdn_profile_read.argtypes = [vp, i32, vp, vp, vp]
     L.pcdn_last_error.argtypes = [vp]
     L.pcdn_last_error.restype = ctypes.c_char_p
+    L.pcdn_server_create.argtypes = [ctypes.POINTER(vp), i32, i64]
+    L.pcdn_server_submit.argtypes = [vp, ctypes.POINTER(pcdn_request), ctypes.POINTER(i64)]
+    L.pcdn_server_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.pcdn_server_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
+    L.pcdn_server_take.argtypes = [vp, i64, vp, ctypes.POINTER(pcdn_info),
+                                   ctypes.POINTER(ctypes.c_int32)]
+    L.pcdn_server_last_error.argtypes = [vp]
+    L.pcdn_server_last_error.restype = ctypes.c_char_p
+    L.pcdn_server_destroy.argtypes = [vp]
     L.pcdn_destroy.argtypes = [vp]
     for s in SYMBOLS:
-        if s != "pcdn_last_error":
+        if s not in ("pcdn_last_error", "pcdn_server_last_error"):
             getattr(L, s).restype = ctypes.c_int
     _lib = L
     return L
@@ -414,3 +434,80 @@ class Solver:
 def solve_batch(jobs):
     """Solve the jobs (from Solver.job) together; list of (status, w, info)."""
     return pcdn_solve_batch(jobs)
+
+
+class Server:
+    """Solve server with continuous batching (pcdn_server_*): submit()
+    queues a problem, step() admits what fits the device-memory budget and
+    runs one outer iteration of every admitted solve, take() returns a
+    finished result.  The submitted arrays are kept referenced until taken."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 64 << 30):
+        L = load_library()
+        h = ctypes.c_void_p()
+        rc = L.pcdn_server_create(ctypes.byref(h), int(device), int(budget_bytes))
+        if rc != PCDN_OK:
+            raise PcdnError(rc, "pcdn_server_create failed")
+        self.h = h
+        self._keep = {}
+        self._p = {}
+
+    def _check(self, rc, allow=(PCDN_OK,)):
+        if rc in allow:
+            return rc
+        m = load_library().pcdn_server_last_error(self.h)
+        raise PcdnError(rc, m.decode() if m else "")
+
+    def submit(self, d, C, P, eps, loss, **opts) -> int:
+        col_ptr = np.ascontiguousarray(d.col_ptr, dtype=np.int64)
+        row_idx = np.ascontiguousarray(d.row_idx, dtype=np.int32)
+        val = np.ascontiguousarray(d.val, dtype=np.float32)
+        y = np.ascontiguousarray(d.y, dtype=np.int8)
+        o, w0 = _opts(**opts)
+        r = pcdn_request(int(d.n), int(d.p), int(col_ptr[-1]), col_ptr.ctypes.data,
+                         row_idx.ctypes.data, val.ctypes.data, y.ctypes.data, float(C), int(P),
+                         float(eps), int(LOSSES.get(loss, loss)), 0, ctypes.pointer(o))
+        rid = ctypes.c_int64()
+        self._check(load_library().pcdn_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
+        self._keep[rid.value] = (col_ptr, row_idx, val, y, o, w0)
+        self._p[rid.value] = int(d.p)
+        return rid.value
+
+    def step(self) -> int:
+        fin = ctypes.c_int32()
+        self._check(load_library().pcdn_server_step(self.h, ctypes.byref(fin)))
+        return fin.value
+
+    def status(self):
+        w, r, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(load_library().pcdn_server_status(self.h, ctypes.byref(w), ctypes.byref(r),
+                                                      ctypes.byref(b)))
+        return w.value, r.value, b.value
+
+    def take(self, rid):
+        """(status, w, info) of a finished request, or None if it has not
+        finished yet."""
+        p = self._p.get(rid)
+        w = np.empty(p) if p is not None else None
+        info = pcdn_info()
+        st = ctypes.c_int32()
+        rc = load_library().pcdn_server_take(self.h, int(rid), None if w is None else w.ctypes.data,
+                                             ctypes.byref(info), ctypes.byref(st))
+        if rc == -5:
+            return None
+        self._check(rc)
+        self._keep.pop(rid, None)
+        self._p.pop(rid, None)
+        return st.value, w, _info_dict(info)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            load_library().pcdn_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -807,6 +807,34 @@ extern "C" const char* pcdn_last_error(const pcdn_ctx* c) {
   return c ? c->err.c_str() : g_create_error.c_str();
 }
 
+namespace pcdn {
+namespace host {
+
+// Device bytes pcdn_load_csc allocates for (n, p, nnz), each buffer rounded
+// up to 4 KiB, plus the context's own small records.
+int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
+  const int64_t max_chunks = p + (nnz + kChunk - 1) / kChunk + 1;
+  const int64_t hist_m = radix_hist_ints(p);
+  const int64_t part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
+  const int64_t sizes[] = {
+      8 * (p + 1), 4 * nnz, 4 * nnz, n,                    // X, y
+      8 * p, 8 * n, 8 * n, 8 * n, 8 * p, 4 * n,            // w, cache, d^T x, scratch, flags
+      8 * p, 8 * p, 8 * p, 8 * p,                          // g, h, d, Delta terms
+      4 * p, 4 * p, 4 * p, 4 * p, 4 * hist_m,              // sort keys and payloads, histogram
+      4 * (std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)) + 1),
+      4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
+      4 * (p + 1), 32 * max_chunks, 4 * p,                 // identity-order descriptors, step bundle
+      16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
+      8 * (int64_t)kLsGrid * (2 * kQMax + 2),              // line-search partials
+      8 * (n + 1), 4 * nnz, 4 * nnz};                      // CSR copy
+  int64_t total = 64 * 1024;
+  for (const int64_t b : sizes) total += (std::max<int64_t>(b, 1) + 4095) / 4096 * 4096;
+  return total;
+}
+
+}  // namespace host
+}  // namespace pcdn
+
 extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
                              const int64_t* col_ptr, const int32_t* row_idx, const float* val,
                              const int8_t* y, int ptr_kind) {

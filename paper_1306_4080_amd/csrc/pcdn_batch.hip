@@ -1,11 +1,17 @@
 // Drivers over several solves on one device: independent problems advanced
-// together (pcdn_solve_batch) and the warm-started regularisation path
-// (pcdn_solve_path).  Each problem follows exactly the sequence of kernels
-// pcdn_solve would run for it; only the interleaving across problems differs.
+// together (pcdn_solve_batch), a request server with continuous batching
+// (pcdn_server_*), the warm-started regularisation path (pcdn_solve_path)
+// and the bundle-size autotuner (pcdn_autotune).  Each problem follows
+// exactly the sequence of kernels pcdn_solve would run for it; only the
+// interleaving across problems differs.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -16,55 +22,273 @@ using namespace pcdn::host;
 
 namespace {
 
-// Device resources of one pcdn_solve_batch call, released on every exit.
-struct BatchRes {
-  int device = 0;
-  hipStream_t narrow_stream = nullptr;  // the multi-problem single-workgroup launch
-  hipStream_t wide_stream = nullptr;    // the executor launches
-  hipEvent_t fused_done = nullptr;
-  std::vector<hipEvent_t> pre_done;
-  NarrowArgs* dtab = nullptr;           // device table of the fused launch
-  NarrowArgs* htab = nullptr;           // pinned staging for it
-  void* dexec = nullptr;                // executor tables (tasks, block offsets, scalar sources)
-  void* hexec = nullptr;                // pinned staging for them
-  size_t exec_bytes = 0;
-  double* dG = nullptr;                 // gathered stopping norms of the multi-kernel jobs
-  double* hG = nullptr;
-  ~BatchRes() {
-    (void)hipSetDevice(device);
-    if (narrow_stream) (void)hipStreamSynchronize(narrow_stream);
-    if (wide_stream) (void)hipStreamSynchronize(wide_stream);
-    for (hipEvent_t e : pre_done)
-      if (e) (void)hipEventDestroy(e);
-    if (fused_done) (void)hipEventDestroy(fused_done);
-    if (dtab) (void)hipFree(dtab);
-    if (htab) (void)hipHostFree(htab);
-    if (dexec) (void)hipFree(dexec);
-    if (hexec) (void)hipHostFree(hexec);
-    if (dG) (void)hipFree(dG);
-    if (hG) (void)hipHostFree(hG);
-    if (narrow_stream) (void)hipStreamDestroy(narrow_stream);
-    if (wide_stream) (void)hipStreamDestroy(wide_stream);
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One solve inside the engine.
+struct EngineJob {
+  SolveRun run;
+  bool narrow = false;
+  std::vector<Task> tasks;       // multi-kernel jobs: the outer iteration after the partition
+  hipEvent_t pre_done = nullptr;
+  bool active = false;
+  int64_t id = 0;                // owner's handle
+};
+
+// Grow-only device + pinned buffer pair.
+struct Staging {
+  void* dev = nullptr;
+  void* host = nullptr;
+  size_t bytes = 0;
+  hipError_t reserve(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    release();
+    want = std::max(want, (size_t)4096);
+    hipError_t e = hipMalloc(&dev, want);
+    if (e == hipSuccess) e = hipHostMalloc(&host, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      release();
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (dev) (void)hipFree(dev);
+    if (host) (void)hipHostFree(host);
+    dev = host = nullptr;
+    bytes = 0;
   }
 };
 
-// Device error of the batch itself, reported on the first job's context.
-int batch_fail(pcdn_ctx* c, hipError_t e, const char* what) {
-  (void)hipGetLastError();
-  return fail(c, PCDN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
-}
+// Rounds of one outer iteration over a changing set of solves.  Jobs on the
+// single-workgroup schedule share one launch per round (one workgroup each);
+// jobs on the multi-kernel schedule run their recorded outer iteration in
+// lock-step executor launches (launch s runs task s of every such job).
+// Every job's partition is a replayed graph on its own context's stream.
+class Engine {
+ public:
+  std::string err;
 
-size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+  ~Engine() {
+    (void)hipSetDevice(device_);
+    if (narrow_stream_) (void)hipStreamSynchronize(narrow_stream_);
+    if (wide_stream_) (void)hipStreamSynchronize(wide_stream_);
+    for (EngineJob* j : jobs_) drop_event(j);
+    if (fused_done_) (void)hipEventDestroy(fused_done_);
+    narrow_tab_.release();
+    exec_.release();
+    gather_.release();
+    if (narrow_stream_) (void)hipStreamDestroy(narrow_stream_);
+    if (wide_stream_) (void)hipStreamDestroy(wide_stream_);
+  }
 
-// Lock-step schedule of the multi-kernel jobs of one round: launch s runs
-// task s of every job that has one (a job's tasks are the kernels of its
-// outer iteration after the partition, in order).
-struct ExecPlan {
-  std::vector<int> jobs;          // job indices, in gather order
-  std::vector<size_t> task_off;   // per launch: first task (index into the task table)
-  std::vector<size_t> first_off;  // per launch: first block offset (index into the offsets)
-  std::vector<int> count, blocks; // per launch
-  size_t n_tasks = 0, n_first = 0;
+  int init(int device) {
+    device_ = device;
+    if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&narrow_stream_, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&wide_stream_, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&fused_done_, hipEventDisableTiming) != hipSuccess)
+      return dev_fail("engine set-up", hipGetLastError());
+    return PCDN_OK;
+  }
+
+  size_t size() const { return jobs_.size(); }
+
+  // Start a job whose run fields (c, o, C, P, eps, loss, w0_device) are set:
+  // reference norm and w (solve_begin), graphs or tasks, iteration record.
+  // Returns an error code on the job's context; afterwards j->active tells
+  // whether it needs rounds (it joins the engine then).
+  int add(EngineJob* j) {
+    SolveRun& r = j->run;
+    int rc = solve_begin(r);
+    if (rc) return rc;
+    j->narrow = use_narrow(r.c, r.o, r.P);
+    rc = ensure_split_graphs(r.c, r.o, r.P);
+    if (rc) return rc;
+    if (!j->narrow) {
+      rc = outer_tasks(r.c, r.o, r.P, j->tasks);
+      if (rc) return rc;
+    }
+    rc = set_iter(r.c, r.o.seed, 0);
+    if (rc) return rc;
+    j->active = !r.converged && r.outer < r.o.max_outer;
+    if (!j->active) return PCDN_OK;
+    if (hipEventCreateWithFlags(&j->pre_done, hipEventDisableTiming) != hipSuccess)
+      return fail(r.c, PCDN_E_DEVICE, "event creation failed");
+    jobs_.push_back(j);
+    if (!j->narrow) plan_stale_ = true;
+    return PCDN_OK;
+  }
+
+  // One outer iteration of every job; the jobs that stop (stopping rule or
+  // max_outer) leave the engine and are appended to `done`.  Errors of a
+  // job's context come back as its code with the message on that context
+  // (*err_ctx set to it); engine-level errors as PCDN_E_DEVICE in `err`.
+  int round(std::vector<EngineJob*>& done, pcdn_ctx** err_ctx) {
+    *err_ctx = nullptr;
+    if (jobs_.empty()) return PCDN_OK;
+    if (hipSetDevice(device_) != hipSuccess) return dev_fail("hipSetDevice", hipGetLastError());
+    int rc = plan_stale_ ? build_plan() : PCDN_OK;
+    if (rc) return rc;
+    // partitions, each on its job's stream
+    size_t m = 0;
+    for (EngineJob* j : jobs_) if (j->narrow) ++m;
+    if (narrow_tab_.reserve(sizeof(NarrowArgs) * m) != hipSuccess)
+      return dev_fail("table allocation", hipErrorOutOfMemory);
+    NarrowArgs* htab = (NarrowArgs*)narrow_tab_.host;
+    m = 0;
+    for (EngineJob* j : jobs_) {
+      pcdn_ctx* c = j->run.c;
+      *err_ctx = c;
+      HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
+      HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(j->narrow ? narrow_stream_ : wide_stream_, j->pre_done, 0));
+      if (j->narrow) {
+        const int64_t nb = (c->p + j->run.P - 1) / j->run.P;
+        htab[m++] = make_narrow_args(c, j->run.o, c->idx0, c->p, j->run.P, 0, nb, nullptr);
+      }
+      count_outer(c, j->run.o, j->run.P, 1);
+    }
+    *err_ctx = nullptr;
+    // single-workgroup jobs: one launch, then each job's stopping sweep
+    if (m > 0) {
+      hipError_t e = hipMemcpyAsync(narrow_tab_.dev, htab, sizeof(NarrowArgs) * m,
+                                    hipMemcpyHostToDevice, narrow_stream_);
+      if (e == hipSuccess) e = launch_narrow_multi((const NarrowArgs*)narrow_tab_.dev, (int)m,
+                                                   narrow_stream_);
+      if (e == hipSuccess) e = hipEventRecord(fused_done_, narrow_stream_);
+      if (e != hipSuccess) return dev_fail("multi-problem launch", e);
+      for (EngineJob* j : jobs_) {
+        if (!j->narrow) continue;
+        pcdn_ctx* c = j->run.c;
+        *err_ctx = c;
+        HIPCHK(c, hipStreamWaitEvent(c->stream, fused_done_, 0));
+        HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+      }
+      *err_ctx = nullptr;
+    }
+    // multi-kernel jobs: every bundle and stopping sweep in lock-step launches
+    if (!plan_jobs_.empty()) {
+      const char* base = (const char*)exec_.dev;
+      for (size_t st = 0; st < plan_count_.size(); ++st) {
+        const hipError_t e = launch_exec((const Task*)(base + plan_task_byte_[st]),
+                                         (const int32_t*)(base + plan_first_byte_[st]),
+                                         plan_count_[st], plan_blocks_[st], wide_stream_);
+        if (e != hipSuccess) return dev_fail("executor launch", e);
+      }
+      hipError_t e = launch_gather((const double* const*)(base + plan_src_byte_),
+                                   (double*)gather_.dev, (int)plan_jobs_.size(), wide_stream_);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(gather_.host, gather_.dev, sizeof(double) * plan_jobs_.size(),
+                           hipMemcpyDeviceToHost, wide_stream_);
+      if (e != hipSuccess) return dev_fail("gather", e);
+    }
+    // the staging tables and every pinned result are reused next round
+    hipError_t e = hipStreamSynchronize(narrow_stream_);
+    if (e == hipSuccess) e = hipStreamSynchronize(wide_stream_);
+    if (e != hipSuccess) return dev_fail("round", e);
+    for (size_t k = 0; k < plan_jobs_.size(); ++k)
+      plan_jobs_[k]->run.c->hscal[0] = ((const double*)gather_.host)[k];
+    std::vector<EngineJob*> keep;
+    keep.reserve(jobs_.size());
+    for (EngineJob* j : jobs_) {
+      pcdn_ctx* c = j->run.c;
+      *err_ctx = c;
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      rc = solve_note_outer(j->run, c->hscal[0]);
+      if (rc) return rc;
+      j->active = !j->run.converged && j->run.outer < j->run.o.max_outer;
+      if (j->active) {
+        keep.push_back(j);
+      } else {
+        drop_event(j);
+        done.push_back(j);
+        if (!j->narrow) plan_stale_ = true;
+      }
+    }
+    *err_ctx = nullptr;
+    jobs_.swap(keep);
+    return PCDN_OK;
+  }
+
+ private:
+  int device_ = 0;
+  hipStream_t narrow_stream_ = nullptr;  // the multi-problem single-workgroup launch
+  hipStream_t wide_stream_ = nullptr;    // the executor launches
+  hipEvent_t fused_done_ = nullptr;
+  std::vector<EngineJob*> jobs_;
+  Staging narrow_tab_, exec_, gather_;
+  bool plan_stale_ = true;
+  // lock-step plan of the multi-kernel jobs (byte offsets into exec_)
+  std::vector<EngineJob*> plan_jobs_;
+  std::vector<size_t> plan_task_byte_, plan_first_byte_;
+  std::vector<int> plan_count_, plan_blocks_;
+  size_t plan_src_byte_ = 0;
+
+  int dev_fail(const char* what, hipError_t e) {
+    (void)hipGetLastError();
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return PCDN_E_DEVICE;
+  }
+
+  static void drop_event(EngineJob* j) {
+    if (j->pre_done) (void)hipEventDestroy(j->pre_done);
+    j->pre_done = nullptr;
+  }
+
+  // Launch s runs task s of every multi-kernel job that has one.
+  int build_plan() {
+    plan_jobs_.clear();
+    plan_task_byte_.clear();
+    plan_first_byte_.clear();
+    plan_count_.clear();
+    plan_blocks_.clear();
+    size_t L = 0, n_tasks = 0;
+    for (EngineJob* j : jobs_) {
+      if (j->narrow) continue;
+      plan_jobs_.push_back(j);
+      L = std::max(L, j->tasks.size());
+      n_tasks += j->tasks.size();
+    }
+    plan_stale_ = false;
+    if (plan_jobs_.empty()) return PCDN_OK;
+    const size_t task_bytes = align_up(sizeof(Task) * n_tasks);
+    const size_t first_bytes = align_up(sizeof(int32_t) * (n_tasks + L));
+    const size_t src_bytes = align_up(sizeof(double*) * plan_jobs_.size());
+    // the previous plan's tables may still be read by nothing: rounds end synchronised
+    if (exec_.reserve(task_bytes + first_bytes + src_bytes) != hipSuccess ||
+        gather_.reserve(sizeof(double) * plan_jobs_.size()) != hipSuccess)
+      return dev_fail("executor table allocation", hipErrorOutOfMemory);
+    char* h = (char*)exec_.host;
+    Task* htasks = (Task*)h;
+    int32_t* hfirst = (int32_t*)(h + task_bytes);
+    const double** hsrc = (const double**)(h + task_bytes + first_bytes);
+    size_t nt = 0, nf = 0;
+    for (size_t st = 0; st < L; ++st) {
+      plan_task_byte_.push_back(sizeof(Task) * nt);
+      plan_first_byte_.push_back(task_bytes + sizeof(int32_t) * nf);
+      int cnt = 0, blk = 0;
+      hfirst[nf++] = 0;
+      for (EngineJob* j : plan_jobs_) {
+        if (st >= j->tasks.size()) continue;
+        htasks[nt++] = j->tasks[st];
+        blk += j->tasks[st].nblk;
+        hfirst[nf++] = blk;
+        ++cnt;
+      }
+      plan_count_.push_back(cnt);
+      plan_blocks_.push_back(blk);
+    }
+    for (size_t k = 0; k < plan_jobs_.size(); ++k) hsrc[k] = plan_jobs_[k]->run.c->scal;
+    plan_src_byte_ = task_bytes + first_bytes;
+    const hipError_t e = hipMemcpyAsync(exec_.dev, exec_.host, task_bytes + first_bytes + src_bytes,
+                                        hipMemcpyHostToDevice, wide_stream_);
+    if (e != hipSuccess) return dev_fail("executor table upload", e);
+    return PCDN_OK;
+  }
 };
 
 }  // namespace
@@ -73,7 +297,7 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
   if (count == 0) return PCDN_OK;
   if (!jobs || count < 0) return PCDN_E_ARG;
   // argument checks for every job before any work
-  std::vector<SolveRun> runs(count);
+  std::vector<EngineJob> ej(count);
   for (int32_t i = 0; i < count; ++i) {
     pcdn_job& j = jobs[i];
     j.status = PCDN_E_ARG;
@@ -82,199 +306,261 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
       if (jobs[k].ctx == j.ctx) return fail(j.ctx, PCDN_E_ARG, "two jobs share a context");
     if (j.ctx->device != jobs[0].ctx->device)
       return fail(j.ctx, PCDN_E_ARG, "the contexts of a batch must share one device");
-    const int rc = check_solve_args(j.ctx, j.C, j.P == 0 ? 1 : j.P, j.eps, j.loss, j.opts,
-                                    &runs[i].o);
+    SolveRun& r = ej[i].run;
+    const int rc = check_solve_args(j.ctx, j.C, j.P == 0 ? 1 : j.P, j.eps, j.loss, j.opts, &r.o);
     if (rc) {
       j.status = rc;
       return rc;
     }
-    runs[i].c = j.ctx;
-    runs[i].C = j.C;
-    runs[i].P = j.P;
-    runs[i].eps = j.eps;
-    runs[i].loss = j.loss;
+    r.c = j.ctx;
+    r.C = j.C;
+    r.P = j.P;
+    r.eps = j.eps;
+    r.loss = j.loss;
   }
   // bundle sizes left to the autotuner
   for (int32_t i = 0; i < count; ++i) {
     if (jobs[i].P != 0) continue;
+    SolveRun& r = ej[i].run;
     pcdn_tune t;
-    const int rc = pcdn_autotune(runs[i].c, runs[i].loss, runs[i].C, runs[i].eps, jobs[i].opts, &t);
+    const int rc = pcdn_autotune(r.c, r.loss, r.C, r.eps, jobs[i].opts, &t);
     if (rc) {
       jobs[i].status = rc;
       return rc;
     }
-    runs[i].P = t.P;
+    r.P = t.P;
     jobs[i].P = t.P;
   }
-  pcdn_ctx* c0 = jobs[0].ctx;
-  BatchRes res;
-  res.device = c0->device;
-  HIPCHK(c0, hipSetDevice(res.device));
-  HIPCHK(c0, hipStreamCreateWithFlags(&res.narrow_stream, hipStreamNonBlocking));
-  HIPCHK(c0, hipStreamCreateWithFlags(&res.wide_stream, hipStreamNonBlocking));
-  HIPCHK(c0, hipEventCreateWithFlags(&res.fused_done, hipEventDisableTiming));
-  res.pre_done.assign(count, nullptr);
-  for (int32_t i = 0; i < count; ++i)
-    HIPCHK(c0, hipEventCreateWithFlags(&res.pre_done[i], hipEventDisableTiming));
-
-  // set-up: reference norm and w per job, graphs or task lists, iteration record
-  std::vector<char> narrow(count, 0), active(count, 0);
-  std::vector<std::vector<Task>> tasks(count);
-  int32_t n_narrow = 0;
-  size_t all_tasks = 0, all_first = 0, max_len = 0;
+  Engine eng;
+  int rc = eng.init(jobs[0].ctx->device);
+  if (rc) return fail(jobs[0].ctx, rc, eng.err);
   for (int32_t i = 0; i < count; ++i) {
-    SolveRun& r = runs[i];
-    int rc = solve_begin(r);
+    rc = eng.add(&ej[i]);
     if (rc) return rc;
-    narrow[i] = use_narrow(r.c, r.o, r.P) ? 1 : 0;
-    n_narrow += narrow[i];
-    rc = ensure_split_graphs(r.c, r.o, r.P);
-    if (rc) return rc;
-    if (!narrow[i]) {
-      rc = outer_tasks(r.c, r.o, r.P, tasks[i]);
-      if (rc) return rc;
-      all_tasks += tasks[i].size();
-      max_len = std::max(max_len, tasks[i].size());
-    }
-    rc = set_iter(r.c, r.o.seed, 0);
-    if (rc) return rc;
-    active[i] = !r.converged && r.outer < r.o.max_outer;
   }
-  const int32_t n_wide = count - n_narrow;
-  // at most one block-offset entry per task plus one per launch
-  all_first = all_tasks + max_len;
-  if (n_narrow > 0) {
-    if (dalloc(&res.dtab, n_narrow) != hipSuccess ||
-        hipHostMalloc((void**)&res.htab, sizeof(NarrowArgs) * n_narrow) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c0, PCDN_E_OOM, "allocation failed for the batch table");
-    }
-  }
-  if (n_wide > 0) {
-    res.exec_bytes = align_up(sizeof(Task) * all_tasks) + align_up(sizeof(int32_t) * all_first) +
-                     align_up(sizeof(double*) * n_wide);
-    if (hipMalloc(&res.dexec, res.exec_bytes) != hipSuccess ||
-        hipHostMalloc(&res.hexec, res.exec_bytes) != hipSuccess ||
-        dalloc(&res.dG, n_wide) != hipSuccess ||
-        hipHostMalloc((void**)&res.hG, sizeof(double) * n_wide) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(c0, PCDN_E_OOM, "allocation failed for the executor tables");
-    }
-  }
-  Task* const htasks = (Task*)res.hexec;
-  int32_t* const hfirst = (int32_t*)((char*)res.hexec + align_up(sizeof(Task) * all_tasks));
-  const double** const hsrc =
-      (const double**)((char*)hfirst + align_up(sizeof(int32_t) * all_first));
-  const Task* const dtasks = (const Task*)res.dexec;
-  const int32_t* const dfirst = (const int32_t*)((char*)res.dexec + ((char*)hfirst - (char*)res.hexec));
-  const double* const* const dsrc =
-      (const double* const*)((char*)res.dexec + ((char*)hsrc - (char*)res.hexec));
-
-  ExecPlan plan;
-  bool plan_stale = true;
-  // rounds: one outer iteration of every active job
-  for (;;) {
-    int32_t live = 0;
-    for (int32_t i = 0; i < count; ++i) live += active[i];
-    if (live == 0) break;
-    // multi-kernel jobs: (re)build the lock-step tables when the set changed
-    if (plan_stale) {
-      plan = ExecPlan();
-      for (int32_t i = 0; i < count; ++i)
-        if (active[i] && !narrow[i]) plan.jobs.push_back(i);
-      size_t L = 0;
-      for (int i : plan.jobs) L = std::max(L, tasks[i].size());
-      for (size_t st = 0; st < L; ++st) {
-        plan.task_off.push_back(plan.n_tasks);
-        plan.first_off.push_back(plan.n_first);
-        int cnt = 0, blk = 0;
-        hfirst[plan.n_first++] = 0;
-        for (int i : plan.jobs) {
-          if (st >= tasks[i].size()) continue;
-          htasks[plan.n_tasks++] = tasks[i][st];
-          blk += tasks[i][st].nblk;
-          hfirst[plan.n_first++] = blk;
-          ++cnt;
-        }
-        plan.count.push_back(cnt);
-        plan.blocks.push_back(blk);
-      }
-      for (size_t k = 0; k < plan.jobs.size(); ++k) hsrc[k] = runs[plan.jobs[k]].c->scal;
-      if (!plan.jobs.empty()) {
-        const hipError_t e = hipMemcpyAsync(res.dexec, res.hexec, res.exec_bytes,
-                                            hipMemcpyHostToDevice, res.wide_stream);
-        if (e != hipSuccess) return batch_fail(c0, e, "executor table upload");
-      }
-      plan_stale = false;
-    }
-    // partitions of every active job, each on its own stream
-    int32_t m = 0;
-    for (int32_t i = 0; i < count; ++i) {
-      if (!active[i]) continue;
-      pcdn_ctx* c = runs[i].c;
-      HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
-      HIPCHK(c, hipEventRecord(res.pre_done[i], c->stream));
-      hipStream_t group = narrow[i] ? res.narrow_stream : res.wide_stream;
-      HIPCHK(c, hipStreamWaitEvent(group, res.pre_done[i], 0));
-      if (narrow[i]) {
-        const int64_t nb = (c->p + runs[i].P - 1) / runs[i].P;
-        res.htab[m++] = make_narrow_args(c, runs[i].o, c->idx0, c->p, runs[i].P, 0, nb, nullptr);
-      }
-      count_outer(c, runs[i].o, runs[i].P, 1);
-    }
-    // single-workgroup jobs: one launch, then each job's stopping sweep
-    if (m > 0) {
-      hipError_t e = hipMemcpyAsync(res.dtab, res.htab, sizeof(NarrowArgs) * m,
-                                    hipMemcpyHostToDevice, res.narrow_stream);
-      if (e != hipSuccess) return batch_fail(c0, e, "batch table upload");
-      e = launch_narrow_multi(res.dtab, m, res.narrow_stream);
-      if (e != hipSuccess) return batch_fail(c0, e, "multi-problem launch");
-      e = hipEventRecord(res.fused_done, res.narrow_stream);
-      if (e != hipSuccess) return batch_fail(c0, e, "event record");
-      for (int32_t i = 0; i < count; ++i) {
-        if (!active[i] || !narrow[i]) continue;
-        pcdn_ctx* c = runs[i].c;
-        HIPCHK(c, hipStreamWaitEvent(c->stream, res.fused_done, 0));
-        HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost,
-                                 c->stream));
-      }
-    }
-    // multi-kernel jobs: every bundle and stopping sweep in lock-step launches
-    if (!plan.jobs.empty()) {
-      for (size_t st = 0; st < plan.count.size(); ++st) {
-        const hipError_t e = launch_exec(dtasks + plan.task_off[st], dfirst + plan.first_off[st],
-                                         plan.count[st], plan.blocks[st], res.wide_stream);
-        if (e != hipSuccess) return batch_fail(c0, e, "executor launch");
-      }
-      hipError_t e = launch_gather(dsrc, res.dG, (int)plan.jobs.size(), res.wide_stream);
-      if (e != hipSuccess) return batch_fail(c0, e, "gather");
-      e = hipMemcpyAsync(res.hG, res.dG, sizeof(double) * plan.jobs.size(),
-                         hipMemcpyDeviceToHost, res.wide_stream);
-      if (e != hipSuccess) return batch_fail(c0, e, "gather copy");
-    }
-    // the staging tables and every pinned result are reused next round
-    hipError_t e = hipStreamSynchronize(res.narrow_stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(res.wide_stream);
-    if (e != hipSuccess) return batch_fail(c0, e, "round");
-    for (size_t k = 0; k < plan.jobs.size(); ++k) runs[plan.jobs[k]].c->hscal[0] = res.hG[k];
-    for (int32_t i = 0; i < count; ++i) {
-      if (!active[i]) continue;
-      pcdn_ctx* c = runs[i].c;
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      const int rc = solve_note_outer(runs[i], c->hscal[0]);
-      if (rc) return rc;
-      active[i] = !runs[i].converged && runs[i].outer < runs[i].o.max_outer;
-      if (!active[i] && !narrow[i]) plan_stale = true;
-    }
+  std::vector<EngineJob*> done;
+  while (eng.size() > 0) {
+    pcdn_ctx* ec = nullptr;
+    rc = eng.round(done, &ec);
+    if (rc) return ec ? rc : fail(jobs[0].ctx, rc, eng.err);
   }
   int first_err = PCDN_OK;
   for (int32_t i = 0; i < count; ++i) {
-    const int rc = solve_end(runs[i], jobs[i].w_out, jobs[i].info);
+    rc = solve_end(ej[i].run, jobs[i].w_out, jobs[i].info);
     jobs[i].status = rc;
     if (rc < 0 && first_err == PCDN_OK) first_err = rc;
   }
   return first_err;
+}
+
+// ===========================================================================
+// Solve server: continuous batching.  Requests wait in arrival order; a step
+// admits them while their device state fits the budget, runs one engine
+// round over everything admitted, and finishes (and frees) what stopped.
+// ===========================================================================
+namespace {
+
+struct ServerReq {
+  int64_t id = 0;
+  pcdn_request r{};
+  pcdn_opts opts{};
+  bool has_opts = false;
+  int64_t footprint = 0;
+  pcdn_ctx* ctx = nullptr;
+  EngineJob job;
+  ~ServerReq() {
+    if (ctx) pcdn_destroy(ctx);
+  }
+};
+
+struct ServerResult {
+  std::vector<double> w;
+  pcdn_info info{};
+  int32_t status = PCDN_OK;
+  std::string msg;  // error message of a failed request
+};
+
+}  // namespace
+
+struct pcdn_server {
+  int device = 0;
+  int64_t budget = 0, used = 0;
+  int64_t next_id = 1;
+  std::string err;
+  // declared before the engine so that the engine (which refers to the
+  // admitted jobs) is destroyed first
+  std::deque<std::unique_ptr<ServerReq>> waiting;
+  std::map<int64_t, std::unique_ptr<ServerReq>> running;
+  std::map<int64_t, ServerResult> finished;
+  Engine eng;
+};
+
+namespace {
+
+int server_fail(pcdn_server* s, int code, const std::string& msg) {
+  s->err = msg;
+  return code;
+}
+
+// Record the outcome of an admitted or rejected request and free its state.
+void server_finish(pcdn_server* s, std::unique_ptr<ServerReq> q, int status, bool ran) {
+  ServerResult res;
+  res.status = status;
+  if (ran) {
+    res.w.assign((size_t)q->r.p, 0.0);
+    res.status = solve_end(q->job.run, res.w.data(), &res.info);
+  }
+  if (res.status < 0) res.msg = q->ctx ? pcdn_last_error(q->ctx) : pcdn_last_error(nullptr);
+  s->used -= q->footprint;
+  s->finished[q->id] = std::move(res);
+  // q (and its context) are released here
+}
+
+// Upload and set up one request; on success it joins the engine (or has
+// already stopped, e.g. w = 0 optimal).
+int server_admit(pcdn_server* s, ServerReq* q) {
+  int rc = pcdn_create(&q->ctx, s->device, nullptr);
+  if (rc) return rc;
+  const pcdn_request& r = q->r;
+  rc = pcdn_load_csc(q->ctx, r.n, r.p, r.nnz, r.col_ptr, r.row_idx, r.val, r.y, 0);
+  if (rc) return rc;
+  SolveRun& run = q->job.run;
+  const int64_t P = r.P == 0 ? std::max<int64_t>(1, std::llround(0.05 * (double)r.p)) : r.P;
+  rc = check_solve_args(q->ctx, r.C, P, r.eps, r.loss, q->has_opts ? &q->opts : nullptr, &run.o);
+  if (rc) return rc;
+  run.c = q->ctx;
+  run.C = r.C;
+  run.P = P;
+  run.eps = r.eps;
+  run.loss = r.loss;
+  q->job.id = q->id;
+  return s->eng.add(&q->job);
+}
+
+}  // namespace
+
+extern "C" int pcdn_server_create(pcdn_server** out, int device, int64_t hbm_budget_bytes) {
+  if (!out) return PCDN_E_ARG;
+  *out = nullptr;
+  if (hbm_budget_bytes <= 0) return PCDN_E_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PCDN_E_DEVICE;
+  if (device < 0 || device >= ndev) return PCDN_E_ARG;
+  pcdn_server* s = new (std::nothrow) pcdn_server();
+  if (!s) return PCDN_E_OOM;
+  s->device = device;
+  s->budget = hbm_budget_bytes;
+  if (s->eng.init(device) != PCDN_OK) {
+    delete s;
+    return PCDN_E_DEVICE;
+  }
+  *out = s;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_server_submit(pcdn_server* s, const pcdn_request* r, int64_t* id) {
+  if (!s) return PCDN_E_ARG;
+  if (!r || !id) return server_fail(s, PCDN_E_ARG, "null argument");
+  if (r->n < 1 || r->p < 1 || r->nnz < 0 || r->n >= ((int64_t)1 << 31) || r->p >= ((int64_t)1 << 31))
+    return server_fail(s, PCDN_E_ARG, "sizes out of range");
+  if (!r->col_ptr || !r->y || (r->nnz > 0 && (!r->row_idx || !r->val)))
+    return server_fail(s, PCDN_E_ARG, "null array");
+  if (r->loss != PCDN_LOSS_LOGISTIC && r->loss != PCDN_LOSS_L2SVM)
+    return server_fail(s, PCDN_E_ARG, "unknown loss");
+  if (!(r->C > 0.0) || !std::isfinite(r->C)) return server_fail(s, PCDN_E_ARG, "C must be > 0");
+  if (!(r->eps >= 0.0) || !std::isfinite(r->eps)) return server_fail(s, PCDN_E_ARG, "eps must be >= 0");
+  if (r->P < 0 || r->P > r->p) return server_fail(s, PCDN_E_ARG, "P must lie in [0, p]");
+  if (r->reserved != 0) return server_fail(s, PCDN_E_ARG, "reserved field must be 0");
+  auto q = std::make_unique<ServerReq>();
+  q->r = *r;
+  if (r->opts) {
+    q->opts = *r->opts;
+    q->has_opts = true;
+  }
+  q->footprint = ctx_footprint_bytes(r->n, r->p, r->nnz);
+  if (q->footprint > s->budget)
+    return server_fail(s, PCDN_E_OOM, "the request's device state exceeds the server's budget");
+  q->id = s->next_id++;
+  *id = q->id;
+  s->waiting.push_back(std::move(q));
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_server_step(pcdn_server* s, int32_t* finished) {
+  if (!s) return PCDN_E_ARG;
+  int32_t nfin = 0;
+  if (finished) *finished = 0;
+  // admission, first in first out, while the state fits
+  while (!s->waiting.empty() && s->used + s->waiting.front()->footprint <= s->budget) {
+    std::unique_ptr<ServerReq> q = std::move(s->waiting.front());
+    s->waiting.pop_front();
+    s->used += q->footprint;
+    const int rc = server_admit(s, q.get());
+    if (rc != PCDN_OK) {
+      server_finish(s, std::move(q), rc, false);
+      ++nfin;
+    } else if (!q->job.active) {
+      server_finish(s, std::move(q), PCDN_OK, true);
+      ++nfin;
+    } else {
+      const int64_t id = q->id;
+      s->running[id] = std::move(q);
+    }
+  }
+  // one outer iteration of every admitted solve
+  if (s->eng.size() > 0) {
+    std::vector<EngineJob*> done;
+    pcdn_ctx* ec = nullptr;
+    const int rc = s->eng.round(done, &ec);
+    if (rc) return server_fail(s, rc, ec ? pcdn_last_error(ec) : s->eng.err);
+    for (EngineJob* j : done) {
+      auto it = s->running.find(j->id);
+      if (it == s->running.end()) continue;
+      std::unique_ptr<ServerReq> q = std::move(it->second);
+      s->running.erase(it);
+      server_finish(s, std::move(q), PCDN_OK, true);
+      ++nfin;
+    }
+  }
+  if (finished) *finished = nfin;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_server_status(const pcdn_server* s, int32_t* waiting, int32_t* running,
+                                  int64_t* bytes_in_use) {
+  if (!s) return PCDN_E_ARG;
+  if (waiting) *waiting = (int32_t)s->waiting.size();
+  if (running) *running = (int32_t)s->running.size();
+  if (bytes_in_use) *bytes_in_use = s->used;
+  return PCDN_OK;
+}
+
+extern "C" int pcdn_server_take(pcdn_server* s, int64_t id, double* w_out, pcdn_info* info,
+                                int32_t* status) {
+  if (!s) return PCDN_E_ARG;
+  auto it = s->finished.find(id);
+  if (it == s->finished.end()) {
+    if (s->running.count(id)) return server_fail(s, PCDN_E_STATE, "request still running");
+    for (const auto& q : s->waiting)
+      if (q->id == id) return server_fail(s, PCDN_E_STATE, "request still waiting");
+    return server_fail(s, PCDN_E_ARG, "unknown request id");
+  }
+  const ServerResult& res = it->second;
+  if (w_out && !res.w.empty()) std::memcpy(w_out, res.w.data(), res.w.size() * sizeof(double));
+  if (info) *info = res.info;
+  if (status) *status = res.status;
+  if (res.status < 0) s->err = res.msg;
+  s->finished.erase(it);
+  return PCDN_OK;
+}
+
+extern "C" const char* pcdn_server_last_error(const pcdn_server* s) {
+  return s ? s->err.c_str() : "";
+}
+
+extern "C" int pcdn_server_destroy(pcdn_server* s) {
+  delete s;
+  return PCDN_OK;
 }
 
 extern "C" int pcdn_solve_path(pcdn_ctx* c, const double* Cs, int32_t count, int64_t P,

@@ -189,6 +189,8 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<pcdn::Task>& 
 int ensure_split_graphs(pcdn_ctx* c, const Opts& o, int64_t P);
 // Capture (once per key) a whole outer iteration (graph).
 int ensure_graph(pcdn_ctx* c, const Opts& o, int64_t P);
+// Device bytes a context holding (n, p, nnz) allocates (admission estimate).
+int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz);
 // Host-known work of `count` outer iterations (sweep and stopping counters).
 void count_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t count);
 // Set the device-side outer-iteration record (seed, k) read by graph replays.
