@@ -37,6 +37,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -71,6 +73,10 @@ def parse():
                     help="skip the batched-solve and regularisation-path measurements")
     ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="shrink n and p of the 64 batched problems (1.0: full size)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serving-scale", type=float, default=0.1,
+                    help="shrink the served problems' n and p ranges (1.0: full size)")
+    ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the kernel sources that traffic records are keyed by")
     return ap.parse_args()
@@ -199,6 +205,82 @@ def path_measurement(pc, d) -> dict:
             "plain_outer_iters": int(outer)}
 
 
+def _percentiles(lat):
+    lat = sorted(lat)
+    pick = lambda q: lat[min(len(lat) - 1, int(np.ceil(q * len(lat))) - 1)]
+    return {"p50_s": pick(0.50), "p99_s": pick(0.99), "max_s": lat[-1],
+            "mean_s": float(np.mean(lat))}
+
+
+def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
+    """A Poisson stream (50 requests/s) of mixed LR/SVM solves drawn from a
+    pool of 16 problems, replayed by arrival time through the solve server
+    (continuous batching, 64 GiB budget) and through one pcdn_load_csc +
+    pcdn_solve after another in arrival order ("plain"); latency = finish
+    time - arrival time.  P per pool problem from the autotuner, chosen
+    before the stream starts."""
+    pool = synth.c5_pool(scale=scale)
+    stream = synth.c5_stream(count=n_req, pool=len(pool))
+    Ps = []
+    for d, loss in pool:
+        s = pc.Solver(device=0).load_data(d)
+        Ps.append(s.autotune(1.0, 1e-4, loss, seed=SEED)["P"])
+        s.close()
+    # served
+    srv = pc.Server(device=0, budget_bytes=64 << 30)
+    arrival, finish, F_srv = {}, {}, {}
+    out = {}
+    k = 0
+    t0 = time.perf_counter()
+    while len(finish) < len(stream):
+        now = time.perf_counter() - t0
+        while k < len(stream) and stream[k][0] <= now:
+            t_arr, i, C = stream[k]
+            d, loss = pool[i]
+            rid = srv.submit(d, C, Ps[i], 1e-4, loss, seed=SEED)
+            out[rid] = k
+            arrival[k] = t_arr
+            k += 1
+        waiting, running, _ = srv.status()
+        if waiting + running == 0:
+            if k < len(stream):
+                time.sleep(max(0.0, stream[k][0] - (time.perf_counter() - t0)))
+            continue
+        srv.step()
+        for rid in [r for r in out if out[r] not in finish]:
+            r = srv.take(rid)
+            if r is not None:
+                finish[out[rid]] = time.perf_counter() - t0
+                F_srv[out[rid]] = r[2]["objective"]
+    srv.close()
+    lat_srv = [finish[q] - arrival[q] for q in range(len(stream))]
+    span_srv = max(finish.values()) - stream[0][0]
+    # plain: one request at a time, in arrival order
+    s = pc.Solver(device=0)
+    F_plain, lat_plain = {}, []
+    t0 = time.perf_counter()
+    for q, (t_arr, i, C) in enumerate(stream):
+        now = time.perf_counter() - t0
+        if now < t_arr:
+            time.sleep(t_arr - now)
+        d, loss = pool[i]
+        s.load_data(d)
+        _, _, info = s.solve(C, Ps[i], 1e-4, loss, seed=SEED)
+        F_plain[q] = info["objective"]
+        lat_plain.append(time.perf_counter() - t0 - t_arr)
+    span_plain = time.perf_counter() - t0 - stream[0][0]
+    s.close()
+    worst = max(abs(F_srv[q] - F_plain[q]) / abs(F_plain[q]) for q in range(len(stream)))
+    return {"workload": f"{len(stream)} requests, Poisson 50/s, pool of {len(pool)} problems "
+                        f"(LR/SVM 1:1, n log-U[1e3, {2e5 * scale:.0f}], p log-U[1e3, "
+                        f"{2e6 * scale:.0f}], U{{20..150}} nnz/row, Zipf(1.1) columns), "
+                        f"C log-U[0.1, 10], eps=1e-4, autotuned P per pool problem",
+            "served": dict(_percentiles(lat_srv), solves_per_s=len(stream) / span_srv),
+            "plain": dict(_percentiles(lat_plain), solves_per_s=len(stream) / span_plain),
+            "max_rel_objective_gap": worst,
+            "nnz_mean": float(np.mean([d.nnz for d, _ in pool]))}
+
+
 def main():
     args = parse()
     if args.source_hash:
@@ -319,6 +401,9 @@ def main():
     if not args.no_batched:
         line["batched"] = batched_measurement(pc, synth, args.batched_scale)
         line["path"] = path_measurement(pc, d)
+    if not args.no_serving:
+        line["serving"] = serving_measurement(pc, synth, args.serving_scale,
+                                              args.serving_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds, settings)
     print(json.dumps(line), flush=True)

@@ -239,17 +239,20 @@ typedef struct {
   pcdn_tune_point tried[8];
 } pcdn_tune;
 
-/* Choose the bundle size P (and the schedule, when opts->schedule is
- * PCDN_SCHED_AUTO) for solving the loaded problem with (loss, C, eps), by
- * the pilot procedure of Sec. 5.1 ("Bundle Size Choice"): candidates around
- * the paper's starting point of about 5% of the features (P0 * 4^k,
- * k = -3..2, clipped to [1, p]); each runs a pilot of three outer iterations
- * from the start pcdn_solve would use; the time per outer iteration and the
- * decay rate of the stopping norm (iterations 2-3, as eq. (15) separates the
- * per-iteration cost from the number of iterations) predict the time to reach
- * eps; the smallest prediction wins (a pilot that already meets eps counts
- * with its measured time).  The context's device state afterwards is the
- * last pilot's.  Returns PCDN_OK or an error. */
+/* Choose the bundle size P (and with it the schedule, when opts->schedule
+ * is PCDN_SCHED_AUTO) for solving the loaded problem with (loss, C, eps) by
+ * the pilot procedure of Sec. 5.1 ("Bundle Size Choice"): the paper starts
+ * at about 5% of the features, P0 = 0.05 p, and adjusts P by measured
+ * runtime.  Candidates P0 * 4^k for k = 0, -1, 1, -2, 2, -3 (clipped to
+ * [1, p]) are tried in that order; each pilot is the solve itself, from the
+ * start pcdn_solve would use, to the target eps (graphs captured before the
+ * clock starts), and a pilot is abandoned as soon as it has run longer than
+ * the fastest finished one.  The fastest finished candidate wins (if none
+ * finishes within max_outer, the one with the largest decrease of the
+ * stopping norm per second).  tried[] reports every pilot
+ * (predicted_seconds: its measured time, INFINITY if it did not finish).
+ * The context's device state afterwards is the last pilot's.  Returns
+ * PCDN_OK or an error. */
 int pcdn_autotune(pcdn_ctx* ctx, int loss, double C, double eps, const pcdn_opts* opts,
                   pcdn_tune* out);
 

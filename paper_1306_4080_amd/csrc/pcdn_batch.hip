@@ -614,19 +614,21 @@ extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const 
   if (rc) return rc;
   std::memset(out, 0, sizeof(*out));
   const int64_t p = c->p;
-  // the paper's pilot start: about 5% of the features
+  // the paper's pilot start, about 5% of the features, then its neighbours
+  // on a factor-4 ladder, nearest first
   const int64_t P0 = std::max<int64_t>(1, std::llround(0.05 * (double)p));
   std::vector<int64_t> cands;
-  for (int k = -3; k <= 2; ++k) {
+  for (const int k : {0, -1, 1, -2, 2, -3}) {
     const double v = (double)P0 * std::pow(4.0, k);
     const int64_t P = std::min<int64_t>(p, std::max<int64_t>(1, std::llround(v)));
     if (std::find(cands.begin(), cands.end(), P) == cands.end()) cands.push_back(P);
   }
-  // a target below the rounding floor cannot be predicted; eps = 0 tunes for 1e-12
-  const double eps_eff = std::max(eps, 1e-12);
-  constexpr int kPilot = 3;
   using clock = std::chrono::steady_clock;
-  double best = INFINITY, best_speed = -1.0;
+  double best = INFINITY;          // fastest finished pilot
+  double best_progress = -1.0;     // fallback when none finishes: log-decrease per second
+  out->P = P0;
+  out->schedule = use_narrow(c, o, P0) ? PCDN_SCHED_NARROW : PCDN_SCHED_WIDE;
+  out->predicted_seconds = INFINITY;
   for (const int64_t P : cands) {
     SolveRun r;
     r.o = o;
@@ -647,45 +649,44 @@ extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const 
       out->predicted_seconds = 0.0;
       return PCDN_OK;
     }
-    // iteration 1 pays for graph capture; iterations 2.. are timed
-    double G1 = 0.0, timed = 0.0, total = 0.0;
-    for (int k = 0; k < kPilot && !r.converged && r.outer < o.max_outer; ++k) {
-      const auto t0 = clock::now();
-      rc = run_outer(c, o, P, r.outer, 1);
+    if (c->use_graphs && c->prof.mask == 0) {  // capture outside the timed pilot
+      rc = ensure_graph(c, r.o, P);
+      if (rc) return rc;
+    }
+    bool pruned = false;
+    const auto t0 = clock::now();
+    double elapsed = 0.0;
+    while (!r.converged && r.outer < o.max_outer) {
+      rc = run_outer(c, r.o, P, r.outer, 1);
       if (rc) return rc;
       double G = 0.0;
       rc = read_scalar(c, 0, &G);
       if (rc) return rc;
       rc = solve_note_outer(r, G);
       if (rc) return rc;
-      const double dt = std::chrono::duration<double>(clock::now() - t0).count();
-      total += dt;
-      if (k == 0)
-        G1 = G;
-      else
-        timed += dt;
+      elapsed = std::chrono::duration<double>(clock::now() - t0).count();
+      if (!r.converged && elapsed > best) {  // already slower than the best finished pilot
+        pruned = true;
+        break;
+      }
     }
     tp.outer = r.outer;
-    tp.sec_per_outer = r.outer > 1 ? timed / (r.outer - 1) : total;
-    tp.rate = (r.outer > 1 && G1 > 0.0 && r.G > 0.0) ? (std::log(G1) - std::log(r.G)) / (r.outer - 1)
-                                                    : 0.0;
-    if (r.G <= eps_eff * r.G0) {
-      tp.predicted_seconds = total;
-    } else if (tp.rate > 0.0) {
-      const double more = std::log(r.G / (eps_eff * r.G0)) / tp.rate;
-      tp.predicted_seconds = total + more * tp.sec_per_outer;
-    } else {
-      tp.predicted_seconds = INFINITY;
-    }
-    // ties (all unpredictable) go to the fastest decay per second
-    const double speed = tp.sec_per_outer > 0.0 ? tp.rate / tp.sec_per_outer : 0.0;
-    if (tp.predicted_seconds < best ||
-        (!std::isfinite(best) && !std::isfinite(tp.predicted_seconds) && speed > best_speed)) {
-      best = tp.predicted_seconds;
-      best_speed = speed;
+    tp.sec_per_outer = r.outer > 0 ? elapsed / r.outer : 0.0;
+    tp.rate = (r.outer > 0 && r.G > 0.0) ? std::log(r.G0 / r.G) / r.outer : 0.0;
+    tp.predicted_seconds = r.converged ? elapsed : INFINITY;
+    if (r.converged && elapsed < best) {
+      best = elapsed;
       out->P = P;
       out->schedule = tp.schedule;
-      out->predicted_seconds = tp.predicted_seconds;
+      out->predicted_seconds = elapsed;
+    } else if (!std::isfinite(best) && !pruned) {
+      // nothing has finished yet: keep the candidate that went furthest per second
+      const double progress = elapsed > 0.0 ? std::log(r.G0 / std::max(r.G, 1e-300)) / elapsed : 0.0;
+      if (progress > best_progress) {
+        best_progress = progress;
+        out->P = P;
+        out->schedule = tp.schedule;
+      }
     }
   }
   return PCDN_OK;

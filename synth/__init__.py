@@ -297,3 +297,64 @@ def c4b(seed: int = BASE_SEED + 4, count: int = 64, scale: float = 1.0) -> list:
     bernoulli_csc with its own seed."""
     return [bernoulli_csc(seed * 1000 + i, n, p, d)
             for i, (n, p, d) in enumerate(c4b_shapes(seed, count, scale))]
+
+
+def zipf_rows_csc(seed: int, n: int, p: int, row_lo: int, row_hi: int, a: float,
+                  binary: bool, flip: float = 0.05, w_nnz: int = 500) -> Data:
+    """Rows of U{row_lo..row_hi} entries whose columns follow a truncated
+    Zipf(a) over p (column ranks mapped through a random permutation); a
+    column drawn twice in one row is kept once.  Values: 1 (binary) or
+    lognormal(0, 1) L2-normalised per row.  Labels y = sign(x^T w*) with
+    min(w_nnz, p / 10) N(0, 1) nonzeros in w*, ties to a coin, `flip` flipped.
+    Drawn in column-major order (CSC without a re-sort)."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(row_lo, row_hi + 1, size=n)
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    cdf = _zipf_cdf(p, a)
+    ranks = np.minimum(np.searchsorted(cdf, rng.random(len(rows)), side="right"), p - 1)
+    cols = rng.permutation(p)[ranks].astype(np.int64)
+    pos = np.unique(cols * n + rows)
+    cols = pos // n
+    rows = (pos - cols * n).astype(np.int32)
+    del pos
+    if binary:
+        val = np.ones(len(rows), dtype=np.float32)
+    else:
+        v = rng.lognormal(0.0, 1.0, len(rows))
+        norm = np.sqrt(np.bincount(rows, weights=v * v, minlength=n))
+        val = (v / norm[rows]).astype(np.float32)
+    col_ptr = np.zeros(p + 1, dtype=np.int64)
+    np.cumsum(np.bincount(cols, minlength=p), out=col_ptr[1:])
+    w_star = np.zeros(p)
+    k = max(1, min(w_nnz, p // 10))
+    w_star[rng.choice(p, k, replace=False)] = rng.standard_normal(k)
+    y = _labels_from_scores(rng, _row_scores(n, rows, cols, val, w_star), flip)
+    return Data(n=n, p=p, col_ptr=col_ptr, row_idx=rows, val=val, y=y, w_star=w_star,
+                meta=dict(name="zipf_rows", binary=binary))
+
+
+def c5_pool(seed: int = BASE_SEED + 5, count: int = 16, scale: float = 1.0) -> list:
+    """Pool of served problems: LR or SVM with probability 1/2; n log-uniform
+    in [1e3, 2e5 * scale], p log-uniform in [1e3, 2e6 * scale], U{20..150}
+    entries per row over Zipf(1.1) columns; LR values lognormal and
+    row-normalised, SVM values binary.  Returns (data, loss) pairs."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        loss = "lr" if rng.random() < 0.5 else "svm"
+        n = int(np.exp(rng.uniform(np.log(1e3), np.log(max(1e3, 2e5 * scale)))))
+        p = int(np.exp(rng.uniform(np.log(1e3), np.log(max(1e3, 2e6 * scale)))))
+        out.append((zipf_rows_csc(seed * 100 + i, n, p, 20, 150, 1.1, binary=(loss == "svm")),
+                    loss))
+    return out
+
+
+def c5_stream(seed: int = BASE_SEED + 6, count: int = 500, rate: float = 50.0,
+              pool: int = 16) -> list:
+    """Poisson arrivals at `rate` per second: (arrival time in s, pool index,
+    C log-uniform in [0.1, 10])."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    idx = rng.integers(0, pool, size=count)
+    C = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=count))
+    return [(float(t[k]), int(idx[k]), float(C[k])) for k in range(count)]
