@@ -228,7 +228,7 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
         s.close()
     # served
     srv = pc.Server(device=0, budget_bytes=64 << 30)
-    arrival, finish, F_srv = {}, {}, {}
+    arrival, finish, F_srv, st_srv = {}, {}, {}, {}
     out = {}
     k = 0
     t0 = time.perf_counter()
@@ -252,12 +252,13 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
             if r is not None:
                 finish[out[rid]] = time.perf_counter() - t0
                 F_srv[out[rid]] = r[2]["objective"]
+                st_srv[out[rid]] = r[0]
     srv.close()
     lat_srv = [finish[q] - arrival[q] for q in range(len(stream))]
     span_srv = max(finish.values()) - stream[0][0]
     # plain: one request at a time, in arrival order
     s = pc.Solver(device=0)
-    F_plain, lat_plain = {}, []
+    F_plain, st_plain, lat_plain = {}, {}, []
     t0 = time.perf_counter()
     for q, (t_arr, i, C) in enumerate(stream):
         now = time.perf_counter() - t0
@@ -265,19 +266,23 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
             time.sleep(t_arr - now)
         d, loss = pool[i]
         s.load_data(d)
-        _, _, info = s.solve(C, Ps[i], 1e-4, loss, seed=SEED)
+        st_plain[q], _, info = s.solve(C, Ps[i], 1e-4, loss, seed=SEED)
         F_plain[q] = info["objective"]
         lat_plain.append(time.perf_counter() - t0 - t_arr)
     span_plain = time.perf_counter() - t0 - stream[0][0]
     s.close()
-    worst = max(abs(F_srv[q] - F_plain[q]) / abs(F_plain[q]) for q in range(len(stream)))
+    both = [q for q in range(len(stream)) if st_srv[q] == 0 and st_plain[q] == 0]
+    gap = lambda qs: max((abs(F_srv[q] - F_plain[q]) / abs(F_plain[q]) for q in qs), default=0.0)
     return {"workload": f"{len(stream)} requests, Poisson 50/s, pool of {len(pool)} problems "
                         f"(LR/SVM 1:1, n log-U[1e3, {2e5 * scale:.0f}], p log-U[1e3, "
                         f"{2e6 * scale:.0f}], U{{20..150}} nnz/row, Zipf(1.1) columns), "
                         f"C log-U[0.1, 10], eps=1e-4, autotuned P per pool problem",
             "served": dict(_percentiles(lat_srv), solves_per_s=len(stream) / span_srv),
             "plain": dict(_percentiles(lat_plain), solves_per_s=len(stream) / span_plain),
-            "max_rel_objective_gap": worst,
+            "converged": {"served": sum(v == 0 for v in st_srv.values()),
+                          "plain": sum(v == 0 for v in st_plain.values())},
+            "max_rel_objective_gap_converged": gap(both),
+            "max_rel_objective_gap_all": gap(range(len(stream))),
             "nnz_mean": float(np.mean([d.nnz for d, _ in pool]))}
 
 
