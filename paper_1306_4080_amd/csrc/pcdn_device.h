@@ -24,7 +24,7 @@ namespace pcdn {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kChunk = 1024;   // nonzeros per wavefront work item
+constexpr int kChunk = 128;    // nonzeros per wavefront work item
 constexpr int kQMax = 32;      // line-search candidates evaluated per pass
 constexpr int kQGroup = 4;     // candidates per line-search thread (grid y covers the rest)
 constexpr int kLsGrid = 256;   // blocks of the line-search kernel (at most)

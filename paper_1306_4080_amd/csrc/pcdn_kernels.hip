@@ -291,6 +291,34 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t* block_tot
   if (threadIdx.x == 0) *out_total = tot;
 }
 
+// Whole scan in one block when m <= kScanSmall: thread t scans a contiguous
+// chunk of ceil(m / 1024) items (in and out may alias: a thread reads its
+// whole chunk before the block scan's barriers and writes it afterwards).
+constexpr int64_t kScanSmall = 16 * kScanThreads;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_small(const int32_t* in, int32_t* out,
+                                                             int64_t m) {
+  __shared__ int32_t lds[kScanThreads / kWave + 1];
+  const int64_t per = (m + kScanThreads - 1) / kScanThreads;
+  const int64_t lo = (int64_t)threadIdx.x * per;
+  const int64_t hi = lo + per < m ? lo + per : m;
+  int32_t v[16];
+  int32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    v[k] = lo + k < hi ? in[lo + k] : 0;
+    s += v[k];
+  }
+  int32_t tot;
+  int32_t run = block_exclusive_scan(s, lds, &tot);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (lo + k < hi) out[lo + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) out[m] = tot;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t m,
                                                            const int32_t* block_tot) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
@@ -307,7 +335,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t
 // from per-digit running offsets in LDS.
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 16;
+constexpr int kSortRounds = 4;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* keys, int64_t p,
@@ -1296,6 +1324,10 @@ int64_t scan_tmp_ints(int64_t m) { return (m + kScanTile - 1) / kScanTile + 1; }
 int64_t radix_hist_ints(int64_t p) { return 256 * ((p + kSortTile - 1) / kSortTile) + 1; }
 
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s) {
+  if (m >= 1 && m <= kScanSmall) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanThreads), 0, s, in, out, m);
+    return hipGetLastError();
+  }
   const int64_t nb = (m + kScanTile - 1) / kScanTile;
   if (nb < 1) {
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tmp, (int64_t)0,
