@@ -13,11 +13,16 @@ stopping test), continuing each setting's trajectory from w = 0 (the warmup
 steps are the first iterations).  value = bundle-sweep nonzeros processed per
 second over the timed steps.
 
-The timed region (A) replays the library's captured HIP graphs without
-instrumentation.  A second region (B) runs the next `steps` outer iterations
-with every kernel launch bracketed by HIP events on the library's stream; the
-roofline object reports the kernel class with the most time there
-(algorithmic bytes per launch / average launch duration).
+The timed region (A) runs the steps through pcdn_iterate_batch: each step is
+one round of the batch engine, in which the six settings' outer iterations
+run concurrently (the two single-workgroup settings in one launch, the four
+multi-kernel settings through the lock-step executor), without
+instrumentation.  Region A2 runs the next steps one setting after another
+(pcdn_iterate, replayed graphs) and is reported as "sequential", with the
+per-setting times.  Region B runs the next steps with every kernel launch
+bracketed by HIP events on the library's stream; the roofline object reports
+the kernel class with the most time there (algorithmic bytes per launch /
+average launch duration).
 The FP64 CPU oracle is timed on a bounded sample of the same workload.
 
 Two more objects on the same line (skipped with --no-batched):
@@ -325,20 +330,27 @@ def main():
             s.iterate(P, k, 1, want_subgrad=True, seed=SEED)
     torch.cuda.synchronize()
 
-    # timed region A: graph replays, no instrumentation
+    # timed region A: the settings' outer iterations concurrently, one engine
+    # round per step, no instrumentation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pc.iterate_batch([s for s, _, _ in solvers], [P for _, _, P in solvers], args.warmup,
+                     args.steps, seed=SEED)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nnz_total = d.nnz * len(settings) * args.steps
+    value = nnz_total / elapsed
+    # region A2: the next steps one setting after another (graph replays)
     per_setting = {f"C={C},P={P}": 0.0 for _, C, P in solvers}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(args.steps):
         for s, C, P in solvers:
             ts = time.perf_counter()
-            s.iterate(P, args.warmup + step, 1, want_subgrad=True, seed=SEED)
+            s.iterate(P, args.warmup + args.steps + step, 1, want_subgrad=True, seed=SEED)
             per_setting[f"C={C},P={P}"] += time.perf_counter() - ts
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    nnz_total = d.nnz * len(settings) * args.steps
-    value = nnz_total / elapsed
+    elapsed_seq = time.perf_counter() - t0
 
     # timed region B: the next `steps` outer iterations with every kernel class
     # bracketed by HIP events on the library's stream (launched directly, not
@@ -349,7 +361,7 @@ def main():
     tb0 = time.perf_counter()
     for step in range(args.steps):
         for s, C, P in solvers:
-            s.iterate(P, args.warmup + args.steps + step, 1, want_subgrad=True, seed=SEED)
+            s.iterate(P, args.warmup + 2 * args.steps + step, 1, want_subgrad=True, seed=SEED)
     tb1 = time.perf_counter()
     kernels = {}
     totals = {}
@@ -399,6 +411,8 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6, "launches": int(dom_n),
                      "measured": "HIP events in timed region B (the next steps after region A)",
                      "region_b_ms_per_step": 1e3 * (tb1 - tb0) / args.steps},
+        "sequential": {"value": nnz_total / elapsed_seq, "ms_per_step": 1e3 * elapsed_seq / args.steps,
+                       "measured": "region A2: the next steps, one setting after another"},
         "per_setting_ms_per_iter": {k: 1e3 * v / args.steps for k, v in per_setting.items()},
         "kernels": kernels,
         "objective_after": F,

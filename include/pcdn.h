@@ -211,6 +211,16 @@ const char* pcdn_server_last_error(const pcdn_server* s);
 /* Release the server, its queue and every admitted solve.  NULL is accepted. */
 int pcdn_server_destroy(pcdn_server* s);
 
+/* Continue the current states of several contexts on one device together:
+ * for each context j, what pcdn_iterate(ctxs[j], P[j], k_first, iters, opts,
+ * &subgrads[j]) does (outer iterations k_first .. k_first+iters-1 of
+ * Algorithm 3 from the state left by pcdn_reset, pcdn_solve or earlier
+ * iterations, no stopping test), advanced in the rounds of pcdn_solve_batch.
+ * iters >= 1; subgrads (nullable, count entries) receives each context's
+ * ||grad^S F(w)||_1 after its last iteration. */
+int pcdn_iterate_batch(pcdn_ctx* const* ctxs, const int64_t* P, int32_t count, int64_t k_first,
+                       int64_t iters, const pcdn_opts* opts, double* subgrads);
+
 /* Regularisation path: pcdn_solve for C = Cs[0], Cs[1], ... in order, each
  * warm-started from the previous solution (the first from opts->w0, or 0),
  * with the reference norm of the stopping rule at w = 0 for every C.  W_out

@@ -32,7 +32,7 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
 # entry points declared in include/pcdn.h
 SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
            "pcdn_iterate",
-           "pcdn_solve_batch", "pcdn_solve_path", "pcdn_autotune",
+           "pcdn_solve_batch", "pcdn_solve_path", "pcdn_autotune", "pcdn_iterate_batch",
            "pcdn_server_create", "pcdn_server_submit", "pcdn_server_step", "pcdn_server_status",
            "pcdn_server_take", "pcdn_server_last_error", "pcdn_server_destroy",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
@@ -122,6 +122,8 @@ def load_library(path: str = LIB_PATH):
                             ctypes.POINTER(pcdn_step_info), vp, vp, vp, vp]
     L.pcdn_iterate.argtypes = [vp, i64, i64, i64, ctypes.POINTER(pcdn_opts), vp]
     L.pcdn_solve_batch.argtypes = [ctypes.POINTER(pcdn_job), ctypes.c_int32]
+    L.pcdn_iterate_batch.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.c_int32, i64,
+                                     i64, ctypes.POINTER(pcdn_opts), ctypes.POINTER(dbl)]
     L.pcdn_autotune.argtypes = [vp, i32, dbl, dbl, ctypes.POINTER(pcdn_opts),
                                 ctypes.POINTER(pcdn_tune)]
     L.pcdn_solve_path.argtypes = [vp, ctypes.POINTER(dbl), ctypes.c_int32, i64, dbl, i32,
@@ -275,6 +277,25 @@ def pcdn_autotune(ctx, C, eps, loss, **opts) -> dict:
              for k in range(t.n_tried)]
     return {"P": t.P, "schedule": t.schedule, "predicted_seconds": t.predicted_seconds,
             "tried": tried}
+
+
+def pcdn_iterate_batch(ctxs, Ps, k_first, iters, **opts):
+    """Outer iterations of several contexts' current states together;
+    returns each one's stopping norm after the last iteration."""
+    n = len(ctxs)
+    arr = (ctypes.c_void_p * max(n, 1))(*[c.value if hasattr(c, "value") else c for c in ctxs])
+    P = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in Ps])
+    G = (ctypes.c_double * max(n, 1))()
+    o, keep = _opts(**opts)
+    rc = load_library().pcdn_iterate_batch(arr, P, n, int(k_first), int(iters), ctypes.byref(o), G)
+    if rc != PCDN_OK:
+        _check(ctxs[0] if n else None, rc)
+    return [G[k] for k in range(n)]
+
+
+def iterate_batch(solvers, Ps, k_first, iters, **opts):
+    """pcdn_iterate_batch over Solver objects."""
+    return pcdn_iterate_batch([s.ctx for s in solvers], Ps, k_first, iters, **opts)
 
 
 def pcdn_solve_path(ctx, Cs, P, eps, loss, p, **opts):

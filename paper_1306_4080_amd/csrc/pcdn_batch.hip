@@ -32,6 +32,8 @@ struct EngineJob {
   hipEvent_t pre_done = nullptr;
   bool active = false;
   int64_t id = 0;                // owner's handle
+  bool resume = false;           // continue the context's state (no set-up, no stopping rule)
+  int64_t k_first = 0;           // first outer-iteration index when resuming
 };
 
 // Grow-only device + pinned buffer pair.
@@ -72,23 +74,30 @@ class Engine {
 
   ~Engine() {
     (void)hipSetDevice(device_);
-    if (narrow_stream_) (void)hipStreamSynchronize(narrow_stream_);
+    for (hipStream_t st : narrow_stream_)
+      if (st) (void)hipStreamSynchronize(st);
     if (wide_stream_) (void)hipStreamSynchronize(wide_stream_);
     for (EngineJob* j : jobs_) drop_event(j);
-    if (fused_done_) (void)hipEventDestroy(fused_done_);
+    for (hipEvent_t e : fused_done_)
+      if (e) (void)hipEventDestroy(e);
+    if (table_ready_) (void)hipEventDestroy(table_ready_);
     narrow_tab_.release();
     exec_.release();
     gather_.release();
-    if (narrow_stream_) (void)hipStreamDestroy(narrow_stream_);
+    for (hipStream_t st : narrow_stream_)
+      if (st) (void)hipStreamDestroy(st);
     if (wide_stream_) (void)hipStreamDestroy(wide_stream_);
   }
 
   int init(int device) {
     device_ = device;
     if (hipSetDevice(device) != hipSuccess ||
-        hipStreamCreateWithFlags(&narrow_stream_, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&narrow_stream_[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&narrow_stream_[1], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&wide_stream_, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&fused_done_, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&fused_done_[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&fused_done_[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&table_ready_, hipEventDisableTiming) != hipSuccess)
       return dev_fail("engine set-up", hipGetLastError());
     return PCDN_OK;
   }
@@ -101,8 +110,16 @@ class Engine {
   // whether it needs rounds (it joins the engine then).
   int add(EngineJob* j) {
     SolveRun& r = j->run;
-    int rc = solve_begin(r);
-    if (rc) return rc;
+    int rc = PCDN_OK;
+    if (j->resume) {  // iterations only: run.o.max_outer of them, no stopping test
+      r.converged = false;
+      r.outer = 0;
+      r.G0 = 1.0;
+      r.eps = -1.0;
+    } else {
+      rc = solve_begin(r);
+      if (rc) return rc;
+    }
     j->narrow = use_narrow(r.c, r.o, r.P);
     rc = ensure_split_graphs(r.c, r.o, r.P);
     if (rc) return rc;
@@ -110,7 +127,7 @@ class Engine {
       rc = outer_tasks(r.c, r.o, r.P, j->tasks);
       if (rc) return rc;
     }
-    rc = set_iter(r.c, r.o.seed, 0);
+    rc = set_iter(r.c, r.o.seed, j->resume ? j->k_first : 0);
     if (rc) return rc;
     j->active = !r.converged && r.outer < r.o.max_outer;
     if (!j->active) return PCDN_OK;
@@ -131,39 +148,51 @@ class Engine {
     if (hipSetDevice(device_) != hipSuccess) return dev_fail("hipSetDevice", hipGetLastError());
     int rc = plan_stale_ ? build_plan() : PCDN_OK;
     if (rc) return rc;
-    // partitions, each on its job's stream
-    size_t m = 0;
-    for (EngineJob* j : jobs_) if (j->narrow) ++m;
+    // partitions, each on its job's stream; the single-workgroup jobs'
+    // table lists the logistic jobs first, then the SVM jobs (one launch each)
+    size_t m = 0, m_lr = 0;
+    for (EngineJob* j : jobs_)
+      if (j->narrow) {
+        ++m;
+        m_lr += j->run.loss == PCDN_LOSS_LOGISTIC ? 1 : 0;
+      }
     if (narrow_tab_.reserve(sizeof(NarrowArgs) * m) != hipSuccess)
       return dev_fail("table allocation", hipErrorOutOfMemory);
     NarrowArgs* htab = (NarrowArgs*)narrow_tab_.host;
-    m = 0;
+    size_t at[2] = {0, m_lr};
     for (EngineJob* j : jobs_) {
       pcdn_ctx* c = j->run.c;
       *err_ctx = c;
+      const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
       HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
       HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
-      HIPCHK(c, hipStreamWaitEvent(j->narrow ? narrow_stream_ : wide_stream_, j->pre_done, 0));
+      HIPCHK(c, hipStreamWaitEvent(j->narrow ? narrow_stream_[g] : wide_stream_, j->pre_done, 0));
       if (j->narrow) {
         const int64_t nb = (c->p + j->run.P - 1) / j->run.P;
-        htab[m++] = make_narrow_args(c, j->run.o, c->idx0, c->p, j->run.P, 0, nb, nullptr);
+        htab[at[g]++] = make_narrow_args(c, j->run.o, c->idx0, c->p, j->run.P, 0, nb, nullptr);
       }
       count_outer(c, j->run.o, j->run.P, 1);
     }
     *err_ctx = nullptr;
-    // single-workgroup jobs: one launch, then each job's stopping sweep
+    // single-workgroup jobs: one launch per loss, then each job's stopping sweep
     if (m > 0) {
+      const NarrowArgs* dtab = (const NarrowArgs*)narrow_tab_.dev;
       hipError_t e = hipMemcpyAsync(narrow_tab_.dev, htab, sizeof(NarrowArgs) * m,
-                                    hipMemcpyHostToDevice, narrow_stream_);
-      if (e == hipSuccess) e = launch_narrow_multi((const NarrowArgs*)narrow_tab_.dev, (int)m,
-                                                   narrow_stream_);
-      if (e == hipSuccess) e = hipEventRecord(fused_done_, narrow_stream_);
+                                    hipMemcpyHostToDevice, narrow_stream_[0]);
+      if (e == hipSuccess) e = hipEventRecord(table_ready_, narrow_stream_[0]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(narrow_stream_[1], table_ready_, 0);
+      if (e == hipSuccess) e = launch_narrow_multi(kLogistic, dtab, (int)m_lr, narrow_stream_[0]);
+      if (e == hipSuccess)
+        e = launch_narrow_multi(kL2Svm, dtab + m_lr, (int)(m - m_lr), narrow_stream_[1]);
+      if (e == hipSuccess) e = hipEventRecord(fused_done_[0], narrow_stream_[0]);
+      if (e == hipSuccess) e = hipEventRecord(fused_done_[1], narrow_stream_[1]);
       if (e != hipSuccess) return dev_fail("multi-problem launch", e);
       for (EngineJob* j : jobs_) {
         if (!j->narrow) continue;
         pcdn_ctx* c = j->run.c;
         *err_ctx = c;
-        HIPCHK(c, hipStreamWaitEvent(c->stream, fused_done_, 0));
+        const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
+        HIPCHK(c, hipStreamWaitEvent(c->stream, fused_done_[g], 0));
         HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
@@ -187,7 +216,8 @@ class Engine {
       if (e != hipSuccess) return dev_fail("gather", e);
     }
     // the staging tables and every pinned result are reused next round
-    hipError_t e = hipStreamSynchronize(narrow_stream_);
+    hipError_t e = hipStreamSynchronize(narrow_stream_[0]);
+    if (e == hipSuccess) e = hipStreamSynchronize(narrow_stream_[1]);
     if (e == hipSuccess) e = hipStreamSynchronize(wide_stream_);
     if (e != hipSuccess) return dev_fail("round", e);
     for (size_t k = 0; k < plan_jobs_.size(); ++k)
@@ -216,9 +246,10 @@ class Engine {
 
  private:
   int device_ = 0;
-  hipStream_t narrow_stream_ = nullptr;  // the multi-problem single-workgroup launch
-  hipStream_t wide_stream_ = nullptr;    // the executor launches
-  hipEvent_t fused_done_ = nullptr;
+  hipStream_t narrow_stream_[2] = {nullptr, nullptr};  // single-workgroup launches, per loss
+  hipStream_t wide_stream_ = nullptr;                  // the executor launches
+  hipEvent_t fused_done_[2] = {nullptr, nullptr};
+  hipEvent_t table_ready_ = nullptr;
   std::vector<EngineJob*> jobs_;
   Staging narrow_tab_, exec_, gather_;
   bool plan_stale_ = true;
@@ -351,6 +382,52 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
     if (rc < 0 && first_err == PCDN_OK) first_err = rc;
   }
   return first_err;
+}
+
+extern "C" int pcdn_iterate_batch(pcdn_ctx* const* ctxs, const int64_t* P, int32_t count,
+                                  int64_t k_first, int64_t iters, const pcdn_opts* opts,
+                                  double* subgrads) {
+  if (count == 0) return PCDN_OK;
+  if (!ctxs || !P || count < 0) return PCDN_E_ARG;
+  std::vector<EngineJob> ej(count);
+  for (int32_t i = 0; i < count; ++i) {
+    pcdn_ctx* c = ctxs[i];
+    if (!c) return PCDN_E_ARG;
+    for (int32_t k = 0; k < i; ++k)
+      if (ctxs[k] == c) return fail(c, PCDN_E_ARG, "a context appears twice");
+    if (c->device != ctxs[0]->device)
+      return fail(c, PCDN_E_ARG, "the contexts must share one device");
+    if (!c->loaded || !c->has_state) return fail(c, PCDN_E_STATE, "call pcdn_reset or pcdn_solve first");
+    if (P[i] < 1 || P[i] > c->p) return fail(c, PCDN_E_ARG, "bundle size P must lie in [1, p]");
+    if (k_first < 0 || iters < 1 || iters > (1 << 30))
+      return fail(c, PCDN_E_ARG, "k_first must be >= 0 and iters in [1, 2^30]");
+    SolveRun& r = ej[i].run;
+    const int rc = resolve_opts(c, opts, &r.o);
+    if (rc) return rc;
+    r.o.max_outer = (int)iters;
+    r.c = c;
+    r.C = c->C;
+    r.P = P[i];
+    r.loss = c->loss;
+    ej[i].resume = true;
+    ej[i].k_first = k_first;
+  }
+  Engine eng;
+  int rc = eng.init(ctxs[0]->device);
+  if (rc) return fail(ctxs[0], rc, eng.err);
+  for (int32_t i = 0; i < count; ++i) {
+    rc = eng.add(&ej[i]);
+    if (rc) return rc;
+  }
+  std::vector<EngineJob*> done;
+  while (eng.size() > 0) {
+    pcdn_ctx* ec = nullptr;
+    rc = eng.round(done, &ec);
+    if (rc) return ec ? rc : fail(ctxs[0], rc, eng.err);
+  }
+  if (subgrads)
+    for (int32_t i = 0; i < count; ++i) subgrads[i] = ej[i].run.G;
+  return PCDN_OK;
 }
 
 // ===========================================================================

@@ -230,8 +230,8 @@ hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int b
                        hipStream_t s);
 // dst[i] = *src[i] for i < count (device pointers).
 hipError_t launch_gather(const double* const* src, double* dst, int count, hipStream_t s);
-// One workgroup per entry of the device table tab[0..count).
-hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s);
+// One workgroup per entry of the device table tab[0..count), all of one loss.
+hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipStream_t s);
 // X in partition order for the single-workgroup schedule (needs nnz < 2^31).
 // `chunks`/`cstart` are the chunk descriptors of the same slot order.
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,

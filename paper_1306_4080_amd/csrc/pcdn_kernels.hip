@@ -1131,15 +1131,15 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
   narrow_body<LOSS>(na, L);
 }
 
-// Independent problems in one launch: workgroup b runs the bundles of
-// problem tab[b] (each with its own loss, data and state).
-__global__ __launch_bounds__(kNarrowBlock) void k_narrow_multi(const NarrowArgs* tab) {
+// Independent problems of one loss in one launch: workgroup b runs the
+// bundles of problem tab[b] (its own data and state).
+template <int LOSS>
+__global__ __launch_bounds__(kNarrowBlock) void k_narrow_multi(const NarrowArgs* __restrict__ tab) {
   __shared__ NarrowLds L;
-  const NarrowArgs& na = tab[blockIdx.x];
-  if (na.loss == kLogistic)
-    narrow_body<kLogistic>(na, L);
-  else
-    narrow_body<kL2Svm>(na, L);
+  // a private copy: the kernel stores to global memory, so fields read
+  // through the table could otherwise be re-read after stores
+  const NarrowArgs na = tab[blockIdx.x];
+  narrow_body<LOSS>(na, L);
 }
 
 // Copy X into partition order: the nonzeros of slot r land at
@@ -1236,8 +1236,10 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_exec(const Task* tasks, const int32_t* first,
-                                                 int count) {
+// The tables are not written by any task (__restrict__), so task fields
+// read once can stay in registers across the bodies' stores.
+__global__ __launch_bounds__(kBlock) void k_exec(const Task* __restrict__ tasks,
+                                                 const int32_t* __restrict__ first, int count) {
   const int b = blockIdx.x;
   const int i = task_of_block(first, count, b);
   const Task& t = tasks[i];
@@ -1479,9 +1481,12 @@ hipError_t launch_gather(const double* const* src, double* dst, int count, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s) {
+hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_narrow_multi, dim3(count), dim3(kNarrowBlock), 0, s, tab);
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_narrow_multi<kLogistic>, dim3(count), dim3(kNarrowBlock), 0, s, tab);
+  else
+    hipLaunchKernelGGL(k_narrow_multi<kL2Svm>, dim3(count), dim3(kNarrowBlock), 0, s, tab);
   return hipGetLastError();
 }
 

@@ -235,3 +235,30 @@ def test_batch_autotuned_jobs(pc):
         _assert_same_run(b, alone)
     for s in solvers:
         s.close()
+
+
+def test_iterate_batch_matches_sequential_and_oracle(pc):
+    """pcdn_iterate_batch continues several contexts' states together (both
+    schedules, both losses); each ends where pcdn_iterate alone ends, and
+    where the oracle's first outer iterations end."""
+    c1 = synth.c1()
+    rnd = synth.bernoulli_csc(77, 1200, 3000, 0.01)
+    cases = [(c1, "lr", 1.0, 32), (c1, "svm", 0.5, 100), (rnd, "lr", 2.0, 600),
+             (rnd, "svm", 1.0, 64)]
+    iters = 5
+    a = [pc.Solver(device=0).load_data(d) for d, *_ in cases]
+    b = [pc.Solver(device=0).load_data(d) for d, *_ in cases]
+    for s, (d, loss, C, P) in zip(a + b, cases + cases):
+        s.reset(loss, C)
+    G_batch = pc.iterate_batch(a, [P for *_, P in cases], 0, iters, seed=11)
+    for sa, sb, (d, loss, C, P), g in zip(a, b, cases, G_batch):
+        g_alone = sb.iterate(P, 0, iters, seed=11)
+        assert g == pytest.approx(g_alone, rel=1e-9)
+        np.testing.assert_allclose(sa.w(), sb.w(), rtol=1e-9, atol=1e-12)
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss=loss, C=C),
+                                  P=P, eps=0.0, seed=11, max_outer=iters)
+        F, G = sa.evaluate()
+        assert F == pytest.approx(io["objective"], rel=RTOL)
+        assert G == pytest.approx(io["subgrad"], rel=1e-5)
+    for s in a + b:
+        s.close()
