@@ -817,8 +817,14 @@ __device__ inline void block_sums(double (&v)[NV], double (*red)[kNarrowWaves][4
   buf ^= 1;
 }
 
+// d^T x is built with L2 atomics while a stale copy of the line may sit in the
+// CU's L1: read it at workgroup scope, which bypasses L1 and is served by the
+// L2 of this XCD.  The single-workgroup kernel's problem state is touched by
+// no other workgroup while it runs (kernel boundaries make it visible to the
+// rest of the GPU), so workgroup scope suffices; agent scope would also ask
+// for coherence with the other XCDs' L2s and go to the memory side.
 __device__ inline double load_l2(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 struct NarrowLds {
@@ -1088,7 +1094,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           else
             na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sc : -sc);
         }
-        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         na.rowflag[i] = 0u;
       }
     } else {
@@ -1102,7 +1108,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           else
             na.cache[i] -= a.y[i] > 0 ? sc : -sc;
         }
-        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         na.rowflag[i] = 0u;
       }
     }
