@@ -112,6 +112,16 @@ int pcdn_load_csc(pcdn_ctx* ctx, int64_t n, int64_t p, int64_t nnz,
                   const int64_t* col_ptr, const int32_t* row_idx,
                   const float* val, const int8_t* y, int ptr_kind);
 
+/* pcdn_load_csc of X with a bias feature appended: column p (the last of
+ * p + 1) holds the value `bias` (finite, non-zero) in every row, and its
+ * weight is regularised like every other coordinate (the bias term of the
+ * paper's logistic-regression experiments, Sec. 5.2).  w then has p + 1
+ * entries, the bias weight last.  Same checks and ownership as
+ * pcdn_load_csc. */
+int pcdn_load_csc_bias(pcdn_ctx* ctx, int64_t n, int64_t p, int64_t nnz,
+                       const int64_t* col_ptr, const int32_t* row_idx,
+                       const float* val, const int8_t* y, int ptr_kind, float bias);
+
 /* Algorithm 3 (PCDN) with Algorithm 4's line search on the loaded data:
  * for outer iteration k the features are split by a seeded uniform random
  * permutation into ceil(p/P) bundles of P (the last may be smaller), each

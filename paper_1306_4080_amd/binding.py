@@ -30,7 +30,7 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
           "svm": PCDN_LOSS_L2SVM, "l2svm": PCDN_LOSS_L2SVM}
 
 # entry points declared in include/pcdn.h
-SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_solve", "pcdn_reset", "pcdn_step",
+SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_load_csc_bias", "pcdn_solve", "pcdn_reset", "pcdn_step",
            "pcdn_iterate",
            "pcdn_solve_batch", "pcdn_solve_path", "pcdn_autotune", "pcdn_iterate_batch",
            "pcdn_server_create", "pcdn_server_submit", "pcdn_server_step", "pcdn_server_status",
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
                               ctypes.c_uint64, ctypes.c_double)
     L.pcdn_create.argtypes = [ctypes.POINTER(vp), i32, vp]
     L.pcdn_load_csc.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i32]
+    L.pcdn_load_csc_bias.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, i32, ctypes.c_float]
     L.pcdn_solve.argtypes = [vp, dbl, i64, dbl, i32, ctypes.POINTER(pcdn_opts), vp,
                              ctypes.POINTER(pcdn_info)]
     L.pcdn_reset.argtypes = [vp, i32, dbl, vp]
@@ -214,6 +215,20 @@ def pcdn_load_csc(ctx, n, p, col_ptr, row_idx, val, y) -> None:
     nnz = int(col_ptr[-1])
     rc = load_library().pcdn_load_csc(ctx, int(n), int(p), nnz, _ptr(col_ptr), _ptr(row_idx),
                                       _ptr(val), _ptr(y), 1 if on_device else 0)
+    _check(ctx, rc)
+
+
+def pcdn_load_csc_bias(ctx, n, p, col_ptr, row_idx, val, y, bias: float) -> None:
+    """pcdn_load_csc with a constant feature of value `bias` appended."""
+    on_device = hasattr(col_ptr, "is_cuda") and col_ptr.is_cuda
+    if not on_device:
+        col_ptr = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        row_idx = np.ascontiguousarray(row_idx, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.int8)
+    nnz = int(col_ptr[-1])
+    rc = load_library().pcdn_load_csc_bias(ctx, int(n), int(p), nnz, _ptr(col_ptr), _ptr(row_idx),
+                                           _ptr(val), _ptr(y), 1 if on_device else 0, float(bias))
     _check(ctx, rc)
 
 
@@ -402,8 +417,13 @@ class Solver:
         self.n, self.p = int(n), int(p)
         return self
 
-    def load_data(self, d):
-        return self.load(d.n, d.p, d.col_ptr, d.row_idx, d.val, d.y)
+    def load_data(self, d, bias=None):
+        """Load a synth.Data; bias (a number): append the constant feature."""
+        if bias is None:
+            return self.load(d.n, d.p, d.col_ptr, d.row_idx, d.val, d.y)
+        pcdn_load_csc_bias(self.ctx, d.n, d.p, d.col_ptr, d.row_idx, d.val, d.y, bias)
+        self.n, self.p = int(d.n), int(d.p) + 1
+        return self
 
     def solve(self, C, P, eps, loss, **opts):
         return pcdn_solve(self.ctx, C, P, eps, loss, self.p, **opts)

@@ -973,6 +973,37 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   return PCDN_OK;
 }
 
+extern "C" int pcdn_load_csc_bias(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
+                                  const int64_t* col_ptr, const int32_t* row_idx,
+                                  const float* val, const int8_t* y, int ptr_kind, float bias) {
+  if (!c) return PCDN_E_ARG;
+  if (!std::isfinite(bias) || bias == 0.0f) return fail(c, PCDN_E_ARG, "bias must be finite and non-zero");
+  if (n < 1 || p < 1 || n >= (int64_t)1 << 31 || p + 1 >= (int64_t)1 << 31 || nnz < 0)
+    return fail(c, PCDN_E_ARG, "sizes out of range (need 1 <= n, p + 1 < 2^31, nnz >= 0)");
+  if (!col_ptr || !y || (nnz > 0 && (!row_idx || !val))) return fail(c, PCDN_E_ARG, "null array");
+  if (ptr_kind != 0 && ptr_kind != 1) return fail(c, PCDN_E_ARG, "ptr_kind must be 0 or 1");
+  HIPCHK(c, hipSetDevice(c->device));
+  // X with the constant column appended, on the host (checked by pcdn_load_csc)
+  std::vector<int64_t> cp(p + 2);
+  std::vector<int32_t> ri(nnz + n);
+  std::vector<float> v(nnz + n);
+  std::vector<int8_t> hy(n);
+  const hipMemcpyKind kind = ptr_kind == 1 ? hipMemcpyDeviceToHost : hipMemcpyHostToHost;
+  HIPCHK(c, hipMemcpy(cp.data(), col_ptr, (p + 1) * sizeof(int64_t), kind));
+  if (nnz) {
+    HIPCHK(c, hipMemcpy(ri.data(), row_idx, nnz * sizeof(int32_t), kind));
+    HIPCHK(c, hipMemcpy(v.data(), val, nnz * sizeof(float), kind));
+  }
+  HIPCHK(c, hipMemcpy(hy.data(), y, n, kind));
+  if (cp[p] != nnz) return fail(c, PCDN_E_CSC, "col_ptr must start at 0 and end at nnz");
+  cp[p + 1] = nnz + n;
+  for (int64_t i = 0; i < n; ++i) {
+    ri[nnz + i] = (int32_t)i;
+    v[nnz + i] = bias;
+  }
+  return pcdn_load_csc(c, n, p + 1, nnz + n, cp.data(), ri.data(), v.data(), hy.data(), 0);
+}
+
 extern "C" int pcdn_reset(pcdn_ctx* c, int loss, double C, const double* w) {
   if (!c) return PCDN_E_ARG;
   if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");

@@ -358,3 +358,14 @@ def c5_stream(seed: int = BASE_SEED + 6, count: int = 500, rate: float = 50.0,
     idx = rng.integers(0, pool, size=count)
     C = np.exp(rng.uniform(np.log(0.1), np.log(10.0), size=count))
     return [(float(t[k]), int(idx[k]), float(C[k])) for k in range(count)]
+
+
+def with_bias(d: Data, bias: float = 1.0) -> Data:
+    """The same data with a constant feature of value `bias` appended as the
+    last column (every row holds it)."""
+    col_ptr = np.concatenate([d.col_ptr, [d.col_ptr[-1] + d.n]]).astype(np.int64)
+    row_idx = np.concatenate([d.row_idx, np.arange(d.n, dtype=np.int32)])
+    val = np.concatenate([d.val, np.full(d.n, bias, dtype=np.float32)])
+    w_star = None if d.w_star is None else np.concatenate([d.w_star, [0.0]])
+    return Data(n=d.n, p=d.p + 1, col_ptr=col_ptr, row_idx=row_idx, val=val, y=d.y.copy(),
+                w_star=w_star, meta=dict(d.meta, bias=bias))

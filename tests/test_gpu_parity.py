@@ -317,3 +317,36 @@ def test_abi_errors(pc):
     rc, w, info = s.solve(1.0, 2, 1e-3, "lr")
     assert rc == 0
     s.close()
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_bias_feature(pc, loss):
+    """pcdn_load_csc_bias appends a constant feature (regularised like the
+    others): the solve equals the oracle's on the matrix with that column
+    written out, from host and from device arrays."""
+    import torch
+    from paper_1306_4080_amd import PcdnError
+    d = synth.c1()
+    db = synth.with_bias(d, 1.0)
+    s = pc.Solver(device=0).load_data(d, bias=1.0)
+    assert s.p == d.p + 1
+    g = s.solve(1.0, 32, 1e-4, loss, seed=2)
+    w_o, io, _ = oracle.solve(oracle.Problem.from_data(db), oracle.Params(loss=loss, C=1.0), P=32,
+                              eps=1e-4, seed=2)
+    _assert_solve_parity(g, (w_o, io))
+    assert g[1].shape == (d.p + 1,)
+    # device arrays
+    dev = {k: torch.from_numpy(getattr(d, k)).cuda() for k in ("col_ptr", "row_idx", "val", "y")}
+    s2 = pc.Solver(device=0)
+    pc.pcdn_load_csc_bias(s2.ctx, d.n, d.p, dev["col_ptr"], dev["row_idx"], dev["val"], dev["y"], 1.0)
+    s2.n, s2.p = d.n, d.p + 1
+    g2 = s2.solve(1.0, 32, 1e-4, loss, seed=2)
+    assert g2[2]["objective"] == pytest.approx(g[2]["objective"], rel=1e-9)
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.pcdn_load_csc_bias(s2.ctx, d.n, d.p, d.col_ptr, d.row_idx, d.val, d.y, 0.0)
+    bad = d.col_ptr.copy()
+    bad[-1] += 1
+    with pytest.raises(PcdnError, match="E_CSC"):
+        pc.pcdn_load_csc_bias(s2.ctx, d.n, d.p, bad, d.row_idx, d.val, d.y, 1.0)
+    s.close()
+    s2.close()

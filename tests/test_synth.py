@@ -60,3 +60,12 @@ def test_bernoulli_csc_and_batched_shapes():
     Cs = synth.c4_path_Cs()
     assert len(Cs) == 32 and Cs[0] == 2.0 ** -4 and abs(Cs[-1] - 2.0 ** 6) < 1e-12
     assert np.all(np.diff(np.log2(Cs)) > 0)
+
+
+def test_with_bias_appends_constant_column():
+    d = synth.tiny(5, n=7, p=4, density=0.5)
+    b = synth.with_bias(d, 2.5)
+    assert b.p == d.p + 1 and b.nnz == d.nnz + d.n
+    X, Xb = d.dense(), b.dense()
+    assert np.array_equal(Xb[:, :d.p], X) and np.all(Xb[:, d.p] == 2.5)
+    assert np.array_equal(b.y, d.y)
