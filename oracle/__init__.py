@@ -42,7 +42,7 @@ class _Par(ctypes.Structure):
     _fields_ = [("loss", ctypes.c_int32), ("max_ls", ctypes.c_int32),
                 ("C", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("nu", ctypes.c_double)]
+                ("nu", ctypes.c_double), ("shrink", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -75,6 +75,8 @@ def lib():
     L.orc_splitmix64.restype = u64
     L.orc_permutation.argtypes = [u64, i64, i64, vp]
     L.orc_permutation.restype = None
+    L.orc_permutation_active.argtypes = [u64, i64, i64, vp, vp]
+    L.orc_permutation_active.restype = i64
     L.orc_margins.argtypes = [vp, vp, vp]
     L.orc_cache_from_w.argtypes = [vp, i32, vp, vp]
     L.orc_grad_hess.argtypes = [vp, vp, vp, vp, i64, vp, vp]
@@ -140,6 +142,7 @@ class Params:
     gamma: float = 0.0
     nu: float = 1e-12
     max_ls: int = 30
+    shrink: bool = False
 
     def __post_init__(self):
         if isinstance(self.loss, str):
@@ -147,7 +150,7 @@ class Params:
 
     def c(self):
         return _Par(int(self.loss), int(self.max_ls), float(self.C), float(self.sigma),
-                    float(self.beta), float(self.gamma), float(self.nu))
+                    float(self.beta), float(self.gamma), float(self.nu), int(bool(self.shrink)), 0)
 
 
 def splitmix64(seed: int, i: int) -> int:
@@ -158,6 +161,15 @@ def permutation(seed: int, k: int, p: int) -> np.ndarray:
     out = np.empty(p, dtype=np.int32)
     lib().orc_permutation(seed, k, p, _ptr(out))
     return out
+
+
+def permutation_active(seed: int, k: int, active) -> tuple:
+    """The partition restricted to the active features (shrinking): returns
+    (permutation of all features, number of active ones leading it)."""
+    active = np.ascontiguousarray(active, dtype=np.int8)
+    out = np.empty(len(active), dtype=np.int32)
+    n_act = lib().orc_permutation_active(seed, k, len(active), _ptr(active), _ptr(out))
+    return out, int(n_act)
 
 
 def margins(prob: Problem, w: np.ndarray) -> np.ndarray:

@@ -44,6 +44,8 @@ typedef struct {
   int32_t loss;
   int32_t max_ls;
   double C, sigma, beta, gamma, nu;
+  int32_t shrink;  /* outer-iteration shrinking (see orc_solve); 0: off */
+  int32_t pad;
 } orc_par;
 
 typedef struct {
@@ -111,6 +113,32 @@ void orc_permutation(uint64_t seed, int64_t k, int64_t p, int32_t* perm) {
   qsort(a, (size_t)p, sizeof(key_index), cmp_key_index);
   for (int64_t r = 0; r < p; ++r) perm[r] = a[r].j;
   free(a);
+}
+
+/* The partition restricted to the active features (shrinking): active
+ * features keep their keys (capped at 0xFFFFFFFE), inactive ones take
+ * 0xFFFFFFFF, so the active features come first, in the order of the full
+ * permutation; returns their count. */
+int64_t orc_permutation_active(uint64_t seed, int64_t k, int64_t p, const char* active,
+                               int32_t* perm) {
+  key_index* a = (key_index*)malloc((size_t)p * sizeof(key_index));
+  uint64_t stream = orc_splitmix64(seed, (uint64_t)k);
+  int64_t n_act = 0;
+  for (int64_t j = 0; j < p; ++j) {
+    uint32_t key = (uint32_t)(orc_splitmix64(stream, (uint64_t)j) >> 32);
+    if (active[j]) {
+      if (key == 0xFFFFFFFFu) key = 0xFFFFFFFEu;
+      ++n_act;
+    } else {
+      key = 0xFFFFFFFFu;
+    }
+    a[j].key = key;
+    a[j].j = (int32_t)j;
+  }
+  qsort(a, (size_t)p, sizeof(key_index), cmp_key_index);
+  for (int64_t r = 0; r < p; ++r) perm[r] = a[r].j;
+  free(a);
+  return n_act;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -391,6 +419,17 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
 /* w holds the starting point on entry (the paper starts from 0) and the     */
 /* result on exit.  trace_F (nullable, max_outer long) receives F after each  */
 /* outer iteration.  Returns 0 when converged, 1 when max_outer was hit.     */
+/*                                                                          */
+/* Shrinking (par->shrink; the paper's experiments shrink between outer     */
+/* iterations, not inside the parallel loop, and give no rule): after outer */
+/* iteration k, with the gradient g at w^k, feature j stays active for      */
+/* iteration k+1 iff w_j != 0 or |g_j| >= 1 - M_{k-1}/n, where M_{k-1} is   */
+/* the largest |grad^S_j F| over all features after iteration k-1          */
+/* (M_{-1} = infinity: the first two iterations use every feature; the      */
+/* threshold is LIBLINEAR's CDN rule).  Iteration k+1 partitions only the   */
+/* active features (orc_permutation_active) into bundles of P.  The         */
+/* stopping rule is unchanged: it uses all features, and a feature is only  */
+/* left out while its minimum-norm subgradient is 0.                        */
 /* ------------------------------------------------------------------------ */
 int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
                   uint64_t seed, int32_t max_outer, double* w, orc_info* info,
@@ -417,11 +456,19 @@ int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
     converged = I.subgrad <= eps * I.subgrad0;
   }
 
-  int64_t nb = (p + P - 1) / P;
+  char* active = (char*)malloc((size_t)p);
+  double* gfull = (double*)malloc((size_t)p * sizeof(double));
+  for (int64_t j = 0; j < p; ++j) active[j] = 1;
+  double M_prev = INFINITY;
   while (!converged && I.outer_iters < max_outer) {
-    orc_permutation(seed, I.outer_iters, p, perm);
+    int64_t p_act = p;
+    if (par->shrink)
+      p_act = orc_permutation_active(seed, I.outer_iters, p, active, perm);
+    else
+      orc_permutation(seed, I.outer_iters, p, perm);
+    int64_t nb = (p_act + P - 1) / P;
     for (int64_t t = 0; t < nb; ++t) {
-      int64_t lo = t * P, hi = lo + P < p ? lo + P : p;
+      int64_t lo = t * P, hi = lo + P < p_act ? lo + P : p_act;
       orc_step_info si;
       int32_t q = orc_step(X, par, w, cache, perm + lo, hi - lo, NULL, NULL, NULL, NULL, &si);
       I.bundles += 1;
@@ -436,9 +483,21 @@ int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
     }
     if (trace_F) trace_F[I.outer_iters] = orc_objective_cache(X, par, w, cache);
     I.outer_iters += 1;
-    I.subgrad = orc_subgrad_l1(X, par, w, cache, NULL);
+    I.subgrad = orc_subgrad_l1(X, par, w, cache, gfull);
     converged = I.subgrad <= eps * I.subgrad0;
+    if (par->shrink) {
+      double M = 0.0;
+      const double thr = 1.0 - M_prev / (double)n;
+      for (int64_t j = 0; j < p; ++j) {
+        const double v = fabs(min_norm_subgrad(gfull[j], w[j]));
+        if (v > M) M = v;
+        active[j] = (w[j] != 0.0 || fabs(gfull[j]) >= thr) ? 1 : 0;
+      }
+      M_prev = M;
+    }
   }
+  free(active);
+  free(gfull);
 
   I.converged = converged;
   I.objective = orc_objective_cache(X, par, w, cache);

@@ -399,3 +399,71 @@ def test_ls_failure_leaves_state_unchanged():
             assert np.array_equal(w, w0) and np.array_equal(cache, c0) and s["alpha"] == 0.0
             break
     assert found
+
+
+# --------------------------------------------------------------------------
+# shrinking (an outer-iteration active set; off by default)
+# --------------------------------------------------------------------------
+def test_permutation_active_matches_its_definition():
+    """Active features keep their keys (capped at 2^32 - 2), inactive ones
+    take 2^32 - 1; built here in pure Python integers: the active features
+    lead, in the order of the full permutation."""
+    rng = np.random.default_rng(3)
+    for seed, k, p in ((0, 0, 17), (20130616, 3, 1000), (2**64 - 1, 7, 257)):
+        active = (rng.random(p) < 0.3).astype(np.int8)
+        stream = _py_splitmix64(seed, k)
+        keys = []
+        for j in range(p):
+            key = _py_splitmix64(stream, j) >> 32
+            key = min(key, 2**32 - 2) if active[j] else 2**32 - 1
+            keys.append((key, j))
+        ref = [j for _, j in sorted(keys)]
+        perm, n_act = oracle.permutation_active(seed, k, active)
+        assert perm.tolist() == ref and n_act == int(active.sum())
+        full = oracle.permutation(seed, k, p).tolist()
+        assert perm[:n_act].tolist() == [j for j in full if active[j]]
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_shrinking_reaches_brute_force_optimum(loss, seed):
+    d = synth.tiny(100 + seed, n=30, p=4, density=0.8, flip=0.15)
+    X, y = d.dense(), d.y.astype(float)
+    C = [0.3, 1.0, 2.5][seed - 1]
+    Fstar, _ = R.brute_force_optimum(X, y, C, loss)
+    for P in (1, 2, 4):
+        par = oracle.Params(loss=loss, C=C, shrink=True)
+        w, info, _ = oracle.solve(_prob(d), par, P=P, eps=1e-12, seed=seed, max_outer=5000)
+        assert info["converged"] == 1
+        assert info["objective"] == pytest.approx(Fstar, rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_shrinking_kkt_monotone_and_less_work(loss):
+    """With shrinking the returned w satisfies the optimality conditions (a
+    dense gradient), F never increases, the final F agrees with the solve
+    without shrinking to the accuracy eps implies, and fewer nonzeros are
+    swept (the solution is sparse)."""
+    d = synth.c1() if loss == "lr" else synth.tiny(41, n=300, p=80, density=0.1, binary=True)
+    X, y = d.dense(), d.y.astype(float)
+    prob = _prob(d)
+    C = 1.0
+    base_w, base, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C), P=16, eps=1e-8, seed=4,
+                                   max_outer=3000)
+    w, info, trace = oracle.solve(prob, oracle.Params(loss=loss, C=C, shrink=True), P=16, eps=1e-8,
+                                  seed=4, max_outer=3000)
+    assert info["converged"] == 1
+    z = X @ w
+    if loss == "lr":
+        g = -C * X.T @ (y / (1.0 + np.exp(y * z)))
+    else:
+        b = 1.0 - y * z
+        g = -2.0 * C * X.T @ (y * b * (b > 0))
+    G0 = info["subgrad0"]
+    nz = w != 0
+    assert np.all(np.abs(g[nz] + np.sign(w[nz])) <= 1e-6 * G0)
+    assert np.all(np.abs(g[~nz]) <= 1.0 + 1e-6 * G0)
+    t = trace[:info["outer_iters"]]
+    assert np.all(np.diff(t) <= 1e-12 * np.abs(t[:-1]))
+    assert info["objective"] == pytest.approx(base["objective"], rel=1e-8)
+    assert info["nnz_swept"] < base["nnz_swept"]
