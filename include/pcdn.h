@@ -63,8 +63,20 @@ typedef struct {
   double nu;            /* floor added to a Hessian entry <= 0 (0: 1e-12)   */
   const double* w0;     /* host, p entries, warm start; NULL: zeros         */
   int32_t schedule;     /* PCDN_SCHED_*: how bundles map onto the GPU       */
-  int32_t reserved;     /* must be 0                                        */
+  int32_t shrink;       /* 1: outer-iteration shrinking (below); 0: off     */
 } pcdn_opts;
+
+/* Shrinking (opt-in; the paper shrinks between outer iterations, not inside
+ * the parallel loop, and gives no rule): after outer iteration k, feature j
+ * stays active for iteration k+1 iff w_j != 0 or |g_j| >= 1 - M_{k-1}/n,
+ * where M_{k-1} is the largest minimum-norm subgradient after iteration k-1
+ * (infinite before the first, so the first two iterations use every
+ * feature).  Iteration k+1 partitions only the active features: the seeded
+ * permutation restricted to them (inactive features sort last), bundles of P.
+ * The stopping rule still uses every feature; a feature is only left out
+ * while its minimum-norm subgradient is 0.  pcdn_reset and pcdn_solve start
+ * with every feature active; pcdn_iterate continues the current active set.
+ * pcdn_step ignores it. */
 
 /* Bundle schedules (same arithmetic, different launch structure):
  *  WIDE:   every bundle is four kernels over the whole GPU (many nonzeros);

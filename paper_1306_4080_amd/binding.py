@@ -50,7 +50,7 @@ class pcdn_opts(ctypes.Structure):
                 ("max_ls", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("nu", ctypes.c_double), ("w0", ctypes.c_void_p),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("shrink", ctypes.c_int32)]
 
 
 class pcdn_info(ctypes.Structure):
@@ -174,9 +174,10 @@ SCHEDULES = {"auto": 0, "wide": 1, "narrow": 2}
 
 
 def _opts(seed=0, max_outer=0, max_ls=0, sigma=0.0, beta=0.0, gamma=0.0, nu=0.0, w0=None,
-          schedule="auto"):
+          schedule="auto", shrink=False):
     schedule = SCHEDULES.get(schedule, schedule)
-    o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None, int(schedule), 0)
+    o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None, int(schedule),
+                  int(bool(shrink)))
     keep = None
     if w0 is not None:
         keep = np.ascontiguousarray(w0, dtype=np.float64)

@@ -66,6 +66,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->part); dfree(c->ls_part);
   dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32);
   dfree(c->rp); dfree(c->rc); dfree(c->rv);
+  dfree(c->act);
   drop_graph(c);
   c->loaded = false;
   c->has_state = false;
@@ -87,7 +88,8 @@ int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
   r->schedule = o ? o->schedule : PCDN_SCHED_AUTO;
   if (r->schedule < PCDN_SCHED_AUTO || r->schedule > PCDN_SCHED_NARROW)
     return fail(c, PCDN_E_ARG, "unknown schedule");
-  if (o && o->reserved != 0) return fail(c, PCDN_E_ARG, "reserved option field must be 0");
+  r->shrink = o ? o->shrink : 0;
+  if (r->shrink != 0 && r->shrink != 1) return fail(c, PCDN_E_ARG, "shrink must be 0 or 1");
   if (r->max_outer < 0) return fail(c, PCDN_E_ARG, "max_outer must be >= 0");
   if (r->max_ls < 1 || r->max_ls > kQMax) return fail(c, PCDN_E_ARG, "max_ls must lie in [1, 32]");
   if (!(r->sigma > 0.0 && r->sigma < 1.0)) return fail(c, PCDN_E_ARG, "sigma must lie in (0, 1)");
@@ -182,17 +184,20 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
 // Inner iteration of Algorithm 3 on slots [lo, hi) of `perm` whose chunk
 // descriptors are c->chunks / c->cstart, first half: sweep (g, h, d, fused
 // d^T x) and split columns.
-SweepArgs bundle_sweep_args(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
+// clip: the bundle is one of an outer iteration with shrinking (its slots
+// are clipped to the active count on the device)
+SweepArgs bundle_sweep_args(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) {
   SweepArgs a = sweep_args(c, o);
   a.chunks = c->chunks;
   a.cstart = c->cstart;
   a.slot_lo = lo;
   a.slot_hi = hi;
+  a.p_active = clip ? c->scal + 5 : nullptr;
   return a;
 }
 
-int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
-  const SweepArgs a = bundle_sweep_args(c, o, lo, hi);
+int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) {
+  const SweepArgs a = bundle_sweep_args(c, o, lo, hi, clip);
   {
     ProfScope ps(c, 0);
     HIPCHK(c, launch_sweep(c->loss, false, a, c->stream));
@@ -206,8 +211,10 @@ int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi) {
 
 // Second half: line-search partials, then decision + apply.  With the first
 // half, four kernel boundaries are the only synchronisation of a bundle.
-LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
+               bool clip) {
   LsArgs l{};
+  l.p_active = clip ? c->scal + 5 : nullptr;
   l.dtx = c->dtx;
   l.cache = c->cache;
   l.y = c->y;
@@ -225,8 +232,10 @@ LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
   return l;
 }
 
-ApplyArgs apply_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+ApplyArgs apply_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
+                     bool clip) {
   ApplyArgs ap{};
+  ap.p_active = clip ? c->scal + 5 : nullptr;
   ap.dtx = c->dtx;
   ap.cache = c->cache;
   ap.y = c->y;
@@ -248,22 +257,24 @@ ApplyArgs apply_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo
   return ap;
 }
 
-int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
+int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
+                    bool clip) {
   {
     ProfScope ps(c, 2);
-    HIPCHK(c, launch_linesearch(c->loss, ls_args(c, o, perm, lo, hi), c->stream));
+    HIPCHK(c, launch_linesearch(c->loss, ls_args(c, o, perm, lo, hi, clip), c->stream));
   }
   {
     ProfScope ps(c, 3);
-    HIPCHK(c, launch_apply(c->loss, apply_args(c, o, perm, lo, hi), c->stream));
+    HIPCHK(c, launch_apply(c->loss, apply_args(c, o, perm, lo, hi, clip), c->stream));
   }
   return PCDN_OK;
 }
 
-int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi) {
-  int rc = bundle_sweep(c, o, lo, hi);
+int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
+               bool clip) {
+  int rc = bundle_sweep(c, o, lo, hi, clip);
   if (rc) return rc;
-  return bundle_ls_apply(c, o, perm, lo, hi);
+  return bundle_ls_apply(c, o, perm, lo, hi, clip);
 }
 
 // ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0);
@@ -286,6 +297,48 @@ int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) 
     HIPCHK(c, launch_split(c->loss, true, a, c->stream));
   }
   HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->scal, it, c->stream));
+  return PCDN_OK;
+}
+
+// Stopping sweep of an outer iteration with shrinking: the norm, the next
+// active mask (threshold scal[4] of the previous iteration), the largest
+// violation, the next threshold, active count and nonzeros (scal[0..6]).
+int launch_stopping_shrink(pcdn_ctx* c, const Opts& o, IterState* it) {
+  SweepArgs a = stop_args(c, o, c->w);
+  a.act = c->act;
+  a.thr = c->scal + 4;
+  {
+    ProfScope ps(c, 4);
+    HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
+    HIPCHK(c, launch_split(c->loss, true, a, c->stream));
+  }
+  const StopSumArgs s{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, it,
+                      sum_grid(c->p)};
+  HIPCHK(c, launch_stop_sum(s, c->stream));
+  return PCDN_OK;
+}
+
+// Every feature active, threshold below any |g| (the first outer iterations).
+int init_shrink(pcdn_ctx* c) {
+  HIPCHK(c, launch_fill(c->act, 1.0, c->p, c->stream));
+  HIPCHK(c, launch_fill(c->scal + 4, -1e300, 1, c->stream));
+  HIPCHK(c, launch_fill(c->scal + 5, (double)c->p, 1, c->stream));
+  HIPCHK(c, launch_fill(c->scal + 6, (double)c->nnz, 1, c->stream));
+  c->p_active_h = (double)c->p;
+  c->nnz_active_h = (double)c->nnz;
+  return PCDN_OK;
+}
+
+// The scalars after an outer iteration: *G = the stopping norm; the host's
+// copy of the next active count and nonzeros (shrinking) is refreshed.
+int read_outer(pcdn_ctx* c, double* G) {
+  HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->prof.mask) prof_harvest(c);
+  *G = c->hscal[0];
+  c->p_active_h = c->hscal[5];
+  c->nnz_active_h = c->hscal[6];
   return PCDN_OK;
 }
 
@@ -342,8 +395,9 @@ int set_w(pcdn_ctx* c, const double* w_host) {
 }
 
 // Partition of outer iteration k (it != null: k and seed read on the device).
-int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, const IterState* it) {
-  HIPCHK(c, launch_perm_keys(it, seed, k, c->p, c->keys0, c->idx0, c->stream));
+int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, const IterState* it,
+                       const double* act = nullptr) {
+  HIPCHK(c, launch_perm_keys(it, seed, k, c->p, act, c->keys0, c->idx0, c->stream));
   HIPCHK(c, launch_radix_sort(c->keys0, c->idx0, c->keys1, c->idx1, c->p, c->hist, c->scan_tmp,
                               c->stream));
   return PCDN_OK;
@@ -410,7 +464,7 @@ int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64
 // The outer iteration in three parts.  Before the bundles: partition,
 // chunk descriptors, and (single-workgroup schedule) X in partition order.
 int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
-  int rc = device_permutation(c, o.seed, k, it);
+  int rc = device_permutation(c, o.seed, k, it, o.shrink ? c->act : nullptr);
   if (rc) return rc;
   HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunks, c->scan_tmp,
                           c->stream));
@@ -418,18 +472,26 @@ int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it)
   return PCDN_OK;
 }
 
+// Single-workgroup arguments for every bundle of an outer iteration's
+// partition (with shrinking, the kernel stops after the active features).
+NarrowArgs outer_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P) {
+  NarrowArgs na = make_narrow_args(c, o, c->idx0, c->p, P, 0, (c->p + P - 1) / P, nullptr);
+  if (o.shrink) na.p_active = c->scal + 5;
+  return na;
+}
+
 // Every bundle of the partition.
 int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
   const int64_t nb = (c->p + P - 1) / P;
   if (use_narrow(c, o, P)) {
-    const NarrowArgs na = make_narrow_args(c, o, c->idx0, c->p, P, 0, nb, nullptr);
+    const NarrowArgs na = outer_narrow_args(c, o, P);
     ProfScope ps(c, 5);
     HIPCHK(c, launch_narrow(c->loss, na, c->stream));
     return PCDN_OK;
   }
   for (int64_t t = 0; t < nb; ++t) {
     const int64_t lo = t * P, hi = std::min(lo + P, c->p);
-    int rc = run_bundle(c, o, c->idx0, lo, hi);
+    int rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
     if (rc) return rc;
   }
   return PCDN_OK;
@@ -437,8 +499,9 @@ int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
 
 // After the bundles: scatter counters and the stopping sweep.
 int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
-  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, use_narrow(c, o, P), c->stats,
-                                 c->stream));
+  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, use_narrow(c, o, P),
+                                 o.shrink ? c->scal + 5 : nullptr, c->stats, c->stream));
+  if (o.shrink) return launch_stopping_shrink(c, o, it);
   return launch_stopping(c, o, c->w, it);
 }
 
@@ -467,30 +530,42 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t lo = b * P, hi = std::min(lo + P, c->p);
     Task t = task(kTaskSweep, sweep_grid(hi - lo), 0);
-    t.u.sw = bundle_sweep_args(c, o, lo, hi);
+    t.u.sw = bundle_sweep_args(c, o, lo, hi, o.shrink);
     out.push_back(t);
     t.kind = kTaskSplit;
     out.push_back(t);
     t = task(kTaskLinesearch, lsx * lsy, lsx);
-    t.u.ls = ls_args(c, o, c->idx0, lo, hi);
+    t.u.ls = ls_args(c, o, c->idx0, lo, hi, o.shrink);
     out.push_back(t);
     t = task(kTaskApply, apply_grid(c->n, hi - lo), 0);
-    t.u.ap = apply_args(c, o, c->idx0, lo, hi);
+    t.u.ap = apply_args(c, o, c->idx0, lo, hi, o.shrink);
     out.push_back(t);
   }
   Task t = task(kTaskScatterCount, scatter_count_grid(c->p), 0);
-  t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, 0, c->stats};
+  t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, 0, c->stats,
+                            o.shrink ? c->scal + 5 : nullptr};
   out.push_back(t);
   t = task(kTaskSweepStop, sweep_grid(c->p), 0);
   t.u.sw = stop_args(c, o, c->w);
+  if (o.shrink) {
+    t.u.sw.act = c->act;
+    t.u.sw.thr = c->scal + 4;
+  }
   out.push_back(t);
   t.kind = kTaskSplitStop;
   out.push_back(t);
   const int sb = sum_grid(c->p);
-  t = task(kTaskSumPartial, sb, 0);
-  t.u.sum = SumArgs{c->tmp_p, c->p, c->sum_part, c->scal, c->iter, sb};
-  out.push_back(t);
-  t.kind = kTaskSumFinal;
+  if (o.shrink) {
+    t = task(kTaskStopPartial, sb, 0);
+    t.u.stop = StopSumArgs{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, c->iter, sb};
+    out.push_back(t);
+    t.kind = kTaskStopFinal;
+  } else {
+    t = task(kTaskSumPartial, sb, 0);
+    t.u.sum = SumArgs{c->tmp_p, c->p, c->sum_part, c->scal, c->iter, sb};
+    out.push_back(t);
+    t.kind = kTaskSumFinal;
+  }
   t.nblk = 1;
   out.push_back(t);
   return PCDN_OK;
@@ -507,6 +582,7 @@ pcdn_ctx::GraphKey graph_key_of(const pcdn_ctx* c, const Opts& o, int64_t P) {
   key.nu = o.nu;
   key.max_ls = o.max_ls;
   key.schedule = o.schedule;
+  key.shrink = o.shrink;
   return key;
 }
 
@@ -562,11 +638,15 @@ int ensure_split_graphs(pcdn_ctx* c, const Opts& o, int64_t P) {
 void count_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t count) {
   // every outer iteration sweeps each feature once in a bundle and once more
   // in the stopping test
-  c->hc.nnz_gh += (double)c->nnz * count;
-  c->hc.slots += (double)c->p * count;
+  // (with shrinking: the active features the previous stopping sweep chose;
+  // exact for one iteration at a time, as the drivers run them)
+  const double nz = o.shrink ? c->nnz_active_h : (double)c->nnz;
+  const double sl = o.shrink ? c->p_active_h : (double)c->p;
+  c->hc.nnz_gh += nz * count;
+  c->hc.slots += sl * count;
   if (use_narrow(c, o, P)) {
-    c->hc.nnz_gh_narrow += (double)c->nnz * count;
-    c->hc.slots_narrow += (double)c->p * count;
+    c->hc.nnz_gh_narrow += nz * count;
+    c->hc.slots_narrow += sl * count;
   }
   c->hc.nnz_stop += (double)c->nnz * count;
   c->hc.stop_sweeps += (double)count;
@@ -661,6 +741,8 @@ int solve_begin(SolveRun& r) {
   c->loss = r.loss;
   c->C = r.C;
   r.outer = 0;
+  rc = init_shrink(c);
+  if (rc) return rc;
   // reference norm at w = 0 (retained quantities all one)
   HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));
   r.G0 = r.G = 0.0;
@@ -768,7 +850,8 @@ extern "C" int pcdn_create(pcdn_ctx** out, int device, void* hip_stream) {
   }
   if (dalloc(&c->iter, 1) != hipSuccess || dalloc(&c->st, 1) != hipSuccess ||
       dalloc(&c->stats, 1) != hipSuccess || dalloc(&c->scal, 8) != hipSuccess ||
-      dalloc(&c->sum_part, kSumGrid) != hipSuccess)
+      dalloc(&c->sum_part, kSumGrid) != hipSuccess ||
+      dalloc(&c->stop_part, 4 * kSumGrid) != hipSuccess)
     return bail(PCDN_E_OOM, "device allocation failed");
   if (hipHostMalloc((void**)&c->hscal, 8 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&c->hstats, sizeof(Stats)) != hipSuccess ||
@@ -789,6 +872,7 @@ extern "C" int pcdn_destroy(pcdn_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_data(c);
   dfree(c->iter); dfree(c->st); dfree(c->stats); dfree(c->scal); dfree(c->sum_part);
+  dfree(c->stop_part);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->hstats) (void)hipHostFree(c->hstats);
   if (c->hst) (void)hipHostFree(c->hst);
@@ -929,6 +1013,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->poff, p + 1);
   ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->ls_part, (size_t)kLsGrid * (2 * kQMax + 2));
+  ALLOC(c, c->act, p);
   ALLOC(c, c->rp, n + 1);
   ALLOC(c, c->rc, nnz);
   ALLOC(c, c->rv, nnz);
@@ -1015,6 +1100,8 @@ extern "C" int pcdn_reset(pcdn_ctx* c, int loss, double C, const double* w) {
   c->C = C;
   rc = set_w(c, w);
   if (rc) return rc;
+  rc = init_shrink(c);
+  if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->has_state = true;
   return PCDN_OK;
@@ -1046,15 +1133,16 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
     rc = launch_narrow_bundles(c, o, c->step_perm, P, P, 0, 1, dtx ? c->tmp_n : nullptr);
     if (rc) return rc;
   } else {
-    rc = bundle_sweep(c, o, 0, P);
+    rc = bundle_sweep(c, o, 0, P, false);
     if (rc) return rc;
     if (dtx)
       HIPCHK(c, hipMemcpyAsync(c->tmp_n, c->dtx, c->n * sizeof(double), hipMemcpyDeviceToDevice,
                                c->stream));
-    rc = bundle_ls_apply(c, o, c->step_perm, 0, P);
+    rc = bundle_ls_apply(c, o, c->step_perm, 0, P, false);
     if (rc) return rc;
   }
-  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, narrow, c->stats, c->stream));
+  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, narrow, nullptr, c->stats,
+                                 c->stream));
   double swept = 0.0;
   for (int64_t t = 0; t < P; ++t) swept += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
   c->hc.nnz_gh += swept;
@@ -1110,7 +1198,7 @@ extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss
     rc = run_outer(c, r.o, P, r.outer, 1);
     if (rc) return rc;
     double G = 0.0;
-    rc = read_scalar(c, 0, &G);
+    rc = read_outer(c, &G);
     if (rc) return rc;
     rc = solve_note_outer(r, G);
     if (rc) return rc;

@@ -167,10 +167,7 @@ class Engine {
       HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
       HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
       HIPCHK(c, hipStreamWaitEvent(j->narrow ? narrow_stream_[g] : wide_stream_, j->pre_done, 0));
-      if (j->narrow) {
-        const int64_t nb = (c->p + j->run.P - 1) / j->run.P;
-        htab[at[g]++] = make_narrow_args(c, j->run.o, c->idx0, c->p, j->run.P, 0, nb, nullptr);
-      }
+      if (j->narrow) htab[at[g]++] = outer_narrow_args(c, j->run.o, j->run.P);
       count_outer(c, j->run.o, j->run.P, 1);
     }
     *err_ctx = nullptr;
@@ -194,7 +191,7 @@ class Engine {
         const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
         HIPCHK(c, hipStreamWaitEvent(c->stream, fused_done_[g], 0));
         HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, sizeof(double), hipMemcpyDeviceToHost,
+        HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
       }
       *err_ctx = nullptr;
@@ -209,9 +206,9 @@ class Engine {
         if (e != hipSuccess) return dev_fail("executor launch", e);
       }
       hipError_t e = launch_gather((const double* const*)(base + plan_src_byte_),
-                                   (double*)gather_.dev, (int)plan_jobs_.size(), wide_stream_);
+                                   (double*)gather_.dev, 3 * (int)plan_jobs_.size(), wide_stream_);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(gather_.host, gather_.dev, sizeof(double) * plan_jobs_.size(),
+        e = hipMemcpyAsync(gather_.host, gather_.dev, 3 * sizeof(double) * plan_jobs_.size(),
                            hipMemcpyDeviceToHost, wide_stream_);
       if (e != hipSuccess) return dev_fail("gather", e);
     }
@@ -220,14 +217,21 @@ class Engine {
     if (e == hipSuccess) e = hipStreamSynchronize(narrow_stream_[1]);
     if (e == hipSuccess) e = hipStreamSynchronize(wide_stream_);
     if (e != hipSuccess) return dev_fail("round", e);
-    for (size_t k = 0; k < plan_jobs_.size(); ++k)
-      plan_jobs_[k]->run.c->hscal[0] = ((const double*)gather_.host)[k];
+    for (size_t k = 0; k < plan_jobs_.size(); ++k) {
+      const double* gv = (const double*)gather_.host + 3 * k;
+      pcdn_ctx* c = plan_jobs_[k]->run.c;
+      c->hscal[0] = gv[0];
+      c->hscal[5] = gv[1];
+      c->hscal[6] = gv[2];
+    }
     std::vector<EngineJob*> keep;
     keep.reserve(jobs_.size());
     for (EngineJob* j : jobs_) {
       pcdn_ctx* c = j->run.c;
       *err_ctx = c;
       HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->p_active_h = c->hscal[5];  // next active count and nonzeros (shrinking)
+      c->nnz_active_h = c->hscal[6];
       rc = solve_note_outer(j->run, c->hscal[0]);
       if (rc) return rc;
       j->active = !j->run.converged && j->run.outer < j->run.o.max_outer;
@@ -288,10 +292,10 @@ class Engine {
     if (plan_jobs_.empty()) return PCDN_OK;
     const size_t task_bytes = align_up(sizeof(Task) * n_tasks);
     const size_t first_bytes = align_up(sizeof(int32_t) * (n_tasks + L));
-    const size_t src_bytes = align_up(sizeof(double*) * plan_jobs_.size());
+    const size_t src_bytes = align_up(3 * sizeof(double*) * plan_jobs_.size());
     // the previous plan's tables may still be read by nothing: rounds end synchronised
     if (exec_.reserve(task_bytes + first_bytes + src_bytes) != hipSuccess ||
-        gather_.reserve(sizeof(double) * plan_jobs_.size()) != hipSuccess)
+        gather_.reserve(3 * sizeof(double) * plan_jobs_.size()) != hipSuccess)
       return dev_fail("executor table allocation", hipErrorOutOfMemory);
     char* h = (char*)exec_.host;
     Task* htasks = (Task*)h;
@@ -313,7 +317,13 @@ class Engine {
       plan_count_.push_back(cnt);
       plan_blocks_.push_back(blk);
     }
-    for (size_t k = 0; k < plan_jobs_.size(); ++k) hsrc[k] = plan_jobs_[k]->run.c->scal;
+    // per job: the stopping norm, the next active count and nonzeros
+    for (size_t k = 0; k < plan_jobs_.size(); ++k) {
+      double* sc = plan_jobs_[k]->run.c->scal;
+      hsrc[3 * k] = sc;
+      hsrc[3 * k + 1] = sc + 5;
+      hsrc[3 * k + 2] = sc + 6;
+    }
     plan_src_byte_ = task_bytes + first_bytes;
     const hipError_t e = hipMemcpyAsync(exec_.dev, exec_.host, task_bytes + first_bytes + src_bytes,
                                         hipMemcpyHostToDevice, wide_stream_);
@@ -669,7 +679,7 @@ extern "C" int pcdn_solve_path(pcdn_ctx* c, const double* Cs, int32_t count, int
       rc = run_outer(c, r.o, P, r.outer, 1);
       if (rc) return rc;
       double G = 0.0;
-      rc = read_scalar(c, 0, &G);
+      rc = read_outer(c, &G);
       if (rc) return rc;
       rc = solve_note_outer(r, G);
       if (rc) return rc;
@@ -737,7 +747,7 @@ extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const 
       rc = run_outer(c, r.o, P, r.outer, 1);
       if (rc) return rc;
       double G = 0.0;
-      rc = read_scalar(c, 0, &G);
+      rc = read_outer(c, &G);
       if (rc) return rc;
       rc = solve_note_outer(r, G);
       if (rc) return rc;

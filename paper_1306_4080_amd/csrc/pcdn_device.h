@@ -92,6 +92,12 @@ struct SweepArgs {
   double* dtx;                // d^T x accumulator
   Stats* stats;
   double C, gamma, nu;
+  // shrinking (all nullable): bundle mode clips the slots to the first
+  // *p_active; stopping mode writes act[j] = 1 if feature j stays active
+  // (w_j != 0 or |g_j| >= *thr), else 0
+  const double* p_active;
+  double* act;
+  const double* thr;
 };
 
 struct LsArgs {
@@ -108,6 +114,7 @@ struct LsArgs {
   Stats* stats;
   double beta;
   int Q;
+  const double* p_active;  // nullable: slots clipped to the first *p_active
 };
 
 struct ApplyArgs {
@@ -125,6 +132,7 @@ struct ApplyArgs {
   Stats* stats;
   double C, sigma, beta;
   int Q, max_ls;
+  const double* p_active;  // nullable: slots clipped to the first *p_active
 };
 
 struct ScatterCountArgs {
@@ -134,6 +142,23 @@ struct ScatterCountArgs {
   int64_t p;                 // slots
   int32_t narrow;            // count for the single-workgroup kernel
   Stats* stats;
+  const double* p_active;    // nullable: slots clipped to the first *p_active
+};
+
+// Stopping reduction with shrinking: sums ||grad^S F||_1 = sum sg, the
+// largest violation M = max sg, and the next iteration's active count and
+// nonzeros (sum act, sum act_j nnz_j); the final level writes scal[0] = the
+// norm, scal[3] = M, scal[4] = 1 - M/n (the next threshold), scal[5] = the
+// active count, scal[6] = their nonzeros, and advances it->k.
+struct StopSumArgs {
+  const double* sg;
+  const double* act;
+  const int64_t* cp;
+  int64_t p, n;
+  double* part;              // 4 partials per block of the first level
+  double* scal;
+  IterState* it;
+  int32_t nb;
 };
 
 struct SumArgs {
@@ -158,6 +183,8 @@ enum TaskKind : int32_t {
   kTaskScatterCount,
   kTaskSumPartial,
   kTaskSumFinal,
+  kTaskStopPartial,
+  kTaskStopFinal,
 };
 struct Task {
   int32_t kind;
@@ -170,6 +197,7 @@ struct Task {
     ApplyArgs ap;
     ScatterCountArgs sc;
     SumArgs sum;
+    StopSumArgs stop;
   } u;
 };
 
@@ -195,6 +223,7 @@ struct NarrowArgs {
   double C, sigma, beta;
   int max_ls;
   int loss;            // kLogistic / kL2Svm (read by the multi-problem kernel)
+  const double* p_active;  // nullable: bundles stop at ceil(*p_active / P)
 };
 
 // ---- host-callable launchers (pcdn_kernels.hip) -------------------------
@@ -202,8 +231,11 @@ hipError_t launch_fill(double* a, double v, int64_t n, hipStream_t s);
 // Keys of the partition of outer iteration it->k (or of the given k if it is
 // null): upper 32 bits of SplitMix64 output j of the stream seeded with output
 // k of the stream seeded with `seed`.
+// act (nullable, shrinking): inactive features (act[j] == 0) take key
+// 0xFFFFFFFF and active ones keep theirs capped at 0xFFFFFFFE, so the active
+// features lead the order.
 hipError_t launch_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
-                            uint32_t* keys, int32_t* idx, hipStream_t s);
+                            const double* act, uint32_t* keys, int32_t* idx, hipStream_t s);
 // Stable LSD radix sort of (keys, idx) by the 32-bit keys; results end in keys0/idx0.
 hipError_t launch_radix_sort(uint32_t* keys0, int32_t* idx0, uint32_t* keys1, int32_t* idx1,
                              int64_t p, int32_t* hist, int32_t* scan_tmp, hipStream_t s);
@@ -241,10 +273,14 @@ hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, con
 // Nonzeros of the features with d != 0 (slots 0..p of perm) into stats
 // (narrow: counted for the single-workgroup kernel).
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, bool narrow, Stats* stats, hipStream_t s);
+                                int64_t p, bool narrow, const double* p_active, Stats* stats,
+                                hipStream_t s);
 // Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s);
+// The stopping reduction with shrinking (see StopSumArgs); part holds
+// 4 * sum_grid(p) doubles.
+hipError_t launch_stop_sum(const StopSumArgs& a, hipStream_t s);
 hipError_t launch_loss_terms(int loss, const double* cache, const int8_t* y, int64_t n,
                              double* out, hipStream_t s);
 hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s);

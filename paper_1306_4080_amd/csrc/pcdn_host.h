@@ -90,6 +90,11 @@ struct pcdn_ctx {
   float* pv = nullptr;
   int64_t* poff = nullptr;
   int32_t* off32 = nullptr;
+  // shrinking: active mask (1/0 per feature), reduction partials, and the
+  // host's copy of the next iteration's active count and nonzeros
+  double* act = nullptr;
+  double* stop_part = nullptr;
+  double p_active_h = 0.0, nnz_active_h = 0.0;
   // X in CSR order (warm-start margins)
   int64_t* rp = nullptr;
   int32_t* rc = nullptr;
@@ -118,9 +123,11 @@ struct pcdn_ctx {
     double C = 0, sigma = 0, beta = 0, gamma = 0, nu = 0;
     int max_ls = 0;
     int schedule = -1;
+    int shrink = -1;
     bool operator==(const GraphKey& o) const {
       return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
-             gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule;
+             gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule &&
+             shrink == o.shrink;
     }
   } graph_key;
   // the same outer iteration in two parts around the bundles, for drivers
@@ -168,6 +175,7 @@ struct Opts {
   double sigma, beta, gamma, nu;
   const double* w0;
   int schedule;
+  int shrink;
 };
 
 // Options with defaults filled in and validated (o may be null).
@@ -179,6 +187,8 @@ bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
 pcdn::NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm,
                                   int64_t p_slots, int64_t P, int64_t t_begin, int64_t t_end,
                                   double* dtx_copy);
+// ... for every bundle of the current outer iteration's partition.
+pcdn::NarrowArgs outer_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P);
 // The kernels of one outer iteration after the partition (every bundle,
 // counters, stopping sweep) as tasks for the multi-problem executor, with
 // the arguments and grids the single-problem launches use (multi-kernel
@@ -200,6 +210,11 @@ int read_stats(pcdn_ctx* c);
 int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t count);
 // Copy c->scal[idx] to the host (synchronises the stream).
 int read_scalar(pcdn_ctx* c, int idx, double* out);
+// The scalars after an outer iteration (the stopping norm into *G; the next
+// active count and nonzeros into the context's host copy).
+int read_outer(pcdn_ctx* c, double* G);
+// Shrinking state at the start of a solve: every feature active.
+int init_shrink(pcdn_ctx* c);
 
 // One pcdn_solve in progress: solve_begin validates nothing (callers do),
 // computes the reference norm at w = 0 and sets up w; the caller runs outer

@@ -202,7 +202,7 @@ __global__ void k_fill(double* a, double v, int64_t n) {
 }
 
 __global__ void k_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
-                            uint32_t* keys, int32_t* idx) {
+                            const double* act, uint32_t* keys, int32_t* idx) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (it) {
     seed = it->seed;
@@ -212,7 +212,9 @@ __global__ void k_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64
   const uint64_t stream = splitmix_out(seed + (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull);
   if (j < p) {
     const uint64_t state = stream + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
-    keys[j] = (uint32_t)(splitmix_out(state) >> 32);
+    uint32_t key = (uint32_t)(splitmix_out(state) >> 32);
+    if (act) key = act[j] != 0.0 ? (key < 0xFFFFFFFFu ? key : 0xFFFFFFFEu) : 0xFFFFFFFFu;
+    keys[j] = key;
     idx[j] = (int32_t)j;
   }
 }
@@ -493,7 +495,10 @@ __device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, dou
   const double wj = a.w ? a.w[ch.feat] : 0.0;
   const int64_t o = ch.slot;
   if (STOP) {
-    if (writer) a.sg[o] = fabs(min_norm_subgradient(g, wj));
+    if (writer) {
+      a.sg[o] = fabs(min_norm_subgradient(g, wj));
+      if (a.act) a.act[o] = (wj != 0.0 || fabs(g) >= *a.thr) ? 1.0 : 0.0;
+    }
     return 0.0;
   }
   const double dj = newton_dir(g, h, wj);
@@ -506,6 +511,14 @@ __device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, dou
   return dj;
 }
 
+// Last slot of a launch's range, clipped to the active features when
+// shrinking (the slot order lists them first).
+__device__ inline int64_t clipped_hi(int64_t hi, const double* p_active) {
+  if (!p_active) return hi;
+  const int64_t pa = (int64_t)*p_active;
+  return pa < hi ? pa : hi;
+}
+
 // Kernel bodies take the block index and block count of their launch as
 // arguments, so that the multi-problem executor (k_exec) can run them on a
 // slice of its grid with exactly the work split of a launch of their own.
@@ -514,8 +527,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
   const int lane = lane_id();
   const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = nblk * kWavesPerBlock;
+  const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
+  if (hi <= a.slot_lo) return;
   const int32_t c_lo = a.cstart[a.slot_lo];
-  const int32_t c_hi = a.cstart[a.slot_hi];
+  const int32_t c_hi = a.cstart[hi];
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
     const Chunk ch = a.chunks[c];
     const int64_t khi = ch.klo + ch.len;
@@ -545,8 +560,10 @@ __device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int6
   const int lane = lane_id();
   const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = nblk * kWavesPerBlock;
+  const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
+  if (hi <= a.slot_lo) return;
   const int32_t c_lo = a.cstart[a.slot_lo];
-  const int32_t c_hi = a.cstart[a.slot_hi];
+  const int32_t c_hi = a.cstart[hi];
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
     const Chunk ch = a.chunks[c];
     if (ch.nch == 1) continue;
@@ -574,7 +591,8 @@ __device__ __forceinline__ void scatter_count_body(const ScatterCountArgs& a, in
                                                    int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
   double fused = 0.0, split = 0.0;
-  for (int64_t r = bid * kBlock + threadIdx.x; r < a.p; r += nblk * kBlock) {
+  const int64_t p = clipped_hi(a.p, a.p_active);
+  for (int64_t r = bid * kBlock + threadIdx.x; r < p; r += nblk * kBlock) {
     if (a.d[r] == 0.0) continue;
     const int32_t j = a.perm[r];
     const double len = (double)(a.cp[j + 1] - a.cp[j]);
@@ -609,6 +627,8 @@ template <int LOSS>
 __device__ __forceinline__ void linesearch_body(const LsArgs& a, int bx, int by, int G) {
   __shared__ double red[kWavesPerBlock][kQGroup];
   __shared__ double lds4[kWavesPerBlock];
+  // no active feature in this bundle (shrinking): the apply skips it too
+  if (clipped_hi(a.slot_hi, a.p_active) <= a.slot_lo) return;
   const int lane = lane_id(), wv = wave_in_block();
   const int q_lo = by * kQGroup;
   const int nq = a.Q - q_lo < kQGroup ? a.Q - q_lo : kQGroup;
@@ -650,7 +670,7 @@ __device__ __forceinline__ void linesearch_body(const LsArgs& a, int bx, int by,
   double del = 0.0;
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
-  const int64_t Pt = a.slot_hi - a.slot_lo;
+  const int64_t Pt = clipped_hi(a.slot_hi, a.p_active) - a.slot_lo;
   for (int64_t r = bx * (int64_t)kBlock + threadIdx.x; r < Pt;
        r += (int64_t)G * kBlock) {
     const int64_t slot = a.slot_lo + r;
@@ -708,6 +728,8 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
 template <int LOSS>
 __device__ __forceinline__ void apply_body(const ApplyArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
+  const int64_t hi_active = clipped_hi(a.slot_hi, a.p_active);
+  if (hi_active <= a.slot_lo) return;  // no active feature in this bundle: nothing ran
   const double Delta = ls_total(a.part, 2 * a.Q, a.ls_blocks, lds4);
   double Dq = Delta, al = 1.0, dF = 0.0;
   int q_acc = -1;
@@ -750,7 +772,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, int64_t bid, int6
     a.dtx[i] = 0.0;
   }
   if (q_acc >= 0) {
-    for (int64_t r = a.slot_lo + tid; r < a.slot_hi; r += nthr) a.w[a.perm[r]] += al * a.d[r];
+    for (int64_t r = a.slot_lo + tid; r < hi_active; r += nthr) a.w[a.perm[r]] += al * a.d[r];
   }
 }
 
@@ -870,9 +892,16 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
   const SweepArgs& a = na.sw;
   const int tid = threadIdx.x;
   double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0;
-  for (int64_t t = na.t_begin; t < na.t_end; ++t) {
+  int64_t t_end = na.t_end, p_lim = na.p;
+  if (na.p_active) {  // shrinking: bundles of the active features only
+    const int64_t pa = (int64_t)*na.p_active;
+    if (pa < p_lim) p_lim = pa;
+    const int64_t te = (p_lim + na.P - 1) / na.P;
+    if (te < t_end) t_end = te;
+  }
+  for (int64_t t = na.t_begin; t < t_end; ++t) {
     const int64_t lo = t * na.P;
-    const int64_t hi = lo + na.P < na.p ? lo + na.P : na.p;
+    const int64_t hi = lo + na.P < p_lim ? lo + na.P : p_lim;
     const int32_t ns = (int32_t)(hi - lo);
     const int64_t base = na.poff[lo];
     // bundle metadata into LDS; clear the per-slot sums
@@ -1114,7 +1143,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     }
     if (q_acc >= 0)
       for (int32_t s = tid; s < ns; s += kNarrowBlock) na.w[L.feat[s]] = L.w[s] + al * L.d[s];
-    if (tid == 0 && t == na.t_end - 1) {
+    if (tid == 0 && t == t_end - 1) {
       na.st->q = q_acc;
       na.st->alpha = q_acc >= 0 ? al : 0.0;
       na.st->dF = dF;
@@ -1210,6 +1239,72 @@ __global__ __launch_bounds__(kBlock) void k_sum_partial(SumArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_sum_final(SumArgs a) { sum_final_body(a); }
 
+// Shrinking's stopping reduction (see StopSumArgs): four values per block in
+// a fixed order, then the final level in block order.
+__device__ inline double block_max(double v, double* lds4) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  if (lane_id() == 0) lds4[wave_in_block()] = v;
+  __syncthreads();
+  double r = lds4[0];
+  for (int k = 1; k < kWavesPerBlock; ++k) r = fmax(r, lds4[k]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void stop_partial_body(const StopSumArgs& a, int64_t bid, int64_t nblk) {
+  __shared__ double lds4[kWavesPerBlock];
+  double sg = 0.0, mx = 0.0, na = 0.0, nz = 0.0;
+  for (int64_t j = bid * kBlock + threadIdx.x; j < a.p; j += nblk * kBlock) {
+    const double v = a.sg[j];
+    sg += v;
+    mx = fmax(mx, v);
+    if (a.act[j] != 0.0) {
+      na += 1.0;
+      nz += (double)(a.cp[j + 1] - a.cp[j]);
+    }
+  }
+  sg = block_sum(sg, lds4);
+  mx = block_max(mx, lds4);
+  na = block_sum(na, lds4);
+  nz = block_sum(nz, lds4);
+  if (threadIdx.x == 0) {
+    a.part[4 * bid + 0] = sg;
+    a.part[4 * bid + 1] = mx;
+    a.part[4 * bid + 2] = na;
+    a.part[4 * bid + 3] = nz;
+  }
+}
+
+__device__ __forceinline__ void stop_final_body(const StopSumArgs& a) {
+  __shared__ double lds4[kWavesPerBlock];
+  double sg = 0.0, mx = 0.0, na = 0.0, nz = 0.0;
+  for (int b = threadIdx.x; b < a.nb; b += kBlock) {
+    sg += a.part[4 * b + 0];
+    mx = fmax(mx, a.part[4 * b + 1]);
+    na += a.part[4 * b + 2];
+    nz += a.part[4 * b + 3];
+  }
+  sg = block_sum(sg, lds4);
+  mx = block_max(mx, lds4);
+  na = block_sum(na, lds4);
+  nz = block_sum(nz, lds4);
+  if (threadIdx.x == 0) {
+    a.scal[0] = sg;
+    a.scal[3] = mx;
+    a.scal[4] = 1.0 - mx / (double)a.n;
+    a.scal[5] = na;
+    a.scal[6] = nz;
+    if (a.it) a.it->k += 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stop_partial(StopSumArgs a) {
+  stop_partial_body(a, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_stop_final(StopSumArgs a) { stop_final_body(a); }
+
 // ---------------------------------------------------------------------------
 // Multi-problem executor: one launch runs one task of each of several
 // independent problems.  Block b finds its task i (first[i] <= b <
@@ -1238,6 +1333,8 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskScatterCount: scatter_count_body(t.u.sc, lb, t.nblk); break;
     case kTaskSumPartial: sum_partial_body(t.u.sum, lb, t.nblk); break;
     case kTaskSumFinal: sum_final_body(t.u.sum); break;
+    case kTaskStopPartial: stop_partial_body(t.u.stop, lb, t.nblk); break;
+    case kTaskStopFinal: stop_final_body(t.u.stop); break;
     default: break;
   }
 }
@@ -1322,9 +1419,9 @@ hipError_t launch_fill(double* a, double v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
-                            uint32_t* keys, int32_t* idx, hipStream_t s) {
+                            const double* act, uint32_t* keys, int32_t* idx, hipStream_t s) {
   hipLaunchKernelGGL(k_perm_keys, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, it,
-                     seed, k, p, keys, idx);
+                     seed, k, p, act, keys, idx);
   return hipGetLastError();
 }
 
@@ -1497,8 +1594,9 @@ hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipSt
 }
 
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, bool narrow, Stats* stats, hipStream_t s) {
-  const ScatterCountArgs a{d, perm, cp, p, narrow ? 1 : 0, stats};
+                                int64_t p, bool narrow, const double* p_active, Stats* stats,
+                                hipStream_t s) {
+  const ScatterCountArgs a{d, perm, cp, p, narrow ? 1 : 0, stats, p_active};
   hipLaunchKernelGGL(k_scatter_count, dim3(scatter_count_grid(p)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
@@ -1509,6 +1607,12 @@ hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, Ite
   const SumArgs a{x, m, part, out, it, nb};
   hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop_sum(const StopSumArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_stop_partial, dim3(a.nb), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_stop_final, dim3(1), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

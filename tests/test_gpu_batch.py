@@ -262,3 +262,51 @@ def test_iterate_batch_matches_sequential_and_oracle(pc):
         assert G == pytest.approx(io["subgrad"], rel=1e-5)
     for s in a + b:
         s.close()
+
+
+def test_batch_shrink_jobs(pc):
+    """Shrinking jobs beside plain ones, on both schedules: each batched job
+    equals its solve alone and the oracle's shrinking solve."""
+    c1 = synth.c1()
+    rnd = synth.bernoulli_csc(78, 1500, 4000, 0.008)
+    jobs = [(c1, "lr", 1.0, 32, 1e-4, {"shrink": True}),
+            (c1, "svm", 1.0, 32, 1e-3, {"shrink": True, "schedule": "wide"}),
+            (rnd, "lr", 2.0, 200, 1e-4, {"shrink": True}),
+            (rnd, "lr", 2.0, 200, 1e-4, {}),
+            (rnd, "svm", 0.5, 400, 1e-3, {"shrink": True, "schedule": "wide"})]
+    solvers = [pc.Solver(device=0).load_data(d) for d, *_ in jobs]
+    specs = [s.job(C, P, eps, loss, seed=3, **o) for s, (d, loss, C, P, eps, o) in zip(solvers, jobs)]
+    batched = pc.solve_batch(specs)
+    for s, (d, loss, C, P, eps, o), b in zip(solvers, jobs, batched):
+        print(f"{loss} C={C} P={P} {o}: outer={b[2]['outer_iters']} swept={b[2]['nnz_swept']}",
+              flush=True)
+        _assert_same_run(b, s.solve(C, P, eps, loss, seed=3, **o))
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d),
+                                  oracle.Params(loss=loss, C=C, shrink=o.get("shrink", False)),
+                                  P=P, eps=eps, seed=3)
+        _assert_oracle(b, (w_o, io), True)
+    assert batched[2][2]["nnz_swept"] < batched[3][2]["nnz_swept"]
+    for s in solvers:
+        s.close()
+
+
+def test_iterate_batch_shrink(pc):
+    """pcdn_iterate_batch with shrinking, continued over two calls: the active
+    set carries over inside each context, as in the oracle's run."""
+    c1 = synth.c1()
+    rnd = synth.bernoulli_csc(79, 1200, 3000, 0.01)
+    cases = [(c1, "lr", 1.0, 32), (rnd, "svm", 1.0, 600)]
+    a = [pc.Solver(device=0).load_data(d) for d, *_ in cases]
+    for s, (d, loss, C, P) in zip(a, cases):
+        s.reset(loss, C)
+    Ps = [P for *_, P in cases]
+    pc.iterate_batch(a, Ps, 0, 3, seed=13, shrink=True)
+    pc.iterate_batch(a, Ps, 3, 3, seed=13, shrink=True)
+    for s, (d, loss, C, P) in zip(a, cases):
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d),
+                                  oracle.Params(loss=loss, C=C, shrink=True),
+                                  P=P, eps=0.0, seed=13, max_outer=6)
+        F, G = s.evaluate()
+        assert F == pytest.approx(io["objective"], rel=RTOL)
+        np.testing.assert_allclose(s.w(), w_o, rtol=RTOL, atol=RTOL * np.max(np.abs(w_o)))
+        s.close()

@@ -165,15 +165,15 @@ def test_step_backtracking_and_failure(pc, schedule):
 # whole solves: final objective
 # --------------------------------------------------------------------------
 def _solve_both(pc, d, loss, C, P, eps, seed=1, max_outer=1000, w0=None, s=None,
-                schedule="auto"):
+                schedule="auto", shrink=False):
     prob = oracle.Problem.from_data(d)
-    w_o, info_o, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C), P=P, eps=eps, seed=seed,
-                                  max_outer=max_outer, w0=w0)
+    w_o, info_o, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C, shrink=shrink), P=P,
+                                  eps=eps, seed=seed, max_outer=max_outer, w0=w0)
     own = s is None
     if own:
         s = _solver(pc, d)
     rc, w_g, info_g = s.solve(C, P, eps, loss, seed=seed, max_outer=max_outer, w0=w0,
-                              schedule=schedule)
+                              schedule=schedule, shrink=shrink)
     if own:
         s.close()
     return (rc, w_g, info_g), (w_o, info_o)
@@ -257,6 +257,57 @@ def test_solve_edge_cases(pc, loss, schedule):
     g, o = _solve_both(pc, d0, loss, 1.0, 2, 1e-6, schedule=schedule)
     _assert_solve_parity(g, o, strict=False)
     assert g[2]["outer_iters"] == 0 and np.all(g[1] == 0)
+
+
+# --------------------------------------------------------------------------
+# shrinking (opt-in): the partition of each outer iteration covers only the
+# features still active after the previous one
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("loss,eps", [("lr", 1e-4), ("svm", 1e-3)])
+def test_shrink_parity_c1(pc, loss, eps, schedule):
+    d = synth.c1()
+    s = _solver(pc, d)
+    g, o = _solve_both(pc, d, loss, 1.0, 32, eps, s=s, schedule=schedule, shrink=True)
+    _assert_solve_parity(g, o)
+    full = s.solve(1.0, 32, eps, loss, seed=1, max_outer=1000, schedule=schedule)
+    s.close()
+    # shrinking must have removed work, and the two runs reach the same optimum
+    assert g[2]["nnz_swept"] < full[2]["nnz_swept"]
+    assert g[2]["objective"] == pytest.approx(full[2]["objective"], rel=1e-3)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("C,P,strict", [(0.5, 64, True), (4.0, 1024, True), (0.5, 1024, False)])
+def test_shrink_parity_c2(pc, C, P, strict, schedule):
+    """At C = 0.5, P = 1024 the ~350 active features form one bundle; its
+    step leaves a coordinate geometrically approaching zero (d_j = -w_j, only
+    alpha < 1 accepted), so the run ends only when a unit step passes an
+    Armijo test whose two sides are at the rounding floor (the objective has
+    stopped changing at 1e-14 relative well before): the outer iteration at
+    which that happens is decided by rounding, on either side."""
+    d = _c2_cached()
+    g, o = _solve_both(pc, d, "lr", C, P, 1e-4, schedule=schedule, shrink=True)
+    _assert_solve_parity(g, o, strict=strict)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_shrink_step_by_step(pc, schedule):
+    """pcdn_iterate with shrinking: after every outer iteration the GPU's
+    active set equals the oracle's, so each partition is the same."""
+    d = synth.c1()
+    prob = oracle.Problem.from_data(d)
+    C, P = 1.0, 32
+    w_o, info_o, hist = oracle.solve(prob, oracle.Params(loss="lr", C=C, shrink=True), P=P,
+                                     eps=1e-4, seed=1, max_outer=6)
+    s = _solver(pc, d)
+    rc, w_g, info_g = s.solve(C, P, 1e-4, "lr", seed=1, max_outer=6, schedule=schedule,
+                              shrink=True)
+    assert info_g["outer_iters"] == info_o["outer_iters"] == 6
+    assert info_g["nnz_swept"] == info_o["nnz_swept"]
+    assert info_g["bundles"] == info_o["bundles"]
+    np.testing.assert_allclose(w_g, w_o, rtol=RTOL, atol=RTOL * np.max(np.abs(w_o)))
+    s.close()
 
 
 def test_warm_start_and_max_outer(pc):
