@@ -22,6 +22,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 LOGISTIC = 0
 L2SVM = 1
 _LOSS = {"lr": LOGISTIC, "logistic": LOGISTIC, "svm": L2SVM, "l2svm": L2SVM}
+PENALTIES = {"l1": 0, "elastic": 1, "l2": 2}
 
 
 def build() -> str:
@@ -42,7 +43,8 @@ class _Par(ctypes.Structure):
     _fields_ = [("loss", ctypes.c_int32), ("max_ls", ctypes.c_int32),
                 ("C", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("nu", ctypes.c_double), ("shrink", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("nu", ctypes.c_double), ("shrink", ctypes.c_int32), ("penalty", ctypes.c_int32),
+                ("l2", ctypes.c_double)]
 
 
 class _StepInfo(ctypes.Structure):
@@ -82,6 +84,8 @@ def lib():
     L.orc_grad_hess.argtypes = [vp, vp, vp, vp, i64, vp, vp]
     L.orc_newton_direction.argtypes = [dbl, dbl, dbl]
     L.orc_newton_direction.restype = dbl
+    L.orc_newton_direction_reg.argtypes = [dbl, dbl, dbl, dbl, dbl]
+    L.orc_newton_direction_reg.restype = dbl
     L.orc_subgrad_l1.argtypes = [vp, vp, vp, vp, vp]
     L.orc_subgrad_l1.restype = dbl
     L.orc_loss_change.argtypes = [i32, dbl, i32, dbl]
@@ -143,14 +147,23 @@ class Params:
     nu: float = 1e-12
     max_ls: int = 30
     shrink: bool = False
+    penalty: int = 0     # "l1" (eq. (1)), "elastic" (|w| + l2/2 w^2) or "l2" (l2/2 w^2)
+    l2: float = 0.0
 
     def __post_init__(self):
         if isinstance(self.loss, str):
             self.loss = _LOSS[self.loss]
+        if isinstance(self.penalty, str):
+            self.penalty = PENALTIES[self.penalty]
+
+    def reg_ab(self) -> tuple:
+        """(a, b) of the regulariser sum_j a |w_j| + (b/2) w_j^2."""
+        return (0.0 if self.penalty == 2 else 1.0, 0.0 if self.penalty == 0 else float(self.l2))
 
     def c(self):
         return _Par(int(self.loss), int(self.max_ls), float(self.C), float(self.sigma),
-                    float(self.beta), float(self.gamma), float(self.nu), int(bool(self.shrink)), 0)
+                    float(self.beta), float(self.gamma), float(self.nu), int(bool(self.shrink)),
+                    int(self.penalty), float(self.l2))
 
 
 def splitmix64(seed: int, i: int) -> int:
@@ -197,8 +210,12 @@ def grad_hess(prob: Problem, par: Params, cache: np.ndarray, feats) -> tuple:
     return g, h
 
 
-def newton_direction(g: float, h: float, w: float) -> float:
-    return float(lib().orc_newton_direction(g, h, w))
+def newton_direction(g: float, h: float, w: float, a: float = None, b: float = None) -> float:
+    """Minimiser of g d + h d^2/2 + a|w+d| + (b/2)(w+d)^2; eq. (5) without a, b."""
+    if a is None and b is None:
+        return float(lib().orc_newton_direction(g, h, w))
+    return float(lib().orc_newton_direction_reg(g, h, w, 1.0 if a is None else a,
+                                                0.0 if b is None else b))
 
 
 def subgrad_l1(prob: Problem, par: Params, w, cache, return_grad=False):

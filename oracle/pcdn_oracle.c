@@ -4,7 +4,9 @@
  * A plain, slow, single-threaded FP64 implementation of Parallel Coordinate
  * Descent Newton (Bian, Li, Liu, Yang: "Parallel Coordinate Descent Newton
  * Method for Efficient L1-Regularized Loss Minimization", arXiv:1306.4080)
- * for L1-regularised logistic regression and L1-regularised L2-loss SVM.
+ * for L1-regularised logistic regression and L1-regularised L2-loss SVM,
+ * and the paper's concluding generalisation to other separable regularisers
+ * (ridge, elastic net).
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
  * load this code.  The GPU library shares no code, header, table or helper with
@@ -26,6 +28,7 @@
 #include <string.h>
 
 enum { ORC_LOGISTIC = 0, ORC_L2SVM = 1 };
+enum { ORC_PEN_L1 = 0, ORC_PEN_ELASTIC = 1, ORC_PEN_L2 = 2 };
 
 /* Design matrix in compressed sparse column form plus labels.  Column j holds
  * rows row_idx[col_ptr[j] .. col_ptr[j+1]) with values val[...]; y[i] = +-1. */
@@ -39,14 +42,29 @@ typedef struct {
 
 /* Loss and Armijo parameters (Sec. 2.1; the experiments use sigma = 0.01,
  * gamma = 0, beta = 0.5; nu = 1e-12 is the Hessian floor of Lemma 1(b)'s
- * proof). */
+ * proof).
+ *
+ * Regulariser.  Eq. (1) is F(w) = ||w||_1 + C sum_i phi_i.  The conclusion
+ * (Sec. 6) extends PCDN to any separable regulariser; this oracle takes
+ * R(w) = sum_j [a |w_j| + (b/2) w_j^2] in place of ||w||_1 everywhere it
+ * appears: in F, in the one-dimensional subproblem eq. (4), in Delta
+ * eq. (7) and in the Armijo test eq. (6).  penalty selects
+ *   ORC_PEN_L1      a = 1, b = 0   (eq. (1), the default)
+ *   ORC_PEN_ELASTIC a = 1, b = l2  (elastic net)
+ *   ORC_PEN_L2      a = 0, b = l2  (ridge).
+ * g_j and h_j stay those of the loss term C sum_i phi_i. */
 typedef struct {
   int32_t loss;
   int32_t max_ls;
   double C, sigma, beta, gamma, nu;
-  int32_t shrink;  /* outer-iteration shrinking (see orc_solve); 0: off */
-  int32_t pad;
+  int32_t shrink;   /* outer-iteration shrinking (see orc_solve); 0: off */
+  int32_t penalty;  /* ORC_PEN_* */
+  double l2;        /* b of the elastic-net and ridge penalties */
 } orc_par;
+
+/* a and b of R for the parameters. */
+static double reg_a(const orc_par* par) { return par->penalty == ORC_PEN_L2 ? 0.0 : 1.0; }
+static double reg_b(const orc_par* par) { return par->penalty == ORC_PEN_L1 ? 0.0 : par->l2; }
 
 typedef struct {
   double alpha;   /* accepted step beta^q, 0 when the search failed        */
@@ -211,21 +229,30 @@ void orc_grad_hess(const orc_X* X, const orc_par* par, const double* cache,
   }
 }
 
-/* Closed-form minimiser of g d + h d^2 / 2 + |w + d| (eqs. (4)-(5)).  The
- * printed case conditions are garbled; minimising eq. (4) gives the
- * soft-threshold rule below. */
-double orc_newton_direction(double g, double h, double w) {
-  if (g + 1.0 <= h * w) return -(g + 1.0) / h;
-  if (g - 1.0 >= h * w) return -(g - 1.0) / h;
+/* Closed-form minimiser over d of g d + h d^2 / 2 + R_j(w + d) (eq. (4) with
+ * R_j(u) = a |u| + (b/2) u^2 in place of |u|).  With u = w + d, stationarity
+ * reads g + h (u - w) + b u + a sign(u) = 0, so u > 0 exactly when
+ * g + a < h w, u < 0 exactly when g - a > h w, and u = 0 otherwise.  For
+ * a = 1, b = 0 this is eq. (5) (whose printed case conditions are garbled;
+ * minimising eq. (4) gives the rule below). */
+double orc_newton_direction_reg(double g, double h, double w, double a, double b) {
+  if (g + a <= h * w) return -(g + a + b * w) / (h + b);
+  if (g - a >= h * w) return -(g - a + b * w) / (h + b);
   return -w;
 }
 
-/* Minimum-norm subgradient component of F at w_j given g_j = grad_j L(w). */
-static double min_norm_subgrad(double g, double w) {
-  if (w > 0.0) return g + 1.0;
-  if (w < 0.0) return g - 1.0;
-  if (g < -1.0) return g + 1.0;
-  if (g > 1.0) return g - 1.0;
+double orc_newton_direction(double g, double h, double w) {
+  return orc_newton_direction_reg(g, h, w, 1.0, 0.0);
+}
+
+/* Minimum-norm subgradient component of F at w_j given g_j = grad_j L(w):
+ * the gradient of the smooth part is G = g + b w, the nonsmooth part a|w|. */
+static double min_norm_subgrad(double g, double w, double a, double b) {
+  double G = g + b * w;
+  if (w > 0.0) return G + a;
+  if (w < 0.0) return G - a;
+  if (G < -a) return G + a;
+  if (G > a) return G - a;
   return 0.0;
 }
 
@@ -239,7 +266,8 @@ double orc_subgrad_l1(const orc_X* X, const orc_par* par, const double* w,
   for (int64_t j = 0; j < X->p; ++j) all[j] = (int32_t)j;
   orc_grad_hess(X, par, cache, all, X->p, g, h);
   double G = 0.0;
-  for (int64_t j = 0; j < X->p; ++j) G += fabs(min_norm_subgrad(g[j], w[j]));
+  const double ra = reg_a(par), rb = reg_b(par);
+  for (int64_t j = 0; j < X->p; ++j) G += fabs(min_norm_subgrad(g[j], w[j], ra, rb));
   if (gfull) memcpy(gfull, g, (size_t)X->p * sizeof(double));
   free(all);
   free(g);
@@ -283,7 +311,18 @@ double orc_loss_change(int32_t loss, double cache, int32_t y, double a) {
   return loss_change(loss, cache, y, a);
 }
 
-/* F(w) = ||w||_1 + C sum_i phi_i (eq. (1)), from the retained quantities. */
+/* R(w) = a ||w||_1 + (b/2) ||w||_2^2 */
+static double regulariser(const orc_par* par, const double* w, int64_t p) {
+  double l1 = 0.0, sq = 0.0;
+  for (int64_t j = 0; j < p; ++j) {
+    l1 += fabs(w[j]);
+    sq += w[j] * w[j];
+  }
+  return reg_a(par) * l1 + 0.5 * reg_b(par) * sq;
+}
+
+/* F(w) = R(w) + C sum_i phi_i (eq. (1) with the regulariser above), from the
+ * retained quantities. */
 double orc_objective_cache(const orc_X* X, const orc_par* par, const double* w,
                            const double* cache) {
   double s = 0.0;
@@ -296,9 +335,7 @@ double orc_objective_cache(const orc_X* X, const orc_par* par, const double* w,
       s += b * b;
     }
   }
-  double l1 = 0.0;
-  for (int64_t j = 0; j < X->p; ++j) l1 += fabs(w[j]);
-  return l1 + par->C * s;
+  return regulariser(par, w, X->p) + par->C * s;
 }
 
 /* F(w) evaluated from X and w directly (no retained quantities). */
@@ -317,15 +354,13 @@ double orc_objective_direct(const orc_X* X, const orc_par* par, const double* w)
     }
   }
   free(z);
-  double l1 = 0.0;
-  for (int64_t j = 0; j < X->p; ++j) l1 += fabs(w[j]);
-  return l1 + par->C * s;
+  return regulariser(par, w, X->p) + par->C * s;
 }
 
 /* ------------------------------------------------------------------------ */
 /* One inner iteration t of Algorithm 3 on bundle B (size P):                */
 /*   1. d_j = d(w; j) for every j in B (parallel loop of Algorithm 3);       */
-/*   2. Delta by eq. (7) with H = diag(h);                                   */
+/*   2. Delta by eq. (7) with H = diag(h) and R in place of ||.||_1;         */
 /*   3. Algorithm 4: d^T x_i for every sample; for q = 0, 1, ...: test the   */
 /*      descent condition eq. (10) with the scaled d^T x_i and Delta; on     */
 /*      acceptance w += beta^q d and e^{w^T x_i} *= e^{beta^q d^T x_i}       */
@@ -344,14 +379,18 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
   double* a = (double*)malloc((size_t)X->n * sizeof(double));
 
   /* 1. one-dimensional Newton directions */
+  const double ra = reg_a(par), rb = reg_b(par);
   orc_grad_hess(X, par, cache, bundle, P, g, h);
-  for (int64_t t = 0; t < P; ++t) d[t] = orc_newton_direction(g[t], h[t], w[bundle[t]]);
+  for (int64_t t = 0; t < P; ++t)
+    d[t] = orc_newton_direction_reg(g[t], h[t], w[bundle[t]], ra, rb);
 
-  /* 2. Delta (eq. (7)) */
+  /* 2. Delta (eq. (7)); R_j(w + d) - R_j(w) is formed per coordinate, its
+   *    quadratic part as b d (w + d/2) */
   double Delta = 0.0;
   for (int64_t t = 0; t < P; ++t) {
     double wj = w[bundle[t]];
-    Delta += g[t] * d[t] + par->gamma * h[t] * d[t] * d[t] + fabs(wj + d[t]) - fabs(wj);
+    Delta += g[t] * d[t] + par->gamma * h[t] * d[t] * d[t] + ra * fabs(wj + d[t]) -
+             ra * fabs(wj) + rb * d[t] * (wj + 0.5 * d[t]);
   }
 
   /* 3. Algorithm 4: d^T x_i */
@@ -366,10 +405,10 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
   double Dq = Delta, alpha = 1.0, dF = 0.0;
   int32_t q_acc = -1;
   for (int32_t q = 0; q < par->max_ls; ++q) {
-    double l1 = 0.0;
+    double l1 = 0.0; /* R(w + alpha d) - R(w) */
     for (int64_t t = 0; t < P; ++t) {
-      double wj = w[bundle[t]];
-      l1 += fabs(wj + alpha * d[t]) - fabs(wj);
+      double wj = w[bundle[t]], s = alpha * d[t];
+      l1 += ra * fabs(wj + s) - ra * fabs(wj) + rb * s * (wj + 0.5 * s);
     }
     double sL = 0.0;
     for (int64_t i = 0; i < X->n; ++i) sL += loss_change(par->loss, cache[i], X->y[i], a[i]);
@@ -423,13 +462,14 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
 /* Shrinking (par->shrink; the paper's experiments shrink between outer     */
 /* iterations, not inside the parallel loop, and give no rule): after outer */
 /* iteration k, with the gradient g at w^k, feature j stays active for      */
-/* iteration k+1 iff w_j != 0 or |g_j| >= 1 - M_{k-1}/n, where M_{k-1} is   */
+/* iteration k+1 iff w_j != 0 or |g_j| >= a - M_{k-1}/n, where M_{k-1} is   */
 /* the largest |grad^S_j F| over all features after iteration k-1          */
-/* (M_{-1} = infinity: the first two iterations use every feature; the      */
-/* threshold is LIBLINEAR's CDN rule).  Iteration k+1 partitions only the   */
-/* active features (orc_permutation_active) into bundles of P.  The         */
-/* stopping rule is unchanged: it uses all features, and a feature is only  */
-/* left out while its minimum-norm subgradient is 0.                        */
+/* (M_{-1} = infinity: the first two iterations use every feature; with     */
+/* a = 1 the threshold is LIBLINEAR's CDN rule, and with a = 0, ridge, no   */
+/* feature is ever left out).  Iteration k+1 partitions only the active     */
+/* features (orc_permutation_active) into bundles of P.  The stopping rule  */
+/* is unchanged: it uses all features, and a feature is only left out while */
+/* its minimum-norm subgradient is 0.                                       */
 /* ------------------------------------------------------------------------ */
 int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
                   uint64_t seed, int32_t max_outer, double* w, orc_info* info,
@@ -487,9 +527,9 @@ int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
     converged = I.subgrad <= eps * I.subgrad0;
     if (par->shrink) {
       double M = 0.0;
-      const double thr = 1.0 - M_prev / (double)n;
+      const double thr = reg_a(par) - M_prev / (double)n;
       for (int64_t j = 0; j < p; ++j) {
-        const double v = fabs(min_norm_subgrad(gfull[j], w[j]));
+        const double v = fabs(min_norm_subgrad(gfull[j], w[j], reg_a(par), reg_b(par)));
         if (v > M) M = v;
         active[j] = (w[j] != 0.0 || fabs(gfull[j]) >= thr) ? 1 : 0;
       }

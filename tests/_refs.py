@@ -28,8 +28,9 @@ def loss_vec(z, y, loss):
     return np.where(b > 0, b * b, 0.0)
 
 
-def F_dense(X, y, w, C, loss):
-    return float(np.abs(w).sum() + C * loss_vec(X @ w, y, loss).sum())
+def F_dense(X, y, w, C, loss, a=1.0, b=0.0):
+    """a ||w||_1 + (b/2) ||w||^2 + C sum_i phi_i (eq. (1) for a = 1, b = 0)."""
+    return float(a * np.abs(w).sum() + 0.5 * b * np.dot(w, w) + C * loss_vec(X @ w, y, loss).sum())
 
 
 def _mp_loss(zm, yi, loss):
@@ -39,8 +40,9 @@ def _mp_loss(zm, yi, loss):
     return b * b if b > 0 else mpmath.mpf(0)
 
 
-def F_mp(X, y, w, C, loss, dps=50):
-    """F(w) in multiprecision from the dense matrix (entries taken exactly)."""
+def F_mp(X, y, w, C, loss, dps=50, a=1, b=0):
+    """F(w) in multiprecision from the dense matrix (entries taken exactly),
+    with the regulariser a ||w||_1 + (b/2) ||w||^2."""
     with mpmath.workdps(dps):
         W = [mpmath.mpf(float(v)) for v in w]
         s = mpmath.mpf(0)
@@ -48,7 +50,10 @@ def F_mp(X, y, w, C, loss, dps=50):
             zi = mpmath.fsum(mpmath.mpf(float(X[i, j])) * W[j]
                              for j in range(X.shape[1]) if X[i, j] != 0)
             s += _mp_loss(zi, int(y[i]), loss)
-        return mpmath.fsum(abs(v) for v in W) + mpmath.mpf(C) * s
+        reg = mpmath.mpf(a) * mpmath.fsum(abs(v) for v in W)
+        if b:
+            reg += mpmath.mpf(b) / 2 * mpmath.fsum(v * v for v in W)
+        return reg + mpmath.mpf(C) * s
 
 
 def L_mp_shift(X, y, w, C, loss, j, eps, dps=60):
@@ -92,8 +97,10 @@ def loss_change_mp(loss, E, y, a, dps=60):
 # --------------------------------------------------------------------------
 # the one-dimensional subproblem, eq. (4), minimised numerically
 # --------------------------------------------------------------------------
-def subproblem_value(g, h, w, d):
-    return g * d + 0.5 * h * d * d + abs(w + d)
+def subproblem_value(g, h, w, d, a=1.0, b=0.0):
+    """Eq. (4) with the regulariser a|u| + (b/2)u^2 in place of |u| (the
+    constant R(w) dropped)."""
+    return g * d + 0.5 * h * d * d + a * abs(w + d) + 0.5 * b * (w + d) ** 2
 
 
 def golden_section_min(f, lo, hi, iters=400):
@@ -132,7 +139,8 @@ def lemma1a_expected_max(lams, P):
 # Algorithm 1 (CDN), with the 1-D Armijo search by direct multiprecision
 # evaluation of F (no retained quantities)
 # --------------------------------------------------------------------------
-def cdn(X, y, C, loss, orders, sigma=0.01, beta=0.5, gamma=0.0, nu=1e-12, max_ls=30):
+def cdn(X, y, C, loss, orders, sigma=0.01, beta=0.5, gamma=0.0, nu=1e-12, max_ls=30,
+        a=1.0, b=0.0):
     n, p = X.shape
     w = np.zeros(p)
     for order in orders:
@@ -145,25 +153,26 @@ def cdn(X, y, C, loss, orders, sigma=0.01, beta=0.5, gamma=0.0, nu=1e-12, max_ls
                 g = -C * np.sum(err * y * x)
                 h = C * np.sum(err * (1.0 - err) * x * x)
             else:
-                b = 1.0 - y * z
-                act = b > 0
-                g = -2.0 * C * np.sum((y * x * b)[act])
+                bz = 1.0 - y * z
+                act = bz > 0
+                g = -2.0 * C * np.sum((y * x * bz)[act])
                 h = 2.0 * C * np.sum((x * x)[act])
             if h <= 0:
                 h += nu
             # 1-D subproblem by numerical minimisation, then the kink if lower
-            R = (abs(g) + 1.0) / h + abs(w[j]) + 1.0
-            f = lambda dd: subproblem_value(g, h, w[j], dd)
+            R = (abs(g) + a) / h + (1.0 + b / h) * abs(w[j]) + 1.0
+            f = lambda dd: subproblem_value(g, h, w[j], dd, a, b)
             d = golden_section_min(f, -R, R)
             if f(-w[j]) <= f(d):
                 d = -w[j]
-            delta = g * d + gamma * h * d * d + abs(w[j] + d) - abs(w[j])
-            F0 = F_mp(X, y, w, C, loss)
+            reg = lambda u: a * abs(u) + 0.5 * b * u * u
+            delta = g * d + gamma * h * d * d + reg(w[j] + d) - reg(w[j])
+            F0 = F_mp(X, y, w, C, loss, a=a, b=b)
             alpha = 1.0
             for _ in range(max_ls):
                 wn = w.copy()
                 wn[j] += alpha * d
-                if F_mp(X, y, wn, C, loss) - F0 <= sigma * alpha * delta:
+                if F_mp(X, y, wn, C, loss, a=a, b=b) - F0 <= sigma * alpha * delta:
                     w = wn
                     break
                 alpha *= beta
@@ -173,29 +182,30 @@ def cdn(X, y, C, loss, orders, sigma=0.01, beta=0.5, gamma=0.0, nu=1e-12, max_ls
 # --------------------------------------------------------------------------
 # exact optimum of tiny problems by enumerating sign patterns
 # --------------------------------------------------------------------------
-def _smooth_min(Xs, y, C, loss, s):
-    """argmin_v C sum phi(X_s v) + s.v by damped Newton; None if unbounded."""
+def _smooth_min(Xs, y, C, loss, s, b=0.0):
+    """argmin_v C sum phi(X_s v) + s.v + (b/2)||v||^2 by damped Newton; None if
+    unbounded."""
     m = Xs.shape[1]
     v = np.zeros(m)
 
     def f(v):
-        return C * loss_vec(Xs @ v, y, loss).sum() + s @ v
+        return C * loss_vec(Xs @ v, y, loss).sum() + s @ v + 0.5 * b * (v @ v)
 
     scale = 1.0 + C * np.abs(Xs).sum()
     for _ in range(500):
         z = Xs @ v
         if loss == "lr":
             err = 1.0 / (1.0 + np.exp(y * z))
-            grad = -C * Xs.T @ (y * err) + s
+            grad = -C * Xs.T @ (y * err) + s + b * v
             D = C * err * (1.0 - err)
         else:
-            b = 1.0 - y * z
-            act = (b > 0).astype(float)
-            grad = -2.0 * C * Xs.T @ (y * b * act) + s
+            bb = 1.0 - y * z
+            act = (bb > 0).astype(float)
+            grad = -2.0 * C * Xs.T @ (y * bb * act) + s + b * v
             D = 2.0 * C * act
         if np.max(np.abs(grad)) <= 1e-13 * scale:
             return v
-        H = Xs.T @ (D[:, None] * Xs)
+        H = Xs.T @ (D[:, None] * Xs) + b * np.eye(m)
         step = np.linalg.lstsq(H, -grad, rcond=1e-14)[0]
         if not np.all(np.isfinite(step)) or grad @ step >= 0:
             step = -grad
@@ -210,22 +220,30 @@ def _smooth_min(Xs, y, C, loss, s):
     return v
 
 
-def brute_force_optimum(X, y, C, loss):
-    """min F over w by enumerating sign patterns {-,0,+}^p (p <= 5)."""
+def brute_force_optimum(X, y, C, loss, a=1.0, b=0.0):
+    """min F over w by enumerating sign patterns {-,0,+}^p (p <= 5); F with the
+    regulariser a ||w||_1 + (b/2) ||w||^2."""
     n, p = X.shape
-    best = F_dense(X, y, np.zeros(p), C, loss)
+    best = F_dense(X, y, np.zeros(p), C, loss, a, b)
     best_w = np.zeros(p)
     for s in itertools.product((-1, 0, 1), repeat=p):
         s = np.array(s, dtype=float)
         S = np.flatnonzero(s)
         if len(S) == 0:
             continue
-        v = _smooth_min(X[:, S], y, C, loss, s[S])
+        v = _smooth_min(X[:, S], y, C, loss, a * s[S], b)
         if v is None or np.any(s[S] * v < -1e-12):
             continue
         w = np.zeros(p)
         w[S] = v
-        Fw = F_dense(X, y, w, C, loss)
+        Fw = F_dense(X, y, w, C, loss, a, b)
         if Fw < best:
             best, best_w = Fw, w
     return best, best_w
+
+
+def ridge_optimum(X, y, C, loss, b):
+    """min (b/2)||w||^2 + C sum phi (smooth and strongly convex): damped Newton
+    over every feature at once."""
+    w = _smooth_min(X, y, C, loss, np.zeros(X.shape[1]), b)
+    return F_dense(X, y, w, C, loss, 0.0, b), w

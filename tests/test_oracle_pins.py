@@ -467,3 +467,157 @@ def test_shrinking_kkt_monotone_and_less_work(loss):
     assert np.all(np.diff(t) <= 1e-12 * np.abs(t[:-1]))
     assert info["objective"] == pytest.approx(base["objective"], rel=1e-8)
     assert info["nnz_swept"] < base["nnz_swept"]
+
+
+# --------------------------------------------------------------------------
+# separable regularisers (the generalisation in the conclusion, Sec. 6):
+# R(w) = sum_j a |w_j| + (b/2) w_j^2 in place of ||w||_1 in eqs. (1), (4),
+# (6), (7); ridge a = 0, elastic net a = 1, b > 0
+# --------------------------------------------------------------------------
+REGS = [("elastic", 1.0, 0.5), ("elastic", 1.0, 3.0), ("l2", 0.0, 0.7)]
+
+
+@pytest.mark.parametrize("a,b", [(1.0, 0.5), (1.0, 3.0), (0.0, 0.7), (0.0, 5.0), (1.0, 0.0)])
+def test_regularised_direction_minimises_subproblem(a, b):
+    """The closed form returns the minimiser of g d + h d^2/2 + a|w+d| +
+    (b/2)(w+d)^2, against golden-section minimisation and the kink at -w."""
+    cases = _direction_cases() + [(a + 0.7 * 2.0, 2.0, 0.7), (-a - 3.0, 3.0, -1.0)]
+    for g, h, w in cases:
+        d = oracle.newton_direction(g, h, w, a, b)
+        f = lambda x: R.subproblem_value(g, h, w, x, a, b)
+        scale = (abs(g) + a) / h + abs(w) + 1.0
+        bf = R.golden_section_min(f, -scale, scale)
+        if f(-w) <= f(bf):
+            bf = -w
+        assert f(d) <= f(bf) + 1e-12 * (1.0 + abs(f(bf))), (g, h, w, d, bf)
+        assert abs(d - bf) <= 1e-5 * (1.0 + abs(bf)), (g, h, w, d, bf)
+        if b == 0.0 and a == 1.0:
+            assert d == oracle.newton_direction(g, h, w)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("pen,a,b", REGS)
+def test_regularised_step_dF_equals_objective_difference(loss, pen, a, b):
+    """The accepted dF equals F(w + alpha d) - F(w) of the regularised
+    objective recomputed from X in multiprecision; eq. (6) holds with Delta."""
+    d = synth.tiny(32, n=30, p=6, density=0.6)
+    X, y = d.dense(), d.y.astype(float)
+    prob = _prob(d)
+    par = oracle.Params(loss=loss, C=2.0, penalty=pen, l2=b)
+    rng = np.random.default_rng(10)
+    w = rng.normal(0, 0.3, d.p) * (rng.random(d.p) < 0.6)
+    cache = oracle.cache_from_w(prob, loss, w)
+    for bundle in ([0, 2, 4], [1, 3, 5], [5], list(range(6))):
+        w_old = w.copy()
+        s = oracle.step(prob, par, w, cache, bundle)
+        assert s["q"] >= 0
+        dmp = float(R.F_mp(X, y, w, 2.0, loss, a=a, b=b) - R.F_mp(X, y, w_old, 2.0, loss, a=a, b=b))
+        assert s["dF"] == pytest.approx(dmp, rel=1e-9, abs=1e-12)
+        assert s["dF"] <= par.sigma * s["alpha"] * s["delta"] + 1e-15
+        # Delta from its definition with R in place of the l1 norm
+        wb, dd, g, h = w_old[bundle], s["d"], s["g"], s["h"]
+        reg = lambda u: a * np.abs(u) + 0.5 * b * u * u
+        assert s["delta"] == pytest.approx(float(np.sum(g * dd + reg(wb + dd) - reg(wb))),
+                                           rel=1e-12, abs=1e-14)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("seed", [1, 2])
+@pytest.mark.parametrize("b", [0.5, 3.0])
+def test_elastic_net_reaches_brute_force_optimum(loss, seed, b):
+    d = synth.tiny(110 + seed, n=30, p=4, density=0.8, flip=0.15)
+    X, y = d.dense(), d.y.astype(float)
+    prob = _prob(d)
+    C = [0.8, 2.5][seed - 1]
+    Fstar, wstar = R.brute_force_optimum(X, y, C, loss, 1.0, b)
+    for P in (1, 2, 4):
+        par = oracle.Params(loss=loss, C=C, penalty="elastic", l2=b)
+        w, info, _ = oracle.solve(prob, par, P=P, eps=1e-12, seed=seed, max_outer=5000)
+        assert info["converged"] == 1
+        assert info["objective"] == pytest.approx(Fstar, rel=1e-9, abs=1e-12), (P, w, wstar)
+        assert info["objective"] == pytest.approx(R.F_dense(X, y, w, C, loss, 1.0, b), rel=1e-12)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("b", [0.1, 2.0])
+def test_ridge_matches_newton_optimum(loss, b):
+    """Ridge (a = 0) is smooth and strongly convex: PCDN reaches the optimum
+    that Newton's method finds with every feature at once."""
+    d = synth.tiny(120, n=200, p=30, density=0.2)
+    X, y = d.dense(), d.y.astype(float)
+    prob = _prob(d)
+    C = 1.0
+    Fstar, wstar = R.ridge_optimum(X, y, C, loss, b)
+    for P in (1, 8, 30):
+        par = oracle.Params(loss=loss, C=C, penalty="l2", l2=b)
+        w, info, _ = oracle.solve(prob, par, P=P, eps=1e-11, seed=3, max_outer=20000)
+        assert info["converged"] == 1
+        assert info["objective"] == pytest.approx(Fstar, rel=1e-10)
+        np.testing.assert_allclose(w, wstar, rtol=1e-5, atol=1e-7 * np.abs(wstar).max())
+        # stopping reference at w = 0 is ||grad L(0)||_1 (no soft threshold)
+        g0 = (-0.5 if loss == "lr" else -2.0) * C * X.T @ y
+        assert info["subgrad0"] == pytest.approx(np.abs(g0).sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("pen,a,b", REGS)
+def test_regularised_P1_equals_independent_cdn(loss, pen, a, b):
+    """P = 1 is CDN (Algorithm 1) on the regularised objective: 1-D subproblem
+    minimised numerically, line search by direct multiprecision F."""
+    d = synth.tiny(56, n=40, p=6, density=0.6)
+    X, y = d.dense(), d.y.astype(float)
+    prob = _prob(d)
+    C, K, seed = 1.5, 4, 9
+    orders = [oracle.permutation(seed, k, d.p) for k in range(K)]
+    w_cdn = R.cdn(X, y, C, loss, orders, a=a, b=b)
+    par = oracle.Params(loss=loss, C=C, penalty=pen, l2=b)
+    w, info, _ = oracle.solve(prob, par, P=1, eps=0.0, seed=seed, max_outer=K)
+    assert info["outer_iters"] == K
+    np.testing.assert_allclose(w, w_cdn, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("shrink", [False, True])
+def test_elastic_net_kkt_and_monotone_on_c1(loss, shrink):
+    """Elastic net on C1 (and a small SVM problem), with and without
+    shrinking: F never increases and the optimality conditions hold at the
+    returned w with a dense gradient: |G_j + sign(w_j)| small where w_j != 0,
+    |G_j| <= 1 where w_j = 0, G = grad L + b w."""
+    d = synth.c1() if loss == "lr" else synth.tiny(41, n=300, p=80, density=0.1, binary=True)
+    X, y = d.dense(), d.y.astype(float)
+    prob = _prob(d)
+    C, b = 1.0, 0.8
+    par = oracle.Params(loss=loss, C=C, penalty="elastic", l2=b, shrink=shrink)
+    w, info, trace = oracle.solve(prob, par, P=16, eps=1e-8, seed=4, max_outer=3000)
+    assert info["converged"] == 1
+    assert np.all(np.diff(trace) <= 1e-12 * abs(trace[0]))
+    z = X @ w
+    if loss == "lr":
+        g = -C * X.T @ (y / (1.0 + np.exp(y * z)))
+    else:
+        bb = 1.0 - y * z
+        g = -2.0 * C * X.T @ (y * bb * (bb > 0))
+    G = g + b * w
+    G0 = info["subgrad0"]
+    nz = w != 0
+    assert np.all(np.abs(G[nz] + np.sign(w[nz])) <= 1e-6 * G0)
+    assert np.all(np.abs(G[~nz]) <= 1.0 + 1e-6 * G0)
+    assert info["objective"] == pytest.approx(R.F_dense(X, y, w, C, loss, 1.0, b), rel=1e-12)
+
+
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_ridge_shrinking_leaves_nothing_out(loss):
+    """With a = 0 the shrinking threshold a - M/n is <= 0: every feature,
+    including empty columns that keep w_j = 0, stays active, so the shrinking
+    solve is the plain one step for step."""
+    d = synth.tiny(121, n=120, p=23, density=0.25, empty_cols=(0, 7, 8, 15))
+    prob = _prob(d)
+    runs = []
+    for shrink in (False, True):
+        par = oracle.Params(loss=loss, C=1.0, penalty="l2", l2=0.3, shrink=shrink)
+        runs.append(oracle.solve(prob, par, P=4, eps=1e-9, seed=2, max_outer=5000))
+    (w0, i0, _), (w1, i1, _) = runs
+    assert i0["converged"] == i1["converged"] == 1
+    for k in ("outer_iters", "bundles", "ls_steps", "nnz_swept"):
+        assert i0[k] == i1[k], k
+    assert np.array_equal(w0, w1)
