@@ -64,7 +64,26 @@ typedef struct {
   const double* w0;     /* host, p entries, warm start; NULL: zeros         */
   int32_t schedule;     /* PCDN_SCHED_*: how bundles map onto the GPU       */
   int32_t shrink;       /* 1: outer-iteration shrinking (below); 0: off     */
+  int32_t penalty;      /* PCDN_PENALTY_*: the regulariser (below)          */
+  int32_t reserved;     /* set to 0                                         */
+  double l2;            /* ridge weight b of ELASTIC and L2 (> 0); 0 for L1 */
 } pcdn_opts;
+
+/* Regulariser.  Eq. (1) is F(w) = ||w||_1 + C sum_i phi_i; the paper's
+ * conclusion extends PCDN to any separable regulariser.  With
+ * R(w) = sum_j a |w_j| + (b/2) w_j^2 in place of ||w||_1 in F, in the
+ * one-dimensional subproblem (eq. (4)), in Delta (eq. (7)) and in the Armijo
+ * test (eq. (6)):
+ *   PCDN_PENALTY_L1       a = 1, b = 0   (eq. (1); default)
+ *   PCDN_PENALTY_ELASTIC  a = 1, b = l2  (elastic net)
+ *   PCDN_PENALTY_L2       a = 0, b = l2  (ridge).
+ * The direction keeps eq. (5)'s form: d = -(g + a + b w)/(h + b) if
+ * g + a <= h w, -(g - a + b w)/(h + b) if g - a >= h w, else -w (g, h are
+ * the loss term's, as pcdn_step reports them).  The stopping rule uses the
+ * minimum-norm subgradient of this F, and shrinking's threshold is a - M/n
+ * (nothing is left out for ridge).  Other values of penalty, l2 != 0 with L1,
+ * or l2 <= 0 otherwise: PCDN_E_ARG. */
+enum { PCDN_PENALTY_L1 = 0, PCDN_PENALTY_ELASTIC = 1, PCDN_PENALTY_L2 = 2 };
 
 /* Shrinking (opt-in; the paper shrinks between outer iterations, not inside
  * the parallel loop, and gives no rule): after outer iteration k, feature j
@@ -326,7 +345,9 @@ int pcdn_get_w(pcdn_ctx* ctx, double* w_out);
 int pcdn_get_cache(pcdn_ctx* ctx, double* cache_out);
 
 /* F(w) (eq. (1)) and ||grad^S F(w)||_1 at the current state (either pointer
- * may be NULL). */
+ * may be NULL), with the regulariser of the last pcdn_solve, pcdn_iterate,
+ * pcdn_step or batched call that advanced this state (eq. (1)'s after
+ * pcdn_reset). */
 int pcdn_evaluate(pcdn_ctx* ctx, double* objective, double* subgrad);
 
 /* Kernel timing.  Kernel classes: 0 gradient/direction sweep (with the fused

@@ -50,7 +50,9 @@ class pcdn_opts(ctypes.Structure):
                 ("max_ls", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("nu", ctypes.c_double), ("w0", ctypes.c_void_p),
-                ("schedule", ctypes.c_int32), ("shrink", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("shrink", ctypes.c_int32),
+                ("penalty", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("l2", ctypes.c_double)]
 
 
 class pcdn_info(ctypes.Structure):
@@ -171,13 +173,15 @@ def _check(ctx, rc, allow=(PCDN_OK,)):
 
 
 SCHEDULES = {"auto": 0, "wide": 1, "narrow": 2}
+PENALTIES = {"l1": 0, "elastic": 1, "l2": 2}
 
 
 def _opts(seed=0, max_outer=0, max_ls=0, sigma=0.0, beta=0.0, gamma=0.0, nu=0.0, w0=None,
-          schedule="auto", shrink=False):
+          schedule="auto", shrink=False, penalty="l1", l2=0.0):
     schedule = SCHEDULES.get(schedule, schedule)
+    penalty = PENALTIES.get(penalty, penalty)
     o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None, int(schedule),
-                  int(bool(shrink)))
+                  int(bool(shrink)), int(penalty), 0, float(l2))
     keep = None
     if w0 is not None:
         keep = np.ascontiguousarray(w0, dtype=np.float64)

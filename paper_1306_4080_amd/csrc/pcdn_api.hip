@@ -90,6 +90,14 @@ int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
     return fail(c, PCDN_E_ARG, "unknown schedule");
   r->shrink = o ? o->shrink : 0;
   if (r->shrink != 0 && r->shrink != 1) return fail(c, PCDN_E_ARG, "shrink must be 0 or 1");
+  r->penalty = o ? o->penalty : PCDN_PENALTY_L1;
+  r->l2 = o ? o->l2 : 0.0;
+  if (r->penalty < PCDN_PENALTY_L1 || r->penalty > PCDN_PENALTY_L2)
+    return fail(c, PCDN_E_ARG, "unknown penalty");
+  if (r->penalty == PCDN_PENALTY_L1 && r->l2 != 0.0)
+    return fail(c, PCDN_E_ARG, "l2 must be 0 with the L1 penalty");
+  if (r->penalty != PCDN_PENALTY_L1 && !(r->l2 > 0.0 && std::isfinite(r->l2)))
+    return fail(c, PCDN_E_ARG, "l2 must be finite and > 0 for the elastic-net and ridge penalties");
   if (r->max_outer < 0) return fail(c, PCDN_E_ARG, "max_outer must be >= 0");
   if (r->max_ls < 1 || r->max_ls > kQMax) return fail(c, PCDN_E_ARG, "max_ls must lie in [1, 32]");
   if (!(r->sigma > 0.0 && r->sigma < 1.0)) return fail(c, PCDN_E_ARG, "sigma must lie in (0, 1)");
@@ -97,6 +105,11 @@ int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
   if (!(r->gamma >= 0.0 && r->gamma < 1.0)) return fail(c, PCDN_E_ARG, "gamma must lie in [0, 1)");
   if (!(r->nu > 0.0) || !std::isfinite(r->nu)) return fail(c, PCDN_E_ARG, "nu must be > 0");
   return PCDN_OK;
+}
+
+void note_regulariser(pcdn_ctx* c, const Opts& o) {
+  c->penalty = o.penalty;
+  c->l2 = o.l2;
 }
 
 int check_loss(pcdn_ctx* c, int loss) {
@@ -178,6 +191,8 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   a.C = c->C;
   a.gamma = o.gamma;
   a.nu = o.nu;
+  a.ra = o.ra();
+  a.rb = o.rb();
   return a;
 }
 
@@ -229,6 +244,8 @@ LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
   l.stats = c->stats;
   l.beta = o.beta;
   l.Q = o.max_ls;
+  l.ra = o.ra();
+  l.rb = o.rb();
   return l;
 }
 
@@ -313,7 +330,7 @@ int launch_stopping_shrink(pcdn_ctx* c, const Opts& o, IterState* it) {
     HIPCHK(c, launch_split(c->loss, true, a, c->stream));
   }
   const StopSumArgs s{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, it,
-                      sum_grid(c->p)};
+                      sum_grid(c->p), o.ra()};
   HIPCHK(c, launch_stop_sum(s, c->stream));
   return PCDN_OK;
 }
@@ -359,10 +376,11 @@ int stopping_norm(pcdn_ctx* c, const Opts& o, const double* w, double* G) {
   return read_scalar(c, 0, G);
 }
 
-int objective(pcdn_ctx* c, double* F) {
+// F(w) = R(w) + C sum_i phi_i with the regulariser of o.
+int objective(pcdn_ctx* c, const Opts& o, double* F) {
   HIPCHK(c, launch_loss_terms(c->loss, c->cache, c->y, c->n, c->tmp_n, c->stream));
   HIPCHK(c, launch_sum(c->tmp_n, c->n, c->sum_part, c->scal + 1, nullptr, c->stream));
-  HIPCHK(c, launch_abs(c->w, c->p, c->tmp_p, c->stream));
+  HIPCHK(c, launch_reg_terms(c->w, c->p, o.ra(), o.rb(), c->tmp_p, c->stream));
   HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->scal + 2, nullptr, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->hscal + 1, c->scal + 1, 2 * sizeof(double), hipMemcpyDeviceToHost,
                            c->stream));
@@ -557,7 +575,8 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   const int sb = sum_grid(c->p);
   if (o.shrink) {
     t = task(kTaskStopPartial, sb, 0);
-    t.u.stop = StopSumArgs{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, c->iter, sb};
+    t.u.stop = StopSumArgs{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, c->iter, sb,
+                           o.ra()};
     out.push_back(t);
     t.kind = kTaskStopFinal;
   } else {
@@ -583,6 +602,8 @@ pcdn_ctx::GraphKey graph_key_of(const pcdn_ctx* c, const Opts& o, int64_t P) {
   key.max_ls = o.max_ls;
   key.schedule = o.schedule;
   key.shrink = o.shrink;
+  key.penalty = o.penalty;
+  key.l2 = o.l2;
   return key;
 }
 
@@ -740,6 +761,7 @@ int solve_begin(SolveRun& r) {
   r.hbase = c->hc;
   c->loss = r.loss;
   c->C = r.C;
+  note_regulariser(c, r.o);
   r.outer = 0;
   rc = init_shrink(c);
   if (rc) return rc;
@@ -783,7 +805,7 @@ int solve_note_outer(SolveRun& r, double G) {
 int solve_end(SolveRun& r, double* w_out, pcdn_info* info) {
   pcdn_ctx* c = r.c;
   double F = 0.0;
-  int rc = objective(c, &F);
+  int rc = objective(c, r.o, &F);
   if (rc) return rc;
   if (std::isnan(F)) return fail(c, PCDN_E_NUMERIC, "objective is NaN");
   if (w_out)
@@ -1098,6 +1120,8 @@ extern "C" int pcdn_reset(pcdn_ctx* c, int loss, double C, const double* w) {
   HIPCHK(c, hipSetDevice(c->device));
   c->loss = loss;
   c->C = C;
+  c->penalty = PCDN_PENALTY_L1;
+  c->l2 = 0.0;
   rc = set_w(c, w);
   if (rc) return rc;
   rc = init_shrink(c);
@@ -1115,6 +1139,7 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
   Opts o;
   int rc = resolve_opts(c, opts, &o);
   if (rc) return rc;
+  note_regulariser(c, o);
   std::vector<unsigned char> seen(c->p, 0);
   for (int64_t t = 0; t < P; ++t) {
     const int32_t j = bundle[t];
@@ -1215,6 +1240,7 @@ extern "C" int pcdn_iterate(pcdn_ctx* c, int64_t P, int64_t k_first, int64_t cou
   Opts o;
   int rc = resolve_opts(c, opts, &o);
   if (rc) return rc;
+  note_regulariser(c, o);
   HIPCHK(c, hipSetDevice(c->device));
   rc = run_outer(c, o, P, k_first, count);
   if (rc) return rc;
@@ -1257,12 +1283,14 @@ extern "C" int pcdn_evaluate(pcdn_ctx* c, double* F, double* G) {
   Opts o;
   int rc = resolve_opts(c, nullptr, &o);
   if (rc) return rc;
+  o.penalty = c->penalty;
+  o.l2 = c->l2;
   if (G) {
     rc = stopping_norm(c, o, c->w, G);
     if (rc) return rc;
   }
   if (F) {
-    rc = objective(c, F);
+    rc = objective(c, o, F);
     if (rc) return rc;
   }
   return PCDN_OK;

@@ -414,6 +414,7 @@ extern "C" int pcdn_iterate_batch(pcdn_ctx* const* ctxs, const int64_t* P, int32
     SolveRun& r = ej[i].run;
     const int rc = resolve_opts(c, opts, &r.o);
     if (rc) return rc;
+    note_regulariser(c, r.o);
     r.o.max_outer = (int)iters;
     r.c = c;
     r.C = c->C;

@@ -86,12 +86,14 @@ struct SweepArgs {
   double* g;                  // per-slot outputs, indexed by the absolute slot
   double* h;
   double* d;
-  double* dterm;              // g d + gamma h d^2 + |w + d| - |w|
+  double* dterm;              // g d + gamma h d^2 + R_j(w + d) - R_j(w)
   double* sg;                 // stopping mode: |grad^S_j F|
   double2* part;              // split-column partial sums, per chunk
   double* dtx;                // d^T x accumulator
   Stats* stats;
   double C, gamma, nu;
+  // regulariser R_j(u) = ra |u| + (rb/2) u^2 (eq. (1): ra = 1, rb = 0)
+  double ra, rb;
   // shrinking (all nullable): bundle mode clips the slots to the first
   // *p_active; stopping mode writes act[j] = 1 if feature j stays active
   // (w_j != 0 or |g_j| >= *thr), else 0
@@ -115,6 +117,7 @@ struct LsArgs {
   double beta;
   int Q;
   const double* p_active;  // nullable: slots clipped to the first *p_active
+  double ra, rb;           // regulariser, as in SweepArgs
 };
 
 struct ApplyArgs {
@@ -159,6 +162,7 @@ struct StopSumArgs {
   double* scal;
   IterState* it;
   int32_t nb;
+  double ra;                 // L1 weight of the regulariser (threshold ra - M/n)
 };
 
 struct SumArgs {
@@ -283,7 +287,8 @@ hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, Ite
 hipError_t launch_stop_sum(const StopSumArgs& a, hipStream_t s);
 hipError_t launch_loss_terms(int loss, const double* cache, const int8_t* y, int64_t n,
                              double* out, hipStream_t s);
-hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s);
+hipError_t launch_reg_terms(const double* w, int64_t p, double ra, double rb, double* out,
+                            hipStream_t s);
 // Retained quantities from w (e^{x_i^T w}, or 1 - y_i x_i^T w) with X in CSR
 // order (rp int64[n+1], col, v); deterministic.
 hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, const float* v,

@@ -56,6 +56,10 @@ struct pcdn_ctx {
   // state
   int loss = -1;
   double C = 0.0;
+  // regulariser of the state: the one the last solve, iteration or step ran
+  // with (pcdn_reset: eq. (1)); pcdn_evaluate reports F with it
+  int penalty = 0;
+  double l2 = 0.0;
   bool has_state = false;
   double* w = nullptr;
   double* cache = nullptr;
@@ -124,10 +128,12 @@ struct pcdn_ctx {
     int max_ls = 0;
     int schedule = -1;
     int shrink = -1;
+    int penalty = -1;
+    double l2 = 0;
     bool operator==(const GraphKey& o) const {
       return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
              gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule &&
-             shrink == o.shrink;
+             shrink == o.shrink && penalty == o.penalty && l2 == o.l2;
     }
   } graph_key;
   // the same outer iteration in two parts around the bundles, for drivers
@@ -176,11 +182,18 @@ struct Opts {
   const double* w0;
   int schedule;
   int shrink;
+  int penalty;  // PCDN_PENALTY_*
+  double l2;
+  // the regulariser sum_j ra |w_j| + (rb/2) w_j^2
+  double ra() const { return penalty == PCDN_PENALTY_L2 ? 0.0 : 1.0; }
+  double rb() const { return penalty == PCDN_PENALTY_L1 ? 0.0 : l2; }
 };
 
 // Options with defaults filled in and validated (o may be null).
 int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r);
 int check_loss(pcdn_ctx* c, int loss);
+// Record the regulariser that the state is being advanced with.
+void note_regulariser(pcdn_ctx* c, const Opts& o);
 // Whether outer iterations with bundle size P run in one workgroup.
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
 // Arguments of the single-workgroup kernel for bundles [t_begin, t_end).

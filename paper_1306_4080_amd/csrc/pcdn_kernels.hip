@@ -175,20 +175,29 @@ __device__ inline double loss_delta(double c, int yi, double a) {
   }
 }
 
-// Minimiser of g d + h d^2/2 + |w + d| (eqs. (4)-(5), soft-threshold form).
-__device__ inline double newton_dir(double g, double h, double w) {
+// Minimiser of g d + h d^2/2 + R(w + d) with R(u) = ra |u| + (rb/2) u^2
+// (eq. (4) with the separable regulariser in place of |u|; for ra = 1,
+// rb = 0 the soft-threshold form of eq. (5)).  u = w + d is > 0 exactly
+// when g + ra < h w and < 0 exactly when g - ra > h w.
+__device__ inline double newton_dir(double g, double h, double w, double ra, double rb) {
   const double hw = h * w;
-  if (g + 1.0 <= hw) return -(g + 1.0) / h;
-  if (g - 1.0 >= hw) return -(g - 1.0) / h;
+  if (g + ra <= hw) return -(g + ra + rb * w) / (h + rb);
+  if (g - ra >= hw) return -(g - ra + rb * w) / (h + rb);
   return -w;
 }
 
+// R_j(w + s) - R_j(w), the quadratic part as rb s (w + s/2).
+__device__ inline double reg_change(double w, double s, double ra, double rb) {
+  return ra * (fabs(w + s) - fabs(w)) + rb * s * (w + 0.5 * s);
+}
+
 // Minimum-norm subgradient of F in coordinate j.
-__device__ inline double min_norm_subgradient(double g, double w) {
-  if (w > 0.0) return g + 1.0;
-  if (w < 0.0) return g - 1.0;
-  if (g > 1.0) return g - 1.0;
-  if (g < -1.0) return g + 1.0;
+__device__ inline double min_norm_subgradient(double g, double w, double ra, double rb) {
+  const double G = g + rb * w;  // gradient of the smooth part
+  if (w > 0.0) return G + ra;
+  if (w < 0.0) return G - ra;
+  if (G > ra) return G - ra;
+  if (G < -ra) return G + ra;
   return 0.0;
 }
 
@@ -496,17 +505,17 @@ __device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, dou
   const int64_t o = ch.slot;
   if (STOP) {
     if (writer) {
-      a.sg[o] = fabs(min_norm_subgradient(g, wj));
+      a.sg[o] = fabs(min_norm_subgradient(g, wj, a.ra, a.rb));
       if (a.act) a.act[o] = (wj != 0.0 || fabs(g) >= *a.thr) ? 1.0 : 0.0;
     }
     return 0.0;
   }
-  const double dj = newton_dir(g, h, wj);
+  const double dj = newton_dir(g, h, wj, a.ra, a.rb);
   if (writer) {
     a.g[o] = g;
     a.h[o] = h;
     a.d[o] = dj;
-    a.dterm[o] = g * dj + a.gamma * h * dj * dj + (fabs(wj + dj) - fabs(wj));
+    a.dterm[o] = g * dj + a.gamma * h * dj * dj + reg_change(wj, dj, a.ra, a.rb);
   }
   return dj;
 }
@@ -681,7 +690,7 @@ __device__ __forceinline__ void linesearch_body(const LsArgs& a, int bx, int by,
 #pragma unroll
     for (int q = 0; q < kQGroup; ++q) {
       if (q < nq) {
-        acc[q] += fabs(wj + al * dj) - fabs(wj);
+        acc[q] += reg_change(wj, al * dj, a.ra, a.rb);
         al *= a.beta;
       }
     }
@@ -1010,9 +1019,9 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       }
       if (h <= 0.0) h += a.nu;
       const double wj = L.w[s];
-      const double dj = newton_dir(g, h, wj);
+      const double dj = newton_dir(g, h, wj, a.ra, a.rb);
       L.d[s] = dj;
-      del += g * dj + a.gamma * h * dj * dj + (fabs(wj + dj) - fabs(wj));
+      del += g * dj + a.gamma * h * dj * dj + reg_change(wj, dj, a.ra, a.rb);
       a.g[lo + s] = g;
       a.h[lo + s] = h;
       a.d[lo + s] = dj;
@@ -1078,7 +1087,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], sc);
         }
       }
-      for (int32_t s = tid; s < ns; s += kNarrowBlock) l1 += fabs(L.w[s] + al * L.d[s]) - fabs(L.w[s]);
+      for (int32_t s = tid; s < ns; s += kNarrowBlock) l1 += reg_change(L.w[s], al * L.d[s], a.ra, a.rb);
       double sL, L1;
       if (q == 0) {
         double v4[4] = {sl, l1, del, touched};
@@ -1292,7 +1301,7 @@ __device__ __forceinline__ void stop_final_body(const StopSumArgs& a) {
   if (threadIdx.x == 0) {
     a.scal[0] = sg;
     a.scal[3] = mx;
-    a.scal[4] = 1.0 - mx / (double)a.n;
+    a.scal[4] = a.ra - mx / (double)a.n;
     a.scal[5] = na;
     a.scal[6] = nz;
     if (a.it) a.it->k += 1;
@@ -1367,9 +1376,10 @@ __global__ void k_loss_terms(const double* cache, const int8_t* y, int64_t n, do
   }
 }
 
-__global__ void k_abs(const double* w, int64_t p, double* out) {
+// Regulariser terms ra |w_j| + (rb/2) w_j^2 of F.
+__global__ void k_reg_terms(const double* w, int64_t p, double ra, double rb, double* out) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j < p) out[j] = fabs(w[j]);
+  if (j < p) out[j] = ra * fabs(w[j]) + 0.5 * rb * w[j] * w[j];
 }
 
 // Retained quantities from w, one wavefront per row over X in CSR order: the
@@ -1626,8 +1636,10 @@ hipError_t launch_loss_terms(int loss, const double* cache, const int8_t* y, int
   return hipGetLastError();
 }
 
-hipError_t launch_abs(const double* w, int64_t p, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_abs, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, w, p, out);
+hipError_t launch_reg_terms(const double* w, int64_t p, double ra, double rb, double* out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_reg_terms, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, w, p,
+                     ra, rb, out);
   return hipGetLastError();
 }
 

@@ -310,3 +310,28 @@ def test_iterate_batch_shrink(pc):
         assert F == pytest.approx(io["objective"], rel=RTOL)
         np.testing.assert_allclose(s.w(), w_o, rtol=RTOL, atol=RTOL * np.max(np.abs(w_o)))
         s.close()
+
+
+def test_batch_regularised_jobs(pc):
+    """Elastic-net and ridge jobs beside an L1 job in one batch (both
+    schedules, one with shrinking): each equals its solve alone and the
+    oracle's."""
+    c1 = synth.c1()
+    rnd = synth.bernoulli_csc(80, 1500, 4000, 0.008)
+    jobs = [(c1, "lr", 1.0, 32, 1e-4, {"penalty": "elastic", "l2": 0.5}),
+            (c1, "svm", 1.0, 32, 1e-3, {"penalty": "l2", "l2": 0.7, "schedule": "wide"}),
+            (rnd, "lr", 2.0, 200, 1e-4, {"penalty": "elastic", "l2": 1.0, "shrink": True}),
+            (rnd, "lr", 2.0, 200, 1e-4, {})]
+    solvers = [pc.Solver(device=0).load_data(d) for d, *_ in jobs]
+    specs = [s.job(C, P, eps, loss, seed=4, **o) for s, (d, loss, C, P, eps, o) in zip(solvers, jobs)]
+    batched = pc.solve_batch(specs)
+    for s, (d, loss, C, P, eps, o), b in zip(solvers, jobs, batched):
+        print(f"{loss} C={C} P={P} {o}: outer={b[2]['outer_iters']} F={b[2]['objective']:.15g}",
+              flush=True)
+        _assert_same_run(b, s.solve(C, P, eps, loss, seed=4, **o))
+        reg = {k: o[k] for k in ("penalty", "l2", "shrink") if k in o}
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss=loss, C=C, **reg),
+                                  P=P, eps=eps, seed=4)
+        _assert_oracle(b, (w_o, io), True)
+    for s in solvers:
+        s.close()

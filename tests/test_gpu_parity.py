@@ -165,15 +165,15 @@ def test_step_backtracking_and_failure(pc, schedule):
 # whole solves: final objective
 # --------------------------------------------------------------------------
 def _solve_both(pc, d, loss, C, P, eps, seed=1, max_outer=1000, w0=None, s=None,
-                schedule="auto", shrink=False):
+                schedule="auto", shrink=False, **reg):
     prob = oracle.Problem.from_data(d)
-    w_o, info_o, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C, shrink=shrink), P=P,
+    w_o, info_o, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C, shrink=shrink, **reg), P=P,
                                   eps=eps, seed=seed, max_outer=max_outer, w0=w0)
     own = s is None
     if own:
         s = _solver(pc, d)
     rc, w_g, info_g = s.solve(C, P, eps, loss, seed=seed, max_outer=max_outer, w0=w0,
-                              schedule=schedule, shrink=shrink)
+                              schedule=schedule, shrink=shrink, **reg)
     if own:
         s.close()
     return (rc, w_g, info_g), (w_o, info_o)
@@ -307,6 +307,92 @@ def test_shrink_step_by_step(pc, schedule):
     assert info_g["nnz_swept"] == info_o["nnz_swept"]
     assert info_g["bundles"] == info_o["bundles"]
     np.testing.assert_allclose(w_g, w_o, rtol=RTOL, atol=RTOL * np.max(np.abs(w_o)))
+    s.close()
+
+
+# --------------------------------------------------------------------------
+# separable regularisers: elastic net and ridge in place of the l1 norm
+# --------------------------------------------------------------------------
+REGS = [{"penalty": "elastic", "l2": 0.5}, {"penalty": "l2", "l2": 0.7}]
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+@pytest.mark.parametrize("reg", REGS, ids=["elastic", "ridge"])
+def test_regularised_step_parity_c1(pc, reg, loss, schedule):
+    d = synth.c1()
+    prob = oracle.Problem.from_data(d)
+    C = 1.0
+    par = oracle.Params(loss=loss, C=C, **reg)
+    s = _solver(pc, d)
+    rng = np.random.default_rng(6)
+    for trial in range(4):
+        w = _random_w(rng, d.p) if trial else np.zeros(d.p)
+        s.reset(loss, C, w)
+        cache = oracle.cache_from_w(prob, loss, w)
+        bundle = oracle.permutation(4, trial, d.p)[:[32, 1, 500, 77][trial]]
+        w_o = w.copy()
+        s_orc = oracle.step(prob, par, w_o, cache, bundle)
+        s_gpu = s.step(bundle, schedule=schedule, **reg)
+        _compare_step(d, s_gpu, s_orc, bundle, C)
+        np.testing.assert_allclose(s.w(), w_o, rtol=1e-12, atol=1e-15)
+    s.close()
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("loss,eps", [("lr", 1e-4), ("svm", 1e-3)])
+@pytest.mark.parametrize("reg", REGS, ids=["elastic", "ridge"])
+def test_regularised_solve_parity_c1(pc, reg, loss, eps, schedule):
+    d = synth.c1()
+    s = _solver(pc, d)
+    g, o = _solve_both(pc, d, loss, 1.0, 32, eps, s=s, schedule=schedule, **reg)
+    _assert_solve_parity(g, o)
+    assert g[0] == 0
+    # pcdn_evaluate reports F with the regulariser the state was solved with
+    F, G = s.evaluate()
+    assert F == pytest.approx(o[1]["objective"], rel=RTOL)
+    assert G == pytest.approx(g[2]["subgrad"], rel=1e-9)
+    X, y = d.dense(), d.y.astype(float)
+    a, b = oracle.Params(**reg).reg_ab()
+    Fd = a * np.abs(g[1]).sum() + 0.5 * b * g[1] @ g[1] + _loss_sum(X, y, g[1], loss)
+    assert g[2]["objective"] == pytest.approx(Fd, rel=1e-9)
+    s.close()
+
+
+def _loss_sum(X, y, w, loss):
+    m = y * (X @ w)
+    if loss == "lr":
+        return float(np.logaddexp(0.0, -m).sum())
+    return float((np.maximum(1.0 - m, 0.0) ** 2).sum())
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("reg,C,P", [({"penalty": "elastic", "l2": 2.0}, 0.5, 64),
+                                     ({"penalty": "l2", "l2": 1.0}, 4.0, 1024)],
+                         ids=["elastic", "ridge"])
+def test_regularised_solve_parity_c2(pc, reg, C, P, schedule):
+    d = _c2_cached()
+    g, o = _solve_both(pc, d, "lr", C, P, 1e-4, schedule=schedule, **reg)
+    _assert_solve_parity(g, o)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_elastic_net_with_shrinking_c1(pc, schedule):
+    d = synth.c1()
+    g, o = _solve_both(pc, d, "lr", 1.0, 32, 1e-4, schedule=schedule, shrink=True,
+                       penalty="elastic", l2=0.3)
+    _assert_solve_parity(g, o)
+
+
+def test_regulariser_argument_errors(pc):
+    from paper_1306_4080_amd import PcdnError
+    d = synth.c1()
+    s = _solver(pc, d)
+    for bad in ({"penalty": 3, "l2": 1.0}, {"penalty": -1}, {"penalty": "l1", "l2": 0.5},
+                {"penalty": "elastic", "l2": 0.0}, {"penalty": "l2", "l2": -1.0},
+                {"penalty": "l2", "l2": float("inf")}):
+        with pytest.raises(PcdnError, match="E_ARG"):
+            s.solve(1.0, 32, 1e-4, "lr", **bad)
     s.close()
 
 
