@@ -4,6 +4,7 @@
 // pcdn_kernels.hip; this file only sizes launches, orders them on the
 // context's stream and reads back scalars.
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -64,7 +65,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
   dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
   dfree(c->part); dfree(c->ls_part);
-  dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32);
+  dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32); dfree(c->plid); dfree(c->pR);
   dfree(c->rp); dfree(c->rc); dfree(c->rv);
   dfree(c->act);
   drop_graph(c);
@@ -428,6 +429,21 @@ bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P) {
   return (double)c->nnz * (double)P / (double)c->p <= kNarrowMaxBundleNnz;
 }
 
+bool use_hybrid(const pcdn_ctx* c, const Opts& o, int64_t P) {
+  if (o.schedule != PCDN_SCHED_AUTO || !use_narrow(c, o, P) || c->top_len.empty()) return false;
+  const int64_t k = std::min<int64_t>(P, (int64_t)c->top_len.size() - 1);
+  return c->top_len[k] >= kHeavyNnz;
+}
+
+// Whether bundles of P over p_slots slots get local row ids (the
+// single-workgroup kernel then keeps their d^T x in LDS): the row bitmap must
+// fit LDS, and the per-bundle bitmap passes must stay cheap.
+bool use_bundle_rows(const pcdn_ctx* c, int64_t P, int64_t p_slots) {
+  const int64_t words = (c->n + 31) / 32;
+  const int64_t bundles = (p_slots + P - 1) / P;
+  return words <= kRowsMaxWords && (double)words * (double)bundles <= (double)(1 << 27);
+}
+
 // Bundles [t_begin, t_end) of size P over the order `perm` (descriptors in
 // c->chunks / c->cstart, p_slots slots) in one workgroup, after copying X into
 // that order.
@@ -456,19 +472,27 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   na.max_ls = o.max_ls;
   na.dtx_copy = dtx_copy;
   na.loss = c->loss;
+  if (use_bundle_rows(c, P, p_slots)) {
+    na.plid = c->plid;
+    na.pR = c->pR;
+  }
   return na;
 }
 
 // Copy X into the order `perm` (descriptors in c->chunks / c->cstart).
-int permute_x(pcdn_ctx* c, const int32_t* perm, int64_t p_slots) {
+// Copy X into the order `perm` for bundles of P, with the bundles'
+// local row ids where the single-workgroup kernel can use them.
+int permute_x(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
   HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
                            c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->stream));
+  if (use_bundle_rows(c, P, p_slots))
+    HIPCHK(c, launch_bundle_rows(c->poff, c->pri, p_slots, P, c->n, c->plid, c->pR, c->stream));
   return PCDN_OK;
 }
 
 int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
                           int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
-  int rc = permute_x(c, perm, p_slots);
+  int rc = permute_x(c, perm, p_slots, P);
   if (rc) return rc;
   const NarrowArgs na = make_narrow_args(c, o, perm, p_slots, P, t_begin, t_end, dtx_copy);
   ProfScope ps(c, 5);
@@ -480,20 +504,31 @@ int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64
 // stopping sweep (result in c->scal[0]).  it != null: k is read from and
 // advanced on the device (graph replays).
 // The outer iteration in three parts.  Before the bundles: partition,
-// chunk descriptors, and (single-workgroup schedule) X in partition order.
-int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
+// chunk descriptors, and (single-workgroup schedule) X in partition order;
+// heavy_list: also the list of heavy bundles, for the batch engine.
+int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it,
+                bool heavy_list) {
   int rc = device_permutation(c, o.seed, k, it, o.shrink ? c->act : nullptr);
   if (rc) return rc;
   HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunks, c->scan_tmp,
                           c->stream));
-  if (use_narrow(c, o, P)) return permute_x(c, c->idx0, c->p);
+  if (!use_narrow(c, o, P)) return PCDN_OK;
+  rc = permute_x(c, c->idx0, c->p, P);
+  if (rc) return rc;
+  if (heavy_list && use_hybrid(c, o, P))
+    HIPCHK(c, launch_heavy_bundles(c->poff, c->p, P, kHeavyNnz, kHeavyCap, c->heavy, c->stream));
   return PCDN_OK;
 }
 
 // Single-workgroup arguments for every bundle of an outer iteration's
 // partition (with shrinking, the kernel stops after the active features).
 NarrowArgs outer_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P) {
-  NarrowArgs na = make_narrow_args(c, o, c->idx0, c->p, P, 0, (c->p + P - 1) / P, nullptr);
+  return segment_narrow_args(c, o, P, 0, (c->p + P - 1) / P);
+}
+
+NarrowArgs segment_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P, int64_t t_begin,
+                               int64_t t_end) {
+  NarrowArgs na = make_narrow_args(c, o, c->idx0, c->p, P, t_begin, t_end, nullptr);
   if (o.shrink) na.p_active = c->scal + 5;
   return na;
 }
@@ -524,7 +559,7 @@ int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
 }
 
 int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
-  int rc = enqueue_pre(c, o, P, k, it);
+  int rc = enqueue_pre(c, o, P, k, it, false);
   if (rc) return rc;
   rc = enqueue_bundles(c, o, P);
   if (rc) return rc;
@@ -648,7 +683,7 @@ int ensure_split_graphs(pcdn_ctx* c, const Opts& o, int64_t P) {
   if (c->graph_post) (void)hipGraphExecDestroy(c->graph_post);
   c->graph_pre = c->graph_post = nullptr;
   c->split_key = pcdn_ctx::GraphKey();
-  int rc = capture(c, &c->graph_pre, [&] { return enqueue_pre(c, o, P, 0, c->iter); });
+  int rc = capture(c, &c->graph_pre, [&] { return enqueue_pre(c, o, P, 0, c->iter, true); });
   if (rc) return rc;
   rc = capture(c, &c->graph_post, [&] { return enqueue_post(c, o, P, c->iter); });
   if (rc) return rc;
@@ -873,12 +908,14 @@ extern "C" int pcdn_create(pcdn_ctx** out, int device, void* hip_stream) {
   if (dalloc(&c->iter, 1) != hipSuccess || dalloc(&c->st, 1) != hipSuccess ||
       dalloc(&c->stats, 1) != hipSuccess || dalloc(&c->scal, 8) != hipSuccess ||
       dalloc(&c->sum_part, kSumGrid) != hipSuccess ||
-      dalloc(&c->stop_part, 4 * kSumGrid) != hipSuccess)
+      dalloc(&c->stop_part, 4 * kSumGrid) != hipSuccess ||
+      dalloc(&c->heavy, kHeavyCap + 1) != hipSuccess)
     return bail(PCDN_E_OOM, "device allocation failed");
   if (hipHostMalloc((void**)&c->hscal, 8 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&c->hstats, sizeof(Stats)) != hipSuccess ||
       hipHostMalloc((void**)&c->hst, sizeof(StepState)) != hipSuccess ||
-      hipHostMalloc((void**)&c->hiter, sizeof(IterState)) != hipSuccess)
+      hipHostMalloc((void**)&c->hiter, sizeof(IterState)) != hipSuccess ||
+      hipHostMalloc((void**)&c->hheavy, (kHeavyCap + 1) * sizeof(int32_t)) != hipSuccess)
     return bail(PCDN_E_OOM, "pinned host allocation failed");
   if (hipMemsetAsync(c->iter, 0, sizeof(IterState), c->stream) != hipSuccess ||
       hipMemsetAsync(c->stats, 0, sizeof(Stats), c->stream) != hipSuccess ||
@@ -895,6 +932,8 @@ extern "C" int pcdn_destroy(pcdn_ctx* c) {
   free_data(c);
   dfree(c->iter); dfree(c->st); dfree(c->stats); dfree(c->scal); dfree(c->sum_part);
   dfree(c->stop_part);
+  dfree(c->heavy);
+  if (c->hheavy) (void)hipHostFree(c->hheavy);
   if (c->hscal) (void)hipHostFree(c->hscal);
   if (c->hstats) (void)hipHostFree(c->hstats);
   if (c->hst) (void)hipHostFree(c->hst);
@@ -931,7 +970,9 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
       4 * (p + 1), 32 * max_chunks, 4 * p,                 // identity-order descriptors, step bundle
       16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
+      2 * nnz, 4 * (p + 1),                                // bundle-local row ids
       8 * (int64_t)kLsGrid * (2 * kQMax + 2),              // line-search partials
+      8 * p,                                               // active mask (shrinking)
       8 * (n + 1), 4 * nnz, 4 * nnz};                      // CSR copy
   int64_t total = 64 * 1024;
   for (const int64_t b : sizes) total += (std::max<int64_t>(b, 1) + 4095) / 4096 * 4096;
@@ -997,6 +1038,14 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   HIPCHK(c, hipStreamSynchronize(c->stream));
   free_data(c);
   c->h_cp.assign(Hcp, Hcp + p + 1);
+  {
+    std::vector<int64_t> lens(p);
+    for (int64_t j = 0; j < p; ++j) lens[j] = Hcp[j + 1] - Hcp[j];
+    const int64_t k = std::min<int64_t>(p, kNarrowMaxP);
+    std::partial_sort(lens.begin(), lens.begin() + k, lens.end(), std::greater<int64_t>());
+    c->top_len.assign(k + 1, 0);
+    for (int64_t i = 0; i < k; ++i) c->top_len[i + 1] = c->top_len[i] + lens[i];
+  }
   c->n = n;
   c->p = p;
   c->nnz = nnz;
@@ -1034,6 +1083,8 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->pv, nnz);
   ALLOC(c, c->poff, p + 1);
   ALLOC(c, c->off32, p + 1);
+  ALLOC(c, c->plid, nnz);
+  ALLOC(c, c->pR, p + 1);
   ALLOC(c, c->ls_part, (size_t)kLsGrid * (2 * kQMax + 2));
   ALLOC(c, c->act, p);
   ALLOC(c, c->rp, n + 1);

@@ -28,6 +28,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct EngineJob {
   SolveRun run;
   bool narrow = false;
+  bool hybrid = false;           // single-workgroup segments between heavy bundles, own stream
   std::vector<Task> tasks;       // multi-kernel jobs: the outer iteration after the partition
   hipEvent_t pre_done = nullptr;
   bool active = false;
@@ -121,6 +122,7 @@ class Engine {
       if (rc) return rc;
     }
     j->narrow = use_narrow(r.c, r.o, r.P);
+    j->hybrid = j->narrow && use_hybrid(r.c, r.o, r.P);
     rc = ensure_split_graphs(r.c, r.o, r.P);
     if (rc) return rc;
     if (!j->narrow) {
@@ -151,11 +153,14 @@ class Engine {
     // partitions, each on its job's stream; the single-workgroup jobs'
     // table lists the logistic jobs first, then the SVM jobs (one launch each)
     size_t m = 0, m_lr = 0;
-    for (EngineJob* j : jobs_)
-      if (j->narrow) {
+    bool any_hybrid = false;
+    for (EngineJob* j : jobs_) {
+      any_hybrid = any_hybrid || j->hybrid;
+      if (j->narrow && !j->hybrid) {
         ++m;
         m_lr += j->run.loss == PCDN_LOSS_LOGISTIC ? 1 : 0;
       }
+    }
     if (narrow_tab_.reserve(sizeof(NarrowArgs) * m) != hipSuccess)
       return dev_fail("table allocation", hipErrorOutOfMemory);
     NarrowArgs* htab = (NarrowArgs*)narrow_tab_.host;
@@ -165,10 +170,15 @@ class Engine {
       *err_ctx = c;
       const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
       HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
+      count_outer(c, j->run.o, j->run.P, 1);
+      if (j->hybrid) {  // its bundles follow on its own stream once the list is read
+        HIPCHK(c, hipMemcpyAsync(c->hheavy, c->heavy, (kHeavyCap + 1) * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, c->stream));
+        continue;
+      }
       HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
       HIPCHK(c, hipStreamWaitEvent(j->narrow ? narrow_stream_[g] : wide_stream_, j->pre_done, 0));
       if (j->narrow) htab[at[g]++] = outer_narrow_args(c, j->run.o, j->run.P);
-      count_outer(c, j->run.o, j->run.P, 1);
     }
     *err_ctx = nullptr;
     // single-workgroup jobs: one launch per loss, then each job's stopping sweep
@@ -185,7 +195,7 @@ class Engine {
       if (e == hipSuccess) e = hipEventRecord(fused_done_[1], narrow_stream_[1]);
       if (e != hipSuccess) return dev_fail("multi-problem launch", e);
       for (EngineJob* j : jobs_) {
-        if (!j->narrow) continue;
+        if (!j->narrow || j->hybrid) continue;
         pcdn_ctx* c = j->run.c;
         *err_ctx = c;
         const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
@@ -211,6 +221,35 @@ class Engine {
         e = hipMemcpyAsync(gather_.host, gather_.dev, 3 * sizeof(double) * plan_jobs_.size(),
                            hipMemcpyDeviceToHost, wide_stream_);
       if (e != hipSuccess) return dev_fail("gather", e);
+    }
+    // single-workgroup jobs with heavy bundles, each on its own stream: the
+    // segments between heavy bundles in one workgroup, each heavy bundle on
+    // the multi-kernel path, in partition order
+    if (any_hybrid) {
+      for (EngineJob* j : jobs_) {
+        if (!j->hybrid) continue;
+        pcdn_ctx* c = j->run.c;
+        *err_ctx = c;
+        const Opts& o = j->run.o;
+        const int64_t P = j->run.P, nb = (c->p + P - 1) / P;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const int32_t nh = std::min<int32_t>(std::max<int32_t>(c->hheavy[0], 0), kHeavyCap);
+        int64_t t = 0;
+        for (int32_t k = 0; k <= nh; ++k) {
+          const int64_t te = k < nh ? std::min<int64_t>(std::max<int64_t>(c->hheavy[1 + k], t), nb)
+                                    : nb;
+          if (te > t) HIPCHK(c, launch_narrow(c->loss, segment_narrow_args(c, o, P, t, te), c->stream));
+          if (k == nh || te >= nb) break;
+          const int64_t lo = te * P, hi = std::min(lo + P, c->p);
+          rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
+          if (rc) return rc;
+          t = te + 1;
+        }
+        HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+      }
+      *err_ctx = nullptr;
     }
     // the staging tables and every pinned result are reused next round
     hipError_t e = hipStreamSynchronize(narrow_stream_[0]);

@@ -228,10 +228,37 @@ struct NarrowArgs {
   int max_ls;
   int loss;            // kLogistic / kL2Svm (read by the multi-problem kernel)
   const double* p_active;  // nullable: bundles stop at ceil(*p_active / P)
+  // bundle-local row ids (launch_bundle_rows; nullable: none): plid[k] is the
+  // rank of nonzero k's row among the distinct rows of its bundle, pR[t] the
+  // number of distinct rows of bundle t or -1 (more than kNarrowLidCap)
+  const uint16_t* plid;
+  const int32_t* pR;
 };
+
+// Largest number of distinct rows of a bundle whose d^T x the
+// single-workgroup kernel keeps in LDS.
+constexpr int kNarrowLidCap = 4096;
+// Bundle-local row ids are computed from a bitmap of the n rows in LDS:
+// n <= 32 * kRowsMaxWords.
+constexpr int64_t kRowsMaxWords = 7936;
+
+// Bundles with at least kHeavyNnz nonzeros run on the multi-kernel path
+// between single-workgroup segments (batch engine, automatic schedule); at
+// most kHeavyCap of them per outer iteration are listed.
+constexpr int64_t kHeavyNnz = 6144;
+constexpr int kHeavyCap = 256;
 
 // ---- host-callable launchers (pcdn_kernels.hip) -------------------------
 hipError_t launch_fill(double* a, double v, int64_t n, hipStream_t s);
+// Bundle-local row ids of the bundles [tP, min((t+1)P, p_slots)) of X in
+// partition order (poff, pri): see NarrowArgs.  Needs n <= 32 * kRowsMaxWords.
+hipError_t launch_bundle_rows(const int64_t* poff, const int32_t* pri, int64_t p_slots, int64_t P,
+                              int64_t n, uint16_t* plid, int32_t* pR, hipStream_t s);
+// out[0] = number of bundles t (of P slots over p_slots) with at least
+// `thresh` nonzeros in partition order (poff), capped at `cap`; out[1..] their
+// indices in ascending order.  out holds cap + 1 entries.
+hipError_t launch_heavy_bundles(const int64_t* poff, int64_t p_slots, int64_t P, int64_t thresh,
+                                int32_t cap, int32_t* out, hipStream_t s);
 // Keys of the partition of outer iteration it->k (or of the given k if it is
 // null): upper 32 bits of SplitMix64 output j of the stream seeded with output
 // k of the stream seeded with `seed`.

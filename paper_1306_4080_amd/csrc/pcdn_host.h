@@ -94,6 +94,8 @@ struct pcdn_ctx {
   float* pv = nullptr;
   int64_t* poff = nullptr;
   int32_t* off32 = nullptr;
+  uint16_t* plid = nullptr;  // bundle-local row ids of X in partition order
+  int32_t* pR = nullptr;     // distinct rows per bundle (or -1)
   // shrinking: active mask (1/0 per feature), reduction partials, and the
   // host's copy of the next iteration's active count and nonzeros
   double* act = nullptr;
@@ -149,6 +151,12 @@ struct pcdn_ctx {
     double nnz_gh_narrow = 0, slots_narrow = 0;
   } hc, prof_hc;
   std::vector<int64_t> h_cp;  // host copy of col_ptr
+  // top_len[k]: nonzeros of the k longest columns (k <= kNarrowMaxP), an
+  // upper bound on the nonzeros of any bundle of k features
+  std::vector<int64_t> top_len;
+  // heavy-bundle list of the current partition (device, and pinned host copy)
+  int32_t* heavy = nullptr;
+  int32_t* hheavy = nullptr;
 
   pcdn::host::Profiler prof;
   Stats prof_base{};
@@ -196,6 +204,16 @@ int check_loss(pcdn_ctx* c, int loss);
 void note_regulariser(pcdn_ctx* c, const Opts& o);
 // Whether outer iterations with bundle size P run in one workgroup.
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
+// Whether the batch engine runs this single-workgroup job's bundles of at
+// least kHeavyNnz nonzeros on the multi-kernel path (automatic schedule, and
+// such bundles can exist).
+bool use_hybrid(const pcdn_ctx* c, const Opts& o, int64_t P);
+// Single-workgroup arguments for bundles [t_begin, t_end) of the current
+// outer iteration's partition.
+pcdn::NarrowArgs segment_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P, int64_t t_begin,
+                                     int64_t t_end);
+// The multi-kernel bundle on slots [lo, hi) of the current partition.
+int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi, bool clip);
 // Arguments of the single-workgroup kernel for bundles [t_begin, t_end).
 pcdn::NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm,
                                   int64_t p_slots, int64_t P, int64_t t_begin, int64_t t_end,

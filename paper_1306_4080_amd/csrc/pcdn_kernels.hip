@@ -791,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Single-workgroup schedule: one 1024-thread workgroup runs every bundle of an
+// Single-workgroup schedule: one 512-thread workgroup runs every bundle of an
 // outer iteration of one problem, phase after phase, with workgroup barriers
 // as the only synchronisation (no kernel boundary per bundle).  Same
 // arithmetic as the multi-kernel path.  Small bundles are bound by the
@@ -801,10 +801,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
 //    segmented wavefront scan (keys = slot) sums g_j, h_j; slots that cross a
 //    64-nonzero chunk are completed from LDS partials in chunk order, so the
 //    sums are deterministic;
-//  - the thread that first touches a row in the scatter (per-row flag) stores
-//    the row's retained quantity and label, already in its registers, in an
-//    LDS list; the line search and the apply then run from LDS, and the only
-//    reads after the scatter are the d^T x values (built with L2 atomics);
+//  - the thread that first touches a row in the scatter lists the row, its
+//    retained quantity and label, already in its registers, in LDS; the line
+//    search and the apply then run over that list;
+//  - with bundle-local row ids (k_bundle_rows, at most kNarrowLidCap distinct
+//    rows) d^T x is accumulated in LDS by local id and the first toucher is
+//    found with an LDS bit per id: the scatter, the line search and the
+//    apply touch global memory only to write the updated retained
+//    quantities;
+//  - otherwise d^T x is built in global memory with L2 atomics, the first
+//    toucher is found with a per-row flag in global memory, and d^T x of the
+//    listed rows is read back;
 //  - candidates are tested one pass at a time in increasing q (Algorithm 4's
 //    order), so an accepted unit step costs a single pass.
 // Overflowing any LDS list falls back to global-memory passes (correct, slower).
@@ -858,6 +865,63 @@ __device__ inline double load_l2(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Bundle-local row ids for the single-workgroup schedule: one workgroup per
+// bundle marks the rows of its nonzeros in an LDS bitmap of the n rows; a
+// row's id is the number of marked rows below it (so ids follow the row
+// order and do not depend on timing), found from per-word prefix counts.
+constexpr int kRowsBlock = 256;
+
+__global__ __launch_bounds__(kRowsBlock) void k_bundle_rows(const int64_t* poff,
+                                                            const int32_t* pri, int64_t p_slots,
+                                                            int64_t P, int64_t n, uint16_t* plid,
+                                                            int32_t* pR) {
+  extern __shared__ uint32_t rows_lds[];
+  __shared__ uint32_t part[kRowsBlock];
+  const int64_t words = (n + 31) >> 5;
+  uint32_t* bits = rows_lds;
+  uint32_t* pre = rows_lds + words;
+  const int64_t t = blockIdx.x;
+  const int64_t lo = t * P, hi = lo + P < p_slots ? lo + P : p_slots;
+  const int64_t k0 = poff[lo], k1 = poff[hi];
+  for (int64_t w = threadIdx.x; w < words; w += kRowsBlock) bits[w] = 0u;
+  __syncthreads();
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kRowsBlock) {
+    const int32_t r = pri[k];
+    atomicOr(&bits[r >> 5], 1u << (r & 31));
+  }
+  __syncthreads();
+  // exclusive prefix of the words' popcounts: thread i covers a contiguous
+  // run of words, then an inclusive scan of the runs' counts
+  const int64_t per = (words + kRowsBlock - 1) / kRowsBlock;
+  const int64_t w0 = threadIdx.x * per, w1 = w0 + per < words ? w0 + per : words;
+  uint32_t cnt = 0;
+  for (int64_t w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < kRowsBlock; off <<= 1) {
+    const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - cnt;
+  for (int64_t w = w0; w < w1; ++w) {
+    pre[w] = run;
+    run += __popc(bits[w]);
+  }
+  const uint32_t R = part[kRowsBlock - 1];
+  __syncthreads();
+  if (threadIdx.x == 0) pR[t] = R <= (uint32_t)kNarrowLidCap ? (int32_t)R : -1;
+  if (R > (uint32_t)kNarrowLidCap) return;
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kRowsBlock) {
+    const int32_t r = pri[k];
+    const uint32_t below = bits[r >> 5] & ((1u << (r & 31)) - 1u);
+    plid[k] = (uint16_t)(pre[r >> 5] + __popc(below));
+  }
+}
+
+static_assert(kNarrowLidCap <= kTouchCap, "local row ids index the LDS row lists");
+
 struct NarrowLds {
   double lds16[kNarrowWaves];
   double red[2][kNarrowWaves][4];
@@ -870,6 +934,8 @@ struct NarrowLds {
   double2 pf[kNarrowChunkCap];         // first segment of each 64-nonzero chunk
   double2 pl[kNarrowChunkCap];         // last segment of each chunk
   int32_t t_row[kTouchCap];
+  int16_t t_lid[kTouchCap];            // local row id of each listed row
+  uint32_t t_seen[kTouchCap / 32];     // local row ids already listed
   int8_t t_y[kTouchCap];
   double t_c[kTouchCap];
   double t_dtx[kTouchCap];
@@ -885,6 +951,16 @@ __device__ inline int32_t slot_of(const int32_t* off, int32_t nslots, int32_t v)
   return lo;
 }
 
+// List a row by its local id (at most kNarrowLidCap distinct rows: no
+// overflow).
+__device__ inline void list_lid(NarrowLds& L, int32_t lid, int32_t row, double c, int yi) {
+  const int32_t e = atomicAdd(&L.n_touch, 1);
+  L.t_row[e] = row;
+  L.t_lid[e] = (int16_t)lid;
+  L.t_c[e] = c;
+  L.t_y[e] = (int8_t)yi;
+}
+
 // Append a row, first touched by this thread, to the bundle's LDS list (the
 // count keeps growing past the capacity so that an overflow is seen).
 __device__ inline void list_row(NarrowLds& L, int32_t row, double c, int yi) {
@@ -893,6 +969,38 @@ __device__ inline void list_row(NarrowLds& L, int32_t row, double c, int yi) {
     L.t_row[e] = row;
     L.t_c[e] = c;
     L.t_y[e] = (int8_t)yi;
+  }
+}
+
+// One round of the sweep for bundle nonzero v (slot s, row, value x, the
+// row's retained quantity c and label yi): its g, h terms, the segmented
+// wavefront sums, and the per-slot or per-chunk record of each segment end.
+// Every lane of the wavefront calls it (lanes past nb carry slot -1).
+template <int LOSS>
+__device__ __forceinline__ void narrow_term(NarrowLds& L, int32_t v, int32_t nb, int32_t ns,
+                                            int32_t row, float x, double c, int yi, int32_t s,
+                                            double2* pf, double2* pl) {
+  (void)row;
+  (void)ns;
+  const bool valid = v < nb;
+  if (!valid) s = -1;
+  double g = 0.0, h = 0.0;
+  if (valid) grad_hess_term<LOSS>(c, yi, (double)x, g, h);
+  // inclusive segmented scan over the wavefront (slots ascend along lanes;
+  // lanes past the end carry slot -1 and zero terms)
+  seg_scan(g, h, s);
+  const bool seg_end = valid && next_lane_key(s) != s;
+  if (seg_end) {
+    const int32_t m = v / kWave;                 // chunk of this nonzero
+    const int32_t cbeg = m * kWave, cend = cbeg + kWave - 1;
+    const bool left_open = L.off[s] < cbeg;
+    const bool right_open = L.off[s + 1] - 1 > cend;
+    if (!left_open && !right_open)
+      L.acc[s] = make_double2(g, h);             // the slot lies in this chunk
+    else if (left_open)
+      pf[m] = make_double2(g, h);                // first segment of chunk m
+    else
+      pl[m] = make_double2(g, h);                // last segment of chunk m
   }
 }
 
@@ -922,6 +1030,12 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       L.acc[s] = make_double2(0.0, 0.0);
     }
     if (tid == 0) L.n_touch = 0;
+    // distinct rows of the bundle with d^T x kept in LDS (t_row/t_c/t_y/t_dtx
+    // indexed by local row id), or -1: d^T x in global memory, rows listed
+    // by their first toucher
+    const int32_t R = na.pR ? na.pR[t] : -1;
+    for (int32_t e = tid; e < R; e += kNarrowBlock) L.t_dtx[e] = 0.0;
+    for (int32_t e = tid; e < (R + 31) / 32; e += kNarrowBlock) L.t_seen[e] = 0u;
     __syncthreads();
     const int32_t nb = L.off[ns];
     const int32_t nchunks = (nb + kWave - 1) / kWave;
@@ -934,11 +1048,13 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     double rc[kNarrowRegRounds];
     int ry[kNarrowRegRounds];
     int32_t rs[kNarrowRegRounds];
+    int32_t rl[kNarrowRegRounds];
 #pragma unroll
     for (int u = 0; u < kNarrowRegRounds; ++u) {
       const int32_t v = u * kNarrowBlock + tid;
       rrow[u] = v < nb ? na.pri[base + v] : 0;
       rx[u] = v < nb ? na.pv[base + v] : 0.0f;
+      rl[u] = (v < nb && R >= 0) ? (int32_t)na.plid[base + v] : 0;
     }
 #pragma unroll
     for (int u = 0; u < kNarrowRegRounds; ++u) {
@@ -947,49 +1063,37 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       rc[u] = v < nb ? a.cache[rrow[u]] : 0.0;
       ry[u] = v < nb ? (int)a.y[rrow[u]] : 0;
     }
-    int round = 0;
-    for (int32_t r0 = 0; r0 < nb; r0 += kNarrowBlock, ++round) {
-      const int32_t v = r0 + tid;
-      const bool valid = v < nb;
-      int32_t row = 0, s = -1;
-      float x = 0.0f;
-      double c = 0.0;
-      int yi = 0;
-      if (round < kNarrowRegRounds) {
 #pragma unroll
-        for (int u = 0; u < kNarrowRegRounds; ++u)
-          if (u == round) {
-            row = rrow[u];
-            x = rx[u];
-            c = rc[u];
-            yi = ry[u];
-            s = rs[u];
-          }
-      } else if (valid) {
-        row = na.pri[base + v];
-        x = na.pv[base + v];
-        s = slot_of(L.off, ns, v);
-        c = a.cache[row];
-        yi = (int)a.y[row];
+    for (int u = 0; u < kNarrowRegRounds; ++u)
+      if (u * kNarrowBlock < nb)
+        narrow_term<LOSS>(L, u * kNarrowBlock + tid, nb, ns, rrow[u], rx[u], rc[u], ry[u], rs[u],
+                          pf, pl);
+    // later rounds in groups of kNarrowRegRounds, each group's loads issued
+    // together (two dependent round trips per group)
+    for (int32_t g0 = kNarrowRegRounds * kNarrowBlock; g0 < nb;
+         g0 += kNarrowRegRounds * kNarrowBlock) {
+      int32_t grow[kNarrowRegRounds], gs[kNarrowRegRounds];
+      float gx[kNarrowRegRounds];
+      double gc[kNarrowRegRounds];
+      int gy[kNarrowRegRounds];
+#pragma unroll
+      for (int u = 0; u < kNarrowRegRounds; ++u) {
+        const int32_t v = g0 + u * kNarrowBlock + tid;
+        grow[u] = v < nb ? na.pri[base + v] : 0;
+        gx[u] = v < nb ? na.pv[base + v] : 0.0f;
       }
-      double g = 0.0, h = 0.0;
-      if (valid) grad_hess_term<LOSS>(c, yi, (double)x, g, h);
-      // inclusive segmented scan over the wavefront (slots ascend along lanes;
-      // lanes past the end carry slot -1 and zero terms)
-      seg_scan(g, h, s);
-      const bool seg_end = valid && next_lane_key(s) != s;
-      if (seg_end) {
-        const int32_t m = v / kWave;                 // chunk of this nonzero
-        const int32_t cbeg = m * kWave, cend = cbeg + kWave - 1;
-        const bool left_open = L.off[s] < cbeg;
-        const bool right_open = L.off[s + 1] - 1 > cend;
-        if (!left_open && !right_open)
-          L.acc[s] = make_double2(g, h);             // the slot lies in this chunk
-        else if (left_open)
-          pf[m] = make_double2(g, h);                // first segment of chunk m
-        else
-          pl[m] = make_double2(g, h);                // last segment of chunk m
+#pragma unroll
+      for (int u = 0; u < kNarrowRegRounds; ++u) {
+        const int32_t v = g0 + u * kNarrowBlock + tid;
+        gs[u] = v < nb ? slot_of(L.off, ns, v) : -1;
+        gc[u] = v < nb ? a.cache[grow[u]] : 0.0;
+        gy[u] = v < nb ? (int)a.y[grow[u]] : 0;
       }
+#pragma unroll
+      for (int u = 0; u < kNarrowRegRounds; ++u)
+        if (g0 + u * kNarrowBlock < nb)
+          narrow_term<LOSS>(L, g0 + u * kNarrowBlock + tid, nb, ns, grow[u], gx[u], gc[u], gy[u],
+                            gs[u], pf, pl);
     }
     __syncthreads();
     // slots spanning several chunks: head (pl) + middle chunks (pf) + tail (pf)
@@ -1030,7 +1134,61 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     // 2. scatter d_j x_ij into d^T x; list touched rows with their retained
     //    quantity and label
     //    The register rounds issue every flag exchange before waiting on any.
-    {
+    if (R >= 0) {
+      // d^T x by local row id with LDS atomics; the first toucher of a row
+      // (LDS bit per local id) lists it: no global memory traffic
+#pragma unroll
+      for (int u = 0; u < kNarrowRegRounds; ++u) {
+        if (u * kNarrowBlock + tid < nb) {
+          const double dj = L.d[rs[u]];
+          if (dj != 0.0) {
+            atomicAdd(&L.t_dtx[rl[u]], dj * (double)rx[u]);
+            const uint32_t bit = 1u << (rl[u] & 31);
+            if ((atomicOr(&L.t_seen[rl[u] >> 5], bit) & bit) == 0u)
+              list_lid(L, rl[u], rrow[u], rc[u], ry[u]);
+          }
+        }
+      }
+      // later rounds in groups, loads of a group issued together
+      for (int32_t g0 = kNarrowRegRounds * kNarrowBlock; g0 < nb;
+           g0 += kNarrowRegRounds * kNarrowBlock) {
+        double gd[kNarrowRegRounds], gc[kNarrowRegRounds];
+        int32_t glid[kNarrowRegRounds], grow[kNarrowRegRounds];
+        float gx[kNarrowRegRounds];
+        int gy[kNarrowRegRounds];
+        bool first[kNarrowRegRounds];
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int32_t v = g0 + u * kNarrowBlock + tid;
+          gd[u] = v < nb ? L.d[slot_of(L.off, ns, v)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int32_t v = g0 + u * kNarrowBlock + tid;
+          const bool on = gd[u] != 0.0;
+          glid[u] = on ? (int32_t)na.plid[base + v] : 0;
+          gx[u] = on ? na.pv[base + v] : 0.0f;
+          grow[u] = on ? na.pri[base + v] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          first[u] = false;
+          if (gd[u] != 0.0) {
+            atomicAdd(&L.t_dtx[glid[u]], gd[u] * (double)gx[u]);
+            const uint32_t bit = 1u << (glid[u] & 31);
+            first[u] = (atomicOr(&L.t_seen[glid[u] >> 5], bit) & bit) == 0u;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          gc[u] = first[u] ? a.cache[grow[u]] : 0.0;
+          gy[u] = first[u] ? (int)a.y[grow[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u)
+          if (first[u]) list_lid(L, glid[u], grow[u], gc[u], gy[u]);
+      }
+    } else {
       unsigned was[kNarrowRegRounds];
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u) {
@@ -1046,20 +1204,47 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u)
         if (was[u] == 0u) list_row(L, rrow[u], rc[u], ry[u]);
-    }
-    for (int32_t v = kNarrowRegRounds * kNarrowBlock + tid; v < nb; v += kNarrowBlock) {
-      const int32_t row = na.pri[base + v];
-      const float x = na.pv[base + v];
-      const int32_t s = slot_of(L.off, ns, v);
-      const double dj = L.d[s];
-      if (dj == 0.0) continue;
-      unsafeAtomicAdd(&a.dtx[row], dj * (double)x);
-      if (atomicExch(&na.rowflag[row], 1u) == 0u) list_row(L, row, a.cache[row], (int)a.y[row]);
+      for (int32_t g0 = kNarrowRegRounds * kNarrowBlock; g0 < nb;
+           g0 += kNarrowRegRounds * kNarrowBlock) {
+        double gd[kNarrowRegRounds], gc[kNarrowRegRounds];
+        int32_t grow[kNarrowRegRounds];
+        float gx[kNarrowRegRounds];
+        int gy[kNarrowRegRounds];
+        unsigned gwas[kNarrowRegRounds];
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int32_t v = g0 + u * kNarrowBlock + tid;
+          gd[u] = v < nb ? L.d[slot_of(L.off, ns, v)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int32_t v = g0 + u * kNarrowBlock + tid;
+          const bool on = gd[u] != 0.0;
+          grow[u] = on ? na.pri[base + v] : 0;
+          gx[u] = on ? na.pv[base + v] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          gwas[u] = 1u;
+          if (gd[u] != 0.0) {
+            unsafeAtomicAdd(&a.dtx[grow[u]], gd[u] * (double)gx[u]);
+            gwas[u] = atomicExch(&na.rowflag[grow[u]], 1u);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          gc[u] = gwas[u] == 0u ? a.cache[grow[u]] : 0.0;
+          gy[u] = gwas[u] == 0u ? (int)a.y[grow[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u)
+          if (gwas[u] == 0u) list_row(L, grow[u], gc[u], gy[u]);
+      }
     }
     __syncthreads();
     const int32_t n_touch = L.n_touch;
     const bool listed = n_touch <= kTouchCap;
-    if (listed)
+    if (listed && R < 0)
       for (int32_t e = tid; e < n_touch; e += kNarrowBlock) L.t_dtx[e] = load_l2(&a.dtx[L.t_row[e]]);
     __syncthreads();
     // 3. candidates q = 0, 1, ... until the Armijo test (eq. (6)) holds
@@ -1070,7 +1255,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       double sl = 0.0, l1 = 0.0, touched = 0.0;
       if (listed) {
         for (int32_t e = tid; e < n_touch; e += kNarrowBlock) {
-          const double dl = L.t_dtx[e];
+          const double dl = L.t_dtx[R >= 0 ? (int32_t)L.t_lid[e] : e];
           if (dl == 0.0) continue;
           touched += 1.0;
           double sc = dl;
@@ -1078,13 +1263,31 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           sl += loss_delta<LOSS>(L.t_c[e], (int)L.t_y[e], sc);
         }
       } else {
-        for (int64_t i = tid; i < na.n; i += kNarrowBlock) {
-          const double dl = load_l2(&a.dtx[i]);
-          if (dl == 0.0) continue;
-          touched += 1.0;
-          double sc = dl;
-          for (int u = 0; u < q; ++u) sc *= na.beta;
-          sl += loss_delta<LOSS>(a.cache[i], (int)a.y[i], sc);
+        // every sample (more touched rows than the LDS list holds), the loads
+        // of kNarrowRegRounds samples issued together; same summation order
+        for (int64_t i0 = tid; i0 < na.n; i0 += (int64_t)kNarrowRegRounds * kNarrowBlock) {
+          double fd[kNarrowRegRounds], fc[kNarrowRegRounds];
+          int fy[kNarrowRegRounds];
+#pragma unroll
+          for (int u = 0; u < kNarrowRegRounds; ++u) {
+            const int64_t i = i0 + (int64_t)u * kNarrowBlock;
+            fd[u] = i < na.n ? load_l2(&a.dtx[i]) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kNarrowRegRounds; ++u) {
+            const int64_t i = i0 + (int64_t)u * kNarrowBlock;
+            fc[u] = fd[u] != 0.0 ? a.cache[i] : 0.0;
+            fy[u] = fd[u] != 0.0 ? (int)a.y[i] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < kNarrowRegRounds; ++u) {
+            if (fd[u] != 0.0) {
+              touched += 1.0;
+              double sc = fd[u];
+              for (int k = 0; k < q; ++k) sc *= na.beta;
+              sl += loss_delta<LOSS>(fc[u], fy[u], sc);
+            }
+          }
         }
       }
       for (int32_t s = tid; s < ns; s += kNarrowBlock) l1 += reg_change(L.w[s], al * L.d[s], a.ra, a.rb);
@@ -1117,13 +1320,21 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     n_fail += q_acc < 0 ? 1.0 : 0.0;
     // 4. accept: w, retained quantities; clear d^T x and the row flags
     if (na.dtx_copy) {
-      for (int64_t i = tid; i < na.n; i += kNarrowBlock) na.dtx_copy[i] = load_l2(&a.dtx[i]);
+      if (R >= 0) {
+        // the listed rows' values over zeros
+        for (int64_t i = tid; i < na.n; i += kNarrowBlock) na.dtx_copy[i] = 0.0;
+        __syncthreads();
+        for (int32_t e = tid; e < n_touch; e += kNarrowBlock)
+          na.dtx_copy[L.t_row[e]] = L.t_dtx[L.t_lid[e]];
+      } else {
+        for (int64_t i = tid; i < na.n; i += kNarrowBlock) na.dtx_copy[i] = load_l2(&a.dtx[i]);
+      }
       __syncthreads();  // copied before any thread clears d^T x below
     }
     if (listed) {
       for (int32_t e = tid; e < n_touch; e += kNarrowBlock) {
         const int32_t i = L.t_row[e];
-        const double dl = L.t_dtx[e];
+        const double dl = L.t_dtx[R >= 0 ? (int32_t)L.t_lid[e] : e];
         if (q_acc >= 0 && dl != 0.0) {
           double sc = dl;
           for (int u = 0; u < q_acc; ++u) sc *= na.beta;
@@ -1132,22 +1343,42 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           else
             na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sc : -sc);
         }
-        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        na.rowflag[i] = 0u;
+        if (R < 0) {
+          __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          na.rowflag[i] = 0u;
+        }
       }
     } else {
-      for (int64_t i = tid; i < na.n; i += kNarrowBlock) {
-        const double dl = load_l2(&a.dtx[i]);
-        if (q_acc >= 0 && dl != 0.0) {
-          double sc = dl;
-          for (int u = 0; u < q_acc; ++u) sc *= na.beta;
-          if (LOSS == kLogistic)
-            na.cache[i] *= exp(sc);
-          else
-            na.cache[i] -= a.y[i] > 0 ? sc : -sc;
+      for (int64_t i0 = tid; i0 < na.n; i0 += (int64_t)kNarrowRegRounds * kNarrowBlock) {
+        double fd[kNarrowRegRounds], fc[kNarrowRegRounds];
+        int fy[kNarrowRegRounds];
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int64_t i = i0 + (int64_t)u * kNarrowBlock;
+          fd[u] = i < na.n ? load_l2(&a.dtx[i]) : 0.0;
         }
-        __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        na.rowflag[i] = 0u;
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int64_t i = i0 + (int64_t)u * kNarrowBlock;
+          const bool upd = q_acc >= 0 && fd[u] != 0.0;
+          fc[u] = upd ? na.cache[i] : 0.0;
+          fy[u] = (upd && LOSS != kLogistic) ? (int)a.y[i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kNarrowRegRounds; ++u) {
+          const int64_t i = i0 + (int64_t)u * kNarrowBlock;
+          if (i >= na.n) continue;
+          if (q_acc >= 0 && fd[u] != 0.0) {
+            double sc = fd[u];
+            for (int k = 0; k < q_acc; ++k) sc *= na.beta;
+            if (LOSS == kLogistic)
+              na.cache[i] = fc[u] * exp(sc);
+            else
+              na.cache[i] = fc[u] - (fy[u] > 0 ? sc : -sc);
+          }
+          __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          na.rowflag[i] = 0u;
+        }
       }
     }
     if (q_acc >= 0)
@@ -1564,6 +1795,61 @@ hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, con
                      poff);
   hipLaunchKernelGGL(k_permute, dim3(grid_for(p, kWavesPerBlock, 8192)), dim3(kBlock), 0, s, ri, v,
                      cp, chunks, cstart, p, poff, pri, pv);
+  return hipGetLastError();
+}
+
+hipError_t launch_bundle_rows(const int64_t* poff, const int32_t* pri, int64_t p_slots, int64_t P,
+                              int64_t n, uint16_t* plid, int32_t* pR, hipStream_t s) {
+  const int64_t words = (n + 31) >> 5;
+  if (words > kRowsMaxWords || P < 1 || p_slots < 1) return hipErrorInvalidValue;
+  const int64_t nbundles = (p_slots + P - 1) / P;
+  hipLaunchKernelGGL(k_bundle_rows, dim3((unsigned)nbundles), dim3(kRowsBlock),
+                     (size_t)(2 * words * sizeof(uint32_t)), s, poff, pri, p_slots, P, n, plid, pR);
+  return hipGetLastError();
+}
+
+// Heavy-bundle list: one workgroup walks the bundles 1024 at a time; ballots
+// and per-wave counts give each heavy bundle its position, so the list is in
+// ascending order.
+__global__ __launch_bounds__(1024) void k_heavy_bundles(const int64_t* poff, int64_t p_slots,
+                                                        int64_t P, int64_t thresh, int32_t cap,
+                                                        int32_t* out) {
+  __shared__ int32_t wcnt[1024 / kWave];
+  __shared__ int32_t total;
+  if (threadIdx.x == 0) total = 0;
+  __syncthreads();
+  const int lane = lane_id(), wv = threadIdx.x / kWave;
+  const int64_t nb = (p_slots + P - 1) / P;
+  for (int64_t t0 = 0; t0 < nb; t0 += 1024) {
+    const int64_t t = t0 + threadIdx.x;
+    bool heavy = false;
+    if (t < nb) {
+      const int64_t lo = t * P, hi = lo + P < p_slots ? lo + P : p_slots;
+      heavy = poff[hi] - poff[lo] >= thresh;
+    }
+    const uint64_t m = __ballot(heavy);
+    if (lane == 0) wcnt[wv] = __popcll(m);
+    __syncthreads();
+    int32_t pos = total;
+    for (int k = 0; k < wv; ++k) pos += wcnt[k];
+    pos += __popcll(m & ((1ull << lane) - 1ull));
+    if (heavy && pos < cap) out[1 + pos] = (int32_t)t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t sum = 0;
+      for (int k = 0; k < 1024 / kWave; ++k) sum += wcnt[k];
+      total += sum;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = total < cap ? total : cap;
+}
+
+hipError_t launch_heavy_bundles(const int64_t* poff, int64_t p_slots, int64_t P, int64_t thresh,
+                                int32_t cap, int32_t* out, hipStream_t s) {
+  if (P < 1 || p_slots < 1 || cap < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_heavy_bundles, dim3(1), dim3(1024), 0, s, poff, p_slots, P, thresh, cap,
+                     out);
   return hipGetLastError();
 }
 
