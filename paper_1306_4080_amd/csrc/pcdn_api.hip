@@ -1263,6 +1263,12 @@ extern "C" int pcdn_solve(pcdn_ctx* c, double C, int64_t P, double eps, int loss
   SolveRun r;
   int rc = check_solve_args(c, C, P, eps, loss, opts, &r.o);
   if (rc) return rc;
+  if (use_hybrid(c, r.o, P) && !c->prof.mask) {
+    // heavy bundles on the multi-kernel path: the batch engine's rounds
+    pcdn_job job{c, C, P, eps, loss, PCDN_OK, opts, w_out, info};
+    rc = pcdn_solve_batch(&job, 1);
+    return rc < 0 ? rc : job.status;
+  }
   r.c = c;
   r.C = C;
   r.P = P;
@@ -1291,6 +1297,8 @@ extern "C" int pcdn_iterate(pcdn_ctx* c, int64_t P, int64_t k_first, int64_t cou
   Opts o;
   int rc = resolve_opts(c, opts, &o);
   if (rc) return rc;
+  if (count > 0 && use_hybrid(c, o, P) && !c->prof.mask)  // as pcdn_solve
+    return pcdn_iterate_batch(&c, &P, 1, k_first, count, opts, subgrad);
   note_regulariser(c, o);
   HIPCHK(c, hipSetDevice(c->device));
   rc = run_outer(c, o, P, k_first, count);

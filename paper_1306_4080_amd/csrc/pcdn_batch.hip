@@ -226,25 +226,44 @@ class Engine {
     // segments between heavy bundles in one workgroup, each heavy bundle on
     // the multi-kernel path, in partition order
     if (any_hybrid) {
+      std::vector<EngineJob*> hj;
+      std::vector<int64_t> next;  // first bundle not yet enqueued, per job
       for (EngineJob* j : jobs_) {
         if (!j->hybrid) continue;
         pcdn_ctx* c = j->run.c;
         *err_ctx = c;
-        const Opts& o = j->run.o;
-        const int64_t P = j->run.P, nb = (c->p + P - 1) / P;
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        const int32_t nh = std::min<int32_t>(std::max<int32_t>(c->hheavy[0], 0), kHeavyCap);
-        int64_t t = 0;
-        for (int32_t k = 0; k <= nh; ++k) {
-          const int64_t te = k < nh ? std::min<int64_t>(std::max<int64_t>(c->hheavy[1 + k], t), nb)
-                                    : nb;
+        hj.push_back(j);
+        next.push_back(0);
+      }
+      // enqueue the jobs' segments round-robin, so that every job starts at once
+      for (int32_t k = 0;; ++k) {
+        bool more = false;
+        for (size_t i = 0; i < hj.size(); ++i) {
+          pcdn_ctx* c = hj[i]->run.c;
+          const Opts& o = hj[i]->run.o;
+          const int64_t P = hj[i]->run.P, nb = (c->p + P - 1) / P;
+          const int32_t nh = std::min<int32_t>(std::max<int32_t>(c->hheavy[0], 0), kHeavyCap);
+          int64_t& t = next[i];
+          if (k > nh || t >= nb) continue;
+          *err_ctx = c;
+          const int64_t te =
+              k < nh ? std::min<int64_t>(std::max<int64_t>(c->hheavy[1 + k], t), nb) : nb;
           if (te > t) HIPCHK(c, launch_narrow(c->loss, segment_narrow_args(c, o, P, t, te), c->stream));
-          if (k == nh || te >= nb) break;
-          const int64_t lo = te * P, hi = std::min(lo + P, c->p);
-          rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
-          if (rc) return rc;
-          t = te + 1;
+          t = te;
+          if (k < nh && te < nb) {
+            const int64_t lo = te * P, hi = std::min(lo + P, c->p);
+            rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
+            if (rc) return rc;
+            t = te + 1;
+          }
+          more = true;
         }
+        if (!more) break;
+      }
+      for (EngineJob* j : hj) {
+        pcdn_ctx* c = j->run.c;
+        *err_ctx = c;
         HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));

@@ -343,7 +343,9 @@ def test_batch_heavy_bundles_on_multi_kernel_path(pc):
     on the multi-kernel path between single-workgroup segments.  Each job
     equals the plain single-workgroup solve alone and the oracle's, with and
     without shrinking; pcdn_iterate_batch on the same jobs ends where
-    pcdn_iterate does."""
+    pcdn_iterate does (the plain runs forced onto the single-workgroup
+    schedule; pcdn_solve and pcdn_iterate take the engine's path under the
+    automatic one)."""
     d = synth.c2()
     prob = oracle.Problem.from_data(d)
     jobs = [(0.5, 64, {}), (4.0, 64, {}), (0.5, 64, {"shrink": True})]
@@ -353,6 +355,7 @@ def test_batch_heavy_bundles_on_multi_kernel_path(pc):
     for s, (C, P, o), b in zip(solvers, jobs, batched):
         print(f"C={C} P={P} {o}: outer={b[2]['outer_iters']} F={b[2]['objective']:.15g}",
               flush=True)
+        _assert_same_run(b, s.solve(C, P, 1e-4, "lr", seed=1, schedule="narrow", **o))
         _assert_same_run(b, s.solve(C, P, 1e-4, "lr", seed=1, **o))
         w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=C, **o), P=P, eps=1e-4, seed=1)
         _assert_oracle(b, (w_o, io), True)
@@ -363,7 +366,7 @@ def test_batch_heavy_bundles_on_multi_kernel_path(pc):
         t.reset("lr", C)
     G = pc.iterate_batch(solvers[:2], [64, 64], 0, 4, seed=2)
     for s, t, g in zip(solvers[:2], other, G):
-        assert g == pytest.approx(t.iterate(64, 0, 4, seed=2), rel=1e-9)
+        assert g == pytest.approx(t.iterate(64, 0, 4, seed=2, schedule="narrow"), rel=1e-9)
         np.testing.assert_allclose(s.w(), t.w(), rtol=1e-9, atol=1e-12)
     for s in solvers + other:
         s.close()
