@@ -244,8 +244,9 @@ constexpr int64_t kRowsMaxWords = 7936;
 
 // Bundles with at least kHeavyNnz nonzeros run on the multi-kernel path
 // between single-workgroup segments (batch engine, automatic schedule); at
-// most kHeavyCap of them per outer iteration are listed.
-constexpr int64_t kHeavyNnz = 6144;
+// most kHeavyCap of them per outer iteration are listed.  At kNarrowLidCap,
+// every bundle left to the single workgroup keeps its d^T x in LDS.
+constexpr int64_t kHeavyNnz = 4096;
 constexpr int kHeavyCap = 256;
 
 // ---- host-callable launchers (pcdn_kernels.hip) -------------------------

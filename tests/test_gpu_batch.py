@@ -339,7 +339,7 @@ def test_batch_regularised_jobs(pc):
 
 def test_batch_heavy_bundles_on_multi_kernel_path(pc):
     """The text-like matrix at P = 64 (automatic schedule) in the batch engine:
-    bundles of at least 6,144 nonzeros (those holding Zipf-head columns) run
+    bundles of at least 4,096 nonzeros (those holding Zipf-head columns) run
     on the multi-kernel path between single-workgroup segments.  Each job
     equals the plain single-workgroup solve alone and the oracle's, with and
     without shrinking; pcdn_iterate_batch on the same jobs ends where
