@@ -106,7 +106,7 @@ enum { PCDN_PENALTY_L1 = 0, PCDN_PENALTY_ELASTIC = 1, PCDN_PENALTY_L2 = 2 };
  *          (long columns), the solve runs in the rounds of the batch engine
  *          (pcdn_solve_batch), which reads each partition's list of such
  *          bundles and runs them as WIDE between single-workgroup segments
- *          (not while kernel profiling is on). */
+ *          (with kernel profiling on, direct launches that do the same). */
 enum { PCDN_SCHED_AUTO = 0, PCDN_SCHED_WIDE = 1, PCDN_SCHED_NARROW = 2 };
 
 /* Per-solve report. */

@@ -558,10 +558,39 @@ int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
   return launch_stopping(c, o, c->w, it);
 }
 
+// Every bundle with the heavy ones on the multi-kernel path (the list that
+// enqueue_pre wrote is read back first: direct launches only).
+int enqueue_bundles_hybrid(pcdn_ctx* c, const Opts& o, int64_t P) {
+  HIPCHK(c, hipMemcpyAsync(c->hheavy, c->heavy, (kHeavyCap + 1) * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int64_t nb = (c->p + P - 1) / P;
+  const int32_t nh = std::min<int32_t>(std::max<int32_t>(c->hheavy[0], 0), kHeavyCap);
+  int64_t t = 0;
+  for (int32_t k = 0; k <= nh && t < nb; ++k) {
+    const int64_t te = k < nh ? std::min<int64_t>(std::max<int64_t>(c->hheavy[1 + k], t), nb) : nb;
+    if (te > t) {
+      ProfScope ps(c, 5);
+      HIPCHK(c, launch_narrow(c->loss, segment_narrow_args(c, o, P, t, te), c->stream));
+    }
+    t = te;
+    if (k < nh && te < nb) {
+      const int64_t lo = te * P, hi = std::min(lo + P, c->p);
+      const int rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
+      if (rc) return rc;
+      t = te + 1;
+    }
+  }
+  return PCDN_OK;
+}
+
 int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it) {
-  int rc = enqueue_pre(c, o, P, k, it, false);
+  // heavy bundles on the multi-kernel path only for direct launches (not
+  // while a graph is captured, it != null)
+  const bool hybrid = it == nullptr && use_hybrid(c, o, P);
+  int rc = enqueue_pre(c, o, P, k, it, hybrid);
   if (rc) return rc;
-  rc = enqueue_bundles(c, o, P);
+  rc = hybrid ? enqueue_bundles_hybrid(c, o, P) : enqueue_bundles(c, o, P);
   if (rc) return rc;
   return enqueue_post(c, o, P, it);
 }
