@@ -552,8 +552,8 @@ int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
 
 // After the bundles: scatter counters and the stopping sweep.
 int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
-  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, use_narrow(c, o, P),
-                                 o.shrink ? c->scal + 5 : nullptr, c->stats, c->stream));
+  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, o.shrink ? c->scal + 5 : nullptr,
+                                 c->stats, c->stream));
   if (o.shrink) return launch_stopping_shrink(c, o, it);
   return launch_stopping(c, o, c->w, it);
 }
@@ -624,7 +624,7 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     out.push_back(t);
   }
   Task t = task(kTaskScatterCount, scatter_count_grid(c->p), 0);
-  t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, 0, c->stats,
+  t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, c->stats,
                             o.shrink ? c->scal + 5 : nullptr};
   out.push_back(t);
   t = task(kTaskSweepStop, sweep_grid(c->p), 0);
@@ -727,12 +727,9 @@ void count_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t count) {
   // exact for one iteration at a time, as the drivers run them)
   const double nz = o.shrink ? c->nnz_active_h : (double)c->nnz;
   const double sl = o.shrink ? c->p_active_h : (double)c->p;
+  (void)P;
   c->hc.nnz_gh += nz * count;
   c->hc.slots += sl * count;
-  if (use_narrow(c, o, P)) {
-    c->hc.nnz_gh_narrow += nz * count;
-    c->hc.slots_narrow += sl * count;
-  }
   c->hc.nnz_stop += (double)c->nnz * count;
   c->hc.stop_sweeps += (double)count;
 }
@@ -777,14 +774,18 @@ int read_stats(pcdn_ctx* c) {
 double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& h,
                     const pcdn_ctx::HostCounts& hb, int cls, int64_t p) {
   // multi-kernel schedule (classes 0-3) and single-workgroup kernel (class 5)
-  const double n_nnz_gh = h.nnz_gh_narrow - hb.nnz_gh_narrow;
-  const double n_slots = h.slots_narrow - hb.slots_narrow;
-  const double n_scat = (double)(s.nnz_scat_narrow - b.nnz_scat_narrow);
+  // (the single-workgroup kernel counts its own bundles on the device, so a
+  // heavy bundle run on the multi-kernel path is credited to classes 0-3)
+  const double n_nnz_gh = (double)(s.nnz_gh_narrow - b.nnz_gh_narrow);
+  const double n_slots = (double)(s.slots_narrow - b.slots_narrow);
+  const double n_fused = (double)(s.nnz_scat_narrow - b.nnz_scat_narrow);
+  const double n_long = (double)(s.nnz_scat_narrow_split - b.nnz_scat_narrow_split);
+  const double n_scat = n_fused + n_long;
   const double n_rows = (double)(s.rows_touched_narrow - b.rows_touched_narrow);
-  const double d_nnz_gh = h.nnz_gh - hb.nnz_gh - n_nnz_gh;
-  const double d_slots = h.slots - hb.slots - n_slots;
-  const double d_fused = (double)(s.nnz_scat_fused - b.nnz_scat_fused);
-  const double d_split = (double)(s.nnz_scat_split - b.nnz_scat_split);
+  const double d_nnz_gh = std::max(0.0, h.nnz_gh - hb.nnz_gh - n_nnz_gh);
+  const double d_slots = std::max(0.0, h.slots - hb.slots - n_slots);
+  const double d_fused = std::max(0.0, (double)(s.nnz_scat_fused - b.nnz_scat_fused) - n_fused);
+  const double d_split = std::max(0.0, (double)(s.nnz_scat_split - b.nnz_scat_split) - n_long);
   const double d_rows = (double)(s.rows_touched - b.rows_touched) - n_rows;
   const double d_stop = h.nnz_stop - hb.nnz_stop;
   const double d_sweeps = h.stop_sweeps - hb.stop_sweeps;
@@ -1246,16 +1247,11 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
     rc = bundle_ls_apply(c, o, c->step_perm, 0, P, false);
     if (rc) return rc;
   }
-  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, narrow, nullptr, c->stats,
-                                 c->stream));
+  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, nullptr, c->stats, c->stream));
   double swept = 0.0;
   for (int64_t t = 0; t < P; ++t) swept += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
   c->hc.nnz_gh += swept;
   c->hc.slots += (double)P;
-  if (narrow) {
-    c->hc.nnz_gh_narrow += swept;
-    c->hc.slots_narrow += (double)P;
-  }
   if (g) HIPCHK(c, hipMemcpyAsync(g, c->g, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (h) HIPCHK(c, hipMemcpyAsync(h, c->h, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if (d) HIPCHK(c, hipMemcpyAsync(d, c->d, P * sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -52,9 +52,14 @@ struct Stats {
   unsigned long long nnz_scat_fused; // nonzeros scattered into d^T x by the sweep kernel
   unsigned long long nnz_scat_split; // nonzeros scattered by the split-column kernel
   unsigned long long rows_touched;   // rows with d^T x_i != 0, summed over bundles
-  unsigned long long nnz_scat_narrow;  // nonzeros scattered by the single-workgroup kernel
-  unsigned long long rows_touched_narrow;  // part of rows_touched from that kernel
-  unsigned long long pad[8];
+  // counted by the single-workgroup kernel for its own bundles (the others
+  // above count every bundle of any schedule)
+  unsigned long long nnz_scat_narrow;      // nonzeros it scattered, columns of <= kChunk
+  unsigned long long rows_touched_narrow;  // part of rows_touched from it
+  unsigned long long nnz_gh_narrow;        // bundle nonzeros it swept
+  unsigned long long slots_narrow;         // bundle slots it processed
+  unsigned long long nnz_scat_narrow_split;  // nonzeros it scattered, longer columns
+  unsigned long long pad[5];
 };
 
 // Result of the line search of the current inner iteration.
@@ -143,7 +148,6 @@ struct ScatterCountArgs {
   const int32_t* perm;       // slot -> feature
   const int64_t* cp;
   int64_t p;                 // slots
-  int32_t narrow;            // count for the single-workgroup kernel
   Stats* stats;
   const double* p_active;    // nullable: slots clipped to the first *p_active
 };
@@ -302,11 +306,10 @@ hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, con
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, hipStream_t s);
-// Nonzeros of the features with d != 0 (slots 0..p of perm) into stats
-// (narrow: counted for the single-workgroup kernel).
+// Nonzeros of the features with d != 0 (slots 0..p of perm) into stats:
+// columns of <= kChunk nonzeros count as fused, longer ones as split.
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, bool narrow, const double* p_active, Stats* stats,
-                                hipStream_t s);
+                                int64_t p, const double* p_active, Stats* stats, hipStream_t s);
 // Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s);

@@ -145,10 +145,10 @@ struct pcdn_ctx {
   GraphKey split_key;
 
   // counters known on the host (launch structure): sweep and stopping work
-  // (the *_narrow parts were swept by the single-workgroup kernel)
+  // of every schedule (the single-workgroup kernel's share is counted on the
+  // device, in Stats)
   struct HostCounts {
     double nnz_gh = 0, slots = 0, nnz_stop = 0, stop_sweeps = 0;
-    double nnz_gh_narrow = 0, slots_narrow = 0;
   } hc, prof_hc;
   std::vector<int64_t> h_cp;  // host copy of col_ptr
   // top_len[k]: nonzeros of the k longest columns (k <= kNarrowMaxP), an

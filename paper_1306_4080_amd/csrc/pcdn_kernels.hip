@@ -605,7 +605,7 @@ __device__ __forceinline__ void scatter_count_body(const ScatterCountArgs& a, in
     if (a.d[r] == 0.0) continue;
     const int32_t j = a.perm[r];
     const double len = (double)(a.cp[j + 1] - a.cp[j]);
-    if (len > kChunk && !a.narrow)
+    if (len > kChunk)
       split += len;
     else
       fused += len;
@@ -613,9 +613,7 @@ __device__ __forceinline__ void scatter_count_body(const ScatterCountArgs& a, in
   fused = block_sum(fused, lds4);
   split = block_sum(split, lds4);
   if (threadIdx.x == 0) {
-    if (fused > 0.0)
-      atomicAdd(a.narrow ? &a.stats->nnz_scat_narrow : &a.stats->nnz_scat_fused,
-                (unsigned long long)fused);
+    if (fused > 0.0) atomicAdd(&a.stats->nnz_scat_fused, (unsigned long long)fused);
     if (split > 0.0) atomicAdd(&a.stats->nnz_scat_split, (unsigned long long)split);
   }
 }
@@ -1009,6 +1007,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
   const SweepArgs& a = na.sw;
   const int tid = threadIdx.x;
   double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0;
+  double n_nnz = 0.0, n_slots = 0.0;      // uniform
+  double n_scat = 0.0, n_scat_long = 0.0;  // this thread's slots
   int64_t t_end = na.t_end, p_lim = na.p;
   if (na.p_active) {  // shrinking: bundles of the active features only
     const int64_t pa = (int64_t)*na.p_active;
@@ -1125,6 +1125,13 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       const double wj = L.w[s];
       const double dj = newton_dir(g, h, wj, a.ra, a.rb);
       L.d[s] = dj;
+      if (dj != 0.0) {
+        const int32_t len = L.off[s + 1] - L.off[s];
+        if (len > kChunk)
+          n_scat_long += (double)len;
+        else
+          n_scat += (double)len;
+      }
       del += g * dj + a.gamma * h * dj * dj + reg_change(wj, dj, a.ra, a.rb);
       a.g[lo + s] = g;
       a.h[lo + s] = h;
@@ -1316,6 +1323,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       al *= na.beta;
     }
     n_bundles += 1.0;
+    n_nnz += (double)nb;
+    n_slots += (double)ns;
     n_ls += q_acc >= 0 ? q_acc + 1 : na.max_ls;
     n_fail += q_acc < 0 ? 1.0 : 0.0;
     // 4. accept: w, retained quantities; clear d^T x and the row flags
@@ -1391,7 +1400,15 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     }
     __syncthreads();
   }
+  if (na.stats) {
+    n_scat = block_sum16(n_scat, L.lds16);
+    n_scat_long = block_sum16(n_scat_long, L.lds16);
+  }
   if (tid == 0 && na.stats) {
+    atomicAdd(&na.stats->nnz_gh_narrow, (unsigned long long)n_nnz);
+    atomicAdd(&na.stats->slots_narrow, (unsigned long long)n_slots);
+    atomicAdd(&na.stats->nnz_scat_narrow, (unsigned long long)n_scat);
+    atomicAdd(&na.stats->nnz_scat_narrow_split, (unsigned long long)n_scat_long);
     atomicAdd(&na.stats->bundles, (unsigned long long)n_bundles);
     atomicAdd(&na.stats->ls_steps, (unsigned long long)n_ls);
     if (n_fail > 0.0) atomicAdd(&na.stats->ls_fail, (unsigned long long)n_fail);
@@ -1890,9 +1907,8 @@ hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipSt
 }
 
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, bool narrow, const double* p_active, Stats* stats,
-                                hipStream_t s) {
-  const ScatterCountArgs a{d, perm, cp, p, narrow ? 1 : 0, stats, p_active};
+                                int64_t p, const double* p_active, Stats* stats, hipStream_t s) {
+  const ScatterCountArgs a{d, perm, cp, p, stats, p_active};
   hipLaunchKernelGGL(k_scatter_count, dim3(scatter_count_grid(p)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
