@@ -29,7 +29,8 @@ Two more objects on the same line (skipped with --no-batched):
 - "batched": 64 independent LR problems (the batched recipe: n U[500,20000],
   p U[1000,100000], density U[0.001,0.02]) solved to eps = 1e-4 one
   pcdn_solve after another and in one pcdn_solve_batch call, solves/s of
-  each (bundle sizes from the autotuner, tuned before timing);
+  each (bundle size, schedule and chunk length from the autotuner, tuned
+  before timing);
 - "path": 32 C values on the text-like matrix with warm starts,
   pcdn_solve_path against the same chain of pcdn_solve calls.
 """
@@ -146,23 +147,35 @@ def cpu_baseline(d, budget_s: float, settings) -> dict:
                       f"from w = 0 ({done_nnz} bundle nonzeros, {dt:.1f} s, single thread)"}
 
 
+def _chosen_pilot(t: dict) -> dict:
+    """The autotuner's pilot that ran with the chosen configuration."""
+    for x in t["tried"]:
+        if (x["P"], x["schedule"], x["chunk"]) == (t["P"], t["schedule"], t["chunk"]):
+            return x
+    return {"narrow": 0}
+
+
 def batched_measurement(pc, synth, scale: float) -> dict:
-    """64 independent LR problems (C = 1, eps = 1e-4), bundle sizes from the
-    autotuner (not timed): one pcdn_solve after another ("plain") against one
-    pcdn_solve_batch call; both give the same results."""
+    """64 independent LR problems (C = 1, eps = 1e-4), bundle size, schedule
+    and chunk length from the autotuner (not timed): one pcdn_solve after
+    another ("plain") against one pcdn_solve_batch call; both give the same
+    results."""
     import torch
     data = synth.c4b(scale=scale)
     solvers = [pc.Solver(device=0).load_data(d) for d in data]
     t0 = time.perf_counter()
     tunes = [s.autotune(1.0, 1e-4, "lr", seed=SEED) for s in solvers]
     t_tune = time.perf_counter() - t0
-    Ps = [t["P"] for t in tunes]
+    # the tuned bundle size, schedule and chunk length of each problem
+    cfg = [dict(P=t["P"], schedule=t["schedule"], chunk=t["chunk"]) for t in tunes]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = [s.solve(1.0, P, 1e-4, "lr", seed=SEED) for s, P in zip(solvers, Ps)]
+    plain = [s.solve(1.0, c["P"], 1e-4, "lr", seed=SEED, schedule=c["schedule"], chunk=c["chunk"])
+             for s, c in zip(solvers, cfg)]
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
-    batch = pc.solve_batch([s.job(1.0, P, 1e-4, "lr", seed=SEED) for s, P in zip(solvers, Ps)])
+    batch = pc.solve_batch([s.job(1.0, c["P"], 1e-4, "lr", seed=SEED, schedule=c["schedule"],
+                                  chunk=c["chunk"]) for s, c in zip(solvers, cfg)])
     t_batch = time.perf_counter() - t0
     same = all(a[2]["outer_iters"] == b[2]["outer_iters"] and
                abs(a[2]["objective"] - b[2]["objective"]) <= 1e-12 * abs(a[2]["objective"])
@@ -172,13 +185,18 @@ def batched_measurement(pc, synth, scale: float) -> dict:
         s.close()
     n = len(data)
     return {"workload": f"{n} independent L1-LR problems, n U[500,20000], p U[1000,100000], "
-                        f"density U[0.001,0.02] (scale {scale}), C=1, eps=1e-4, autotuned P",
+                        f"density U[0.001,0.02] (scale {scale}), C=1, eps=1e-4, "
+                        "autotuned P, schedule and chunk",
             "nnz_total": int(sum(d.nnz for d in data)),
             "plain_solves_per_s": n / t_plain, "batched_solves_per_s": n / t_batch,
             "speedup": t_plain / t_batch, "plain_s": t_plain, "batched_s": t_batch,
             "batched_nnz_per_s": nnz_swept / t_batch,
             "autotune_s": t_tune, "same_results": same,
-            "narrow_jobs": sum(t["schedule"] == 2 for t in tunes),
+            "narrow_jobs": sum(_chosen_pilot(t)["narrow"] for t in tunes),
+            "tuned": {"schedules": {str(k): sum(t["schedule"] == k for t in tunes)
+                                    for k in (0, 1, 2)},
+                      "chunks": {str(k): sum(t["chunk"] == k for t in tunes)
+                                 for k in (64, 128, 256, 512)}},
             "outer_iters_total": int(sum(b[2]["outer_iters"] for b in batch))}
 
 
@@ -222,14 +240,15 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
     pool of 16 problems, replayed by arrival time through the solve server
     (continuous batching, 64 GiB budget) and through one pcdn_load_csc +
     pcdn_solve after another in arrival order ("plain"); latency = finish
-    time - arrival time.  P per pool problem from the autotuner, chosen
+    time - arrival time.  P, schedule and chunk per pool problem from the autotuner, chosen
     before the stream starts."""
     pool = synth.c5_pool(scale=scale)
     stream = synth.c5_stream(count=n_req, pool=len(pool))
     Ps = []
     for d, loss in pool:
         s = pc.Solver(device=0).load_data(d)
-        Ps.append(s.autotune(1.0, 1e-4, loss, seed=SEED)["P"])
+        t = s.autotune(1.0, 1e-4, loss, seed=SEED)
+        Ps.append(dict(P=t["P"], schedule=t["schedule"], chunk=t["chunk"]))
         s.close()
     # served
     srv = pc.Server(device=0, budget_bytes=64 << 30)
@@ -242,7 +261,8 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
         while k < len(stream) and stream[k][0] <= now:
             t_arr, i, C = stream[k]
             d, loss = pool[i]
-            rid = srv.submit(d, C, Ps[i], 1e-4, loss, seed=SEED)
+            rid = srv.submit(d, C, Ps[i]["P"], 1e-4, loss, seed=SEED, schedule=Ps[i]["schedule"],
+                             chunk=Ps[i]["chunk"])
             out[rid] = k
             arrival[k] = t_arr
             k += 1
@@ -271,7 +291,8 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
             time.sleep(t_arr - now)
         d, loss = pool[i]
         s.load_data(d)
-        st_plain[q], _, info = s.solve(C, Ps[i], 1e-4, loss, seed=SEED)
+        st_plain[q], _, info = s.solve(C, Ps[i]["P"], 1e-4, loss, seed=SEED,
+                                       schedule=Ps[i]["schedule"], chunk=Ps[i]["chunk"])
         F_plain[q] = info["objective"]
         lat_plain.append(time.perf_counter() - t0 - t_arr)
     span_plain = time.perf_counter() - t0 - stream[0][0]
@@ -281,7 +302,8 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
     return {"workload": f"{len(stream)} requests, Poisson 50/s, pool of {len(pool)} problems "
                         f"(LR/SVM 1:1, n log-U[1e3, {2e5 * scale:.0f}], p log-U[1e3, "
                         f"{2e6 * scale:.0f}], U{{20..150}} nnz/row, Zipf(1.1) columns), "
-                        f"C log-U[0.1, 10], eps=1e-4, autotuned P per pool problem",
+                        "C log-U[0.1, 10], eps=1e-4, autotuned P, schedule and chunk per pool "
+                        "problem",
             "served": dict(_percentiles(lat_srv), solves_per_s=len(stream) / span_srv),
             "plain": dict(_percentiles(lat_plain), solves_per_s=len(stream) / span_plain),
             "converged": {"served": sum(v == 0 for v in st_srv.values()),

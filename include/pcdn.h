@@ -65,7 +65,10 @@ typedef struct {
   int32_t schedule;     /* PCDN_SCHED_*: how bundles map onto the GPU       */
   int32_t shrink;       /* 1: outer-iteration shrinking (below); 0: off     */
   int32_t penalty;      /* PCDN_PENALTY_*: the regulariser (below)          */
-  int32_t reserved;     /* set to 0                                         */
+  int32_t chunk;        /* nonzeros per wavefront work item of the WIDE
+                           schedule: a column of L nonzeros is swept by
+                           ceil(L / chunk) wavefronts (0: 128; 64, 128, 256
+                           or 512)                                          */
   double l2;            /* ridge weight b of ELASTIC and L2 (> 0); 0 for L1 */
 } pcdn_opts;
 
@@ -280,35 +283,46 @@ int pcdn_solve_path(pcdn_ctx* ctx, const double* Cs, int32_t count, int64_t P, d
 /* Bundle-size autotuning (pcdn_autotune). */
 typedef struct {
   int64_t P;                /* candidate bundle size                             */
-  int32_t schedule;         /* PCDN_SCHED_WIDE or PCDN_SCHED_NARROW it ran with  */
+  int32_t schedule;         /* pcdn_opts.schedule it ran with                    */
   int32_t outer;            /* pilot outer iterations run                        */
   double sec_per_outer;     /* measured seconds per outer iteration              */
   double rate;              /* measured decay of log ||grad^S F||_1 per iteration */
   double predicted_seconds; /* predicted time to reach eps (INFINITY: no progress) */
+  int32_t chunk;            /* pcdn_opts.chunk it ran with (resolved)            */
+  int32_t narrow;           /* 1 if it ran on the single-workgroup schedule      */
 } pcdn_tune_point;
 
 typedef struct {
   int64_t P;                /* chosen bundle size                                */
-  int32_t schedule;         /* chosen schedule                                   */
+  int32_t schedule;         /* chosen pcdn_opts.schedule                         */
   int32_t n_tried;          /* entries of tried[]                                */
   double predicted_seconds; /* prediction for the chosen P                       */
-  pcdn_tune_point tried[8];
+  int32_t chunk;            /* chosen pcdn_opts.chunk                            */
+  int32_t pad;
+  pcdn_tune_point tried[12];
 } pcdn_tune;
 
-/* Choose the bundle size P (and with it the schedule, when opts->schedule
- * is PCDN_SCHED_AUTO) for solving the loaded problem with (loss, C, eps) by
- * the pilot procedure of Sec. 5.1 ("Bundle Size Choice"): the paper starts
- * at about 5% of the features, P0 = 0.05 p, and adjusts P by measured
- * runtime.  Candidates P0 * 4^k for k = 0, -1, 1, -2, 2, -3 (clipped to
- * [1, p]) are tried in that order; each pilot is the solve itself, from the
- * start pcdn_solve would use, to the target eps (graphs captured before the
- * clock starts), and a pilot is abandoned as soon as it has run longer than
- * the fastest finished one.  The fastest finished candidate wins (if none
- * finishes within max_outer, the one with the largest decrease of the
- * stopping norm per second).  tried[] reports every pilot
- * (predicted_seconds: its measured time, INFINITY if it did not finish).
- * The context's device state afterwards is the last pilot's.  Returns
- * PCDN_OK or an error. */
+/* Choose the bundle size P, the schedule and the wavefronts per column for
+ * solving the loaded problem with (loss, C, eps), by the pilot procedure of
+ * Sec. 5.1 ("Bundle Size Choice"): the paper starts at about 5% of the
+ * features, P0 = 0.05 p, and adjusts P by measured runtime.
+ *  1. P: candidates P0 * 4^k for k = 0, -1, 1, -2, 2, -3 (clipped to [1, p])
+ *     in that order, with opts->schedule and opts->chunk;
+ *  2. schedule (only if opts->schedule is PCDN_SCHED_AUTO): at the best P,
+ *     the schedule the automatic choice did not take (WIDE after a
+ *     single-workgroup run; NARROW after a WIDE run when P <= 1024);
+ *  3. wavefronts per column (only if opts->chunk is 0, and the best pilot
+ *     so far ran WIDE bundles): chunks of 64, 256 and 512 nonzeros.
+ * Each pilot is the solve itself through the batch engine (the path
+ * pcdn_solve_batch takes), from the start pcdn_solve would use, to the
+ * target eps (graphs captured before the clock starts), abandoned as soon as
+ * it has run longer than the fastest finished one.  The fastest finished
+ * pilot wins (if none finishes within max_outer, the one with the largest
+ * decrease of the stopping norm per second); P, schedule and chunk are the
+ * values to pass to pcdn_solve (pcdn_solve_batch applies them to a job
+ * with P = 0).  tried[] reports every pilot (predicted_seconds: its measured
+ * time, INFINITY if it did not finish).  The context's device state
+ * afterwards is the last pilot's.  Returns PCDN_OK or an error. */
 int pcdn_autotune(pcdn_ctx* ctx, int loss, double C, double eps, const pcdn_opts* opts,
                   pcdn_tune* out);
 

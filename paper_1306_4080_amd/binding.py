@@ -51,7 +51,7 @@ class pcdn_opts(ctypes.Structure):
                 ("beta", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("nu", ctypes.c_double), ("w0", ctypes.c_void_p),
                 ("schedule", ctypes.c_int32), ("shrink", ctypes.c_int32),
-                ("penalty", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("penalty", ctypes.c_int32), ("chunk", ctypes.c_int32),
                 ("l2", ctypes.c_double)]
 
 
@@ -79,12 +79,14 @@ class pcdn_job(ctypes.Structure):
 class pcdn_tune_point(ctypes.Structure):
     _fields_ = [("P", ctypes.c_int64), ("schedule", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("sec_per_outer", ctypes.c_double), ("rate", ctypes.c_double),
-                ("predicted_seconds", ctypes.c_double)]
+                ("predicted_seconds", ctypes.c_double), ("chunk", ctypes.c_int32),
+                ("narrow", ctypes.c_int32)]
 
 
 class pcdn_tune(ctypes.Structure):
     _fields_ = [("P", ctypes.c_int64), ("schedule", ctypes.c_int32), ("n_tried", ctypes.c_int32),
-                ("predicted_seconds", ctypes.c_double), ("tried", pcdn_tune_point * 8)]
+                ("predicted_seconds", ctypes.c_double), ("chunk", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tried", pcdn_tune_point * 12)]
 
 
 class pcdn_request(ctypes.Structure):
@@ -177,11 +179,11 @@ PENALTIES = {"l1": 0, "elastic": 1, "l2": 2}
 
 
 def _opts(seed=0, max_outer=0, max_ls=0, sigma=0.0, beta=0.0, gamma=0.0, nu=0.0, w0=None,
-          schedule="auto", shrink=False, penalty="l1", l2=0.0):
+          schedule="auto", shrink=False, penalty="l1", l2=0.0, chunk=0):
     schedule = SCHEDULES.get(schedule, schedule)
     penalty = PENALTIES.get(penalty, penalty)
     o = pcdn_opts(seed, max_outer, max_ls, sigma, beta, gamma, nu, None, int(schedule),
-                  int(bool(shrink)), int(penalty), 0, float(l2))
+                  int(bool(shrink)), int(penalty), int(chunk), float(l2))
     keep = None
     if w0 is not None:
         keep = np.ascontiguousarray(w0, dtype=np.float64)
@@ -295,8 +297,8 @@ def pcdn_autotune(ctx, C, eps, loss, **opts) -> dict:
                                              ctypes.byref(o), ctypes.byref(t)))
     tried = [{f: getattr(t.tried[k], f) for f, _ in pcdn_tune_point._fields_}
              for k in range(t.n_tried)]
-    return {"P": t.P, "schedule": t.schedule, "predicted_seconds": t.predicted_seconds,
-            "tried": tried}
+    return {"P": t.P, "schedule": t.schedule, "chunk": t.chunk,
+            "predicted_seconds": t.predicted_seconds, "tried": tried}
 
 
 def pcdn_iterate_batch(ctxs, Ps, k_first, iters, **opts):

@@ -91,6 +91,9 @@ int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
     return fail(c, PCDN_E_ARG, "unknown schedule");
   r->shrink = o ? o->shrink : 0;
   if (r->shrink != 0 && r->shrink != 1) return fail(c, PCDN_E_ARG, "shrink must be 0 or 1");
+  r->chunk = (o && o->chunk) ? o->chunk : kChunk;
+  if (r->chunk != 64 && r->chunk != 128 && r->chunk != 256 && r->chunk != 512)
+    return fail(c, PCDN_E_ARG, "chunk must be 0, 64, 128, 256 or 512");
   r->penalty = o ? o->penalty : PCDN_PENALTY_L1;
   r->l2 = o ? o->l2 : 0.0;
   if (r->penalty < PCDN_PENALTY_L1 || r->penalty > PCDN_PENALTY_L2)
@@ -472,6 +475,7 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   na.max_ls = o.max_ls;
   na.dtx_copy = dtx_copy;
   na.loss = c->loss;
+  na.chunk = o.chunk;
   if (use_bundle_rows(c, P, p_slots)) {
     na.plid = c->plid;
     na.pR = c->pR;
@@ -510,8 +514,8 @@ int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it,
                 bool heavy_list) {
   int rc = device_permutation(c, o.seed, k, it, o.shrink ? c->act : nullptr);
   if (rc) return rc;
-  HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, c->nch, c->cstart, c->chunks, c->scan_tmp,
-                          c->stream));
+  HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, o.chunk, c->nch, c->cstart, c->chunks,
+                          c->scan_tmp, c->stream));
   if (!use_narrow(c, o, P)) return PCDN_OK;
   rc = permute_x(c, c->idx0, c->p, P);
   if (rc) return rc;
@@ -553,7 +557,7 @@ int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
 // After the bundles: scatter counters and the stopping sweep.
 int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
   HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, o.shrink ? c->scal + 5 : nullptr,
-                                 c->stats, c->stream));
+                                 o.chunk, c->stats, c->stream));
   if (o.shrink) return launch_stopping_shrink(c, o, it);
   return launch_stopping(c, o, c->w, it);
 }
@@ -625,7 +629,7 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   }
   Task t = task(kTaskScatterCount, scatter_count_grid(c->p), 0);
   t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, c->stats,
-                            o.shrink ? c->scal + 5 : nullptr};
+                            o.shrink ? c->scal + 5 : nullptr, o.chunk};
   out.push_back(t);
   t = task(kTaskSweepStop, sweep_grid(c->p), 0);
   t.u.sw = stop_args(c, o, c->w);
@@ -668,6 +672,7 @@ pcdn_ctx::GraphKey graph_key_of(const pcdn_ctx* c, const Opts& o, int64_t P) {
   key.shrink = o.shrink;
   key.penalty = o.penalty;
   key.l2 = o.l2;
+  key.chunk = o.chunk;
   return key;
 }
 
@@ -988,7 +993,7 @@ namespace host {
 // Device bytes pcdn_load_csc allocates for (n, p, nnz), each buffer rounded
 // up to 4 KiB, plus the context's own small records.
 int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
-  const int64_t max_chunks = p + (nnz + kChunk - 1) / kChunk + 1;
+  const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   const int64_t hist_m = radix_hist_ints(p);
   const int64_t part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
   const int64_t sizes[] = {
@@ -1021,7 +1026,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   if (!col_ptr || !y || (nnz > 0 && (!row_idx || !val)))
     return fail(c, PCDN_E_ARG, "null array");
   if (ptr_kind != 0 && ptr_kind != 1) return fail(c, PCDN_E_ARG, "ptr_kind must be 0 or 1");
-  const int64_t max_chunks = p + (nnz + kChunk - 1) / kChunk + 1;
+  const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   if (max_chunks >= ((int64_t)1 << 31) - 1) return fail(c, PCDN_E_ARG, "matrix too large");
   HIPCHK(c, hipSetDevice(c->device));
 
@@ -1150,8 +1155,8 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   HIPCHK(c, hipMemcpyAsync(c->y, y, n, kind, c->stream));
   HIPCHK(c, hipMemsetAsync(c->dtx, 0, n * sizeof(double), c->stream));
   HIPCHK(c, hipMemsetAsync(c->rowflag, 0, n * sizeof(unsigned), c->stream));
-  HIPCHK(c, launch_chunks(nullptr, c->cp, p, c->nch, c->id_cstart, c->id_chunks, c->scan_tmp,
-                          c->stream));
+  HIPCHK(c, launch_chunks(nullptr, c->cp, p, kChunk, c->nch, c->id_cstart, c->id_chunks,
+                          c->scan_tmp, c->stream));
   int32_t total = 0;
   HIPCHK(c, hipMemcpyAsync(&total, c->id_cstart + p, sizeof(int32_t), hipMemcpyDeviceToHost,
                            c->stream));
@@ -1231,8 +1236,8 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipMemcpyAsync(c->step_perm, bundle, P * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream));
-  HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, c->nch, c->cstart, c->chunks, c->scan_tmp,
-                          c->stream));
+  HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, o.chunk, c->nch, c->cstart, c->chunks,
+                          c->scan_tmp, c->stream));
   // run the bundle; keep d^T x before it is cleared
   const bool narrow = use_narrow(c, o, P);
   if (narrow) {
@@ -1247,7 +1252,8 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
     rc = bundle_ls_apply(c, o, c->step_perm, 0, P, false);
     if (rc) return rc;
   }
-  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, nullptr, c->stats, c->stream));
+  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, nullptr, o.chunk, c->stats,
+                                 c->stream));
   double swept = 0.0;
   for (int64_t t = 0; t < P; ++t) swept += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
   c->hc.nnz_gh += swept;

@@ -428,6 +428,8 @@ extern "C" int pcdn_solve_batch(pcdn_job* jobs, int32_t count) {
       return rc;
     }
     r.P = t.P;
+    r.o.schedule = t.schedule;
+    r.o.chunk = t.chunk;
     jobs[i].P = t.P;
   }
   Engine eng;
@@ -760,79 +762,123 @@ extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const 
   if (rc) return rc;
   std::memset(out, 0, sizeof(*out));
   const int64_t p = c->p;
+  const int max_tried = (int)(sizeof(out->tried) / sizeof(out->tried[0]));
+  const bool tune_schedule = o.schedule == PCDN_SCHED_AUTO;
+  const bool tune_chunk = !(opts && opts->chunk);
   // the paper's pilot start, about 5% of the features, then its neighbours
   // on a factor-4 ladder, nearest first
   const int64_t P0 = std::max<int64_t>(1, std::llround(0.05 * (double)p));
+  using clock = std::chrono::steady_clock;
+  double best = INFINITY;          // fastest finished pilot
+  double best_progress = -1.0;     // fallback when none finishes: log-decrease per second
+  int best_narrow = use_narrow(c, o, P0) ? 1 : 0;
+  out->P = P0;
+  out->schedule = o.schedule;
+  out->chunk = o.chunk;
+  out->predicted_seconds = INFINITY;
+  bool done = false;               // a pilot met the rule at its start
+  // One pilot: the solve through the batch engine (one job), timed after its
+  // set-up, abandoned once slower than the fastest finished pilot.
+  auto pilot = [&](int64_t P, int schedule, int chunk) -> int {
+    if (done || out->n_tried >= max_tried) return PCDN_OK;
+    EngineJob j;
+    SolveRun& r = j.run;
+    r.o = o;
+    r.o.schedule = schedule;
+    r.o.chunk = chunk;
+    r.c = c;
+    r.C = C;
+    r.P = P;
+    r.eps = eps;
+    r.loss = loss;
+    Engine eng;
+    int prc = eng.init(c->device);
+    if (prc) return fail(c, prc, eng.err);
+    prc = eng.add(&j);
+    if (prc) return prc;
+    pcdn_tune_point& tp = out->tried[out->n_tried++];
+    tp.P = P;
+    tp.schedule = schedule;
+    tp.chunk = chunk;
+    tp.narrow = j.narrow ? 1 : 0;
+    if (!j.active && r.converged) {  // w = 0 (or the warm start) already meets the rule
+      tp.predicted_seconds = 0.0;
+      out->P = P;
+      out->schedule = schedule;
+      out->chunk = chunk;
+      out->predicted_seconds = 0.0;
+      done = true;
+      return PCDN_OK;
+    }
+    bool pruned = false;
+    const auto t0 = clock::now();
+    double elapsed = 0.0;
+    std::vector<EngineJob*> fin;
+    while (eng.size() > 0) {
+      pcdn_ctx* ec = nullptr;
+      prc = eng.round(fin, &ec);
+      if (prc) return ec ? prc : fail(c, prc, eng.err);
+      elapsed = std::chrono::duration<double>(clock::now() - t0).count();
+      if (eng.size() > 0 && elapsed > best) {  // already slower than the best finished pilot
+        pruned = true;
+        break;
+      }
+    }
+    tp.outer = (int32_t)r.outer;
+    tp.sec_per_outer = r.outer > 0 ? elapsed / r.outer : 0.0;
+    tp.rate = (r.outer > 0 && r.G > 0.0) ? std::log(r.G0 / r.G) / r.outer : 0.0;
+    tp.predicted_seconds = r.converged ? elapsed : INFINITY;
+    if (r.converged && elapsed < best) {
+      best = elapsed;
+      best_narrow = tp.narrow;
+      out->P = P;
+      out->schedule = schedule;
+      out->chunk = chunk;
+      out->predicted_seconds = elapsed;
+    } else if (!std::isfinite(best) && !pruned) {
+      // nothing has finished yet: keep the pilot that went furthest per second
+      const double progress = elapsed > 0.0 ? std::log(r.G0 / std::max(r.G, 1e-300)) / elapsed : 0.0;
+      if (progress > best_progress) {
+        best_progress = progress;
+        best_narrow = tp.narrow;
+        out->P = P;
+        out->schedule = schedule;
+        out->chunk = chunk;
+      }
+    }
+    return PCDN_OK;
+  };
+  // 1. bundle size
   std::vector<int64_t> cands;
   for (const int k : {0, -1, 1, -2, 2, -3}) {
     const double v = (double)P0 * std::pow(4.0, k);
     const int64_t P = std::min<int64_t>(p, std::max<int64_t>(1, std::llround(v)));
     if (std::find(cands.begin(), cands.end(), P) == cands.end()) cands.push_back(P);
   }
-  using clock = std::chrono::steady_clock;
-  double best = INFINITY;          // fastest finished pilot
-  double best_progress = -1.0;     // fallback when none finishes: log-decrease per second
-  out->P = P0;
-  out->schedule = use_narrow(c, o, P0) ? PCDN_SCHED_NARROW : PCDN_SCHED_WIDE;
-  out->predicted_seconds = INFINITY;
   for (const int64_t P : cands) {
-    SolveRun r;
-    r.o = o;
-    r.c = c;
-    r.C = C;
-    r.P = P;
-    r.eps = eps;
-    r.loss = loss;
-    rc = solve_begin(r);
+    rc = pilot(P, o.schedule, o.chunk);
     if (rc) return rc;
-    pcdn_tune_point& tp = out->tried[out->n_tried++];
-    tp.P = P;
-    tp.schedule = use_narrow(c, o, P) ? PCDN_SCHED_NARROW : PCDN_SCHED_WIDE;
-    if (r.converged) {  // w = 0 (or the warm start) already meets the rule
-      tp.predicted_seconds = 0.0;
-      out->P = P;
-      out->schedule = tp.schedule;
-      out->predicted_seconds = 0.0;
-      return PCDN_OK;
-    }
-    if (c->use_graphs && c->prof.mask == 0) {  // capture outside the timed pilot
-      rc = ensure_graph(c, r.o, P);
+  }
+  // 2. the schedule the automatic choice did not take, at the best P
+  const int64_t Pb = out->P;
+  if (tune_schedule && !done) {
+    Opts on = o;
+    on.schedule = PCDN_SCHED_NARROW;
+    if (best_narrow)
+      rc = pilot(Pb, PCDN_SCHED_WIDE, o.chunk);
+    else if (use_narrow(c, on, Pb))
+      rc = pilot(Pb, PCDN_SCHED_NARROW, o.chunk);
+    if (rc) return rc;
+  }
+  // 3. wavefronts per column, when multi-kernel bundles ran (WIDE, or the
+  //    heavy bundles of the automatic single-workgroup schedule)
+  Opts ob = o;
+  ob.schedule = out->schedule;
+  if (tune_chunk && !done && (!best_narrow || use_hybrid(c, ob, Pb))) {
+    const int sched = out->schedule;
+    for (const int ch : {64, 256, 512}) {
+      rc = pilot(Pb, sched, ch);
       if (rc) return rc;
-    }
-    bool pruned = false;
-    const auto t0 = clock::now();
-    double elapsed = 0.0;
-    while (!r.converged && r.outer < o.max_outer) {
-      rc = run_outer(c, r.o, P, r.outer, 1);
-      if (rc) return rc;
-      double G = 0.0;
-      rc = read_outer(c, &G);
-      if (rc) return rc;
-      rc = solve_note_outer(r, G);
-      if (rc) return rc;
-      elapsed = std::chrono::duration<double>(clock::now() - t0).count();
-      if (!r.converged && elapsed > best) {  // already slower than the best finished pilot
-        pruned = true;
-        break;
-      }
-    }
-    tp.outer = r.outer;
-    tp.sec_per_outer = r.outer > 0 ? elapsed / r.outer : 0.0;
-    tp.rate = (r.outer > 0 && r.G > 0.0) ? std::log(r.G0 / r.G) / r.outer : 0.0;
-    tp.predicted_seconds = r.converged ? elapsed : INFINITY;
-    if (r.converged && elapsed < best) {
-      best = elapsed;
-      out->P = P;
-      out->schedule = tp.schedule;
-      out->predicted_seconds = elapsed;
-    } else if (!std::isfinite(best) && !pruned) {
-      // nothing has finished yet: keep the candidate that went furthest per second
-      const double progress = elapsed > 0.0 ? std::log(r.G0 / std::max(r.G, 1e-300)) / elapsed : 0.0;
-      if (progress > best_progress) {
-        best_progress = progress;
-        out->P = P;
-        out->schedule = tp.schedule;
-      }
     }
   }
   return PCDN_OK;

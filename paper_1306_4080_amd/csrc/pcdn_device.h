@@ -24,7 +24,8 @@ namespace pcdn {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kChunk = 128;    // nonzeros per wavefront work item
+constexpr int kChunk = 128;    // nonzeros per wavefront work item (default)
+constexpr int kChunkMin = 64;  // smallest selectable (descriptor storage is sized for it)
 constexpr int kQMax = 32;      // line-search candidates evaluated per pass
 constexpr int kQGroup = 4;     // candidates per line-search thread (grid y covers the rest)
 constexpr int kLsGrid = 256;   // blocks of the line-search kernel (at most)
@@ -54,7 +55,7 @@ struct Stats {
   unsigned long long rows_touched;   // rows with d^T x_i != 0, summed over bundles
   // counted by the single-workgroup kernel for its own bundles (the others
   // above count every bundle of any schedule)
-  unsigned long long nnz_scat_narrow;      // nonzeros it scattered, columns of <= kChunk
+  unsigned long long nnz_scat_narrow;      // nonzeros it scattered, columns of <= chunk
   unsigned long long rows_touched_narrow;  // part of rows_touched from it
   unsigned long long nnz_gh_narrow;        // bundle nonzeros it swept
   unsigned long long slots_narrow;         // bundle slots it processed
@@ -150,6 +151,7 @@ struct ScatterCountArgs {
   int64_t p;                 // slots
   Stats* stats;
   const double* p_active;    // nullable: slots clipped to the first *p_active
+  int32_t chunk;             // longer columns count as split
 };
 
 // Stopping reduction with shrinking: sums ||grad^S F||_1 = sum sg, the
@@ -237,6 +239,7 @@ struct NarrowArgs {
   // number of distinct rows of bundle t or -1 (more than kNarrowLidCap)
   const uint16_t* plid;
   const int32_t* pR;
+  int32_t chunk;       // the multi-kernel chunk length (for the scatter counters)
 };
 
 // Largest number of distinct rows of a bundle whose d^T x the
@@ -279,9 +282,12 @@ int64_t scan_tmp_ints(int64_t m);
 int64_t radix_hist_ints(int64_t p);
 // Exclusive scan of in[0..m) into out[0..m], out[m] = total (int32).
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s);
-// Chunk descriptors for a slot order (perm null: identity).
-hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* nch,
-                         int32_t* cstart, Chunk* chunks, int32_t* tmp, hipStream_t s);
+// Chunk descriptors for a slot order (perm null: identity): every column is
+// cut into ceil(len / chunk) >= 1 pieces of at most `chunk` nonzeros
+// (kChunkMin <= chunk).
+hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
+                         int32_t* nch, int32_t* cstart, Chunk* chunks, int32_t* tmp,
+                         hipStream_t s);
 int sweep_grid(int64_t slots);
 hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
 hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
@@ -307,9 +313,10 @@ hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, con
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, hipStream_t s);
 // Nonzeros of the features with d != 0 (slots 0..p of perm) into stats:
-// columns of <= kChunk nonzeros count as fused, longer ones as split.
+// columns of <= chunk nonzeros count as fused, longer ones as split.
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, const double* p_active, Stats* stats, hipStream_t s);
+                                int64_t p, const double* p_active, int32_t chunk, Stats* stats,
+                                hipStream_t s);
 // Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s);

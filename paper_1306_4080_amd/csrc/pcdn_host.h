@@ -132,10 +132,11 @@ struct pcdn_ctx {
     int shrink = -1;
     int penalty = -1;
     double l2 = 0;
+    int chunk = 0;
     bool operator==(const GraphKey& o) const {
       return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
              gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule &&
-             shrink == o.shrink && penalty == o.penalty && l2 == o.l2;
+             shrink == o.shrink && penalty == o.penalty && l2 == o.l2 && chunk == o.chunk;
     }
   } graph_key;
   // the same outer iteration in two parts around the bundles, for drivers
@@ -192,6 +193,7 @@ struct Opts {
   int shrink;
   int penalty;  // PCDN_PENALTY_*
   double l2;
+  int chunk;    // nonzeros per wavefront work item of the multi-kernel schedule
   // the regulariser sum_j ra |w_j| + (rb/2) w_j^2
   double ra() const { return penalty == PCDN_PENALTY_L2 ? 0.0 : 1.0; }
   double rb() const { return penalty == PCDN_PENALTY_L1 ? 0.0 : l2; }

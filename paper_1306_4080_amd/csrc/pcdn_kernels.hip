@@ -411,18 +411,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 // chunk bookkeeping: nch = chunks per slot, cstart = exclusive scan, then one
 // descriptor per chunk
 // ---------------------------------------------------------------------------
-__global__ void k_chunk_count(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* nch) {
+__global__ void k_chunk_count(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
+                              int32_t* nch) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r < p) {
     const int32_t j = perm ? perm[r] : (int32_t)r;
     const int64_t len = cp[j + 1] - cp[j];
-    const int64_t c = (len + kChunk - 1) / kChunk;
+    const int64_t c = (len + chunk - 1) / chunk;
     nch[r] = (int32_t)(c > 0 ? c : 1);
   }
 }
 
 __global__ void k_chunk_fill(const int32_t* perm, const int64_t* cp, const int32_t* cstart,
-                             int64_t p, Chunk* chunks) {
+                             int64_t p, int32_t chunk, Chunk* chunks) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r < p) {
     const int32_t j = perm ? perm[r] : (int32_t)r;
@@ -430,9 +431,9 @@ __global__ void k_chunk_fill(const int32_t* perm, const int64_t* cp, const int32
     const int32_t c0 = cstart[r], nch = cstart[r + 1] - c0;
     for (int32_t q = 0; q < nch; ++q) {
       Chunk ch;
-      ch.klo = k0 + (int64_t)q * kChunk;
-      const int64_t rem = len - (int64_t)q * kChunk;
-      ch.len = (int32_t)(rem < kChunk ? (rem > 0 ? rem : 0) : kChunk);
+      ch.klo = k0 + (int64_t)q * chunk;
+      const int64_t rem = len - (int64_t)q * chunk;
+      ch.len = (int32_t)(rem < chunk ? (rem > 0 ? rem : 0) : chunk);
       ch.slot = (int32_t)r;
       ch.c0 = c0;
       ch.nch = nch;
@@ -605,7 +606,7 @@ __device__ __forceinline__ void scatter_count_body(const ScatterCountArgs& a, in
     if (a.d[r] == 0.0) continue;
     const int32_t j = a.perm[r];
     const double len = (double)(a.cp[j + 1] - a.cp[j]);
-    if (len > kChunk)
+    if (len > a.chunk)
       split += len;
     else
       fused += len;
@@ -1127,7 +1128,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       L.d[s] = dj;
       if (dj != 0.0) {
         const int32_t len = L.off[s + 1] - L.off[s];
-        if (len > kChunk)
+        if (len > na.chunk)
           n_scat_long += (double)len;
         else
           n_scat += (double)len;
@@ -1731,14 +1732,16 @@ hipError_t launch_radix_sort(uint32_t* keys0, int32_t* idx0, uint32_t* keys1, in
   return hipGetLastError();
 }
 
-hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* nch,
-                         int32_t* cstart, Chunk* chunks, int32_t* tmp, hipStream_t s) {
+hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
+                         int32_t* nch, int32_t* cstart, Chunk* chunks, int32_t* tmp,
+                         hipStream_t s) {
+  if (chunk < kChunkMin) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
-                     cp, p, nch);
+                     cp, p, chunk, nch);
   hipError_t e = launch_scan(nch, cstart, p, tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
-                     cp, cstart, p, chunks);
+                     cp, cstart, p, chunk, chunks);
   return hipGetLastError();
 }
 
@@ -1907,8 +1910,9 @@ hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipSt
 }
 
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, const double* p_active, Stats* stats, hipStream_t s) {
-  const ScatterCountArgs a{d, perm, cp, p, stats, p_active};
+                                int64_t p, const double* p_active, int32_t chunk, Stats* stats,
+                                hipStream_t s) {
+  const ScatterCountArgs a{d, perm, cp, p, stats, p_active, chunk};
   hipLaunchKernelGGL(k_scatter_count, dim3(scatter_count_grid(p)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

@@ -199,8 +199,10 @@ def test_path_svm_wide(pc):
 
 def test_autotune_ladder_and_choice(pc):
     """The candidates are the paper's pilot start (5% of the features) and
-    its factor-4 neighbours, nearest first; the chosen P is the fastest
-    finished pilot; solving with it matches the oracle at that P."""
+    its factor-4 neighbours, nearest first; then, at the best of those, the
+    schedule the automatic choice did not take, and chunk lengths when
+    multi-kernel bundles won.  The choice is the fastest finished pilot;
+    solving with it matches the oracle at that P."""
     d = synth.c1()
     s = pc.Solver(device=0).load_data(d)
     t = s.autotune(1.0, 1e-4, "lr", seed=1)
@@ -210,13 +212,25 @@ def test_autotune_ladder_and_choice(pc):
         P = min(d.p, max(1, int(np.floor(P0 * 4.0 ** k + 0.5))))
         if P not in ladder:
             ladder.append(P)
-    assert [x["P"] for x in t["tried"]] == ladder
-    done = [x for x in t["tried"] if np.isfinite(x["predicted_seconds"])]
-    assert done and t["P"] in ladder
-    assert t["predicted_seconds"] == min(x["predicted_seconds"] for x in done)
-    assert all(x["outer"] > 0 for x in t["tried"])
-    print("tuned:", t, flush=True)
-    g = s.solve(1.0, t["P"], 1e-4, "lr", seed=1)
+    tried = t["tried"]
+    print("tuned:", {k: t[k] for k in ("P", "schedule", "chunk", "predicted_seconds")}, flush=True)
+    for x in tried:
+        print("  ", x, flush=True)
+    assert [x["P"] for x in tried[:len(ladder)]] == ladder
+    assert all(x["schedule"] == 0 and x["chunk"] == 128 for x in tried[:len(ladder)])
+    first = [x for x in tried[:len(ladder)] if np.isfinite(x["predicted_seconds"])]
+    assert first
+    Pb = min(first, key=lambda x: x["predicted_seconds"])["P"]
+    rest = tried[len(ladder):]
+    assert rest and all(x["P"] == Pb for x in rest)
+    assert rest[0]["schedule"] in (1, 2) and rest[0]["narrow"] == (rest[0]["schedule"] == 2)
+    assert {x["chunk"] for x in rest[1:]} <= {64, 256, 512}
+    done = [x for x in tried if np.isfinite(x["predicted_seconds"])]
+    best = min(done, key=lambda x: x["predicted_seconds"])
+    assert t["predicted_seconds"] == best["predicted_seconds"]
+    assert (t["P"], t["schedule"], t["chunk"]) == (best["P"], best["schedule"], best["chunk"])
+    assert all(x["outer"] > 0 for x in tried)
+    g = s.solve(1.0, t["P"], 1e-4, "lr", seed=1, schedule=t["schedule"], chunk=t["chunk"])
     w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss="lr", C=1.0),
                               P=t["P"], eps=1e-4, seed=1)
     _assert_oracle(g, (w_o, io), True)

@@ -396,6 +396,29 @@ def test_regulariser_argument_errors(pc):
     s.close()
 
 
+@pytest.mark.parametrize("chunk", [64, 256, 512])
+def test_chunk_lengths_same_trajectory(pc, chunk):
+    """Nonzeros per wavefront work item (pcdn_opts.chunk) change only the work
+    split of the multi-kernel schedule: C2's long columns at P = 1,024 give
+    the oracle's trajectory for every chunk length."""
+    d = _c2_cached()
+    prob = oracle.Problem.from_data(d)
+    w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=0.5), P=1024, eps=1e-4, seed=1)
+    s = _solver(pc, d)
+    g = s.solve(0.5, 1024, 1e-4, "lr", seed=1, schedule="wide", chunk=chunk)
+    s.close()
+    _assert_solve_parity(g, (w_o, io))
+
+
+def test_chunk_argument_errors(pc):
+    from paper_1306_4080_amd import PcdnError
+    s = _solver(pc, synth.c1())
+    for bad in (1, 32, 100, 1024, -64):
+        with pytest.raises(PcdnError, match="E_ARG"):
+            s.solve(1.0, 32, 1e-4, "lr", chunk=bad)
+    s.close()
+
+
 def test_warm_start_and_max_outer(pc):
     d = synth.c1()
     prob = oracle.Problem.from_data(d)
