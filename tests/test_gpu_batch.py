@@ -361,26 +361,28 @@ def test_batch_heavy_bundles_on_multi_kernel_path(pc):
     bundles of at least 4,096 nonzeros (those holding Zipf-head columns) run
     on the multi-kernel path between single-workgroup segments.  Each job
     equals the plain single-workgroup solve alone and the oracle's, with and
-    without shrinking; pcdn_iterate_batch on the same jobs ends where
+    without shrinking, and for an elastic-net L2-SVM job; pcdn_iterate_batch on the same jobs ends where
     pcdn_iterate does (the plain runs forced onto the single-workgroup
     schedule; pcdn_solve and pcdn_iterate take the engine's path under the
     automatic one)."""
     d = synth.c2()
     prob = oracle.Problem.from_data(d)
-    jobs = [(0.5, 64, {}), (4.0, 64, {}), (0.5, 64, {"shrink": True})]
+    jobs = [(0.5, 64, {}, "lr", 1e-4), (4.0, 64, {}, "lr", 1e-4),
+            (0.5, 64, {"shrink": True}, "lr", 1e-4),
+            (0.5, 64, {"penalty": "elastic", "l2": 0.5}, "svm", 1e-3)]
     solvers = [pc.Solver(device=0).load_data(d) for _ in jobs]
-    specs = [s.job(C, P, 1e-4, "lr", seed=1, **o) for s, (C, P, o) in zip(solvers, jobs)]
+    specs = [s.job(C, P, eps, loss, seed=1, **o) for s, (C, P, o, loss, eps) in zip(solvers, jobs)]
     batched = pc.solve_batch(specs)
-    for s, (C, P, o), b in zip(solvers, jobs, batched):
-        print(f"C={C} P={P} {o}: outer={b[2]['outer_iters']} F={b[2]['objective']:.15g}",
+    for s, (C, P, o, loss, eps), b in zip(solvers, jobs, batched):
+        print(f"{loss} C={C} P={P} {o}: outer={b[2]['outer_iters']} F={b[2]['objective']:.15g}",
               flush=True)
-        _assert_same_run(b, s.solve(C, P, 1e-4, "lr", seed=1, schedule="narrow", **o))
-        _assert_same_run(b, s.solve(C, P, 1e-4, "lr", seed=1, **o))
-        w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=C, **o), P=P, eps=1e-4, seed=1)
+        _assert_same_run(b, s.solve(C, P, eps, loss, seed=1, schedule="narrow", **o))
+        _assert_same_run(b, s.solve(C, P, eps, loss, seed=1, **o))
+        w_o, io, _ = oracle.solve(prob, oracle.Params(loss=loss, C=C, **o), P=P, eps=eps, seed=1)
         _assert_oracle(b, (w_o, io), True)
     # a few outer iterations continued together vs one context at a time
     other = [pc.Solver(device=0).load_data(d) for _ in jobs[:2]]
-    for s, t, (C, P, o) in zip(solvers[:2], other, jobs[:2]):
+    for s, t, (C, P, o, loss, eps) in zip(solvers[:2], other, jobs[:2]):
         s.reset("lr", C)
         t.reset("lr", C)
     G = pc.iterate_batch(solvers[:2], [64, 64], 0, 4, seed=2)
