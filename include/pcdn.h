@@ -106,7 +106,8 @@ enum { PCDN_PENALTY_L1 = 0, PCDN_PENALTY_ELASTIC = 1, PCDN_PENALTY_L2 = 2 };
  *          bundles, where kernel-boundary latency would dominate);
  *  AUTO:   NARROW when the average bundle holds few nonzeros, else WIDE;
  *          under NARROW, when a bundle can hold 4,096 nonzeros or more
- *          (long columns), the solve runs in the rounds of the batch engine
+ *          (long columns), pcdn_solve, pcdn_iterate and each solve of
+ *          pcdn_solve_path run in the rounds of the batch engine
  *          (pcdn_solve_batch), which reads each partition's list of such
  *          bundles and runs them as WIDE between single-workgroup segments
  *          (with kernel profiling on, direct launches that do the same). */

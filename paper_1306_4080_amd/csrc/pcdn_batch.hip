@@ -734,16 +734,34 @@ extern "C" int pcdn_solve_path(pcdn_ctx* c, const double* Cs, int32_t count, int
     r.loss = loss;
     r.w0_device = k > 0;  // the previous solution is still on the device
     if (k > 0) r.o.w0 = nullptr;
-    rc = solve_begin(r);
-    if (rc) return rc;
-    while (!r.converged && r.outer < r.o.max_outer) {
-      rc = run_outer(c, r.o, P, r.outer, 1);
+    if (use_hybrid(c, r.o, P) && !c->prof.mask) {
+      // heavy bundles on the multi-kernel path: the engine's rounds, one job
+      EngineJob j;
+      j.run = r;
+      Engine eng;
+      rc = eng.init(c->device);
+      if (rc) return fail(c, rc, eng.err);
+      rc = eng.add(&j);
       if (rc) return rc;
-      double G = 0.0;
-      rc = read_outer(c, &G);
+      std::vector<EngineJob*> fin;
+      while (eng.size() > 0) {
+        pcdn_ctx* ec = nullptr;
+        rc = eng.round(fin, &ec);
+        if (rc) return ec ? rc : fail(c, rc, eng.err);
+      }
+      r = j.run;
+    } else {
+      rc = solve_begin(r);
       if (rc) return rc;
-      rc = solve_note_outer(r, G);
-      if (rc) return rc;
+      while (!r.converged && r.outer < r.o.max_outer) {
+        rc = run_outer(c, r.o, P, r.outer, 1);
+        if (rc) return rc;
+        double G = 0.0;
+        rc = read_outer(c, &G);
+        if (rc) return rc;
+        rc = solve_note_outer(r, G);
+        if (rc) return rc;
+      }
     }
     rc = solve_end(r, W_out ? W_out + (size_t)k * (size_t)c->p : nullptr,
                    infos ? infos + k : nullptr);

@@ -187,6 +187,27 @@ def test_path_matches_oracle_chain(pc):
     s.close()
 
 
+def test_path_heavy_bundles(pc):
+    """A path on the text-like matrix at P = 64 (automatic schedule: the
+    engine's heavy-bundle path, one job per C): the oracle's warm-started
+    chain, and the chain forced onto the plain single-workgroup schedule."""
+    d = synth.c2()
+    Cs = [0.25, 0.5, 1.0]
+    s = pc.Solver(device=0).load_data(d)
+    rc, W, infos = s.solve_path(Cs, 64, 1e-4, "lr", seed=2)
+    rn, Wn, infn = s.solve_path(Cs, 64, 1e-4, "lr", seed=2, schedule="narrow")
+    prob = oracle.Problem.from_data(d)
+    w_prev = None
+    for k, C in enumerate(Cs):
+        w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=C), P=64, eps=1e-4, seed=2,
+                                  w0=w_prev)
+        print(f"C={C}: outer {infos[k]['outer_iters']}/{io['outer_iters']}", flush=True)
+        _assert_oracle((rc, W[k], infos[k]), (w_o, io), True)
+        _assert_same_run((rc, W[k], infos[k]), (rn, Wn[k], infn[k]))
+        w_prev = w_o
+    s.close()
+
+
 def test_path_svm_wide(pc):
     d = synth.sparse_random(21, 1500, 4000, 0.003, binary=True)
     Cs = [0.05, 0.2, 0.8]
