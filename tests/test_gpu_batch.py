@@ -187,6 +187,20 @@ def test_path_matches_oracle_chain(pc):
     s.close()
 
 
+def test_heavy_bundles_beyond_the_list_cap(pc):
+    """Every bundle heavy (1,000 bundles of ~6,000 nonzeros, more than the
+    256 the list holds, each with more distinct rows than the LDS holds):
+    the first 256 run on the multi-kernel path, the rest in the single
+    workgroup's global-memory path; the trajectory is the oracle's."""
+    d = synth.bernoulli_csc(91, 20000, 64000, 0.0047)
+    s = pc.Solver(device=0).load_data(d)
+    g = s.solve(1.0, 64, 1e-3, "lr", seed=5)
+    s.close()
+    w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss="lr", C=1.0),
+                              P=64, eps=1e-3, seed=5)
+    _assert_oracle(g, (w_o, io), True)
+
+
 def test_path_heavy_bundles(pc):
     """A path on the text-like matrix at P = 64 (automatic schedule: the
     engine's heavy-bundle path, one job per C): the oracle's warm-started
