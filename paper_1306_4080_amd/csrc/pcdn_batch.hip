@@ -206,25 +206,12 @@ class Engine {
       }
       *err_ctx = nullptr;
     }
-    // multi-kernel jobs: every bundle and stopping sweep in lock-step launches
-    if (!plan_jobs_.empty()) {
-      const char* base = (const char*)exec_.dev;
-      for (size_t st = 0; st < plan_count_.size(); ++st) {
-        const hipError_t e = launch_exec((const Task*)(base + plan_task_byte_[st]),
-                                         (const int32_t*)(base + plan_first_byte_[st]),
-                                         plan_count_[st], plan_blocks_[st], wide_stream_);
-        if (e != hipSuccess) return dev_fail("executor launch", e);
-      }
-      hipError_t e = launch_gather((const double* const*)(base + plan_src_byte_),
-                                   (double*)gather_.dev, 3 * (int)plan_jobs_.size(), wide_stream_);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(gather_.host, gather_.dev, 3 * sizeof(double) * plan_jobs_.size(),
-                           hipMemcpyDeviceToHost, wide_stream_);
-      if (e != hipSuccess) return dev_fail("gather", e);
-    }
     // single-workgroup jobs with heavy bundles, each on its own stream: the
     // segments between heavy bundles in one workgroup, each heavy bundle on
-    // the multi-kernel path, in partition order
+    // the multi-kernel path, in partition order.  They are enqueued before
+    // the multi-kernel jobs' executor launches: their chains of dependent
+    // launches are the round's longest, so they must not start behind the
+    // host time of the executor's enqueue.
     if (any_hybrid) {
       std::vector<EngineJob*> hj;
       std::vector<int64_t> next;  // first bundle not yet enqueued, per job
@@ -269,6 +256,22 @@ class Engine {
                                  c->stream));
       }
       *err_ctx = nullptr;
+    }
+    // multi-kernel jobs: every bundle and stopping sweep in lock-step launches
+    if (!plan_jobs_.empty()) {
+      const char* base = (const char*)exec_.dev;
+      for (size_t st = 0; st < plan_count_.size(); ++st) {
+        const hipError_t e = launch_exec((const Task*)(base + plan_task_byte_[st]),
+                                         (const int32_t*)(base + plan_first_byte_[st]),
+                                         plan_count_[st], plan_blocks_[st], wide_stream_);
+        if (e != hipSuccess) return dev_fail("executor launch", e);
+      }
+      hipError_t e = launch_gather((const double* const*)(base + plan_src_byte_),
+                                   (double*)gather_.dev, 3 * (int)plan_jobs_.size(), wide_stream_);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(gather_.host, gather_.dev, 3 * sizeof(double) * plan_jobs_.size(),
+                           hipMemcpyDeviceToHost, wide_stream_);
+      if (e != hipSuccess) return dev_fail("gather", e);
     }
     // the staging tables and every pinned result are reused next round
     hipError_t e = hipStreamSynchronize(narrow_stream_[0]);
