@@ -602,6 +602,10 @@ int enqueue_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* i
 int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   if (use_narrow(c, o, P)) return fail(c, PCDN_E_ARG, "outer_tasks: single-workgroup schedule");
   out.clear();
+  // the partition (enqueue_pre of the multi-kernel schedule)
+  partition_tasks(c->loss, c->iter, o.seed, c->p, o.shrink ? c->act : nullptr, c->keys0, c->idx0,
+                  c->keys1, c->idx1, c->hist, c->scan_tmp, c->cp, o.chunk, c->nch, c->cstart,
+                  c->chunks, out);
   auto task = [&](int kind, int nblk, int gx) {
     Task t;
     std::memset(&t, 0, sizeof(t));

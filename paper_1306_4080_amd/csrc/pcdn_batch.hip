@@ -29,8 +29,9 @@ struct EngineJob {
   SolveRun run;
   bool narrow = false;
   bool hybrid = false;           // single-workgroup segments between heavy bundles, own stream
-  std::vector<Task> tasks;       // multi-kernel jobs: the outer iteration after the partition
+  std::vector<Task> tasks;       // multi-kernel jobs: the outer iteration, partition included
   hipEvent_t pre_done = nullptr;
+  bool fresh = true;             // no round yet: the executor waits for its set-up once
   bool active = false;
   int64_t id = 0;                // owner's handle
   bool resume = false;           // continue the context's state (no set-up, no stopping rule)
@@ -169,16 +170,24 @@ class Engine {
       pcdn_ctx* c = j->run.c;
       *err_ctx = c;
       const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
-      HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
       count_outer(c, j->run.o, j->run.P, 1);
+      if (!j->narrow) {  // partition and bundles in the executor launches
+        if (j->fresh) {
+          HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
+          HIPCHK(c, hipStreamWaitEvent(wide_stream_, j->pre_done, 0));
+        }
+        j->fresh = false;
+        continue;
+      }
+      HIPCHK(c, hipGraphLaunch(c->graph_pre, c->stream));
       if (j->hybrid) {  // its bundles follow on its own stream once the list is read
         HIPCHK(c, hipMemcpyAsync(c->hheavy, c->heavy, (kHeavyCap + 1) * sizeof(int32_t),
                                  hipMemcpyDeviceToHost, c->stream));
         continue;
       }
       HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
-      HIPCHK(c, hipStreamWaitEvent(j->narrow ? narrow_stream_[g] : wide_stream_, j->pre_done, 0));
-      if (j->narrow) htab[at[g]++] = outer_narrow_args(c, j->run.o, j->run.P);
+      HIPCHK(c, hipStreamWaitEvent(narrow_stream_[g], j->pre_done, 0));
+      htab[at[g]++] = outer_narrow_args(c, j->run.o, j->run.P);
     }
     *err_ctx = nullptr;
     // single-workgroup jobs: one launch per loss, then each job's stopping sweep

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace pcdn {
 
 constexpr int kWave = 64;
@@ -180,6 +182,41 @@ struct SumArgs {
   int32_t nb;                // blocks of the first level
 };
 
+// Partition kernels as executor tasks (the launches of launch_perm_keys,
+// launch_radix_sort and launch_chunks, one task per launch).
+struct PermKeysArgs {
+  const IterState* it;
+  uint64_t seed;
+  int64_t k, p;
+  const double* act;
+  uint32_t* keys;
+  int32_t* idx;
+};
+struct RadixArgs {          // one histogram or scatter pass
+  const uint32_t* kin;
+  const int32_t* iin;
+  uint32_t* kout;
+  int32_t* iout;
+  int32_t* hist;            // digit offsets (scanned histogram)
+  int64_t p, ntiles;
+  int32_t shift;
+};
+struct ScanArgs {           // exclusive scan of in[0..m) into out (out[m] = total)
+  const int32_t* in;
+  int32_t* out;
+  int32_t* tmp;             // block totals
+  int64_t m, nb;
+};
+struct ChunkArgs {
+  const int32_t* perm;
+  const int64_t* cp;
+  const int32_t* cstart;
+  int32_t* nch;
+  Chunk* chunks;
+  int64_t p;
+  int32_t chunk;
+};
+
 // One kernel invocation of one problem, as run by the multi-problem
 // executor: the kernel, its arguments, and the grid a launch of its own
 // would have (nblk blocks; the line search's grid is gx x nblk/gx).
@@ -195,6 +232,15 @@ enum TaskKind : int32_t {
   kTaskSumFinal,
   kTaskStopPartial,
   kTaskStopFinal,
+  kTaskPermKeys,
+  kTaskRadixHist,
+  kTaskRadixScatter,
+  kTaskScanSmall,
+  kTaskScanBlocks,
+  kTaskScanTotals,
+  kTaskScanAdd,
+  kTaskChunkCount,
+  kTaskChunkFill,
 };
 struct Task {
   int32_t kind;
@@ -208,6 +254,10 @@ struct Task {
     ScatterCountArgs sc;
     SumArgs sum;
     StopSumArgs stop;
+    PermKeysArgs pk;
+    RadixArgs rx;
+    ScanArgs scan;
+    ChunkArgs ch;
   } u;
 };
 
@@ -298,6 +348,13 @@ int sum_grid(int64_t m);
 hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s);
 hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s);
 hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
+// The partition of one outer iteration (launch_perm_keys, launch_radix_sort
+// and launch_chunks on the same buffers) as executor tasks, appended to out;
+// the same permutation and chunk descriptors as those launches.
+void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, const double* act,
+                     uint32_t* keys0, int32_t* idx0, uint32_t* keys1, int32_t* idx1,
+                     int32_t* hist, int32_t* scan_tmp, const int64_t* cp, int32_t chunk,
+                     int32_t* nch, int32_t* cstart, Chunk* chunks, std::vector<Task>& out);
 // Every task of tasks[0..count) in one launch of `blocks` blocks: task i
 // takes blocks [first[i], first[i+1]) (first[count] = blocks).
 hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int blocks,

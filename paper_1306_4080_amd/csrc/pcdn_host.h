@@ -222,10 +222,11 @@ pcdn::NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* per
                                   double* dtx_copy);
 // ... for every bundle of the current outer iteration's partition.
 pcdn::NarrowArgs outer_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P);
-// The kernels of one outer iteration after the partition (every bundle,
-// counters, stopping sweep) as tasks for the multi-problem executor, with
-// the arguments and grids the single-problem launches use (multi-kernel
-// schedule only).
+// The kernels of one outer iteration (partition, every bundle, counters,
+// stopping sweep) as tasks for the multi-problem executor, with the
+// arguments and grids of the single-problem launches (the partition's scans
+// in smaller blocks, with the same integer results); multi-kernel schedule
+// only.
 int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<pcdn::Task>& out);
 // Capture (once per key) the two halves of an outer iteration around the
 // single-workgroup bundles: graph_pre and graph_post (see pcdn_ctx).

@@ -6,6 +6,9 @@
 // stopping norm) is FP64 and deterministic for a fixed launch shape; the only
 // atomics are the FP64 adds that build d^T x_i, whose order can differ in the
 // last bit between runs.
+#include <cstring>
+#include <utility>
+
 #include "pcdn_device.h"
 
 namespace pcdn {
@@ -210,9 +213,12 @@ __global__ void k_fill(double* a, double v, int64_t n) {
     a[i] = v;
 }
 
-__global__ void k_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64_t p,
-                            const double* act, uint32_t* keys, int32_t* idx) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Kernel bodies that the multi-problem executor also runs take their block
+// index (and block count) as arguments; see k_exec.
+__device__ __forceinline__ void perm_keys_body(const IterState* it, uint64_t seed, int64_t k,
+                                               int64_t p, const double* act, uint32_t* keys,
+                                               int32_t* idx, int64_t bid) {
+  const int64_t j = bid * (int64_t)kBlock + threadIdx.x;
   if (it) {
     seed = it->seed;
     k = it->k;
@@ -228,16 +234,26 @@ __global__ void k_perm_keys(const IterState* it, uint64_t seed, int64_t k, int64
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_perm_keys(const IterState* it, uint64_t seed,
+                                                      int64_t k, int64_t p, const double* act,
+                                                      uint32_t* keys, int32_t* idx) {
+  perm_keys_body(it, seed, k, p, act, keys, idx, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // exclusive scan (int32), three launches: per-block scan, scan of block
-// totals, add-back.  A block covers kScanTile items.
+// totals, add-back.  A block of THREADS threads covers kScanTile items (PER
+// = kScanTile / THREADS each): 1024-thread blocks in direct launches,
+// kBlock-thread blocks in the multi-problem executor.  Integer sums, so
+// every block size gives the same result.
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 4;
-constexpr int kScanTile = kScanThreads * kScanPer;
+constexpr int kScanTile = 4096;
 
-// Exclusive scan of one value per thread across a 1024-thread block.
-__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* lds16, int32_t* total) {
+// Exclusive scan of one value per thread across a THREADS-thread block
+// (lds holds THREADS / kWave + 1 ints).
+template <int THREADS>
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
   const int lane = lane_id(), wv = wave_in_block();
   int32_t x = v;
 #pragma unroll
@@ -245,55 +261,58 @@ __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* lds16, int32_
     const int32_t y = __shfl_up(x, o, kWave);
     if (lane >= o) x += y;
   }
-  if (lane == kWave - 1) lds16[wv] = x;
+  if (lane == kWave - 1) lds[wv] = x;
   __syncthreads();
   if (threadIdx.x == 0) {
     int32_t run = 0;
-    for (int k = 0; k < kScanThreads / kWave; ++k) {
-      const int32_t t = lds16[k];
-      lds16[k] = run;
+    for (int k = 0; k < THREADS / kWave; ++k) {
+      const int32_t t = lds[k];
+      lds[k] = run;
       run += t;
     }
-    lds16[kScanThreads / kWave] = run;
+    lds[THREADS / kWave] = run;
   }
   __syncthreads();
-  const int32_t r = lds16[wv] + x - v;
-  *total = lds16[kScanThreads / kWave];
+  const int32_t r = lds[wv] + x - v;
+  *total = lds[THREADS / kWave];
   __syncthreads();
   return r;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t* in, int32_t* out,
-                                                              int64_t m, int32_t* block_tot) {
-  __shared__ int32_t lds[kScanThreads / kWave + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-  int32_t v[kScanPer];
+template <int THREADS>
+__device__ __forceinline__ void scan_blocks_body(const int32_t* in, int32_t* out, int64_t m,
+                                                 int32_t* block_tot, int64_t bid) {
+  constexpr int PER = kScanTile / THREADS;
+  __shared__ int32_t lds[THREADS / kWave + 1];
+  const int64_t base = bid * kScanTile + (int64_t)threadIdx.x * PER;
+  int32_t v[PER];
   int32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
+  for (int k = 0; k < PER; ++k) {
     v[k] = base + k < m ? in[base + k] : 0;
     s += v[k];
   }
   int32_t tot;
-  int32_t run = block_exclusive_scan(s, lds, &tot);
+  int32_t run = block_exclusive_scan<THREADS>(s, lds, &tot);
 #pragma unroll
-  for (int k = 0; k < kScanPer; ++k) {
+  for (int k = 0; k < PER; ++k) {
     if (base + k < m) out[base + k] = run;
     run += v[k];
   }
-  if (threadIdx.x == 0) block_tot[blockIdx.x] = tot;
+  if (threadIdx.x == 0) block_tot[bid] = tot;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t* block_tot, int64_t nb,
-                                                              int32_t* out_total) {
-  __shared__ int32_t lds[kScanThreads / kWave + 1];
-  const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
+template <int THREADS>
+__device__ __forceinline__ void scan_totals_body(int32_t* block_tot, int64_t nb,
+                                                 int32_t* out_total) {
+  __shared__ int32_t lds[THREADS / kWave + 1];
+  const int64_t per = (nb + THREADS - 1) / THREADS;
   const int64_t lo = (int64_t)threadIdx.x * per;
   const int64_t hi = lo + per < nb ? lo + per : nb;
   int32_t s = 0;
   for (int64_t k = lo; k < hi; ++k) s += block_tot[k];
   int32_t tot;
-  int32_t run = block_exclusive_scan(s, lds, &tot);
+  int32_t run = block_exclusive_scan<THREADS>(s, lds, &tot);
   for (int64_t k = lo; k < hi; ++k) {
     const int32_t t = block_tot[k];
     block_tot[k] = run;
@@ -302,15 +321,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t* block_tot
   if (threadIdx.x == 0) *out_total = tot;
 }
 
-// Whole scan in one block when m <= kScanSmall: thread t scans a contiguous
-// chunk of ceil(m / 1024) items (in and out may alias: a thread reads its
+// Whole scan in one block when m <= 16 THREADS: thread t scans a contiguous
+// chunk of ceil(m / THREADS) items (in and out may alias: a thread reads its
 // whole chunk before the block scan's barriers and writes it afterwards).
-constexpr int64_t kScanSmall = 16 * kScanThreads;
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_small(const int32_t* in, int32_t* out,
-                                                             int64_t m) {
-  __shared__ int32_t lds[kScanThreads / kWave + 1];
-  const int64_t per = (m + kScanThreads - 1) / kScanThreads;
+template <int THREADS>
+__device__ __forceinline__ void scan_small_body(const int32_t* in, int32_t* out, int64_t m) {
+  __shared__ int32_t lds[THREADS / kWave + 1];
+  const int64_t per = (m + THREADS - 1) / THREADS;
   const int64_t lo = (int64_t)threadIdx.x * per;
   const int64_t hi = lo + per < m ? lo + per : m;
   int32_t v[16];
@@ -321,7 +338,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_small(const int32_t* in, 
     s += v[k];
   }
   int32_t tot;
-  int32_t run = block_exclusive_scan(s, lds, &tot);
+  int32_t run = block_exclusive_scan<THREADS>(s, lds, &tot);
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     if (lo + k < hi) out[lo + k] = run;
@@ -330,13 +347,37 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_small(const int32_t* in, 
   if (threadIdx.x == 0) out[m] = tot;
 }
 
+template <int THREADS>
+__device__ __forceinline__ void scan_add_body(int32_t* out, int64_t m, const int32_t* block_tot,
+                                              int64_t bid) {
+  constexpr int PER = kScanTile / THREADS;
+  const int64_t base = bid * kScanTile + (int64_t)threadIdx.x * PER;
+  const int32_t add = block_tot[bid];
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (base + k < m) out[base + k] += add;
+}
+
+constexpr int64_t kScanSmall = 16 * kScanThreads;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t* in, int32_t* out,
+                                                              int64_t m, int32_t* block_tot) {
+  scan_blocks_body<kScanThreads>(in, out, m, block_tot, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t* block_tot, int64_t nb,
+                                                              int32_t* out_total) {
+  scan_totals_body<kScanThreads>(block_tot, nb, out_total);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_small(const int32_t* in, int32_t* out,
+                                                             int64_t m) {
+  scan_small_body<kScanThreads>(in, out, m);
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t m,
                                                            const int32_t* block_tot) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-  const int32_t add = block_tot[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kScanPer; ++k)
-    if (base + k < m) out[base + k] += add;
+  scan_add_body<kScanThreads>(out, m, block_tot, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -349,30 +390,38 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 4;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* keys, int64_t p,
-                                                             int shift, int32_t* hist,
-                                                             int64_t ntiles) {
+static_assert(kSortThreads == kBlock, "the executor runs the sort passes in kBlock-thread blocks");
+
+__device__ __forceinline__ void radix_hist_body(const uint32_t* keys, int64_t p, int shift,
+                                                int32_t* hist, int64_t ntiles, int64_t bid) {
   __shared__ int32_t cnt[256];
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = bid * kSortTile;
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t i = base + r * kSortThreads + threadIdx.x;
     if (i < p) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+  hist[(int64_t)threadIdx.x * ntiles + bid] = cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t* kin, const int32_t* iin, uint32_t* kout, int32_t* iout, int64_t p, int shift,
-    const int32_t* offs, int64_t ntiles) {
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* keys, int64_t p,
+                                                             int shift, int32_t* hist,
+                                                             int64_t ntiles) {
+  radix_hist_body(keys, p, shift, hist, ntiles, blockIdx.x);
+}
+
+__device__ __forceinline__ void radix_scatter_body(const uint32_t* kin, const int32_t* iin,
+                                                   uint32_t* kout, int32_t* iout, int64_t p,
+                                                   int shift, const int32_t* offs, int64_t ntiles,
+                                                   int64_t bid) {
   __shared__ int32_t base_off[256];
   __shared__ int32_t wcnt[kWavesPerBlock][256];
-  base_off[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  base_off[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + bid];
   const int lane = lane_id(), wv = wave_in_block();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+  const int64_t tile = bid * kSortTile;
   for (int r = 0; r < kSortRounds; ++r) {
 #pragma unroll
     for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][threadIdx.x] = 0;
@@ -407,13 +456,20 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
   }
 }
 
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t* kin, const int32_t* iin, uint32_t* kout, int32_t* iout, int64_t p, int shift,
+    const int32_t* offs, int64_t ntiles) {
+  radix_scatter_body(kin, iin, kout, iout, p, shift, offs, ntiles, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // chunk bookkeeping: nch = chunks per slot, cstart = exclusive scan, then one
 // descriptor per chunk
 // ---------------------------------------------------------------------------
-__global__ void k_chunk_count(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
-                              int32_t* nch) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void chunk_count_body(const int32_t* perm, const int64_t* cp,
+                                                 int64_t p, int32_t chunk, int32_t* nch,
+                                                 int64_t bid) {
+  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
   if (r < p) {
     const int32_t j = perm ? perm[r] : (int32_t)r;
     const int64_t len = cp[j + 1] - cp[j];
@@ -422,9 +478,15 @@ __global__ void k_chunk_count(const int32_t* perm, const int64_t* cp, int64_t p,
   }
 }
 
-__global__ void k_chunk_fill(const int32_t* perm, const int64_t* cp, const int32_t* cstart,
-                             int64_t p, int32_t chunk, Chunk* chunks) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_chunk_count(const int32_t* perm, const int64_t* cp,
+                                                        int64_t p, int32_t chunk, int32_t* nch) {
+  chunk_count_body(perm, cp, p, chunk, nch, blockIdx.x);
+}
+
+__device__ __forceinline__ void chunk_fill_body(const int32_t* perm, const int64_t* cp,
+                                                const int32_t* cstart, int64_t p, int32_t chunk,
+                                                Chunk* chunks, int64_t bid) {
+  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
   if (r < p) {
     const int32_t j = perm ? perm[r] : (int32_t)r;
     const int64_t k0 = cp[j], len = cp[j + 1] - k0;
@@ -442,6 +504,12 @@ __global__ void k_chunk_fill(const int32_t* perm, const int64_t* cp, const int32
       chunks[c0 + q] = ch;
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_fill(const int32_t* perm, const int64_t* cp,
+                                                       const int32_t* cstart, int64_t p,
+                                                       int32_t chunk, Chunk* chunks) {
+  chunk_fill_body(perm, cp, cstart, p, chunk, chunks, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,6 +1661,32 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskSumFinal: sum_final_body(t.u.sum); break;
     case kTaskStopPartial: stop_partial_body(t.u.stop, lb, t.nblk); break;
     case kTaskStopFinal: stop_final_body(t.u.stop); break;
+    case kTaskPermKeys:
+      perm_keys_body(t.u.pk.it, t.u.pk.seed, t.u.pk.k, t.u.pk.p, t.u.pk.act, t.u.pk.keys,
+                     t.u.pk.idx, lb);
+      break;
+    case kTaskRadixHist:
+      radix_hist_body(t.u.rx.kin, t.u.rx.p, t.u.rx.shift, t.u.rx.hist, t.u.rx.ntiles, lb);
+      break;
+    case kTaskRadixScatter:
+      radix_scatter_body(t.u.rx.kin, t.u.rx.iin, t.u.rx.kout, t.u.rx.iout, t.u.rx.p, t.u.rx.shift,
+                         t.u.rx.hist, t.u.rx.ntiles, lb);
+      break;
+    case kTaskScanSmall: scan_small_body<kBlock>(t.u.scan.in, t.u.scan.out, t.u.scan.m); break;
+    case kTaskScanBlocks:
+      scan_blocks_body<kBlock>(t.u.scan.in, t.u.scan.out, t.u.scan.m, t.u.scan.tmp, lb);
+      break;
+    case kTaskScanTotals:
+      scan_totals_body<kBlock>(t.u.scan.tmp, t.u.scan.nb, t.u.scan.out + t.u.scan.m);
+      break;
+    case kTaskScanAdd: scan_add_body<kBlock>(t.u.scan.out, t.u.scan.m, t.u.scan.tmp, lb); break;
+    case kTaskChunkCount:
+      chunk_count_body(t.u.ch.perm, t.u.ch.cp, t.u.ch.p, t.u.ch.chunk, t.u.ch.nch, lb);
+      break;
+    case kTaskChunkFill:
+      chunk_fill_body(t.u.ch.perm, t.u.ch.cp, t.u.ch.cstart, t.u.ch.p, t.u.ch.chunk,
+                      t.u.ch.chunks, lb);
+      break;
     default: break;
   }
 }
@@ -1743,6 +1837,80 @@ hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int3
   hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
                      cp, cstart, p, chunk, chunks);
   return hipGetLastError();
+}
+
+namespace {
+
+Task partition_task(int kind, int loss, int64_t nblk) {
+  Task t;
+  std::memset(&t, 0, sizeof(t));
+  t.kind = kind;
+  t.loss = loss;
+  t.nblk = (int32_t)nblk;
+  return t;
+}
+
+// The tasks of launch_scan(in, out, m, tmp); kBlock-thread blocks, so the
+// one-block scan takes m <= 16 kBlock.
+void scan_tasks(int loss, const int32_t* in, int32_t* out, int64_t m, int32_t* tmp,
+                std::vector<Task>& v) {
+  Task t = partition_task(kTaskScanSmall, loss, 1);
+  t.u.scan = ScanArgs{in, out, tmp, m, 0};
+  if (m >= 1 && m <= 16 * kBlock) {
+    v.push_back(t);
+    return;
+  }
+  const int64_t nb = (m + kScanTile - 1) / kScanTile;
+  t.u.scan.nb = nb;
+  if (nb < 1) {
+    t.kind = kTaskScanTotals;
+    v.push_back(t);
+    return;
+  }
+  t.kind = kTaskScanBlocks;
+  t.nblk = (int32_t)nb;
+  v.push_back(t);
+  t.kind = kTaskScanTotals;
+  t.nblk = 1;
+  v.push_back(t);
+  t.kind = kTaskScanAdd;
+  t.nblk = (int32_t)nb;
+  v.push_back(t);
+}
+
+}  // namespace
+
+void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, const double* act,
+                     uint32_t* keys0, int32_t* idx0, uint32_t* keys1, int32_t* idx1,
+                     int32_t* hist, int32_t* scan_tmp, const int64_t* cp, int32_t chunk,
+                     int32_t* nch, int32_t* cstart, Chunk* chunks, std::vector<Task>& out) {
+  const int64_t pg = grid_for(p, kBlock, 1 << 30);
+  Task t = partition_task(kTaskPermKeys, loss, pg);
+  t.u.pk = PermKeysArgs{it, seed, 0, p, act, keys0, idx0};
+  out.push_back(t);
+  // launch_radix_sort's passes
+  const int64_t ntiles = (p + kSortTile - 1) / kSortTile;
+  uint32_t* kin = keys0;
+  int32_t* iin = idx0;
+  uint32_t* kout = keys1;
+  int32_t* iout = idx1;
+  for (int pass = 0; pass < 4; ++pass) {
+    t = partition_task(kTaskRadixHist, loss, ntiles);
+    t.u.rx = RadixArgs{kin, iin, kout, iout, hist, p, ntiles, 8 * pass};
+    out.push_back(t);
+    scan_tasks(loss, hist, hist, 256 * ntiles, scan_tmp, out);
+    t.kind = kTaskRadixScatter;
+    out.push_back(t);
+    std::swap(kin, kout);
+    std::swap(iin, iout);
+  }
+  // launch_chunks
+  t = partition_task(kTaskChunkCount, loss, pg);
+  t.u.ch = ChunkArgs{idx0, cp, cstart, nch, chunks, p, chunk};
+  out.push_back(t);
+  scan_tasks(loss, nch, cstart, p, scan_tmp, out);
+  t.kind = kTaskChunkFill;
+  out.push_back(t);
 }
 
 int sweep_grid(int64_t slots) { return grid_for(slots, kWavesPerBlock, 8192); }
