@@ -250,6 +250,8 @@ LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
   l.Q = o.max_ls;
   l.ra = o.ra();
   l.rb = o.rb();
+  l.C = c->C;
+  l.sigma = o.sigma;
   return l;
 }
 
@@ -624,9 +626,16 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     out.push_back(t);
     t.kind = kTaskSplit;
     out.push_back(t);
-    t = task(kTaskLinesearch, lsx * lsy, lsx);
+    // the first candidate group, then the others (which stop at once when
+    // the first group holds the accepted step: the common case)
+    t = task(kTaskLinesearch, lsx, lsx);
     t.u.ls = ls_args(c, o, c->idx0, lo, hi, o.shrink);
     out.push_back(t);
+    if (lsy > 1) {
+      t.kind = kTaskLinesearchRest;
+      t.nblk = lsx * (lsy - 1);
+      out.push_back(t);
+    }
     t = task(kTaskApply, apply_grid(c->n, hi - lo), 0);
     t.u.ap = apply_args(c, o, c->idx0, lo, hi, o.shrink);
     out.push_back(t);

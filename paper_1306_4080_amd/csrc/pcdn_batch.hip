@@ -24,6 +24,11 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Blocks of the later line-search candidate groups, summed over one bundle
+// of every multi-kernel job, from which they run as tasks of their own: two
+// rounds of the 2,048 blocks of 256 threads that the GPU holds at once.
+constexpr int64_t kLsSplitBlocks = 4096;
+
 // One solve inside the engine.
 struct EngineJob {
   SolveRun run;
@@ -360,6 +365,19 @@ class Engine {
     }
     plan_stale_ = false;
     if (plan_jobs_.empty()) return PCDN_OK;
+    // The later line-search candidate groups get tasks of their own (which
+    // stop early when the first group holds the accepted step) only when
+    // the blocks they save exceed what the GPU holds at once; otherwise the
+    // extra lock-step launch per bundle costs more latency than it saves,
+    // and the first-group task takes the whole grid as in a launch of its own.
+    int64_t rest_blocks = 0;
+    for (EngineJob* j : plan_jobs_)
+      for (const Task& t : j->tasks)
+        if (t.kind == kTaskLinesearchRest) {
+          rest_blocks += t.nblk;
+          break;
+        }
+    const bool split_ls = rest_blocks >= kLsSplitBlocks;
     const size_t task_bytes = align_up(sizeof(Task) * n_tasks);
     const size_t first_bytes = align_up(sizeof(int32_t) * (n_tasks + L));
     const size_t src_bytes = align_up(3 * sizeof(double*) * plan_jobs_.size());
@@ -379,8 +397,16 @@ class Engine {
       hfirst[nf++] = 0;
       for (EngineJob* j : plan_jobs_) {
         if (st >= j->tasks.size()) continue;
-        htasks[nt++] = j->tasks[st];
-        blk += j->tasks[st].nblk;
+        Task t = j->tasks[st];
+        if (!split_ls) {
+          if (t.kind == kTaskLinesearch && st + 1 < j->tasks.size() &&
+              j->tasks[st + 1].kind == kTaskLinesearchRest)
+            t.nblk += j->tasks[st + 1].nblk;
+          else if (t.kind == kTaskLinesearchRest)
+            t.nblk = 0;  // no block maps to an empty task
+        }
+        htasks[nt++] = t;
+        blk += t.nblk;
         hfirst[nf++] = blk;
         ++cnt;
       }

@@ -126,6 +126,7 @@ struct LsArgs {
   int Q;
   const double* p_active;  // nullable: slots clipped to the first *p_active
   double ra, rb;           // regulariser, as in SweepArgs
+  double C, sigma;         // the Armijo test (read by the executor's later candidate groups)
 };
 
 struct ApplyArgs {
@@ -226,6 +227,7 @@ enum TaskKind : int32_t {
   kTaskSplit,
   kTaskSplitStop,
   kTaskLinesearch,
+  kTaskLinesearchRest,
   kTaskApply,
   kTaskScatterCount,
   kTaskSumPartial,

@@ -793,6 +793,27 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
   return block_sum(x, lds4);
 }
 
+// The executor runs the line search in two tasks: the first candidate
+// group (grid row 0, which also writes Delta and the touched count), then
+// the other rows.  A block of the second task first takes the Armijo
+// decision over the first group's candidates exactly as the apply does; if
+// one of them passes, the apply reads no other candidate, and the block
+// returns without computing its group.  by >= 1 is the block's grid row.
+template <int LOSS>
+__device__ __forceinline__ void linesearch_rest_body(const LsArgs& a, int bx, int by, int G) {
+  __shared__ double lds4[kWavesPerBlock];
+  if (clipped_hi(a.slot_hi, a.p_active) <= a.slot_lo) return;
+  double Dq = ls_total(a.part, 2 * a.Q, G, lds4);
+  const int nq0 = a.Q < kQGroup ? a.Q : kQGroup;
+  for (int q = 0; q < nq0; ++q) {
+    const double sL = ls_total(a.part, q, G, lds4);
+    const double l1 = ls_total(a.part, a.Q + q, G, lds4);
+    if (l1 + a.C * sL <= a.sigma * Dq) return;
+    Dq *= a.beta;
+  }
+  linesearch_body<LOSS>(a, bx, by, G);
+}
+
 // ---------------------------------------------------------------------------
 // Armijo decision and accept.  Every block takes the decision itself from the
 // line-search partials (increasing q, eq. (6)'s test with Delta scaled by beta
@@ -1655,6 +1676,9 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskSplit: split_body<LOSS, false>(t.u.sw, lb, t.nblk); break;
     case kTaskSplitStop: split_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
     case kTaskLinesearch: linesearch_body<LOSS>(t.u.ls, lb % t.gx, lb / t.gx, t.gx); break;
+    case kTaskLinesearchRest:
+      linesearch_rest_body<LOSS>(t.u.ls, lb % t.gx, 1 + lb / t.gx, t.gx);
+      break;
     case kTaskApply: apply_body<LOSS>(t.u.ap, lb, t.nblk); break;
     case kTaskScatterCount: scatter_count_body(t.u.sc, lb, t.nblk); break;
     case kTaskSumPartial: sum_partial_body(t.u.sum, lb, t.nblk); break;

@@ -167,6 +167,37 @@ def test_executor_partition_with_multiblock_scans(pc):
         s.close()
 
 
+def test_executor_split_line_search(pc):
+    """Enough multi-kernel jobs with n = 20,000 that the executor runs the
+    later line-search candidate groups as a task of its own (which stops at
+    once when the first group of four holds the accepted step).  Bundles of
+    all features at C = 16 need q = 4 (the second group) in most outer
+    iterations, so both ways out of that task run.  Every job equals its
+    solve alone and the oracle."""
+    specs = []
+    for i in range(8):
+        lr = i % 2 == 0
+        d = synth.sparse_random(130 + i, 20000, 1500, 0.02 if lr else 0.01, binary=True)
+        specs.append((d, "lr" if lr else "svm", 16.0 if lr else 4.0, d.p if i < 4 else d.p // 6))
+    solvers = [pc.Solver(device=0).load_data(d) for d, *_ in specs]
+    opts = dict(seed=3, schedule="wide", max_outer=8)
+    batched = pc.solve_batch([s.job(C, P, 1e-12, loss, **opts)
+                              for s, (d, loss, C, P) in zip(solvers, specs)])
+    long_searches = 0
+    for s, (d, loss, C, P), b in zip(solvers, specs, batched):
+        ib = b[2]
+        print(f"{loss} C={C} P={P}: outer={ib['outer_iters']} bundles={ib['bundles']} "
+              f"ls_steps={ib['ls_steps']} F={ib['objective']:.15g}", flush=True)
+        _assert_same_run(b, s.solve(C, P, 1e-12, loss, **opts))
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss=loss, C=C),
+                                  P=P, eps=1e-12, seed=3, max_outer=8)
+        _assert_oracle(b, (w_o, io), True)
+        long_searches += ib["ls_steps"] > 4 * ib["bundles"]
+    assert long_searches >= 1
+    for s in solvers:
+        s.close()
+
+
 def test_batch_errors_run_nothing(pc):
     from paper_1306_4080_amd import PcdnError
     d = synth.c1()
