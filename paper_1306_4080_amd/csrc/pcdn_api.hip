@@ -221,7 +221,7 @@ int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) 
     ProfScope ps(c, 0);
     HIPCHK(c, launch_sweep(c->loss, false, a, c->stream));
   }
-  {
+  if (has_split_columns(c, o.chunk)) {
     ProfScope ps(c, 1);
     HIPCHK(c, launch_split(c->loss, false, a, c->stream));
   }
@@ -317,7 +317,7 @@ int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) 
   {
     ProfScope ps(c, 4);
     HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
-    HIPCHK(c, launch_split(c->loss, true, a, c->stream));
+    if (has_split_columns(c, kChunk)) HIPCHK(c, launch_split(c->loss, true, a, c->stream));
   }
   HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->scal, it, c->stream));
   return PCDN_OK;
@@ -333,7 +333,7 @@ int launch_stopping_shrink(pcdn_ctx* c, const Opts& o, IterState* it) {
   {
     ProfScope ps(c, 4);
     HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
-    HIPCHK(c, launch_split(c->loss, true, a, c->stream));
+    if (has_split_columns(c, kChunk)) HIPCHK(c, launch_split(c->loss, true, a, c->stream));
   }
   const StopSumArgs s{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, it,
                       sum_grid(c->p), o.ra()};
@@ -425,6 +425,10 @@ int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, const IterState* i
   HIPCHK(c, launch_radix_sort(c->keys0, c->idx0, c->keys1, c->idx1, c->p, c->hist, c->scan_tmp,
                               c->stream));
   return PCDN_OK;
+}
+
+bool has_split_columns(const pcdn_ctx* c, int chunk) {
+  return c->top_len.size() < 2 || c->top_len[1] > chunk;
 }
 
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P) {
@@ -625,7 +629,7 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     t.u.sw = bundle_sweep_args(c, o, lo, hi, o.shrink);
     out.push_back(t);
     t.kind = kTaskSplit;
-    out.push_back(t);
+    if (has_split_columns(c, o.chunk)) out.push_back(t);
     // the first candidate group, then the others (which stop at once when
     // the first group holds the accepted step: the common case)
     t = task(kTaskLinesearch, lsx, lsx);
@@ -652,7 +656,7 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   }
   out.push_back(t);
   t.kind = kTaskSplitStop;
-  out.push_back(t);
+  if (has_split_columns(c, kChunk)) out.push_back(t);
   const int sb = sum_grid(c->p);
   if (o.shrink) {
     t = task(kTaskStopPartial, sb, 0);

@@ -204,6 +204,10 @@ int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r);
 int check_loss(pcdn_ctx* c, int loss);
 // Record the regulariser that the state is being advanced with.
 void note_regulariser(pcdn_ctx* c, const Opts& o);
+// Whether a column has more than `chunk` nonzeros: only then do work items
+// of that size split a column, and only then is k_split launched (with no
+// split column it does nothing).
+bool has_split_columns(const pcdn_ctx* c, int chunk);
 // Whether outer iterations with bundle size P run in one workgroup.
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
 // Whether the batch engine runs this single-workgroup job's bundles of at
