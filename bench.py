@@ -51,6 +51,7 @@ if ROOT not in sys.path:
 
 METRIC = "bundle-sweep nnz/s (HBM GB/s %peak); batched solves/s + p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
+NARROW_CLASS = 5  # index of "narrow" in KERNEL_CLASSES
 KERNEL_CLASSES = ("sweep", "split_columns", "linesearch", "apply", "stopping_sweep", "narrow")
 KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep, direction, fused d^T x scatter)",
                 "k_split (split-column finish and scatter)",
@@ -432,7 +433,11 @@ def main():
                      "alg_bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches": int(dom_n),
                      "measured": "HIP events in timed region B (the next steps after region A)",
-                     "region_b_ms_per_step": 1e3 * (tb1 - tb0) / args.steps},
+                     "region_b_ms_per_step": 1e3 * (tb1 - tb0) / args.steps,
+                     # a one-workgroup kernel runs on one of the 256 compute
+                     # units: its share of the HBM peak is peak / 256
+                     "frac_of_one_cu_share": (achieved / (HBM_PEAK_GBS / 256)
+                                              if dominant == NARROW_CLASS else None)},
         "sequential": {"value": nnz_total / elapsed_seq, "ms_per_step": 1e3 * elapsed_seq / args.steps,
                        "measured": "region A2: the next steps, one setting after another"},
         "per_setting_ms_per_iter": {k: 1e3 * v / args.steps for k, v in per_setting.items()},
