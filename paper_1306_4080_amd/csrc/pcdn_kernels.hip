@@ -1014,6 +1014,7 @@ struct NarrowLds {
   double lds16[kNarrowWaves];
   double red[2][kNarrowWaves][4];
   int32_t n_touch;
+  int32_t any_d;                        // some direction of the bundle is nonzero
   int32_t off[kNarrowMaxP + 1];        // nonzero offsets of the bundle's slots
   int32_t feat[kNarrowMaxP];
   double w[kNarrowMaxP];
@@ -1119,7 +1120,10 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       L.w[s] = na.w[j];
       L.acc[s] = make_double2(0.0, 0.0);
     }
-    if (tid == 0) L.n_touch = 0;
+    if (tid == 0) {
+      L.n_touch = 0;
+      L.any_d = 0;
+    }
     // distinct rows of the bundle with d^T x kept in LDS (t_row/t_c/t_y/t_dtx
     // indexed by local row id), or -1: d^T x in global memory, rows listed
     // by their first toucher
@@ -1216,6 +1220,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       const double dj = newton_dir(g, h, wj, a.ra, a.rb);
       L.d[s] = dj;
       if (dj != 0.0) {
+        L.any_d = 1;
         const int32_t len = L.off[s + 1] - L.off[s];
         if (len > na.chunk)
           n_scat_long += (double)len;
@@ -1228,6 +1233,23 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       a.d[lo + s] = dj;
     }
     __syncthreads();  // publishes L.d; Delta's per-thread part stays in `del`
+    if (L.any_d == 0 && !na.dtx_copy) {
+      // every direction is zero: no row is touched, Delta = 0, the first
+      // candidate passes (eq. (6): 0 <= 0) with dF = 0, and w and the
+      // retained quantities stay as they are
+      n_bundles += 1.0;
+      n_nnz += (double)nb;
+      n_slots += (double)ns;
+      n_ls += 1.0;
+      if (tid == 0 && t == t_end - 1) {
+        na.st->q = 0;
+        na.st->alpha = 1.0;
+        na.st->dF = 0.0;
+        na.st->delta = 0.0;
+      }
+      __syncthreads();
+      continue;
+    }
     // 2. scatter d_j x_ij into d^T x; list touched rows with their retained
     //    quantity and label
     //    The register rounds issue every flag exchange before waiting on any.
