@@ -71,10 +71,11 @@ struct Staging {
 };
 
 // Rounds of one outer iteration over a changing set of solves.  Jobs on the
-// single-workgroup schedule share one launch per round (one workgroup each);
-// jobs on the multi-kernel schedule run their recorded outer iteration in
-// lock-step executor launches (launch s runs task s of every such job).
-// Every job's partition is a replayed graph on its own context's stream.
+// single-workgroup schedule share one launch per round (one workgroup each),
+// their partitions and stopping sweeps replayed graphs on their own
+// contexts' streams; jobs on the multi-kernel schedule run their recorded
+// outer iteration, partition included, in lock-step executor launches
+// (launch s runs task s of every such job).
 class Engine {
  public:
   std::string err;
@@ -129,12 +130,10 @@ class Engine {
     }
     j->narrow = use_narrow(r.c, r.o, r.P);
     j->hybrid = j->narrow && use_hybrid(r.c, r.o, r.P);
-    rc = ensure_split_graphs(r.c, r.o, r.P);
+    // single-workgroup jobs replay the two halves of an outer iteration
+    // around their bundles; multi-kernel jobs run theirs as executor tasks
+    rc = j->narrow ? ensure_split_graphs(r.c, r.o, r.P) : outer_tasks(r.c, r.o, r.P, j->tasks);
     if (rc) return rc;
-    if (!j->narrow) {
-      rc = outer_tasks(r.c, r.o, r.P, j->tasks);
-      if (rc) return rc;
-    }
     rc = set_iter(r.c, r.o.seed, j->resume ? j->k_first : 0);
     if (rc) return rc;
     j->active = !r.converged && r.outer < r.o.max_outer;
@@ -271,7 +270,8 @@ class Engine {
       }
       *err_ctx = nullptr;
     }
-    // multi-kernel jobs: every bundle and stopping sweep in lock-step launches
+    // multi-kernel jobs: partition, every bundle and the stopping sweep in
+    // lock-step launches
     if (!plan_jobs_.empty()) {
       const char* base = (const char*)exec_.dev;
       for (size_t st = 0; st < plan_count_.size(); ++st) {
