@@ -29,13 +29,23 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // rounds of the 2,048 blocks of 256 threads that the GPU holds at once.
 constexpr int64_t kLsSplitBlocks = 4096;
 
+// Point a context's stream at another stream for the launches in a scope.
+struct StreamSwap {
+  pcdn_ctx* c;
+  hipStream_t own;
+  StreamSwap(pcdn_ctx* c_, hipStream_t s) : c(c_), own(c_->stream) { c->stream = s; }
+  ~StreamSwap() { c->stream = own; }
+  StreamSwap(const StreamSwap&) = delete;
+  StreamSwap& operator=(const StreamSwap&) = delete;
+};
+
 // One solve inside the engine.
 struct EngineJob {
   SolveRun run;
   bool narrow = false;
   bool hybrid = false;           // single-workgroup segments between heavy bundles, own stream
   std::vector<Task> tasks;       // multi-kernel jobs: the outer iteration, partition included
-  hipEvent_t pre_done = nullptr;
+  hipEvent_t pre_done = nullptr;  // partition done (or, heavy-bundle jobs: chain done)
   bool fresh = true;             // no round yet: the executor waits for its set-up once
   bool active = false;
   int64_t id = 0;                // owner's handle
@@ -82,6 +92,8 @@ class Engine {
 
   ~Engine() {
     (void)hipSetDevice(device_);
+    for (hipStream_t st : chain_stream_)
+      if (st) (void)hipStreamSynchronize(st);
     for (hipStream_t st : narrow_stream_)
       if (st) (void)hipStreamSynchronize(st);
     if (wide_stream_) (void)hipStreamSynchronize(wide_stream_);
@@ -95,11 +107,20 @@ class Engine {
     for (hipStream_t st : narrow_stream_)
       if (st) (void)hipStreamDestroy(st);
     if (wide_stream_) (void)hipStreamDestroy(wide_stream_);
+    for (hipStream_t st : chain_stream_)
+      if (st) (void)hipStreamDestroy(st);
   }
 
   int init(int device) {
     device_ = device;
+    // The chain streams first: the runtime gives a new stream the hardware
+    // queue with the fewest streams, so streams created one after another
+    // tend to land on different queues, and launches on one queue run one
+    // after another whatever their streams (two heavy-bundle chains on one
+    // queue would take the sum of their times).
     if (hipSetDevice(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&chain_stream_[0], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&chain_stream_[1], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&narrow_stream_[0], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&narrow_stream_[1], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&wide_stream_, hipStreamNonBlocking) != hipSuccess ||
@@ -219,12 +240,14 @@ class Engine {
       }
       *err_ctx = nullptr;
     }
-    // single-workgroup jobs with heavy bundles, each on its own stream: the
+    // single-workgroup jobs with heavy bundles, each on a chain stream: the
     // segments between heavy bundles in one workgroup, each heavy bundle on
     // the multi-kernel path, in partition order.  They are enqueued before
     // the multi-kernel jobs' executor launches: their chains of dependent
     // launches are the round's longest, so they must not start behind the
-    // host time of the executor's enqueue.
+    // host time of the executor's enqueue.  A job's partition ran on its own
+    // stream (the host waited for it to read the heavy-bundle list); its
+    // stopping sweep follows there once its chain is done.
     if (any_hybrid) {
       std::vector<EngineJob*> hj;
       std::vector<int64_t> next;  // first bundle not yet enqueued, per job
@@ -247,6 +270,7 @@ class Engine {
           int64_t& t = next[i];
           if (k > nh || t >= nb) continue;
           *err_ctx = c;
+          StreamSwap on_chain(c, chain_stream_[i % 2]);  // run_bundle launches on c->stream
           const int64_t te =
               k < nh ? std::min<int64_t>(std::max<int64_t>(c->hheavy[1 + k], t), nb) : nb;
           if (te > t) HIPCHK(c, launch_narrow(c->loss, segment_narrow_args(c, o, P, t, te), c->stream));
@@ -261,9 +285,12 @@ class Engine {
         }
         if (!more) break;
       }
-      for (EngineJob* j : hj) {
+      for (size_t i = 0; i < hj.size(); ++i) {
+        EngineJob* j = hj[i];
         pcdn_ctx* c = j->run.c;
         *err_ctx = c;
+        HIPCHK(c, hipEventRecord(j->pre_done, chain_stream_[i % 2]));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, j->pre_done, 0));
         HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
@@ -325,6 +352,8 @@ class Engine {
 
  private:
   int device_ = 0;
+  // the heavy-bundle jobs' chains (job i of a round on chain i mod 2)
+  hipStream_t chain_stream_[2] = {nullptr, nullptr};
   hipStream_t narrow_stream_[2] = {nullptr, nullptr};  // single-workgroup launches, per loss
   hipStream_t wide_stream_ = nullptr;                  // the executor launches
   hipEvent_t fused_done_[2] = {nullptr, nullptr};
