@@ -113,17 +113,18 @@ class Engine {
 
   int init(int device) {
     device_ = device;
-    // The chain streams first: the runtime gives a new stream the hardware
-    // queue with the fewest streams, so streams created one after another
-    // tend to land on different queues, and launches on one queue run one
-    // after another whatever their streams (two heavy-bundle chains on one
-    // queue would take the sum of their times).
+    // The chain streams and the executor's stream first: the runtime gives a
+    // new stream the hardware queue with the fewest streams, so streams
+    // created one after another tend to land on different queues, and
+    // launches on one queue run one after another whatever their streams
+    // (two heavy-bundle chains on one queue would take the sum of their
+    // times, and executor launches queued behind a chain would wait for it).
     if (hipSetDevice(device) != hipSuccess ||
         hipStreamCreateWithFlags(&chain_stream_[0], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&chain_stream_[1], hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&wide_stream_, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&narrow_stream_[0], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&narrow_stream_[1], hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&wide_stream_, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&fused_done_[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&fused_done_[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&table_ready_, hipEventDisableTiming) != hipSuccess)
