@@ -1959,7 +1959,16 @@ void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, co
   out.push_back(t);
 }
 
-int sweep_grid(int64_t slots) { return grid_for(slots, kWavesPerBlock, 8192); }
+// One wavefront per slot, and at least 512 wavefronts: a bundle of few
+// features with long columns (the heavy bundles of the single-workgroup
+// schedule: 64 features, up to ~300 chunk work items) then needs one pass
+// over its chunks instead of several.  Which wavefront takes a chunk does
+// not change any sum (each chunk is summed by one wavefront; split columns
+// add their chunk partials in chunk order).
+constexpr int64_t kSweepMinWaves = 512;
+int sweep_grid(int64_t slots) {
+  return grid_for(slots > kSweepMinWaves ? slots : kSweepMinWaves, kWavesPerBlock, 8192);
+}
 
 hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s) {
   const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
