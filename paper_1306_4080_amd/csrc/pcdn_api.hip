@@ -66,6 +66,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
   dfree(c->part); dfree(c->ls_part);
   dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32); dfree(c->plid); dfree(c->pR);
+  dfree(c->pw);
   dfree(c->rp); dfree(c->rc); dfree(c->rv);
   dfree(c->act);
   drop_graph(c);
@@ -467,6 +468,7 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   na.poff = c->poff;
   na.pri = c->pri;
   na.pv = c->pv;
+  na.pw = c->pw;
   na.part = c->part;
   na.n = c->n;
   na.p = p_slots;
@@ -494,7 +496,8 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
 // local row ids where the single-workgroup kernel can use them.
 int permute_x(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
   HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
-                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->stream));
+                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->w, c->pw,
+                           c->stream));
   if (use_bundle_rows(c, P, p_slots))
     HIPCHK(c, launch_bundle_rows(c->poff, c->pri, p_slots, P, c->n, c->plid, c->pR, c->stream));
   return PCDN_OK;
@@ -1022,6 +1025,7 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
       4 * (p + 1), 32 * max_chunks, 4 * p,                 // identity-order descriptors, step bundle
       16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
+      8 * p,                                               // w in partition order
       2 * nnz, 4 * (p + 1),                                // bundle-local row ids
       8 * (int64_t)kLsGrid * (2 * kQMax + 2),              // line-search partials
       8 * p,                                               // active mask (shrinking)
@@ -1134,6 +1138,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->pri, nnz);
   ALLOC(c, c->pv, nnz);
   ALLOC(c, c->poff, p + 1);
+  ALLOC(c, c->pw, p);
   ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->plid, nnz);
   ALLOC(c, c->pR, p + 1);

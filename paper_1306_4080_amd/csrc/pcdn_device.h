@@ -276,6 +276,8 @@ struct NarrowArgs {
   const int64_t* poff; // p+1 partition-order offsets
   const int32_t* pri;
   const float* pv;
+  const double* pw;    // w in partition order, taken with the partition (a bundle's
+                       // features are updated only by that bundle)
   double2* part;       // global chunk partials when a bundle has > 32768 nonzeros
   int64_t n, p, P;
   int64_t t_begin, t_end;
@@ -365,12 +367,14 @@ hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int b
 hipError_t launch_gather(const double* const* src, double* dst, int count, hipStream_t s);
 // One workgroup per entry of the device table tab[0..count), all of one loss.
 hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipStream_t s);
-// X in partition order for the single-workgroup schedule (needs nnz < 2^31).
-// `chunks`/`cstart` are the chunk descriptors of the same slot order.
+// X in partition order for the single-workgroup schedule (needs nnz < 2^31),
+// and w in the same slot order (pw).  `chunks`/`cstart` are the chunk
+// descriptors of the same slot order.
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
-                          int32_t* pri, float* pv, hipStream_t s);
+                          int32_t* pri, float* pv, const double* w, double* pw,
+                          hipStream_t s);
 // Nonzeros of the features with d != 0 (slots 0..p of perm) into stats:
 // columns of <= chunk nonzeros count as fused, longer ones as split.
 hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,

@@ -96,6 +96,7 @@ struct pcdn_ctx {
   int32_t* off32 = nullptr;
   uint16_t* plid = nullptr;  // bundle-local row ids of X in partition order
   int32_t* pR = nullptr;     // distinct rows per bundle (or -1)
+  double* pw = nullptr;      // w in partition order (taken with the partition)
   // shrinking: active mask (1/0 per feature), reduction partials, and the
   // host's copy of the next iteration's active count and nonzeros
   double* act = nullptr;

@@ -1115,9 +1115,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     // bundle metadata into LDS; clear the per-slot sums
     for (int32_t s = tid; s <= ns; s += kNarrowBlock) L.off[s] = (int32_t)(na.poff[lo + s] - base);
     for (int32_t s = tid; s < ns; s += kNarrowBlock) {
-      const int32_t j = na.perm[lo + s];
-      L.feat[s] = j;
-      L.w[s] = na.w[j];
+      L.feat[s] = na.perm[lo + s];
+      L.w[s] = na.pw[lo + s];  // no load that waits on perm
       L.acc[s] = make_double2(0.0, 0.0);
     }
     if (tid == 0) {
@@ -1567,11 +1566,14 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int32_t* ri, const flo
 }
 
 // Column lengths in slot order (for the partition-order offsets).
-__global__ void k_slot_len(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* len) {
+// Column length of each slot, and w in slot order (pw[r] = w[perm[r]]).
+__global__ void k_slot_len(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* len,
+                           const double* w, double* pw) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r < p) {
     const int32_t j = perm[r];
     len[r] = (int32_t)(cp[j + 1] - cp[j]);
+    pw[r] = w[j];
   }
 }
 
@@ -2029,9 +2031,9 @@ hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s) {
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
-                          int32_t* pri, float* pv, hipStream_t s) {
+                          int32_t* pri, float* pv, const double* w, double* pw, hipStream_t s) {
   hipLaunchKernelGGL(k_slot_len, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm, cp,
-                     p, len_tmp);
+                     p, len_tmp, w, pw);
   hipError_t e = launch_scan(len_tmp, off32, p, scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_widen, dim3(grid_for(p + 1, kBlock, 1 << 30)), dim3(kBlock), 0, s, off32, p,
