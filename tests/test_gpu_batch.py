@@ -143,24 +143,29 @@ def test_batch_many_small_problems(pc):
 def test_executor_partition_with_multiblock_scans(pc):
     """Multi-kernel jobs run their partition as executor tasks, whose scans
     take several blocks once p > 4,096 (chunk counts) and p > 16,384 (the
-    radix histograms).  Two outer iterations of such jobs (a different
-    permutation would move w and F far beyond the bars) equal the solve
-    alone, and w equals the oracle's, which draws the same seeded
-    permutation, to the parity bar."""
+    radix histograms), also with shrinking (active features keyed first).
+    A few outer iterations of such jobs (a different permutation would move
+    w and F far beyond the bars) equal the solve alone, and w equals the
+    oracle's, which draws the same seeded permutation, to the parity bar."""
     data = [synth.sparse_random(120, 3000, 20000, 0.002),
             synth.sparse_random(121, 2000, 70000, 0.001),
-            synth.sparse_random(122, 1500, 3000, 0.004)]
+            synth.sparse_random(122, 1500, 3000, 0.004),
+            synth.sparse_random(123, 3000, 30000, 0.002)]
     solvers = [pc.Solver(device=0).load_data(d) for d in data]
     Ps = [d.p // 10 for d in data]
-    opts = dict(seed=3, schedule="wide", max_outer=2)
-    batched = pc.solve_batch([s.job(1.0, P, 1e-12, "lr", **opts) for s, P in zip(solvers, Ps)])
-    for s, d, P, b in zip(solvers, data, Ps, batched):
-        print(f"p={d.p}: status={b[0]} outer={b[2]['outer_iters']} F={b[2]['objective']:.15g}",
-              flush=True)
-        assert b[0] == 1 and b[2]["outer_iters"] == 2
-        _assert_same_run(b, s.solve(1.0, P, 1e-12, "lr", **opts))
-        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d), oracle.Params(loss="lr", C=1.0),
-                                  P=P, eps=1e-12, seed=3, max_outer=2)
+    # the last job shrinks: its keys put the active features first
+    opts = [dict(seed=3, schedule="wide", max_outer=m, shrink=sh)
+            for m, sh in ((2, False), (2, False), (2, False), (4, True))]
+    batched = pc.solve_batch([s.job(1.0, P, 1e-12, "lr", **o)
+                              for s, P, o in zip(solvers, Ps, opts)])
+    for s, d, P, o, b in zip(solvers, data, Ps, opts, batched):
+        print(f"p={d.p} shrink={o['shrink']}: status={b[0]} outer={b[2]['outer_iters']} "
+              f"F={b[2]['objective']:.15g}", flush=True)
+        assert b[0] == 1 and b[2]["outer_iters"] == o["max_outer"]
+        _assert_same_run(b, s.solve(1.0, P, 1e-12, "lr", **o))
+        w_o, io, _ = oracle.solve(oracle.Problem.from_data(d),
+                                  oracle.Params(loss="lr", C=1.0, shrink=o["shrink"]),
+                                  P=P, eps=1e-12, seed=3, max_outer=o["max_outer"])
         _assert_oracle(b, (w_o, io), True)
         np.testing.assert_allclose(b[1], w_o, rtol=RTOL, atol=RTOL * max(1.0, np.max(np.abs(w_o))))
     for s in solvers:
