@@ -94,18 +94,14 @@ class Engine {
     (void)hipSetDevice(device_);
     for (hipStream_t st : chain_stream_)
       if (st) (void)hipStreamSynchronize(st);
-    for (hipStream_t st : narrow_stream_)
-      if (st) (void)hipStreamSynchronize(st);
+    if (narrow_stream_) (void)hipStreamSynchronize(narrow_stream_);
     if (wide_stream_) (void)hipStreamSynchronize(wide_stream_);
     for (EngineJob* j : jobs_) drop_event(j);
-    for (hipEvent_t e : fused_done_)
-      if (e) (void)hipEventDestroy(e);
-    if (table_ready_) (void)hipEventDestroy(table_ready_);
+    if (fused_done_) (void)hipEventDestroy(fused_done_);
     narrow_tab_.release();
     exec_.release();
     gather_.release();
-    for (hipStream_t st : narrow_stream_)
-      if (st) (void)hipStreamDestroy(st);
+    if (narrow_stream_) (void)hipStreamDestroy(narrow_stream_);
     if (wide_stream_) (void)hipStreamDestroy(wide_stream_);
     for (hipStream_t st : chain_stream_)
       if (st) (void)hipStreamDestroy(st);
@@ -123,11 +119,8 @@ class Engine {
         hipStreamCreateWithFlags(&chain_stream_[0], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&chain_stream_[1], hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&wide_stream_, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&narrow_stream_[0], hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&narrow_stream_[1], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&fused_done_[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&fused_done_[1], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&table_ready_, hipEventDisableTiming) != hipSuccess)
+        hipStreamCreateWithFlags(&narrow_stream_, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&fused_done_, hipEventDisableTiming) != hipSuccess)
       return dev_fail("engine set-up", hipGetLastError());
     return PCDN_OK;
   }
@@ -177,25 +170,21 @@ class Engine {
     if (hipSetDevice(device_) != hipSuccess) return dev_fail("hipSetDevice", hipGetLastError());
     int rc = plan_stale_ ? build_plan() : PCDN_OK;
     if (rc) return rc;
-    // partitions, each on its job's stream; the single-workgroup jobs'
-    // table lists the logistic jobs first, then the SVM jobs (one launch each)
-    size_t m = 0, m_lr = 0;
+    // partitions, each on its job's stream (the multi-kernel jobs': executor
+    // tasks); the single-workgroup jobs' table, one launch for all of them
+    size_t m = 0;
     bool any_hybrid = false;
     for (EngineJob* j : jobs_) {
       any_hybrid = any_hybrid || j->hybrid;
-      if (j->narrow && !j->hybrid) {
-        ++m;
-        m_lr += j->run.loss == PCDN_LOSS_LOGISTIC ? 1 : 0;
-      }
+      if (j->narrow && !j->hybrid) ++m;
     }
     if (narrow_tab_.reserve(sizeof(NarrowArgs) * m) != hipSuccess)
       return dev_fail("table allocation", hipErrorOutOfMemory);
     NarrowArgs* htab = (NarrowArgs*)narrow_tab_.host;
-    size_t at[2] = {0, m_lr};
+    size_t at = 0;
     for (EngineJob* j : jobs_) {
       pcdn_ctx* c = j->run.c;
       *err_ctx = c;
-      const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
       count_outer(c, j->run.o, j->run.P, 1);
       if (!j->narrow) {  // partition and bundles in the executor launches
         if (j->fresh) {
@@ -212,29 +201,24 @@ class Engine {
         continue;
       }
       HIPCHK(c, hipEventRecord(j->pre_done, c->stream));
-      HIPCHK(c, hipStreamWaitEvent(narrow_stream_[g], j->pre_done, 0));
-      htab[at[g]++] = outer_narrow_args(c, j->run.o, j->run.P);
+      HIPCHK(c, hipStreamWaitEvent(narrow_stream_, j->pre_done, 0));
+      htab[at++] = outer_narrow_args(c, j->run.o, j->run.P);
     }
     *err_ctx = nullptr;
-    // single-workgroup jobs: one launch per loss, then each job's stopping sweep
+    // single-workgroup jobs: one launch (both losses), then each job's
+    // stopping sweep
     if (m > 0) {
-      const NarrowArgs* dtab = (const NarrowArgs*)narrow_tab_.dev;
       hipError_t e = hipMemcpyAsync(narrow_tab_.dev, htab, sizeof(NarrowArgs) * m,
-                                    hipMemcpyHostToDevice, narrow_stream_[0]);
-      if (e == hipSuccess) e = hipEventRecord(table_ready_, narrow_stream_[0]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(narrow_stream_[1], table_ready_, 0);
-      if (e == hipSuccess) e = launch_narrow_multi(kLogistic, dtab, (int)m_lr, narrow_stream_[0]);
+                                    hipMemcpyHostToDevice, narrow_stream_);
       if (e == hipSuccess)
-        e = launch_narrow_multi(kL2Svm, dtab + m_lr, (int)(m - m_lr), narrow_stream_[1]);
-      if (e == hipSuccess) e = hipEventRecord(fused_done_[0], narrow_stream_[0]);
-      if (e == hipSuccess) e = hipEventRecord(fused_done_[1], narrow_stream_[1]);
+        e = launch_narrow_multi((const NarrowArgs*)narrow_tab_.dev, (int)m, narrow_stream_);
+      if (e == hipSuccess) e = hipEventRecord(fused_done_, narrow_stream_);
       if (e != hipSuccess) return dev_fail("multi-problem launch", e);
       for (EngineJob* j : jobs_) {
         if (!j->narrow || j->hybrid) continue;
         pcdn_ctx* c = j->run.c;
         *err_ctx = c;
-        const int g = j->run.loss == PCDN_LOSS_LOGISTIC ? 0 : 1;
-        HIPCHK(c, hipStreamWaitEvent(c->stream, fused_done_[g], 0));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, fused_done_, 0));
         HIPCHK(c, hipGraphLaunch(c->graph_post, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, 8 * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
@@ -316,8 +300,7 @@ class Engine {
       if (e != hipSuccess) return dev_fail("gather", e);
     }
     // the staging tables and every pinned result are reused next round
-    hipError_t e = hipStreamSynchronize(narrow_stream_[0]);
-    if (e == hipSuccess) e = hipStreamSynchronize(narrow_stream_[1]);
+    hipError_t e = hipStreamSynchronize(narrow_stream_);
     if (e == hipSuccess) e = hipStreamSynchronize(wide_stream_);
     if (e != hipSuccess) return dev_fail("round", e);
     for (size_t k = 0; k < plan_jobs_.size(); ++k) {
@@ -355,10 +338,9 @@ class Engine {
   int device_ = 0;
   // the heavy-bundle jobs' chains (job i of a round on chain i mod 2)
   hipStream_t chain_stream_[2] = {nullptr, nullptr};
-  hipStream_t narrow_stream_[2] = {nullptr, nullptr};  // single-workgroup launches, per loss
+  hipStream_t narrow_stream_ = nullptr;                // the single-workgroup jobs' launch
   hipStream_t wide_stream_ = nullptr;                  // the executor launches
-  hipEvent_t fused_done_[2] = {nullptr, nullptr};
-  hipEvent_t table_ready_ = nullptr;
+  hipEvent_t fused_done_ = nullptr;
   std::vector<EngineJob*> jobs_;
   Staging narrow_tab_, exec_, gather_;
   bool plan_stale_ = true;

@@ -365,8 +365,9 @@ hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int b
                        hipStream_t s);
 // dst[i] = *src[i] for i < count (device pointers).
 hipError_t launch_gather(const double* const* src, double* dst, int count, hipStream_t s);
-// One workgroup per entry of the device table tab[0..count), all of one loss.
-hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipStream_t s);
+// One workgroup per entry of the device table tab[0..count) (each entry
+// with its own loss).
+hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s);
 // X in partition order for the single-workgroup schedule (needs nnz < 2^31),
 // and w in the same slot order (pw).  `chunks`/`cstart` are the chunk
 // descriptors of the same slot order.

@@ -1534,15 +1534,17 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow(NarrowArgs na) {
   narrow_body<LOSS>(na, L);
 }
 
-// Independent problems of one loss in one launch: workgroup b runs the
-// bundles of problem tab[b] (its own data and state).
-template <int LOSS>
+// Independent problems in one launch: workgroup b runs the bundles of
+// problem tab[b] (its own data, state and loss).
 __global__ __launch_bounds__(kNarrowBlock) void k_narrow_multi(const NarrowArgs* __restrict__ tab) {
   __shared__ NarrowLds L;
   // a private copy: the kernel stores to global memory, so fields read
   // through the table could otherwise be re-read after stores
   const NarrowArgs na = tab[blockIdx.x];
-  narrow_body<LOSS>(na, L);
+  if (na.loss == kLogistic)
+    narrow_body<kLogistic>(na, L);
+  else
+    narrow_body<kL2Svm>(na, L);
 }
 
 // Copy X into partition order: the nonzeros of slot r land at
@@ -2125,12 +2127,9 @@ hipError_t launch_gather(const double* const* src, double* dst, int count, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_narrow_multi(int loss, const NarrowArgs* tab, int count, hipStream_t s) {
+hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (loss == kLogistic)
-    hipLaunchKernelGGL(k_narrow_multi<kLogistic>, dim3(count), dim3(kNarrowBlock), 0, s, tab);
-  else
-    hipLaunchKernelGGL(k_narrow_multi<kL2Svm>, dim3(count), dim3(kNarrowBlock), 0, s, tab);
+  hipLaunchKernelGGL(k_narrow_multi, dim3(count), dim3(kNarrowBlock), 0, s, tab);
   return hipGetLastError();
 }
 
