@@ -16,8 +16,11 @@
  *    pcdn_last_error() describes it; the context stays usable unless the code
  *    is PCDN_E_DEVICE.
  *  - No exception crosses the ABI.  A context is not thread-safe: use one per
- *    host thread.  All work runs on the context's HIP stream; every entry point
- *    that returns host data synchronises that stream before returning.
+ *    host thread.  Work runs on the context's HIP stream, except that the
+ *    multi-problem drivers (and pcdn_solve / pcdn_iterate on the heavy-bundle
+ *    path of the automatic schedule) also launch on streams of their own,
+ *    ordered after the context stream's earlier work; every entry point that
+ *    returns host data synchronises all of them before returning.
  *  - Host arrays are borrowed for the duration of the call only.  The library
  *    owns every device buffer it allocates and frees them in pcdn_destroy().
  *  - Layouts: X is compressed sparse column (CSC).  Column j holds rows
@@ -194,9 +197,12 @@ typedef struct {
  * arithmetic; Algorithm 3 per problem).  The jobs advance in rounds of one
  * outer iteration each: the bundles of every job on the single-workgroup
  * schedule run in one launch, one workgroup per job (their partition and
- * stopping sweeps are replayed graphs on each context's stream); jobs on the
- * multi-kernel schedule replay their own outer-iteration graph on their
- * context's stream in the same round.  A job leaves the batch when its
+ * stopping sweeps are replayed graphs on each context's stream); a job whose
+ * bundles include heavy ones (automatic schedule) runs its segments and
+ * heavy bundles as a chain of launches on a stream of the batch; jobs on the
+ * multi-kernel schedule run their whole outer iteration (partition included)
+ * as tasks of lock-step multi-problem launches, launch s running task s of
+ * every such job with the grid of its own launch.  A job leaves the batch when its
  * stopping rule holds or at its max_outer.  Arguments are checked for every
  * job before any work: an invalid job makes the call return that job's error
  * code (its context holds the message) with nothing run.  Otherwise returns
