@@ -322,7 +322,7 @@ typedef struct {
  *     so far ran WIDE bundles): chunks of 64, 256 and 512 nonzeros.
  * Each pilot is the solve itself through the batch engine (the path
  * pcdn_solve_batch takes), from the start pcdn_solve would use, to the
- * target eps (graphs and task tables built before the clock starts), abandoned as soon as
+ * target eps (graphs and task lists built before the clock starts), abandoned as soon as
  * it has run longer than the fastest finished one.  The fastest finished
  * pilot wins (if none finishes within max_outer, the one with the largest
  * decrease of the stopping norm per second); P, schedule and chunk are the
