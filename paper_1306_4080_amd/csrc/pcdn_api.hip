@@ -59,11 +59,13 @@ void dfree(T*& ptr) {
 void free_data(pcdn_ctx* c) {
   dfree(c->cp); dfree(c->ri); dfree(c->v); dfree(c->y);
   dfree(c->w); dfree(c->cache); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
-  dfree(c->rowflag);
   dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
   dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
   dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
+  dfree(c->rr); dfree(c->islot); dfree(c->br_row); dfree(c->br_slot); dfree(c->br_val);
+  dfree(c->bt_row); dfree(c->bt_slot); dfree(c->bt_val); dfree(c->br_hist);
+  dfree(c->u_cnt); dfree(c->u_row); dfree(c->u_dtx);
   dfree(c->part); dfree(c->ls_part);
   dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32); dfree(c->plid); dfree(c->pR);
   dfree(c->pw);
@@ -77,6 +79,8 @@ void free_data(pcdn_ctx* c) {
 
 // Average nonzeros per bundle up to which one workgroup runs the bundles.
 constexpr double kNarrowMaxBundleNnz = 8192.0;
+// Nonzero positions are int32 in the partition and bundle-row orders.
+constexpr int64_t kMaxNnz = ((int64_t)1 << 31) - ((int64_t)1 << 16);
 
 int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r) {
   r->seed = o ? o->seed : 0;
@@ -229,76 +233,69 @@ int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) 
   return PCDN_OK;
 }
 
-// Second half: line-search partials, then decision + apply.  With the first
-// half, four kernel boundaries are the only synchronisation of a bundle.
-LsArgs ls_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
-               bool clip) {
-  LsArgs l{};
-  l.p_active = clip ? c->scal + 5 : nullptr;
-  l.dtx = c->dtx;
-  l.cache = c->cache;
-  l.y = c->y;
-  l.n = c->n;
-  l.w = c->w;
-  l.perm = perm;
-  l.slot_lo = lo;
-  l.slot_hi = hi;
-  l.d = c->d;
-  l.dterm = c->dterm;
-  l.part = c->ls_part;
-  l.stats = c->stats;
-  l.beta = o.beta;
-  l.Q = o.max_ls;
-  l.ra = o.ra();
-  l.rb = o.rb();
-  l.C = c->C;
-  l.sigma = o.sigma;
-  return l;
-}
-
-ApplyArgs apply_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
-                     bool clip) {
-  ApplyArgs ap{};
-  ap.p_active = clip ? c->scal + 5 : nullptr;
-  ap.dtx = c->dtx;
-  ap.cache = c->cache;
-  ap.y = c->y;
-  ap.n = c->n;
-  ap.w = c->w;
-  ap.perm = perm;
-  ap.slot_lo = lo;
-  ap.slot_hi = hi;
-  ap.d = c->d;
-  ap.part = c->ls_part;
-  ap.ls_blocks = ls_grid(c->n);
-  ap.st = c->st;
-  ap.stats = c->stats;
-  ap.C = c->C;
-  ap.sigma = o.sigma;
-  ap.beta = o.beta;
-  ap.Q = o.max_ls;
-  ap.max_ls = o.max_ls;
-  return ap;
+// Second half: d^T x by row with the first line-search candidates, then the
+// decision and the update.  With the first half, four kernel boundaries
+// are the only synchronisation of a bundle.
+RowsArgs rows_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
+                   bool clip, int64_t P) {
+  RowsArgs r{};
+  r.br_row = c->br_row;
+  r.br_slot = c->br_slot;
+  r.br_val = c->br_val;
+  r.poff = c->poff;
+  r.slot_lo = lo;
+  r.slot_hi = hi;
+  r.d = c->d;
+  r.dterm = c->dterm;
+  r.w = c->w;
+  r.perm = perm;
+  r.cache = c->cache;
+  r.y = c->y;
+  r.u_cnt = c->u_cnt;
+  r.u_row = c->u_row;
+  r.u_dtx = c->u_dtx;
+  r.part = c->ls_part;
+  r.G = rows_grid((double)c->nnz * (double)P / (double)c->p);
+  r.st = c->st;
+  r.stats = c->stats;
+  r.beta = o.beta;
+  r.ra = o.ra();
+  r.rb = o.rb();
+  r.C = c->C;
+  r.sigma = o.sigma;
+  r.Q = o.max_ls;
+  r.max_ls = o.max_ls;
+  r.p_active = clip ? c->scal + 5 : nullptr;
+  return r;
 }
 
 int bundle_ls_apply(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
-                    bool clip) {
+                    bool clip, int64_t P) {
+  const RowsArgs r = rows_args(c, o, perm, lo, hi, clip, P);
   {
     ProfScope ps(c, 2);
-    HIPCHK(c, launch_linesearch(c->loss, ls_args(c, o, perm, lo, hi, clip), c->stream));
+    HIPCHK(c, launch_rows_dtx(c->loss, r, c->stream));
   }
   {
     ProfScope ps(c, 3);
-    HIPCHK(c, launch_apply(c->loss, apply_args(c, o, perm, lo, hi, clip), c->stream));
+    HIPCHK(c, launch_rows_apply(c->loss, r, c->stream));
   }
   return PCDN_OK;
 }
 
 int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi,
-               bool clip) {
+               bool clip, int64_t P) {
   int rc = bundle_sweep(c, o, lo, hi, clip);
   if (rc) return rc;
-  return bundle_ls_apply(c, o, perm, lo, hi, clip);
+  return bundle_ls_apply(c, o, perm, lo, hi, clip, P);
+}
+
+int build_bundle_rows(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
+  HIPCHK(c, launch_bundle_row_order(perm, c->p, p_slots, P, c->cp, c->rr, c->rc, c->rv, c->nnz,
+                                    c->islot, c->nch, c->off32, c->scan_tmp, c->poff, c->br_row,
+                                    c->br_slot, c->br_val, c->bt_row, c->bt_slot, c->bt_val,
+                                    c->br_hist, c->stream));
+  return PCDN_OK;
 }
 
 // ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0);
@@ -463,7 +460,6 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   na.sw = sweep_args(c, o);
   na.cache = c->cache;
   na.w = c->w;
-  na.rowflag = c->rowflag;
   na.perm = perm;
   na.poff = c->poff;
   na.pri = c->pri;
@@ -484,6 +480,7 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   na.dtx_copy = dtx_copy;
   na.loss = c->loss;
   na.chunk = o.chunk;
+  na.xrow = c->xrow;
   if (use_bundle_rows(c, P, p_slots)) {
     na.plid = c->plid;
     na.pR = c->pR;
@@ -525,11 +522,15 @@ int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it,
   if (rc) return rc;
   HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, o.chunk, c->nch, c->cstart, c->chunks,
                           c->scan_tmp, c->stream));
-  if (!use_narrow(c, o, P)) return PCDN_OK;
+  if (!use_narrow(c, o, P)) return build_bundle_rows(c, c->idx0, c->p, P);
   rc = permute_x(c, c->idx0, c->p, P);
   if (rc) return rc;
-  if (heavy_list && use_hybrid(c, o, P))
+  if (heavy_list && use_hybrid(c, o, P)) {
     HIPCHK(c, launch_heavy_bundles(c->poff, c->p, P, kHeavyNnz, kHeavyCap, c->heavy, c->stream));
+    // the heavy bundles run on the multi-kernel path
+    rc = build_bundle_rows(c, c->idx0, c->p, P);
+    if (rc) return rc;
+  }
   return PCDN_OK;
 }
 
@@ -557,7 +558,7 @@ int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
   }
   for (int64_t t = 0; t < nb; ++t) {
     const int64_t lo = t * P, hi = std::min(lo + P, c->p);
-    int rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
+    int rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink, P);
     if (rc) return rc;
   }
   return PCDN_OK;
@@ -589,7 +590,7 @@ int enqueue_bundles_hybrid(pcdn_ctx* c, const Opts& o, int64_t P) {
     t = te;
     if (k < nh && te < nb) {
       const int64_t lo = te * P, hi = std::min(lo + P, c->p);
-      const int rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
+      const int rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink, P);
       if (rc) return rc;
       t = te + 1;
     }
@@ -624,8 +625,10 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     t.gx = gx;
     return t;
   };
+  bundle_row_tasks(c->loss, c->idx0, c->p, c->p, P, c->cp, c->rr, c->rc, c->rv, c->nnz, c->islot,
+                   c->nch, c->off32, c->scan_tmp, c->poff, c->br_row, c->br_slot, c->br_val,
+                   c->bt_row, c->bt_slot, c->bt_val, c->br_hist, out);
   const int64_t nb = (c->p + P - 1) / P;
-  const int lsx = ls_grid(c->n), lsy = (o.max_ls + kQGroup - 1) / kQGroup;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t lo = b * P, hi = std::min(lo + P, c->p);
     Task t = task(kTaskSweep, sweep_grid(hi - lo), 0);
@@ -633,18 +636,11 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     out.push_back(t);
     t.kind = kTaskSplit;
     if (has_split_columns(c, o.chunk)) out.push_back(t);
-    // the first candidate group, then the others (which stop at once when
-    // the first group holds the accepted step: the common case)
-    t = task(kTaskLinesearch, lsx, lsx);
-    t.u.ls = ls_args(c, o, c->idx0, lo, hi, o.shrink);
+    const RowsArgs r = rows_args(c, o, c->idx0, lo, hi, o.shrink, P);
+    t = task(kTaskRowsDtx, r.G, 0);
+    t.u.rw = r;
     out.push_back(t);
-    if (lsy > 1) {
-      t.kind = kTaskLinesearchRest;
-      t.nblk = lsx * (lsy - 1);
-      out.push_back(t);
-    }
-    t = task(kTaskApply, apply_grid(c->n, hi - lo), 0);
-    t.u.ap = apply_args(c, o, c->idx0, lo, hi, o.shrink);
+    t.kind = kTaskRowsApply;
     out.push_back(t);
   }
   Task t = task(kTaskScatterCount, scatter_count_grid(c->p), 0);
@@ -1016,20 +1012,23 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
   const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   const int64_t hist_m = radix_hist_ints(p);
   const int64_t part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
+  const int64_t br_m = br_hist_ints(nnz);
   const int64_t sizes[] = {
       8 * (p + 1), 4 * nnz, 4 * nnz, n,                    // X, y
-      8 * p, 8 * n, 8 * n, 8 * n, 8 * p, 4 * n,            // w, cache, d^T x, scratch, flags
+      8 * p, 8 * n, 8 * n, 8 * n, 8 * p,                   // w, cache, d^T x, scratch
       8 * p, 8 * p, 8 * p, 8 * p,                          // g, h, d, Delta terms
       4 * p, 4 * p, 4 * p, 4 * p, 4 * hist_m,              // sort keys and payloads, histogram
-      4 * (std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)) + 1),
+      4 * (std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1),
       4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
       4 * (p + 1), 32 * max_chunks, 4 * p,                 // identity-order descriptors, step bundle
       16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
       8 * p,                                               // w in partition order
       2 * nnz, 4 * (p + 1),                                // bundle-local row ids
-      8 * (int64_t)kLsGrid * (2 * kQMax + 2),              // line-search partials
+      8 * (int64_t)kRowsGridMax * (2 * kQMax + 2),         // line-search partials
       8 * p,                                               // active mask (shrinking)
-      8 * (n + 1), 4 * nnz, 4 * nnz};                      // CSR copy
+      8 * (n + 1), 4 * nnz, 4 * nnz, 4 * nnz,              // CSR copy
+      4 * p, 12 * nnz, 12 * nnz, 4 * br_m,                 // bundle-row order, sort buffers
+      4 * ((nnz + kRangeW - 1) / kRangeW + 1), 12 * (nnz + kRangeW)};  // touched rows
   int64_t total = 64 * 1024;
   for (const int64_t b : sizes) total += (std::max<int64_t>(b, 1) + 4095) / 4096 * 4096;
   return total;
@@ -1048,7 +1047,8 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
     return fail(c, PCDN_E_ARG, "null array");
   if (ptr_kind != 0 && ptr_kind != 1) return fail(c, PCDN_E_ARG, "ptr_kind must be 0 or 1");
   const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
-  if (max_chunks >= ((int64_t)1 << 31) - 1) return fail(c, PCDN_E_ARG, "matrix too large");
+  if (max_chunks >= ((int64_t)1 << 31) - 1 || nnz > kMaxNnz)
+    return fail(c, PCDN_E_ARG, "matrix too large (at most 2^31 - 2^16 nonzeros)");
   HIPCHK(c, hipSetDevice(c->device));
 
   // host view for validation (device input is copied down once)
@@ -1116,7 +1116,6 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->dtx, n);
   ALLOC(c, c->tmp_n, n);
   ALLOC(c, c->tmp_p, p);
-  ALLOC(c, c->rowflag, n);
   ALLOC(c, c->g, p);
   ALLOC(c, c->h, p);
   ALLOC(c, c->d, p);
@@ -1126,7 +1125,9 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->idx0, p);
   ALLOC(c, c->idx1, p);
   ALLOC(c, c->hist, hist_m);
-  ALLOC(c, c->scan_tmp, std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)) + 1);
+  const int64_t br_m = br_hist_ints(nnz);
+  ALLOC(c, c->scan_tmp,
+        std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1);
   ALLOC(c, c->nch, p);
   ALLOC(c, c->cstart, p + 1);
   ALLOC(c, c->chunks, max_chunks);
@@ -1142,28 +1143,47 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->plid, nnz);
   ALLOC(c, c->pR, p + 1);
-  ALLOC(c, c->ls_part, (size_t)kLsGrid * (2 * kQMax + 2));
+  ALLOC(c, c->ls_part, (size_t)kRowsGridMax * (2 * kQMax + 2));
   ALLOC(c, c->act, p);
   ALLOC(c, c->rp, n + 1);
+  ALLOC(c, c->rr, nnz);
   ALLOC(c, c->rc, nnz);
   ALLOC(c, c->rv, nnz);
+  ALLOC(c, c->islot, p);
+  ALLOC(c, c->br_row, nnz);
+  ALLOC(c, c->br_slot, nnz);
+  ALLOC(c, c->br_val, nnz);
+  ALLOC(c, c->bt_row, nnz);
+  ALLOC(c, c->bt_slot, nnz);
+  ALLOC(c, c->bt_val, nnz);
+  ALLOC(c, c->br_hist, br_m);
+  ALLOC(c, c->u_cnt, (nnz + kRangeW - 1) / kRangeW + 1);
+  ALLOC(c, c->u_row, nnz + kRangeW);
+  ALLOC(c, c->u_dtx, nnz + kRangeW);
   // CSR copy (rows in order, columns ascending within a row) for the
-  // deterministic margin computation of warm starts
+  // deterministic margin computation of warm starts and the bundle-row
+  // order; the largest row 1-norm for the fixed-point d^T x
   {
     std::vector<int64_t> hrp(n + 1, 0);
     for (int64_t k = 0; k < nnz; ++k) ++hrp[Hri[k] + 1];
     for (int64_t i = 0; i < n; ++i) hrp[i + 1] += hrp[i];
     std::vector<int64_t> next(hrp.begin(), hrp.end() - 1);
-    std::vector<int32_t> hrc(nnz);
+    std::vector<int32_t> hrr(nnz), hrc(nnz);
     std::vector<float> hrv(nnz);
+    std::vector<double> l1(n, 0.0);
     for (int64_t j = 0; j < p; ++j)
       for (int64_t k = Hcp[j]; k < Hcp[j + 1]; ++k) {
         const int64_t at = next[Hri[k]]++;
+        hrr[at] = Hri[k];
         hrc[at] = (int32_t)j;
         hrv[at] = Hv[k];
+        l1[Hri[k]] += std::fabs((double)Hv[k]);
       }
+    c->xrow = 0.0;
+    for (int64_t i = 0; i < n; ++i) c->xrow = std::max(c->xrow, l1[i]);
     HIPCHK(c, hipMemcpy(c->rp, hrp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     if (nnz) {
+      HIPCHK(c, hipMemcpy(c->rr, hrr.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
       HIPCHK(c, hipMemcpy(c->rc, hrc.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
       HIPCHK(c, hipMemcpy(c->rv, hrv.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
     }
@@ -1176,7 +1196,6 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   }
   HIPCHK(c, hipMemcpyAsync(c->y, y, n, kind, c->stream));
   HIPCHK(c, hipMemsetAsync(c->dtx, 0, n * sizeof(double), c->stream));
-  HIPCHK(c, hipMemsetAsync(c->rowflag, 0, n * sizeof(unsigned), c->stream));
   HIPCHK(c, launch_chunks(nullptr, c->cp, p, kChunk, c->nch, c->id_cstart, c->id_chunks,
                           c->scan_tmp, c->stream));
   int32_t total = 0;
@@ -1266,13 +1285,15 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
     rc = launch_narrow_bundles(c, o, c->step_perm, P, P, 0, 1, dtx ? c->tmp_n : nullptr);
     if (rc) return rc;
   } else {
-    rc = bundle_sweep(c, o, 0, P, false);
+    rc = build_bundle_rows(c, c->step_perm, P, P);
     if (rc) return rc;
-    if (dtx)
-      HIPCHK(c, hipMemcpyAsync(c->tmp_n, c->dtx, c->n * sizeof(double), hipMemcpyDeviceToDevice,
-                               c->stream));
-    rc = bundle_ls_apply(c, o, c->step_perm, 0, P, false);
+    rc = run_bundle(c, o, c->step_perm, 0, P, false, P);
     if (rc) return rc;
+    if (dtx) {
+      HIPCHK(c, launch_fill(c->tmp_n, 0.0, c->n, c->stream));
+      HIPCHK(c, launch_rows_scatter(rows_args(c, o, c->step_perm, 0, P, false, P), c->tmp_n,
+                                    c->stream));
+    }
   }
   HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, nullptr, o.chunk, c->stats,
                                  c->stream));

@@ -24,11 +24,6 @@ namespace {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Blocks of the later line-search candidate groups, summed over one bundle
-// of every multi-kernel job, from which they run as tasks of their own: two
-// rounds of the 2,048 blocks of 256 threads that the GPU holds at once.
-constexpr int64_t kLsSplitBlocks = 4096;
-
 // Point a context's stream at another stream for the launches in a scope.
 struct StreamSwap {
   pcdn_ctx* c;
@@ -262,7 +257,7 @@ class Engine {
           t = te;
           if (k < nh && te < nb) {
             const int64_t lo = te * P, hi = std::min(lo + P, c->p);
-            rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink);
+            rc = run_bundle(c, o, c->idx0, lo, hi, o.shrink, P);
             if (rc) return rc;
             t = te + 1;
           }
@@ -377,19 +372,6 @@ class Engine {
     }
     plan_stale_ = false;
     if (plan_jobs_.empty()) return PCDN_OK;
-    // The later line-search candidate groups get tasks of their own (which
-    // stop early when the first group holds the accepted step) only when
-    // the blocks they save exceed what the GPU holds at once; otherwise the
-    // extra lock-step launch per bundle costs more latency than it saves,
-    // and the first-group task takes the whole grid as in a launch of its own.
-    int64_t rest_blocks = 0;
-    for (EngineJob* j : plan_jobs_)
-      for (const Task& t : j->tasks)
-        if (t.kind == kTaskLinesearchRest) {
-          rest_blocks += t.nblk;
-          break;
-        }
-    const bool split_ls = rest_blocks >= kLsSplitBlocks;
     const size_t task_bytes = align_up(sizeof(Task) * n_tasks);
     const size_t first_bytes = align_up(sizeof(int32_t) * (n_tasks + L));
     const size_t src_bytes = align_up(3 * sizeof(double*) * plan_jobs_.size());
@@ -409,14 +391,7 @@ class Engine {
       hfirst[nf++] = 0;
       for (EngineJob* j : plan_jobs_) {
         if (st >= j->tasks.size()) continue;
-        Task t = j->tasks[st];
-        if (!split_ls) {
-          if (t.kind == kTaskLinesearch && st + 1 < j->tasks.size() &&
-              j->tasks[st + 1].kind == kTaskLinesearchRest)
-            t.nblk += j->tasks[st + 1].nblk;
-          else if (t.kind == kTaskLinesearchRest)
-            t.nblk = 0;  // no block maps to an empty task
-        }
+        const Task& t = j->tasks[st];
         htasks[nt++] = t;
         blk += t.nblk;
         hfirst[nf++] = blk;

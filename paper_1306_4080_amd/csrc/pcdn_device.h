@@ -2,8 +2,9 @@
 //
 // Layout in HBM (per context):
 //   X       : col_ptr int64[p+1], row_idx int32[nnz], val fp32[nnz], y int8[n]
-//   state   : w fp64[p], cache fp64[n] (e^{w^T x_i} or b_i), dtx fp64[n]
-//             (kept all-zero between inner iterations)
+//   state   : w fp64[p], cache fp64[n] (e^{w^T x_i} or b_i), dtx 8 bytes[n]
+//             (the single-workgroup kernel's fixed-point d^T x when a bundle
+//             has too many rows for LDS; all zero between inner iterations)
 //   bundle  : perm int32[p] (slot -> feature), per-slot g, h, d, dterm fp64
 //   chunks  : every feature owns ceil(nnz_j / kChunk) >= 1 work chunks.  For
 //             the slot order of one outer iteration, Chunk descriptors list
@@ -30,7 +31,6 @@ constexpr int kChunk = 128;    // nonzeros per wavefront work item (default)
 constexpr int kChunkMin = 64;  // smallest selectable (descriptor storage is sized for it)
 constexpr int kQMax = 32;      // line-search candidates evaluated per pass
 constexpr int kQGroup = 4;     // candidates per line-search thread (grid y covers the rest)
-constexpr int kLsGrid = 256;   // blocks of the line-search kernel (at most)
 constexpr int kSumGrid = 256;  // blocks of the first reduction level
 constexpr int kLogistic = 0;
 constexpr int kL2Svm = 1;
@@ -110,41 +110,76 @@ struct SweepArgs {
   const double* thr;
 };
 
-struct LsArgs {
-  const double* dtx;
-  const double* cache;
-  const int8_t* y;
-  int64_t n;
-  const double* w;
-  const int32_t* perm;        // slot -> feature
-  int64_t slot_lo, slot_hi;
-  const double* d;
+// Multi-kernel bundle after the sweep: the bundle's nonzeros in row order
+// (bundle-row order: bundles ascending, rows ascending inside a bundle,
+// columns ascending inside a row) give d^T x_i of each touched row as one
+// fixed-order sum, fused with the first line-search candidates; the apply
+// then updates the touched rows.  The nonzeros of bundle t are split into
+// ranges of kRangeW; range r owns the rows whose first nonzero lies in it
+// and lists them (row, d^T x_i) at u_row/u_dtx[r kRangeW ...], u_cnt[r] of
+// them, rows with d^T x_i = 0 left out.
+constexpr int kRangeW = 256;
+constexpr int kRowsGridMax = 2048;  // blocks of the d^T x / line-search launch (at most)
+struct RowsArgs {
+  const int32_t* br_row;     // bundle-row order: row, slot and value of each nonzero
+  const int32_t* br_slot;
+  const float* br_val;
+  const int64_t* poff;       // slot -> first nonzero of the slot's bundle-row block
+  int64_t slot_lo, slot_hi;  // this bundle
+  const double* d;           // per-slot outputs of the sweep
   const double* dterm;
-  double* part;        // [value][block]: Q loss sums, Q l1 sums, Delta, touched rows
-  Stats* stats;
-  double beta;
-  int Q;
-  const double* p_active;  // nullable: slots clipped to the first *p_active
-  double ra, rb;           // regulariser, as in SweepArgs
-  double C, sigma;         // the Armijo test (read by the executor's later candidate groups)
-};
-
-struct ApplyArgs {
-  double* dtx;
+  double* w;
+  const int32_t* perm;       // slot -> feature
   double* cache;
   const int8_t* y;
-  int64_t n;
-  double* w;
-  const int32_t* perm;        // slot -> feature
-  int64_t slot_lo, slot_hi;
-  const double* d;
-  const double* part;  // line-search partials
-  int ls_blocks;       // blocks that wrote them
+  int32_t* u_cnt;
+  int32_t* u_row;
+  double* u_dtx;
+  double* part;              // [v * G + block]: Q loss sums, Q regulariser sums, Delta, touched rows
+  int32_t G;                 // blocks of the d^T x / line-search launch
   StepState* st;
   Stats* stats;
-  double C, sigma, beta;
+  double beta, ra, rb, C, sigma;
   int Q, max_ls;
-  const double* p_active;  // nullable: slots clipped to the first *p_active
+  const double* p_active;    // nullable: slots clipped to the first *p_active
+};
+
+// One pass of the stable counting sort that puts X's nonzeros into
+// bundle-row order: the key of a nonzero is its bundle (slot / P; a nonzero
+// of a feature outside the order, slot -1, takes bundle nb), 8 bits per pass,
+// least significant first.  Pass 0 reads the CSR copy (rows ascending,
+// columns ascending in a row) with columns mapped through islot; later
+// passes read the previous pass's output.
+constexpr int kBrRounds = 8;
+struct BrArgs {
+  const int32_t* islot;      // pass 0: feature -> slot (-1: not in the order); else null
+  const int32_t* srow;
+  const int32_t* scol;       // pass 0: columns; later passes: slots
+  const float* sval;
+  int32_t* drow;
+  int32_t* dslot;
+  float* dval;
+  int32_t* hist;             // [256][ntiles] digit counts, scanned between the passes
+  int64_t m, ntiles, P;
+  int32_t shift, nb;
+};
+struct SlotLenArgs {         // column length (and w) in slot order
+  const int32_t* perm;
+  const int64_t* cp;
+  int64_t p;
+  int32_t* len;
+  const double* w;           // nullable: no copy of w
+  double* pw;
+};
+struct WidenArgs {
+  const int32_t* in;
+  int64_t m;
+  int64_t* out;
+};
+struct IslotArgs {           // islot[perm[r]] = r for r < p
+  const int32_t* perm;
+  int64_t p;
+  int32_t* islot;
 };
 
 struct ScatterCountArgs {
@@ -226,9 +261,8 @@ enum TaskKind : int32_t {
   kTaskSweepStop,
   kTaskSplit,
   kTaskSplitStop,
-  kTaskLinesearch,
-  kTaskLinesearchRest,
-  kTaskApply,
+  kTaskRowsDtx,
+  kTaskRowsApply,
   kTaskScatterCount,
   kTaskSumPartial,
   kTaskSumFinal,
@@ -243,6 +277,11 @@ enum TaskKind : int32_t {
   kTaskScanAdd,
   kTaskChunkCount,
   kTaskChunkFill,
+  kTaskSlotLen,
+  kTaskWiden,
+  kTaskIslot,
+  kTaskBrHist,
+  kTaskBrScatter,
 };
 struct Task {
   int32_t kind;
@@ -251,8 +290,11 @@ struct Task {
   int32_t gx;
   union {
     SweepArgs sw;
-    LsArgs ls;
-    ApplyArgs ap;
+    RowsArgs rw;
+    BrArgs br;
+    SlotLenArgs sl;
+    WidenArgs wd;
+    IslotArgs is;
     ScatterCountArgs sc;
     SumArgs sum;
     StopSumArgs stop;
@@ -271,7 +313,6 @@ struct NarrowArgs {
   SweepArgs sw;        // ri/v unused; cache, y, g, h, d, dtx, C, gamma, nu used
   double* cache;       // the same arrays as sw.cache / sw.w, writable
   double* w;
-  unsigned* rowflag;   // per-row "touched" flags, all zero between bundles
   const int32_t* perm;
   const int64_t* poff; // p+1 partition-order offsets
   const int32_t* pri;
@@ -294,6 +335,10 @@ struct NarrowArgs {
   const uint16_t* plid;
   const int32_t* pR;
   int32_t chunk;       // the multi-kernel chunk length (for the scatter counters)
+  // max_i sum_j |x_ij| over X: with D = max_j |d_j| of a bundle, D * xrow
+  // bounds every partial sum of d^T x_i, which sets the bundle's fixed-point
+  // scale
+  double xrow;
 };
 
 // Largest number of distinct rows of a bundle whose d^T x the
@@ -345,12 +390,38 @@ hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int3
 int sweep_grid(int64_t slots);
 hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
 hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
-int ls_grid(int64_t n);
-int apply_grid(int64_t n, int64_t slots);
 int scatter_count_grid(int64_t p);
 int sum_grid(int64_t m);
-hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s);
-hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s);
+// Blocks of the d^T x / line-search launch for bundles of about `nnz_bundle`
+// nonzeros (RowsArgs::G).
+int rows_grid(double nnz_bundle);
+// d^T x of the bundle's touched rows and the first kQGroup line-search
+// candidates (a.G blocks); then the Armijo decision and the update.
+hipError_t launch_rows_dtx(int loss, const RowsArgs& a, hipStream_t s);
+hipError_t launch_rows_apply(int loss, const RowsArgs& a, hipStream_t s);
+// X's nonzeros in bundle-row order for bundles of P over the order perm
+// (p_slots slots; with p_slots < p the other features' nonzeros go last):
+// poff (p_slots + 1) and the br arrays; tmp arrays and hist / scan_tmp as
+// working storage (br_hist_ints(nnz) and scan_tmp_ints of it).
+int br_passes(int64_t p_slots, int64_t P);
+int64_t br_hist_ints(int64_t nnz);
+hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
+                                   const int64_t* cp, const int32_t* rr, const int32_t* rc,
+                                   const float* rv, int64_t nnz, int32_t* islot, int32_t* len_tmp,
+                                   int32_t* off32, int32_t* scan_tmp, int64_t* poff,
+                                   int32_t* br_row, int32_t* br_slot, float* br_val,
+                                   int32_t* bt_row, int32_t* bt_slot, float* bt_val,
+                                   int32_t* hist, hipStream_t s);
+// The same as executor tasks (appended to out).
+void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
+                      const int64_t* cp, const int32_t* rr, const int32_t* rc, const float* rv,
+                      int64_t nnz, int32_t* islot, int32_t* len_tmp, int32_t* off32,
+                      int32_t* scan_tmp, int64_t* poff, int32_t* br_row, int32_t* br_slot,
+                      float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val,
+                      int32_t* hist, std::vector<Task>& out);
+// dense[i] = d^T x_i of the touched rows listed by the last d^T x launch of
+// the bundle [a.slot_lo, a.slot_hi) (dense must be zero elsewhere).
+hipError_t launch_rows_scatter(const RowsArgs& a, double* dense, hipStream_t s);
 hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
 // The partition of one outer iteration (launch_perm_keys, launch_radix_sort
 // and launch_chunks on the same buffers) as executor tasks, appended to out;

@@ -63,10 +63,9 @@ struct pcdn_ctx {
   bool has_state = false;
   double* w = nullptr;
   double* cache = nullptr;
-  double* dtx = nullptr;
+  double* dtx = nullptr;  // single-workgroup kernel's fixed-point d^T x (bundles of many rows)
   double* tmp_n = nullptr;
   double* tmp_p = nullptr;
-  unsigned* rowflag = nullptr;
   double* g = nullptr;
   double* h = nullptr;
   double* d = nullptr;
@@ -102,10 +101,28 @@ struct pcdn_ctx {
   double* act = nullptr;
   double* stop_part = nullptr;
   double p_active_h = 0.0, nnz_active_h = 0.0;
-  // X in CSR order (warm-start margins)
+  // X in CSR order (warm-start margins, and the source of the bundle-row
+  // order): row pointers, and per nonzero its row, column and value
   int64_t* rp = nullptr;
+  int32_t* rr = nullptr;
   int32_t* rc = nullptr;
   float* rv = nullptr;
+  // multi-kernel schedule: X in bundle-row order for the current order
+  // (br_*, with bt_* the sort's other buffer and br_hist its digit counts),
+  // feature -> slot, and the touched rows of the current bundle per range
+  int32_t* islot = nullptr;
+  int32_t* br_row = nullptr;
+  int32_t* br_slot = nullptr;
+  float* br_val = nullptr;
+  int32_t* bt_row = nullptr;
+  int32_t* bt_slot = nullptr;
+  float* bt_val = nullptr;
+  int32_t* br_hist = nullptr;
+  int32_t* u_cnt = nullptr;
+  int32_t* u_row = nullptr;
+  double* u_dtx = nullptr;
+  // max_i sum_j |x_ij| (the single-workgroup kernel's fixed-point scale)
+  double xrow = 0.0;
 
   // reductions and small device records
   double* ls_part = nullptr;
@@ -219,8 +236,12 @@ bool use_hybrid(const pcdn_ctx* c, const Opts& o, int64_t P);
 // outer iteration's partition.
 pcdn::NarrowArgs segment_narrow_args(pcdn_ctx* c, const Opts& o, int64_t P, int64_t t_begin,
                                      int64_t t_end);
-// The multi-kernel bundle on slots [lo, hi) of the current partition.
-int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi, bool clip);
+// The multi-kernel bundle on slots [lo, hi) of the order perm (chunk
+// descriptors and bundle-row order of that order already built).
+int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int64_t hi, bool clip,
+               int64_t P);
+// X in bundle-row order for bundles of P over the first p_slots slots of perm.
+int build_bundle_rows(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P);
 // Arguments of the single-workgroup kernel for bundles [t_begin, t_end).
 pcdn::NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm,
                                   int64_t p_slots, int64_t P, int64_t t_begin, int64_t t_end,

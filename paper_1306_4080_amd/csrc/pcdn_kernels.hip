@@ -2,10 +2,11 @@
 //
 // The work is sparse gather/scatter at well under one flop per byte, so it is
 // bound by memory bandwidth and latency, not by the matrix cores: no MFMA here.
-// Every reduction that decides anything (g_j, h_j, the line-search sums, the
-// stopping norm) is FP64 and deterministic for a fixed launch shape; the only
-// atomics are the FP64 adds that build d^T x_i, whose order can differ in the
-// last bit between runs.
+// Every sum is FP64 and deterministic for a fixed launch shape: g_j, h_j,
+// the line-search sums and the stopping norm are fixed-order tree sums, and
+// d^T x_i is a fixed-order row sum (multi-kernel schedule) or an integer
+// fixed-point sum, exact in any order (single workgroup), so a solve gives
+// the same bits on every run, alone or beside other problems.
 #include <cstring>
 #include <utility>
 
@@ -515,10 +516,9 @@ __global__ __launch_bounds__(kBlock) void k_chunk_fill(const int32_t* perm, cons
 // ---------------------------------------------------------------------------
 // gradient / Hessian sweep over a bundle's columns, one wavefront per chunk.
 // Bundle mode: per-feature g, h, the direction d (eq. (5)) and its Delta
-// term; a feature whose column fits one chunk also scatters d_j x^j into
-// d^T x right away (the second read of x^j, Sec. 3.1, served from L2).  Split
-// columns only leave their partial sums; k_split finishes them after the
-// kernel boundary.  Stopping mode: |grad^S_j F| per feature, no direction.
+// term.  Split columns only leave their partial sums; k_split finishes them
+// after the kernel boundary.  Stopping mode: |grad^S_j F| per feature, no
+// direction.  (d^T x, the second read of x, is formed by row afterwards.)
 // ---------------------------------------------------------------------------
 constexpr int kUnroll = 4;
 
@@ -545,14 +545,6 @@ __device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi,
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       if (row[u] >= 0) grad_hess_term<LOSS>(cv[u], yv[u], (double)xv[u], gs, hs);
-  }
-}
-
-__device__ inline void scatter_range(const SweepArgs& a, int64_t klo, int64_t khi, int lane,
-                                     double dj) {
-  for (int64_t k = klo + lane; k < khi; k += kWave) {
-    const int32_t row = a.ri[k];
-    unsafeAtomicAdd(&a.dtx[row], dj * (double)a.v[k]);
   }
 }
 
@@ -620,8 +612,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
       if (lane == 0) a.part[c] = make_double2(gs, hs);
       continue;
     }
-    const double dj = finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0);
-    if (!STOP && dj != 0.0) scatter_range(a, ch.klo, khi, lane, dj);
+    (void)finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0);
   }
 }
 
@@ -630,9 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   sweep_body<LOSS, STOP>(a, blockIdx.x, gridDim.x);
 }
 
-// Split columns: every wavefront of a split feature sums all of its chunk
-// partials in chunk order (so all of them agree bit for bit), finishes the
-// feature, and scatters its own chunk.
+// Split columns: the first wavefront of a split feature sums its chunk
+// partials in chunk order and finishes the feature.
 template <int LOSS, bool STOP>
 __device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
@@ -644,7 +634,7 @@ __device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int6
   const int32_t c_hi = a.cstart[hi];
   for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
     const Chunk ch = a.chunks[c];
-    if (ch.nch == 1) continue;
+    if (ch.nch == 1 || c != ch.c0) continue;
     double gs = 0.0, hs = 0.0;
     for (int32_t q = lane; q < ch.nch; q += kWave) {
       const double2 pq = a.part[ch.c0 + q];
@@ -653,8 +643,7 @@ __device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int6
     }
     gs = wave_sum(gs);
     hs = wave_sum(hs);
-    const double dj = finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0 && c == ch.c0);
-    if (!STOP && dj != 0.0) scatter_range(a, ch.klo, ch.klo + ch.len, lane, dj);
+    (void)finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0);
   }
 }
 
@@ -692,68 +681,190 @@ __global__ __launch_bounds__(kBlock) void k_scatter_count(ScatterCountArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// P-dimensional line search (Algorithm 4 with eq. (10)): per block, partial
-// sums over the samples of the loss change for every candidate q < Q (the
-// per-sample argument is d^T x_i scaled by beta once per rejected candidate,
-// as Algorithm 4 scales its retained d^T x_i), of the l1 change of the bundle
-// coordinates, and of Delta.  Layout: part[v * gridDim.x + block].
+// d^T x by row, the line search (Algorithm 4 with eq. (10)) and the update,
+// over the bundle's nonzeros in bundle-row order (see RowsArgs).
+//
+// d^T x_i = sum_{j in B} d_j x_ij is formed for each touched row by one
+// wavefront in a fixed order (a segmented wavefront scan over the row's
+// nonzeros in column order, rounds of 64 added in order), so it does not
+// depend on timing; no atomics.  The same pass evaluates the first kQGroup
+// line-search candidates on the row (the per-sample argument is d^T x_i
+// scaled by beta once per rejected candidate, as Algorithm 4 scales its
+// retained d^T x_i) and lists the row for the apply.  Per-block partials
+// land at part[v * G + block] and are summed in block order by every block
+// of the apply, which takes the Armijo decision (eq. (6)) identically.
 // ---------------------------------------------------------------------------
-// bx, by: block of the (G x ceil(Q / kQGroup)) launch grid.
+// Segmented inclusive scan of one value (the step sequence of seg_scan).
+template <int CTRL, int ROW_MASK>
+__device__ inline void seg_scan1_step(double& g, int32_t key) {
+  const int32_t k2 = __builtin_amdgcn_update_dpp(-1, key, CTRL, ROW_MASK, 0xf, false);
+  const double g2 = dpp_f64<CTRL, ROW_MASK, 0xf>(g);
+  if (k2 == key) g += g2;
+}
+
+__device__ inline void seg_scan1(double& g, int32_t key) {
+  seg_scan1_step<0x111, 0xf>(g, key);
+  seg_scan1_step<0x112, 0xf>(g, key);
+  seg_scan1_step<0x114, 0xf>(g, key);
+  seg_scan1_step<0x118, 0xf>(g, key);
+  seg_scan1_step<0x142, 0xa>(g, key);
+  seg_scan1_step<0x143, 0xc>(g, key);
+}
+
+// Orders this wavefront's LDS accesses (the queue below is wave-private).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Loss changes of one row for candidates 0..nq-1 (argument scaled by beta
+// once per candidate).
 template <int LOSS>
-__device__ __forceinline__ void linesearch_body(const LsArgs& a, int bx, int by, int G) {
-  __shared__ double red[kWavesPerBlock][kQGroup];
-  __shared__ double lds4[kWavesPerBlock];
-  // no active feature in this bundle (shrinking): the apply skips it too
-  if (clipped_hi(a.slot_hi, a.p_active) <= a.slot_lo) return;
+__device__ inline void row_ls_terms(double c, int yi, double dl, double beta, int nq,
+                                    double (&acc)[kQGroup]) {
+  double s = dl;
+#pragma unroll
+  for (int q = 0; q < kQGroup; ++q) {
+    if (q < nq) {
+      acc[q] += loss_delta<LOSS>(c, yi, s);
+      s *= beta;
+    }
+  }
+}
+
+// n <= 64 queued rows (lane i takes queue entry i): list them for the apply
+// and add their line-search terms.
+template <int LOSS>
+__device__ inline void rows_flush(const RowsArgs& a, const int32_t* qrow, const double* qdtx,
+                                  int n, int64_t ubase, int nq, double (&acc)[kQGroup],
+                                  double& touched) {
+  const int lane = lane_id();
+  if (lane < n) {
+    const int32_t row = qrow[lane];
+    const double dl = qdtx[lane];
+    a.u_row[ubase + lane] = row;
+    a.u_dtx[ubase + lane] = dl;
+    const double c = a.cache[row];
+    const int yi = a.y[row];
+    touched += 1.0;
+    row_ls_terms<LOSS>(c, yi, dl, a.beta, nq, acc);
+  }
+}
+
+// Block bx of the G-block launch: wavefront w = bx * 4 + wave takes ranges
+// w, w + 4G, ... of the bundle's nonzeros.
+template <int LOSS>
+__device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
+  __shared__ int32_t qrow[kWavesPerBlock][2 * kWave];
+  __shared__ double qdtx[kWavesPerBlock][2 * kWave];
+  __shared__ double red[kWavesPerBlock][kQGroup + 1];
+  const int64_t hi_act = clipped_hi(a.slot_hi, a.p_active);
+  if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: the apply skips it too
   const int lane = lane_id(), wv = wave_in_block();
-  const int q_lo = by * kQGroup;
-  const int nq = a.Q - q_lo < kQGroup ? a.Q - q_lo : kQGroup;
-  double beta_lo = 1.0;
-  for (int t = 0; t < q_lo; ++t) beta_lo *= a.beta;
+  const int G = a.G;
+  const int nq = a.Q < kQGroup ? a.Q : kQGroup;
+  const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
+  const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
+  const int64_t nwaves = (int64_t)G * kWavesPerBlock;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int32_t* qr = qrow[wv];
+  double* qd = qdtx[wv];
   double acc[kQGroup];
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
   double touched = 0.0;
-  for (int64_t i = bx * (int64_t)kBlock + threadIdx.x; i < a.n;
-       i += (int64_t)G * kBlock) {
-    const double dl = a.dtx[i];
-    if (dl == 0.0) continue;
-    touched += 1.0;
-    const double c = a.cache[i];
-    const int yi = a.y[i];
-    // d^T x_i scaled by beta once per rejected candidate before q_lo
-    double s = dl;
-    for (int t = 0; t < q_lo; ++t) s *= a.beta;
-#pragma unroll
-    for (int q = 0; q < kQGroup; ++q) {
-      if (q < nq) {
-        acc[q] += loss_delta<LOSS>(c, yi, s);
-        s *= a.beta;
+  for (int64_t r = (int64_t)bx * kWavesPerBlock + wv; r < nr; r += nwaves) {
+    const int64_t rb = e0 + r * kRangeW;
+    const int64_t re = rb + kRangeW < e1 ? rb + kRangeW : e1;
+    // rows owned by this range: those whose first nonzero lies in [rb, re);
+    // the range's first row may have started earlier (skip), its last row
+    // may continue past re (tail)
+    const int32_t skip = rb > e0 ? a.br_row[rb - 1] : -1;
+    int32_t tail = a.br_row[re - 1];
+    if (tail == skip) tail = -1;
+    int qn = 0;            // rows queued in LDS
+    int32_t listed = 0;    // rows listed for this range
+    int32_t crow = -1;     // row carried into the next round
+    double cval = 0.0;
+    for (int64_t s0 = rb; s0 < re || crow >= 0; s0 += kWave) {
+      const int64_t k = s0 + lane;
+      const bool in = k < e1;
+      const int32_t row = in ? a.br_row[k] : -1;
+      const bool owned = in && row != skip && (k < re || row == tail);
+      double t = 0.0;
+      if (owned) {
+        const int32_t sl = a.br_slot[k];
+        if (sl >= a.slot_lo && sl < hi_act) t = a.d[sl] * (double)a.br_val[k];
+      }
+      const int32_t key = owned ? row : -1;
+      seg_scan1(t, key);
+      if (crow >= 0 && key == crow) t += cval;
+      // the row ends at this nonzero unless the next one is of the same row
+      int32_t nxt = next_lane_key(key);
+      if (lane == kWave - 1) nxt = k + 1 < e1 ? a.br_row[k + 1] : -2;
+      const bool ends = owned && nxt != row;
+      const int32_t row63 = __builtin_amdgcn_readlane(key, kWave - 1);
+      const bool open63 = __builtin_amdgcn_readlane((int)(owned && !ends), kWave - 1) != 0;
+      const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
+      const unsigned lo63 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(tb & 0xffffffffull), kWave - 1);
+      const unsigned hi63 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(tb >> 32), kWave - 1);
+      crow = open63 ? row63 : -1;
+      cval = open63 ? __longlong_as_double((long long)(((unsigned long long)hi63 << 32) | lo63)) : 0.0;
+      // queue the finished rows with d^T x_i != 0 (a zero changes nothing)
+      const bool done = ends && t != 0.0;
+      const uint64_t m = __ballot(done);
+      if (done) {
+        const int pos = qn + __popcll(m & lt_mask);
+        qr[pos] = row;
+        qd[pos] = t;
+      }
+      qn += __popcll(m);
+      if (qn >= kWave) {
+        wave_lds_sync();
+        rows_flush<LOSS>(a, qr, qd, kWave, r * kRangeW + listed, nq, acc, touched);
+        listed += kWave;
+        qn -= kWave;
+        wave_lds_sync();
+        if (lane < qn) {
+          qr[lane] = qr[kWave + lane];
+          qd[lane] = qd[kWave + lane];
+        }
       }
     }
+    wave_lds_sync();
+    rows_flush<LOSS>(a, qr, qd, qn, r * kRangeW + listed, nq, acc, touched);
+    listed += qn;
+    if (lane == 0) a.u_cnt[r] = listed;
+    wave_lds_sync();
   }
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) {
     const double v = wave_sum(acc[q]);
     if (lane == 0) red[wv][q] = v;
   }
+  {
+    const double v = wave_sum(touched);
+    if (lane == 0) red[wv][kQGroup] = v;
+  }
   __syncthreads();
   if (threadIdx.x < nq)
-    a.part[(int64_t)(q_lo + threadIdx.x) * G + bx] =
+    a.part[(int64_t)threadIdx.x * G + bx] =
         ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+  if (threadIdx.x == kQGroup)
+    a.part[(int64_t)(2 * a.Q + 1) * G + bx] =
+        ((red[0][kQGroup] + red[1][kQGroup]) + red[2][kQGroup]) + red[3][kQGroup];
   __syncthreads();
-  // l1 change of the bundle coordinates for these candidates
+  // Delta and the regulariser change of the bundle coordinates
   double del = 0.0;
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
-  const int64_t Pt = clipped_hi(a.slot_hi, a.p_active) - a.slot_lo;
-  for (int64_t r = bx * (int64_t)kBlock + threadIdx.x; r < Pt;
-       r += (int64_t)G * kBlock) {
+  const int64_t Pt = hi_act - a.slot_lo;
+  for (int64_t r = (int64_t)bx * kBlock + threadIdx.x; r < Pt; r += (int64_t)G * kBlock) {
     const int64_t slot = a.slot_lo + r;
     const double wj = a.w[a.perm[slot]];
     const double dj = a.d[slot];
     del += a.dterm[slot];
-    double al = beta_lo;
+    double al = 1.0;
 #pragma unroll
     for (int q = 0; q < kQGroup; ++q) {
       if (q < nq) {
@@ -767,23 +878,22 @@ __device__ __forceinline__ void linesearch_body(const LsArgs& a, int bx, int by,
     const double v = wave_sum(acc[q]);
     if (lane == 0) red[wv][q] = v;
   }
+  {
+    const double v = wave_sum(del);
+    if (lane == 0) red[wv][kQGroup] = v;
+  }
   __syncthreads();
   if (threadIdx.x < nq)
-    a.part[(int64_t)(a.Q + q_lo + threadIdx.x) * G + bx] =
+    a.part[(int64_t)(a.Q + threadIdx.x) * G + bx] =
         ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-  if (by == 0) {
-    const double dsum = block_sum(del, lds4);
-    const double tsum = block_sum(touched, lds4);
-    if (threadIdx.x == 0) {
-      a.part[(int64_t)(2 * a.Q) * G + bx] = dsum;
-      a.part[(int64_t)(2 * a.Q + 1) * G + bx] = tsum;
-    }
-  }
+  if (threadIdx.x == kQGroup)
+    a.part[(int64_t)(2 * a.Q) * G + bx] =
+        ((red[0][kQGroup] + red[1][kQGroup]) + red[2][kQGroup]) + red[3][kQGroup];
 }
 
 template <int LOSS>
-__global__ __launch_bounds__(kBlock) void k_linesearch(LsArgs a) {
-  linesearch_body<LOSS>(a, blockIdx.x, blockIdx.y, gridDim.x);
+__global__ __launch_bounds__(kBlock) void k_rows_dtx(RowsArgs a) {
+  rows_dtx_body<LOSS>(a, blockIdx.x);
 }
 
 // Sum of row v of the line-search partials, same order in every block.
@@ -793,46 +903,59 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
   return block_sum(x, lds4);
 }
 
-// The executor runs the line search in two tasks: the first candidate
-// group (grid row 0, which also writes Delta and the touched count), then
-// the other rows.  A block of the second task first takes the Armijo
-// decision over the first group's candidates exactly as the apply does; if
-// one of them passes, the apply reads no other candidate, and the block
-// returns without computing its group.  by >= 1 is the block's grid row.
+// Candidates q >= kQGroup (none of the first group passed: rare), in one
+// block: one pass over the listed rows per candidate, in Algorithm 4's
+// order, until the test passes.  Returns the accepted q (or -1) with its
+// step and objective change.
 template <int LOSS>
-__device__ __forceinline__ void linesearch_rest_body(const LsArgs& a, int bx, int by, int G) {
-  __shared__ double lds4[kWavesPerBlock];
-  if (clipped_hi(a.slot_hi, a.p_active) <= a.slot_lo) return;
-  double Dq = ls_total(a.part, 2 * a.Q, G, lds4);
-  const int nq0 = a.Q < kQGroup ? a.Q : kQGroup;
-  for (int q = 0; q < nq0; ++q) {
-    const double sL = ls_total(a.part, q, G, lds4);
-    const double l1 = ls_total(a.part, a.Q + q, G, lds4);
-    if (l1 + a.C * sL <= a.sigma * Dq) return;
+__device__ inline int rows_more_candidates(const RowsArgs& a, int64_t nr, int64_t hi_act,
+                                           double& Dq, double& al, double& dF, double* lds4) {
+  const int lane = lane_id(), wv = wave_in_block();
+  for (int q = kQGroup; q < a.Q; ++q) {
+    double sl = 0.0;
+    for (int64_t r = wv; r < nr; r += kWavesPerBlock) {
+      const int32_t cnt = a.u_cnt[r];
+      for (int32_t i = lane; i < cnt; i += kWave) {
+        const int32_t row = a.u_row[r * kRangeW + i];
+        double s = a.u_dtx[r * kRangeW + i];
+        for (int t = 0; t < q; ++t) s *= a.beta;
+        sl += loss_delta<LOSS>(a.cache[row], (int)a.y[row], s);
+      }
+    }
+    double l1 = 0.0;
+    for (int64_t slot = a.slot_lo + threadIdx.x; slot < hi_act; slot += kBlock)
+      l1 += reg_change(a.w[a.perm[slot]], al * a.d[slot], a.ra, a.rb);
+    const double sL = block_sum(sl, lds4);
+    const double L1 = block_sum(l1, lds4);
+    const double f = L1 + a.C * sL;
+    if (f <= a.sigma * Dq) {
+      dF = f;
+      return q;
+    }
     Dq *= a.beta;
+    al *= a.beta;
   }
-  linesearch_body<LOSS>(a, bx, by, G);
+  return -1;
 }
 
-// ---------------------------------------------------------------------------
-// Armijo decision and accept.  Every block takes the decision itself from the
-// line-search partials (increasing q, eq. (6)'s test with Delta scaled by beta
-// per rejection, as in Algorithm 4), identically, so no block waits for
-// another.  Then w_B += alpha d_B and the retained quantities of the touched
-// rows are updated (e^{w^T x} multiplicatively, Algorithm 4; b_i -= y_i alpha
-// d^T x_i), and d^T x is cleared for the next inner iteration.
-// ---------------------------------------------------------------------------
+// Armijo decision and accept: every block takes the decision from the
+// partials identically, so no block waits for another; then w_B += alpha
+// d_B and the retained quantities of the listed rows are updated (e^{w^T x}
+// multiplicatively, Algorithm 4; b_i -= y_i alpha d^T x_i).  When no
+// candidate of the first group passes, block 0 alone tests the later ones
+// and applies the step.
 template <int LOSS>
-__device__ __forceinline__ void apply_body(const ApplyArgs& a, int64_t bid, int64_t nblk) {
+__device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
-  const int64_t hi_active = clipped_hi(a.slot_hi, a.p_active);
-  if (hi_active <= a.slot_lo) return;  // no active feature in this bundle: nothing ran
-  const double Delta = ls_total(a.part, 2 * a.Q, a.ls_blocks, lds4);
+  const int64_t hi_act = clipped_hi(a.slot_hi, a.p_active);
+  if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: nothing ran
+  const int nq = a.Q < kQGroup ? a.Q : kQGroup;
+  const double Delta = ls_total(a.part, 2 * a.Q, a.G, lds4);
   double Dq = Delta, al = 1.0, dF = 0.0;
   int q_acc = -1;
-  for (int q = 0; q < a.Q; ++q) {
-    const double sL = ls_total(a.part, q, a.ls_blocks, lds4);
-    const double l1 = ls_total(a.part, a.Q + q, a.ls_blocks, lds4);
+  for (int q = 0; q < nq; ++q) {
+    const double sL = ls_total(a.part, q, a.G, lds4);
+    const double l1 = ls_total(a.part, a.Q + q, a.G, lds4);
     const double f = l1 + a.C * sL;
     if (f <= a.sigma * Dq) {
       q_acc = q;
@@ -842,7 +965,15 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, int64_t bid, int6
     Dq *= a.beta;
     al *= a.beta;
   }
-  const double touched = ls_total(a.part, 2 * a.Q + 1, a.ls_blocks, lds4);
+  const double touched = ls_total(a.part, 2 * a.Q + 1, a.G, lds4);
+  const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
+  const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
+  bool alone = false;
+  if (q_acc < 0 && a.Q > nq) {
+    if (bid != 0) return;
+    alone = true;
+    q_acc = rows_more_candidates<LOSS>(a, nr, hi_act, Dq, al, dF, lds4);
+  }
   if (bid == 0 && threadIdx.x == 0) {
     a.st->q = q_acc;
     a.st->alpha = q_acc >= 0 ? al : 0.0;
@@ -853,29 +984,133 @@ __device__ __forceinline__ void apply_body(const ApplyArgs& a, int64_t bid, int6
     if (q_acc < 0) atomicAdd(&a.stats->ls_fail, 1ull);
     atomicAdd(&a.stats->rows_touched, (unsigned long long)touched);
   }
-  const int64_t tid = bid * kBlock + threadIdx.x;
-  const int64_t nthr = nblk * kBlock;
-  for (int64_t i = tid; i < a.n; i += nthr) {
-    const double dl = a.dtx[i];
-    if (dl == 0.0) continue;
-    if (q_acc >= 0) {
-      double s = dl;
+  if (q_acc < 0) return;
+  const int lane = lane_id();
+  const int64_t wave = alone ? wave_in_block() : (bid * kBlock + threadIdx.x) / kWave;
+  const int64_t nwaves = alone ? kWavesPerBlock : nblk * kWavesPerBlock;
+  for (int64_t r = wave; r < nr; r += nwaves) {
+    const int32_t cnt = a.u_cnt[r];
+    for (int32_t i = lane; i < cnt; i += kWave) {
+      const int32_t row = a.u_row[r * kRangeW + i];
+      double s = a.u_dtx[r * kRangeW + i];
       for (int t = 0; t < q_acc; ++t) s *= a.beta;
       if (LOSS == kLogistic)
-        a.cache[i] *= exp(s);
+        a.cache[row] *= exp(s);
       else
-        a.cache[i] -= a.y[i] > 0 ? s : -s;
+        a.cache[row] -= a.y[row] > 0 ? s : -s;
     }
-    a.dtx[i] = 0.0;
   }
-  if (q_acc >= 0) {
-    for (int64_t r = a.slot_lo + tid; r < hi_active; r += nthr) a.w[a.perm[r]] += al * a.d[r];
-  }
+  const int64_t tid = alone ? threadIdx.x : bid * kBlock + threadIdx.x;
+  const int64_t nthr = alone ? kBlock : nblk * kBlock;
+  for (int64_t r = a.slot_lo + tid; r < hi_act; r += nthr) a.w[a.perm[r]] += al * a.d[r];
 }
 
 template <int LOSS>
-__global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
-  apply_body<LOSS>(a, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kBlock) void k_rows_apply(RowsArgs a) {
+  rows_apply_body<LOSS>(a, blockIdx.x, gridDim.x);
+}
+
+// d^T x of the listed rows into a dense vector (pcdn_step's read-back).
+__global__ __launch_bounds__(kBlock) void k_rows_scatter(RowsArgs a, double* dense) {
+  const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
+  const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
+  for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
+    const int32_t cnt = a.u_cnt[r];
+    for (int32_t i = threadIdx.x; i < cnt; i += kBlock)
+      dense[a.u_row[r * kRangeW + i]] = a.u_dtx[r * kRangeW + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bundle-row order: islot, column lengths and offsets in slot order, then a
+// stable counting sort of the CSR copy by bundle (8-bit digits, tiles of
+// kBrTile nonzeros; stability inside a round from wavefront peer masks built
+// with ballots, across waves and rounds from per-digit running offsets)
+// ---------------------------------------------------------------------------
+constexpr int kBrTile = kSortThreads * kBrRounds;
+
+__device__ __forceinline__ void islot_body(const IslotArgs& a, int64_t bid) {
+  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
+  if (r < a.p) a.islot[a.perm[r]] = (int32_t)r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_islot(IslotArgs a) { islot_body(a, blockIdx.x); }
+
+__global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__device__ __forceinline__ uint32_t br_digit(const BrArgs& a, int64_t k, int32_t& slot) {
+  const int32_t c = a.scol[k];
+  slot = a.islot ? a.islot[c] : c;
+  const uint32_t b = slot >= 0 ? (uint32_t)slot / (uint32_t)a.P : (uint32_t)a.nb;
+  return (b >> a.shift) & 255u;
+}
+
+__device__ __forceinline__ void br_hist_body(const BrArgs& a, int64_t bid) {
+  __shared__ int32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = bid * kBrTile;
+  for (int r = 0; r < kBrRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < a.m) {
+      int32_t slot;
+      atomicAdd(&cnt[br_digit(a, i, slot)], 1);
+    }
+  }
+  __syncthreads();
+  a.hist[(int64_t)threadIdx.x * a.ntiles + bid] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_br_hist(BrArgs a) { br_hist_body(a, blockIdx.x); }
+
+__device__ __forceinline__ void br_scatter_body(const BrArgs& a, int64_t bid) {
+  __shared__ int32_t base_off[256];
+  __shared__ int32_t wcnt[kWavesPerBlock][256];
+  base_off[threadIdx.x] = a.hist[(int64_t)threadIdx.x * a.ntiles + bid];
+  const int lane = lane_id(), wv = wave_in_block();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile = bid * kBrTile;
+  for (int r = 0; r < kBrRounds; ++r) {
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t i = tile + r * kSortThreads + threadIdx.x;
+    const bool valid = i < a.m;
+    int32_t slot = 0;
+    const uint32_t dig = valid ? br_digit(a, i, slot) : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const int rank = __popcll(peers & lt_mask);
+    const bool leader = valid && ((peers & lt_mask) == 0);
+    if (leader) wcnt[wv][dig] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int32_t pos = base_off[dig] + rank;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w][dig];
+      a.drow[pos] = a.srow[i];
+      a.dslot[pos] = slot;
+      a.dval[pos] = a.sval[i];
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][threadIdx.x];
+    base_off[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_br_scatter(BrArgs a) {
+  br_scatter_body(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -889,20 +1124,22 @@ __global__ __launch_bounds__(kBlock) void k_apply(ApplyArgs a) {
 //    segmented wavefront scan (keys = slot) sums g_j, h_j; slots that cross a
 //    64-nonzero chunk are completed from LDS partials in chunk order, so the
 //    sums are deterministic;
-//  - the thread that first touches a row in the scatter lists the row, its
-//    retained quantity and label, already in its registers, in LDS; the line
-//    search and the apply then run over that list;
+//  - d^T x is accumulated in 64-bit fixed point: each term d_j x_ij is
+//    rounded to a multiple of 2^-e, where 2^-e is set by the bundle's
+//    largest |d_j| and the largest row 1-norm of X so that no partial sum can
+//    overflow, and integer additions give the same sum in any order: d^T x
+//    does not depend on timing;
 //  - with bundle-local row ids (k_bundle_rows, at most kNarrowLidCap distinct
-//    rows) d^T x is accumulated in LDS by local id and the first toucher is
-//    found with an LDS bit per id: the scatter, the line search and the
-//    apply touch global memory only to write the updated retained
-//    quantities;
-//  - otherwise d^T x is built in global memory with L2 atomics, the first
-//    toucher is found with a per-row flag in global memory, and d^T x of the
-//    listed rows is read back;
+//    rows) d^T x is accumulated in LDS by local id, and the thread that first
+//    touches a row (an LDS bit per id) records the row, its retained
+//    quantity and label, already in its registers, at the row's local id;
+//    the line search and the apply then run over the local ids in order and
+//    touch global memory only to write the updated retained quantities;
+//  - otherwise (more distinct rows, or no ids) d^T x is accumulated in global
+//    memory with L2 integer atomics, and the line search and the apply pass
+//    over every sample;
 //  - candidates are tested one pass at a time in increasing q (Algorithm 4's
 //    order), so an accepted unit step costs a single pass.
-// Overflowing any LDS list falls back to global-memory passes (correct, slower).
 // ---------------------------------------------------------------------------
 constexpr int kNarrowBlock = 512;      // 256 VGPRs per lane: no spills
 constexpr int kNarrowWaves = kNarrowBlock / kWave;
@@ -943,14 +1180,35 @@ __device__ inline void block_sums(double (&v)[NV], double (*red)[kNarrowWaves][4
   buf ^= 1;
 }
 
-// d^T x is built with L2 atomics while a stale copy of the line may sit in the
-// CU's L1: read it at workgroup scope, which bypasses L1 and is served by the
-// L2 of this XCD.  The single-workgroup kernel's problem state is touched by
-// no other workgroup while it runs (kernel boundaries make it visible to the
-// rest of the GPU), so workgroup scope suffices; agent scope would also ask
-// for coherence with the other XCDs' L2s and go to the memory side.
-__device__ inline double load_l2(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// Fixed-point d^T x: a term in units of 2^-e (sc = 2^e) and back.
+__device__ inline unsigned long long fx_term(double dj, float x, double sc) {
+  return (unsigned long long)(long long)rint((dj * (double)x) * sc);
+}
+__device__ inline double fx_value(unsigned long long acc, double isc) {
+  return (double)(long long)acc * isc;
+}
+
+// Exponent e of the bundle's fixed-point scale: with D = max |d_j| and
+// xrow = max_i sum_j |x_ij|, every partial sum of d^T x_i is below
+// D xrow < 2^(ilogb(D) + ilogb(xrow) + 2), so units of 2^-e with
+// e = 59 - ilogb(D) - ilogb(xrow) keep it below 2^61 (64-bit sums cannot
+// overflow, whatever the order); clamped so that 2^e and 2^-e are normal.
+__device__ inline int fx_exponent(double D, double xrow) {
+  if (!(D > 0.0) || !(D <= 1.7976931348623157e308)) return 0;  // no nonzero (finite) term
+  int e = 59 - ilogb(D) - ilogb(xrow > 0.0 ? xrow : 1.0);
+  return e < -1000 ? -1000 : (e > 1000 ? 1000 : e);
+}
+
+// The global fixed-point d^T x is built with L2 atomics while a stale copy
+// of the line may sit in the CU's L1: read it at workgroup scope, which
+// bypasses L1 and is served by the L2 of this XCD.  The single-workgroup
+// kernel's problem state is touched by no other workgroup while it runs
+// (kernel boundaries make it visible to the rest of the GPU), so workgroup
+// scope suffices; agent scope would also ask for coherence with the other
+// XCDs' L2s and go to the memory side.
+__device__ inline unsigned long long load_l2_fx(const double* p) {
+  return __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Bundle-local row ids for the single-workgroup schedule: one workgroup per
@@ -1013,7 +1271,7 @@ static_assert(kNarrowLidCap <= kTouchCap, "local row ids index the LDS row lists
 struct NarrowLds {
   double lds16[kNarrowWaves];
   double red[2][kNarrowWaves][4];
-  int32_t n_touch;
+  double dmx[kNarrowWaves];             // per-wave max |d_j|
   int32_t any_d;                        // some direction of the bundle is nonzero
   int32_t off[kNarrowMaxP + 1];        // nonzero offsets of the bundle's slots
   int32_t feat[kNarrowMaxP];
@@ -1022,12 +1280,13 @@ struct NarrowLds {
   double2 acc[kNarrowMaxP];            // (sum g terms, sum h terms) per slot
   double2 pf[kNarrowChunkCap];         // first segment of each 64-nonzero chunk
   double2 pl[kNarrowChunkCap];         // last segment of each chunk
+  // by local row id: the row, its label and retained quantity (written by
+  // the row's first toucher), and the fixed-point d^T x
   int32_t t_row[kTouchCap];
-  int16_t t_lid[kTouchCap];            // local row id of each listed row
-  uint32_t t_seen[kTouchCap / 32];     // local row ids already listed
+  uint32_t t_seen[kTouchCap / 32];     // local row ids already recorded
   int8_t t_y[kTouchCap];
   double t_c[kTouchCap];
-  double t_dtx[kTouchCap];
+  unsigned long long t_acc[kTouchCap];
 };
 
 // slot of bundle nonzero v: the largest s with off[s] <= v
@@ -1040,25 +1299,11 @@ __device__ inline int32_t slot_of(const int32_t* off, int32_t nslots, int32_t v)
   return lo;
 }
 
-// List a row by its local id (at most kNarrowLidCap distinct rows: no
-// overflow).
+// Record a row at its local id (first toucher only).
 __device__ inline void list_lid(NarrowLds& L, int32_t lid, int32_t row, double c, int yi) {
-  const int32_t e = atomicAdd(&L.n_touch, 1);
-  L.t_row[e] = row;
-  L.t_lid[e] = (int16_t)lid;
-  L.t_c[e] = c;
-  L.t_y[e] = (int8_t)yi;
-}
-
-// Append a row, first touched by this thread, to the bundle's LDS list (the
-// count keeps growing past the capacity so that an overflow is seen).
-__device__ inline void list_row(NarrowLds& L, int32_t row, double c, int yi) {
-  const int32_t e = atomicAdd(&L.n_touch, 1);
-  if (e < kTouchCap) {
-    L.t_row[e] = row;
-    L.t_c[e] = c;
-    L.t_y[e] = (int8_t)yi;
-  }
+  L.t_row[lid] = row;
+  L.t_c[lid] = c;
+  L.t_y[lid] = (int8_t)yi;
 }
 
 // One round of the sweep for bundle nonzero v (slot s, row, value x, the
@@ -1119,15 +1364,11 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       L.w[s] = na.pw[lo + s];  // no load that waits on perm
       L.acc[s] = make_double2(0.0, 0.0);
     }
-    if (tid == 0) {
-      L.n_touch = 0;
-      L.any_d = 0;
-    }
-    // distinct rows of the bundle with d^T x kept in LDS (t_row/t_c/t_y/t_dtx
-    // indexed by local row id), or -1: d^T x in global memory, rows listed
-    // by their first toucher
+    if (tid == 0) L.any_d = 0;
+    // distinct rows of the bundle with d^T x kept in LDS (t_row/t_c/t_y/t_acc
+    // indexed by local row id), or -1: d^T x in global memory
     const int32_t R = na.pR ? na.pR[t] : -1;
-    for (int32_t e = tid; e < R; e += kNarrowBlock) L.t_dtx[e] = 0.0;
+    for (int32_t e = tid; e < R; e += kNarrowBlock) L.t_acc[e] = 0ull;
     for (int32_t e = tid; e < (R + 31) / 32; e += kNarrowBlock) L.t_seen[e] = 0u;
     __syncthreads();
     const int32_t nb = L.off[ns];
@@ -1204,7 +1445,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     }
     __syncthreads();
     // finish each slot: g, h, d (eqs. (4)-(5), (11)), Delta term
-    double del = 0.0;
+    double del = 0.0, dmax = 0.0;
     for (int32_t s = tid; s < ns; s += kNarrowBlock) {
       double g, h;
       if (LOSS == kLogistic) {
@@ -1218,6 +1459,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       const double wj = L.w[s];
       const double dj = newton_dir(g, h, wj, a.ra, a.rb);
       L.d[s] = dj;
+      dmax = fmax(dmax, fabs(dj));
       if (dj != 0.0) {
         L.any_d = 1;
         const int32_t len = L.off[s + 1] - L.off[s];
@@ -1231,6 +1473,9 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       a.h[lo + s] = h;
       a.d[lo + s] = dj;
     }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o, kWave));
+    if (lane_id() == 0) L.dmx[wave_in_block()] = dmax;
     __syncthreads();  // publishes L.d; Delta's per-thread part stays in `del`
     if (L.any_d == 0 && !na.dtx_copy) {
       // every direction is zero: no row is touched, Delta = 0, the first
@@ -1249,18 +1494,23 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
       __syncthreads();
       continue;
     }
-    // 2. scatter d_j x_ij into d^T x; list touched rows with their retained
-    //    quantity and label
-    //    The register rounds issue every flag exchange before waiting on any.
+    // 2. scatter d_j x_ij into d^T x (fixed point, see above); record the
+    //    touched rows with their retained quantity and label by local id.
+    //    The register rounds issue every atomic before waiting on any.
+    double D = L.dmx[0];
+#pragma unroll
+    for (int k = 1; k < kNarrowWaves; ++k) D = fmax(D, L.dmx[k]);
+    const int fe = fx_exponent(D, na.xrow);
+    const double sc = ldexp(1.0, fe), isc = ldexp(1.0, -fe);
     if (R >= 0) {
       // d^T x by local row id with LDS atomics; the first toucher of a row
-      // (LDS bit per local id) lists it: no global memory traffic
+      // (LDS bit per local id) records it: no global memory traffic
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u) {
         if (u * kNarrowBlock + tid < nb) {
           const double dj = L.d[rs[u]];
           if (dj != 0.0) {
-            atomicAdd(&L.t_dtx[rl[u]], dj * (double)rx[u]);
+            atomicAdd(&L.t_acc[rl[u]], fx_term(dj, rx[u], sc));
             const uint32_t bit = 1u << (rl[u] & 31);
             if ((atomicOr(&L.t_seen[rl[u] >> 5], bit) & bit) == 0u)
               list_lid(L, rl[u], rrow[u], rc[u], ry[u]);
@@ -1292,7 +1542,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           first[u] = false;
           if (gd[u] != 0.0) {
-            atomicAdd(&L.t_dtx[glid[u]], gd[u] * (double)gx[u]);
+            atomicAdd(&L.t_acc[glid[u]], fx_term(gd[u], gx[u], sc));
             const uint32_t bit = 1u << (glid[u] & 31);
             first[u] = (atomicOr(&L.t_seen[glid[u] >> 5], bit) & bit) == 0u;
           }
@@ -1307,28 +1557,19 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           if (first[u]) list_lid(L, glid[u], grow[u], gc[u], gy[u]);
       }
     } else {
-      unsigned was[kNarrowRegRounds];
+      unsigned long long* gacc = (unsigned long long*)a.dtx;
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u) {
-        was[u] = 1u;
         if (u * kNarrowBlock + tid < nb) {
           const double dj = L.d[rs[u]];
-          if (dj != 0.0) {
-            unsafeAtomicAdd(&a.dtx[rrow[u]], dj * (double)rx[u]);
-            was[u] = atomicExch(&na.rowflag[rrow[u]], 1u);
-          }
+          if (dj != 0.0) atomicAdd(&gacc[rrow[u]], fx_term(dj, rx[u], sc));
         }
       }
-#pragma unroll
-      for (int u = 0; u < kNarrowRegRounds; ++u)
-        if (was[u] == 0u) list_row(L, rrow[u], rc[u], ry[u]);
       for (int32_t g0 = kNarrowRegRounds * kNarrowBlock; g0 < nb;
            g0 += kNarrowRegRounds * kNarrowBlock) {
-        double gd[kNarrowRegRounds], gc[kNarrowRegRounds];
+        double gd[kNarrowRegRounds];
         int32_t grow[kNarrowRegRounds];
         float gx[kNarrowRegRounds];
-        int gy[kNarrowRegRounds];
-        unsigned gwas[kNarrowRegRounds];
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           const int32_t v = g0 + u * kNarrowBlock + tid;
@@ -1342,29 +1583,12 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           gx[u] = on ? na.pv[base + v] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < kNarrowRegRounds; ++u) {
-          gwas[u] = 1u;
-          if (gd[u] != 0.0) {
-            unsafeAtomicAdd(&a.dtx[grow[u]], gd[u] * (double)gx[u]);
-            gwas[u] = atomicExch(&na.rowflag[grow[u]], 1u);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kNarrowRegRounds; ++u) {
-          gc[u] = gwas[u] == 0u ? a.cache[grow[u]] : 0.0;
-          gy[u] = gwas[u] == 0u ? (int)a.y[grow[u]] : 0;
-        }
-#pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u)
-          if (gwas[u] == 0u) list_row(L, grow[u], gc[u], gy[u]);
+          if (gd[u] != 0.0) atomicAdd(&gacc[grow[u]], fx_term(gd[u], gx[u], sc));
       }
     }
     __syncthreads();
-    const int32_t n_touch = L.n_touch;
-    const bool listed = n_touch <= kTouchCap;
-    if (listed && R < 0)
-      for (int32_t e = tid; e < n_touch; e += kNarrowBlock) L.t_dtx[e] = load_l2(&a.dtx[L.t_row[e]]);
-    __syncthreads();
+    const bool listed = R >= 0;
     // 3. candidates q = 0, 1, ... until the Armijo test (eq. (6)) holds
     int rbuf = 0;
     double Delta = 0.0, Dq = 0.0, al = 1.0, dF = 0.0;
@@ -1372,38 +1596,39 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     for (int q = 0; q < na.max_ls; ++q) {
       double sl = 0.0, l1 = 0.0, touched = 0.0;
       if (listed) {
-        for (int32_t e = tid; e < n_touch; e += kNarrowBlock) {
-          const double dl = L.t_dtx[R >= 0 ? (int32_t)L.t_lid[e] : e];
-          if (dl == 0.0) continue;
+        for (int32_t e = tid; e < R; e += kNarrowBlock) {
+          const unsigned long long ac = L.t_acc[e];
+          if (ac == 0ull) continue;
           touched += 1.0;
-          double sc = dl;
-          for (int u = 0; u < q; ++u) sc *= na.beta;
-          sl += loss_delta<LOSS>(L.t_c[e], (int)L.t_y[e], sc);
+          double sv = fx_value(ac, isc);
+          for (int u = 0; u < q; ++u) sv *= na.beta;
+          sl += loss_delta<LOSS>(L.t_c[e], (int)L.t_y[e], sv);
         }
       } else {
-        // every sample (more touched rows than the LDS list holds), the loads
-        // of kNarrowRegRounds samples issued together; same summation order
+        // every sample, the loads of kNarrowRegRounds samples issued
+        // together; a fixed summation order
         for (int64_t i0 = tid; i0 < na.n; i0 += (int64_t)kNarrowRegRounds * kNarrowBlock) {
-          double fd[kNarrowRegRounds], fc[kNarrowRegRounds];
+          unsigned long long fa[kNarrowRegRounds];
+          double fc[kNarrowRegRounds];
           int fy[kNarrowRegRounds];
 #pragma unroll
           for (int u = 0; u < kNarrowRegRounds; ++u) {
             const int64_t i = i0 + (int64_t)u * kNarrowBlock;
-            fd[u] = i < na.n ? load_l2(&a.dtx[i]) : 0.0;
+            fa[u] = i < na.n ? load_l2_fx(&a.dtx[i]) : 0ull;
           }
 #pragma unroll
           for (int u = 0; u < kNarrowRegRounds; ++u) {
             const int64_t i = i0 + (int64_t)u * kNarrowBlock;
-            fc[u] = fd[u] != 0.0 ? a.cache[i] : 0.0;
-            fy[u] = fd[u] != 0.0 ? (int)a.y[i] : 0;
+            fc[u] = fa[u] != 0ull ? a.cache[i] : 0.0;
+            fy[u] = fa[u] != 0ull ? (int)a.y[i] : 0;
           }
 #pragma unroll
           for (int u = 0; u < kNarrowRegRounds; ++u) {
-            if (fd[u] != 0.0) {
+            if (fa[u] != 0ull) {
               touched += 1.0;
-              double sc = fd[u];
-              for (int k = 0; k < q; ++k) sc *= na.beta;
-              sl += loss_delta<LOSS>(fc[u], fy[u], sc);
+              double sv = fx_value(fa[u], isc);
+              for (int k = 0; k < q; ++k) sv *= na.beta;
+              sl += loss_delta<LOSS>(fc[u], fy[u], sv);
             }
           }
         }
@@ -1438,66 +1663,65 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     n_slots += (double)ns;
     n_ls += q_acc >= 0 ? q_acc + 1 : na.max_ls;
     n_fail += q_acc < 0 ? 1.0 : 0.0;
-    // 4. accept: w, retained quantities; clear d^T x and the row flags
+    // 4. accept: w, retained quantities; clear the global d^T x
     if (na.dtx_copy) {
       if (R >= 0) {
-        // the listed rows' values over zeros
+        // the recorded rows' values over zeros
         for (int64_t i = tid; i < na.n; i += kNarrowBlock) na.dtx_copy[i] = 0.0;
         __syncthreads();
-        for (int32_t e = tid; e < n_touch; e += kNarrowBlock)
-          na.dtx_copy[L.t_row[e]] = L.t_dtx[L.t_lid[e]];
+        for (int32_t e = tid; e < R; e += kNarrowBlock)
+          if (L.t_acc[e] != 0ull) na.dtx_copy[L.t_row[e]] = fx_value(L.t_acc[e], isc);
       } else {
-        for (int64_t i = tid; i < na.n; i += kNarrowBlock) na.dtx_copy[i] = load_l2(&a.dtx[i]);
+        for (int64_t i = tid; i < na.n; i += kNarrowBlock)
+          na.dtx_copy[i] = fx_value(load_l2_fx(&a.dtx[i]), isc);
       }
       __syncthreads();  // copied before any thread clears d^T x below
     }
     if (listed) {
-      for (int32_t e = tid; e < n_touch; e += kNarrowBlock) {
-        const int32_t i = L.t_row[e];
-        const double dl = L.t_dtx[R >= 0 ? (int32_t)L.t_lid[e] : e];
-        if (q_acc >= 0 && dl != 0.0) {
-          double sc = dl;
-          for (int u = 0; u < q_acc; ++u) sc *= na.beta;
+      if (q_acc >= 0) {
+        for (int32_t e = tid; e < R; e += kNarrowBlock) {
+          const unsigned long long ac = L.t_acc[e];
+          if (ac == 0ull) continue;
+          double sv = fx_value(ac, isc);
+          for (int u = 0; u < q_acc; ++u) sv *= na.beta;
+          const int32_t i = L.t_row[e];
           if (LOSS == kLogistic)
-            na.cache[i] = L.t_c[e] * exp(sc);
+            na.cache[i] = L.t_c[e] * exp(sv);
           else
-            na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sc : -sc);
-        }
-        if (R < 0) {
-          __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          na.rowflag[i] = 0u;
+            na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sv : -sv);
         }
       }
     } else {
+      unsigned long long* gacc = (unsigned long long*)a.dtx;
       for (int64_t i0 = tid; i0 < na.n; i0 += (int64_t)kNarrowRegRounds * kNarrowBlock) {
-        double fd[kNarrowRegRounds], fc[kNarrowRegRounds];
+        unsigned long long fa[kNarrowRegRounds];
+        double fc[kNarrowRegRounds];
         int fy[kNarrowRegRounds];
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           const int64_t i = i0 + (int64_t)u * kNarrowBlock;
-          fd[u] = i < na.n ? load_l2(&a.dtx[i]) : 0.0;
+          fa[u] = i < na.n ? load_l2_fx(&a.dtx[i]) : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           const int64_t i = i0 + (int64_t)u * kNarrowBlock;
-          const bool upd = q_acc >= 0 && fd[u] != 0.0;
+          const bool upd = q_acc >= 0 && fa[u] != 0ull;
           fc[u] = upd ? na.cache[i] : 0.0;
           fy[u] = (upd && LOSS != kLogistic) ? (int)a.y[i] : 0;
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           const int64_t i = i0 + (int64_t)u * kNarrowBlock;
-          if (i >= na.n) continue;
-          if (q_acc >= 0 && fd[u] != 0.0) {
-            double sc = fd[u];
-            for (int k = 0; k < q_acc; ++k) sc *= na.beta;
+          if (fa[u] == 0ull) continue;
+          if (q_acc >= 0) {
+            double sv = fx_value(fa[u], isc);
+            for (int k = 0; k < q_acc; ++k) sv *= na.beta;
             if (LOSS == kLogistic)
-              na.cache[i] = fc[u] * exp(sc);
+              na.cache[i] = fc[u] * exp(sv);
             else
-              na.cache[i] = fc[u] - (fy[u] > 0 ? sc : -sc);
+              na.cache[i] = fc[u] - (fy[u] > 0 ? sv : -sv);
           }
-          __hip_atomic_store(&a.dtx[i], 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          na.rowflag[i] = 0u;
+          __hip_atomic_store(&gacc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
     }
@@ -1567,22 +1791,24 @@ __global__ __launch_bounds__(kBlock) void k_permute(const int32_t* ri, const flo
   }
 }
 
-// Column lengths in slot order (for the partition-order offsets).
 // Column length of each slot, and w in slot order (pw[r] = w[perm[r]]).
-__global__ void k_slot_len(const int32_t* perm, const int64_t* cp, int64_t p, int32_t* len,
-                           const double* w, double* pw) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r < p) {
-    const int32_t j = perm[r];
-    len[r] = (int32_t)(cp[j + 1] - cp[j]);
-    pw[r] = w[j];
+__device__ __forceinline__ void slot_len_body(const SlotLenArgs& a, int64_t bid) {
+  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
+  if (r < a.p) {
+    const int32_t j = a.perm[r];
+    a.len[r] = (int32_t)(a.cp[j + 1] - a.cp[j]);
+    if (a.w) a.pw[r] = a.w[j];
   }
 }
 
-__global__ void k_widen(const int32_t* in, int64_t m, int64_t* out) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r <= m) out[r] = in[r];
+__global__ __launch_bounds__(kBlock) void k_slot_len(SlotLenArgs a) { slot_len_body(a, blockIdx.x); }
+
+__device__ __forceinline__ void widen_body(const WidenArgs& a, int64_t bid) {
+  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
+  if (r <= a.m) a.out[r] = a.in[r];
 }
+
+__global__ __launch_bounds__(kBlock) void k_widen(WidenArgs a) { widen_body(a, blockIdx.x); }
 
 // ---------------------------------------------------------------------------
 // deterministic sum (two kernels), loss terms, margins
@@ -1701,11 +1927,13 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskSweepStop: sweep_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
     case kTaskSplit: split_body<LOSS, false>(t.u.sw, lb, t.nblk); break;
     case kTaskSplitStop: split_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
-    case kTaskLinesearch: linesearch_body<LOSS>(t.u.ls, lb % t.gx, lb / t.gx, t.gx); break;
-    case kTaskLinesearchRest:
-      linesearch_rest_body<LOSS>(t.u.ls, lb % t.gx, 1 + lb / t.gx, t.gx);
-      break;
-    case kTaskApply: apply_body<LOSS>(t.u.ap, lb, t.nblk); break;
+    case kTaskRowsDtx: rows_dtx_body<LOSS>(t.u.rw, lb); break;
+    case kTaskRowsApply: rows_apply_body<LOSS>(t.u.rw, lb, t.nblk); break;
+    case kTaskSlotLen: slot_len_body(t.u.sl, lb); break;
+    case kTaskWiden: widen_body(t.u.wd, lb); break;
+    case kTaskIslot: islot_body(t.u.is, lb); break;
+    case kTaskBrHist: br_hist_body(t.u.br, lb); break;
+    case kTaskBrScatter: br_scatter_body(t.u.br, lb); break;
     case kTaskScatterCount: scatter_count_body(t.u.sc, lb, t.nblk); break;
     case kTaskSumPartial: sum_partial_body(t.u.sum, lb, t.nblk); break;
     case kTaskSumFinal: sum_final_body(t.u.sum); break;
@@ -2006,40 +2234,210 @@ hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t
   return hipGetLastError();
 }
 
-int ls_grid(int64_t n) { return grid_for(n, kBlock, kLsGrid); }
-
-hipError_t launch_linesearch(int loss, const LsArgs& a, hipStream_t s) {
-  const dim3 g(ls_grid(a.n), (a.Q + kQGroup - 1) / kQGroup);
-  if (loss == kLogistic)
-    hipLaunchKernelGGL(k_linesearch<kLogistic>, g, dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_linesearch<kL2Svm>, g, dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-int apply_grid(int64_t n, int64_t slots) { return grid_for(n > slots ? n : slots, kBlock, 512); }
 int scatter_count_grid(int64_t p) { return grid_for(p, kBlock, 64); }
 int sum_grid(int64_t m) { return grid_for(m, kBlock, kSumGrid); }
 
-hipError_t launch_apply(int loss, const ApplyArgs& a, hipStream_t s) {
-  const dim3 g(apply_grid(a.n, a.slot_hi - a.slot_lo));
+// One wavefront per range of an average bundle, at least 128 blocks: a
+// bundle with more ranges than wavefronts takes several per wavefront.
+int rows_grid(double nnz_bundle) {
+  const double ranges = nnz_bundle / kRangeW;
+  double g = ranges / kWavesPerBlock;
+  if (g < 128) g = 128;
+  if (g > kRowsGridMax) g = kRowsGridMax;
+  return (int)g;
+}
+
+hipError_t launch_rows_dtx(int loss, const RowsArgs& a, hipStream_t s) {
+  if (a.G < 1 || a.G > kRowsGridMax) return hipErrorInvalidValue;
   if (loss == kLogistic)
-    hipLaunchKernelGGL(k_apply<kLogistic>, g, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rows_dtx<kLogistic>, dim3(a.G), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(k_apply<kL2Svm>, g, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rows_dtx<kL2Svm>, dim3(a.G), dim3(kBlock), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_rows_apply(int loss, const RowsArgs& a, hipStream_t s) {
+  if (a.G < 1 || a.G > kRowsGridMax) return hipErrorInvalidValue;
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_rows_apply<kLogistic>, dim3(a.G), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_rows_apply<kL2Svm>, dim3(a.G), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_scatter(const RowsArgs& a, double* dense, hipStream_t s) {
+  hipLaunchKernelGGL(k_rows_scatter, dim3(256), dim3(kBlock), 0, s, a, dense);
+  return hipGetLastError();
+}
+
+// Passes of the bundle-row sort: enough 8-bit digits for bundles 0 .. nb
+// (nb = the bundle of features outside the order).
+int br_passes(int64_t p_slots, int64_t P) {
+  const int64_t nb = (p_slots + P - 1) / P;
+  int passes = 1;
+  while (passes < 4 && (nb >> (8 * passes)) != 0) ++passes;
+  return passes;
+}
+
+int64_t br_hist_ints(int64_t nnz) { return 256 * ((nnz + kBrTile - 1) / kBrTile) + 1; }
+
+namespace {
+
+// The launches of the bundle-row order, in order: (kernel kind, block count,
+// arguments).  Shared by the direct launcher and the executor's task list.
+struct BrStep {
+  int kind;  // kTaskIslot, kTaskSlotLen, kTaskWiden, kTaskBrHist, kTaskBrScatter; -1: scan
+  int64_t nblk;
+  IslotArgs is;
+  SlotLenArgs sl;
+  WidenArgs wd;
+  BrArgs br;
+  const int32_t* scan_in;
+  int32_t* scan_out;
+  int64_t scan_m;
+};
+
+std::vector<BrStep> br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp,
+                             const int32_t* rr, const int32_t* rc, const float* rv, int64_t nnz,
+                             int32_t* islot, int32_t* len_tmp, int32_t* off32, int64_t* poff,
+                             int32_t* br_row, int32_t* br_slot, float* br_val, int32_t* bt_row,
+                             int32_t* bt_slot, float* bt_val, int32_t* hist) {
+  std::vector<BrStep> v;
+  BrStep st{};
+  const int64_t pg = grid_for(p_slots, kBlock, 1 << 30);
+  st.kind = kTaskIslot;
+  st.nblk = pg;
+  st.is = IslotArgs{perm, p_slots, islot};
+  v.push_back(st);
+  st = BrStep{};
+  st.kind = kTaskSlotLen;
+  st.nblk = pg;
+  st.sl = SlotLenArgs{perm, cp, p_slots, len_tmp, nullptr, nullptr};
+  v.push_back(st);
+  st = BrStep{};
+  st.kind = -1;
+  st.scan_in = len_tmp;
+  st.scan_out = off32;
+  st.scan_m = p_slots;
+  v.push_back(st);
+  st = BrStep{};
+  st.kind = kTaskWiden;
+  st.nblk = grid_for(p_slots + 1, kBlock, 1 << 30);
+  st.wd = WidenArgs{off32, p_slots, poff};
+  v.push_back(st);
+  if (nnz == 0) return v;
+  const int passes = br_passes(p_slots, P);
+  const int64_t ntiles = (nnz + kBrTile - 1) / kBrTile;
+  const int32_t nb = (int32_t)((p_slots + P - 1) / P);
+  // the last pass writes the br arrays
+  const int32_t* srow = rr;
+  const int32_t* scol = rc;
+  const float* sval = rv;
+  for (int pass = 0; pass < passes; ++pass) {
+    const bool to_br = ((passes - 1 - pass) % 2) == 0;
+    int32_t* drow = to_br ? br_row : bt_row;
+    int32_t* dslot = to_br ? br_slot : bt_slot;
+    float* dval = to_br ? br_val : bt_val;
+    BrArgs b{pass == 0 ? islot : nullptr, srow, scol, sval, drow, dslot, dval, hist,
+             nnz, ntiles, P, 8 * pass, nb};
+    st = BrStep{};
+    st.kind = kTaskBrHist;
+    st.nblk = ntiles;
+    st.br = b;
+    v.push_back(st);
+    st = BrStep{};
+    st.kind = -1;
+    st.scan_in = hist;
+    st.scan_out = hist;
+    st.scan_m = 256 * ntiles;
+    v.push_back(st);
+    st = BrStep{};
+    st.kind = kTaskBrScatter;
+    st.nblk = ntiles;
+    st.br = b;
+    v.push_back(st);
+    srow = drow;
+    scol = dslot;
+    sval = dval;
+  }
+  return v;
+}
+
+}  // namespace
+
+hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
+                                   const int64_t* cp, const int32_t* rr, const int32_t* rc,
+                                   const float* rv, int64_t nnz, int32_t* islot, int32_t* len_tmp,
+                                   int32_t* off32, int32_t* scan_tmp, int64_t* poff,
+                                   int32_t* br_row, int32_t* br_slot, float* br_val,
+                                   int32_t* bt_row, int32_t* bt_slot, float* bt_val,
+                                   int32_t* hist, hipStream_t s) {
+  if (P < 1 || p_slots < 1 || p_slots > p) return hipErrorInvalidValue;
+  if (p_slots < p)  // features outside the order keep slot -1
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p, kBlock, 4096)), dim3(kBlock), 0, s, islot, -1,
+                       p);
+  for (const BrStep& st : br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32,
+                                   poff, br_row, br_slot, br_val, bt_row, bt_slot, bt_val, hist)) {
+    hipError_t e = hipSuccess;
+    switch (st.kind) {
+      case kTaskIslot:
+        hipLaunchKernelGGL(k_islot, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.is);
+        break;
+      case kTaskSlotLen:
+        hipLaunchKernelGGL(k_slot_len, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.sl);
+        break;
+      case kTaskWiden:
+        hipLaunchKernelGGL(k_widen, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.wd);
+        break;
+      case kTaskBrHist:
+        hipLaunchKernelGGL(k_br_hist, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s, st.br);
+        break;
+      case kTaskBrScatter:
+        hipLaunchKernelGGL(k_br_scatter, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s, st.br);
+        break;
+      default:
+        e = launch_scan(st.scan_in, st.scan_out, st.scan_m, scan_tmp, s);
+        break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
+                      const int64_t* cp, const int32_t* rr, const int32_t* rc, const float* rv,
+                      int64_t nnz, int32_t* islot, int32_t* len_tmp, int32_t* off32,
+                      int32_t* scan_tmp, int64_t* poff, int32_t* br_row, int32_t* br_slot,
+                      float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val,
+                      int32_t* hist, std::vector<Task>& out) {
+  (void)p;  // every feature has a slot in an outer iteration's order (p_slots == p)
+  for (const BrStep& st : br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32,
+                                   poff, br_row, br_slot, br_val, bt_row, bt_slot, bt_val, hist)) {
+    if (st.kind < 0) {
+      scan_tasks(loss, st.scan_in, st.scan_out, st.scan_m, scan_tmp, out);
+      continue;
+    }
+    Task t = partition_task(st.kind, loss, st.nblk);
+    switch (st.kind) {
+      case kTaskIslot: t.u.is = st.is; break;
+      case kTaskSlotLen: t.u.sl = st.sl; break;
+      case kTaskWiden: t.u.wd = st.wd; break;
+      default: t.u.br = st.br; break;
+    }
+    out.push_back(t);
+  }
 }
 
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, const double* w, double* pw, hipStream_t s) {
-  hipLaunchKernelGGL(k_slot_len, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm, cp,
-                     p, len_tmp, w, pw);
+  hipLaunchKernelGGL(k_slot_len, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s,
+                     SlotLenArgs{perm, cp, p, len_tmp, w, pw});
   hipError_t e = launch_scan(len_tmp, off32, p, scan_tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_widen, dim3(grid_for(p + 1, kBlock, 1 << 30)), dim3(kBlock), 0, s, off32, p,
-                     poff);
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(p + 1, kBlock, 1 << 30)), dim3(kBlock), 0, s,
+                     WidenArgs{off32, p, poff});
   hipLaunchKernelGGL(k_permute, dim3(grid_for(p, kWavesPerBlock, 8192)), dim3(kBlock), 0, s, ri, v,
                      cp, chunks, cstart, p, poff, pri, pv);
   return hipGetLastError();
