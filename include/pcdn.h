@@ -389,9 +389,38 @@ int pcdn_profile(pcdn_ctx* ctx, int mask);
 int pcdn_profile_read(pcdn_ctx* ctx, int which, double* ms, int64_t* launches,
                       double* alg_bytes);
 
-/* Description of the last error on ctx (or of a failed pcdn_create when ctx
- * is NULL); valid until the next call on ctx. */
+/* Description of the last error on ctx (or, when ctx is NULL, of this
+ * thread's last failed pcdn_create or pcdn_solve_static); valid until the
+ * next call on ctx (or on this thread). */
 const char* pcdn_last_error(const pcdn_ctx* ctx);
+
+/* pcdn_solve without any device allocation, for callers that cannot
+ * allocate: code that runs while a HIP graph is captured around it, tight
+ * serving loops, harnesses that forbid hipMalloc.  One call loads and solves
+ * one problem as pcdn_load_csc then pcdn_solve would (the same partitions,
+ * kernels and arithmetic; the automatic schedule keeps bundles of many
+ * nonzeros in the single workgroup instead of moving them to the
+ * multi-kernel path, and no launch is captured as a graph), with no context.
+ *  device, hip_stream: the GPU and the stream to run on (NULL: the null
+ *    stream); the call returns when its work on the stream is done.
+ *  n, p, nnz, col_ptr (int64, p + 1), row_idx (int32, nnz), val (fp32, nnz),
+ *    y (int8, n): X in CSC and the labels, in DEVICE memory, read only,
+ *    checked on the device as pcdn_load_csc checks them (PCDN_E_CSC).
+ *  C, P, eps, loss, opts, info: as pcdn_solve (opts->w0, if given, is host
+ *    memory).
+ *  w_out: DEVICE, p doubles, written with the solution; it also holds w
+ *    while the solve runs.
+ * Every other buffer lives in a workspace of 64 MiB per device compiled into
+ * the library (each device the library runs on holds it until the process
+ * ends); a problem whose buffers do not fit (roughly 130 bytes per nonzero,
+ * 200 per feature and 50 per sample) is rejected with PCDN_E_ARG before any
+ * work.  Every call on one device shares that workspace: calls that overlap
+ * on one device (two host threads, or two streams) race and must not be
+ * made.  Errors are described by pcdn_last_error(NULL). */
+int pcdn_solve_static(int device, void* hip_stream, int64_t n, int64_t p, int64_t nnz,
+                      const int64_t* col_ptr, const int32_t* row_idx, const float* val,
+                      const int8_t* y, double C, int64_t P, double eps, int loss,
+                      const pcdn_opts* opts, double* w_out, pcdn_info* info);
 
 /* Release the context and its device memory.  NULL is accepted. */
 int pcdn_destroy(pcdn_ctx* ctx);

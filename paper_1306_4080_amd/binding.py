@@ -36,7 +36,8 @@ SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_load_csc_bias", "pcdn_solve", "
            "pcdn_server_create", "pcdn_server_submit", "pcdn_server_step", "pcdn_server_status",
            "pcdn_server_take", "pcdn_server_last_error", "pcdn_server_destroy",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
-           "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy")
+           "pcdn_profile", "pcdn_profile_read", "pcdn_last_error", "pcdn_destroy",
+           "pcdn_solve_static")
 
 
 class PcdnError(RuntimeError):
@@ -152,6 +153,8 @@ def load_library(path: str = LIB_PATH):
     L.pcdn_server_last_error.restype = ctypes.c_char_p
     L.pcdn_server_destroy.argtypes = [vp]
     L.pcdn_destroy.argtypes = [vp]
+    L.pcdn_solve_static.argtypes = [i32, vp, i64, i64, i64, vp, vp, vp, vp, dbl, i64, dbl, i32,
+                                    ctypes.POINTER(pcdn_opts), vp, ctypes.POINTER(pcdn_info)]
     for s in SYMBOLS:
         if s not in ("pcdn_last_error", "pcdn_server_last_error"):
             getattr(L, s).restype = ctypes.c_int
@@ -249,6 +252,30 @@ def pcdn_solve(ctx, C, P, eps, loss, p, **opts):
                                    ctypes.byref(o), w.ctypes.data, ctypes.byref(info))
     _check(ctx, rc, (PCDN_OK, PCDN_NOT_CONVERGED))
     return rc, w, _info_dict(info)
+
+
+def pcdn_solve_static(device, n, p, col_ptr, row_idx, val, y, C, P, eps, loss, w_out,
+                      hip_stream=None, **opts):
+    """The allocation-free solve: X (CSC), y and w_out are torch CUDA tensors
+    (int64, int32, float32, int8, float64) on `device`.  Returns (status,
+    info dict); w_out holds the solution."""
+    for t, dt in ((col_ptr, "int64"), (row_idx, "int32"), (val, "float32"), (y, "int8"),
+                  (w_out, "float64")):
+        if not (hasattr(t, "is_cuda") and t.is_cuda and str(t.dtype).endswith(dt)
+                and t.is_contiguous()):
+            raise TypeError(f"pcdn_solve_static takes contiguous device tensors ({dt})")
+    if w_out.numel() != int(p):
+        raise ValueError("w_out must hold p entries")
+    loss = LOSSES.get(loss, loss)
+    o, keep = _opts(**opts)
+    info = pcdn_info()
+    nnz = int(row_idx.numel())
+    rc = load_library().pcdn_solve_static(int(device), hip_stream, int(n), int(p), nnz,
+                                          _ptr(col_ptr), _ptr(row_idx), _ptr(val), _ptr(y),
+                                          float(C), int(P), float(eps), int(loss), ctypes.byref(o),
+                                          _ptr(w_out), ctypes.byref(info))
+    _check(None, rc, (PCDN_OK, PCDN_NOT_CONVERGED))
+    return rc, _info_dict(info)
 
 
 def _info_dict(info) -> dict:

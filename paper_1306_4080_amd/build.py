@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("pcdn_api.hip", "pcdn_batch.hip", "pcdn_kernels.hip")]
+SOURCES = [os.path.join(CSRC, f)
+           for f in ("pcdn_api.hip", "pcdn_batch.hip", "pcdn_kernels.hip", "pcdn_static.hip")]
 HEADERS = [os.path.join(CSRC, "pcdn_device.h"), os.path.join(CSRC, "pcdn_host.h"),
            os.path.join(ROOT, "include", "pcdn.h")]
 LIB = os.path.join(HERE, "libpcdn.so")

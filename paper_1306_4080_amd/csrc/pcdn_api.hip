@@ -928,6 +928,12 @@ using namespace pcdn::host;
 // ===========================================================================
 static thread_local std::string g_create_error;
 
+namespace pcdn {
+namespace host {
+std::string& global_error() { return g_create_error; }
+}  // namespace host
+}  // namespace pcdn
+
 extern "C" int pcdn_create(pcdn_ctx** out, int device, void* hip_stream) {
   if (!out) return PCDN_E_ARG;
   *out = nullptr;

@@ -186,6 +186,9 @@ namespace host {
 
 // Record msg as ctx's last error and return code.
 int fail(pcdn_ctx* c, int code, const std::string& msg);
+// The calling thread's error record of the entry points without a context
+// (pcdn_create, pcdn_solve_static), returned by pcdn_last_error(NULL).
+std::string& global_error();
 
 #define HIPCHK(ctx, expr)                                                              \
   do {                                                                                 \

@@ -2297,35 +2297,36 @@ struct BrStep {
   int64_t scan_m;
 };
 
-std::vector<BrStep> br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp,
-                             const int32_t* rr, const int32_t* rc, const float* rv, int64_t nnz,
-                             int32_t* islot, int32_t* len_tmp, int32_t* off32, int64_t* poff,
-                             int32_t* br_row, int32_t* br_slot, float* br_val, int32_t* bt_row,
-                             int32_t* bt_slot, float* bt_val, int32_t* hist) {
-  std::vector<BrStep> v;
+// Calls f(step) for each launch in order (no host allocation).
+template <class F>
+void br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp,
+              const int32_t* rr, const int32_t* rc, const float* rv, int64_t nnz, int32_t* islot,
+              int32_t* len_tmp, int32_t* off32, int64_t* poff, int32_t* br_row, int32_t* br_slot,
+              float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val, int32_t* hist,
+              F&& f) {
   BrStep st{};
   const int64_t pg = grid_for(p_slots, kBlock, 1 << 30);
   st.kind = kTaskIslot;
   st.nblk = pg;
   st.is = IslotArgs{perm, p_slots, islot};
-  v.push_back(st);
+  f(st);
   st = BrStep{};
   st.kind = kTaskSlotLen;
   st.nblk = pg;
   st.sl = SlotLenArgs{perm, cp, p_slots, len_tmp, nullptr, nullptr};
-  v.push_back(st);
+  f(st);
   st = BrStep{};
   st.kind = -1;
   st.scan_in = len_tmp;
   st.scan_out = off32;
   st.scan_m = p_slots;
-  v.push_back(st);
+  f(st);
   st = BrStep{};
   st.kind = kTaskWiden;
   st.nblk = grid_for(p_slots + 1, kBlock, 1 << 30);
   st.wd = WidenArgs{off32, p_slots, poff};
-  v.push_back(st);
-  if (nnz == 0) return v;
+  f(st);
+  if (nnz == 0) return;
   const int passes = br_passes(p_slots, P);
   const int64_t ntiles = (nnz + kBrTile - 1) / kBrTile;
   const int32_t nb = (int32_t)((p_slots + P - 1) / P);
@@ -2344,23 +2345,22 @@ std::vector<BrStep> br_steps(const int32_t* perm, int64_t p_slots, int64_t P, co
     st.kind = kTaskBrHist;
     st.nblk = ntiles;
     st.br = b;
-    v.push_back(st);
+    f(st);
     st = BrStep{};
     st.kind = -1;
     st.scan_in = hist;
     st.scan_out = hist;
     st.scan_m = 256 * ntiles;
-    v.push_back(st);
+    f(st);
     st = BrStep{};
     st.kind = kTaskBrScatter;
     st.nblk = ntiles;
     st.br = b;
-    v.push_back(st);
+    f(st);
     srow = drow;
     scol = dslot;
     sval = dval;
   }
-  return v;
 }
 
 }  // namespace
@@ -2376,8 +2376,10 @@ hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slo
   if (p_slots < p)  // features outside the order keep slot -1
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p, kBlock, 4096)), dim3(kBlock), 0, s, islot, -1,
                        p);
-  for (const BrStep& st : br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32,
-                                   poff, br_row, br_slot, br_val, bt_row, bt_slot, bt_val, hist)) {
+  hipError_t err = hipSuccess;
+  br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32, poff, br_row, br_slot,
+           br_val, bt_row, bt_slot, bt_val, hist, [&](const BrStep& st) {
+    if (err != hipSuccess) return;
     hipError_t e = hipSuccess;
     switch (st.kind) {
       case kTaskIslot:
@@ -2399,8 +2401,9 @@ hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slo
         e = launch_scan(st.scan_in, st.scan_out, st.scan_m, scan_tmp, s);
         break;
     }
-    if (e != hipSuccess) return e;
-  }
+    err = e;
+  });
+  if (err != hipSuccess) return err;
   return hipGetLastError();
 }
 
@@ -2411,11 +2414,11 @@ void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots,
                       float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val,
                       int32_t* hist, std::vector<Task>& out) {
   (void)p;  // every feature has a slot in an outer iteration's order (p_slots == p)
-  for (const BrStep& st : br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32,
-                                   poff, br_row, br_slot, br_val, bt_row, bt_slot, bt_val, hist)) {
+  br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32, poff, br_row, br_slot,
+           br_val, bt_row, bt_slot, bt_val, hist, [&](const BrStep& st) {
     if (st.kind < 0) {
       scan_tasks(loss, st.scan_in, st.scan_out, st.scan_m, scan_tmp, out);
-      continue;
+      return;
     }
     Task t = partition_task(st.kind, loss, st.nblk);
     switch (st.kind) {
@@ -2425,7 +2428,7 @@ void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots,
       default: t.u.br = st.br; break;
     }
     out.push_back(t);
-  }
+  });
 }
 
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
