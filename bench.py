@@ -1,38 +1,42 @@
 #!/usr/bin/env python3
 """PCDN bundle-sweep benchmark on one MI355X.
 
-Workload: the text-like L1-regularised logistic-regression problem
-(n = 20,000 samples, p = 50,000 features, ~1.6M fp32 nonzeros, Zipf(1.1) column
-frequencies, row-normalised lognormal values) at its six settings
-C in {0.5, 4} x P in {64, 1024, 8192}; synthetic, seeded, generated in-process.
+Workload (the headline): the huge sparse binary L1-regularised L2-loss SVM
+problem (n = 100,000 samples, p = 1,000,000 features, ~12M binary fp32
+nonzeros, ~120 per row, Zipf(1.05) column frequencies with columns capped at
+50,000 nonzeros), C = 1, bundle size P = 16,384; synthetic, seeded, generated
+in-process.  It is the largest configuration that the method's benchmark
+set runs on one GPU.
 
-A step is one pass of the whole hot path for each of the six settings: one outer
-iteration of Algorithm 3 (seeded partition, every bundle's gradient/Hessian
-sweep, direction, d^T x scatter, line search and apply, then the full-gradient
-stopping test), continuing each setting's trajectory from w = 0 (the warmup
-steps are the first iterations).  value = bundle-sweep nonzeros processed per
-second over the timed steps.
+A step is one pass of the whole hot path: one outer iteration of Algorithm 3
+(seeded partition, every bundle's gradient/Hessian sweep, direction, d^T x,
+line search and apply, then the full-gradient stopping test), continuing the
+trajectory from w = 0 (the warmup steps are the first iterations).  value =
+bundle-sweep nonzeros processed per second over the timed steps (nnz(X) per
+step), with X resident in HBM before timing.
 
-The timed region (A) runs the steps through pcdn_iterate_batch: each step is
-one round of the batch engine, in which the six settings' outer iterations
-run concurrently (the two single-workgroup settings in one launch, the four
-multi-kernel settings through the lock-step executor), without
-instrumentation.  Region A2 runs the next steps one setting after another
-(pcdn_iterate, replayed graphs) and is reported as "sequential", with the
-per-setting times.  Region B runs the next steps with every kernel launch
-bracketed by HIP events on the library's stream; the roofline object reports
-the kernel class with the most time there (algorithmic bytes per launch /
-average launch duration).
+Region A (value) replays the captured outer iteration on the library's
+stream.  Region B runs the next steps of the same solve with every kernel
+launch bracketed by HIP events on that stream (direct launches, same kernels
+and launch shapes); the roofline object reports the kernel class with the
+most time there (algorithmic bytes per launch / average launch duration),
+beside a device-to-device copy measured in the same process.
 The FP64 CPU oracle is timed on a bounded sample of the same workload.
 
-Two more objects on the same line (skipped with --no-batched):
-- "batched": 64 independent LR problems (the batched recipe: n U[500,20000],
-  p U[1000,100000], density U[0.001,0.02]) solved to eps = 1e-4 one
-  pcdn_solve after another and in one pcdn_solve_batch call, solves/s of
-  each (bundle size, schedule and chunk length from the autotuner, tuned
-  before timing);
+More objects on the same line:
+- "text_like": the text-like L1-LR problem (20,000 x 50,000, ~1.6M nonzeros)
+  at its six settings C in {0.5, 4} x P in {64, 1024, 8192}, one outer
+  iteration of each per step, run concurrently through pcdn_iterate_batch
+  and one after another;
+- "batched" (skipped with --no-batched): 64 independent LR problems (n
+  U[500,20000], p U[1000,100000], density U[0.001,0.02]) solved to
+  eps = 1e-4 one pcdn_solve after another and in one pcdn_solve_batch call
+  (bundle size, schedule and chunk length from the autotuner, tuned before
+  timing);
 - "path": 32 C values on the text-like matrix with warm starts,
-  pcdn_solve_path against the same chain of pcdn_solve calls.
+  pcdn_solve_path against the same chain of pcdn_solve calls;
+- "serving" (skipped with --no-serving): a Poisson stream of mixed LR/SVM
+  solves through the solve server against one solve after another.
 """
 from __future__ import annotations
 
@@ -51,14 +55,14 @@ if ROOT not in sys.path:
 
 METRIC = "bundle-sweep nnz/s (HBM GB/s %peak); batched solves/s + p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
-NARROW_CLASS = 5  # index of "narrow" in KERNEL_CLASSES
-KERNEL_CLASSES = ("sweep", "split_columns", "linesearch", "apply", "stopping_sweep", "narrow")
-KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep, direction, fused d^T x scatter)",
-                "k_split (split-column finish and scatter)",
-                "k_linesearch (per-candidate loss-change partial sums)",
-                "k_apply (Armijo decision, w and retained-quantity update)",
+KERNEL_CLASSES = ("sweep", "split_columns", "dtx_linesearch", "apply", "stopping_sweep", "narrow")
+KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep and direction, one wavefront per column chunk)",
+                "k_split (finish of columns cut into several chunks)",
+                "k_rows_dtx (d^T x by row and the first line-search candidates)",
+                "k_rows_apply (Armijo decision, w and retained-quantity update)",
                 "k_sweep+k_split stopping mode (full-gradient subgradient norm)",
                 "k_narrow (one workgroup runs every bundle of an outer iteration)")
+C3 = dict(C=1.0, P=16384, eps=1e-3, loss="svm")
 SETTINGS = [(0.5, 64), (0.5, 1024), (0.5, 8192), (4.0, 64), (4.0, 1024), (4.0, 8192)]
 SEED = 1
 
@@ -71,8 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", action="append", default=None, metavar="C,P",
-                    help="run only this (C, P) setting (repeatable); for profiling runs")
+    ap.add_argument("--no-text-like", action="store_true",
+                    help="skip the text-like six-setting measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-mebibyte device buffer three times (the plain copy "
                          "kernel that scales the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -113,7 +117,7 @@ def kernel_source_hash() -> str:
 def measured_traffic(kernel_class: str):
     """HBM bytes per launch of a kernel class from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_class}_c2_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel_class}_c3_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
@@ -124,28 +128,23 @@ def measured_traffic(kernel_class: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(d, budget_s: float, settings) -> dict:
-    """The FP64 oracle (single-threaded C) on a bounded sample: the first outer
-    iterations of each of the six settings, round-robin until the budget."""
+def cpu_baseline(d, budget_s: float) -> dict:
+    """The FP64 oracle (single-threaded C) on a bounded sample of the headline
+    workload: the first outer iterations of the solve from w = 0, as many as
+    fit the budget (one probe iteration sets the count)."""
     import oracle
     prob = oracle.Problem.from_data(d)
-    done_nnz = 0
-    # run each setting for m outer iterations, m chosen from a one-iteration probe
-    t_probe = time.perf_counter()
-    for C, P in settings:
-        par = oracle.Params(loss="lr", C=C)
-        oracle.solve(prob, par, P=P, eps=0.0, seed=SEED, max_outer=1)
-    probe = time.perf_counter() - t_probe
+    par = oracle.Params(loss=C3["loss"], C=C3["C"])
+    t0 = time.perf_counter()
+    oracle.solve(prob, par, P=C3["P"], eps=0.0, seed=SEED, max_outer=1)
+    probe = time.perf_counter() - t0
     m = max(1, int(budget_s / max(probe, 1e-3)))
     t0 = time.perf_counter()
-    for C, P in settings:
-        par = oracle.Params(loss="lr", C=C)
-        w, info, _ = oracle.solve(prob, par, P=P, eps=0.0, seed=SEED, max_outer=m)
-        done_nnz += info["nnz_swept"]
+    w, info, _ = oracle.solve(prob, par, P=C3["P"], eps=0.0, seed=SEED, max_outer=m)
     dt = time.perf_counter() - t0
-    return {"value": done_nnz / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} outer iterations of each of the {len(settings)} (C, P) settings "
-                      f"from w = 0 ({done_nnz} bundle nonzeros, {dt:.1f} s, single thread)"}
+    return {"value": info["nnz_swept"] / dt, "unit": "nnz/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {m} outer iterations of the solve from w = 0 "
+                      f"({info['nnz_swept']} bundle nonzeros, {dt:.1f} s, single thread)"}
 
 
 def _chosen_pilot(t: dict) -> dict:
@@ -314,6 +313,105 @@ def serving_measurement(pc, synth, scale: float, n_req: int) -> dict:
             "nnz_mean": float(np.mean([d.nnz for d, _ in pool]))}
 
 
+def copy_peak() -> dict:
+    """Device-to-device copy of 1 GiB (torch's copy kernel), best of five:
+    bytes read + written per second."""
+    import torch
+    nbytes = 1 << 30
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(x)
+    best = float("inf")
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del x, y
+    return {"copy_GBps": 2 * nbytes / best / 1e9, "bytes": 2 * nbytes,
+            "measured": "1 GiB device-to-device copy, HIP events, best of 5"}
+
+
+def headline(pc, d, steps: int, warmup: int) -> dict:
+    """The huge sparse L2-SVM problem: region A (value) and region B (kernel
+    classes with HIP events), one solve continued step by step."""
+    import torch
+    s = pc.Solver(device=0).load_data(d)
+    C, P = C3["C"], C3["P"]
+    s.reset(C3["loss"], C)
+    opts = dict(seed=SEED)
+    for k in range(warmup):
+        s.iterate(P, k, 1, want_subgrad=True, **opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G = s.iterate(P, warmup, steps, want_subgrad=True, **opts)
+    elapsed = time.perf_counter() - t0
+    # region B: the next steps, every kernel class bracketed by events
+    pc.pcdn_profile(s.ctx, (1 << len(KERNEL_CLASSES)) - 1)
+    tb0 = time.perf_counter()
+    s.iterate(P, warmup + steps, steps, want_subgrad=True, **opts)
+    tb1 = time.perf_counter()
+    kernels, totals = {}, {}
+    for cls, name in enumerate(KERNEL_CLASSES):
+        ms, n, b = pc.pcdn_profile_read(s.ctx, cls)
+        totals[cls] = (ms, n, b)
+        kernels[name] = {"launches": int(n), "ms_total": round(ms, 4),
+                         "us_per_launch": round(1e3 * ms / max(n, 1), 3),
+                         "alg_bytes_per_launch": round(b / max(n, 1)),
+                         "alg_GBps": round(b / (ms / 1e3) / 1e9, 1) if ms > 0 and b > 0 else None}
+    pc.pcdn_profile(s.ctx, 0)
+    F, Gs = s.evaluate()
+    s.close()
+    return {"value": d.nnz * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "subgrad_after_region_a": G, "objective_after": F, "subgrad_after": Gs,
+            "region_b_ms_per_step": 1e3 * (tb1 - tb0) / steps,
+            "kernels": kernels, "totals": totals}
+
+
+def text_like(pc, d, steps: int, warmup: int) -> dict:
+    """The text-like LR problem at its six (C, P) settings: one outer
+    iteration of each per step, concurrently (one round of the batch engine
+    per step) and one setting after another."""
+    import torch
+    solvers = []
+    for C, P in SETTINGS:
+        s = pc.Solver(device=0).load_data(d)
+        s.reset("lr", C)
+        solvers.append((s, C, P))
+    for k in range(warmup):
+        for s, C, P in solvers:
+            s.iterate(P, k, 1, want_subgrad=True, seed=SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pc.iterate_batch([s for s, _, _ in solvers], [P for _, _, P in solvers], warmup, steps,
+                     seed=SEED)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    per_setting = {f"C={C},P={P}": 0.0 for _, C, P in solvers}
+    t0 = time.perf_counter()
+    for step in range(steps):
+        for s, C, P in solvers:
+            ts = time.perf_counter()
+            s.iterate(P, warmup + steps + step, 1, want_subgrad=True, seed=SEED)
+            per_setting[f"C={C},P={P}"] += time.perf_counter() - ts
+    torch.cuda.synchronize()
+    elapsed_seq = time.perf_counter() - t0
+    F = {f"C={C},P={P}": s.evaluate()[0] for s, C, P in solvers}
+    for s, _, _ in solvers:
+        s.close()
+    nnz_total = d.nnz * len(SETTINGS) * steps
+    return {"workload": "text-like L1-LR 20000x50000, Zipf(1.1) columns, "
+                        "C in {0.5,4} x P in {64,1024,8192}, one outer iteration of each per step",
+            "n": d.n, "p": d.p, "nnz": d.nnz,
+            "value": nnz_total / elapsed, "unit": "nnz/s", "ms_per_step": 1e3 * elapsed / steps,
+            "measured": "six settings concurrently, one pcdn_iterate_batch round per step",
+            "sequential": {"value": nnz_total / elapsed_seq,
+                           "ms_per_step": 1e3 * elapsed_seq / steps},
+            "per_setting_ms_per_iter": {k: 1e3 * v / steps for k, v in per_setting.items()},
+            "objective_after": F}
+
+
 def main():
     args = parse()
     if args.source_hash:
@@ -336,122 +434,67 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    settings = SETTINGS
-    if args.only:
-        settings = [(float(c), int(p)) for c, p in (o.split(",") for o in args.only)]
     pc.ensure_built()
-    d = synth.c2()
-    solvers = []
-    for C, P in settings:
-        s = pc.Solver(device=0).load_data(d)
-        s.reset("lr", C)
-        solvers.append((s, C, P))
-
-    # warmup: the first outer iterations of each trajectory
-    for k in range(args.warmup):
-        for s, C, P in solvers:
-            s.iterate(P, k, 1, want_subgrad=True, seed=SEED)
-    torch.cuda.synchronize()
-
-    # timed region A: the settings' outer iterations concurrently, one engine
-    # round per step, no instrumentation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pc.iterate_batch([s for s, _, _ in solvers], [P for _, _, P in solvers], args.warmup,
-                     args.steps, seed=SEED)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    nnz_total = d.nnz * len(settings) * args.steps
-    value = nnz_total / elapsed
-    # region A2: the next steps one setting after another (graph replays)
-    per_setting = {f"C={C},P={P}": 0.0 for _, C, P in solvers}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for step in range(args.steps):
-        for s, C, P in solvers:
-            ts = time.perf_counter()
-            s.iterate(P, args.warmup + args.steps + step, 1, want_subgrad=True, seed=SEED)
-            per_setting[f"C={C},P={P}"] += time.perf_counter() - ts
-    torch.cuda.synchronize()
-    elapsed_seq = time.perf_counter() - t0
-
-    # timed region B: the next `steps` outer iterations with every kernel class
-    # bracketed by HIP events on the library's stream (launched directly, not
-    # from a graph, so events can bracket each kernel); the roofline is taken
-    # for the class with the most kernel time
-    for s, _, _ in solvers:
-        pc.pcdn_profile(s.ctx, (1 << len(KERNEL_CLASSES)) - 1)
-    tb0 = time.perf_counter()
-    for step in range(args.steps):
-        for s, C, P in solvers:
-            s.iterate(P, args.warmup + 2 * args.steps + step, 1, want_subgrad=True, seed=SEED)
-    tb1 = time.perf_counter()
-    kernels = {}
-    totals = {}
-    for cls, name in enumerate(KERNEL_CLASSES):
-        ms = n = b = 0.0
-        for s, _, _ in solvers:
-            a_ms, a_n, a_b = pc.pcdn_profile_read(s.ctx, cls)
-            ms += a_ms
-            n += a_n
-            b += a_b
-        totals[cls] = (ms, n, b)
-        kernels[name] = {"launches": int(n), "ms_total": round(ms, 4),
-                         "us_per_launch": round(1e3 * ms / max(n, 1), 3),
-                         "alg_GBps": round(b / (ms / 1e3) / 1e9, 1) if ms > 0 else None}
+    print("bench: generating the huge sparse L2-SVM problem", file=sys.stderr, flush=True)
+    d3 = synth.c3()
+    print("bench: headline", file=sys.stderr, flush=True)
+    h = headline(pc, d3, args.steps, args.warmup)
+    cp = copy_peak()
+    totals = h.pop("totals")
     dominant = max(totals, key=lambda k: totals[k][0])
     dom_ms, dom_n, dom_bytes = totals[dominant]
     avg_launch_s = dom_ms / 1e3 / max(dom_n, 1)
     bytes_per_launch = dom_bytes / max(dom_n, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    traffic = measured_traffic(KERNEL_CLASSES[dominant])
-    F = {f"C={C},P={P}": s.evaluate()[0] for s, C, P in solvers}
-    for s, _, _ in solvers:
-        s.close()
-
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": h["value"],
         "unit": "nnz/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "text-like L1-LR 20000x50000, Zipf(1.1) columns, "
-                               "C in {0.5,4} x P in {64,1024,8192}",
-                   "n": d.n, "p": d.p, "nnz": d.nnz, "loss": "logistic", "seed": SEED,
-                   "settings": [f"C={C},P={P}" for C, P in settings]},
+        "config": {"workload": "huge sparse binary L1-regularised L2-SVM 100000x1000000, "
+                               "~120 nonzeros per row, Zipf(1.05) columns capped at 50000, "
+                               "C=1, P=16384, one outer iteration per step",
+                   "n": d3.n, "p": d3.p, "nnz": d3.nnz, "loss": "l2svm", "C": C3["C"],
+                   "P": C3["P"], "seed": SEED},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic,
+                     "traffic": measured_traffic(KERNEL_CLASSES[dominant]),
                      "kernel": KERNEL_NAMES[dominant],
                      "alg_bytes_per_launch": bytes_per_launch,
                      "avg_launch_us": avg_launch_s * 1e6, "launches": int(dom_n),
-                     "measured": "HIP events in timed region B (the next steps after region A)",
-                     "region_b_ms_per_step": 1e3 * (tb1 - tb0) / args.steps,
-                     # a one-workgroup kernel runs on one of the 256 compute
-                     # units: its share of the HBM peak is peak / 256
-                     "frac_of_one_cu_share": (achieved / (HBM_PEAK_GBS / 256)
-                                              if dominant == NARROW_CLASS else None)},
-        "sequential": {"value": nnz_total / elapsed_seq, "ms_per_step": 1e3 * elapsed_seq / args.steps,
-                       "measured": "region A2: the next steps, one setting after another"},
-        "per_setting_ms_per_iter": {k: 1e3 * v / args.steps for k, v in per_setting.items()},
-        "kernels": kernels,
-        "objective_after": F,
+                     "copy_GBps": cp["copy_GBps"],
+                     "frac_of_copy": achieved / cp["copy_GBps"],
+                     "measured": "HIP events around each launch on the library's stream in "
+                                 "region B (the next steps of the same solve)",
+                     "region_b_ms_per_step": h["region_b_ms_per_step"]},
+        "kernels": h["kernels"],
+        "objective_after": h["objective_after"],
+        "subgrad_after": h["subgrad_after"],
     }
+    del d3
+    d2 = synth.c2()
+    if not args.no_text_like:
+        print("bench: text-like settings", file=sys.stderr, flush=True)
+        line["text_like"] = text_like(pc, d2, args.steps, args.warmup)
     if not args.no_batched:
+        print("bench: batched problems and path", file=sys.stderr, flush=True)
         line["batched"] = batched_measurement(pc, synth, args.batched_scale)
-        line["path"] = path_measurement(pc, d)
+        line["path"] = path_measurement(pc, d2)
     if not args.no_serving:
+        print("bench: serving", file=sys.stderr, flush=True)
         line["serving"] = serving_measurement(pc, synth, args.serving_scale,
                                               args.serving_requests)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds, settings)
+        print("bench: CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(synth.c3(), args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

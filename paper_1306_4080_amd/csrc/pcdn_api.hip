@@ -63,7 +63,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
   dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
   dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
-  dfree(c->rr); dfree(c->islot); dfree(c->br_row); dfree(c->br_slot); dfree(c->br_val);
+  dfree(c->ccol); dfree(c->rr); dfree(c->islot); dfree(c->br_row); dfree(c->br_slot); dfree(c->br_val);
   dfree(c->bt_row); dfree(c->bt_slot); dfree(c->bt_val); dfree(c->br_hist);
   dfree(c->u_cnt); dfree(c->u_row); dfree(c->u_dtx);
   dfree(c->part); dfree(c->ls_part);
@@ -224,11 +224,11 @@ int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) 
   const SweepArgs a = bundle_sweep_args(c, o, lo, hi, clip);
   {
     ProfScope ps(c, 0);
-    HIPCHK(c, launch_sweep(c->loss, false, a, c->stream));
+    HIPCHK(c, launch_sweep(c->loss, a, c->stream));
   }
   if (has_split_columns(c, o.chunk)) {
     ProfScope ps(c, 1);
-    HIPCHK(c, launch_split(c->loss, false, a, c->stream));
+    HIPCHK(c, launch_split(c->loss, a, c->stream));
   }
   return PCDN_OK;
 }
@@ -300,22 +300,30 @@ int build_bundle_rows(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t
 
 // ||grad^S F(w)||_1 over all features into c->scal[0] (w == nullptr: w = 0);
 // `it` (nullable) is advanced by the final reduction.
-SweepArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
-  SweepArgs a = sweep_args(c, o);
+StopArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
+  StopArgs a{};
+  a.ri = c->ri;
+  a.v = c->v;
+  a.ccol = c->ccol;
+  a.cp = c->cp;
+  a.y = c->y;
+  a.cache = c->cache;
   a.w = w;
-  a.chunks = c->id_chunks;
-  a.cstart = c->id_cstart;
-  a.slot_lo = 0;
-  a.slot_hi = c->p;
+  a.p = c->p;
+  a.nnz = c->nnz;
+  a.sg = c->tmp_p;
+  a.part = c->part;
+  a.C = c->C;
+  a.ra = o.ra();
+  a.rb = o.rb();
   return a;
 }
 
 int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) {
-  const SweepArgs a = stop_args(c, o, w);
+  const StopArgs a = stop_args(c, o, w);
   {
     ProfScope ps(c, 4);
-    HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
-    if (has_split_columns(c, kChunk)) HIPCHK(c, launch_split(c->loss, true, a, c->stream));
+    HIPCHK(c, launch_stop_sweep(c->loss, a, c->stream));
   }
   HIPCHK(c, launch_sum(c->tmp_p, c->p, c->sum_part, c->scal, it, c->stream));
   return PCDN_OK;
@@ -325,13 +333,12 @@ int launch_stopping(pcdn_ctx* c, const Opts& o, const double* w, IterState* it) 
 // active mask (threshold scal[4] of the previous iteration), the largest
 // violation, the next threshold, active count and nonzeros (scal[0..6]).
 int launch_stopping_shrink(pcdn_ctx* c, const Opts& o, IterState* it) {
-  SweepArgs a = stop_args(c, o, c->w);
+  StopArgs a = stop_args(c, o, c->w);
   a.act = c->act;
   a.thr = c->scal + 4;
   {
     ProfScope ps(c, 4);
-    HIPCHK(c, launch_sweep(c->loss, true, a, c->stream));
-    if (has_split_columns(c, kChunk)) HIPCHK(c, launch_split(c->loss, true, a, c->stream));
+    HIPCHK(c, launch_stop_sweep(c->loss, a, c->stream));
   }
   const StopSumArgs s{c->tmp_p, c->act, c->cp, c->p, c->n, c->stop_part, c->scal, it,
                       sum_grid(c->p), o.ra()};
@@ -566,8 +573,6 @@ int enqueue_bundles(pcdn_ctx* c, const Opts& o, int64_t P) {
 
 // After the bundles: scatter counters and the stopping sweep.
 int enqueue_post(pcdn_ctx* c, const Opts& o, int64_t P, IterState* it) {
-  HIPCHK(c, launch_scatter_count(c->d, c->idx0, c->cp, c->p, o.shrink ? c->scal + 5 : nullptr,
-                                 o.chunk, c->stats, c->stream));
   if (o.shrink) return launch_stopping_shrink(c, o, it);
   return launch_stopping(c, o, c->w, it);
 }
@@ -643,19 +648,16 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     t.kind = kTaskRowsApply;
     out.push_back(t);
   }
-  Task t = task(kTaskScatterCount, scatter_count_grid(c->p), 0);
-  t.u.sc = ScatterCountArgs{c->d, c->idx0, c->cp, c->p, c->stats,
-                            o.shrink ? c->scal + 5 : nullptr, o.chunk};
-  out.push_back(t);
-  t = task(kTaskSweepStop, sweep_grid(c->p), 0);
-  t.u.sw = stop_args(c, o, c->w);
+  Task t = task(kTaskStopRanges, stop_ranges_grid(c->nnz), 0);
+  t.u.so = stop_args(c, o, c->w);
   if (o.shrink) {
-    t.u.sw.act = c->act;
-    t.u.sw.thr = c->scal + 4;
+    t.u.so.act = c->act;
+    t.u.so.thr = c->scal + 4;
   }
+  if (c->nnz > 0) out.push_back(t);
+  t.kind = kTaskStopFinish;
+  t.nblk = stop_finish_grid(c->p);
   out.push_back(t);
-  t.kind = kTaskSplitStop;
-  if (has_split_columns(c, kChunk)) out.push_back(t);
   const int sb = sum_grid(c->p);
   if (o.shrink) {
     t = task(kTaskStopPartial, sb, 0);
@@ -805,16 +807,15 @@ double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& 
   const double n_rows = (double)(s.rows_touched_narrow - b.rows_touched_narrow);
   const double d_nnz_gh = std::max(0.0, h.nnz_gh - hb.nnz_gh - n_nnz_gh);
   const double d_slots = std::max(0.0, h.slots - hb.slots - n_slots);
-  const double d_fused = std::max(0.0, (double)(s.nnz_scat_fused - b.nnz_scat_fused) - n_fused);
-  const double d_split = std::max(0.0, (double)(s.nnz_scat_split - b.nnz_scat_split) - n_long);
+  const double d_scat = (double)(s.nnz_scat_rows - b.nnz_scat_rows);
   const double d_rows = (double)(s.rows_touched - b.rows_touched) - n_rows;
   const double d_stop = h.nnz_stop - hb.nnz_stop;
   const double d_sweeps = h.stop_sweeps - hb.stop_sweeps;
   switch (cls) {
-    case 0: return kBytesPerNnzSweep * d_nnz_gh + kBytesPerSlotSweep * d_slots +
-                   kBytesPerNnzScatter * d_fused;
-    case 1: return kBytesPerNnzScatter * d_split;
-    case 2: return kBytesPerRowLs * d_rows + kBytesPerSlotLs * d_slots;
+    case 0: return kBytesPerNnzSweep * d_nnz_gh + kBytesPerSlotSweep * d_slots;
+    case 1: return 0.0;  // finishes the split columns from partials already counted
+    case 2: return kBytesPerNnzScatter * d_scat + kBytesPerRowLs * d_rows +
+                   kBytesPerSlotLs * d_slots;
     case 3: return kBytesPerRowApply * d_rows + kBytesPerSlotApply * d_slots;
     case 4: return kBytesPerNnzStop * d_stop + kBytesPerFeatStop * (double)p * d_sweeps;
     case 5: return kBytesPerNnzSweep * n_nnz_gh + kBytesPerSlotSweep * n_slots +
@@ -1030,9 +1031,9 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
       8 * p,                                               // w in partition order
       2 * nnz, 4 * (p + 1),                                // bundle-local row ids
-      8 * (int64_t)kRowsGridMax * (2 * kQMax + 2),         // line-search partials
+      8 * (int64_t)kRowsGridMax * (2 * kQMax + 3),         // line-search partials
       8 * p,                                               // active mask (shrinking)
-      8 * (n + 1), 4 * nnz, 4 * nnz, 4 * nnz,              // CSR copy
+      8 * (n + 1), 4 * nnz, 4 * nnz, 4 * nnz, 4 * nnz,     // CSR copy, column of each nonzero
       4 * p, 12 * nnz, 12 * nnz, 4 * br_m,                 // bundle-row order, sort buffers
       4 * ((nnz + kRangeW - 1) / kRangeW + 1), 12 * (nnz + kRangeW)};  // touched rows
   int64_t total = 64 * 1024;
@@ -1149,9 +1150,10 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->plid, nnz);
   ALLOC(c, c->pR, p + 1);
-  ALLOC(c, c->ls_part, (size_t)kRowsGridMax * (2 * kQMax + 2));
+  ALLOC(c, c->ls_part, (size_t)kRowsGridMax * (2 * kQMax + 3));
   ALLOC(c, c->act, p);
   ALLOC(c, c->rp, n + 1);
+  ALLOC(c, c->ccol, nnz);
   ALLOC(c, c->rr, nnz);
   ALLOC(c, c->rc, nnz);
   ALLOC(c, c->rv, nnz);
@@ -1189,6 +1191,10 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
     for (int64_t i = 0; i < n; ++i) c->xrow = std::max(c->xrow, l1[i]);
     HIPCHK(c, hipMemcpy(c->rp, hrp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
     if (nnz) {
+      std::vector<int32_t> hcc(nnz);
+      for (int64_t j = 0; j < p; ++j)
+        for (int64_t k = Hcp[j]; k < Hcp[j + 1]; ++k) hcc[k] = (int32_t)j;
+      HIPCHK(c, hipMemcpy(c->ccol, hcc.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
       HIPCHK(c, hipMemcpy(c->rr, hrr.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
       HIPCHK(c, hipMemcpy(c->rc, hrc.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
       HIPCHK(c, hipMemcpy(c->rv, hrv.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
@@ -1301,8 +1307,6 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
                                     c->stream));
     }
   }
-  HIPCHK(c, launch_scatter_count(c->d, c->step_perm, c->cp, P, nullptr, o.chunk, c->stats,
-                                 c->stream));
   double swept = 0.0;
   for (int64_t t = 0; t < P; ++t) swept += (double)(c->h_cp[bundle[t] + 1] - c->h_cp[bundle[t]]);
   c->hc.nnz_gh += swept;

@@ -52,8 +52,8 @@ struct Stats {
   unsigned long long bundles;        // inner iterations
   unsigned long long ls_steps;       // candidates tested (q + 1, or max_ls on failure)
   unsigned long long ls_fail;        // inner iterations without an accepted step
-  unsigned long long nnz_scat_fused; // nonzeros scattered into d^T x by the sweep kernel
-  unsigned long long nnz_scat_split; // nonzeros scattered by the split-column kernel
+  unsigned long long nnz_scat_rows;  // nonzeros with d_j != 0 in the multi-kernel d^T x pass
+  unsigned long long nnz_unused;
   unsigned long long rows_touched;   // rows with d^T x_i != 0, summed over bundles
   // counted by the single-workgroup kernel for its own bundles (the others
   // above count every bundle of any schedule)
@@ -87,7 +87,7 @@ struct SweepArgs {
   const float* v;
   const int8_t* y;
   const double* cache;
-  const double* w;            // nullable: treated as zero
+  const double* w;
   const Chunk* chunks;        // chunk descriptors of the order
   const int32_t* cstart;      // slot -> first chunk, p+1 entries
   int64_t slot_lo, slot_hi;   // this launch covers slots [slot_lo, slot_hi)
@@ -108,6 +108,30 @@ struct SweepArgs {
   const double* p_active;
   double* act;
   const double* thr;
+};
+
+// Stopping sweep (full gradient, every feature) over X in column order, in
+// ranges of kStopW nonzeros, one wavefront per range: a segmented wavefront
+// scan keyed by column sums g_j of the columns that lie inside the range and
+// finishes them; a column that crosses a range boundary leaves a partial
+// (part[m].x: its part in range m when it began before m, part[m].y: when it
+// begins in m and continues), and k_stop_finish completes those and the empty
+// columns, adding the partials in range order.
+constexpr int kStopW = 256;
+struct StopArgs {
+  const int32_t* ri;
+  const float* v;
+  const int32_t* ccol;       // column of each nonzero
+  const int64_t* cp;
+  const int8_t* y;
+  const double* cache;
+  const double* w;           // nullable: treated as zero
+  int64_t p, nnz;
+  double* sg;                // |grad^S_j F|
+  double* act;               // nullable (shrinking): next active mask, threshold *thr
+  const double* thr;
+  double2* part;             // per range
+  double C, ra, rb;
 };
 
 // Multi-kernel bundle after the sweep: the bundle's nonzeros in row order
@@ -135,7 +159,8 @@ struct RowsArgs {
   int32_t* u_cnt;
   int32_t* u_row;
   double* u_dtx;
-  double* part;              // [v * G + block]: Q loss sums, Q regulariser sums, Delta, touched rows
+  double* part;              // [v * G + block]: Q loss sums, Q regulariser sums, Delta, touched
+                             // rows, nonzeros with d_j != 0
   int32_t G;                 // blocks of the d^T x / line-search launch
   StepState* st;
   Stats* stats;
@@ -160,6 +185,7 @@ struct BrArgs {
   int32_t* dslot;
   float* dval;
   int32_t* hist;             // [256][ntiles] digit counts, scanned between the passes
+  int32_t* slot_out;         // pass 0 histogram: the slots, in source order
   int64_t m, ntiles, P;
   int32_t shift, nb;
 };
@@ -182,15 +208,6 @@ struct IslotArgs {           // islot[perm[r]] = r for r < p
   int32_t* islot;
 };
 
-struct ScatterCountArgs {
-  const double* d;           // per-slot directions
-  const int32_t* perm;       // slot -> feature
-  const int64_t* cp;
-  int64_t p;                 // slots
-  Stats* stats;
-  const double* p_active;    // nullable: slots clipped to the first *p_active
-  int32_t chunk;             // longer columns count as split
-};
 
 // Stopping reduction with shrinking: sums ||grad^S F||_1 = sum sg, the
 // largest violation M = max sg, and the next iteration's active count and
@@ -258,12 +275,11 @@ struct ChunkArgs {
 // would have (nblk blocks; the line search's grid is gx x nblk/gx).
 enum TaskKind : int32_t {
   kTaskSweep = 0,
-  kTaskSweepStop,
+  kTaskStopRanges,
   kTaskSplit,
-  kTaskSplitStop,
+  kTaskStopFinish,
   kTaskRowsDtx,
   kTaskRowsApply,
-  kTaskScatterCount,
   kTaskSumPartial,
   kTaskSumFinal,
   kTaskStopPartial,
@@ -290,12 +306,12 @@ struct Task {
   int32_t gx;
   union {
     SweepArgs sw;
+    StopArgs so;
     RowsArgs rw;
     BrArgs br;
     SlotLenArgs sl;
     WidenArgs wd;
     IslotArgs is;
-    ScatterCountArgs sc;
     SumArgs sum;
     StopSumArgs stop;
     PermKeysArgs pk;
@@ -388,9 +404,12 @@ hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int3
                          int32_t* nch, int32_t* cstart, Chunk* chunks, int32_t* tmp,
                          hipStream_t s);
 int sweep_grid(int64_t slots);
-hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
-hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s);
-int scatter_count_grid(int64_t p);
+hipError_t launch_sweep(int loss, const SweepArgs& a, hipStream_t s);
+// The stopping sweep (both kernels) and the grids they take.
+int stop_ranges_grid(int64_t nnz);
+int stop_finish_grid(int64_t p);
+hipError_t launch_stop_sweep(int loss, const StopArgs& a, hipStream_t s);
+hipError_t launch_split(int loss, const SweepArgs& a, hipStream_t s);
 int sum_grid(int64_t m);
 // Blocks of the d^T x / line-search launch for bundles of about `nnz_bundle`
 // nonzeros (RowsArgs::G).
@@ -447,11 +466,6 @@ hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, con
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, const double* w, double* pw,
                           hipStream_t s);
-// Nonzeros of the features with d != 0 (slots 0..p of perm) into stats:
-// columns of <= chunk nonzeros count as fused, longer ones as split.
-hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, const double* p_active, int32_t chunk, Stats* stats,
-                                hipStream_t s);
 // Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,
                       hipStream_t s);

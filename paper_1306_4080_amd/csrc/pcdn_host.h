@@ -104,6 +104,7 @@ struct pcdn_ctx {
   // X in CSR order (warm-start margins, and the source of the bundle-row
   // order): row pointers, and per nonzero its row, column and value
   int64_t* rp = nullptr;
+  int32_t* ccol = nullptr;  // column of each nonzero in CSC order (stopping sweep)
   int32_t* rr = nullptr;
   int32_t* rc = nullptr;
   float* rv = nullptr;

@@ -74,6 +74,23 @@ __device__ inline void seg_scan(double& g, double& h, int32_t key) {
   seg_scan_step<0x143, 0xc>(g, h, key);
 }
 
+// Segmented inclusive scan of one value (the step sequence of seg_scan).
+template <int CTRL, int ROW_MASK>
+__device__ inline void seg_scan1_step(double& g, int32_t key) {
+  const int32_t k2 = __builtin_amdgcn_update_dpp(-1, key, CTRL, ROW_MASK, 0xf, false);
+  const double g2 = dpp_f64<CTRL, ROW_MASK, 0xf>(g);
+  if (k2 == key) g += g2;
+}
+
+__device__ inline void seg_scan1(double& g, int32_t key) {
+  seg_scan1_step<0x111, 0xf>(g, key);
+  seg_scan1_step<0x112, 0xf>(g, key);
+  seg_scan1_step<0x114, 0xf>(g, key);
+  seg_scan1_step<0x118, 0xf>(g, key);
+  seg_scan1_step<0x142, 0xa>(g, key);
+  seg_scan1_step<0x143, 0xc>(g, key);
+}
+
 // Key of the next lane (wave_shl1); lane 63 reads -2.
 __device__ inline int32_t next_lane_key(int32_t key) {
   return __builtin_amdgcn_update_dpp(-2, key, 0x130, 0xf, 0xf, false);
@@ -90,6 +107,16 @@ __device__ inline double block_sum(double v, double* lds4) {
   const double r = ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
   __syncthreads();
   return r;
+}
+
+// p[i] when ok, else def, with the load itself unconditional (index 0
+// stands in for i; every array has at least one element): a conditional
+// load ends its basic block and the wavefront then waits for it before the
+// next load issues, which serialises the loads that should overlap.
+template <class T>
+__device__ __forceinline__ T ldz(const T* p, bool ok, int64_t i, T def) {
+  const T x = p[ok ? i : 0];
+  return ok ? x : def;
 }
 
 // Wave-uniform value as a scalar (lets descriptor loads become scalar loads).
@@ -532,15 +559,15 @@ __device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi,
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t kk = k + (int64_t)u * kWave;
       const bool ok = kk < khi;
-      row[u] = ok ? a.ri[kk] : -1;
-      xv[u] = ok ? a.v[kk] : 0.0f;
+      row[u] = ldz(a.ri, ok, kk, -1);
+      xv[u] = ldz(a.v, ok, kk, 0.0f);
     }
     double cv[kUnroll];
     int yv[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      cv[u] = row[u] >= 0 ? a.cache[row[u]] : 0.0;
-      yv[u] = row[u] >= 0 ? (int)a.y[row[u]] : 0;
+      cv[u] = ldz(a.cache, row[u] >= 0, row[u], 0.0);
+      yv[u] = (int)ldz(a.y, row[u] >= 0, row[u], (int8_t)0);
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
@@ -548,11 +575,12 @@ __device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi,
   }
 }
 
-// g, h from the summed column terms; writes the per-feature outputs (lane 0)
-// and returns the direction (0 in stopping mode).
-template <int LOSS, bool STOP>
-__device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, double gs,
-                                        double hs, bool writer) {
+// g, h from the summed column terms (eq. (11); SVM: eq. (3) and the
+// generalised Hessian), the direction (eq. (5)) and the Delta term (eq. (7));
+// lane 0 writes the per-slot outputs.
+template <int LOSS>
+__device__ inline void finish_feature(const SweepArgs& a, const Chunk& ch, double gs, double hs,
+                                      double wj, bool writer) {
   double g, h;
   if (LOSS == kLogistic) {
     g = a.C * gs;
@@ -562,23 +590,14 @@ __device__ inline double finish_feature(const SweepArgs& a, const Chunk& ch, dou
     h = 2.0 * a.C * hs;
   }
   if (h <= 0.0) h += a.nu;
-  const double wj = a.w ? a.w[ch.feat] : 0.0;
-  const int64_t o = ch.slot;
-  if (STOP) {
-    if (writer) {
-      a.sg[o] = fabs(min_norm_subgradient(g, wj, a.ra, a.rb));
-      if (a.act) a.act[o] = (wj != 0.0 || fabs(g) >= *a.thr) ? 1.0 : 0.0;
-    }
-    return 0.0;
-  }
   const double dj = newton_dir(g, h, wj, a.ra, a.rb);
   if (writer) {
+    const int64_t o = ch.slot;
     a.g[o] = g;
     a.h[o] = h;
     a.d[o] = dj;
     a.dterm[o] = g * dj + a.gamma * h * dj * dj + reg_change(wj, dj, a.ra, a.rb);
   }
-  return dj;
 }
 
 // Last slot of a launch's range, clipped to the active features when
@@ -592,7 +611,16 @@ __device__ inline int64_t clipped_hi(int64_t hi, const double* p_active) {
 // Kernel bodies take the block index and block count of their launch as
 // arguments, so that the multi-problem executor (k_exec) can run them on a
 // slice of its grid with exactly the work split of a launch of their own.
-template <int LOSS, bool STOP>
+//
+// Bundle sweep: a wavefront takes kSweepGroup consecutive chunks at a time
+// and issues their loads together (descriptors, then w and the first 128
+// nonzeros of each, then the retained quantities and labels of their rows):
+// short columns would otherwise cost one chain of dependent round trips
+// each.  Entries past the first 128 of a chunk (chunks longer than the
+// default) follow in the same per-lane order.
+constexpr int kSweepGroup = 4;
+
+template <int LOSS>
 __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
   const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
@@ -601,29 +629,69 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
   if (hi <= a.slot_lo) return;
   const int32_t c_lo = a.cstart[a.slot_lo];
   const int32_t c_hi = a.cstart[hi];
-  for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
-    const Chunk ch = a.chunks[c];
-    const int64_t khi = ch.klo + ch.len;
-    double gs = 0.0, hs = 0.0;
-    sweep_range<LOSS>(a, ch.klo, khi, lane, gs, hs);
-    gs = wave_sum(gs);
-    hs = wave_sum(hs);
-    if (ch.nch > 1) {
-      if (lane == 0) a.part[c] = make_double2(gs, hs);
-      continue;
+  for (int64_t c0 = c_lo + wave * kSweepGroup; c0 < c_hi; c0 += nwaves * kSweepGroup) {
+    Chunk ch[kSweepGroup];
+#pragma unroll
+    for (int g = 0; g < kSweepGroup; ++g) {
+      // past the end: the first chunk again, with no nonzeros and no output
+      ch[g] = a.chunks[c0 + g < c_hi ? c0 + g : c_lo];
+      if (c0 + g >= c_hi) ch[g].len = 0;
     }
-    (void)finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0);
+    double wj[kSweepGroup];
+    int32_t row[kSweepGroup][2];
+    float xv[kSweepGroup][2];
+#pragma unroll
+    for (int g = 0; g < kSweepGroup; ++g) {
+      wj[g] = ldz(a.w, c0 + g < c_hi, ch[g].feat, 0.0);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool ok = lane + u * kWave < ch[g].len;
+        row[g][u] = ldz(a.ri, ok, ch[g].klo + lane + u * kWave, -1);
+        xv[g][u] = ldz(a.v, ok, ch[g].klo + lane + u * kWave, 0.0f);
+      }
+    }
+    double cv[kSweepGroup][2];
+    int yv[kSweepGroup][2];
+#pragma unroll
+    for (int g = 0; g < kSweepGroup; ++g)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        cv[g][u] = ldz(a.cache, row[g][u] >= 0, row[g][u], 0.0);
+        yv[g][u] = (int)ldz(a.y, row[g][u] >= 0, row[g][u], (int8_t)0);
+      }
+    double gs[kSweepGroup], hs[kSweepGroup];
+#pragma unroll
+    for (int g = 0; g < kSweepGroup; ++g) {
+      gs[g] = 0.0;
+      hs[g] = 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+        if (row[g][u] >= 0) grad_hess_term<LOSS>(cv[g][u], yv[g][u], (double)xv[g][u], gs[g], hs[g]);
+      if (ch[g].len > 2 * kWave)
+        sweep_range<LOSS>(a, ch[g].klo + 2 * kWave, ch[g].klo + ch[g].len, lane, gs[g], hs[g]);
+    }
+#pragma unroll
+    for (int g = 0; g < kSweepGroup; ++g) {
+      if (c0 + g >= c_hi) break;
+      const double gt = wave_sum(gs[g]);
+      const double ht = wave_sum(hs[g]);
+      if (ch[g].nch > 1) {
+        if (lane == 0) a.part[c0 + g] = make_double2(gt, ht);
+        continue;
+      }
+      finish_feature<LOSS>(a, ch[g], gt, ht, wj[g], lane == 0);
+    }
   }
 }
 
-template <int LOSS, bool STOP>
+template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
-  sweep_body<LOSS, STOP>(a, blockIdx.x, gridDim.x);
+  sweep_body<LOSS>(a, blockIdx.x, gridDim.x);
 }
 
 // Split columns: the first wavefront of a split feature sums its chunk
 // partials in chunk order and finishes the feature.
-template <int LOSS, bool STOP>
+template <int LOSS>
 __device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
   const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
@@ -643,41 +711,150 @@ __device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int6
     }
     gs = wave_sum(gs);
     hs = wave_sum(hs);
-    (void)finish_feature<LOSS, STOP>(a, ch, gs, hs, lane == 0);
+    finish_feature<LOSS>(a, ch, gs, hs, a.w[ch.feat], lane == 0);
   }
 }
 
-template <int LOSS, bool STOP>
+template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
-  split_body<LOSS, STOP>(a, blockIdx.x, gridDim.x);
+  split_body<LOSS>(a, blockIdx.x, gridDim.x);
 }
 
-// Nonzeros scattered into d^T x during one outer iteration (features with
-// d_j != 0; split columns counted apart), one atomic per block.
-__device__ __forceinline__ void scatter_count_body(const ScatterCountArgs& a, int64_t bid,
-                                                   int64_t nblk) {
-  __shared__ double lds4[kWavesPerBlock];
-  double fused = 0.0, split = 0.0;
-  const int64_t p = clipped_hi(a.p, a.p_active);
-  for (int64_t r = bid * kBlock + threadIdx.x; r < p; r += nblk * kBlock) {
-    if (a.d[r] == 0.0) continue;
-    const int32_t j = a.perm[r];
-    const double len = (double)(a.cp[j + 1] - a.cp[j]);
-    if (len > a.chunk)
-      split += len;
-    else
-      fused += len;
+// ---------------------------------------------------------------------------
+// stopping sweep over X in column order (see StopArgs)
+// ---------------------------------------------------------------------------
+// Gradient contribution of one nonzero (grad_hess_term without h).
+template <int LOSS>
+__device__ inline double grad_term(double c, int yi, double x) {
+  if (LOSS == kLogistic) {
+    double s0, s1;
+    logistic_weights(c, s0, s1);
+    return (yi > 0 ? -s0 : s1) * x;
   }
-  fused = block_sum(fused, lds4);
-  split = block_sum(split, lds4);
-  if (threadIdx.x == 0) {
-    if (fused > 0.0) atomicAdd(&a.stats->nnz_scat_fused, (unsigned long long)fused);
-    if (split > 0.0) atomicAdd(&a.stats->nnz_scat_split, (unsigned long long)split);
+  return c > 0.0 ? (yi > 0 ? c : -c) * x : 0.0;  // y_i b_i x_ij on the active set
+}
+
+template <int LOSS>
+__device__ inline void stop_finish_one(const StopArgs& a, int64_t j, double gs) {
+  const double g = LOSS == kLogistic ? a.C * gs : -2.0 * a.C * gs;
+  const double wj = a.w ? a.w[j] : 0.0;
+  a.sg[j] = fabs(min_norm_subgradient(g, wj, a.ra, a.rb));
+  if (a.act) a.act[j] = (wj != 0.0 || fabs(g) >= *a.thr) ? 1.0 : 0.0;
+}
+
+// Wavefront w of the launch takes ranges w, w + nwaves, ...; the loads of a
+// range's four rounds are issued together.
+template <int LOSS>
+__device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid, int64_t nblk) {
+  constexpr int kR = kStopW / kWave;
+  const int lane = lane_id();
+  const int64_t nr = (a.nnz + kStopW - 1) / kStopW;
+  const int64_t nwaves = nblk * kWavesPerBlock;
+  for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
+    const int64_t rb = m * kStopW;
+    const int64_t re = rb + kStopW < a.nnz ? rb + kStopW : a.nnz;
+    int32_t col[kR], row[kR];
+    float xv[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      const int64_t k = rb + u * kWave + lane;
+      const bool in = k < re;
+      col[u] = ldz(a.ccol, in, k, -1);
+      row[u] = ldz(a.ri, in, k, 0);
+      xv[u] = ldz(a.v, in, k, 0.0f);
+    }
+    // columns open at the range's ends
+    const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
+    const int32_t right = re < a.nnz ? a.ccol[re] : -1;
+    double cv[kR];
+    int yv[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      cv[u] = ldz(a.cache, col[u] >= 0, row[u], 0.0);
+      yv[u] = (int)ldz(a.y, col[u] >= 0, row[u], (int8_t)0);
+    }
+    int32_t ccar = -1;  // column carried into the next round
+    double gcar = 0.0;
+    double pf = 0.0, pl = 0.0;
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      if (rb + u * kWave >= re) break;
+      double gs = col[u] >= 0 ? grad_term<LOSS>(cv[u], yv[u], (double)xv[u]) : 0.0;
+      seg_scan1(gs, col[u]);
+      if (ccar >= 0 && col[u] == ccar) gs += gcar;
+      // column of the next nonzero of the range (-1: none): the next lane's,
+      // for lane 63 the next round's first
+      const int32_t next0 = u + 1 < kR ? __builtin_amdgcn_readlane(col[u + 1], 0) : -1;
+      int32_t nxt = next_lane_key(col[u]);
+      if (lane == kWave - 1) nxt = next0;
+      const int64_t k = rb + u * kWave + lane;
+      const bool seg_end = col[u] >= 0 && nxt != col[u];
+      // the segment at lane 63 that goes on into the next round
+      const int32_t c63 = __builtin_amdgcn_readlane(col[u], kWave - 1);
+      const bool open63 = c63 >= 0 && next0 == c63;
+      const unsigned long long gb = (unsigned long long)__double_as_longlong(gs);
+      const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(gb & 0xffffffffull), kWave - 1);
+      const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(gb >> 32), kWave - 1);
+      ccar = open63 ? c63 : -1;
+      gcar = open63 ? __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) : 0.0;
+      if (seg_end) {
+        const bool lopen = col[u] == left;
+        const bool ropen = col[u] == right && k + 1 == re;
+        if (lopen)
+          pf = gs;  // (also when right-open: a column through the whole range)
+        else if (ropen)
+          pl = gs;
+        else
+          stop_finish_one<LOSS>(a, col[u], gs);
+      }
+    }
+    // the partials (held by the lanes that ended the open segments)
+    const uint64_t mf = __ballot(pf != 0.0), ml = __ballot(pl != 0.0);
+    double2 pr = make_double2(0.0, 0.0);
+    if (mf) {
+      const int src = __builtin_ctzll(mf);
+      const unsigned long long b = (unsigned long long)__double_as_longlong(pf);
+      const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+      const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+      pr.x = __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
+    }
+    if (ml) {
+      const int src = __builtin_ctzll(ml);
+      const unsigned long long b = (unsigned long long)__double_as_longlong(pl);
+      const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+      const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+      pr.y = __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
+    }
+    if (lane == 0) a.part[m] = pr;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_count(ScatterCountArgs a) {
-  scatter_count_body(a, blockIdx.x, gridDim.x);
+template <int LOSS>
+__global__ __launch_bounds__(kBlock) void k_stop_ranges(StopArgs a) {
+  stop_ranges_body<LOSS>(a, blockIdx.x, gridDim.x);
+}
+
+// Columns that cross a range boundary (the partials in range order) and
+// empty columns (g_j = 0); one thread per column.
+template <int LOSS>
+__device__ __forceinline__ void stop_finish_body(const StopArgs& a, int64_t bid, int64_t nblk) {
+  for (int64_t j = bid * kBlock + threadIdx.x; j < a.p; j += nblk * kBlock) {
+    const int64_t k0 = a.cp[j], k1 = a.cp[j + 1];
+    if (k1 == k0) {
+      stop_finish_one<LOSS>(a, j, 0.0);
+      continue;
+    }
+    const int64_t m1 = k0 / kStopW, m2 = (k1 - 1) / kStopW;
+    if (m1 == m2) continue;  // finished by its range
+    double gs = a.part[m1].y;
+    for (int64_t m = m1 + 1; m <= m2; ++m) gs += a.part[m].x;
+    stop_finish_one<LOSS>(a, j, gs);
+  }
+}
+
+template <int LOSS>
+__global__ __launch_bounds__(kBlock) void k_stop_finish(StopArgs a) {
+  stop_finish_body<LOSS>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,23 +871,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter_count(ScatterCountArgs a) {
 // land at part[v * G + block] and are summed in block order by every block
 // of the apply, which takes the Armijo decision (eq. (6)) identically.
 // ---------------------------------------------------------------------------
-// Segmented inclusive scan of one value (the step sequence of seg_scan).
-template <int CTRL, int ROW_MASK>
-__device__ inline void seg_scan1_step(double& g, int32_t key) {
-  const int32_t k2 = __builtin_amdgcn_update_dpp(-1, key, CTRL, ROW_MASK, 0xf, false);
-  const double g2 = dpp_f64<CTRL, ROW_MASK, 0xf>(g);
-  if (k2 == key) g += g2;
-}
-
-__device__ inline void seg_scan1(double& g, int32_t key) {
-  seg_scan1_step<0x111, 0xf>(g, key);
-  seg_scan1_step<0x112, 0xf>(g, key);
-  seg_scan1_step<0x114, 0xf>(g, key);
-  seg_scan1_step<0x118, 0xf>(g, key);
-  seg_scan1_step<0x142, 0xa>(g, key);
-  seg_scan1_step<0x143, 0xc>(g, key);
-}
-
 // Orders this wavefront's LDS accesses (the queue below is wave-private).
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -732,32 +892,74 @@ __device__ inline void row_ls_terms(double c, int yi, double dl, double beta, in
   }
 }
 
+// A wavefront's queue of finished rows in LDS: row, d^T x_i, retained
+// quantity and label.
+struct RowQueue {
+  int32_t row[2 * kWave];
+  int32_t y[2 * kWave];
+  double dtx[2 * kWave];
+  double c[2 * kWave];
+};
+
 // n <= 64 queued rows (lane i takes queue entry i): list them for the apply
 // and add their line-search terms.
 template <int LOSS>
-__device__ inline void rows_flush(const RowsArgs& a, const int32_t* qrow, const double* qdtx,
-                                  int n, int64_t ubase, int nq, double (&acc)[kQGroup],
-                                  double& touched) {
+__device__ inline void rows_flush(const RowsArgs& a, const RowQueue& qu, int n, int64_t ubase,
+                                  int nq, double (&acc)[kQGroup], double& touched) {
   const int lane = lane_id();
   if (lane < n) {
-    const int32_t row = qrow[lane];
-    const double dl = qdtx[lane];
-    a.u_row[ubase + lane] = row;
+    const double dl = qu.dtx[lane];
+    a.u_row[ubase + lane] = qu.row[lane];
     a.u_dtx[ubase + lane] = dl;
-    const double c = a.cache[row];
-    const int yi = a.y[row];
     touched += 1.0;
-    row_ls_terms<LOSS>(c, yi, dl, a.beta, nq, acc);
+    row_ls_terms<LOSS>(qu.c[lane], qu.y[lane], dl, a.beta, nq, acc);
   }
 }
 
+// One round of 64 nonzeros of a range: the segmented row sums (carried across
+// rounds), and the rows that end in it queued.  Returns the number queued.
+__device__ inline int rows_round(const RowsArgs& a, RowQueue& qu, int qn, int32_t row, bool owned,
+                                 double t, double c, int yi, int64_t k, int64_t e1,
+                                 int32_t& crow, double& cval) {
+  const int lane = lane_id();
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int32_t key = owned ? row : -1;
+  seg_scan1(t, key);
+  if (crow >= 0 && key == crow) t += cval;
+  // the row ends at this nonzero unless the next one is of the same row
+  int32_t nxt = next_lane_key(key);
+  if (lane == kWave - 1) nxt = k + 1 < e1 ? a.br_row[k + 1] : -2;
+  const bool ends = owned && nxt != row;
+  const int32_t row63 = __builtin_amdgcn_readlane(key, kWave - 1);
+  const bool open63 = __builtin_amdgcn_readlane((int)(owned && !ends), kWave - 1) != 0;
+  const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
+  const unsigned lo63 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(tb & 0xffffffffull), kWave - 1);
+  const unsigned hi63 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(tb >> 32), kWave - 1);
+  crow = open63 ? row63 : -1;
+  cval = open63 ? __longlong_as_double((long long)(((unsigned long long)hi63 << 32) | lo63)) : 0.0;
+  // queue the finished rows with d^T x_i != 0 (a zero changes nothing)
+  const bool done = ends && t != 0.0;
+  const uint64_t m = __ballot(done);
+  if (done) {
+    const int pos = qn + __popcll(m & lt_mask);
+    qu.row[pos] = row;
+    qu.y[pos] = yi;
+    qu.dtx[pos] = t;
+    qu.c[pos] = c;
+  }
+  return __popcll(m);
+}
+
 // Block bx of the G-block launch: wavefront w = bx * 4 + wave takes ranges
-// w, w + 4G, ... of the bundle's nonzeros.
+// w, w + 4G, ... of the bundle's nonzeros.  The loads of a range's four
+// rounds are issued together (rows, slots and values, then the directions
+// and the rows' retained quantities and labels), so a range costs two
+// dependent round trips to memory.
 template <int LOSS>
 __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
-  __shared__ int32_t qrow[kWavesPerBlock][2 * kWave];
-  __shared__ double qdtx[kWavesPerBlock][2 * kWave];
-  __shared__ double red[kWavesPerBlock][kQGroup + 1];
+  constexpr int kR = kRangeW / kWave;
+  __shared__ RowQueue queue[kWavesPerBlock];
+  __shared__ double red[kWavesPerBlock][kQGroup + 2];
   const int64_t hi_act = clipped_hi(a.slot_hi, a.p_active);
   if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: the apply skips it too
   const int lane = lane_id(), wv = wave_in_block();
@@ -766,73 +968,99 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   const int64_t nwaves = (int64_t)G * kWavesPerBlock;
-  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  int32_t* qr = qrow[wv];
-  double* qd = qdtx[wv];
+  RowQueue& qu = queue[wv];
   double acc[kQGroup];
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
-  double touched = 0.0;
+  double touched = 0.0, nz_d = 0.0;
   for (int64_t r = (int64_t)bx * kWavesPerBlock + wv; r < nr; r += nwaves) {
     const int64_t rb = e0 + r * kRangeW;
     const int64_t re = rb + kRangeW < e1 ? rb + kRangeW : e1;
     // rows owned by this range: those whose first nonzero lies in [rb, re);
     // the range's first row may have started earlier (skip), its last row
     // may continue past re (tail)
+    int32_t prow[kR], psl[kR];
+    float pv[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      const int64_t k = rb + u * kWave + lane;
+      prow[u] = ldz(a.br_row, k < e1, k, -1);
+      psl[u] = ldz(a.br_slot, k < e1, k, -1);
+      pv[u] = ldz(a.br_val, k < e1, k, 0.0f);
+    }
     const int32_t skip = rb > e0 ? a.br_row[rb - 1] : -1;
     int32_t tail = a.br_row[re - 1];
     if (tail == skip) tail = -1;
+    double pd[kR], pc[kR];
+    int py[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      const bool act = psl[u] >= a.slot_lo && psl[u] < hi_act;
+      pd[u] = ldz(a.d, act, psl[u], 0.0);
+      pc[u] = ldz(a.cache, prow[u] >= 0, prow[u], 0.0);
+      py[u] = (int)ldz(a.y, prow[u] >= 0, prow[u], (int8_t)0);
+    }
     int qn = 0;            // rows queued in LDS
     int32_t listed = 0;    // rows listed for this range
     int32_t crow = -1;     // row carried into the next round
     double cval = 0.0;
-    for (int64_t s0 = rb; s0 < re || crow >= 0; s0 += kWave) {
+    int64_t s0 = rb;
+#pragma unroll
+    for (int u = 0; u < kR; ++u, s0 += kWave) {
+      if (s0 >= re && crow < 0) break;
       const int64_t k = s0 + lane;
-      const bool in = k < e1;
-      const int32_t row = in ? a.br_row[k] : -1;
-      const bool owned = in && row != skip && (k < re || row == tail);
-      double t = 0.0;
-      if (owned) {
-        const int32_t sl = a.br_slot[k];
-        if (sl >= a.slot_lo && sl < hi_act) t = a.d[sl] * (double)a.br_val[k];
-      }
-      const int32_t key = owned ? row : -1;
-      seg_scan1(t, key);
-      if (crow >= 0 && key == crow) t += cval;
-      // the row ends at this nonzero unless the next one is of the same row
-      int32_t nxt = next_lane_key(key);
-      if (lane == kWave - 1) nxt = k + 1 < e1 ? a.br_row[k + 1] : -2;
-      const bool ends = owned && nxt != row;
-      const int32_t row63 = __builtin_amdgcn_readlane(key, kWave - 1);
-      const bool open63 = __builtin_amdgcn_readlane((int)(owned && !ends), kWave - 1) != 0;
-      const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
-      const unsigned lo63 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(tb & 0xffffffffull), kWave - 1);
-      const unsigned hi63 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(tb >> 32), kWave - 1);
-      crow = open63 ? row63 : -1;
-      cval = open63 ? __longlong_as_double((long long)(((unsigned long long)hi63 << 32) | lo63)) : 0.0;
-      // queue the finished rows with d^T x_i != 0 (a zero changes nothing)
-      const bool done = ends && t != 0.0;
-      const uint64_t m = __ballot(done);
-      if (done) {
-        const int pos = qn + __popcll(m & lt_mask);
-        qr[pos] = row;
-        qd[pos] = t;
-      }
-      qn += __popcll(m);
+      const bool owned = k < e1 && prow[u] != skip && (k < re || prow[u] == tail);
+      const double t = owned ? pd[u] * (double)pv[u] : 0.0;
+      nz_d += owned && pd[u] != 0.0 ? 1.0 : 0.0;
+      qn += rows_round(a, qu, qn, prow[u], owned, t, pc[u], py[u], k, e1, crow, cval);
       if (qn >= kWave) {
         wave_lds_sync();
-        rows_flush<LOSS>(a, qr, qd, kWave, r * kRangeW + listed, nq, acc, touched);
+        rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, touched);
         listed += kWave;
         qn -= kWave;
         wave_lds_sync();
         if (lane < qn) {
-          qr[lane] = qr[kWave + lane];
-          qd[lane] = qd[kWave + lane];
+          qu.row[lane] = qu.row[kWave + lane];
+          qu.y[lane] = qu.y[kWave + lane];
+          qu.dtx[lane] = qu.dtx[kWave + lane];
+          qu.c[lane] = qu.c[kWave + lane];
+        }
+      }
+    }
+    // the tail row continues past the loaded rounds (one row only)
+    for (; crow >= 0; s0 += kWave) {
+      const int64_t k = s0 + lane;
+      const int32_t row = k < e1 ? a.br_row[k] : -1;
+      const bool owned = k < e1 && row == tail;
+      double t = 0.0, c = 0.0;
+      int yi = 0;
+      if (owned) {
+        const int32_t sl = a.br_slot[k];
+        if (sl >= a.slot_lo && sl < hi_act) {
+          const double dj = a.d[sl];
+          t = dj * (double)a.br_val[k];
+          nz_d += dj != 0.0 ? 1.0 : 0.0;
+        }
+        c = a.cache[row];
+        yi = (int)a.y[row];
+      }
+      qn += rows_round(a, qu, qn, row, owned, t, c, yi, k, e1, crow, cval);
+      if (qn >= kWave) {
+        wave_lds_sync();
+        rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, touched);
+        listed += kWave;
+        qn -= kWave;
+        wave_lds_sync();
+        if (lane < qn) {
+          qu.row[lane] = qu.row[kWave + lane];
+          qu.y[lane] = qu.y[kWave + lane];
+          qu.dtx[lane] = qu.dtx[kWave + lane];
+          qu.c[lane] = qu.c[kWave + lane];
         }
       }
     }
     wave_lds_sync();
-    rows_flush<LOSS>(a, qr, qd, qn, r * kRangeW + listed, nq, acc, touched);
+    rows_flush<LOSS>(a, qu, qn, r * kRangeW + listed, nq, acc, touched);
     listed += qn;
     if (lane == 0) a.u_cnt[r] = listed;
     wave_lds_sync();
@@ -844,7 +1072,11 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   }
   {
     const double v = wave_sum(touched);
-    if (lane == 0) red[wv][kQGroup] = v;
+    const double z = wave_sum(nz_d);
+    if (lane == 0) {
+      red[wv][kQGroup] = v;
+      red[wv][kQGroup + 1] = z;
+    }
   }
   __syncthreads();
   if (threadIdx.x < nq)
@@ -853,6 +1085,9 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   if (threadIdx.x == kQGroup)
     a.part[(int64_t)(2 * a.Q + 1) * G + bx] =
         ((red[0][kQGroup] + red[1][kQGroup]) + red[2][kQGroup]) + red[3][kQGroup];
+  if (threadIdx.x == kQGroup + 1)
+    a.part[(int64_t)(2 * a.Q + 2) * G + bx] =
+        ((red[0][kQGroup + 1] + red[1][kQGroup + 1]) + red[2][kQGroup + 1]) + red[3][kQGroup + 1];
   __syncthreads();
   // Delta and the regulariser change of the bundle coordinates
   double del = 0.0;
@@ -966,6 +1201,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
     al *= a.beta;
   }
   const double touched = ls_total(a.part, 2 * a.Q + 1, a.G, lds4);
+  const double nz_d = ls_total(a.part, 2 * a.Q + 2, a.G, lds4);
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   bool alone = false;
@@ -983,6 +1219,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
     atomicAdd(&a.stats->ls_steps, (unsigned long long)(q_acc >= 0 ? q_acc + 1 : a.max_ls));
     if (q_acc < 0) atomicAdd(&a.stats->ls_fail, 1ull);
     atomicAdd(&a.stats->rows_touched, (unsigned long long)touched);
+    atomicAdd(&a.stats->nnz_scat_rows, (unsigned long long)nz_d);
   }
   if (q_acc < 0) return;
   const int lane = lane_id();
@@ -1042,24 +1279,41 @@ __global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
     a[i] = v;
 }
 
-__device__ __forceinline__ uint32_t br_digit(const BrArgs& a, int64_t k, int32_t& slot) {
-  const int32_t c = a.scol[k];
-  slot = a.islot ? a.islot[c] : c;
+__device__ __forceinline__ uint32_t br_digit_of(const BrArgs& a, int32_t slot) {
   const uint32_t b = slot >= 0 ? (uint32_t)slot / (uint32_t)a.P : (uint32_t)a.nb;
   return (b >> a.shift) & 255u;
 }
 
+// Digit counts of one tile.  Every round's loads are issued before any is
+// used; with islot (pass 0) the slots are also written out (slot_out, in
+// source order) for the scatter pass, which then needs no gather.
 __device__ __forceinline__ void br_hist_body(const BrArgs& a, int64_t bid) {
   __shared__ int32_t cnt[256];
   cnt[threadIdx.x] = 0;
-  __syncthreads();
   const int64_t base = bid * kBrTile;
+  int32_t sl[kBrRounds];
+#pragma unroll
   for (int r = 0; r < kBrRounds; ++r) {
     const int64_t i = base + r * kSortThreads + threadIdx.x;
-    if (i < a.m) {
-      int32_t slot;
-      atomicAdd(&cnt[br_digit(a, i, slot)], 1);
+    sl[r] = ldz(a.scol, i < a.m, i, 0);
+  }
+  if (a.islot) {
+#pragma unroll
+    for (int r = 0; r < kBrRounds; ++r) {
+      const int64_t i = base + r * kSortThreads + threadIdx.x;
+      sl[r] = ldz(a.islot, i < a.m, sl[r], 0);
     }
+#pragma unroll
+    for (int r = 0; r < kBrRounds; ++r) {
+      const int64_t i = base + r * kSortThreads + threadIdx.x;
+      if (i < a.m) a.slot_out[i] = sl[r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kBrRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < a.m) atomicAdd(&cnt[br_digit_of(a, sl[r])], 1);
   }
   __syncthreads();
   a.hist[(int64_t)threadIdx.x * a.ntiles + bid] = cnt[threadIdx.x];
@@ -1067,6 +1321,8 @@ __device__ __forceinline__ void br_hist_body(const BrArgs& a, int64_t bid) {
 
 __global__ __launch_bounds__(kSortThreads) void k_br_hist(BrArgs a) { br_hist_body(a, blockIdx.x); }
 
+// Scatter of one tile (scol holds slots: the hist pass wrote them).  The
+// tile's rows, slots and values are loaded before the ranking rounds.
 __device__ __forceinline__ void br_scatter_body(const BrArgs& a, int64_t bid) {
   __shared__ int32_t base_off[256];
   __shared__ int32_t wcnt[kWavesPerBlock][256];
@@ -1074,14 +1330,24 @@ __device__ __forceinline__ void br_scatter_body(const BrArgs& a, int64_t bid) {
   const int lane = lane_id(), wv = wave_in_block();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t tile = bid * kBrTile;
+  int32_t rrow[kBrRounds], rslot[kBrRounds];
+  float rval[kBrRounds];
+#pragma unroll
+  for (int r = 0; r < kBrRounds; ++r) {
+    const int64_t i = tile + r * kSortThreads + threadIdx.x;
+    const bool valid = i < a.m;
+    rrow[r] = ldz(a.srow, valid, i, 0);
+    rslot[r] = ldz(a.scol, valid, i, 0);
+    rval[r] = ldz(a.sval, valid, i, 0.0f);
+  }
+#pragma unroll
   for (int r = 0; r < kBrRounds; ++r) {
 #pragma unroll
     for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][threadIdx.x] = 0;
     __syncthreads();
     const int64_t i = tile + r * kSortThreads + threadIdx.x;
     const bool valid = i < a.m;
-    int32_t slot = 0;
-    const uint32_t dig = valid ? br_digit(a, i, slot) : 0u;
+    const uint32_t dig = valid ? br_digit_of(a, rslot[r]) : 0u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -1096,16 +1362,15 @@ __device__ __forceinline__ void br_scatter_body(const BrArgs& a, int64_t bid) {
     if (valid) {
       int32_t pos = base_off[dig] + rank;
       for (int w = 0; w < wv; ++w) pos += wcnt[w][dig];
-      a.drow[pos] = a.srow[i];
-      a.dslot[pos] = slot;
-      a.dval[pos] = a.sval[i];
+      a.drow[pos] = rrow[r];
+      a.dslot[pos] = rslot[r];
+      a.dval[pos] = rval[r];
     }
     __syncthreads();
     int32_t add = 0;
 #pragma unroll
     for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][threadIdx.x];
     base_off[threadIdx.x] += add;
-    __syncthreads();
   }
 }
 
@@ -1386,16 +1651,16 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
 #pragma unroll
     for (int u = 0; u < kNarrowRegRounds; ++u) {
       const int32_t v = u * kNarrowBlock + tid;
-      rrow[u] = v < nb ? na.pri[base + v] : 0;
-      rx[u] = v < nb ? na.pv[base + v] : 0.0f;
-      rl[u] = (v < nb && R >= 0) ? (int32_t)na.plid[base + v] : 0;
+      rrow[u] = ldz(na.pri, v < nb, base + v, 0);
+      rx[u] = ldz(na.pv, v < nb, base + v, 0.0f);
+      rl[u] = R >= 0 ? (int32_t)ldz(na.plid, v < nb, base + v, (uint16_t)0) : 0;
     }
 #pragma unroll
     for (int u = 0; u < kNarrowRegRounds; ++u) {
       const int32_t v = u * kNarrowBlock + tid;
       rs[u] = v < nb ? slot_of(L.off, ns, v) : -1;
-      rc[u] = v < nb ? a.cache[rrow[u]] : 0.0;
-      ry[u] = v < nb ? (int)a.y[rrow[u]] : 0;
+      rc[u] = ldz(a.cache, v < nb, rrow[u], 0.0);
+      ry[u] = (int)ldz(a.y, v < nb, rrow[u], (int8_t)0);
     }
 #pragma unroll
     for (int u = 0; u < kNarrowRegRounds; ++u)
@@ -1413,15 +1678,15 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u) {
         const int32_t v = g0 + u * kNarrowBlock + tid;
-        grow[u] = v < nb ? na.pri[base + v] : 0;
-        gx[u] = v < nb ? na.pv[base + v] : 0.0f;
+        grow[u] = ldz(na.pri, v < nb, base + v, 0);
+        gx[u] = ldz(na.pv, v < nb, base + v, 0.0f);
       }
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u) {
         const int32_t v = g0 + u * kNarrowBlock + tid;
         gs[u] = v < nb ? slot_of(L.off, ns, v) : -1;
-        gc[u] = v < nb ? a.cache[grow[u]] : 0.0;
-        gy[u] = v < nb ? (int)a.y[grow[u]] : 0;
+        gc[u] = ldz(a.cache, v < nb, grow[u], 0.0);
+        gy[u] = (int)ldz(a.y, v < nb, grow[u], (int8_t)0);
       }
 #pragma unroll
       for (int u = 0; u < kNarrowRegRounds; ++u)
@@ -1534,9 +1799,9 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           const int32_t v = g0 + u * kNarrowBlock + tid;
           const bool on = gd[u] != 0.0;
-          glid[u] = on ? (int32_t)na.plid[base + v] : 0;
-          gx[u] = on ? na.pv[base + v] : 0.0f;
-          grow[u] = on ? na.pri[base + v] : 0;
+          glid[u] = (int32_t)ldz(na.plid, on, base + v, (uint16_t)0);
+          gx[u] = ldz(na.pv, on, base + v, 0.0f);
+          grow[u] = ldz(na.pri, on, base + v, 0);
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
@@ -1549,8 +1814,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
-          gc[u] = first[u] ? a.cache[grow[u]] : 0.0;
-          gy[u] = first[u] ? (int)a.y[grow[u]] : 0;
+          gc[u] = ldz(a.cache, first[u], grow[u], 0.0);
+          gy[u] = (int)ldz(a.y, first[u], grow[u], (int8_t)0);
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u)
@@ -1579,8 +1844,8 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
         for (int u = 0; u < kNarrowRegRounds; ++u) {
           const int32_t v = g0 + u * kNarrowBlock + tid;
           const bool on = gd[u] != 0.0;
-          grow[u] = on ? na.pri[base + v] : 0;
-          gx[u] = on ? na.pv[base + v] : 0.0f;
+          grow[u] = ldz(na.pri, on, base + v, 0);
+          gx[u] = ldz(na.pv, on, base + v, 0.0f);
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u)
@@ -1923,10 +2188,10 @@ __device__ inline int task_of_block(const int32_t* first, int count, int b) {
 template <int LOSS>
 __device__ __forceinline__ void exec_task(const Task& t, int lb) {
   switch (t.kind) {
-    case kTaskSweep: sweep_body<LOSS, false>(t.u.sw, lb, t.nblk); break;
-    case kTaskSweepStop: sweep_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
-    case kTaskSplit: split_body<LOSS, false>(t.u.sw, lb, t.nblk); break;
-    case kTaskSplitStop: split_body<LOSS, true>(t.u.sw, lb, t.nblk); break;
+    case kTaskSweep: sweep_body<LOSS>(t.u.sw, lb, t.nblk); break;
+    case kTaskStopRanges: stop_ranges_body<LOSS>(t.u.so, lb, t.nblk); break;
+    case kTaskSplit: split_body<LOSS>(t.u.sw, lb, t.nblk); break;
+    case kTaskStopFinish: stop_finish_body<LOSS>(t.u.so, lb, t.nblk); break;
     case kTaskRowsDtx: rows_dtx_body<LOSS>(t.u.rw, lb); break;
     case kTaskRowsApply: rows_apply_body<LOSS>(t.u.rw, lb, t.nblk); break;
     case kTaskSlotLen: slot_len_body(t.u.sl, lb); break;
@@ -1934,7 +2199,6 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskIslot: islot_body(t.u.is, lb); break;
     case kTaskBrHist: br_hist_body(t.u.br, lb); break;
     case kTaskBrScatter: br_scatter_body(t.u.br, lb); break;
-    case kTaskScatterCount: scatter_count_body(t.u.sc, lb, t.nblk); break;
     case kTaskSumPartial: sum_partial_body(t.u.sum, lb, t.nblk); break;
     case kTaskSumFinal: sum_final_body(t.u.sum); break;
     case kTaskStopPartial: stop_partial_body(t.u.stop, lb, t.nblk); break;
@@ -2191,50 +2455,53 @@ void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, co
   out.push_back(t);
 }
 
-// One wavefront per slot, and at least 512 wavefronts: a bundle of few
-// features with long columns (the heavy bundles of the single-workgroup
-// schedule: 64 features, up to ~300 chunk work items) then needs one pass
-// over its chunks instead of several.  Which wavefront takes a chunk does
-// not change any sum (each chunk is summed by one wavefront; split columns
-// add their chunk partials in chunk order).
+// One wavefront per kSweepGroup slots, and at least 512 wavefronts: a bundle
+// of few features with long columns (the heavy bundles of the
+// single-workgroup schedule: 64 features, up to ~300 chunk work items) then
+// needs one pass over its chunks.  Which wavefront takes a chunk does not
+// change any sum (each chunk is summed by one wavefront; split columns add
+// their chunk partials in chunk order).
 constexpr int64_t kSweepMinWaves = 512;
 int sweep_grid(int64_t slots) {
-  return grid_for(slots > kSweepMinWaves ? slots : kSweepMinWaves, kWavesPerBlock, 8192);
+  const int64_t waves = (slots + kSweepGroup - 1) / kSweepGroup;
+  return grid_for(waves > kSweepMinWaves ? waves : kSweepMinWaves, kWavesPerBlock, 8192);
 }
 
-hipError_t launch_sweep(int loss, bool stopping, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_sweep(int loss, const SweepArgs& a, hipStream_t s) {
   const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_sweep<kLogistic>, g, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_sweep<kL2Svm>, g, dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+int stop_ranges_grid(int64_t nnz) {
+  return grid_for((nnz + kStopW - 1) / kStopW, kWavesPerBlock, 8192);
+}
+int stop_finish_grid(int64_t p) { return grid_for(p, kBlock, 4096); }
+
+hipError_t launch_stop_sweep(int loss, const StopArgs& a, hipStream_t s) {
+  const dim3 g1(stop_ranges_grid(a.nnz)), g2(stop_finish_grid(a.p));
   if (loss == kLogistic) {
-    if (stopping)
-      hipLaunchKernelGGL((k_sweep<kLogistic, true>), g, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_sweep<kLogistic, false>), g, dim3(kBlock), 0, s, a);
+    if (a.nnz > 0) hipLaunchKernelGGL(k_stop_ranges<kLogistic>, g1, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_stop_finish<kLogistic>, g2, dim3(kBlock), 0, s, a);
   } else {
-    if (stopping)
-      hipLaunchKernelGGL((k_sweep<kL2Svm, true>), g, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_sweep<kL2Svm, false>), g, dim3(kBlock), 0, s, a);
+    if (a.nnz > 0) hipLaunchKernelGGL(k_stop_ranges<kL2Svm>, g1, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_stop_finish<kL2Svm>, g2, dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_split(int loss, bool stopping, const SweepArgs& a, hipStream_t s) {
+hipError_t launch_split(int loss, const SweepArgs& a, hipStream_t s) {
   const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
-  if (loss == kLogistic) {
-    if (stopping)
-      hipLaunchKernelGGL((k_split<kLogistic, true>), g, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_split<kLogistic, false>), g, dim3(kBlock), 0, s, a);
-  } else {
-    if (stopping)
-      hipLaunchKernelGGL((k_split<kL2Svm, true>), g, dim3(kBlock), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_split<kL2Svm, false>), g, dim3(kBlock), 0, s, a);
-  }
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_split<kLogistic>, g, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_split<kL2Svm>, g, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-int scatter_count_grid(int64_t p) { return grid_for(p, kBlock, 64); }
 int sum_grid(int64_t m) { return grid_for(m, kBlock, kSumGrid); }
 
 // One wavefront per range of an average bundle, at least 128 blocks: a
@@ -2340,12 +2607,18 @@ void br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp
     int32_t* dslot = to_br ? br_slot : bt_slot;
     float* dval = to_br ? br_val : bt_val;
     BrArgs b{pass == 0 ? islot : nullptr, srow, scol, sval, drow, dslot, dval, hist,
-             nnz, ntiles, P, 8 * pass, nb};
+             nullptr, nnz, ntiles, P, 8 * pass, nb};
+    if (pass == 0) b.slot_out = to_br ? bt_slot : br_slot;  // the buffer pass 0 does not write
     st = BrStep{};
     st.kind = kTaskBrHist;
     st.nblk = ntiles;
     st.br = b;
     f(st);
+    if (pass == 0) {  // the scatter reads the slots the histogram pass wrote
+      b.islot = nullptr;
+      b.scol = b.slot_out;
+      b.slot_out = nullptr;
+    }
     st = BrStep{};
     st.kind = -1;
     st.scan_in = hist;
@@ -2531,14 +2804,6 @@ hipError_t launch_gather(const double* const* src, double* dst, int count, hipSt
 hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_narrow_multi, dim3(count), dim3(kNarrowBlock), 0, s, tab);
-  return hipGetLastError();
-}
-
-hipError_t launch_scatter_count(const double* d, const int32_t* perm, const int64_t* cp,
-                                int64_t p, const double* p_active, int32_t chunk, Stats* stats,
-                                hipStream_t s) {
-  const ScatterCountArgs a{d, perm, cp, p, stats, p_active, chunk};
-  hipLaunchKernelGGL(k_scatter_count, dim3(scatter_count_grid(p)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

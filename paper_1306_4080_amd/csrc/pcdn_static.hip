@@ -213,7 +213,7 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->off32 = k.take<int32_t>(p + 1);
   t->plid = k.take<uint16_t>(nnz);
   t->pR = k.take<int32_t>(p + 1);
-  t->ls_part = k.take<double>((int64_t)kRowsGridMax * (2 * kQMax + 2));
+  t->ls_part = k.take<double>((int64_t)kRowsGridMax * (2 * kQMax + 3));
   t->act = k.take<double>(p);
   t->rp = k.take<int64_t>(n + 1);
   t->rr = k.take<int32_t>(nnz);
@@ -230,9 +230,10 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->u_cnt = k.take<int32_t>((nnz + kRangeW - 1) / kRangeW + 1);
   t->u_row = k.take<int32_t>(nnz + kRangeW);
   t->u_dtx = k.take<double>(nnz + kRangeW);
+  t->ccol = k.take<int32_t>(nnz);
   e->err = k.take<int>(1);
   e->xrow = k.take<double>(1);
-  e->ccol = k.take<int32_t>(nnz);
+  e->ccol = t->ccol;
   return k.off;
 }
 
@@ -316,8 +317,10 @@ int solve_static(int device, hipStream_t stream, int64_t n, int64_t p, int64_t n
   c->nnz = nnz;
   c->max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   c->cp = const_cast<int64_t*>(col_ptr);
-  c->ri = const_cast<int32_t*>(row_idx);
-  c->v = const_cast<float*>(val);
+  // without nonzeros the caller's arrays may be NULL: kernels read element 0
+  // of every array (see ldz), so point them at workspace buffers
+  c->ri = nnz ? const_cast<int32_t*>(row_idx) : c->rr;
+  c->v = nnz ? const_cast<float*>(val) : c->rv;
   c->y = const_cast<int8_t*>(y);
   c->w = w_out;
   // no top_len: k_split always launches (it does nothing without split
