@@ -129,6 +129,22 @@ typedef struct {
   double subgrad0;      /* ||grad^S F(0)||_1, the stopping reference        */
   double alg_bytes;     /* algorithmic HBM bytes of the kernels run         */
   double seconds;       /* wall time of the solve (stream-synchronised)     */
+  /* How close the solve's decisions came to their thresholds (a decision at
+   * the rounding floor can fall either way between two summation orders):
+   * the smallest |dF - sigma Delta_q| / S of any Armijo test (eq. (6)),
+   * S = |sigma Delta_q| plus the rounding scales of the terms dF is summed
+   * from (for R_j(w + s) - R_j(w) the magnitudes it is the difference of;
+   * for a logistic loss change its size plus |its argument|; for a squared-
+   * hinge change the two squares plus 2 max(0, b') |argument|), and the
+   * smallest |G_k - eps G0| / (eps G0) of any stopping test; +inf when
+   * there was none. */
+  double min_armijo_margin;
+  double min_stop_margin;
+  /* The schedule and chunk the solve ran with (PCDN_SCHED_*; nonzeros per
+   * work item): the options' values, or the autotuner's for a batch job
+   * with P = 0.  Passing them back reproduces the solve bit for bit. */
+  int32_t schedule;
+  int32_t chunk;
 } pcdn_info;
 
 /* Per-inner-iteration report of pcdn_step(). */

@@ -50,7 +50,7 @@ class _Par(ctypes.Structure):
 class _StepInfo(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("delta", ctypes.c_double),
                 ("dF", ctypes.c_double), ("q", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("margin", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -58,7 +58,8 @@ class _Info(ctypes.Structure):
                 ("bundles", ctypes.c_int64), ("ls_steps", ctypes.c_int64),
                 ("ls_fail", ctypes.c_int64), ("nnz_swept", ctypes.c_int64),
                 ("objective", ctypes.c_double), ("subgrad", ctypes.c_double),
-                ("subgrad0", ctypes.c_double)]
+                ("subgrad0", ctypes.c_double), ("min_armijo_margin", ctypes.c_double),
+                ("min_stop_margin", ctypes.c_double)]
 
 
 _lib = None
@@ -257,7 +258,7 @@ def step(prob: Problem, par: Params, w: np.ndarray, cache: np.ndarray, bundle) -
     pc = par.c()
     q = lib().orc_step(prob.ref, ctypes.byref(pc), _ptr(w), _ptr(cache), _ptr(bundle), P,
                        _ptr(g), _ptr(h), _ptr(d), _ptr(dtx), ctypes.byref(si))
-    return dict(q=int(q), alpha=si.alpha, delta=si.delta, dF=si.dF,
+    return dict(q=int(q), alpha=si.alpha, delta=si.delta, dF=si.dF, margin=si.margin,
                 g=g, h=h, d=d, dtx=dtx)
 
 

@@ -72,6 +72,12 @@ typedef struct {
   double dF;      /* F(w + alpha d) - F(w) at the accepted q (from caches)  */
   int32_t q;      /* accepted backtracking index, -1 if none of max_ls      */
   int32_t pad;
+  double margin;  /* smallest |dF - sigma Delta_q| / S over the candidates
+                     tested, S = |sigma Delta_q| + the rounding scales of
+                     the terms dF is summed from (see change_scale; +inf
+                     when S is 0): how far each Armijo decision was from its
+                     threshold on the scale of the rounding errors of its
+                     two sides                                              */
 } orc_step_info;
 
 typedef struct {
@@ -84,6 +90,12 @@ typedef struct {
   double objective;    /* F(w) at exit, from the retained quantities      */
   double subgrad;      /* ||grad^S F(w)||_1 at exit                       */
   double subgrad0;     /* ||grad^S F(0)||_1, the stopping reference       */
+  /* how close the decisions came to their thresholds (instrumentation; no
+   * decision depends on them): the smallest Armijo margin of any inner
+   * iteration (orc_step_info.margin) and the smallest
+   * |G_k - eps G0| / (eps G0) of any stopping test after an outer iteration */
+  double min_armijo_margin;
+  double min_stop_margin;
 } orc_info;
 
 /* ------------------------------------------------------------------------ */
@@ -307,6 +319,20 @@ static double loss_change(int32_t loss, double cache, int y, double a) {
 }
 
 /* Exported for the pin tests: the per-sample change above. */
+/* Instrumentation only (no decision reads it): the size of the rounding
+ * error a loss change inherits, as a magnitude.  The logistic change is
+ * evaluated directly, so it carries its own relative error plus what an
+ * error in its argument a moves it by (the derivative in a lies in [-1, 1]);
+ * the squared-hinge change is the difference of two squares, whose sizes it
+ * inherits, plus the error of the argument times 2 max(0, b - y a). */
+static double loss_change_scale(int32_t loss, double cache, int y, double a, double lc) {
+  if (loss == ORC_LOGISTIC) return fabs(lc) + fabs(a);
+  double bn = cache - (double)y * a;
+  double pn = bn > 0.0 ? bn : 0.0;
+  double po = cache > 0.0 ? cache : 0.0;
+  return pn * pn + po * po + 2.0 * pn * fabs(a);
+}
+
 double orc_loss_change(int32_t loss, double cache, int32_t y, double a) {
   return loss_change(loss, cache, y, a);
 }
@@ -402,17 +428,27 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
   }
   if (dtx_out) memcpy(dtx_out, a, (size_t)X->n * sizeof(double));
 
-  double Dq = Delta, alpha = 1.0, dF = 0.0;
+  double Dq = Delta, alpha = 1.0, dF = 0.0, margin = INFINITY;
   int32_t q_acc = -1;
   for (int32_t q = 0; q < par->max_ls; ++q) {
-    double l1 = 0.0; /* R(w + alpha d) - R(w) */
+    double l1 = 0.0, l1abs = 0.0; /* R(w + alpha d) - R(w) */
     for (int64_t t = 0; t < P; ++t) {
       double wj = w[bundle[t]], s = alpha * d[t];
-      l1 += ra * fabs(wj + s) - ra * fabs(wj) + rb * s * (wj + 0.5 * s);
+      const double r = ra * fabs(wj + s) - ra * fabs(wj) + rb * s * (wj + 0.5 * s);
+      l1 += r;
+      /* its rounding scale: the magnitudes it is the difference of */
+      l1abs += ra * (fabs(wj + s) + fabs(wj)) + fabs(rb * s) * (fabs(wj) + 0.5 * fabs(s));
     }
-    double sL = 0.0;
-    for (int64_t i = 0; i < X->n; ++i) sL += loss_change(par->loss, cache[i], X->y[i], a[i]);
+    double sL = 0.0, sabs = 0.0;
+    for (int64_t i = 0; i < X->n; ++i) {
+      const double lc = loss_change(par->loss, cache[i], X->y[i], a[i]);
+      sL += lc;
+      sabs += loss_change_scale(par->loss, cache[i], X->y[i], a[i], lc);
+    }
     dF = l1 + par->C * sL;
+    const double thr = par->sigma * Dq;
+    const double scale = fabs(thr) + l1abs + par->C * sabs;
+    if (scale != 0.0 && fabs(dF - thr) / scale < margin) margin = fabs(dF - thr) / scale;
     if (dF <= par->sigma * Dq) {
       q_acc = q;
       break;
@@ -438,6 +474,7 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
     info->dF = q_acc >= 0 ? dF : 0.0;
     info->q = q_acc;
     info->pad = 0;
+    info->margin = margin;
   }
   if (g_out) memcpy(g_out, g, (size_t)P * sizeof(double));
   if (h_out) memcpy(h_out, h, (size_t)P * sizeof(double));
@@ -480,6 +517,8 @@ int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
   int32_t* perm = (int32_t*)malloc((size_t)p * sizeof(int32_t));
   orc_info I;
   memset(&I, 0, sizeof(I));
+  I.min_armijo_margin = INFINITY;
+  I.min_stop_margin = INFINITY;
 
   /* reference norm at w = 0, where e^{w^T x} = 1 and b = 1 */
   for (int64_t i = 0; i < n; ++i) cache[i] = 1.0;
@@ -511,6 +550,7 @@ int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
       int64_t lo = t * P, hi = lo + P < p_act ? lo + P : p_act;
       orc_step_info si;
       int32_t q = orc_step(X, par, w, cache, perm + lo, hi - lo, NULL, NULL, NULL, NULL, &si);
+      if (si.margin < I.min_armijo_margin) I.min_armijo_margin = si.margin;
       I.bundles += 1;
       if (q < 0) {
         I.ls_fail += 1;
@@ -525,6 +565,10 @@ int32_t orc_solve(const orc_X* X, const orc_par* par, int64_t P, double eps,
     I.outer_iters += 1;
     I.subgrad = orc_subgrad_l1(X, par, w, cache, gfull);
     converged = I.subgrad <= eps * I.subgrad0;
+    if (eps > 0.0) {
+      const double sm = fabs(I.subgrad - eps * I.subgrad0) / (eps * I.subgrad0);
+      if (sm < I.min_stop_margin) I.min_stop_margin = sm;
+    }
     if (par->shrink) {
       double M = 0.0;
       const double thr = reg_a(par) - M_prev / (double)n;

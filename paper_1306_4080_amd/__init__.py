@@ -18,8 +18,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpcdn.so"
 
 
 def ensure_built() -> str:
-    """Build libpcdn.so only when no built library is present."""
-    if not os.path.exists(LIB_PATH):
-        from . import build
+    """Build libpcdn.so when it is missing or was built from other sources
+    (its stamp holds the SHA-256 of the sources, headers and compile
+    command)."""
+    from . import build
+    if build.is_stale():
         build.build()
     return LIB_PATH

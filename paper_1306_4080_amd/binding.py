@@ -62,7 +62,9 @@ class pcdn_info(ctypes.Structure):
                 ("ls_fail", ctypes.c_int64), ("nnz_swept", ctypes.c_int64),
                 ("objective", ctypes.c_double), ("subgrad", ctypes.c_double),
                 ("subgrad0", ctypes.c_double), ("alg_bytes", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("min_armijo_margin", ctypes.c_double),
+                ("min_stop_margin", ctypes.c_double), ("schedule", ctypes.c_int32),
+                ("chunk", ctypes.c_int32)]
 
 
 class pcdn_step_info(ctypes.Structure):

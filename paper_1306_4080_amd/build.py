@@ -4,6 +4,7 @@
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -40,21 +41,40 @@ def command(out: str = LIB) -> list:
             "-o", out] + SOURCES
 
 
+STAMP = LIB + ".stamp"
+
+
+def fingerprint() -> str:
+    """SHA-256 of the sources, the headers and the compile command: what the
+    library is built from (contents, not modification times, which a copy of
+    the tree does not keep)."""
+    h = hashlib.sha256()
+    h.update(" ".join(command("libpcdn.so")[1:]).replace(ROOT, "").encode())
+    for f in SOURCES + HEADERS:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = command(tmp)
     if verbose:
         print(" ".join(cmd), flush=True)
+    fp = fingerprint()
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    with open(STAMP, "w") as f:
+        f.write(fp + "\n")
     return LIB
 
 
 def is_stale() -> bool:
-    if not os.path.exists(LIB):
+    """Whether libpcdn.so is missing or was built from other sources."""
+    if not (os.path.exists(LIB) and os.path.exists(STAMP)):
         return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(s) > t for s in SOURCES + HEADERS)
+    with open(STAMP) as f:
+        return f.read().strip() != fingerprint()
 
 
 if __name__ == "__main__":

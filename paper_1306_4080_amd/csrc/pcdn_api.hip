@@ -27,6 +27,9 @@ constexpr double kBytesPerRowLs = 17.0;       // d^T x 8 + retained 8 + label 1
 constexpr double kBytesPerSlotLs = 28.0;      // perm 4 + w 8 + d 8 + dterm 8
 constexpr double kBytesPerRowApply = 33.0;    // d^T x 8 + retained RMW 16 + label 1 + clear 8
 constexpr double kBytesPerSlotApply = 28.0;   // perm 4 + d 8 + w RMW 16
+// the single-workgroup kernel keeps a bundle's w, d and Delta terms in LDS:
+// perm 4 + col_ptr pair 16 + w 8 + g, h, d out 24 + w write 8
+constexpr double kBytesPerSlotNarrow = 60.0;
 constexpr double kBytesPerNnzStop = 17.0;
 constexpr double kBytesPerFeatStop = 32.0;    // col_ptr pair 16 + w 8 + |grad^S| 8
 
@@ -62,7 +65,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
   dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
-  dfree(c->id_cstart); dfree(c->id_chunks); dfree(c->step_perm);
+  dfree(c->step_perm);
   dfree(c->ccol); dfree(c->rr); dfree(c->islot); dfree(c->br_row); dfree(c->br_slot); dfree(c->br_val);
   dfree(c->bt_row); dfree(c->bt_slot); dfree(c->bt_val); dfree(c->br_hist);
   dfree(c->u_cnt); dfree(c->u_row); dfree(c->u_dtx);
@@ -197,7 +200,7 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   a.part = c->part;
   a.dtx = c->dtx;
   a.stats = c->stats;
-  a.C = c->C;
+  a.Cp = c->scal + kScalC;
   a.gamma = o.gamma;
   a.nu = o.nu;
   a.ra = o.ra();
@@ -261,7 +264,7 @@ RowsArgs rows_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, 
   r.beta = o.beta;
   r.ra = o.ra();
   r.rb = o.rb();
-  r.C = c->C;
+  r.Cp = c->scal + kScalC;
   r.sigma = o.sigma;
   r.Q = o.max_ls;
   r.max_ls = o.max_ls;
@@ -313,7 +316,7 @@ StopArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
   a.nnz = c->nnz;
   a.sg = c->tmp_p;
   a.part = c->part;
-  a.C = c->C;
+  a.Cp = c->scal + kScalC;
   a.ra = o.ra();
   a.rb = o.rb();
   return a;
@@ -407,7 +410,14 @@ int cache_from_w(pcdn_ctx* c, bool w_is_zero) {
     return PCDN_OK;
   }
   HIPCHK(c, launch_margins_rows(c->loss, c->rp, c->rc, c->rv, c->w, c->y, c->n, c->cache,
-                                c->stream));
+                                c->stats, c->stream));
+  return range_check(c, "w puts e^{w^T x_i} outside the normal doubles (|w^T x_i| > ~708)");
+}
+
+// C on the host and in the device scalar the kernels read (scal[kScalC]).
+int set_C(pcdn_ctx* c, double C) {
+  c->C = C;
+  HIPCHK(c, launch_fill(c->scal + kScalC, C, 1, c->stream));
   return PCDN_OK;
 }
 
@@ -480,7 +490,6 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   na.t_end = t_end;
   na.st = c->st;
   na.stats = c->stats;
-  na.C = c->C;
   na.sigma = o.sigma;
   na.beta = o.beta;
   na.max_ls = o.max_ls;
@@ -680,7 +689,6 @@ pcdn_ctx::GraphKey graph_key_of(const pcdn_ctx* c, const Opts& o, int64_t P) {
   pcdn_ctx::GraphKey key;
   key.P = P;
   key.loss = c->loss;
-  key.C = c->C;
   key.sigma = o.sigma;
   key.beta = o.beta;
   key.gamma = o.gamma;
@@ -794,6 +802,19 @@ int read_stats(pcdn_ctx* c) {
   return PCDN_OK;
 }
 
+int range_check(pcdn_ctx* c, const char* what) {
+  const int rc = read_stats(c);
+  if (rc) return rc;
+  return range_noted(c, what);
+}
+
+int range_noted(pcdn_ctx* c, const char* what) {
+  const unsigned long long n = c->hstats->range_leaves;
+  if (n == c->range_seen) return PCDN_OK;
+  c->range_seen = n;
+  return fail(c, PCDN_E_NUMERIC, what);
+}
+
 double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& h,
                     const pcdn_ctx::HostCounts& hb, int cls, int64_t p) {
   // multi-kernel schedule (classes 0-3) and single-workgroup kernel (class 5)
@@ -818,9 +839,8 @@ double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& 
                    kBytesPerSlotLs * d_slots;
     case 3: return kBytesPerRowApply * d_rows + kBytesPerSlotApply * d_slots;
     case 4: return kBytesPerNnzStop * d_stop + kBytesPerFeatStop * (double)p * d_sweeps;
-    case 5: return kBytesPerNnzSweep * n_nnz_gh + kBytesPerSlotSweep * n_slots +
-                   kBytesPerNnzScatter * n_scat + (kBytesPerRowLs + kBytesPerRowApply) * n_rows +
-                   (kBytesPerSlotLs + kBytesPerSlotApply) * n_slots;
+    case 5: return kBytesPerNnzSweep * n_nnz_gh + kBytesPerSlotNarrow * n_slots +
+                   kBytesPerNnzScatter * n_scat + (kBytesPerRowLs + kBytesPerRowApply) * n_rows;
     default: return 0.0;
   }
 }
@@ -847,9 +867,13 @@ int solve_begin(SolveRun& r) {
   r.base = *c->hstats;
   r.hbase = c->hc;
   c->loss = r.loss;
-  c->C = r.C;
+  rc = set_C(c, r.C);
+  if (rc) return rc;
   note_regulariser(c, r.o);
   r.outer = 0;
+  r.min_stop_margin = INFINITY;
+  // the smallest Armijo margin of this solve (Stats::min_margin_bits)
+  HIPCHK(c, launch_fill((double*)&c->stats->min_margin_bits, INFINITY, 1, c->stream));
   rc = init_shrink(c);
   if (rc) return rc;
   // reference norm at w = 0 (retained quantities all one)
@@ -886,6 +910,8 @@ int solve_note_outer(SolveRun& r, double G) {
   r.G = G;
   if (!std::isfinite(G)) return fail(r.c, PCDN_E_NUMERIC, "non-finite subgradient norm");
   r.converged = G <= r.eps * r.G0;
+  if (r.eps * r.G0 > 0.0)
+    r.min_stop_margin = std::min(r.min_stop_margin, std::fabs(G - r.eps * r.G0) / (r.eps * r.G0));
   return PCDN_OK;
 }
 
@@ -894,11 +920,11 @@ int solve_end(SolveRun& r, double* w_out, pcdn_info* info) {
   double F = 0.0;
   int rc = objective(c, r.o, &F);
   if (rc) return rc;
-  if (std::isnan(F)) return fail(c, PCDN_E_NUMERIC, "objective is NaN");
   if (w_out)
     HIPCHK(c, hipMemcpyAsync(w_out, c->w, c->p * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  rc = read_stats(c);
+  rc = range_check(c, kRangeStep);
   if (rc) return rc;
+  if (std::isnan(F)) return fail(c, PCDN_E_NUMERIC, "objective is NaN");
   const auto t1 = std::chrono::steady_clock::now();
   if (info) {
     const Stats& s = *c->hstats;
@@ -915,6 +941,12 @@ int solve_end(SolveRun& r, double* w_out, pcdn_info* info) {
     for (int k = 0; k < kProfClasses; ++k) bytes += alg_bytes_of(s, r.base, c->hc, r.hbase, k, c->p);
     info->alg_bytes = bytes;
     info->seconds = std::chrono::duration<double>(t1 - r.t0).count();
+    double m;
+    std::memcpy(&m, &s.min_margin_bits, sizeof m);
+    info->min_armijo_margin = m;
+    info->min_stop_margin = r.min_stop_margin;
+    info->schedule = r.o.schedule;
+    info->chunk = r.o.chunk;
   }
   return r.converged ? PCDN_OK : PCDN_NOT_CONVERGED;
 }
@@ -1027,11 +1059,11 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       4 * p, 4 * p, 4 * p, 4 * p, 4 * hist_m,              // sort keys and payloads, histogram
       4 * (std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1),
       4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
-      4 * (p + 1), 32 * max_chunks, 4 * p,                 // identity-order descriptors, step bundle
+      4 * p,                                               // step bundle
       16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
       8 * p,                                               // w in partition order
       2 * nnz, 4 * (p + 1),                                // bundle-local row ids
-      8 * (int64_t)kRowsGridMax * (2 * kQMax + 3),         // line-search partials
+      8 * (int64_t)kRowsGridMax * (4 * kQMax + 3),         // line-search partials
       8 * p,                                               // active mask (shrinking)
       8 * (n + 1), 4 * nnz, 4 * nnz, 4 * nnz, 4 * nnz,     // CSR copy, column of each nonzero
       4 * p, 12 * nnz, 12 * nnz, 4 * br_m,                 // bundle-row order, sort buffers
@@ -1138,8 +1170,6 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->nch, p);
   ALLOC(c, c->cstart, p + 1);
   ALLOC(c, c->chunks, max_chunks);
-  ALLOC(c, c->id_cstart, p + 1);
-  ALLOC(c, c->id_chunks, max_chunks);
   ALLOC(c, c->step_perm, p);
   c->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
   ALLOC(c, c->part, c->part_len);
@@ -1150,7 +1180,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->off32, p + 1);
   ALLOC(c, c->plid, nnz);
   ALLOC(c, c->pR, p + 1);
-  ALLOC(c, c->ls_part, (size_t)kRowsGridMax * (2 * kQMax + 3));
+  ALLOC(c, c->ls_part, (size_t)kRowsGridMax * (4 * kQMax + 3));
   ALLOC(c, c->act, p);
   ALLOC(c, c->rp, n + 1);
   ALLOC(c, c->ccol, nnz);
@@ -1208,13 +1238,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   }
   HIPCHK(c, hipMemcpyAsync(c->y, y, n, kind, c->stream));
   HIPCHK(c, hipMemsetAsync(c->dtx, 0, n * sizeof(double), c->stream));
-  HIPCHK(c, launch_chunks(nullptr, c->cp, p, kChunk, c->nch, c->id_cstart, c->id_chunks,
-                          c->scan_tmp, c->stream));
-  int32_t total = 0;
-  HIPCHK(c, hipMemcpyAsync(&total, c->id_cstart + p, sizeof(int32_t), hipMemcpyDeviceToHost,
-                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->id_total_chunks = total;
   c->loaded = true;
   return PCDN_OK;
 }
@@ -1258,7 +1282,8 @@ extern "C" int pcdn_reset(pcdn_ctx* c, int loss, double C, const double* w) {
   if (!(C > 0.0) || !std::isfinite(C)) return fail(c, PCDN_E_ARG, "C must be a finite positive number");
   HIPCHK(c, hipSetDevice(c->device));
   c->loss = loss;
-  c->C = C;
+  rc = set_C(c, C);
+  if (rc) return rc;
   c->penalty = PCDN_PENALTY_L1;
   c->l2 = 0.0;
   rc = set_w(c, w);
@@ -1319,6 +1344,8 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
     HIPCHK(c, hipMemcpyAsync(dtx, c->tmp_n, c->n * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  rc = range_check(c, kRangeStep);
+  if (rc) return rc;
   if (out) {
     out->alpha = c->hst->alpha;
     out->delta = c->hst->delta;

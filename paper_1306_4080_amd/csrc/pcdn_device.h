@@ -62,7 +62,13 @@ struct Stats {
   unsigned long long nnz_gh_narrow;        // bundle nonzeros it swept
   unsigned long long slots_narrow;         // bundle slots it processed
   unsigned long long nnz_scat_narrow_split;  // nonzeros it scattered, longer columns
-  unsigned long long pad[5];
+  // smallest Armijo margin |dF - sigma Delta_q| / |sigma Delta_q| since the
+  // last reset, as the bits of a non-negative double (their integer order
+  // is the numeric order)
+  unsigned long long min_margin_bits;
+  // retained quantities set outside their range (see in_range)
+  unsigned long long range_leaves;
+  unsigned long long pad[3];
 };
 
 // Result of the line search of the current inner iteration.
@@ -99,7 +105,8 @@ struct SweepArgs {
   double2* part;              // split-column partial sums, per chunk
   double* dtx;                // d^T x accumulator
   Stats* stats;
-  double C, gamma, nu;
+  const double* Cp;           // C (device scalar: one captured graph serves every C)
+  double gamma, nu;
   // regulariser R_j(u) = ra |u| + (rb/2) u^2 (eq. (1): ra = 1, rb = 0)
   double ra, rb;
   // shrinking (all nullable): bundle mode clips the slots to the first
@@ -131,7 +138,8 @@ struct StopArgs {
   double* act;               // nullable (shrinking): next active mask, threshold *thr
   const double* thr;
   double2* part;             // per range
-  double C, ra, rb;
+  const double* Cp;          // C (device scalar)
+  double ra, rb;
 };
 
 // Multi-kernel bundle after the sweep: the bundle's nonzeros in row order
@@ -160,11 +168,13 @@ struct RowsArgs {
   int32_t* u_row;
   double* u_dtx;
   double* part;              // [v * G + block]: Q loss sums, Q regulariser sums, Delta, touched
-                             // rows, nonzeros with d_j != 0
+                             // rows, nonzeros with d_j != 0, Q sums of |loss change|,
+                             // Q sums of |regulariser change| (4Q + 3 rows)
   int32_t G;                 // blocks of the d^T x / line-search launch
   StepState* st;
   Stats* stats;
-  double beta, ra, rb, C, sigma;
+  const double* Cp;          // C (device scalar)
+  double beta, ra, rb, sigma;
   int Q, max_ls;
   const double* p_active;    // nullable: slots clipped to the first *p_active
 };
@@ -341,7 +351,7 @@ struct NarrowArgs {
   StepState* st;       // record of the last bundle
   Stats* stats;
   double* dtx_copy;    // nullable: receives d^T x of the (last) bundle
-  double C, sigma, beta;
+  double sigma, beta;
   int max_ls;
   int loss;            // kLogistic / kL2Svm (read by the multi-problem kernel)
   const double* p_active;  // nullable: bundles stop at ceil(*p_active / P)
@@ -480,7 +490,7 @@ hipError_t launch_reg_terms(const double* w, int64_t p, double ra, double rb, do
 // order (rp int64[n+1], col, v); deterministic.
 hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, const float* v,
                                const double* w, const int8_t* y, int64_t n, double* cache,
-                               hipStream_t s);
+                               Stats* stats, hipStream_t s);
 hipError_t launch_cache_from_z(int loss, double* z_to_cache, const int8_t* y, int64_t n,
                                hipStream_t s);
 

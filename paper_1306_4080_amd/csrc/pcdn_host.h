@@ -81,9 +81,6 @@ struct pcdn_ctx {
   int32_t* nch = nullptr;
   int32_t* cstart = nullptr;
   Chunk* chunks = nullptr;
-  int32_t* id_cstart = nullptr;
-  Chunk* id_chunks = nullptr;
-  int64_t id_total_chunks = 0;
   int32_t* step_perm = nullptr;
   int64_t max_chunks = 0;
   double2* part = nullptr;
@@ -101,6 +98,7 @@ struct pcdn_ctx {
   double* act = nullptr;
   double* stop_part = nullptr;
   double p_active_h = 0.0, nnz_active_h = 0.0;
+  unsigned long long range_seen = 0;  // Stats::range_leaves at the last range check
   // X in CSR order (warm-start margins, and the source of the bundle-row
   // order): row pointers, and per nonzero its row, column and value
   int64_t* rp = nullptr;
@@ -130,7 +128,8 @@ struct pcdn_ctx {
   IterState* iter = nullptr;
   StepState* st = nullptr;
   Stats* stats = nullptr;
-  double* scal = nullptr;        // [0] stopping norm, [1] loss sum, [2] l1 sum
+  double* scal = nullptr;        // [0] stopping norm, [1] loss sum, [2] l1 sum, ...,
+                                 // [kScalC] C
   double* sum_part = nullptr;
 
   // pinned host mirrors
@@ -145,7 +144,7 @@ struct pcdn_ctx {
   struct GraphKey {
     int64_t P = -1;
     int loss = -1;
-    double C = 0, sigma = 0, beta = 0, gamma = 0, nu = 0;
+    double sigma = 0, beta = 0, gamma = 0, nu = 0;
     int max_ls = 0;
     int schedule = -1;
     int shrink = -1;
@@ -153,7 +152,7 @@ struct pcdn_ctx {
     double l2 = 0;
     int chunk = 0;
     bool operator==(const GraphKey& o) const {
-      return P == o.P && loss == o.loss && C == o.C && sigma == o.sigma && beta == o.beta &&
+      return P == o.P && loss == o.loss && sigma == o.sigma && beta == o.beta &&
              gamma == o.gamma && nu == o.nu && max_ls == o.max_ls && schedule == o.schedule &&
              shrink == o.shrink && penalty == o.penalty && l2 == o.l2 && chunk == o.chunk;
     }
@@ -224,6 +223,10 @@ struct Opts {
 // Options with defaults filled in and validated (o may be null).
 int resolve_opts(pcdn_ctx* c, const pcdn_opts* o, Opts* r);
 int check_loss(pcdn_ctx* c, int loss);
+// The slot of the context's device scalars that holds C (the kernels read
+// it there, so captured graphs do not depend on C).
+constexpr int kScalC = 7;
+int set_C(pcdn_ctx* c, double C);
 // Record the regulariser that the state is being advanced with.
 void note_regulariser(pcdn_ctx* c, const Opts& o);
 // Whether a column has more than `chunk` nonzeros: only then do work items
@@ -270,6 +273,13 @@ void count_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t count);
 // Set the device-side outer-iteration record (seed, k) read by graph replays.
 int set_iter(pcdn_ctx* c, uint64_t seed, int64_t k);
 int read_stats(pcdn_ctx* c);
+// PCDN_E_NUMERIC with `what` if retained quantities left their range since
+// the last check (Stats::range_leaves); range_check reads the counters first.
+int range_check(pcdn_ctx* c, const char* what);
+int range_noted(pcdn_ctx* c, const char* what);
+constexpr const char* kRangeStep =
+    "a step put e^{w^T x_i} outside the normal doubles (|w^T x_i| > ~708) or b_i outside the "
+    "finite ones";
 // Outer iterations k_first .. k_first+count-1 (graph replays unless profiling).
 int run_outer(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k_first, int64_t count);
 // Copy c->scal[idx] to the host (synchronises the stream).
@@ -294,6 +304,7 @@ struct SolveRun {
   double G0 = 0.0, G = 0.0;
   bool converged = false;
   int outer = 0;
+  double min_stop_margin = 0.0;  // (set by solve_begin) smallest |G_k - eps G0| / (eps G0) so far
   bool w0_device = false;  // warm start from the w already on the device
   std::chrono::steady_clock::time_point t0;
 };

@@ -206,6 +206,52 @@ __device__ inline double loss_delta(double c, int yi, double a) {
   }
 }
 
+// Instrumentation of the Armijo decisions (no decision depends on it).
+// The rounding scale of one loss change: what its computed value inherits
+// from the rounding of its operands.  LR: the change itself plus |a| (the
+// change moves by at most |da| for an error da in its argument); SVM: the
+// two squares it is the difference of, plus 2 max(0, b - y a) |a|.
+template <int LOSS>
+__device__ inline double loss_delta_scale(double c, int yi, double a, double ld) {
+  if (LOSS == kLogistic) return fabs(ld) + fabs(a);
+  const double bn = yi > 0 ? c - a : c + a;
+  const double pn = bn > 0.0 ? bn : 0.0;
+  const double po = c > 0.0 ? c : 0.0;
+  return pn * pn + po * po + 2.0 * pn * fabs(a);
+}
+
+// The rounding scale of R_j(w + s) - R_j(w): the magnitudes it is formed
+// from, ra (|w + s| + |w|) and |rb s| (|w| + |s|/2).
+__device__ inline double reg_change_scale(double w, double s, double ra, double rb) {
+  return ra * (fabs(w + s) + fabs(w)) + fabs(rb * s) * (fabs(w) + 0.5 * fabs(s));
+}
+
+// |f - thr| / S for an Armijo test f <= thr, S = |thr| + scale (the summed
+// rounding scales of the terms f is formed from, C included): the
+// decision's distance from its threshold on the scale of the rounding
+// errors of its two sides (+inf when S = 0).
+__device__ inline double armijo_margin(double f, double thr, double abs_terms) {
+  const double S = fabs(thr) + abs_terms;
+  return S != 0.0 ? fabs(f - thr) / S : INFINITY;
+}
+
+// The range a retained quantity must stay in.  e^{w^T x_i} must be a
+// positive normal double (|w^T x_i| below about 708): at 0, a subnormal or
+// inf it no longer determines z_i, and 1/E or E/(1 + E) stop being exact.
+// b_i = 1 - y_i w^T x_i must be finite.  A value outside is counted in
+// Stats::range_leaves (the host reports it as a numeric error).
+template <int LOSS>
+__device__ inline bool in_range(double c) {
+  if (LOSS == kLogistic) return c >= 2.2250738585072014e-308 && c <= 1.7976931348623157e308;
+  return fabs(c) <= 1.7976931348623157e308;
+}
+
+template <int LOSS>
+__device__ inline void store_retained(double* p, double c, Stats* stats) {
+  *p = c;
+  if (!in_range<LOSS>(c)) atomicAdd(&stats->range_leaves, 1ull);
+}
+
 // Minimiser of g d + h d^2/2 + R(w + d) with R(u) = ra |u| + (rb/2) u^2
 // (eq. (4) with the separable regulariser in place of |u|; for ra = 1,
 // rb = 0 the soft-threshold form of eq. (5)).  u = w + d is > 0 exactly
@@ -410,7 +456,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t
 
 // ---------------------------------------------------------------------------
 // stable LSD radix sort of 32-bit keys with int32 payload, 8-bit digits.
-// A tile is 4096 keys (256 threads x 16 rounds).  Stability inside a round
+// A tile is kSortTile = 1024 keys (256 threads x 4 rounds).  Stability inside a round
 // comes from wavefront peer masks built with ballots, across waves and rounds
 // from per-digit running offsets in LDS.
 // ---------------------------------------------------------------------------
@@ -581,13 +627,14 @@ __device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi,
 template <int LOSS>
 __device__ inline void finish_feature(const SweepArgs& a, const Chunk& ch, double gs, double hs,
                                       double wj, bool writer) {
+  const double C = *a.Cp;
   double g, h;
   if (LOSS == kLogistic) {
-    g = a.C * gs;
-    h = a.C * hs;
+    g = C * gs;
+    h = C * hs;
   } else {
-    g = -2.0 * a.C * gs;
-    h = 2.0 * a.C * hs;
+    g = -2.0 * C * gs;
+    h = 2.0 * C * hs;
   }
   if (h <= 0.0) h += a.nu;
   const double dj = newton_dir(g, h, wj, a.ra, a.rb);
@@ -736,7 +783,8 @@ __device__ inline double grad_term(double c, int yi, double x) {
 
 template <int LOSS>
 __device__ inline void stop_finish_one(const StopArgs& a, int64_t j, double gs) {
-  const double g = LOSS == kLogistic ? a.C * gs : -2.0 * a.C * gs;
+  const double C = *a.Cp;
+  const double g = LOSS == kLogistic ? C * gs : -2.0 * C * gs;
   const double wj = a.w ? a.w[j] : 0.0;
   a.sg[j] = fabs(min_norm_subgradient(g, wj, a.ra, a.rb));
   if (a.act) a.act[j] = (wj != 0.0 || fabs(g) >= *a.thr) ? 1.0 : 0.0;
@@ -881,12 +929,14 @@ __device__ inline void wave_lds_sync() {
 // once per candidate).
 template <int LOSS>
 __device__ inline void row_ls_terms(double c, int yi, double dl, double beta, int nq,
-                                    double (&acc)[kQGroup]) {
+                                    double (&acc)[kQGroup], double (&aabs)[kQGroup]) {
   double s = dl;
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) {
     if (q < nq) {
-      acc[q] += loss_delta<LOSS>(c, yi, s);
+      const double t = loss_delta<LOSS>(c, yi, s);
+      acc[q] += t;
+      aabs[q] += loss_delta_scale<LOSS>(c, yi, s, t);
       s *= beta;
     }
   }
@@ -905,14 +955,15 @@ struct RowQueue {
 // and add their line-search terms.
 template <int LOSS>
 __device__ inline void rows_flush(const RowsArgs& a, const RowQueue& qu, int n, int64_t ubase,
-                                  int nq, double (&acc)[kQGroup], double& touched) {
+                                  int nq, double (&acc)[kQGroup], double (&aabs)[kQGroup],
+                                  double& touched) {
   const int lane = lane_id();
   if (lane < n) {
     const double dl = qu.dtx[lane];
     a.u_row[ubase + lane] = qu.row[lane];
     a.u_dtx[ubase + lane] = dl;
     touched += 1.0;
-    row_ls_terms<LOSS>(qu.c[lane], qu.y[lane], dl, a.beta, nq, acc);
+    row_ls_terms<LOSS>(qu.c[lane], qu.y[lane], dl, a.beta, nq, acc, aabs);
   }
 }
 
@@ -959,7 +1010,7 @@ template <int LOSS>
 __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   constexpr int kR = kRangeW / kWave;
   __shared__ RowQueue queue[kWavesPerBlock];
-  __shared__ double red[kWavesPerBlock][kQGroup + 2];
+  __shared__ double red[kWavesPerBlock][2 * kQGroup + 2];
   const int64_t hi_act = clipped_hi(a.slot_hi, a.p_active);
   if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: the apply skips it too
   const int lane = lane_id(), wv = wave_in_block();
@@ -969,9 +1020,9 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   const int64_t nwaves = (int64_t)G * kWavesPerBlock;
   RowQueue& qu = queue[wv];
-  double acc[kQGroup];
+  double acc[kQGroup], aabs[kQGroup];
 #pragma unroll
-  for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kQGroup; ++q) acc[q] = aabs[q] = 0.0;
   double touched = 0.0, nz_d = 0.0;
   for (int64_t r = (int64_t)bx * kWavesPerBlock + wv; r < nr; r += nwaves) {
     const int64_t rb = e0 + r * kRangeW;
@@ -1015,7 +1066,7 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
       qn += rows_round(a, qu, qn, prow[u], owned, t, pc[u], py[u], k, e1, crow, cval);
       if (qn >= kWave) {
         wave_lds_sync();
-        rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, touched);
+        rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, aabs, touched);
         listed += kWave;
         qn -= kWave;
         wave_lds_sync();
@@ -1047,7 +1098,7 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
       qn += rows_round(a, qu, qn, row, owned, t, c, yi, k, e1, crow, cval);
       if (qn >= kWave) {
         wave_lds_sync();
-        rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, touched);
+        rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, aabs, touched);
         listed += kWave;
         qn -= kWave;
         wave_lds_sync();
@@ -1060,7 +1111,7 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
       }
     }
     wave_lds_sync();
-    rows_flush<LOSS>(a, qu, qn, r * kRangeW + listed, nq, acc, touched);
+    rows_flush<LOSS>(a, qu, qn, r * kRangeW + listed, nq, acc, aabs, touched);
     listed += qn;
     if (lane == 0) a.u_cnt[r] = listed;
     wave_lds_sync();
@@ -1068,7 +1119,11 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) {
     const double v = wave_sum(acc[q]);
-    if (lane == 0) red[wv][q] = v;
+    const double va = wave_sum(aabs[q]);
+    if (lane == 0) {
+      red[wv][q] = v;
+      red[wv][kQGroup + 2 + q] = va;
+    }
   }
   {
     const double v = wave_sum(touched);
@@ -1079,20 +1134,25 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
     }
   }
   __syncthreads();
-  if (threadIdx.x < nq)
-    a.part[(int64_t)threadIdx.x * G + bx] =
-        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-  if (threadIdx.x == kQGroup)
-    a.part[(int64_t)(2 * a.Q + 1) * G + bx] =
-        ((red[0][kQGroup] + red[1][kQGroup]) + red[2][kQGroup]) + red[3][kQGroup];
-  if (threadIdx.x == kQGroup + 1)
-    a.part[(int64_t)(2 * a.Q + 2) * G + bx] =
-        ((red[0][kQGroup + 1] + red[1][kQGroup + 1]) + red[2][kQGroup + 1]) + red[3][kQGroup + 1];
+  {
+    // part rows: q -> loss sum of candidate q; 2Q+1 touched rows; 2Q+2
+    // nonzeros with d_j != 0; 2Q+3+q -> rounding scale of the loss changes of
+    // candidate q
+    const int v = threadIdx.x;
+    const double tot = v < 2 * kQGroup + 2
+                           ? ((red[0][v] + red[1][v]) + red[2][v]) + red[3][v]
+                           : 0.0;
+    if (v < nq) a.part[(int64_t)v * G + bx] = tot;
+    if (v == kQGroup) a.part[(int64_t)(2 * a.Q + 1) * G + bx] = tot;
+    if (v == kQGroup + 1) a.part[(int64_t)(2 * a.Q + 2) * G + bx] = tot;
+    if (v >= kQGroup + 2 && v < kQGroup + 2 + nq)
+      a.part[(int64_t)(2 * a.Q + 3 + (v - kQGroup - 2)) * G + bx] = tot;
+  }
   __syncthreads();
   // Delta and the regulariser change of the bundle coordinates
   double del = 0.0;
 #pragma unroll
-  for (int q = 0; q < kQGroup; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kQGroup; ++q) acc[q] = aabs[q] = 0.0;
   const int64_t Pt = hi_act - a.slot_lo;
   for (int64_t r = (int64_t)bx * kBlock + threadIdx.x; r < Pt; r += (int64_t)G * kBlock) {
     const int64_t slot = a.slot_lo + r;
@@ -1103,7 +1163,9 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
 #pragma unroll
     for (int q = 0; q < kQGroup; ++q) {
       if (q < nq) {
-        acc[q] += reg_change(wj, al * dj, a.ra, a.rb);
+        const double rc = reg_change(wj, al * dj, a.ra, a.rb);
+        acc[q] += rc;
+        aabs[q] += reg_change_scale(wj, al * dj, a.ra, a.rb);
         al *= a.beta;
       }
     }
@@ -1111,19 +1173,29 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) {
     const double v = wave_sum(acc[q]);
-    if (lane == 0) red[wv][q] = v;
+    const double va = wave_sum(aabs[q]);
+    if (lane == 0) {
+      red[wv][q] = v;
+      red[wv][kQGroup + 2 + q] = va;
+    }
   }
   {
     const double v = wave_sum(del);
     if (lane == 0) red[wv][kQGroup] = v;
   }
   __syncthreads();
-  if (threadIdx.x < nq)
-    a.part[(int64_t)(a.Q + threadIdx.x) * G + bx] =
-        ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-  if (threadIdx.x == kQGroup)
-    a.part[(int64_t)(2 * a.Q) * G + bx] =
-        ((red[0][kQGroup] + red[1][kQGroup]) + red[2][kQGroup]) + red[3][kQGroup];
+  {
+    // part rows: Q+q -> regulariser change of candidate q; 2Q Delta;
+    // 3Q+3+q -> rounding scale of the regulariser changes of candidate q
+    const int v = threadIdx.x;
+    const double tot = v < 2 * kQGroup + 2
+                           ? ((red[0][v] + red[1][v]) + red[2][v]) + red[3][v]
+                           : 0.0;
+    if (v < nq) a.part[(int64_t)(a.Q + v) * G + bx] = tot;
+    if (v == kQGroup) a.part[(int64_t)(2 * a.Q) * G + bx] = tot;
+    if (v >= kQGroup + 2 && v < kQGroup + 2 + nq)
+      a.part[(int64_t)(3 * a.Q + 3 + (v - kQGroup - 2)) * G + bx] = tot;
+  }
 }
 
 template <int LOSS>
@@ -1144,25 +1216,37 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
 // step and objective change.
 template <int LOSS>
 __device__ inline int rows_more_candidates(const RowsArgs& a, int64_t nr, int64_t hi_act,
-                                           double& Dq, double& al, double& dF, double* lds4) {
+                                           double& Dq, double& al, double& dF, double& margin,
+                                           double* lds4) {
   const int lane = lane_id(), wv = wave_in_block();
   for (int q = kQGroup; q < a.Q; ++q) {
-    double sl = 0.0;
+    double sl = 0.0, sla = 0.0;
     for (int64_t r = wv; r < nr; r += kWavesPerBlock) {
       const int32_t cnt = a.u_cnt[r];
       for (int32_t i = lane; i < cnt; i += kWave) {
         const int32_t row = a.u_row[r * kRangeW + i];
         double s = a.u_dtx[r * kRangeW + i];
         for (int t = 0; t < q; ++t) s *= a.beta;
-        sl += loss_delta<LOSS>(a.cache[row], (int)a.y[row], s);
+        const double c = a.cache[row];
+        const int yi = (int)a.y[row];
+        const double t = loss_delta<LOSS>(c, yi, s);
+        sl += t;
+        sla += loss_delta_scale<LOSS>(c, yi, s, t);
       }
     }
-    double l1 = 0.0;
-    for (int64_t slot = a.slot_lo + threadIdx.x; slot < hi_act; slot += kBlock)
-      l1 += reg_change(a.w[a.perm[slot]], al * a.d[slot], a.ra, a.rb);
+    double l1 = 0.0, l1a = 0.0;
+    for (int64_t slot = a.slot_lo + threadIdx.x; slot < hi_act; slot += kBlock) {
+      const double wj = a.w[a.perm[slot]], sj = al * a.d[slot];
+      const double rc = reg_change(wj, sj, a.ra, a.rb);
+      l1 += rc;
+      l1a += reg_change_scale(wj, sj, a.ra, a.rb);
+    }
     const double sL = block_sum(sl, lds4);
     const double L1 = block_sum(l1, lds4);
-    const double f = L1 + a.C * sL;
+    const double sLa = block_sum(sla, lds4);
+    const double L1a = block_sum(l1a, lds4);
+    const double f = L1 + *a.Cp * sL;
+    margin = fmin(margin, armijo_margin(f, a.sigma * Dq, L1a + *a.Cp * sLa));
     if (f <= a.sigma * Dq) {
       dF = f;
       return q;
@@ -1186,12 +1270,17 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: nothing ran
   const int nq = a.Q < kQGroup ? a.Q : kQGroup;
   const double Delta = ls_total(a.part, 2 * a.Q, a.G, lds4);
-  double Dq = Delta, al = 1.0, dF = 0.0;
+  double Dq = Delta, al = 1.0, dF = 0.0, margin = INFINITY;
   int q_acc = -1;
   for (int q = 0; q < nq; ++q) {
     const double sL = ls_total(a.part, q, a.G, lds4);
     const double l1 = ls_total(a.part, a.Q + q, a.G, lds4);
-    const double f = l1 + a.C * sL;
+    const double f = l1 + *a.Cp * sL;
+    if (bid == 0) {  // only block 0 records the margin
+      const double sabs = ls_total(a.part, 2 * a.Q + 3 + q, a.G, lds4);
+      const double l1abs = ls_total(a.part, 3 * a.Q + 3 + q, a.G, lds4);
+      margin = fmin(margin, armijo_margin(f, a.sigma * Dq, l1abs + *a.Cp * sabs));
+    }
     if (f <= a.sigma * Dq) {
       q_acc = q;
       dF = f;
@@ -1208,7 +1297,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   if (q_acc < 0 && a.Q > nq) {
     if (bid != 0) return;
     alone = true;
-    q_acc = rows_more_candidates<LOSS>(a, nr, hi_act, Dq, al, dF, lds4);
+    q_acc = rows_more_candidates<LOSS>(a, nr, hi_act, Dq, al, dF, margin, lds4);
   }
   if (bid == 0 && threadIdx.x == 0) {
     a.st->q = q_acc;
@@ -1220,6 +1309,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
     if (q_acc < 0) atomicAdd(&a.stats->ls_fail, 1ull);
     atomicAdd(&a.stats->rows_touched, (unsigned long long)touched);
     atomicAdd(&a.stats->nnz_scat_rows, (unsigned long long)nz_d);
+    atomicMin(&a.stats->min_margin_bits, (unsigned long long)__double_as_longlong(margin));
   }
   if (q_acc < 0) return;
   const int lane = lane_id();
@@ -1231,10 +1321,10 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
       const int32_t row = a.u_row[r * kRangeW + i];
       double s = a.u_dtx[r * kRangeW + i];
       for (int t = 0; t < q_acc; ++t) s *= a.beta;
-      if (LOSS == kLogistic)
-        a.cache[row] *= exp(s);
-      else
-        a.cache[row] -= a.y[row] > 0 ? s : -s;
+      const double c = a.cache[row];
+      store_retained<LOSS>(&a.cache[row],
+                           LOSS == kLogistic ? c * exp(s) : c - (a.y[row] > 0 ? s : -s),
+                           a.stats);
     }
   }
   const int64_t tid = alone ? threadIdx.x : bid * kBlock + threadIdx.x;
@@ -1428,7 +1518,7 @@ __device__ inline double block_sum16(double v, double* lds16) {
 // totals.  Double-buffered LDS: one barrier per call suffices because a buffer
 // is rewritten only two calls later, after another barrier.
 template <int NV>
-__device__ inline void block_sums(double (&v)[NV], double (*red)[kNarrowWaves][4], int& buf) {
+__device__ inline void block_sums(double (&v)[NV], double (*red)[kNarrowWaves][6], int& buf) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if (lane_id() == 0)
@@ -1535,7 +1625,7 @@ static_assert(kNarrowLidCap <= kTouchCap, "local row ids index the LDS row lists
 
 struct NarrowLds {
   double lds16[kNarrowWaves];
-  double red[2][kNarrowWaves][4];
+  double red[2][kNarrowWaves][6];
   double dmx[kNarrowWaves];             // per-wave max |d_j|
   int32_t any_d;                        // some direction of the bundle is nonzero
   int32_t off[kNarrowMaxP + 1];        // nonzero offsets of the bundle's slots
@@ -1607,9 +1697,10 @@ template <int LOSS>
 __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) {
   const SweepArgs& a = na.sw;
   const int tid = threadIdx.x;
-  double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0;
+  double n_bundles = 0.0, n_ls = 0.0, n_fail = 0.0, n_touched = 0.0, margin = INFINITY;
   double n_nnz = 0.0, n_slots = 0.0;      // uniform
   double n_scat = 0.0, n_scat_long = 0.0;  // this thread's slots
+  const double Cv = *a.Cp;
   int64_t t_end = na.t_end, p_lim = na.p;
   if (na.p_active) {  // shrinking: bundles of the active features only
     const int64_t pa = (int64_t)*na.p_active;
@@ -1714,11 +1805,11 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     for (int32_t s = tid; s < ns; s += kNarrowBlock) {
       double g, h;
       if (LOSS == kLogistic) {
-        g = na.C * L.acc[s].x;
-        h = na.C * L.acc[s].y;
+        g = Cv * L.acc[s].x;
+        h = Cv * L.acc[s].y;
       } else {
-        g = -2.0 * na.C * L.acc[s].x;
-        h = 2.0 * na.C * L.acc[s].y;
+        g = -2.0 * Cv * L.acc[s].x;
+        h = 2.0 * Cv * L.acc[s].y;
       }
       if (h <= 0.0) h += a.nu;
       const double wj = L.w[s];
@@ -1859,7 +1950,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     double Delta = 0.0, Dq = 0.0, al = 1.0, dF = 0.0;
     int q_acc = -1;
     for (int q = 0; q < na.max_ls; ++q) {
-      double sl = 0.0, l1 = 0.0, touched = 0.0;
+      double sl = 0.0, l1 = 0.0, touched = 0.0, sla = 0.0, l1a = 0.0;
       if (listed) {
         for (int32_t e = tid; e < R; e += kNarrowBlock) {
           const unsigned long long ac = L.t_acc[e];
@@ -1867,7 +1958,9 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           touched += 1.0;
           double sv = fx_value(ac, isc);
           for (int u = 0; u < q; ++u) sv *= na.beta;
-          sl += loss_delta<LOSS>(L.t_c[e], (int)L.t_y[e], sv);
+          const double ld = loss_delta<LOSS>(L.t_c[e], (int)L.t_y[e], sv);
+          sl += ld;
+          sla += loss_delta_scale<LOSS>(L.t_c[e], (int)L.t_y[e], sv, ld);
         }
       } else {
         // every sample, the loads of kNarrowRegRounds samples issued
@@ -1893,28 +1986,39 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
               touched += 1.0;
               double sv = fx_value(fa[u], isc);
               for (int k = 0; k < q; ++k) sv *= na.beta;
-              sl += loss_delta<LOSS>(fc[u], fy[u], sv);
+              const double ld = loss_delta<LOSS>(fc[u], fy[u], sv);
+              sl += ld;
+              sla += loss_delta_scale<LOSS>(fc[u], fy[u], sv, ld);
             }
           }
         }
       }
-      for (int32_t s = tid; s < ns; s += kNarrowBlock) l1 += reg_change(L.w[s], al * L.d[s], a.ra, a.rb);
-      double sL, L1;
+      for (int32_t s = tid; s < ns; s += kNarrowBlock) {
+        const double rc = reg_change(L.w[s], al * L.d[s], a.ra, a.rb);
+        l1 += rc;
+        l1a += reg_change_scale(L.w[s], al * L.d[s], a.ra, a.rb);
+      }
+      double sL, L1, sLa, L1a;
       if (q == 0) {
-        double v4[4] = {sl, l1, del, touched};
+        double v6[6] = {sl, l1, del, touched, sla, l1a};
+        block_sums<6>(v6, L.red, rbuf);
+        sL = v6[0];
+        L1 = v6[1];
+        Delta = v6[2];
+        Dq = Delta;
+        n_touched += v6[3];
+        sLa = v6[4];
+        L1a = v6[5];
+      } else {
+        double v4[4] = {sl, l1, sla, l1a};
         block_sums<4>(v4, L.red, rbuf);
         sL = v4[0];
         L1 = v4[1];
-        Delta = v4[2];
-        Dq = Delta;
-        n_touched += v4[3];
-      } else {
-        double v2[2] = {sl, l1};
-        block_sums<2>(v2, L.red, rbuf);
-        sL = v2[0];
-        L1 = v2[1];
+        sLa = v4[2];
+        L1a = v4[3];
       }
-      const double f = L1 + na.C * sL;
+      const double f = L1 + Cv * sL;
+      margin = fmin(margin, armijo_margin(f, na.sigma * Dq, L1a + Cv * sLa));
       if (f <= na.sigma * Dq) {
         q_acc = q;
         dF = f;
@@ -1950,10 +2054,10 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           double sv = fx_value(ac, isc);
           for (int u = 0; u < q_acc; ++u) sv *= na.beta;
           const int32_t i = L.t_row[e];
-          if (LOSS == kLogistic)
-            na.cache[i] = L.t_c[e] * exp(sv);
-          else
-            na.cache[i] = L.t_c[e] - (L.t_y[e] > 0 ? sv : -sv);
+          store_retained<LOSS>(&na.cache[i],
+                               LOSS == kLogistic ? L.t_c[e] * exp(sv)
+                                                 : L.t_c[e] - (L.t_y[e] > 0 ? sv : -sv),
+                               na.stats);
         }
       }
     } else {
@@ -1981,10 +2085,10 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           if (q_acc >= 0) {
             double sv = fx_value(fa[u], isc);
             for (int k = 0; k < q_acc; ++k) sv *= na.beta;
-            if (LOSS == kLogistic)
-              na.cache[i] = fc[u] * exp(sv);
-            else
-              na.cache[i] = fc[u] - (fy[u] > 0 ? sv : -sv);
+            store_retained<LOSS>(&na.cache[i],
+                                 LOSS == kLogistic ? fc[u] * exp(sv)
+                                                   : fc[u] - (fy[u] > 0 ? sv : -sv),
+                                 na.stats);
           }
           __hip_atomic_store(&gacc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -2014,6 +2118,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
     if (n_fail > 0.0) atomicAdd(&na.stats->ls_fail, (unsigned long long)n_fail);
     atomicAdd(&na.stats->rows_touched, (unsigned long long)n_touched);
     atomicAdd(&na.stats->rows_touched_narrow, (unsigned long long)n_touched);
+    atomicMin(&na.stats->min_margin_bits, (unsigned long long)__double_as_longlong(margin));
   }
 }
 
@@ -2275,7 +2380,7 @@ template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_margins_rows(const int64_t* rp, const int32_t* col,
                                                          const float* v, const double* w,
                                                          const int8_t* y, int64_t n,
-                                                         double* cache) {
+                                                         double* cache, Stats* stats) {
   const int lane = lane_id();
   const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
@@ -2283,7 +2388,9 @@ __global__ __launch_bounds__(kBlock) void k_margins_rows(const int64_t* rp, cons
     double z = 0.0;
     for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kWave) z += (double)v[k] * w[col[k]];
     z = wave_sum(z);
-    if (lane == 0) cache[i] = LOSS == kLogistic ? exp(z) : 1.0 - (y[i] > 0 ? z : -z);
+    if (lane == 0)
+      store_retained<LOSS>(&cache[i], LOSS == kLogistic ? exp(z) : 1.0 - (y[i] > 0 ? z : -z),
+                           stats);
   }
 }
 
@@ -2841,12 +2948,14 @@ hipError_t launch_reg_terms(const double* w, int64_t p, double ra, double rb, do
 
 hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, const float* v,
                                const double* w, const int8_t* y, int64_t n, double* cache,
-                               hipStream_t s) {
+                               Stats* stats, hipStream_t s) {
   const dim3 g(grid_for(n, kWavesPerBlock, 8192));
   if (loss == kLogistic)
-    hipLaunchKernelGGL(k_margins_rows<kLogistic>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n, cache);
+    hipLaunchKernelGGL(k_margins_rows<kLogistic>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n,
+                       cache, stats);
   else
-    hipLaunchKernelGGL(k_margins_rows<kL2Svm>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n, cache);
+    hipLaunchKernelGGL(k_margins_rows<kL2Svm>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n,
+                       cache, stats);
   return hipGetLastError();
 }
 

@@ -202,8 +202,6 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->nch = k.take<int32_t>(p);
   t->cstart = k.take<int32_t>(p + 1);
   t->chunks = k.take<Chunk>(max_chunks);
-  t->id_cstart = k.take<int32_t>(p + 1);
-  t->id_chunks = k.take<Chunk>(max_chunks);
   t->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
   t->part = k.take<double2>(t->part_len);
   t->pri = k.take<int32_t>(nnz);
@@ -213,7 +211,7 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->off32 = k.take<int32_t>(p + 1);
   t->plid = k.take<uint16_t>(nnz);
   t->pR = k.take<int32_t>(p + 1);
-  t->ls_part = k.take<double>((int64_t)kRowsGridMax * (2 * kQMax + 3));
+  t->ls_part = k.take<double>((int64_t)kRowsGridMax * (4 * kQMax + 3));
   t->act = k.take<double>(p);
   t->rp = k.take<int64_t>(n + 1);
   t->rr = k.take<int32_t>(nnz);
@@ -333,6 +331,7 @@ int solve_static(int device, hipStream_t stream, int64_t n, int64_t p, int64_t n
                      (int64_t)(sizeof(IterState) / 8));
   hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (unsigned long long*)c->stats,
                      (int64_t)(sizeof(Stats) / 8));
+  c->range_seen = 0;
   hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (unsigned long long*)x.err, (int64_t)1);
   hipLaunchKernelGGL(k_zero_words, dim3(grid_of(n)), dim3(256), 0, s, (unsigned long long*)c->dtx, n);
   // input checks: col_ptr first (the others index through it)
@@ -366,8 +365,6 @@ int solve_static(int device, hipStream_t stream, int64_t n, int64_t p, int64_t n
   hipLaunchKernelGGL(k_row_ptr, dim3(grid_of(nnz + 1)), dim3(256), 0, s, c->rr, nnz, n, c->rp);
   hipLaunchKernelGGL(k_row_l1, dim3(grid_of(n)), dim3(256), 0, s, c->rp, c->rv, n, c->tmp_n);
   hipLaunchKernelGGL(k_max, dim3(1), dim3(256), 0, s, c->tmp_n, n, x.xrow);
-  HIPCHK(c, launch_chunks(nullptr, c->cp, p, kChunk, c->nch, c->id_cstart, c->id_chunks,
-                          c->scan_tmp, s));
   HIPCHK(c, hipGetLastError());
   double xrow = 0.0;
   HIPCHK(c, hipMemcpyAsync(&xrow, x.xrow, sizeof(double), hipMemcpyDeviceToHost, s));

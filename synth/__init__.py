@@ -295,8 +295,13 @@ def c4b_shapes(seed: int = BASE_SEED + 4, count: int = 64, scale: float = 1.0):
 def c4b(seed: int = BASE_SEED + 4, count: int = 64, scale: float = 1.0) -> list:
     """The batched independent LR problems (see c4b_shapes), each drawn by
     bernoulli_csc with its own seed."""
-    return [bernoulli_csc(seed * 1000 + i, n, p, d)
-            for i, (n, p, d) in enumerate(c4b_shapes(seed, count, scale))]
+    return [c4b_problem(i, seed, count, scale) for i in range(count)]
+
+
+def c4b_problem(i: int, seed: int = BASE_SEED + 4, count: int = 64, scale: float = 1.0) -> Data:
+    """Problem i of c4b alone."""
+    n, p, d = c4b_shapes(seed, count, scale)[i]
+    return bernoulli_csc(seed * 1000 + i, n, p, d)
 
 
 def zipf_rows_csc(seed: int, n: int, p: int, row_lo: int, row_hi: int, a: float,

@@ -354,7 +354,9 @@ def test_batch_autotuned_jobs(pc):
     out = pc.solve_batch([s.job(1.0, 0, 1e-4, "lr", seed=4) for s in solvers])
     for s, b in zip(solvers, out):
         assert b[2]["P"] >= 1
-        alone = s.solve(1.0, b[2]["P"], 1e-4, "lr", seed=4)
+        # the tuner's schedule and chunk, which fix the summation order
+        alone = s.solve(1.0, b[2]["P"], 1e-4, "lr", seed=4, schedule=b[2]["schedule"],
+                        chunk=b[2]["chunk"])
         _assert_same_run(b, alone)
     for s in solvers:
         s.close()
