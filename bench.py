@@ -34,7 +34,10 @@ More objects on the same line:
   (bundle size, schedule and chunk length from the autotuner, tuned before
   timing);
 - "path": 32 C values on the text-like matrix with warm starts,
-  pcdn_solve_path against the same chain of pcdn_solve calls;
+  pcdn_solve_path against the same chain of pcdn_solve calls, against the
+  32 solves one at a time from w = 0, and the path cut into 8 warm-started
+  runs advanced together (pcdn_solve_path_lanes, every solve to the same
+  stopping rule);
 - "serving" (skipped with --no-serving): a Poisson stream of mixed LR/SVM
   solves through the solve server against one solve after another.
 """
@@ -65,6 +68,7 @@ KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep and direction, one wavefront pe
 C3 = dict(C=1.0, P=16384, eps=1e-3, loss="svm")
 SETTINGS = [(0.5, 64), (0.5, 1024), (0.5, 8192), (4.0, 64), (4.0, 1024), (4.0, 8192)]
 SEED = 1
+PATH_LANES = 8
 
 
 def parse():
@@ -219,13 +223,33 @@ def path_measurement(pc, d) -> dict:
         _, w, info = s.solve(float(C), P, 1e-4, "lr", seed=SEED, w0=w)
         outer += info["outer_iters"]
     t_plain = time.perf_counter() - t0
-    s.close()
+    # one solve at a time, each from w = 0
+    t0 = time.perf_counter()
+    cold_outer = 0
+    for C in Cs:
+        cold_outer += s.solve(float(C), P, 1e-4, "lr", seed=SEED)[2]["outer_iters"]
+    t_cold = time.perf_counter() - t0
+    # the path cut into runs on 8 contexts (loaded before the timed region)
+    lanes = [s] + [pc.Solver(device=0).load_data(d) for _ in range(PATH_LANES - 1)]
+    t0 = time.perf_counter()
+    rl, Wl, il = pc.pcdn_solve_path_lanes([x.ctx for x in lanes], Cs, P, 1e-4, "lr", d.p,
+                                          seed=SEED)
+    t_lanes = time.perf_counter() - t0
+    for x in lanes:
+        x.close()
+    n = len(Cs)
     return {"workload": "32 C values 2^-4..2^6 (log-spaced, ascending) on the text-like "
                         "L1-LR matrix, warm starts, eps=1e-4",
             "P": int(P), "path_s": t_path, "plain_chain_s": t_plain,
-            "path_solves_per_s": len(Cs) / t_path, "plain_solves_per_s": len(Cs) / t_plain,
+            "path_solves_per_s": n / t_path, "plain_solves_per_s": n / t_plain,
             "path_outer_iters": int(sum(i["outer_iters"] for i in infos)),
-            "plain_outer_iters": int(outer)}
+            "plain_outer_iters": int(outer),
+            "cold_solves_per_s": n / t_cold, "cold_outer_iters": int(cold_outer),
+            "lanes": PATH_LANES, "lanes_s": t_lanes, "lanes_solves_per_s": n / t_lanes,
+            "lanes_outer_iters": int(sum(i["outer_iters"] for i in il)),
+            "lanes_all_converged": bool(rl == 0 and all(i["converged"] for i in il)),
+            "lanes_speedup_vs_plain_chain": t_plain / t_lanes,
+            "path_speedup_vs_plain_chain": t_plain / t_path}
 
 
 def _percentiles(lat):

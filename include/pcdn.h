@@ -49,7 +49,9 @@ enum {
   PCDN_E_OOM = -3,     /* device allocation failed                          */
   PCDN_E_DEVICE = -4,  /* HIP runtime error                                 */
   PCDN_E_STATE = -5,   /* call out of order (no data loaded, no state set)  */
-  PCDN_E_NUMERIC = -6  /* NaN reached the objective                         */
+  PCDN_E_NUMERIC = -6  /* NaN reached the objective, or a retained quantity
+                          left its range (e^{w^T x_i} not a positive normal
+                          double, |w^T x_i| above about 708; b_i not finite) */
 };
 
 /* Options.  A zero-filled struct (or NULL) selects the paper's settings:
@@ -303,6 +305,23 @@ int pcdn_iterate_batch(pcdn_ctx* const* ctxs, const int64_t* P, int32_t count, i
 int pcdn_solve_path(pcdn_ctx* ctx, const double* Cs, int32_t count, int64_t P, double eps,
                     int loss, const pcdn_opts* opts, double* W_out, pcdn_info* infos);
 
+/* The regularisation path over `lanes` contexts that hold the same X and y
+ * (same n, p, nnz and contents; else PCDN_E_ARG): Cs is cut into
+ * min(lanes, count) contiguous runs of equal length (+-1), run i =
+ * Cs[floor(i count / L)] .. Cs[floor((i + 1) count / L) - 1] is solved on
+ * ctxs[i] as pcdn_solve_path solves it (the first C from opts->w0 or 0, each
+ * next one warm-started from the previous solution), and the runs advance
+ * together, one outer iteration of every unfinished run per round of the
+ * batch engine (as pcdn_solve_batch).  Each solve meets the same stopping
+ * rule as in pcdn_solve_path, and a run's solves are those pcdn_solve_path
+ * gives for that run alone; only the first C of each run starts cold.  The
+ * contexts' states are overwritten; ctxs[i] is left with the last solution
+ * of run i.  W_out (nullable, host, count x p) and infos (nullable, count)
+ * are indexed like Cs.  Returns as pcdn_solve_path. */
+int pcdn_solve_path_lanes(pcdn_ctx* const* ctxs, int32_t lanes, const double* Cs, int32_t count,
+                          int64_t P, double eps, int loss, const pcdn_opts* opts, double* W_out,
+                          pcdn_info* infos);
+
 /* Bundle-size autotuning (pcdn_autotune). */
 typedef struct {
   int64_t P;                /* candidate bundle size                             */
@@ -351,7 +370,9 @@ int pcdn_autotune(pcdn_ctx* ctx, int loss, double C, double eps, const pcdn_opts
 
 /* Set the device state to (loss, C, w): w (host, p doubles) or zeros if NULL;
  * the retained e^{w^T x_i} (logistic) or b_i = 1 - y_i w^T x_i (SVM) are
- * recomputed from w in FP64 (Sec. 3.1). */
+ * recomputed from w in FP64 (Sec. 3.1).  PCDN_E_NUMERIC if a retained
+ * quantity falls outside its range (see PCDN_E_NUMERIC); pcdn_step and the
+ * solves report a step that takes one there the same way. */
 int pcdn_reset(pcdn_ctx* ctx, int loss, double C, const double* w);
 
 /* One inner iteration of Algorithm 3 on an explicit bundle (host array of P

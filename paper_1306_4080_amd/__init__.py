@@ -12,7 +12,7 @@ from .binding import (LOSSES, PCDN_LOSS_L2SVM, PCDN_LOSS_LOGISTIC, PcdnError, Se
                       load_library, pcdn_create, pcdn_destroy, pcdn_evaluate, pcdn_get_cache,
                       pcdn_get_w, pcdn_iterate, pcdn_last_error, pcdn_load_csc, pcdn_load_csc_bias, pcdn_permutation, pcdn_profile,
                       pcdn_autotune, pcdn_profile_read, pcdn_reset, pcdn_solve, pcdn_solve_batch,
-                      pcdn_solve_path, pcdn_solve_static, pcdn_step, solve_batch, pcdn_iterate_batch, iterate_batch)
+                      pcdn_solve_path, pcdn_solve_path_lanes, pcdn_solve_static, pcdn_step, solve_batch, pcdn_iterate_batch, iterate_batch)
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpcdn.so")
 

@@ -32,7 +32,7 @@ LOSSES = {"lr": PCDN_LOSS_LOGISTIC, "logistic": PCDN_LOSS_LOGISTIC,
 # entry points declared in include/pcdn.h
 SYMBOLS = ("pcdn_create", "pcdn_load_csc", "pcdn_load_csc_bias", "pcdn_solve", "pcdn_reset", "pcdn_step",
            "pcdn_iterate",
-           "pcdn_solve_batch", "pcdn_solve_path", "pcdn_autotune", "pcdn_iterate_batch",
+           "pcdn_solve_batch", "pcdn_solve_path", "pcdn_solve_path_lanes", "pcdn_autotune", "pcdn_iterate_batch",
            "pcdn_server_create", "pcdn_server_submit", "pcdn_server_step", "pcdn_server_status",
            "pcdn_server_take", "pcdn_server_last_error", "pcdn_server_destroy",
            "pcdn_permutation", "pcdn_get_w", "pcdn_get_cache", "pcdn_evaluate",
@@ -136,6 +136,9 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(pcdn_tune)]
     L.pcdn_solve_path.argtypes = [vp, ctypes.POINTER(dbl), ctypes.c_int32, i64, dbl, i32,
                                   ctypes.POINTER(pcdn_opts), vp, ctypes.POINTER(pcdn_info)]
+    L.pcdn_solve_path_lanes.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(dbl),
+                                        ctypes.c_int32, i64, dbl, i32, ctypes.POINTER(pcdn_opts),
+                                        vp, ctypes.POINTER(pcdn_info)]
     L.pcdn_permutation.argtypes = [vp, u64, i64, vp]
     L.pcdn_get_w.argtypes = [vp, vp]
     L.pcdn_get_cache.argtypes = [vp, vp]
@@ -360,6 +363,23 @@ def pcdn_solve_path(ctx, Cs, P, eps, loss, p, **opts):
                                         len(Cs), int(P), float(eps), int(loss), ctypes.byref(o),
                                         W.ctypes.data, infos)
     _check(ctx, rc, (PCDN_OK, PCDN_NOT_CONVERGED))
+    return rc, W, [_info_dict(infos[k]) for k in range(len(Cs))]
+
+
+def pcdn_solve_path_lanes(ctxs, Cs, P, eps, loss, p, **opts):
+    """The path over len(ctxs) contexts holding the same data (contiguous runs
+    of Cs advanced together); returns (status, W, list of info dicts)."""
+    loss = LOSSES.get(loss, loss)
+    Cs = np.ascontiguousarray(Cs, dtype=np.float64)
+    o, keep = _opts(**opts)
+    W = np.empty((len(Cs), int(p)), dtype=np.float64)
+    infos = (pcdn_info * max(len(Cs), 1))()
+    arr = (ctypes.c_void_p * len(ctxs))(*ctxs)
+    rc = load_library().pcdn_solve_path_lanes(arr, len(ctxs),
+                                              Cs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              len(Cs), int(P), float(eps), int(loss),
+                                              ctypes.byref(o), W.ctypes.data, infos)
+    _check(ctxs[0], rc, (PCDN_OK, PCDN_NOT_CONVERGED))
     return rc, W, [_info_dict(infos[k]) for k in range(len(Cs))]
 
 

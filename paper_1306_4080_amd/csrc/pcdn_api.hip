@@ -414,6 +414,40 @@ int cache_from_w(pcdn_ctx* c, bool w_is_zero) {
   return range_check(c, "w puts e^{w^T x_i} outside the normal doubles (|w^T x_i| > ~708)");
 }
 
+// A 64-bit fingerprint of (n, p, nnz, X, y): 8-byte words mixed by
+// multiply and xor-shift, to tell whether two contexts hold the same data.
+uint64_t data_fingerprint(int64_t n, int64_t p, int64_t nnz, const int64_t* cp,
+                          const int32_t* ri, const float* v, const int8_t* y) {
+  uint64_t h = 0x243f6a8885a308d3ull;
+  auto mix = [&h](uint64_t x) {
+    h ^= x + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+  };
+  auto bytes = [&mix](const void* a, size_t len) {
+    const unsigned char* b = (const unsigned char*)a;
+    size_t i = 0;
+    for (; i + 8 <= len; i += 8) {
+      uint64_t x;
+      std::memcpy(&x, b + i, 8);
+      mix(x);
+    }
+    uint64_t t = 0;
+    std::memcpy(&t, b + i, len - i);
+    mix(t ^ ((uint64_t)(len - i) << 56));
+  };
+  mix((uint64_t)n);
+  mix((uint64_t)p);
+  mix((uint64_t)nnz);
+  bytes(cp, (size_t)(p + 1) * sizeof(int64_t));
+  if (nnz) {
+    bytes(ri, (size_t)nnz * sizeof(int32_t));
+    bytes(v, (size_t)nnz * sizeof(float));
+  }
+  bytes(y, (size_t)n);
+  return h;
+}
+
 // C on the host and in the device scalar the kernels read (scal[kScalC]).
 int set_C(pcdn_ctx* c, double C) {
   c->C = C;
@@ -1132,6 +1166,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
 
   HIPCHK(c, hipStreamSynchronize(c->stream));
   free_data(c);
+  c->data_hash = data_fingerprint(n, p, nnz, Hcp, Hri, Hv, Hy);
   c->h_cp.assign(Hcp, Hcp + p + 1);
   {
     std::vector<int64_t> lens(p);

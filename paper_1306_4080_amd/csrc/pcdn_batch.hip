@@ -796,6 +796,94 @@ extern "C" int pcdn_solve_path(pcdn_ctx* c, const double* Cs, int32_t count, int
   return status;
 }
 
+extern "C" int pcdn_solve_path_lanes(pcdn_ctx* const* ctxs, int32_t lanes, const double* Cs,
+                                     int32_t count, int64_t P, double eps, int loss,
+                                     const pcdn_opts* opts, double* W_out, pcdn_info* infos) {
+  if (!ctxs || lanes < 1) return PCDN_E_ARG;
+  if (count < 0 || (count > 0 && !Cs)) return ctxs[0] ? fail(ctxs[0], PCDN_E_ARG, "bad C list") : PCDN_E_ARG;
+  const int32_t L = std::min(lanes, std::max(count, (int32_t)1));
+  for (int32_t i = 0; i < L; ++i) {
+    pcdn_ctx* c = ctxs[i];
+    if (!c) return PCDN_E_ARG;
+    for (int32_t k = 0; k < i; ++k)
+      if (ctxs[k] == c) return fail(c, PCDN_E_ARG, "a context appears twice");
+    if (!c->loaded) return fail(c, PCDN_E_STATE, "no data loaded");
+    if (c->device != ctxs[0]->device) return fail(c, PCDN_E_ARG, "the contexts must share one device");
+    if (c->n != ctxs[0]->n || c->p != ctxs[0]->p || c->nnz != ctxs[0]->nnz ||
+        c->data_hash != ctxs[0]->data_hash)
+      return fail(c, PCDN_E_ARG, "the contexts must hold the same X and y");
+  }
+  pcdn_ctx* c0 = ctxs[0];
+  for (int32_t k = 0; k < count; ++k) {
+    Opts o;
+    const int rc = check_solve_args(c0, Cs[k], P, eps, loss, opts, &o);
+    if (rc) return rc;
+  }
+  if (count == 0) return PCDN_OK;
+  // lane i solves Cs[first[i]] .. Cs[first[i + 1] - 1] as a warm-started chain
+  std::vector<int32_t> first(L + 1), next(L);
+  for (int32_t i = 0; i <= L; ++i) first[i] = (int32_t)(((int64_t)i * count) / L);
+  for (int32_t i = 0; i < L; ++i) next[i] = first[i];
+  std::vector<std::unique_ptr<EngineJob>> jobs(L);
+  std::vector<int32_t> at(L, -1);  // index into Cs of the lane's current solve
+  int status = PCDN_OK;
+  Engine eng;
+  int rc = eng.init(c0->device);
+  if (rc) return fail(c0, rc, eng.err);
+  // Starts lane i's next solve; solves that stop at once (w already meets
+  // the rule) finish here and the lane moves on.
+  auto start = [&](int32_t i) -> int {
+    while (next[i] < first[i + 1]) {
+      const int32_t k = next[i]++;
+      auto j = std::make_unique<EngineJob>();
+      SolveRun& r = j->run;
+      int src = check_solve_args(ctxs[i], Cs[k], P, eps, loss, opts, &r.o);
+      if (src) return src;
+      r.c = ctxs[i];
+      r.C = Cs[k];
+      r.P = P;
+      r.eps = eps;
+      r.loss = loss;
+      r.w0_device = k > first[i];  // the lane's previous solution is on the device
+      if (k > first[i]) r.o.w0 = nullptr;
+      j->id = i;
+      src = eng.add(j.get());
+      if (src) return src;
+      at[i] = k;
+      jobs[i] = std::move(j);
+      if (jobs[i]->active) return PCDN_OK;
+      src = solve_end(jobs[i]->run, W_out ? W_out + (size_t)k * (size_t)c0->p : nullptr,
+                      infos ? infos + k : nullptr);
+      if (src < 0) return src;
+      if (src == PCDN_NOT_CONVERGED) status = src;
+      jobs[i].reset();
+    }
+    return PCDN_OK;
+  };
+  for (int32_t i = 0; i < L; ++i) {
+    rc = start(i);
+    if (rc) return rc;
+  }
+  std::vector<EngineJob*> done;
+  while (eng.size() > 0) {
+    pcdn_ctx* ec = nullptr;
+    done.clear();
+    rc = eng.round(done, &ec);
+    if (rc) return ec ? rc : fail(c0, rc, eng.err);
+    for (EngineJob* j : done) {
+      const int32_t i = (int32_t)j->id, k = at[i];
+      rc = solve_end(j->run, W_out ? W_out + (size_t)k * (size_t)c0->p : nullptr,
+                     infos ? infos + k : nullptr);
+      if (rc < 0) return rc;
+      if (rc == PCDN_NOT_CONVERGED) status = rc;
+      jobs[i].reset();
+      rc = start(i);
+      if (rc) return rc;
+    }
+  }
+  return status;
+}
+
 extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const pcdn_opts* opts,
                              pcdn_tune* out) {
   if (!c) return PCDN_E_ARG;

@@ -48,6 +48,7 @@ struct pcdn_ctx {
   // data
   int64_t n = 0, p = 0, nnz = 0;
   bool loaded = false;
+  uint64_t data_hash = 0;  // fingerprint of the loaded X and y (data_fingerprint)
   int64_t* cp = nullptr;
   int32_t* ri = nullptr;
   float* v = nullptr;
@@ -227,6 +228,8 @@ int check_loss(pcdn_ctx* c, int loss);
 // it there, so captured graphs do not depend on C).
 constexpr int kScalC = 7;
 int set_C(pcdn_ctx* c, double C);
+uint64_t data_fingerprint(int64_t n, int64_t p, int64_t nnz, const int64_t* cp,
+                          const int32_t* ri, const float* v, const int8_t* y);
 // Record the regulariser that the state is being advanced with.
 void note_regulariser(pcdn_ctx* c, const Opts& o);
 // Whether a column has more than `chunk` nonzeros: only then do work items

@@ -1,7 +1,7 @@
 """Write the FP64 oracle's results for the full-size batched, path and served
 configurations into tests/golden/*.json.
 
-    python tests/golden/make_goldens.py [--jobs 7] [--only c4b|path|c5]
+    python tests/golden/make_goldens.py [--jobs 7] [--only c4b|path|lanes|c5]
 
 Only the oracle (oracle/) and the seeded input generators (synth/) run here;
 nothing reads the GPU library.  Each record holds the inputs' checksum, the
@@ -137,6 +137,33 @@ def _path() -> list:
     return out
 
 
+PATH_LANES = 8
+
+
+def _lane_runs(count: int, lanes: int) -> list:
+    """The contiguous runs pcdn_solve_path_lanes cuts count C values into."""
+    L = min(lanes, count)
+    first = [(i * count) // L for i in range(L + 1)]
+    return [(first[i], first[i + 1]) for i in range(L)]
+
+
+def _path_run(run) -> list:
+    """One run of the path over lanes: a warm-started chain from w = 0."""
+    lo, hi = run
+    d = synth.c2()
+    prob = oracle.Problem.from_data(d)
+    Cs = synth.c4_path_Cs()
+    out, w = [], None
+    for k in range(lo, hi):
+        w, info, _ = oracle.solve(prob, oracle.Params(loss="lr", C=float(Cs[k])), P=PATH_P,
+                                  eps=PATH_EPS, seed=PATH_SEED, w0=w)
+        r = _record(d, "lr", float(Cs[k]), PATH_P, PATH_EPS, PATH_SEED, info)
+        r["lane_run"] = [lo, hi]
+        out.append(r)
+        print(f"path lanes run {lo}-{hi} C={Cs[k]:.4g}: outer={info['outer_iters']}", flush=True)
+    return out
+
+
 def _write(name: str, payload) -> None:
     with open(os.path.join(HERE, name), "w") as f:
         json.dump(payload, f, indent=1)
@@ -146,9 +173,9 @@ def _write(name: str, payload) -> None:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=max(1, (os.cpu_count() or 2) - 1))
-    ap.add_argument("--only", choices=("c4b", "path", "c5"), action="append")
+    ap.add_argument("--only", choices=("c4b", "path", "lanes", "c5"), action="append")
     args = ap.parse_args()
-    todo = args.only or ["c5", "path", "c4b"]
+    todo = args.only or ["c5", "path", "lanes", "c4b"]
     oracle.build()
     with mp.get_context("fork").Pool(args.jobs) as pool:
         if "c5" in todo:
@@ -164,6 +191,12 @@ def main():
             recs = sorted(pool.map(_c4b_one, order, chunksize=1), key=lambda r: r["index"])
             _write("c4b_batched_problems.json", {"note": "oracle results of the 64 batched LR "
                                                  "problems (P = 5% of p)", "records": recs})
+        if "lanes" in todo:
+            runs = _lane_runs(len(synth.c4_path_Cs()), PATH_LANES)
+            recs = [r for chunk in pool.map(_path_run, runs, chunksize=1) for r in chunk]
+            _write("c4a_path_lanes.json", {"note": "oracle results of the 32-C path cut into "
+                                           f"{PATH_LANES} warm-started runs (each run's first C "
+                                           "from w = 0)", "records": recs})
     if "path" in todo:
         _write("c4a_path.json", {"note": "oracle results of the 32-C warm-started path on the "
                                  "text-like matrix", "records": _path()})

@@ -256,6 +256,53 @@ def test_path_matches_oracle_chain(pc):
     s.close()
 
 
+@pytest.mark.parametrize("schedule", ["wide", "narrow"])
+def test_path_lanes_match_runs_alone_and_oracle(pc, schedule):
+    """Seven C values over three contexts holding the same data: runs
+    Cs[0:2], Cs[2:4], Cs[4:7] advance together, and each run equals
+    pcdn_solve_path over that run alone (bit for bit) and the oracle's
+    warm-started chain over it (first C from w = 0)."""
+    d = synth.c1()
+    Cs = 2.0 ** np.linspace(-4, 2, 7)
+    solvers = [pc.Solver(device=0).load_data(d) for _ in range(3)]
+    rc, W, infos = pc.pcdn_solve_path_lanes([s.ctx for s in solvers], Cs, 32, 1e-4, "lr", d.p,
+                                            seed=3, schedule=schedule)
+    assert rc == 0
+    prob = oracle.Problem.from_data(d)
+    alone = pc.Solver(device=0).load_data(d)
+    for lo, hi in ((0, 2), (2, 4), (4, 7)):
+        ra, Wa, ia = alone.solve_path(Cs[lo:hi], 32, 1e-4, "lr", seed=3, schedule=schedule)
+        w_prev = None
+        for k in range(lo, hi):
+            _assert_same_run((rc, W[k], infos[k]), (ra, Wa[k - lo], ia[k - lo]))
+            w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=float(Cs[k])), P=32,
+                                      eps=1e-4, seed=3, w0=w_prev)
+            _assert_oracle((rc, W[k], infos[k]), (w_o, io), True)
+            w_prev = w_o
+    # more lanes than C values: one C per lane
+    r1, W1, i1 = pc.pcdn_solve_path_lanes([s.ctx for s in solvers], Cs[:2], 32, 1e-4, "lr", d.p,
+                                          seed=3, schedule=schedule)
+    for k in range(2):
+        single = alone.solve(float(Cs[k]), 32, 1e-4, "lr", seed=3, schedule=schedule)
+        _assert_same_run((r1, W1[k], i1[k]), single)
+    alone.close()
+    for s in solvers:
+        s.close()
+
+
+def test_path_lanes_reject_different_data(pc):
+    from paper_1306_4080_amd import PcdnError
+    d = synth.c1()
+    e = synth.tiny(3, n=d.n, p=d.p, density=0.1)
+    a, b = pc.Solver(device=0).load_data(d), pc.Solver(device=0).load_data(e)
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.pcdn_solve_path_lanes([a.ctx, b.ctx], [0.5, 1.0], 32, 1e-4, "lr", d.p)
+    with pytest.raises(PcdnError, match="E_ARG"):
+        pc.pcdn_solve_path_lanes([a.ctx, a.ctx], [0.5, 1.0], 32, 1e-4, "lr", d.p)
+    a.close()
+    b.close()
+
+
 def test_heavy_bundles_beyond_the_list_cap(pc):
     """Every bundle heavy (1,000 bundles of ~6,000 nonzeros, more than the
     256 the list holds, each with more distinct rows than the LDS holds):

@@ -151,6 +151,24 @@ def test_full_size_regularisation_path(pc):
         _assert_golden(f"path C={r['C']:.4g}", info, r)
 
 
+def test_full_size_path_over_lanes(pc):
+    """The same 32-C path over 8 contexts (pcdn_solve_path_lanes, as the
+    bench times it): every point against the oracle's chain over its run."""
+    recs = _golden("c4a_path_lanes.json")
+    d = synth.c2()
+    assert _data_sha(d) == recs[0]["sha"]
+    Cs = synth.c4_path_Cs()
+    np.testing.assert_array_equal([r["C"] for r in recs], Cs)
+    solvers = [pc.Solver(device=0).load_data(d) for _ in range(8)]
+    rc, W, infos = pc.pcdn_solve_path_lanes([s.ctx for s in solvers], Cs, recs[0]["P"],
+                                            recs[0]["eps"], "lr", d.p, seed=recs[0]["seed"])
+    for s in solvers:
+        s.close()
+    assert rc == 0
+    for k, (info, r) in enumerate(zip(infos, recs)):
+        _assert_golden(f"lanes path C={r['C']:.4g}", info, r)
+
+
 def test_full_size_served_requests(pc):
     """Requests from the full-size serving pool (n up to 2e5, p up to 2e6,
     both losses) through the server together: each equals the request
