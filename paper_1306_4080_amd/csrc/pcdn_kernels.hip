@@ -616,6 +616,8 @@ __device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi,
       yv[u] = (int)ldz(a.y, row[u] >= 0, row[u], (int8_t)0);
     }
 #pragma unroll
+    for (int u = 0; u < kUnroll; ++u) asm volatile("" ::"v"(xv[u]), "v"(yv[u]), "v"(cv[u]));
+#pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       if (row[u] >= 0) grad_hess_term<LOSS>(cv[u], yv[u], (double)xv[u], gs, hs);
   }
@@ -706,6 +708,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
         cv[g][u] = ldz(a.cache, row[g][u] >= 0, row[g][u], 0.0);
         yv[g][u] = (int)ldz(a.y, row[g][u] >= 0, row[g][u], (int8_t)0);
       }
+    // every operand of the terms loaded here, before the first use: the
+    // compiler would otherwise sink the value and label loads into the
+    // per-nonzero branches of the loss (the SVM's active-set test) and wait
+    // for each there
+#pragma unroll
+    for (int g = 0; g < kSweepGroup; ++g)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) asm volatile("" ::"v"(xv[g][u]), "v"(yv[g][u]), "v"(cv[g][u]));
     double gs[kSweepGroup], hs[kSweepGroup];
 #pragma unroll
     for (int g = 0; g < kSweepGroup; ++g) {
@@ -782,12 +792,20 @@ __device__ inline double grad_term(double c, int yi, double x) {
 }
 
 template <int LOSS>
-__device__ inline void stop_finish_one(const StopArgs& a, int64_t j, double gs) {
-  const double C = *a.Cp;
+__device__ inline void stop_finish_one(const StopArgs& a, int64_t j, double gs, double C,
+                                       double thr, double wj) {
   const double g = LOSS == kLogistic ? C * gs : -2.0 * C * gs;
-  const double wj = a.w ? a.w[j] : 0.0;
   a.sg[j] = fabs(min_norm_subgradient(g, wj, a.ra, a.rb));
-  if (a.act) a.act[j] = (wj != 0.0 || fabs(g) >= *a.thr) ? 1.0 : 0.0;
+  if (a.act) a.act[j] = (wj != 0.0 || fabs(g) >= thr) ? 1.0 : 0.0;
+}
+
+// C and the shrinking threshold, read once before any store of the launch
+// (so they stay in registers instead of being reloaded behind every store).
+struct StopScalars {
+  double C, thr;
+};
+__device__ inline StopScalars stop_scalars(const StopArgs& a) {
+  return {*a.Cp, a.act ? *a.thr : 0.0};
 }
 
 // Wavefront w of the launch takes ranges w, w + nwaves, ...; the loads of a
@@ -798,6 +816,7 @@ __device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid,
   const int lane = lane_id();
   const int64_t nr = (a.nnz + kStopW - 1) / kStopW;
   const int64_t nwaves = nblk * kWavesPerBlock;
+  const StopScalars sc = stop_scalars(a);
   for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
     const int64_t rb = m * kStopW;
     const int64_t re = rb + kStopW < a.nnz ? rb + kStopW : a.nnz;
@@ -814,13 +833,22 @@ __device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid,
     // columns open at the range's ends
     const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
     const int32_t right = re < a.nnz ? a.ccol[re] : -1;
-    double cv[kR];
+    double cv[kR], wv[kR];
     int yv[kR];
+    // w of the lane's column, for the columns that end in this range (w = 0
+    // when a.w is null: a load of the always valid cache[0], discarded)
+    const double* wsrc = a.w ? a.w : a.cache;
 #pragma unroll
     for (int u = 0; u < kR; ++u) {
       cv[u] = ldz(a.cache, col[u] >= 0, row[u], 0.0);
       yv[u] = (int)ldz(a.y, col[u] >= 0, row[u], (int8_t)0);
+      wv[u] = ldz(wsrc, col[u] >= 0 && a.w != nullptr, col[u], 0.0);
     }
+    // keep the w loads here, issued with the others (the compiler would
+    // otherwise sink each into the branch that finishes a column, and wait
+    // for it there once per round)
+#pragma unroll
+    for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(wv[u]));
     int32_t ccar = -1;  // column carried into the next round
     double gcar = 0.0;
     double pf = 0.0, pl = 0.0;
@@ -853,7 +881,7 @@ __device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid,
         else if (ropen)
           pl = gs;
         else
-          stop_finish_one<LOSS>(a, col[u], gs);
+          stop_finish_one<LOSS>(a, col[u], gs, sc.C, sc.thr, wv[u]);
       }
     }
     // the partials (held by the lanes that ended the open segments)
@@ -886,17 +914,18 @@ __global__ __launch_bounds__(kBlock) void k_stop_ranges(StopArgs a) {
 // empty columns (g_j = 0); one thread per column.
 template <int LOSS>
 __device__ __forceinline__ void stop_finish_body(const StopArgs& a, int64_t bid, int64_t nblk) {
+  const StopScalars sc = stop_scalars(a);
   for (int64_t j = bid * kBlock + threadIdx.x; j < a.p; j += nblk * kBlock) {
     const int64_t k0 = a.cp[j], k1 = a.cp[j + 1];
     if (k1 == k0) {
-      stop_finish_one<LOSS>(a, j, 0.0);
+      stop_finish_one<LOSS>(a, j, 0.0, sc.C, sc.thr, a.w ? a.w[j] : 0.0);
       continue;
     }
     const int64_t m1 = k0 / kStopW, m2 = (k1 - 1) / kStopW;
     if (m1 == m2) continue;  // finished by its range
     double gs = a.part[m1].y;
     for (int64_t m = m1 + 1; m <= m2; ++m) gs += a.part[m].x;
-    stop_finish_one<LOSS>(a, j, gs);
+    stop_finish_one<LOSS>(a, j, gs, sc.C, sc.thr, a.w ? a.w[j] : 0.0);
   }
 }
 
@@ -969,17 +998,17 @@ __device__ inline void rows_flush(const RowsArgs& a, const RowQueue& qu, int n, 
 
 // One round of 64 nonzeros of a range: the segmented row sums (carried across
 // rounds), and the rows that end in it queued.  Returns the number queued.
-__device__ inline int rows_round(const RowsArgs& a, RowQueue& qu, int qn, int32_t row, bool owned,
-                                 double t, double c, int yi, int64_t k, int64_t e1,
-                                 int32_t& crow, double& cval) {
+__device__ inline int rows_round(RowQueue& qu, int qn, int32_t row, bool owned, double t, double c,
+                                 int yi, int32_t next63, int32_t& crow, double& cval) {
   const int lane = lane_id();
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int32_t key = owned ? row : -1;
   seg_scan1(t, key);
   if (crow >= 0 && key == crow) t += cval;
   // the row ends at this nonzero unless the next one is of the same row
+  // (for lane 63: next63, the row of the nonzero after the round, < 0 if none)
   int32_t nxt = next_lane_key(key);
-  if (lane == kWave - 1) nxt = k + 1 < e1 ? a.br_row[k + 1] : -2;
+  if (lane == kWave - 1) nxt = next63;
   const bool ends = owned && nxt != row;
   const int32_t row63 = __builtin_amdgcn_readlane(key, kWave - 1);
   const bool open63 = __builtin_amdgcn_readlane((int)(owned && !ends), kWave - 1) != 0;
@@ -1042,6 +1071,8 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
     const int32_t skip = rb > e0 ? a.br_row[rb - 1] : -1;
     int32_t tail = a.br_row[re - 1];
     if (tail == skip) tail = -1;
+    // the row of the nonzero after the last loaded round (< 0: none)
+    const int32_t after = rb + kRangeW < e1 ? a.br_row[rb + kRangeW] : -2;
     double pd[kR], pc[kR];
     int py[kR];
 #pragma unroll
@@ -1051,6 +1082,10 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
       pc[u] = ldz(a.cache, prow[u] >= 0, prow[u], 0.0);
       py[u] = (int)ldz(a.y, prow[u] >= 0, prow[u], (int8_t)0);
     }
+    // all operands loaded before the rounds use them (no load sunk into a
+    // branch and waited for there)
+#pragma unroll
+    for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(pd[u]), "v"(pc[u]), "v"(py[u]), "v"(pv[u]));
     int qn = 0;            // rows queued in LDS
     int32_t listed = 0;    // rows listed for this range
     int32_t crow = -1;     // row carried into the next round
@@ -1063,7 +1098,8 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
       const bool owned = k < e1 && prow[u] != skip && (k < re || prow[u] == tail);
       const double t = owned ? pd[u] * (double)pv[u] : 0.0;
       nz_d += owned && pd[u] != 0.0 ? 1.0 : 0.0;
-      qn += rows_round(a, qu, qn, prow[u], owned, t, pc[u], py[u], k, e1, crow, cval);
+      const int32_t n63 = u + 1 < kR ? __builtin_amdgcn_readlane(prow[u + 1], 0) : after;
+      qn += rows_round(qu, qn, prow[u], owned, t, pc[u], py[u], n63, crow, cval);
       if (qn >= kWave) {
         wave_lds_sync();
         rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, aabs, touched);
@@ -1095,7 +1131,9 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
         c = a.cache[row];
         yi = (int)a.y[row];
       }
-      qn += rows_round(a, qu, qn, row, owned, t, c, yi, k, e1, crow, cval);
+      const int64_t k63 = s0 + kWave - 1;
+      const int32_t n63 = k63 + 1 < e1 ? a.br_row[k63 + 1] : -2;
+      qn += rows_round(qu, qn, row, owned, t, c, yi, n63, crow, cval);
       if (qn >= kWave) {
         wave_lds_sync();
         rows_flush<LOSS>(a, qu, kWave, r * kRangeW + listed, nq, acc, aabs, touched);
@@ -1210,6 +1248,32 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
   return block_sum(x, lds4);
 }
 
+// ls_total of N partial rows at once: the same sums in the same order (so
+// the same bits), with the rows' loads issued together.
+template <int N>
+__device__ inline void ls_totals(const double* part, const int (&v)[N], int G, double (&out)[N],
+                                 double (*lds)[kWavesPerBlock]) {
+  double x[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = 0.0;
+  for (int b = threadIdx.x; b < G; b += kBlock) {
+    double y[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) y[k] = part[(int64_t)v[k] * G + b];
+#pragma unroll
+    for (int k = 0; k < N; ++k) x[k] += y[k];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = wave_sum(x[k]);
+  if (lane_id() == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) lds[k][wave_in_block()] = x[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) out[k] = ((lds[k][0] + lds[k][1]) + lds[k][2]) + lds[k][3];
+  __syncthreads();
+}
+
 // Candidates q >= kQGroup (none of the first group passed: rare), in one
 // block: one pass over the listed rows per candidate, in Algorithm 4's
 // order, until the test passes.  Returns the accepted q (or -1) with its
@@ -1266,20 +1330,27 @@ __device__ inline int rows_more_candidates(const RowsArgs& a, int64_t nr, int64_
 template <int LOSS>
 __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
+  __shared__ double lds7[7][kWavesPerBlock];
   const int64_t hi_act = clipped_hi(a.slot_hi, a.p_active);
   if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: nothing ran
+  const double C = *a.Cp;
   const int nq = a.Q < kQGroup ? a.Q : kQGroup;
-  const double Delta = ls_total(a.part, 2 * a.Q, a.G, lds4);
+  // Delta, candidate 0's sums and scales, touched rows and nonzeros with
+  // d_j != 0, in one pass over the partials
+  const int first[7] = {2 * a.Q, 0, a.Q, 2 * a.Q + 3, 3 * a.Q + 3, 2 * a.Q + 1, 2 * a.Q + 2};
+  double tot[7];
+  ls_totals(a.part, first, a.G, tot, lds7);
+  const double Delta = tot[0];
   double Dq = Delta, al = 1.0, dF = 0.0, margin = INFINITY;
   int q_acc = -1;
   for (int q = 0; q < nq; ++q) {
-    const double sL = ls_total(a.part, q, a.G, lds4);
-    const double l1 = ls_total(a.part, a.Q + q, a.G, lds4);
-    const double f = l1 + *a.Cp * sL;
+    const double sL = q == 0 ? tot[1] : ls_total(a.part, q, a.G, lds4);
+    const double l1 = q == 0 ? tot[2] : ls_total(a.part, a.Q + q, a.G, lds4);
+    const double f = l1 + C * sL;
     if (bid == 0) {  // only block 0 records the margin
-      const double sabs = ls_total(a.part, 2 * a.Q + 3 + q, a.G, lds4);
-      const double l1abs = ls_total(a.part, 3 * a.Q + 3 + q, a.G, lds4);
-      margin = fmin(margin, armijo_margin(f, a.sigma * Dq, l1abs + *a.Cp * sabs));
+      const double sabs = q == 0 ? tot[3] : ls_total(a.part, 2 * a.Q + 3 + q, a.G, lds4);
+      const double l1abs = q == 0 ? tot[4] : ls_total(a.part, 3 * a.Q + 3 + q, a.G, lds4);
+      margin = fmin(margin, armijo_margin(f, a.sigma * Dq, l1abs + C * sabs));
     }
     if (f <= a.sigma * Dq) {
       q_acc = q;
@@ -1289,8 +1360,8 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
     Dq *= a.beta;
     al *= a.beta;
   }
-  const double touched = ls_total(a.part, 2 * a.Q + 1, a.G, lds4);
-  const double nz_d = ls_total(a.part, 2 * a.Q + 2, a.G, lds4);
+  const double touched = tot[5];
+  const double nz_d = tot[6];
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   bool alone = false;
@@ -1315,15 +1386,34 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   const int lane = lane_id();
   const int64_t wave = alone ? wave_in_block() : (bid * kBlock + threadIdx.x) / kWave;
   const int64_t nwaves = alone ? kWavesPerBlock : nblk * kWavesPerBlock;
+  // a range lists at most kRangeW rows: kR per lane, their loads issued
+  // together
+  constexpr int kR = kRangeW / kWave;
   for (int64_t r = wave; r < nr; r += nwaves) {
     const int32_t cnt = a.u_cnt[r];
-    for (int32_t i = lane; i < cnt; i += kWave) {
-      const int32_t row = a.u_row[r * kRangeW + i];
-      double s = a.u_dtx[r * kRangeW + i];
-      for (int t = 0; t < q_acc; ++t) s *= a.beta;
-      const double c = a.cache[row];
-      store_retained<LOSS>(&a.cache[row],
-                           LOSS == kLogistic ? c * exp(s) : c - (a.y[row] > 0 ? s : -s),
+    int32_t row[kR];
+    double s[kR], c[kR];
+    int yi[kR];
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      const int32_t i = lane + u * kWave;
+      row[u] = ldz(a.u_row, i < cnt, r * kRangeW + i, -1);
+      s[u] = ldz(a.u_dtx, i < cnt, r * kRangeW + i, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      c[u] = ldz(a.cache, row[u] >= 0, row[u], 0.0);
+      yi[u] = LOSS == kLogistic ? 0 : (int)ldz(a.y, row[u] >= 0, row[u], (int8_t)0);
+    }
+#pragma unroll
+    for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(s[u]), "v"(c[u]), "v"(yi[u]));
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      if (row[u] < 0) continue;
+      double sv = s[u];
+      for (int t = 0; t < q_acc; ++t) sv *= a.beta;
+      store_retained<LOSS>(&a.cache[row[u]],
+                           LOSS == kLogistic ? c[u] * exp(sv) : c[u] - (yi[u] > 0 ? sv : -sv),
                            a.stats);
     }
   }
