@@ -18,6 +18,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcdn_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP: the multicore CPU timing baseline only
+# (its reductions over samples run in another order, so parity uses _SO)
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 LOGISTIC = 0
 L2SVM = 1
@@ -25,12 +28,14 @@ _LOSS = {"lr": LOGISTIC, "logistic": LOGISTIC, "svm": L2SVM, "l2svm": L2SVM}
 PENALTIES = {"l1": 0, "elastic": 1, "l2": 2}
 
 
-def build() -> str:
-    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+def build(omp: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math);
+    omp=True: the multicore timing build (-fopenmp)."""
+    out = _SO_OMP if omp else _SO
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-o", _SO, _SRC, "-lm"]
+           "-fno-fast-math"] + (["-fopenmp"] if omp else []) + ["-o", out, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    return _SO
+    return out
 
 
 class _X(ctypes.Structure):
@@ -62,16 +67,21 @@ class _Info(ctypes.Structure):
                 ("min_stop_margin", ctypes.c_double)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        build()
-    L = ctypes.CDLL(_SO)
+def threads_available(threads: int) -> int:
+    """How many threads the multicore build runs with when asked for `threads`."""
+    return int(lib(omp=True).orc_set_threads(int(threads)))
+
+
+def lib(omp: bool = False):
+    if omp in _libs:
+        return _libs[omp]
+    so = _SO_OMP if omp else _SO
+    if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+        build(omp)
+    L = ctypes.CDLL(so)
     vp, i64, i32, u64, dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                               ctypes.c_uint64, ctypes.c_double)
     L.orc_splitmix64.argtypes = [u64, u64]
@@ -99,7 +109,9 @@ def lib():
     L.orc_step.restype = i32
     L.orc_solve.argtypes = [vp, vp, i64, dbl, u64, i32, vp, vp, vp]
     L.orc_solve.restype = i32
-    _lib = L
+    L.orc_set_threads.argtypes = [i32]
+    L.orc_set_threads.restype = i32
+    _libs[omp] = L
     return L
 
 
@@ -263,15 +275,20 @@ def step(prob: Problem, par: Params, w: np.ndarray, cache: np.ndarray, bundle) -
 
 
 def solve(prob: Problem, par: Params, P: int, eps: float, seed: int = 0,
-          max_outer: int = 1000, w0=None) -> tuple:
-    """Algorithm 3 to the relative subgradient stopping rule; returns (w, info, F_trace)."""
+          max_outer: int = 1000, w0=None, threads: int = 0) -> tuple:
+    """Algorithm 3 to the relative subgradient stopping rule; returns (w, info, F_trace).
+    threads > 0 runs the multicore timing build on that many threads (its
+    sums over samples run in another order: not the parity oracle)."""
     if not (1 <= P <= prob.p):
         raise ValueError("bundle size P must lie in [1, p]")
     w = np.zeros(prob.p) if w0 is None else np.array(w0, dtype=np.float64, copy=True)
     trace = np.zeros(max(max_outer, 1))
     info = _Info()
     pc = par.c()
-    status = lib().orc_solve(prob.ref, ctypes.byref(pc), int(P), float(eps), int(seed),
+    L = lib(omp=threads > 0)
+    if threads > 0:
+        L.orc_set_threads(int(threads))
+    status = L.orc_solve(prob.ref, ctypes.byref(pc), int(P), float(eps), int(seed),
                              int(max_outer), _ptr(w), ctypes.byref(info), _ptr(trace))
     d = {f: getattr(info, f) for f, _ in _Info._fields_}
     d["status"] = int(status)

@@ -23,6 +23,9 @@
  * high-precision recomputation, an independent CDN, published RNG outputs).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -210,6 +213,8 @@ static void lr_tau(double E, int y, double* tau, double* one_minus_tau) {
 /* ------------------------------------------------------------------------ */
 void orc_grad_hess(const orc_X* X, const orc_par* par, const double* cache,
                    const int32_t* feats, int64_t m, double* g, double* h) {
+  /* features are independent (the multicore build splits them over threads) */
+#pragma omp parallel for schedule(dynamic, 256)
   for (int64_t t = 0; t < m; ++t) {
     int64_t j = feats[t];
     double gs = 0.0, hs = 0.0;
@@ -333,6 +338,19 @@ static double loss_change_scale(int32_t loss, double cache, int y, double a, dou
   return pn * pn + po * po + 2.0 * pn * fabs(a);
 }
 
+/* Threads of the multicore build (a timing baseline only: the parity oracle
+ * is the single-threaded build, whose sums run in the order written).
+ * Returns the number the build will use (1 without OpenMP). */
+int32_t orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return (int32_t)omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 double orc_loss_change(int32_t loss, double cache, int32_t y, double a) {
   return loss_change(loss, cache, y, a);
 }
@@ -420,6 +438,7 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
   }
 
   /* 3. Algorithm 4: d^T x_i */
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < X->n; ++i) a[i] = 0.0;
   for (int64_t t = 0; t < P; ++t) {
     int64_t j = bundle[t];
@@ -440,6 +459,8 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
       l1abs += ra * (fabs(wj + s) + fabs(wj)) + fabs(rb * s) * (fabs(wj) + 0.5 * fabs(s));
     }
     double sL = 0.0, sabs = 0.0;
+    /* (the multicore build sums over threads: another summation order) */
+#pragma omp parallel for reduction(+ : sL, sabs) schedule(static)
     for (int64_t i = 0; i < X->n; ++i) {
       const double lc = loss_change(par->loss, cache[i], X->y[i], a[i]);
       sL += lc;
@@ -455,11 +476,13 @@ int32_t orc_step(const orc_X* X, const orc_par* par, double* w, double* cache,
     }
     Dq *= par->beta;
     alpha *= par->beta;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < X->n; ++i) a[i] *= par->beta;
   }
 
   if (q_acc >= 0) {
     for (int64_t t = 0; t < P; ++t) w[bundle[t]] += alpha * d[t];
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < X->n; ++i) {
       if (par->loss == ORC_LOGISTIC)
         cache[i] *= exp(a[i]);
