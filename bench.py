@@ -89,9 +89,9 @@ def parse():
     ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="shrink n and p of the 64 batched problems (1.0: full size)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serving-scale", type=float, default=0.1,
+    ap.add_argument("--serving-scale", type=float, default=1.0,
                     help="shrink the served problems' n and p ranges (1.0: full size)")
-    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-requests", type=int, default=500)
     ap.add_argument("--source-hash", action="store_true",
                     help="print the hash of the kernel sources that traffic records are keyed by")
     return ap.parse_args()

@@ -61,7 +61,7 @@ void dfree(T*& ptr) {
 
 void free_data(pcdn_ctx* c) {
   dfree(c->cp); dfree(c->ri); dfree(c->v); dfree(c->y);
-  dfree(c->w); dfree(c->cache); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
+  dfree(c->w); dfree(c->cache); dfree(c->rw); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
   dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
   dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
@@ -191,6 +191,7 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   a.v = c->v;
   a.y = c->y;
   a.cache = c->cache;
+  a.rw = c->rw;
   a.w = c->w;
   a.g = c->g;
   a.h = c->h;
@@ -253,6 +254,7 @@ RowsArgs rows_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, 
   r.w = c->w;
   r.perm = perm;
   r.cache = c->cache;
+  r.rw = c->rw;
   r.y = c->y;
   r.u_cnt = c->u_cnt;
   r.u_row = c->u_row;
@@ -311,6 +313,7 @@ StopArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
   a.cp = c->cp;
   a.y = c->y;
   a.cache = c->cache;
+  a.rw = c->rw;
   a.w = w;
   a.p = c->p;
   a.nnz = c->nnz;
@@ -407,10 +410,12 @@ int objective(pcdn_ctx* c, const Opts& o, double* F) {
 int cache_from_w(pcdn_ctx* c, bool w_is_zero) {
   if (w_is_zero) {
     HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));  // e^0 = 1, b = 1
+    HIPCHK(c, launch_row_weights(c->loss, c->cache, c->y, c->n, c->rw, c->stream));
     return PCDN_OK;
   }
   HIPCHK(c, launch_margins_rows(c->loss, c->rp, c->rc, c->rv, c->w, c->y, c->n, c->cache,
                                 c->stats, c->stream));
+  HIPCHK(c, launch_row_weights(c->loss, c->cache, c->y, c->n, c->rw, c->stream));
   return range_check(c, "w puts e^{w^T x_i} outside the normal doubles (|w^T x_i| > ~708)");
 }
 
@@ -510,6 +515,7 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   NarrowArgs na{};
   na.sw = sweep_args(c, o);
   na.cache = c->cache;
+  na.rw = c->rw;
   na.w = c->w;
   na.perm = perm;
   na.poff = c->poff;
@@ -741,7 +747,10 @@ template <class F>
 int capture(pcdn_ctx* c, hipGraphExec_t* out, F enqueue) {
   *out = nullptr;
   hipGraph_t g = nullptr;
-  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  // relaxed: the capture neither restricts nor is restricted by what other
+  // host threads do meanwhile (a server uploads requests on a thread of its
+  // own while its caller's thread captures a new request's graphs)
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
   int rc = enqueue();
   hipError_t e = hipStreamEndCapture(c->stream, &g);
   if (rc) {
@@ -912,6 +921,7 @@ int solve_begin(SolveRun& r) {
   if (rc) return rc;
   // reference norm at w = 0 (retained quantities all one)
   HIPCHK(c, launch_fill(c->cache, 1.0, c->n, c->stream));
+  HIPCHK(c, launch_row_weights(c->loss, c->cache, c->y, c->n, c->rw, c->stream));
   r.G0 = r.G = 0.0;
   rc = stopping_norm(c, r.o, nullptr, &r.G0);
   if (rc) return rc;
@@ -1088,7 +1098,7 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
   const int64_t br_m = br_hist_ints(nnz);
   const int64_t sizes[] = {
       8 * (p + 1), 4 * nnz, 4 * nnz, n,                    // X, y
-      8 * p, 8 * n, 8 * n, 8 * n, 8 * p,                   // w, cache, d^T x, scratch
+      8 * p, 8 * n, 16 * n, 8 * n, 8 * n, 8 * p,           // w, cache, row weights, d^T x, scratch
       8 * p, 8 * p, 8 * p, 8 * p,                          // g, h, d, Delta terms
       4 * p, 4 * p, 4 * p, 4 * p, 4 * hist_m,              // sort keys and payloads, histogram
       4 * (std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1),
@@ -1187,6 +1197,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->y, n);
   ALLOC(c, c->w, p);
   ALLOC(c, c->cache, n);
+  ALLOC(c, c->rw, n);
   ALLOC(c, c->dtx, n);
   ALLOC(c, c->tmp_n, n);
   ALLOC(c, c->tmp_p, p);

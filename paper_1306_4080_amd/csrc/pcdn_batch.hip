@@ -6,13 +6,16 @@
 // interleaving across problems differs.
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pcdn_host.h"
@@ -540,6 +543,8 @@ struct ServerReq {
   bool has_opts = false;
   int64_t footprint = 0;
   pcdn_ctx* ctx = nullptr;
+  int load_rc = PCDN_OK;  // the loader's outcome (pcdn_create + pcdn_load_csc)
+  std::string msg;        // its error message
   EngineJob job;
   ~ServerReq() {
     if (ctx) pcdn_destroy(ctx);
@@ -555,17 +560,38 @@ struct ServerResult {
 
 }  // namespace
 
+// Requests pass through three queues: waiting (submitted), then loading and
+// loaded on the loader thread, which uploads one request at a time in
+// submission order once its state fits the budget (the budget is reserved
+// when the upload starts), and running once step() has set the solve up in
+// the engine.  Uploads (host checks, copies, the CSR copy's sort) thus overlap
+// with the engine's rounds, which run on the caller's thread.
 struct pcdn_server {
   int device = 0;
-  int64_t budget = 0, used = 0;
+  int64_t budget = 0, used = 0;  // used: reserved by uploads and admitted solves
   int64_t next_id = 1;
   std::string err;
+  mutable std::mutex mu;         // guards waiting, loaded, loading, used and stop
+  std::condition_variable cv;
+  bool stop = false;
+  std::thread loader;
   // declared before the engine so that the engine (which refers to the
   // admitted jobs) is destroyed first
   std::deque<std::unique_ptr<ServerReq>> waiting;
+  std::deque<std::unique_ptr<ServerReq>> loaded;
+  int32_t loading = 0;           // uploads in progress (0 or 1)
+  int64_t loading_id = 0;        // the request being uploaded
   std::map<int64_t, std::unique_ptr<ServerReq>> running;
   std::map<int64_t, ServerResult> finished;
   Engine eng;
+  ~pcdn_server() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (loader.joinable()) loader.join();
+  }
 };
 
 namespace {
@@ -583,23 +609,66 @@ void server_finish(pcdn_server* s, std::unique_ptr<ServerReq> q, int status, boo
     res.w.assign((size_t)q->r.p, 0.0);
     res.status = solve_end(q->job.run, res.w.data(), &res.info);
   }
-  if (res.status < 0) res.msg = q->ctx ? pcdn_last_error(q->ctx) : pcdn_last_error(nullptr);
-  s->used -= q->footprint;
-  s->finished[q->id] = std::move(res);
-  // q (and its context) are released here
+  if (res.status < 0) res.msg = !q->msg.empty() ? q->msg : q->ctx ? pcdn_last_error(q->ctx) : "";
+  const int64_t fp = q->footprint, id = q->id;
+  q.reset();  // the request's context (device memory) is released here
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->used -= fp;
+  }
+  s->cv.notify_all();  // the loader may now fit the next request
+  s->finished[id] = std::move(res);
 }
 
-// Upload and set up one request; on success it joins the engine (or has
+// The loader thread: uploads the next waiting request once it fits.
+void server_loader(pcdn_server* s) {
+  // this thread's runtime calls must not be refused because the caller's
+  // thread is capturing a graph meanwhile
+  hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+  (void)hipThreadExchangeStreamCaptureMode(&mode);
+  for (;;) {
+    std::unique_ptr<ServerReq> q;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [s] {
+        return s->stop ||
+               (!s->waiting.empty() && s->used + s->waiting.front()->footprint <= s->budget);
+      });
+      if (s->stop) return;
+      q = std::move(s->waiting.front());
+      s->waiting.pop_front();
+      s->used += q->footprint;
+      ++s->loading;
+      s->loading_id = q->id;
+    }
+    int rc = pcdn_create(&q->ctx, s->device, nullptr);
+    if (rc) {
+      q->msg = pcdn_last_error(nullptr);
+    } else {
+      const pcdn_request& r = q->r;
+      rc = pcdn_load_csc(q->ctx, r.n, r.p, r.nnz, r.col_ptr, r.row_idx, r.val, r.y, 0);
+      if (rc) q->msg = pcdn_last_error(q->ctx);
+    }
+    q->load_rc = rc;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->loaded.push_back(std::move(q));
+      --s->loading;
+      s->loading_id = 0;
+    }
+    s->cv.notify_all();
+  }
+}
+
+// Set up an uploaded request's solve; on success it joins the engine (or has
 // already stopped, e.g. w = 0 optimal).
 int server_admit(pcdn_server* s, ServerReq* q) {
-  int rc = pcdn_create(&q->ctx, s->device, nullptr);
-  if (rc) return rc;
+  if (q->load_rc) return q->load_rc;
   const pcdn_request& r = q->r;
-  rc = pcdn_load_csc(q->ctx, r.n, r.p, r.nnz, r.col_ptr, r.row_idx, r.val, r.y, 0);
-  if (rc) return rc;
   SolveRun& run = q->job.run;
   const int64_t P = r.P == 0 ? std::max<int64_t>(1, std::llround(0.05 * (double)r.p)) : r.P;
-  rc = check_solve_args(q->ctx, r.C, P, r.eps, r.loss, q->has_opts ? &q->opts : nullptr, &run.o);
+  int rc = check_solve_args(q->ctx, r.C, P, r.eps, r.loss, q->has_opts ? &q->opts : nullptr,
+                            &run.o);
   if (rc) return rc;
   run.c = q->ctx;
   run.C = r.C;
@@ -626,6 +695,12 @@ extern "C" int pcdn_server_create(pcdn_server** out, int device, int64_t hbm_bud
   if (s->eng.init(device) != PCDN_OK) {
     delete s;
     return PCDN_E_DEVICE;
+  }
+  try {
+    s->loader = std::thread(server_loader, s);
+  } catch (...) {
+    delete s;
+    return PCDN_E_OOM;
   }
   *out = s;
   return PCDN_OK;
@@ -655,7 +730,11 @@ extern "C" int pcdn_server_submit(pcdn_server* s, const pcdn_request* r, int64_t
     return server_fail(s, PCDN_E_OOM, "the request's device state exceeds the server's budget");
   q->id = s->next_id++;
   *id = q->id;
-  s->waiting.push_back(std::move(q));
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->waiting.push_back(std::move(q));
+  }
+  s->cv.notify_all();
   return PCDN_OK;
 }
 
@@ -663,11 +742,21 @@ extern "C" int pcdn_server_step(pcdn_server* s, int32_t* finished) {
   if (!s) return PCDN_E_ARG;
   int32_t nfin = 0;
   if (finished) *finished = 0;
-  // admission, first in first out, while the state fits
-  while (!s->waiting.empty() && s->used + s->waiting.front()->footprint <= s->budget) {
-    std::unique_ptr<ServerReq> q = std::move(s->waiting.front());
-    s->waiting.pop_front();
-    s->used += q->footprint;
+  // admission of the uploaded requests, in submission order; with nothing
+  // running, wait for the next upload instead of returning idle
+  std::deque<std::unique_ptr<ServerReq>> ready;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->eng.size() == 0 && s->loaded.empty() && (s->loading > 0 || !s->waiting.empty()))
+      s->cv.wait(lk, [s] { return !s->loaded.empty() || (s->loading == 0 && s->waiting.empty()); });
+    ready.swap(s->loaded);
+  }
+  std::sort(ready.begin(), ready.end(),
+            [](const std::unique_ptr<ServerReq>& x, const std::unique_ptr<ServerReq>& y) {
+              return x->id < y->id;
+            });
+  for (auto& qr : ready) {
+    std::unique_ptr<ServerReq> q = std::move(qr);
     const int rc = server_admit(s, q.get());
     if (rc != PCDN_OK) {
       server_finish(s, std::move(q), rc, false);
@@ -702,7 +791,8 @@ extern "C" int pcdn_server_step(pcdn_server* s, int32_t* finished) {
 extern "C" int pcdn_server_status(const pcdn_server* s, int32_t* waiting, int32_t* running,
                                   int64_t* bytes_in_use) {
   if (!s) return PCDN_E_ARG;
-  if (waiting) *waiting = (int32_t)s->waiting.size();
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (waiting) *waiting = (int32_t)(s->waiting.size() + s->loaded.size()) + s->loading;
   if (running) *running = (int32_t)s->running.size();
   if (bytes_in_use) *bytes_in_use = s->used;
   return PCDN_OK;
@@ -714,8 +804,12 @@ extern "C" int pcdn_server_take(pcdn_server* s, int64_t id, double* w_out, pcdn_
   auto it = s->finished.find(id);
   if (it == s->finished.end()) {
     if (s->running.count(id)) return server_fail(s, PCDN_E_STATE, "request still running");
+    std::lock_guard<std::mutex> lk(s->mu);
     for (const auto& q : s->waiting)
       if (q->id == id) return server_fail(s, PCDN_E_STATE, "request still waiting");
+    for (const auto& q : s->loaded)
+      if (q->id == id) return server_fail(s, PCDN_E_STATE, "request still waiting");
+    if (id == s->loading_id) return server_fail(s, PCDN_E_STATE, "request still waiting");
     return server_fail(s, PCDN_E_ARG, "unknown request id");
   }
   const ServerResult& res = it->second;

@@ -93,6 +93,7 @@ struct SweepArgs {
   const float* v;
   const int8_t* y;
   const double* cache;
+  const double2* rw;          // per-row term weights (row_weights of cache and y)
   const double* w;
   const Chunk* chunks;        // chunk descriptors of the order
   const int32_t* cstart;      // slot -> first chunk, p+1 entries
@@ -132,6 +133,7 @@ struct StopArgs {
   const int64_t* cp;
   const int8_t* y;
   const double* cache;
+  const double2* rw;         // per-row term weights (row_weights of cache and y)
   const double* w;           // nullable: treated as zero
   int64_t p, nnz;
   double* sg;                // |grad^S_j F|
@@ -163,6 +165,7 @@ struct RowsArgs {
   double* w;
   const int32_t* perm;       // slot -> feature
   double* cache;
+  double2* rw;               // per-row term weights, kept with cache
   const int8_t* y;
   int32_t* u_cnt;
   int32_t* u_row;
@@ -338,6 +341,7 @@ constexpr int kNarrowMaxP = 1024;
 struct NarrowArgs {
   SweepArgs sw;        // ri/v unused; cache, y, g, h, d, dtx, C, gamma, nu used
   double* cache;       // the same arrays as sw.cache / sw.w, writable
+  double2* rw;         // per-row term weights, kept with cache
   double* w;
   const int32_t* perm;
   const int64_t* poff; // p+1 partition-order offsets
@@ -488,6 +492,10 @@ hipError_t launch_reg_terms(const double* w, int64_t p, double ra, double rb, do
                             hipStream_t s);
 // Retained quantities from w (e^{x_i^T w}, or 1 - y_i x_i^T w) with X in CSR
 // order (rp int64[n+1], col, v); deterministic.
+// Per-row weights of the gradient and Hessian-diagonal terms from the
+// retained quantities and labels (after they are set in bulk).
+hipError_t launch_row_weights(int loss, const double* cache, const int8_t* y, int64_t n,
+                              double2* rw, hipStream_t s);
 hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, const float* v,
                                const double* w, const int8_t* y, int64_t n, double* cache,
                                Stats* stats, hipStream_t s);

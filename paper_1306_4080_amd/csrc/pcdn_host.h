@@ -64,6 +64,7 @@ struct pcdn_ctx {
   bool has_state = false;
   double* w = nullptr;
   double* cache = nullptr;
+  double2* rw = nullptr;         // per-row term weights, kept with cache
   double* dtx = nullptr;  // single-workgroup kernel's fixed-point d^T x (bundles of many rows)
   double* tmp_n = nullptr;
   double* tmp_p = nullptr;

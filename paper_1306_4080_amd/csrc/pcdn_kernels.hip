@@ -170,6 +170,42 @@ __device__ inline void grad_hess_term(double c, int yi, double x, double& gs, do
   }
 }
 
+// The weights of a row's gradient and Hessian-diagonal terms, a function of
+// its retained quantity c and label: x.x multiplies x_ij in g_j, x.y
+// multiplies x_ij^2 in h_j (logistic: -(1 - tau) or its mirror and
+// tau (1 - tau); SVM: y_i b_i and 1 on the active set, zeros off it).  They
+// are kept beside the retained quantities (row_weights is applied wherever
+// those change), so the sweeps gather one 16-byte value per nonzero instead
+// of the retained quantity and the label; the terms are the same products
+// as grad_hess_term's.
+template <int LOSS>
+__device__ inline double2 row_weights(double c, int yi) {
+  if (LOSS == kLogistic) {
+    double s0, s1;
+    logistic_weights(c, s0, s1);
+    return make_double2(yi > 0 ? -s0 : s1, s0 * s1);
+  }
+  return c > 0.0 ? make_double2(yi > 0 ? c : -c, 1.0) : make_double2(0.0, 0.0);
+}
+
+template <int LOSS>
+__device__ inline void weighted_terms(double2 rw, double x, double& gs, double& hs) {
+  if (LOSS == kLogistic) {
+    gs += rw.x * x;
+    hs += rw.y * (x * x);
+  } else if (rw.y > 0.0) {
+    gs += rw.x * x;
+    hs += x * x;
+  }
+}
+
+// Gradient term alone (the stopping sweep).
+template <int LOSS>
+__device__ inline double weighted_grad(double2 rw, double x) {
+  if (LOSS == kLogistic) return rw.x * x;
+  return rw.y > 0.0 ? rw.x * x : 0.0;
+}
+
 // Loss change of sample i when its margin w^T x_i grows by a (eq. (10)'s
 // summand).  Logistic: log(1+e^{-y(z+a)}) - log(1+e^{-yz}); with m = -y a and
 // tau = tau(y z) it is log(tau + (1 - tau) e^m), written for t = -|m| <= 0 as
@@ -247,9 +283,16 @@ __device__ inline bool in_range(double c) {
 }
 
 template <int LOSS>
-__device__ inline void store_retained(double* p, double c, Stats* stats) {
-  *p = c;
+__device__ inline void count_range(double c, Stats* stats) {
   if (!in_range<LOSS>(c)) atomicAdd(&stats->range_leaves, 1ull);
+}
+
+// A retained quantity and its row's weights, with the range check.
+template <int LOSS>
+__device__ inline void store_retained(double* p, double2* rwp, double c, int yi, Stats* stats) {
+  *p = c;
+  *rwp = row_weights<LOSS>(c, yi);
+  count_range<LOSS>(c, stats);
 }
 
 // Minimiser of g d + h d^2/2 + R(w + d) with R(u) = ra |u| + (rb/2) u^2
@@ -608,18 +651,14 @@ __device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi,
       row[u] = ldz(a.ri, ok, kk, -1);
       xv[u] = ldz(a.v, ok, kk, 0.0f);
     }
-    double cv[kUnroll];
-    int yv[kUnroll];
+    double2 rv[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      cv[u] = ldz(a.cache, row[u] >= 0, row[u], 0.0);
-      yv[u] = (int)ldz(a.y, row[u] >= 0, row[u], (int8_t)0);
-    }
+    for (int u = 0; u < kUnroll; ++u) rv[u] = ldz(a.rw, row[u] >= 0, row[u], make_double2(0.0, 0.0));
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) asm volatile("" ::"v"(xv[u]), "v"(yv[u]), "v"(cv[u]));
+    for (int u = 0; u < kUnroll; ++u) asm volatile("" ::"v"(xv[u]), "v"(rv[u].x), "v"(rv[u].y));
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-      if (row[u] >= 0) grad_hess_term<LOSS>(cv[u], yv[u], (double)xv[u], gs, hs);
+      if (row[u] >= 0) weighted_terms<LOSS>(rv[u], (double)xv[u], gs, hs);
   }
 }
 
@@ -699,15 +738,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
         xv[g][u] = ldz(a.v, ok, ch[g].klo + lane + u * kWave, 0.0f);
       }
     }
-    double cv[kSweepGroup][2];
-    int yv[kSweepGroup][2];
+    double2 rv[kSweepGroup][2];
 #pragma unroll
     for (int g = 0; g < kSweepGroup; ++g)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        cv[g][u] = ldz(a.cache, row[g][u] >= 0, row[g][u], 0.0);
-        yv[g][u] = (int)ldz(a.y, row[g][u] >= 0, row[g][u], (int8_t)0);
-      }
+      for (int u = 0; u < 2; ++u)
+        rv[g][u] = ldz(a.rw, row[g][u] >= 0, row[g][u], make_double2(0.0, 0.0));
     // every operand of the terms loaded here, before the first use: the
     // compiler would otherwise sink the value and label loads into the
     // per-nonzero branches of the loss (the SVM's active-set test) and wait
@@ -715,7 +751,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
 #pragma unroll
     for (int g = 0; g < kSweepGroup; ++g)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) asm volatile("" ::"v"(xv[g][u]), "v"(yv[g][u]), "v"(cv[g][u]));
+      for (int u = 0; u < 2; ++u) asm volatile("" ::"v"(xv[g][u]), "v"(rv[g][u].x), "v"(rv[g][u].y));
     double gs[kSweepGroup], hs[kSweepGroup];
 #pragma unroll
     for (int g = 0; g < kSweepGroup; ++g) {
@@ -723,7 +759,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int6
       hs[g] = 0.0;
 #pragma unroll
       for (int u = 0; u < 2; ++u)
-        if (row[g][u] >= 0) grad_hess_term<LOSS>(cv[g][u], yv[g][u], (double)xv[g][u], gs[g], hs[g]);
+        if (row[g][u] >= 0) weighted_terms<LOSS>(rv[g][u], (double)xv[g][u], gs[g], hs[g]);
       if (ch[g].len > 2 * kWave)
         sweep_range<LOSS>(a, ch[g].klo + 2 * kWave, ch[g].klo + ch[g].len, lane, gs[g], hs[g]);
     }
@@ -780,17 +816,6 @@ __global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
 // ---------------------------------------------------------------------------
 // stopping sweep over X in column order (see StopArgs)
 // ---------------------------------------------------------------------------
-// Gradient contribution of one nonzero (grad_hess_term without h).
-template <int LOSS>
-__device__ inline double grad_term(double c, int yi, double x) {
-  if (LOSS == kLogistic) {
-    double s0, s1;
-    logistic_weights(c, s0, s1);
-    return (yi > 0 ? -s0 : s1) * x;
-  }
-  return c > 0.0 ? (yi > 0 ? c : -c) * x : 0.0;  // y_i b_i x_ij on the active set
-}
-
 template <int LOSS>
 __device__ inline void stop_finish_one(const StopArgs& a, int64_t j, double gs, double C,
                                        double thr, double wj) {
@@ -808,23 +833,31 @@ __device__ inline StopScalars stop_scalars(const StopArgs& a) {
   return {*a.Cp, a.act ? *a.thr : 0.0};
 }
 
-// Wavefront w of the launch takes ranges w, w + nwaves, ...; the loads of a
-// range's four rounds are issued together.
+// Wavefront w of the launch takes ranges w, w + nwaves, ...; lane L holds
+// the range's nonzeros 4L .. 4L+3.  A lane first sums its own nonzeros per
+// column in order (columns that start and end inside the lane are finished
+// there); one segmented wavefront scan over the lanes' last runs (keys =
+// column) then carries the runs across lanes, and each column is finished by
+// the lane where it ends, in the same left-to-right order of its nonzeros.
 template <int LOSS>
 __device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid, int64_t nblk) {
-  constexpr int kR = kStopW / kWave;
+  constexpr int kE = kStopW / kWave;  // consecutive nonzeros per lane
   const int lane = lane_id();
   const int64_t nr = (a.nnz + kStopW - 1) / kStopW;
   const int64_t nwaves = nblk * kWavesPerBlock;
   const StopScalars sc = stop_scalars(a);
+  // w of a nonzero's column (w = 0 when a.w is null: a load of the always
+  // valid cache[0], discarded)
+  const double* wsrc = a.w ? a.w : a.cache;
   for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
     const int64_t rb = m * kStopW;
     const int64_t re = rb + kStopW < a.nnz ? rb + kStopW : a.nnz;
-    int32_t col[kR], row[kR];
-    float xv[kR];
+    const int64_t k0 = rb + (int64_t)lane * kE;
+    int32_t col[kE], row[kE];
+    float xv[kE];
 #pragma unroll
-    for (int u = 0; u < kR; ++u) {
-      const int64_t k = rb + u * kWave + lane;
+    for (int u = 0; u < kE; ++u) {
+      const int64_t k = k0 + u;
       const bool in = k < re;
       col[u] = ldz(a.ccol, in, k, -1);
       row[u] = ldz(a.ri, in, k, 0);
@@ -833,58 +866,73 @@ __device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid,
     // columns open at the range's ends
     const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
     const int32_t right = re < a.nnz ? a.ccol[re] : -1;
-    double cv[kR], wv[kR];
-    int yv[kR];
-    // w of the lane's column, for the columns that end in this range (w = 0
-    // when a.w is null: a load of the always valid cache[0], discarded)
-    const double* wsrc = a.w ? a.w : a.cache;
+    double2 rv[kE];
+    double wv[kE];
 #pragma unroll
-    for (int u = 0; u < kR; ++u) {
-      cv[u] = ldz(a.cache, col[u] >= 0, row[u], 0.0);
-      yv[u] = (int)ldz(a.y, col[u] >= 0, row[u], (int8_t)0);
+    for (int u = 0; u < kE; ++u) {
+      rv[u] = ldz(a.rw, col[u] >= 0, row[u], make_double2(0.0, 0.0));
       wv[u] = ldz(wsrc, col[u] >= 0 && a.w != nullptr, col[u], 0.0);
     }
-    // keep the w loads here, issued with the others (the compiler would
-    // otherwise sink each into the branch that finishes a column, and wait
-    // for it there once per round)
+    // every operand loaded before the first use (the compiler would sink
+    // loads into the finishing branches and wait for each there)
 #pragma unroll
-    for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(wv[u]));
-    int32_t ccar = -1;  // column carried into the next round
-    double gcar = 0.0;
-    double pf = 0.0, pl = 0.0;
+    for (int u = 0; u < kE; ++u)
+      asm volatile("" ::"v"(rv[u].x), "v"(rv[u].y), "v"(wv[u]), "v"(xv[u]));
+    // the lane's runs: head (from its first nonzero), complete middles, tail
+    const int32_t hk = col[0];
+    const double hw = wv[0];
+    int32_t rk = col[0];
+    double run = col[0] >= 0 ? weighted_grad<LOSS>(rv[0], (double)xv[0]) : 0.0;
+    double wk = wv[0], hs = 0.0;
+    bool whole = true;  // one run covers the lane's nonzeros
 #pragma unroll
-    for (int u = 0; u < kR; ++u) {
-      if (rb + u * kWave >= re) break;
-      double gs = col[u] >= 0 ? grad_term<LOSS>(cv[u], yv[u], (double)xv[u]) : 0.0;
-      seg_scan1(gs, col[u]);
-      if (ccar >= 0 && col[u] == ccar) gs += gcar;
-      // column of the next nonzero of the range (-1: none): the next lane's,
-      // for lane 63 the next round's first
-      const int32_t next0 = u + 1 < kR ? __builtin_amdgcn_readlane(col[u + 1], 0) : -1;
-      int32_t nxt = next_lane_key(col[u]);
-      if (lane == kWave - 1) nxt = next0;
-      const int64_t k = rb + u * kWave + lane;
-      const bool seg_end = col[u] >= 0 && nxt != col[u];
-      // the segment at lane 63 that goes on into the next round
-      const int32_t c63 = __builtin_amdgcn_readlane(col[u], kWave - 1);
-      const bool open63 = c63 >= 0 && next0 == c63;
-      const unsigned long long gb = (unsigned long long)__double_as_longlong(gs);
-      const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(gb & 0xffffffffull), kWave - 1);
-      const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(gb >> 32), kWave - 1);
-      ccar = open63 ? c63 : -1;
-      gcar = open63 ? __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo)) : 0.0;
-      if (seg_end) {
-        const bool lopen = col[u] == left;
-        const bool ropen = col[u] == right && k + 1 == re;
-        if (lopen)
-          pf = gs;  // (also when right-open: a column through the whole range)
-        else if (ropen)
-          pl = gs;
-        else
-          stop_finish_one<LOSS>(a, col[u], gs, sc.C, sc.thr, wv[u]);
+    for (int u = 1; u < kE; ++u) {
+      const double t = col[u] >= 0 ? weighted_grad<LOSS>(rv[u], (double)xv[u]) : 0.0;
+      if (col[u] == rk) {
+        run += t;
+      } else {
+        if (whole) {
+          hs = run;  // the head run ends inside the lane
+          whole = false;
+        } else if (rk >= 0) {
+          stop_finish_one<LOSS>(a, rk, run, sc.C, sc.thr, wk);  // starts and ends here
+        }
+        rk = col[u];
+        run = t;
+        wk = wv[u];
       }
     }
-    // the partials (held by the lanes that ended the open segments)
+    if (whole) hs = run;
+    // tail runs carried over the lanes of equal column
+    const int32_t tk = rk;
+    double S = run;
+    seg_scan1(S, tk);
+    const int32_t pk = __builtin_amdgcn_update_dpp(-1, tk, 0x138, 0xf, 0xf, false);  // lane - 1
+    const double pS = dpp_f64<0x138, 0xf, 0xf>(S);
+    const int32_t nk = next_lane_key(hk);  // the next lane's first column
+    const int last_lane = (int)((re - 1 - rb) / kE);
+    double pf = 0.0, pl = 0.0;
+    if (!whole && hk >= 0) {
+      // the head run ends in this lane: add what the previous lanes carried
+      const double H = hs + (lane > 0 && pk == hk ? pS : 0.0);
+      if (hk == left)
+        pf = H;
+      else
+        stop_finish_one<LOSS>(a, hk, H, sc.C, sc.thr, hw);
+    }
+    if (tk >= 0 && lane <= last_lane) {
+      const bool at_end = lane == last_lane;
+      const bool cont = at_end ? right == tk : nk == tk;
+      if (at_end || !cont) {
+        if (tk == left)
+          pf = S;  // (also when right-open: a column through the whole range)
+        else if (cont)
+          pl = S;
+        else
+          stop_finish_one<LOSS>(a, tk, S, sc.C, sc.thr, wk);
+      }
+    }
+    // the partials (held by the lanes that ended the open runs)
     const uint64_t mf = __ballot(pf != 0.0), ml = __ballot(pl != 0.0);
     double2 pr = make_double2(0.0, 0.0);
     if (mf) {
@@ -1403,7 +1451,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
 #pragma unroll
     for (int u = 0; u < kR; ++u) {
       c[u] = ldz(a.cache, row[u] >= 0, row[u], 0.0);
-      yi[u] = LOSS == kLogistic ? 0 : (int)ldz(a.y, row[u] >= 0, row[u], (int8_t)0);
+      yi[u] = (int)ldz(a.y, row[u] >= 0, row[u], (int8_t)0);
     }
 #pragma unroll
     for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(s[u]), "v"(c[u]), "v"(yi[u]));
@@ -1412,9 +1460,9 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
       if (row[u] < 0) continue;
       double sv = s[u];
       for (int t = 0; t < q_acc; ++t) sv *= a.beta;
-      store_retained<LOSS>(&a.cache[row[u]],
+      store_retained<LOSS>(&a.cache[row[u]], &a.rw[row[u]],
                            LOSS == kLogistic ? c[u] * exp(sv) : c[u] - (yi[u] > 0 ? sv : -sv),
-                           a.stats);
+                           yi[u], a.stats);
     }
   }
   const int64_t tid = alone ? threadIdx.x : bid * kBlock + threadIdx.x;
@@ -2144,10 +2192,10 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           double sv = fx_value(ac, isc);
           for (int u = 0; u < q_acc; ++u) sv *= na.beta;
           const int32_t i = L.t_row[e];
-          store_retained<LOSS>(&na.cache[i],
+          store_retained<LOSS>(&na.cache[i], &na.rw[i],
                                LOSS == kLogistic ? L.t_c[e] * exp(sv)
                                                  : L.t_c[e] - (L.t_y[e] > 0 ? sv : -sv),
-                               na.stats);
+                               (int)L.t_y[e], na.stats);
         }
       }
     } else {
@@ -2166,7 +2214,7 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           const int64_t i = i0 + (int64_t)u * kNarrowBlock;
           const bool upd = q_acc >= 0 && fa[u] != 0ull;
           fc[u] = upd ? na.cache[i] : 0.0;
-          fy[u] = (upd && LOSS != kLogistic) ? (int)a.y[i] : 0;
+          fy[u] = upd ? (int)a.y[i] : 0;
         }
 #pragma unroll
         for (int u = 0; u < kNarrowRegRounds; ++u) {
@@ -2175,10 +2223,10 @@ __device__ __forceinline__ void narrow_body(const NarrowArgs& na, NarrowLds& L) 
           if (q_acc >= 0) {
             double sv = fx_value(fa[u], isc);
             for (int k = 0; k < q_acc; ++k) sv *= na.beta;
-            store_retained<LOSS>(&na.cache[i],
+            store_retained<LOSS>(&na.cache[i], &na.rw[i],
                                  LOSS == kLogistic ? fc[u] * exp(sv)
                                                    : fc[u] - (fy[u] > 0 ? sv : -sv),
-                                 na.stats);
+                                 fy[u], na.stats);
           }
           __hip_atomic_store(&gacc[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -2462,6 +2510,13 @@ __global__ void k_reg_terms(const double* w, int64_t p, double ra, double rb, do
   if (j < p) out[j] = ra * fabs(w[j]) + 0.5 * rb * w[j] * w[j];
 }
 
+// Every row's term weights from its retained quantity and label.
+template <int LOSS>
+__global__ void k_row_weights(const double* cache, const int8_t* y, int64_t n, double2* rw) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) rw[i] = row_weights<LOSS>(cache[i], (int)y[i]);
+}
+
 // Retained quantities from w, one wavefront per row over X in CSR order: the
 // margin z_i = sum_j x_ij w_j is summed lane-strided, then by the fixed-order
 // wavefront sum, so it does not depend on scheduling; then e^{z_i} (logistic)
@@ -2478,9 +2533,11 @@ __global__ __launch_bounds__(kBlock) void k_margins_rows(const int64_t* rp, cons
     double z = 0.0;
     for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += kWave) z += (double)v[k] * w[col[k]];
     z = wave_sum(z);
-    if (lane == 0)
-      store_retained<LOSS>(&cache[i], LOSS == kLogistic ? exp(z) : 1.0 - (y[i] > 0 ? z : -z),
-                           stats);
+    if (lane == 0) {
+      const double c = LOSS == kLogistic ? exp(z) : 1.0 - (y[i] > 0 ? z : -z);
+      cache[i] = c;
+      count_range<LOSS>(c, stats);
+    }
   }
 }
 
@@ -3046,6 +3103,16 @@ hipError_t launch_margins_rows(int loss, const int64_t* rp, const int32_t* col, 
   else
     hipLaunchKernelGGL(k_margins_rows<kL2Svm>, g, dim3(kBlock), 0, s, rp, col, v, w, y, n,
                        cache, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_weights(int loss, const double* cache, const int8_t* y, int64_t n,
+                              double2* rw, hipStream_t s) {
+  const dim3 g(grid_for(n, kBlock, 1 << 30));
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_row_weights<kLogistic>, g, dim3(kBlock), 0, s, cache, y, n, rw);
+  else
+    hipLaunchKernelGGL(k_row_weights<kL2Svm>, g, dim3(kBlock), 0, s, cache, y, n, rw);
   return hipGetLastError();
 }
 

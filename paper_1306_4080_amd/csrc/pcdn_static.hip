@@ -186,6 +186,7 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->stop_part = k.take<double>(4 * kSumGrid);
   t->heavy = k.take<int32_t>(kHeavyCap + 1);
   t->cache = k.take<double>(n);
+  t->rw = k.take<double2>(n);
   t->dtx = k.take<double>(n);
   t->tmp_n = k.take<double>(n);
   t->tmp_p = k.take<double>(p);
