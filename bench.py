@@ -59,11 +59,12 @@ if ROOT not in sys.path:
 METRIC = "bundle-sweep nnz/s (HBM GB/s %peak); batched solves/s + p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
 KERNEL_CLASSES = ("sweep", "split_columns", "dtx_linesearch", "apply", "stopping_sweep", "narrow")
-KERNEL_NAMES = ("k_sweep (gradient/Hessian sweep and direction, one wavefront per column chunk)",
-                "k_split (finish of columns cut into several chunks)",
+KERNEL_NAMES = ("k_sweep_ranges (gradient/Hessian sweep and direction over the bundle's "
+                "nonzeros in partition order, 256 per wavefront)",
+                "k_sweep_finish (slots crossing a range boundary, and empty slots)",
                 "k_rows_dtx (d^T x by row and the first line-search candidates)",
                 "k_rows_apply (Armijo decision, w and retained-quantity update)",
-                "k_sweep+k_split stopping mode (full-gradient subgradient norm)",
+                "k_stop_ranges+k_stop_finish (full-gradient subgradient norm)",
                 "k_narrow (one workgroup runs every bundle of an outer iteration)")
 C3 = dict(C=1.0, P=16384, eps=1e-3, loss="svm")
 SETTINGS = [(0.5, 64), (0.5, 1024), (0.5, 8192), (4.0, 64), (4.0, 1024), (4.0, 8192)]

@@ -555,6 +555,10 @@ class Server:
         m = load_library().pcdn_server_last_error(self.h)
         raise PcdnError(rc, m.decode() if m else "")
 
+    def last_error(self) -> str:
+        m = load_library().pcdn_server_last_error(self.h)
+        return m.decode() if m else ""
+
     def submit(self, d, C, P, eps, loss, **opts) -> int:
         col_ptr = np.ascontiguousarray(d.col_ptr, dtype=np.int64)
         row_idx = np.ascontiguousarray(d.row_idx, dtype=np.int32)

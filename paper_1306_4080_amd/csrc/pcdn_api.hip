@@ -70,7 +70,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->bt_row); dfree(c->bt_slot); dfree(c->bt_val); dfree(c->br_hist);
   dfree(c->u_cnt); dfree(c->u_row); dfree(c->u_dtx);
   dfree(c->part); dfree(c->ls_part);
-  dfree(c->pri); dfree(c->pv); dfree(c->poff); dfree(c->off32); dfree(c->plid); dfree(c->pR);
+  dfree(c->pri); dfree(c->pv); dfree(c->pslot); dfree(c->poff); dfree(c->off32); dfree(c->plid); dfree(c->pR);
   dfree(c->pw);
   dfree(c->rp); dfree(c->rc); dfree(c->rv);
   dfree(c->act);
@@ -218,21 +218,32 @@ SweepArgs bundle_sweep_args(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, 
   SweepArgs a = sweep_args(c, o);
   a.chunks = c->chunks;
   a.cstart = c->cstart;
+  a.poff = c->poff;
+  a.pri = c->pri;
+  a.pv = c->pv;
+  a.pslot = c->pslot;
+  a.pw = c->pw;
   a.slot_lo = lo;
   a.slot_hi = hi;
   a.p_active = clip ? c->scal + 5 : nullptr;
   return a;
 }
 
+// Blocks of a bundle sweep over slots [lo, hi): sized for the bundle's
+// expected nonzeros.
+int bundle_sweep_grid(const pcdn_ctx* c, int64_t lo, int64_t hi) {
+  return sweep_ranges_grid((double)c->nnz * (double)(hi - lo) / (double)c->p);
+}
+
 int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) {
   const SweepArgs a = bundle_sweep_args(c, o, lo, hi, clip);
   {
     ProfScope ps(c, 0);
-    HIPCHK(c, launch_sweep(c->loss, a, c->stream));
+    HIPCHK(c, launch_sweep_ranges(c->loss, a, bundle_sweep_grid(c, lo, hi), c->stream));
   }
-  if (has_split_columns(c, o.chunk)) {
+  {
     ProfScope ps(c, 1);
-    HIPCHK(c, launch_split(c->loss, a, c->stream));
+    HIPCHK(c, launch_sweep_finish(c->loss, a, c->stream));
   }
   return PCDN_OK;
 }
@@ -295,11 +306,45 @@ int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
   return bundle_ls_apply(c, o, perm, lo, hi, clip, P);
 }
 
+// The bundle-row order and X in partition order for bundles of P over the
+// order perm (p_slots slots; chunk descriptors of that order in c->chunks).
+BrPlan br_plan(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
+  BrPlan b{};
+  b.perm = perm;
+  b.p = c->p;
+  b.p_slots = p_slots;
+  b.P = P;
+  b.cp = c->cp;
+  b.rr = c->rr;
+  b.rc = c->rc;
+  b.rv = c->rv;
+  b.nnz = c->nnz;
+  b.ri = c->ri;
+  b.v = c->v;
+  b.chunks = c->chunks;
+  b.cstart = c->cstart;
+  b.w = c->w;
+  b.islot = c->islot;
+  b.len_tmp = c->nch;
+  b.off32 = c->off32;
+  b.scan_tmp = c->scan_tmp;
+  b.poff = c->poff;
+  b.br_row = c->br_row;
+  b.br_slot = c->br_slot;
+  b.br_val = c->br_val;
+  b.bt_row = c->bt_row;
+  b.bt_slot = c->bt_slot;
+  b.bt_val = c->bt_val;
+  b.hist = c->br_hist;
+  b.pri = c->pri;
+  b.pv = c->pv;
+  b.pslot = c->pslot;
+  b.pw = c->pw;
+  return b;
+}
+
 int build_bundle_rows(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
-  HIPCHK(c, launch_bundle_row_order(perm, c->p, p_slots, P, c->cp, c->rr, c->rc, c->rv, c->nnz,
-                                    c->islot, c->nch, c->off32, c->scan_tmp, c->poff, c->br_row,
-                                    c->br_slot, c->br_val, c->bt_row, c->bt_slot, c->bt_val,
-                                    c->br_hist, c->stream));
+  HIPCHK(c, launch_bundle_row_order(br_plan(c, perm, p_slots, P), c->stream));
   return PCDN_OK;
 }
 
@@ -549,7 +594,7 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
 // local row ids where the single-workgroup kernel can use them.
 int permute_x(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
   HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
-                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->w, c->pw,
+                           c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->pslot, c->w, c->pw,
                            c->stream));
   if (use_bundle_rows(c, P, p_slots))
     HIPCHK(c, launch_bundle_rows(c->poff, c->pri, p_slots, P, c->n, c->plid, c->pR, c->stream));
@@ -679,17 +724,16 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
     t.gx = gx;
     return t;
   };
-  bundle_row_tasks(c->loss, c->idx0, c->p, c->p, P, c->cp, c->rr, c->rc, c->rv, c->nnz, c->islot,
-                   c->nch, c->off32, c->scan_tmp, c->poff, c->br_row, c->br_slot, c->br_val,
-                   c->bt_row, c->bt_slot, c->bt_val, c->br_hist, out);
+  bundle_row_tasks(c->loss, br_plan(c, c->idx0, c->p, P), out);
   const int64_t nb = (c->p + P - 1) / P;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t lo = b * P, hi = std::min(lo + P, c->p);
-    Task t = task(kTaskSweep, sweep_grid(hi - lo), 0);
+    Task t = task(kTaskSweepRanges, bundle_sweep_grid(c, lo, hi), 0);
     t.u.sw = bundle_sweep_args(c, o, lo, hi, o.shrink);
     out.push_back(t);
-    t.kind = kTaskSplit;
-    if (has_split_columns(c, o.chunk)) out.push_back(t);
+    t.kind = kTaskSweepFinish;
+    t.nblk = sweep_finish_grid(hi - lo);
+    out.push_back(t);
     const RowsArgs r = rows_args(c, o, c->idx0, lo, hi, o.shrink, P);
     t = task(kTaskRowsDtx, r.G, 0);
     t.u.rw = r;
@@ -1079,6 +1123,9 @@ extern "C" int pcdn_destroy(pcdn_ctx* c) {
   for (auto e : c->prof.pool) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
+  // the errors of these releases are ignored: do not leave one for the next
+  // launch check of this thread
+  (void)hipGetLastError();
   return PCDN_OK;
 }
 
@@ -1104,7 +1151,7 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       4 * (std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1),
       4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
       4 * p,                                               // step bundle
-      16 * part_len, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
+      16 * part_len, 4 * nnz, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
       8 * p,                                               // w in partition order
       2 * nnz, 4 * (p + 1),                                // bundle-local row ids
       8 * (int64_t)kRowsGridMax * (4 * kQMax + 3),         // line-search partials
@@ -1221,6 +1268,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->part, c->part_len);
   ALLOC(c, c->pri, nnz);
   ALLOC(c, c->pv, nnz);
+  ALLOC(c, c->pslot, nnz);
   ALLOC(c, c->poff, p + 1);
   ALLOC(c, c->pw, p);
   ALLOC(c, c->off32, p + 1);

@@ -206,12 +206,23 @@ class Engine {
     // single-workgroup jobs: one launch (both losses), then each job's
     // stopping sweep
     if (m > 0) {
+      const char* step = "table upload";
       hipError_t e = hipMemcpyAsync(narrow_tab_.dev, htab, sizeof(NarrowArgs) * m,
                                     hipMemcpyHostToDevice, narrow_stream_);
-      if (e == hipSuccess)
+      if (e == hipSuccess) {
+        step = "single-workgroup launch";
         e = launch_narrow_multi((const NarrowArgs*)narrow_tab_.dev, (int)m, narrow_stream_);
-      if (e == hipSuccess) e = hipEventRecord(fused_done_, narrow_stream_);
-      if (e != hipSuccess) return dev_fail("multi-problem launch", e);
+      }
+      if (e == hipSuccess) {
+        step = "event record";
+        e = hipEventRecord(fused_done_, narrow_stream_);
+      }
+      if (e != hipSuccess) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        (void)hipStreamIsCapturing(narrow_stream_, &cs);
+        return dev_fail((std::string("multi-problem launch (") + step + ", stream capture status " +
+                         std::to_string((int)cs) + ")").c_str(), e);
+      }
       for (EngineJob* j : jobs_) {
         if (!j->narrow || j->hybrid) continue;
         pcdn_ctx* c = j->run.c;
@@ -572,6 +583,11 @@ struct pcdn_server {
   int64_t next_id = 1;
   std::string err;
   mutable std::mutex mu;         // guards waiting, loaded, loading, used and stop
+  // held by the loader while it uploads and by the caller's thread while it
+  // sets a solve up (which captures graphs): the HIP runtime has refused
+  // other threads' calls while a stream was being captured, whatever the
+  // capture mode, so the two never overlap
+  std::mutex capture_mu;
   std::condition_variable cv;
   bool stop = false;
   std::thread loader;
@@ -641,13 +657,17 @@ void server_loader(pcdn_server* s) {
       ++s->loading;
       s->loading_id = q->id;
     }
-    int rc = pcdn_create(&q->ctx, s->device, nullptr);
-    if (rc) {
-      q->msg = pcdn_last_error(nullptr);
-    } else {
-      const pcdn_request& r = q->r;
-      rc = pcdn_load_csc(q->ctx, r.n, r.p, r.nnz, r.col_ptr, r.row_idx, r.val, r.y, 0);
-      if (rc) q->msg = pcdn_last_error(q->ctx);
+    int rc;
+    {
+      std::lock_guard<std::mutex> cap(s->capture_mu);
+      rc = pcdn_create(&q->ctx, s->device, nullptr);
+      if (rc) {
+        q->msg = pcdn_last_error(nullptr);
+      } else {
+        const pcdn_request& r = q->r;
+        rc = pcdn_load_csc(q->ctx, r.n, r.p, r.nnz, r.col_ptr, r.row_idx, r.val, r.y, 0);
+        if (rc) q->msg = pcdn_last_error(q->ctx);
+      }
     }
     q->load_rc = rc;
     {
@@ -676,6 +696,7 @@ int server_admit(pcdn_server* s, ServerReq* q) {
   run.eps = r.eps;
   run.loss = r.loss;
   q->job.id = q->id;
+  std::lock_guard<std::mutex> cap(s->capture_mu);
   return s->eng.add(&q->job);
 }
 

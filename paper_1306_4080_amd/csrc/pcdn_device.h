@@ -97,6 +97,13 @@ struct SweepArgs {
   const double* w;
   const Chunk* chunks;        // chunk descriptors of the order
   const int32_t* cstart;      // slot -> first chunk, p+1 entries
+  // X in partition order (bundle sweep): the nonzeros of slot r are
+  // pri/pv/pslot[poff[r] .. poff[r+1]), pslot holding r; pw[r] = w[perm[r]]
+  const int64_t* poff;
+  const int32_t* pri;
+  const float* pv;
+  const int32_t* pslot;
+  const double* pw;
   int64_t slot_lo, slot_hi;   // this launch covers slots [slot_lo, slot_hi)
   double* g;                  // per-slot outputs, indexed by the absolute slot
   double* h;
@@ -153,6 +160,7 @@ struct StopArgs {
 // and lists them (row, d^T x_i) at u_row/u_dtx[r kRangeW ...], u_cnt[r] of
 // them, rows with d^T x_i = 0 left out.
 constexpr int kRangeW = 256;
+constexpr int kSweepW = 256;  // nonzeros per wavefront range of the bundle sweep
 constexpr int kRowsGridMax = 2048;  // blocks of the d^T x / line-search launch (at most)
 struct RowsArgs {
   const int32_t* br_row;     // bundle-row order: row, slot and value of each nonzero
@@ -215,6 +223,21 @@ struct WidenArgs {
   int64_t m;
   int64_t* out;
 };
+// X copied into partition order (one wavefront per chunk of the order):
+// pri/pv[poff[slot] + e] and, if pslot is not null, pslot = the slot.
+struct PermuteArgs {
+  const int32_t* ri;
+  const float* v;
+  const int64_t* cp;
+  const Chunk* chunks;
+  const int32_t* cstart;
+  int64_t p;                 // slots
+  const int64_t* poff;
+  int32_t* pri;
+  float* pv;
+  int32_t* pslot;
+};
+
 struct IslotArgs {           // islot[perm[r]] = r for r < p
   const int32_t* perm;
   int64_t p;
@@ -287,9 +310,9 @@ struct ChunkArgs {
 // executor: the kernel, its arguments, and the grid a launch of its own
 // would have (nblk blocks; the line search's grid is gx x nblk/gx).
 enum TaskKind : int32_t {
-  kTaskSweep = 0,
+  kTaskSweepRanges = 0,
   kTaskStopRanges,
-  kTaskSplit,
+  kTaskSweepFinish,
   kTaskStopFinish,
   kTaskRowsDtx,
   kTaskRowsApply,
@@ -311,6 +334,7 @@ enum TaskKind : int32_t {
   kTaskIslot,
   kTaskBrHist,
   kTaskBrScatter,
+  kTaskPermute,
 };
 struct Task {
   int32_t kind;
@@ -325,6 +349,7 @@ struct Task {
     SlotLenArgs sl;
     WidenArgs wd;
     IslotArgs is;
+    PermuteArgs pm;
     SumArgs sum;
     StopSumArgs stop;
     PermKeysArgs pk;
@@ -417,13 +442,17 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp,
 hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
                          int32_t* nch, int32_t* cstart, Chunk* chunks, int32_t* tmp,
                          hipStream_t s);
-int sweep_grid(int64_t slots);
-hipError_t launch_sweep(int loss, const SweepArgs& a, hipStream_t s);
+// The bundle sweep (X in partition order, ranges of kSweepW nonzeros) and
+// its finish over the bundle's slots, with the grids they take for a bundle
+// of `slots` slots and about `nnz_bundle` nonzeros.
+int sweep_ranges_grid(double nnz_bundle);
+int sweep_finish_grid(int64_t slots);
+hipError_t launch_sweep_ranges(int loss, const SweepArgs& a, int grid, hipStream_t s);
+hipError_t launch_sweep_finish(int loss, const SweepArgs& a, hipStream_t s);
 // The stopping sweep (both kernels) and the grids they take.
 int stop_ranges_grid(int64_t nnz);
 int stop_finish_grid(int64_t p);
 hipError_t launch_stop_sweep(int loss, const StopArgs& a, hipStream_t s);
-hipError_t launch_split(int loss, const SweepArgs& a, hipStream_t s);
 int sum_grid(int64_t m);
 // Blocks of the d^T x / line-search launch for bundles of about `nnz_bundle`
 // nonzeros (RowsArgs::G).
@@ -438,20 +467,41 @@ hipError_t launch_rows_apply(int loss, const RowsArgs& a, hipStream_t s);
 // working storage (br_hist_ints(nnz) and scan_tmp_ints of it).
 int br_passes(int64_t p_slots, int64_t P);
 int64_t br_hist_ints(int64_t nnz);
-hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
-                                   const int64_t* cp, const int32_t* rr, const int32_t* rc,
-                                   const float* rv, int64_t nnz, int32_t* islot, int32_t* len_tmp,
-                                   int32_t* off32, int32_t* scan_tmp, int64_t* poff,
-                                   int32_t* br_row, int32_t* br_slot, float* br_val,
-                                   int32_t* bt_row, int32_t* bt_slot, float* bt_val,
-                                   int32_t* hist, hipStream_t s);
+// The same pass also copies X into partition order (pri, pv, pslot at poff,
+// from the chunk descriptors of the order) and w into slot order (pw).
+struct BrPlan {
+  const int32_t* perm;
+  int64_t p, p_slots, P;
+  const int64_t* cp;
+  const int32_t* rr;     // the CSR copy of X
+  const int32_t* rc;
+  const float* rv;
+  int64_t nnz;
+  const int32_t* ri;     // X as loaded (CSC)
+  const float* v;
+  const Chunk* chunks;   // chunk descriptors of the order
+  const int32_t* cstart;
+  const double* w;
+  int32_t* islot;
+  int32_t* len_tmp;
+  int32_t* off32;
+  int32_t* scan_tmp;
+  int64_t* poff;
+  int32_t* br_row;
+  int32_t* br_slot;
+  float* br_val;
+  int32_t* bt_row;
+  int32_t* bt_slot;
+  float* bt_val;
+  int32_t* hist;
+  int32_t* pri;
+  float* pv;
+  int32_t* pslot;
+  double* pw;
+};
+hipError_t launch_bundle_row_order(const BrPlan& b, hipStream_t s);
 // The same as executor tasks (appended to out).
-void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
-                      const int64_t* cp, const int32_t* rr, const int32_t* rc, const float* rv,
-                      int64_t nnz, int32_t* islot, int32_t* len_tmp, int32_t* off32,
-                      int32_t* scan_tmp, int64_t* poff, int32_t* br_row, int32_t* br_slot,
-                      float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val,
-                      int32_t* hist, std::vector<Task>& out);
+void bundle_row_tasks(int loss, const BrPlan& b, std::vector<Task>& out);
 // dense[i] = d^T x_i of the touched rows listed by the last d^T x launch of
 // the bundle [a.slot_lo, a.slot_hi) (dense must be zero elsewhere).
 hipError_t launch_rows_scatter(const RowsArgs& a, double* dense, hipStream_t s);
@@ -478,7 +528,7 @@ hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s);
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
-                          int32_t* pri, float* pv, const double* w, double* pw,
+                          int32_t* pri, float* pv, int32_t* pslot, const double* w, double* pw,
                           hipStream_t s);
 // Deterministic two-kernel sum of x[0..m) into *out; optional: advance it->k.
 hipError_t launch_sum(const double* x, int64_t m, double* part, double* out, IterState* it,

@@ -89,6 +89,7 @@ struct pcdn_ctx {
   int64_t part_len = 0;
   // X in partition order (single-workgroup schedule)
   int32_t* pri = nullptr;
+  int32_t* pslot = nullptr;      // slot of each nonzero in partition order
   float* pv = nullptr;
   int64_t* poff = nullptr;
   int32_t* off32 = nullptr;

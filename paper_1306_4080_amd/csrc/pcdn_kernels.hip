@@ -630,45 +630,24 @@ __global__ __launch_bounds__(kBlock) void k_chunk_fill(const int32_t* perm, cons
 }
 
 // ---------------------------------------------------------------------------
-// gradient / Hessian sweep over a bundle's columns, one wavefront per chunk.
-// Bundle mode: per-feature g, h, the direction d (eq. (5)) and its Delta
-// term.  Split columns only leave their partial sums; k_split finishes them
-// after the kernel boundary.  Stopping mode: |grad^S_j F| per feature, no
-// direction.  (d^T x, the second read of x, is formed by row afterwards.)
+// gradient / Hessian sweep of a bundle (eq. (11); SVM: eq. (3) and the
+// generalised Hessian), the direction (eq. (5)) and its Delta term (eq. (7)),
+// over the bundle's nonzeros in partition order (one contiguous range, the
+// nonzeros of each slot together).  Wavefront w takes ranges of kSweepW
+// nonzeros, lane L the range's nonzeros 4L .. 4L+3: a lane sums its own
+// nonzeros per slot in order and finishes the slots that start and end
+// inside it; one segmented wavefront scan over the lanes' last runs carries
+// runs across lanes, and a slot is finished where it ends.  Slots that cross
+// a range boundary leave partials (part[2m]: the part of range m of the slot
+// that began before it, part[2m+1]: of the slot that begins in m and goes on)
+// and k_sweep_finish completes them and the empty slots, adding partials in
+// range order.  Every sum has a fixed order.  (d^T x, the second read of x,
+// is formed by row afterwards.)
 // ---------------------------------------------------------------------------
-constexpr int kUnroll = 4;
-
+// g, h from the summed terms, the direction and Delta's term of slot o.
 template <int LOSS>
-__device__ inline void sweep_range(const SweepArgs& a, int64_t klo, int64_t khi, int lane,
-                                   double& gs, double& hs) {
-  for (int64_t k = klo + lane; k < khi; k += (int64_t)kWave * kUnroll) {
-    int32_t row[kUnroll];
-    float xv[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t kk = k + (int64_t)u * kWave;
-      const bool ok = kk < khi;
-      row[u] = ldz(a.ri, ok, kk, -1);
-      xv[u] = ldz(a.v, ok, kk, 0.0f);
-    }
-    double2 rv[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) rv[u] = ldz(a.rw, row[u] >= 0, row[u], make_double2(0.0, 0.0));
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) asm volatile("" ::"v"(xv[u]), "v"(rv[u].x), "v"(rv[u].y));
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (row[u] >= 0) weighted_terms<LOSS>(rv[u], (double)xv[u], gs, hs);
-  }
-}
-
-// g, h from the summed column terms (eq. (11); SVM: eq. (3) and the
-// generalised Hessian), the direction (eq. (5)) and the Delta term (eq. (7));
-// lane 0 writes the per-slot outputs.
-template <int LOSS>
-__device__ inline void finish_feature(const SweepArgs& a, const Chunk& ch, double gs, double hs,
-                                      double wj, bool writer) {
-  const double C = *a.Cp;
+__device__ inline void finish_slot(const SweepArgs& a, int64_t o, double gs, double hs, double wj,
+                                   double C) {
   double g, h;
   if (LOSS == kLogistic) {
     g = C * gs;
@@ -679,13 +658,10 @@ __device__ inline void finish_feature(const SweepArgs& a, const Chunk& ch, doubl
   }
   if (h <= 0.0) h += a.nu;
   const double dj = newton_dir(g, h, wj, a.ra, a.rb);
-  if (writer) {
-    const int64_t o = ch.slot;
-    a.g[o] = g;
-    a.h[o] = h;
-    a.d[o] = dj;
-    a.dterm[o] = g * dj + a.gamma * h * dj * dj + reg_change(wj, dj, a.ra, a.rb);
-  }
+  a.g[o] = g;
+  a.h[o] = h;
+  a.d[o] = dj;
+  a.dterm[o] = g * dj + a.gamma * h * dj * dj + reg_change(wj, dj, a.ra, a.rb);
 }
 
 // Last slot of a launch's range, clipped to the active features when
@@ -696,121 +672,207 @@ __device__ inline int64_t clipped_hi(int64_t hi, const double* p_active) {
   return pa < hi ? pa : hi;
 }
 
-// Kernel bodies take the block index and block count of their launch as
-// arguments, so that the multi-problem executor (k_exec) can run them on a
-// slice of its grid with exactly the work split of a launch of their own.
-//
-// Bundle sweep: a wavefront takes kSweepGroup consecutive chunks at a time
-// and issues their loads together (descriptors, then w and the first 128
-// nonzeros of each, then the retained quantities and labels of their rows):
-// short columns would otherwise cost one chain of dependent round trips
-// each.  Entries past the first 128 of a chunk (chunks longer than the
-// default) follow in the same per-lane order.
-constexpr int kSweepGroup = 4;
+__device__ inline double lane_pick(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+  const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
+}
 
 template <int LOSS>
-__device__ __forceinline__ void sweep_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
+__device__ __forceinline__ void sweep_ranges_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
+  constexpr int kE = kSweepW / kWave;  // consecutive nonzeros per lane
   const int lane = lane_id();
-  const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
-  const int64_t nwaves = nblk * kWavesPerBlock;
   const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
   if (hi <= a.slot_lo) return;
-  const int32_t c_lo = a.cstart[a.slot_lo];
-  const int32_t c_hi = a.cstart[hi];
-  for (int64_t c0 = c_lo + wave * kSweepGroup; c0 < c_hi; c0 += nwaves * kSweepGroup) {
-    Chunk ch[kSweepGroup];
+  const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[hi];
+  const int64_t nr = (e1 - e0 + kSweepW - 1) / kSweepW;
+  const int64_t nwaves = nblk * kWavesPerBlock;
+  const double C = *a.Cp;
+  for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
+    const int64_t rb = e0 + m * kSweepW;
+    const int64_t re = rb + kSweepW < e1 ? rb + kSweepW : e1;
+    const int64_t k0 = rb + (int64_t)lane * kE;
+    int32_t sl[kE], row[kE];
+    float xv[kE];
 #pragma unroll
-    for (int g = 0; g < kSweepGroup; ++g) {
-      // past the end: the first chunk again, with no nonzeros and no output
-      ch[g] = a.chunks[c0 + g < c_hi ? c0 + g : c_lo];
-      if (c0 + g >= c_hi) ch[g].len = 0;
+    for (int u = 0; u < kE; ++u) {
+      const int64_t k = k0 + u;
+      const bool in = k < re;
+      sl[u] = ldz(a.pslot, in, k, -1);
+      row[u] = ldz(a.pri, in, k, 0);
+      xv[u] = ldz(a.pv, in, k, 0.0f);
     }
-    double wj[kSweepGroup];
-    int32_t row[kSweepGroup][2];
-    float xv[kSweepGroup][2];
+    // slots open at the range's ends
+    const int32_t left = rb > e0 ? a.pslot[rb - 1] : -1;
+    const int32_t right = re < e1 ? a.pslot[re] : -1;
+    double2 rv[kE];
+    double wv[kE];
 #pragma unroll
-    for (int g = 0; g < kSweepGroup; ++g) {
-      wj[g] = ldz(a.w, c0 + g < c_hi, ch[g].feat, 0.0);
+    for (int u = 0; u < kE; ++u) {
+      rv[u] = ldz(a.rw, sl[u] >= 0, row[u], make_double2(0.0, 0.0));
+      wv[u] = ldz(a.pw, sl[u] >= 0, sl[u], 0.0);
+    }
+    // every operand loaded before the first use (no load sunk into a branch)
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const bool ok = lane + u * kWave < ch[g].len;
-        row[g][u] = ldz(a.ri, ok, ch[g].klo + lane + u * kWave, -1);
-        xv[g][u] = ldz(a.v, ok, ch[g].klo + lane + u * kWave, 0.0f);
+    for (int u = 0; u < kE; ++u)
+      asm volatile("" ::"v"(rv[u].x), "v"(rv[u].y), "v"(wv[u]), "v"(xv[u]));
+    // the lane's runs: head (from its first nonzero), complete middles, tail
+    const int32_t hk = sl[0];
+    const double hw = wv[0];
+    int32_t rk = sl[0];
+    double rg = 0.0, rh = 0.0;
+    if (sl[0] >= 0) weighted_terms<LOSS>(rv[0], (double)xv[0], rg, rh);
+    double wk = wv[0], hg = 0.0, hh = 0.0;
+    bool whole = true;  // one run covers the lane's nonzeros
+#pragma unroll
+    for (int u = 1; u < kE; ++u) {
+      double tg = 0.0, th = 0.0;
+      if (sl[u] >= 0) weighted_terms<LOSS>(rv[u], (double)xv[u], tg, th);
+      if (sl[u] == rk) {
+        rg += tg;
+        rh += th;
+      } else {
+        if (whole) {
+          hg = rg;  // the head run ends inside the lane
+          hh = rh;
+          whole = false;
+        } else if (rk >= 0) {
+          finish_slot<LOSS>(a, rk, rg, rh, wk, C);  // starts and ends here
+        }
+        rk = sl[u];
+        rg = tg;
+        rh = th;
+        wk = wv[u];
       }
     }
-    double2 rv[kSweepGroup][2];
-#pragma unroll
-    for (int g = 0; g < kSweepGroup; ++g)
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-        rv[g][u] = ldz(a.rw, row[g][u] >= 0, row[g][u], make_double2(0.0, 0.0));
-    // every operand of the terms loaded here, before the first use: the
-    // compiler would otherwise sink the value and label loads into the
-    // per-nonzero branches of the loss (the SVM's active-set test) and wait
-    // for each there
-#pragma unroll
-    for (int g = 0; g < kSweepGroup; ++g)
-#pragma unroll
-      for (int u = 0; u < 2; ++u) asm volatile("" ::"v"(xv[g][u]), "v"(rv[g][u].x), "v"(rv[g][u].y));
-    double gs[kSweepGroup], hs[kSweepGroup];
-#pragma unroll
-    for (int g = 0; g < kSweepGroup; ++g) {
-      gs[g] = 0.0;
-      hs[g] = 0.0;
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-        if (row[g][u] >= 0) weighted_terms<LOSS>(rv[g][u], (double)xv[g][u], gs[g], hs[g]);
-      if (ch[g].len > 2 * kWave)
-        sweep_range<LOSS>(a, ch[g].klo + 2 * kWave, ch[g].klo + ch[g].len, lane, gs[g], hs[g]);
+    if (whole) {
+      hg = rg;
+      hh = rh;
     }
-#pragma unroll
-    for (int g = 0; g < kSweepGroup; ++g) {
-      if (c0 + g >= c_hi) break;
-      const double gt = wave_sum(gs[g]);
-      const double ht = wave_sum(hs[g]);
-      if (ch[g].nch > 1) {
-        if (lane == 0) a.part[c0 + g] = make_double2(gt, ht);
-        continue;
+    // tail runs carried over the lanes of equal slot
+    const int32_t tk = rk;
+    double Sg = rg, Sh = rh;
+    seg_scan1(Sg, tk);
+    seg_scan1(Sh, tk);
+    const int32_t pk = __builtin_amdgcn_update_dpp(-1, tk, 0x138, 0xf, 0xf, false);  // lane - 1
+    const double pg = dpp_f64<0x138, 0xf, 0xf>(Sg);
+    const double ph = dpp_f64<0x138, 0xf, 0xf>(Sh);
+    const int32_t nk = next_lane_key(hk);  // the next lane's first slot
+    const int last_lane = (int)((re - 1 - rb) / kE);
+    double fg = 0.0, fh = 0.0, lg = 0.0, lh = 0.0;
+    bool has_f = false, has_l = false;
+    if (!whole && hk >= 0) {
+      // the head run ends in this lane: add what the previous lanes carried
+      const bool carried = lane > 0 && pk == hk;
+      const double Hg = hg + (carried ? pg : 0.0), Hh = hh + (carried ? ph : 0.0);
+      if (hk == left) {
+        fg = Hg;
+        fh = Hh;
+        has_f = true;
+      } else {
+        finish_slot<LOSS>(a, hk, Hg, Hh, hw, C);
       }
-      finish_feature<LOSS>(a, ch[g], gt, ht, wj[g], lane == 0);
+    }
+    if (tk >= 0 && lane <= last_lane) {
+      const bool at_end = lane == last_lane;
+      const bool cont = at_end ? right == tk : nk == tk;
+      if (at_end || !cont) {
+        if (tk == left) {  // (also when right-open: a slot through the whole range)
+          fg = Sg;
+          fh = Sh;
+          has_f = true;
+        } else if (cont) {
+          lg = Sg;
+          lh = Sh;
+          has_l = true;
+        } else {
+          finish_slot<LOSS>(a, tk, Sg, Sh, wk, C);
+        }
+      }
+    }
+    // the partials (held by the lanes that ended the open runs)
+    const uint64_t mf = __ballot(has_f), ml = __ballot(has_l);
+    double2 pf = make_double2(0.0, 0.0), pl = make_double2(0.0, 0.0);
+    if (mf) {
+      const int src = __builtin_ctzll(mf);
+      pf = make_double2(lane_pick(fg, src), lane_pick(fh, src));
+    }
+    if (ml) {
+      const int src = __builtin_ctzll(ml);
+      pl = make_double2(lane_pick(lg, src), lane_pick(lh, src));
+    }
+    if (lane == 0) {
+      a.part[2 * m] = pf;
+      a.part[2 * m + 1] = pl;
     }
   }
 }
 
 template <int LOSS>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
-  sweep_body<LOSS>(a, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kBlock) void k_sweep_ranges(SweepArgs a) {
+  sweep_ranges_body<LOSS>(a, blockIdx.x, gridDim.x);
 }
 
-// Split columns: the first wavefront of a split feature sums its chunk
-// partials in chunk order and finishes the feature.
+// Slots that cross a range boundary and empty slots (g_j = h_j = 0 before
+// the floor).  Lane L of a wavefront takes slot base + L: a slot over at
+// most kFinishShort + 1 ranges adds its partials in range order itself; a
+// longer one (a long column) is summed by the whole wavefront, lanes taking
+// every 64th range, then the fixed-order wavefront sum.
+constexpr int kFinishShort = 4;
+
 template <int LOSS>
-__device__ __forceinline__ void split_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
-  const int lane = lane_id();
-  const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
-  const int64_t nwaves = nblk * kWavesPerBlock;
+__device__ __forceinline__ void sweep_finish_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
   const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
   if (hi <= a.slot_lo) return;
-  const int32_t c_lo = a.cstart[a.slot_lo];
-  const int32_t c_hi = a.cstart[hi];
-  for (int64_t c = c_lo + wave; c < c_hi; c += nwaves) {
-    const Chunk ch = a.chunks[c];
-    if (ch.nch == 1 || c != ch.c0) continue;
-    double gs = 0.0, hs = 0.0;
-    for (int32_t q = lane; q < ch.nch; q += kWave) {
-      const double2 pq = a.part[ch.c0 + q];
-      gs += pq.x;
-      hs += pq.y;
+  const int lane = lane_id();
+  const int64_t e0 = a.poff[a.slot_lo];
+  const double C = *a.Cp;
+  const int64_t nwaves = nblk * kWavesPerBlock;
+  for (int64_t base = a.slot_lo + uniform((bid * kBlock + threadIdx.x) / kWave) * kWave; base < hi;
+       base += nwaves * kWave) {
+    const int64_t o = base + lane;
+    const bool valid = o < hi;
+    const int64_t k0 = ldz(a.poff, valid, o, (int64_t)0), k1 = ldz(a.poff, valid, o + 1, (int64_t)0);
+    const int64_t m1 = (k0 - e0) / kSweepW, m2 = k1 > k0 ? (k1 - 1 - e0) / kSweepW : m1;
+    const bool empty = valid && k1 == k0;
+    const bool crossing = valid && k1 > k0 && m2 > m1;
+    const bool longer = crossing && m2 - m1 > kFinishShort;
+    const double wj = ldz(a.pw, valid, o, 0.0);
+    if (empty) finish_slot<LOSS>(a, o, 0.0, 0.0, wj, C);
+    if (crossing && !longer) {
+      double2 t = a.part[2 * m1 + 1];
+      double gs = t.x, hs = t.y;
+      for (int64_t m = m1 + 1; m <= m2; ++m) {
+        t = a.part[2 * m];
+        gs += t.x;
+        hs += t.y;
+      }
+      finish_slot<LOSS>(a, o, gs, hs, wj, C);
     }
-    gs = wave_sum(gs);
-    hs = wave_sum(hs);
-    finish_feature<LOSS>(a, ch, gs, hs, a.w[ch.feat], lane == 0);
+    for (uint64_t lm = __ballot(longer); lm; lm &= lm - 1) {
+      const int src = __builtin_ctzll(lm);
+      const int64_t s1 = (int64_t)__builtin_amdgcn_readlane((int)m1, src) , s2 =
+          (int64_t)__builtin_amdgcn_readlane((int)m2, src);
+      double gs = 0.0, hs = 0.0;
+      for (int64_t m = s1 + 1 + lane; m <= s2; m += kWave) {
+        const double2 t = a.part[2 * m];
+        gs += t.x;
+        hs += t.y;
+      }
+      gs = wave_sum(gs);
+      hs = wave_sum(hs);
+      if (lane == src) {
+        const double2 t = a.part[2 * m1 + 1];
+        finish_slot<LOSS>(a, o, t.x + gs, t.y + hs, wj, C);
+      }
+    }
   }
 }
 
 template <int LOSS>
-__global__ __launch_bounds__(kBlock) void k_split(SweepArgs a) {
-  split_body<LOSS>(a, blockIdx.x, gridDim.x);
+__global__ __launch_bounds__(kBlock) void k_sweep_finish(SweepArgs a) {
+  sweep_finish_body<LOSS>(a, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -963,17 +1025,35 @@ __global__ __launch_bounds__(kBlock) void k_stop_ranges(StopArgs a) {
 template <int LOSS>
 __device__ __forceinline__ void stop_finish_body(const StopArgs& a, int64_t bid, int64_t nblk) {
   const StopScalars sc = stop_scalars(a);
-  for (int64_t j = bid * kBlock + threadIdx.x; j < a.p; j += nblk * kBlock) {
-    const int64_t k0 = a.cp[j], k1 = a.cp[j + 1];
-    if (k1 == k0) {
-      stop_finish_one<LOSS>(a, j, 0.0, sc.C, sc.thr, a.w ? a.w[j] : 0.0);
-      continue;
+  const int lane = lane_id();
+  const int64_t nwaves = nblk * kWavesPerBlock;
+  // lane L of a wavefront takes column base + L; long columns are summed by
+  // the whole wavefront (as the bundle sweep's finish does)
+  for (int64_t base = uniform((bid * kBlock + threadIdx.x) / kWave) * kWave; base < a.p;
+       base += nwaves * kWave) {
+    const int64_t j = base + lane;
+    const bool valid = j < a.p;
+    const int64_t k0 = ldz(a.cp, valid, j, (int64_t)0), k1 = ldz(a.cp, valid, j + 1, (int64_t)0);
+    const int64_t m1 = k0 / kStopW, m2 = k1 > k0 ? (k1 - 1) / kStopW : m1;
+    const bool empty = valid && k1 == k0;
+    const bool crossing = valid && k1 > k0 && m2 > m1;
+    const bool longer = crossing && m2 - m1 > kFinishShort;
+    const double wj = a.w ? ldz(a.w, valid, j, 0.0) : 0.0;
+    if (empty) stop_finish_one<LOSS>(a, j, 0.0, sc.C, sc.thr, wj);
+    if (crossing && !longer) {
+      double gs = a.part[m1].y;
+      for (int64_t m = m1 + 1; m <= m2; ++m) gs += a.part[m].x;
+      stop_finish_one<LOSS>(a, j, gs, sc.C, sc.thr, wj);
     }
-    const int64_t m1 = k0 / kStopW, m2 = (k1 - 1) / kStopW;
-    if (m1 == m2) continue;  // finished by its range
-    double gs = a.part[m1].y;
-    for (int64_t m = m1 + 1; m <= m2; ++m) gs += a.part[m].x;
-    stop_finish_one<LOSS>(a, j, gs, sc.C, sc.thr, a.w ? a.w[j] : 0.0);
+    for (uint64_t lm = __ballot(longer); lm; lm &= lm - 1) {
+      const int src = __builtin_ctzll(lm);
+      const int64_t s1 = (int64_t)__builtin_amdgcn_readlane((int)m1, src);
+      const int64_t s2 = (int64_t)__builtin_amdgcn_readlane((int)m2, src);
+      double gs = 0.0;
+      for (int64_t m = s1 + 1 + lane; m <= s2; m += kWave) gs += a.part[m].x;
+      gs = wave_sum(gs);
+      if (lane == src) stop_finish_one<LOSS>(a, j, a.part[m1].y + gs, sc.C, sc.thr, wj);
+    }
   }
 }
 
@@ -2281,22 +2361,24 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow_multi(const NarrowArgs*
 
 // Copy X into partition order: the nonzeros of slot r land at
 // [poff[r], poff[r+1]) (one wavefront per chunk descriptor).
-__global__ __launch_bounds__(kBlock) void k_permute(const int32_t* ri, const float* v,
-                                                    const int64_t* cp, const Chunk* chunks,
-                                                    const int32_t* cstart, int64_t p,
-                                                    const int64_t* poff, int32_t* pri, float* pv) {
+__device__ __forceinline__ void permute_body(const PermuteArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
-  const int64_t wave = uniform(((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
-  const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-  const int64_t total = cstart[p];
+  const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
+  const int64_t nwaves = nblk * kWavesPerBlock;
+  const int64_t total = a.cstart[a.p];
   for (int64_t c = wave; c < total; c += nwaves) {
-    const Chunk ch = chunks[c];
-    const int64_t dst = poff[ch.slot] + (ch.klo - cp[ch.feat]);
+    const Chunk ch = a.chunks[c];
+    const int64_t dst = a.poff[ch.slot] + (ch.klo - a.cp[ch.feat]);
     for (int32_t e = lane; e < ch.len; e += kWave) {
-      pri[dst + e] = ri[ch.klo + e];
-      pv[dst + e] = v[ch.klo + e];
+      a.pri[dst + e] = a.ri[ch.klo + e];
+      a.pv[dst + e] = a.v[ch.klo + e];
+      if (a.pslot) a.pslot[dst + e] = ch.slot;
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute(PermuteArgs a) {
+  permute_body(a, blockIdx.x, gridDim.x);
 }
 
 // Column length of each slot, and w in slot order (pw[r] = w[perm[r]]).
@@ -2431,15 +2513,16 @@ __device__ inline int task_of_block(const int32_t* first, int count, int b) {
 template <int LOSS>
 __device__ __forceinline__ void exec_task(const Task& t, int lb) {
   switch (t.kind) {
-    case kTaskSweep: sweep_body<LOSS>(t.u.sw, lb, t.nblk); break;
+    case kTaskSweepRanges: sweep_ranges_body<LOSS>(t.u.sw, lb, t.nblk); break;
     case kTaskStopRanges: stop_ranges_body<LOSS>(t.u.so, lb, t.nblk); break;
-    case kTaskSplit: split_body<LOSS>(t.u.sw, lb, t.nblk); break;
+    case kTaskSweepFinish: sweep_finish_body<LOSS>(t.u.sw, lb, t.nblk); break;
     case kTaskStopFinish: stop_finish_body<LOSS>(t.u.so, lb, t.nblk); break;
     case kTaskRowsDtx: rows_dtx_body<LOSS>(t.u.rw, lb); break;
     case kTaskRowsApply: rows_apply_body<LOSS>(t.u.rw, lb, t.nblk); break;
     case kTaskSlotLen: slot_len_body(t.u.sl, lb); break;
     case kTaskWiden: widen_body(t.u.wd, lb); break;
     case kTaskIslot: islot_body(t.u.is, lb); break;
+    case kTaskPermute: permute_body(t.u.pm, lb, t.nblk); break;
     case kTaskBrHist: br_hist_body(t.u.br, lb); break;
     case kTaskBrScatter: br_scatter_body(t.u.br, lb); break;
     case kTaskSumPartial: sum_partial_body(t.u.sum, lb, t.nblk); break;
@@ -2556,6 +2639,8 @@ inline int grid_for(int64_t items, int per_block, int cap) {
   if (g > cap) g = cap;
   return (int)g;
 }
+
+int permute_grid(int64_t p) { return grid_for(p, kWavesPerBlock, 8192); }
 
 }  // namespace
 
@@ -2709,24 +2794,31 @@ void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, co
   out.push_back(t);
 }
 
-// One wavefront per kSweepGroup slots, and at least 512 wavefronts: a bundle
-// of few features with long columns (the heavy bundles of the
-// single-workgroup schedule: 64 features, up to ~300 chunk work items) then
-// needs one pass over its chunks.  Which wavefront takes a chunk does not
-// change any sum (each chunk is summed by one wavefront; split columns add
-// their chunk partials in chunk order).
-constexpr int64_t kSweepMinWaves = 512;
-int sweep_grid(int64_t slots) {
-  const int64_t waves = (slots + kSweepGroup - 1) / kSweepGroup;
-  return grid_for(waves > kSweepMinWaves ? waves : kSweepMinWaves, kWavesPerBlock, 8192);
+// One wavefront per range of a bundle of the expected size and at least 256
+// wavefronts; a larger bundle (the partition is random) takes several ranges
+// per wavefront.  Which wavefront takes a range changes no sum.
+int sweep_ranges_grid(double nnz_bundle) {
+  const double ranges = nnz_bundle / kSweepW + 1.0;
+  const int64_t waves = ranges > 256.0 ? (int64_t)ranges : 256;
+  return grid_for(waves, kWavesPerBlock, 8192);
 }
 
-hipError_t launch_sweep(int loss, const SweepArgs& a, hipStream_t s) {
-  const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
+int sweep_finish_grid(int64_t slots) { return grid_for(slots, kBlock, 4096); }
+
+hipError_t launch_sweep_ranges(int loss, const SweepArgs& a, int grid, hipStream_t s) {
   if (loss == kLogistic)
-    hipLaunchKernelGGL(k_sweep<kLogistic>, g, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sweep_ranges<kLogistic>, dim3(grid), dim3(kBlock), 0, s, a);
   else
-    hipLaunchKernelGGL(k_sweep<kL2Svm>, g, dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sweep_ranges<kL2Svm>, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_finish(int loss, const SweepArgs& a, hipStream_t s) {
+  const dim3 g(sweep_finish_grid(a.slot_hi - a.slot_lo));
+  if (loss == kLogistic)
+    hipLaunchKernelGGL(k_sweep_finish<kLogistic>, g, dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_sweep_finish<kL2Svm>, g, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2744,15 +2836,6 @@ hipError_t launch_stop_sweep(int loss, const StopArgs& a, hipStream_t s) {
     if (a.nnz > 0) hipLaunchKernelGGL(k_stop_ranges<kL2Svm>, g1, dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_stop_finish<kL2Svm>, g2, dim3(kBlock), 0, s, a);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_split(int loss, const SweepArgs& a, hipStream_t s) {
-  const dim3 g(sweep_grid(a.slot_hi - a.slot_lo));
-  if (loss == kLogistic)
-    hipLaunchKernelGGL(k_split<kLogistic>, g, dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_split<kL2Svm>, g, dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2807,11 +2890,12 @@ namespace {
 // The launches of the bundle-row order, in order: (kernel kind, block count,
 // arguments).  Shared by the direct launcher and the executor's task list.
 struct BrStep {
-  int kind;  // kTaskIslot, kTaskSlotLen, kTaskWiden, kTaskBrHist, kTaskBrScatter; -1: scan
+  int kind;  // kTaskIslot, kTaskSlotLen, kTaskWiden, kTaskPermute, kTaskBrHist, kTaskBrScatter; -1: scan
   int64_t nblk;
   IslotArgs is;
   SlotLenArgs sl;
   WidenArgs wd;
+  PermuteArgs pm;
   BrArgs br;
   const int32_t* scan_in;
   int32_t* scan_out;
@@ -2820,49 +2904,53 @@ struct BrStep {
 
 // Calls f(step) for each launch in order (no host allocation).
 template <class F>
-void br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp,
-              const int32_t* rr, const int32_t* rc, const float* rv, int64_t nnz, int32_t* islot,
-              int32_t* len_tmp, int32_t* off32, int64_t* poff, int32_t* br_row, int32_t* br_slot,
-              float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val, int32_t* hist,
-              F&& f) {
+void br_steps(const BrPlan& bp, F&& f) {
+  const int64_t p_slots = bp.p_slots, P = bp.P, nnz = bp.nnz;
   BrStep st{};
   const int64_t pg = grid_for(p_slots, kBlock, 1 << 30);
   st.kind = kTaskIslot;
   st.nblk = pg;
-  st.is = IslotArgs{perm, p_slots, islot};
+  st.is = IslotArgs{bp.perm, p_slots, bp.islot};
   f(st);
   st = BrStep{};
   st.kind = kTaskSlotLen;
   st.nblk = pg;
-  st.sl = SlotLenArgs{perm, cp, p_slots, len_tmp, nullptr, nullptr};
+  st.sl = SlotLenArgs{bp.perm, bp.cp, p_slots, bp.len_tmp, bp.w, bp.pw};
   f(st);
   st = BrStep{};
   st.kind = -1;
-  st.scan_in = len_tmp;
-  st.scan_out = off32;
+  st.scan_in = bp.len_tmp;
+  st.scan_out = bp.off32;
   st.scan_m = p_slots;
   f(st);
   st = BrStep{};
   st.kind = kTaskWiden;
   st.nblk = grid_for(p_slots + 1, kBlock, 1 << 30);
-  st.wd = WidenArgs{off32, p_slots, poff};
+  st.wd = WidenArgs{bp.off32, p_slots, bp.poff};
   f(st);
   if (nnz == 0) return;
+  // X in partition order (the bundle sweep's input)
+  st = BrStep{};
+  st.kind = kTaskPermute;
+  st.nblk = permute_grid(p_slots);
+  st.pm = PermuteArgs{bp.ri, bp.v, bp.cp, bp.chunks, bp.cstart, p_slots, bp.poff, bp.pri, bp.pv,
+                      bp.pslot};
+  f(st);
   const int passes = br_passes(p_slots, P);
   const int64_t ntiles = (nnz + kBrTile - 1) / kBrTile;
   const int32_t nb = (int32_t)((p_slots + P - 1) / P);
   // the last pass writes the br arrays
-  const int32_t* srow = rr;
-  const int32_t* scol = rc;
-  const float* sval = rv;
+  const int32_t* srow = bp.rr;
+  const int32_t* scol = bp.rc;
+  const float* sval = bp.rv;
   for (int pass = 0; pass < passes; ++pass) {
     const bool to_br = ((passes - 1 - pass) % 2) == 0;
-    int32_t* drow = to_br ? br_row : bt_row;
-    int32_t* dslot = to_br ? br_slot : bt_slot;
-    float* dval = to_br ? br_val : bt_val;
-    BrArgs b{pass == 0 ? islot : nullptr, srow, scol, sval, drow, dslot, dval, hist,
+    int32_t* drow = to_br ? bp.br_row : bp.bt_row;
+    int32_t* dslot = to_br ? bp.br_slot : bp.bt_slot;
+    float* dval = to_br ? bp.br_val : bp.bt_val;
+    BrArgs b{pass == 0 ? bp.islot : nullptr, srow, scol, sval, drow, dslot, dval, bp.hist,
              nullptr, nnz, ntiles, P, 8 * pass, nb};
-    if (pass == 0) b.slot_out = to_br ? bt_slot : br_slot;  // the buffer pass 0 does not write
+    if (pass == 0) b.slot_out = to_br ? bp.bt_slot : bp.br_slot;  // the buffer pass 0 does not write
     st = BrStep{};
     st.kind = kTaskBrHist;
     st.nblk = ntiles;
@@ -2875,8 +2963,8 @@ void br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp
     }
     st = BrStep{};
     st.kind = -1;
-    st.scan_in = hist;
-    st.scan_out = hist;
+    st.scan_in = bp.hist;
+    st.scan_out = bp.hist;
     st.scan_m = 256 * ntiles;
     f(st);
     st = BrStep{};
@@ -2892,20 +2980,13 @@ void br_steps(const int32_t* perm, int64_t p_slots, int64_t P, const int64_t* cp
 
 }  // namespace
 
-hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
-                                   const int64_t* cp, const int32_t* rr, const int32_t* rc,
-                                   const float* rv, int64_t nnz, int32_t* islot, int32_t* len_tmp,
-                                   int32_t* off32, int32_t* scan_tmp, int64_t* poff,
-                                   int32_t* br_row, int32_t* br_slot, float* br_val,
-                                   int32_t* bt_row, int32_t* bt_slot, float* bt_val,
-                                   int32_t* hist, hipStream_t s) {
-  if (P < 1 || p_slots < 1 || p_slots > p) return hipErrorInvalidValue;
-  if (p_slots < p)  // features outside the order keep slot -1
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(p, kBlock, 4096)), dim3(kBlock), 0, s, islot, -1,
-                       p);
+hipError_t launch_bundle_row_order(const BrPlan& bp, hipStream_t s) {
+  if (bp.P < 1 || bp.p_slots < 1 || bp.p_slots > bp.p) return hipErrorInvalidValue;
+  if (bp.p_slots < bp.p)  // features outside the order keep slot -1
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(bp.p, kBlock, 4096)), dim3(kBlock), 0, s,
+                       bp.islot, -1, bp.p);
   hipError_t err = hipSuccess;
-  br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32, poff, br_row, br_slot,
-           br_val, bt_row, bt_slot, bt_val, hist, [&](const BrStep& st) {
+  br_steps(bp, [&](const BrStep& st) {
     if (err != hipSuccess) return;
     hipError_t e = hipSuccess;
     switch (st.kind) {
@@ -2918,6 +2999,9 @@ hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slo
       case kTaskWiden:
         hipLaunchKernelGGL(k_widen, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.wd);
         break;
+      case kTaskPermute:
+        hipLaunchKernelGGL(k_permute, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.pm);
+        break;
       case kTaskBrHist:
         hipLaunchKernelGGL(k_br_hist, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s, st.br);
         break;
@@ -2925,7 +3009,7 @@ hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slo
         hipLaunchKernelGGL(k_br_scatter, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s, st.br);
         break;
       default:
-        e = launch_scan(st.scan_in, st.scan_out, st.scan_m, scan_tmp, s);
+        e = launch_scan(st.scan_in, st.scan_out, st.scan_m, bp.scan_tmp, s);
         break;
     }
     err = e;
@@ -2934,17 +3018,11 @@ hipError_t launch_bundle_row_order(const int32_t* perm, int64_t p, int64_t p_slo
   return hipGetLastError();
 }
 
-void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots, int64_t P,
-                      const int64_t* cp, const int32_t* rr, const int32_t* rc, const float* rv,
-                      int64_t nnz, int32_t* islot, int32_t* len_tmp, int32_t* off32,
-                      int32_t* scan_tmp, int64_t* poff, int32_t* br_row, int32_t* br_slot,
-                      float* br_val, int32_t* bt_row, int32_t* bt_slot, float* bt_val,
-                      int32_t* hist, std::vector<Task>& out) {
-  (void)p;  // every feature has a slot in an outer iteration's order (p_slots == p)
-  br_steps(perm, p_slots, P, cp, rr, rc, rv, nnz, islot, len_tmp, off32, poff, br_row, br_slot,
-           br_val, bt_row, bt_slot, bt_val, hist, [&](const BrStep& st) {
+void bundle_row_tasks(int loss, const BrPlan& bp, std::vector<Task>& out) {
+  // every feature has a slot in an outer iteration's order (p_slots == p)
+  br_steps(bp, [&](const BrStep& st) {
     if (st.kind < 0) {
-      scan_tasks(loss, st.scan_in, st.scan_out, st.scan_m, scan_tmp, out);
+      scan_tasks(loss, st.scan_in, st.scan_out, st.scan_m, bp.scan_tmp, out);
       return;
     }
     Task t = partition_task(st.kind, loss, st.nblk);
@@ -2952,6 +3030,7 @@ void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots,
       case kTaskIslot: t.u.is = st.is; break;
       case kTaskSlotLen: t.u.sl = st.sl; break;
       case kTaskWiden: t.u.wd = st.wd; break;
+      case kTaskPermute: t.u.pm = st.pm; break;
       default: t.u.br = st.br; break;
     }
     out.push_back(t);
@@ -2961,15 +3040,16 @@ void bundle_row_tasks(int loss, const int32_t* perm, int64_t p, int64_t p_slots,
 hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
                           const float* v, const Chunk* chunks, const int32_t* cstart,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
-                          int32_t* pri, float* pv, const double* w, double* pw, hipStream_t s) {
+                          int32_t* pri, float* pv, int32_t* pslot, const double* w, double* pw,
+                          hipStream_t s) {
   hipLaunchKernelGGL(k_slot_len, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s,
                      SlotLenArgs{perm, cp, p, len_tmp, w, pw});
   hipError_t e = launch_scan(len_tmp, off32, p, scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_widen, dim3(grid_for(p + 1, kBlock, 1 << 30)), dim3(kBlock), 0, s,
                      WidenArgs{off32, p, poff});
-  hipLaunchKernelGGL(k_permute, dim3(grid_for(p, kWavesPerBlock, 8192)), dim3(kBlock), 0, s, ri, v,
-                     cp, chunks, cstart, p, poff, pri, pv);
+  hipLaunchKernelGGL(k_permute, dim3(permute_grid(p)), dim3(kBlock), 0, s,
+                     PermuteArgs{ri, v, cp, chunks, cstart, p, poff, pri, pv, pslot});
   return hipGetLastError();
 }
 

@@ -207,6 +207,7 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->part = k.take<double2>(t->part_len);
   t->pri = k.take<int32_t>(nnz);
   t->pv = k.take<float>(nnz);
+  t->pslot = k.take<int32_t>(nnz);
   t->poff = k.take<int64_t>(p + 1);
   t->pw = k.take<double>(p);
   t->off32 = k.take<int32_t>(p + 1);

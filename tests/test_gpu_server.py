@@ -54,6 +54,8 @@ def _staggered(pc, srv, reqs, seed):
                 r = srv.take(rid)
                 if r is not None:
                     results[i] = r
+                    if r[0] < 0:
+                        print(f"request {i} failed: {srv.last_error()}", flush=True)
         assert steps < 5000
     return results
 
