@@ -263,6 +263,7 @@ RowsArgs rows_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, 
   r.d = c->d;
   r.dterm = c->dterm;
   r.w = c->w;
+  r.pw = c->pw;
   r.perm = perm;
   r.cache = c->cache;
   r.rw = c->rw;

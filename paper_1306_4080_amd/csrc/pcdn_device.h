@@ -171,6 +171,8 @@ struct RowsArgs {
   const double* d;           // per-slot outputs of the sweep
   const double* dterm;
   double* w;
+  const double* pw;          // w in partition order: w[perm[slot]] for this bundle's slots
+                             // until its apply (only that apply changes them)
   const int32_t* perm;       // slot -> feature
   double* cache;
   double2* rw;               // per-row term weights, kept with cache

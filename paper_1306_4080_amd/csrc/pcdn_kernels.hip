@@ -1177,6 +1177,16 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   const int64_t nwaves = (int64_t)G * kWavesPerBlock;
   RowQueue& qu = queue[wv];
+  // the regulariser terms' operands of this thread's first slot, loaded now
+  // (they depend on nothing the row sums compute; w from its copy in
+  // partition order, which no apply has changed for this bundle's slots)
+  const int64_t Pt = hi_act - a.slot_lo;
+  const int64_t r0 = (int64_t)bx * kBlock + threadIdx.x;
+  const bool has0 = r0 < Pt;
+  const double wj0 = ldz(a.pw, has0, a.slot_lo + r0, 0.0);
+  const double dj0 = ldz(a.d, has0, a.slot_lo + r0, 0.0);
+  const double dt0 = ldz(a.dterm, has0, a.slot_lo + r0, 0.0);
+  asm volatile("" ::"v"(wj0), "v"(dj0), "v"(dt0));
   double acc[kQGroup], aabs[kQGroup];
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = aabs[q] = 0.0;
@@ -1319,12 +1329,12 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   double del = 0.0;
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = aabs[q] = 0.0;
-  const int64_t Pt = hi_act - a.slot_lo;
-  for (int64_t r = (int64_t)bx * kBlock + threadIdx.x; r < Pt; r += (int64_t)G * kBlock) {
+  for (int64_t r = r0; r < Pt; r += (int64_t)G * kBlock) {
     const int64_t slot = a.slot_lo + r;
-    const double wj = a.w[a.perm[slot]];
-    const double dj = a.d[slot];
-    del += a.dterm[slot];
+    const bool pre = r == r0;
+    const double wj = pre ? wj0 : a.pw[slot];
+    const double dj = pre ? dj0 : a.d[slot];
+    del += pre ? dt0 : a.dterm[slot];
     double al = 1.0;
 #pragma unroll
     for (int q = 0; q < kQGroup; ++q) {
@@ -1377,14 +1387,23 @@ __device__ inline double ls_total(const double* part, int v, int G, double* lds4
 }
 
 // ls_total of N partial rows at once: the same sums in the same order (so
-// the same bits), with the rows' loads issued together.
+// the same bits), with the rows' loads issued together.  ls_load issues this
+// thread's first loads (so that other loads can be issued behind them);
+// ls_finish adds the rest and reduces.
 template <int N>
-__device__ inline void ls_totals(const double* part, const int (&v)[N], int G, double (&out)[N],
-                                 double (*lds)[kWavesPerBlock]) {
-  double x[N];
+__device__ inline void ls_load(const double* part, const int (&v)[N], int G, double (&x)[N]) {
+  const int b = threadIdx.x;
+  double y[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) x[k] = 0.0;
-  for (int b = threadIdx.x; b < G; b += kBlock) {
+  for (int k = 0; k < N; ++k) y[k] = ldz(part, b < G, (int64_t)v[k] * G + b, 0.0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) x[k] = 0.0 + y[k];
+}
+
+template <int N>
+__device__ inline void ls_finish(const double* part, const int (&v)[N], int G, double (&x)[N],
+                                 double (&out)[N], double (*lds)[kWavesPerBlock]) {
+  for (int b = threadIdx.x + kBlock; b < G; b += kBlock) {
     double y[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) y[k] = part[(int64_t)v[k] * G + b];
@@ -1400,6 +1419,14 @@ __device__ inline void ls_totals(const double* part, const int (&v)[N], int G, d
 #pragma unroll
   for (int k = 0; k < N; ++k) out[k] = ((lds[k][0] + lds[k][1]) + lds[k][2]) + lds[k][3];
   __syncthreads();
+}
+
+template <int N>
+__device__ inline void ls_totals(const double* part, const int (&v)[N], int G, double (&out)[N],
+                                 double (*lds)[kWavesPerBlock]) {
+  double x[N];
+  ls_load(part, v, G, x);
+  ls_finish(part, v, G, x, out, lds);
 }
 
 // Candidates q >= kQGroup (none of the first group passed: rare), in one
@@ -1428,7 +1455,7 @@ __device__ inline int rows_more_candidates(const RowsArgs& a, int64_t nr, int64_
     }
     double l1 = 0.0, l1a = 0.0;
     for (int64_t slot = a.slot_lo + threadIdx.x; slot < hi_act; slot += kBlock) {
-      const double wj = a.w[a.perm[slot]], sj = al * a.d[slot];
+      const double wj = a.pw[slot], sj = al * a.d[slot];
       const double rc = reg_change(wj, sj, a.ra, a.rb);
       l1 += rc;
       l1a += reg_change_scale(wj, sj, a.ra, a.rb);
@@ -1456,6 +1483,14 @@ __device__ inline int rows_more_candidates(const RowsArgs& a, int64_t nr, int64_
 // candidate of the first group passes, block 0 alone tests the later ones
 // and applies the step.
 template <int LOSS>
+__device__ inline void apply_row(const RowsArgs& a, int32_t row, double s, double c, int yi,
+                                 int q_acc) {
+  for (int t = 0; t < q_acc; ++t) s *= a.beta;
+  store_retained<LOSS>(&a.cache[row], &a.rw[row],
+                       LOSS == kLogistic ? c * exp(s) : c - (yi > 0 ? s : -s), yi, a.stats);
+}
+
+template <int LOSS>
 __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
   __shared__ double lds7[7][kWavesPerBlock];
@@ -1463,11 +1498,46 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   if (hi_act <= a.slot_lo) return;  // no active feature in this bundle: nothing ran
   const double C = *a.Cp;
   const int nq = a.Q < kQGroup ? a.Q : kQGroup;
+  constexpr int kR = kRangeW / kWave;
+  const int lane = lane_id();
   // Delta, candidate 0's sums and scales, touched rows and nonzeros with
-  // d_j != 0, in one pass over the partials
+  // d_j != 0, in one pass over the partials.  Issued with them, before the
+  // decision waits for them (the update's operands depend only on what the
+  // d^T x launch wrote): the bundle's nonzero range, this thread's first slot
+  // of the w update (w from its copy in partition order), then the
+  // wavefront's first listed range (count, rows and d^T x, then the rows'
+  // retained quantities and labels).
   const int first[7] = {2 * a.Q, 0, a.Q, 2 * a.Q + 3, 3 * a.Q + 3, 2 * a.Q + 1, 2 * a.Q + 2};
+  double x7[7];
+  ls_load(a.part, first, a.G, x7);
+  const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
+  const int64_t sl0 = a.slot_lo + bid * kBlock + threadIdx.x;
+  const bool own0 = sl0 < hi_act;
+  const int32_t f0 = ldz(a.perm, own0, sl0, 0);
+  const double d0 = ldz(a.d, own0, sl0, 0.0);
+  const double w0 = ldz(a.pw, own0, sl0, 0.0);
+  const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
+  const int64_t gwave = (bid * kBlock + threadIdx.x) / kWave;
+  const int32_t cnt0 = ldz(a.u_cnt, gwave < nr, gwave, 0);
+  int32_t row0[kR];
+  double sv0[kR], c0[kR];
+  int y0[kR];
+#pragma unroll
+  for (int u = 0; u < kR; ++u) {
+    const int32_t i = lane + u * kWave;
+    row0[u] = ldz(a.u_row, i < cnt0, gwave * kRangeW + i, -1);
+    sv0[u] = ldz(a.u_dtx, i < cnt0, gwave * kRangeW + i, 0.0);
+  }
+#pragma unroll
+  for (int u = 0; u < kR; ++u) {
+    c0[u] = ldz(a.cache, row0[u] >= 0, row0[u], 0.0);
+    y0[u] = (int)ldz(a.y, row0[u] >= 0, row0[u], (int8_t)0);
+  }
+  asm volatile("" ::"v"(f0), "v"(d0), "v"(w0));
+#pragma unroll
+  for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(sv0[u]), "v"(c0[u]), "v"(y0[u]));
   double tot[7];
-  ls_totals(a.part, first, a.G, tot, lds7);
+  ls_finish(a.part, first, a.G, x7, tot, lds7);
   const double Delta = tot[0];
   double Dq = Delta, al = 1.0, dF = 0.0, margin = INFINITY;
   int q_acc = -1;
@@ -1490,8 +1560,6 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   }
   const double touched = tot[5];
   const double nz_d = tot[6];
-  const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
-  const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   bool alone = false;
   if (q_acc < 0 && a.Q > nq) {
     if (bid != 0) return;
@@ -1511,13 +1579,18 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
     atomicMin(&a.stats->min_margin_bits, (unsigned long long)__double_as_longlong(margin));
   }
   if (q_acc < 0) return;
-  const int lane = lane_id();
-  const int64_t wave = alone ? wave_in_block() : (bid * kBlock + threadIdx.x) / kWave;
+  // w_B += alpha d_B and the listed rows' retained quantities; block 0 alone
+  // when it tested the later candidates (the loaded operands then go unused)
+  const int64_t wave = alone ? wave_in_block() : gwave;
   const int64_t nwaves = alone ? kWavesPerBlock : nblk * kWavesPerBlock;
-  // a range lists at most kRangeW rows: kR per lane, their loads issued
-  // together
-  constexpr int kR = kRangeW / kWave;
-  for (int64_t r = wave; r < nr; r += nwaves) {
+  int64_t r = wave;
+  if (!alone && r < nr) {
+#pragma unroll
+    for (int u = 0; u < kR; ++u)
+      if (row0[u] >= 0) apply_row<LOSS>(a, row0[u], sv0[u], c0[u], y0[u], q_acc);
+    r += nwaves;
+  }
+  for (; r < nr; r += nwaves) {
     const int32_t cnt = a.u_cnt[r];
     int32_t row[kR];
     double s[kR], c[kR];
@@ -1536,18 +1609,17 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
 #pragma unroll
     for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(s[u]), "v"(c[u]), "v"(yi[u]));
 #pragma unroll
-    for (int u = 0; u < kR; ++u) {
-      if (row[u] < 0) continue;
-      double sv = s[u];
-      for (int t = 0; t < q_acc; ++t) sv *= a.beta;
-      store_retained<LOSS>(&a.cache[row[u]], &a.rw[row[u]],
-                           LOSS == kLogistic ? c[u] * exp(sv) : c[u] - (yi[u] > 0 ? sv : -sv),
-                           yi[u], a.stats);
-    }
+    for (int u = 0; u < kR; ++u)
+      if (row[u] >= 0) apply_row<LOSS>(a, row[u], s[u], c[u], yi[u], q_acc);
   }
   const int64_t tid = alone ? threadIdx.x : bid * kBlock + threadIdx.x;
   const int64_t nthr = alone ? kBlock : nblk * kBlock;
-  for (int64_t r = a.slot_lo + tid; r < hi_act; r += nthr) a.w[a.perm[r]] += al * a.d[r];
+  int64_t sl = a.slot_lo + tid;
+  if (!alone && own0) {
+    a.w[f0] = w0 + al * d0;
+    sl += nthr;
+  }
+  for (; sl < hi_act; sl += nthr) a.w[a.perm[sl]] = a.pw[sl] + al * a.d[sl];
 }
 
 template <int LOSS>
