@@ -1758,6 +1758,94 @@ __global__ __launch_bounds__(kSortThreads) void k_br_scatter(BrArgs a) {
   br_scatter_body(a, blockIdx.x);
 }
 
+// The scatter pass of a standalone launch, with the tile staged in LDS: each
+// nonzero is ranked as in br_scatter_body, but placed at its position in the
+// tile's digit-sorted order in LDS, which is then stored in that order, so
+// that consecutive threads store consecutive addresses of a digit's run (the
+// stores straight from the ranking rounds put a few nonzeros per digit and
+// round).  The positions are the same, so the output is too.  (The executor
+// keeps br_scatter_body: its LDS is shared by every task body.)
+__global__ __launch_bounds__(kSortThreads) void k_br_scatter_staged(BrArgs a) {
+  __shared__ int32_t gbase[256];  // output position of the tile's first nonzero of each digit
+  __shared__ int32_t lbase[256];  // the same inside the tile's sorted order
+  __shared__ int32_t run_off[256];
+  __shared__ int32_t wcnt[kWavesPerBlock][256];
+  __shared__ int32_t lds_scan[kSortThreads / kWave + 1];
+  __shared__ int32_t s_row[kBrTile], s_slot[kBrTile];
+  __shared__ float s_val[kBrTile];
+  const int64_t bid = blockIdx.x;
+  const int lane = lane_id(), wv = wave_in_block();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile = bid * kBrTile;
+  const int32_t tcount = (int32_t)(a.m - tile < kBrTile ? a.m - tile : kBrTile);
+  gbase[threadIdx.x] = a.hist[(int64_t)threadIdx.x * a.ntiles + bid];
+  wcnt[0][threadIdx.x] = 0;
+  int32_t rrow[kBrRounds], rslot[kBrRounds];
+  float rval[kBrRounds];
+  uint32_t dig[kBrRounds];
+#pragma unroll
+  for (int r = 0; r < kBrRounds; ++r) {
+    const int64_t i = tile + r * kSortThreads + threadIdx.x;
+    const bool valid = i < a.m;
+    rrow[r] = ldz(a.srow, valid, i, 0);
+    rslot[r] = ldz(a.scol, valid, i, 0);
+    rval[r] = ldz(a.sval, valid, i, 0.0f);
+  }
+  __syncthreads();
+  // the tile's digit counts, then their exclusive scan
+#pragma unroll
+  for (int r = 0; r < kBrRounds; ++r) {
+    const bool valid = r * kSortThreads + (int)threadIdx.x < tcount;
+    dig[r] = valid ? br_digit_of(a, rslot[r]) : 0u;
+    if (valid) atomicAdd(&wcnt[0][dig[r]], 1);
+  }
+  __syncthreads();
+  int32_t total;
+  const int32_t lb = block_exclusive_scan<kSortThreads>(wcnt[0][threadIdx.x], lds_scan, &total);
+  lbase[threadIdx.x] = lb;
+  run_off[threadIdx.x] = lb;
+#pragma unroll
+  for (int r = 0; r < kBrRounds; ++r) {
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const bool valid = r * kSortThreads + (int)threadIdx.x < tcount;
+    const uint32_t d = dig[r];
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const int rank = __popcll(peers & lt_mask);
+    const bool leader = valid && ((peers & lt_mask) == 0);
+    if (leader) wcnt[wv][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int32_t pos = run_off[d] + rank;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w][d];
+      s_row[pos] = rrow[r];
+      s_slot[pos] = rslot[r];
+      s_val[pos] = rval[r];
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][threadIdx.x];
+    run_off[threadIdx.x] += add;
+  }
+  __syncthreads();
+  for (int32_t e = threadIdx.x; e < tcount; e += kSortThreads) {
+    const int32_t sl = s_slot[e];
+    const uint32_t d = br_digit_of(a, sl);
+    const int64_t g = (int64_t)gbase[d] + (e - lbase[d]);
+    a.drow[g] = s_row[e];
+    a.dslot[g] = sl;
+    a.dval[g] = s_val[e];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Single-workgroup schedule: one 512-thread workgroup runs every bundle of an
 // outer iteration of one problem, phase after phase, with workgroup barriers
@@ -3078,7 +3166,8 @@ hipError_t launch_bundle_row_order(const BrPlan& bp, hipStream_t s) {
         hipLaunchKernelGGL(k_br_hist, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s, st.br);
         break;
       case kTaskBrScatter:
-        hipLaunchKernelGGL(k_br_scatter, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s, st.br);
+        hipLaunchKernelGGL(k_br_scatter_staged, dim3((unsigned)st.nblk), dim3(kSortThreads), 0, s,
+                           st.br);
         break;
       default:
         e = launch_scan(st.scan_in, st.scan_out, st.scan_m, bp.scan_tmp, s);
