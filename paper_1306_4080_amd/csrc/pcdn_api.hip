@@ -64,7 +64,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->w); dfree(c->cache); dfree(c->rw); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
   dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
-  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->cstart); dfree(c->chunks);
+  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->rfirst); dfree(c->psrc);
   dfree(c->step_perm);
   dfree(c->ccol); dfree(c->rr); dfree(c->islot); dfree(c->br_row); dfree(c->br_slot); dfree(c->br_val);
   dfree(c->bt_row); dfree(c->bt_slot); dfree(c->bt_val); dfree(c->br_hist);
@@ -209,15 +209,13 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   return a;
 }
 
-// Inner iteration of Algorithm 3 on slots [lo, hi) of `perm` whose chunk
-// descriptors are c->chunks / c->cstart, first half: sweep (g, h, d, fused
-// d^T x) and split columns.
+// Inner iteration of Algorithm 3 on slots [lo, hi) of the order X was copied
+// into, first half: the sweep over the bundle's nonzeros (g_j, h_j partials
+// per range) and its finish per slot (d_j and the Delta terms).
 // clip: the bundle is one of an outer iteration with shrinking (its slots
 // are clipped to the active count on the device)
 SweepArgs bundle_sweep_args(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) {
   SweepArgs a = sweep_args(c, o);
-  a.chunks = c->chunks;
-  a.cstart = c->cstart;
   a.poff = c->poff;
   a.pri = c->pri;
   a.pv = c->pv;
@@ -308,7 +306,7 @@ int run_bundle(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, int6
 }
 
 // The bundle-row order and X in partition order for bundles of P over the
-// order perm (p_slots slots; chunk descriptors of that order in c->chunks).
+// order perm (p_slots slots).
 BrPlan br_plan(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
   BrPlan b{};
   b.perm = perm;
@@ -322,8 +320,8 @@ BrPlan br_plan(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
   b.nnz = c->nnz;
   b.ri = c->ri;
   b.v = c->v;
-  b.chunks = c->chunks;
-  b.cstart = c->cstart;
+  b.psrc = c->psrc;
+  b.rfirst = c->rfirst;
   b.w = c->w;
   b.islot = c->islot;
   b.len_tmp = c->nch;
@@ -553,9 +551,8 @@ bool use_bundle_rows(const pcdn_ctx* c, int64_t P, int64_t p_slots) {
   return words <= kRowsMaxWords && (double)words * (double)bundles <= (double)(1 << 27);
 }
 
-// Bundles [t_begin, t_end) of size P over the order `perm` (descriptors in
-// c->chunks / c->cstart, p_slots slots) in one workgroup, after copying X into
-// that order.
+// Bundles [t_begin, t_end) of size P over the order `perm` (p_slots slots)
+// in one workgroup, after copying X into that order.
 NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t p_slots,
                             int64_t P, int64_t t_begin, int64_t t_end, double* dtx_copy) {
   NarrowArgs na{};
@@ -590,11 +587,10 @@ NarrowArgs make_narrow_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int
   return na;
 }
 
-// Copy X into the order `perm` (descriptors in c->chunks / c->cstart).
 // Copy X into the order `perm` for bundles of P, with the bundles'
 // local row ids where the single-workgroup kernel can use them.
 int permute_x(pcdn_ctx* c, const int32_t* perm, int64_t p_slots, int64_t P) {
-  HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->ri, c->v, c->chunks, c->cstart, c->nch,
+  HIPCHK(c, launch_permute(perm, c->cp, p_slots, c->nnz, c->ri, c->v, c->psrc, c->rfirst, c->nch,
                            c->off32, c->scan_tmp, c->poff, c->pri, c->pv, c->pslot, c->w, c->pw,
                            c->stream));
   if (use_bundle_rows(c, P, p_slots))
@@ -615,15 +611,13 @@ int launch_narrow_bundles(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64
 // One outer iteration k of Algorithm 3: partition, every bundle, then the
 // stopping sweep (result in c->scal[0]).  it != null: k is read from and
 // advanced on the device (graph replays).
-// The outer iteration in three parts.  Before the bundles: partition,
-// chunk descriptors, and (single-workgroup schedule) X in partition order;
+// The outer iteration in three parts.  Before the bundles: partition and X
+// in partition order (with the bundle-row order on the multi-kernel path);
 // heavy_list: also the list of heavy bundles, for the batch engine.
 int enqueue_pre(pcdn_ctx* c, const Opts& o, int64_t P, int64_t k, IterState* it,
                 bool heavy_list) {
   int rc = device_permutation(c, o.seed, k, it, o.shrink ? c->act : nullptr);
   if (rc) return rc;
-  HIPCHK(c, launch_chunks(c->idx0, c->cp, c->p, o.chunk, c->nch, c->cstart, c->chunks,
-                          c->scan_tmp, c->stream));
   if (!use_narrow(c, o, P)) return build_bundle_rows(c, c->idx0, c->p, P);
   rc = permute_x(c, c->idx0, c->p, P);
   if (rc) return rc;
@@ -714,8 +708,7 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   out.clear();
   // the partition (enqueue_pre of the multi-kernel schedule)
   partition_tasks(c->loss, c->iter, o.seed, c->p, o.shrink ? c->act : nullptr, c->keys0, c->idx0,
-                  c->keys1, c->idx1, c->hist, c->scan_tmp, c->cp, o.chunk, c->nch, c->cstart,
-                  c->chunks, out);
+                  c->keys1, c->idx1, c->hist, c->scan_tmp, out);
   auto task = [&](int kind, int nblk, int gx) {
     Task t;
     std::memset(&t, 0, sizeof(t));
@@ -1150,7 +1143,7 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       8 * p, 8 * p, 8 * p, 8 * p,                          // g, h, d, Delta terms
       4 * p, 4 * p, 4 * p, 4 * p, 4 * hist_m,              // sort keys and payloads, histogram
       4 * (std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1),
-      4 * p, 4 * (p + 1), 32 * max_chunks,                 // chunk descriptors of the order
+      4 * p, 4 * (nnz / kPermW + 2), 8 * p,                // copy into partition order
       4 * p,                                               // step bundle
       16 * part_len, 4 * nnz, 4 * nnz, 4 * nnz, 8 * (p + 1), 4 * (p + 1),  // partials, X in partition order
       8 * p,                                               // w in partition order
@@ -1262,8 +1255,8 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->scan_tmp,
         std::max(std::max(scan_tmp_ints(hist_m), scan_tmp_ints(p)), scan_tmp_ints(br_m)) + 1);
   ALLOC(c, c->nch, p);
-  ALLOC(c, c->cstart, p + 1);
-  ALLOC(c, c->chunks, max_chunks);
+  ALLOC(c, c->rfirst, nnz / kPermW + 2);
+  ALLOC(c, c->psrc, p);
   ALLOC(c, c->step_perm, p);
   c->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
   ALLOC(c, c->part, c->part_len);
@@ -1409,8 +1402,6 @@ extern "C" int pcdn_step(pcdn_ctx* c, const int32_t* bundle, int64_t P, const pc
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipMemcpyAsync(c->step_perm, bundle, P * sizeof(int32_t), hipMemcpyHostToDevice,
                            c->stream));
-  HIPCHK(c, launch_chunks(c->step_perm, c->cp, P, o.chunk, c->nch, c->cstart, c->chunks,
-                          c->scan_tmp, c->stream));
   // run the bundle; keep d^T x before it is cleared
   const bool narrow = use_narrow(c, o, P);
   if (narrow) {

@@ -6,11 +6,12 @@
 //             (the single-workgroup kernel's fixed-point d^T x when a bundle
 //             has too many rows for LDS; all zero between inner iterations)
 //   bundle  : perm int32[p] (slot -> feature), per-slot g, h, d, dterm fp64
-//   chunks  : every feature owns ceil(nnz_j / kChunk) >= 1 work chunks.  For
-//             the slot order of one outer iteration, Chunk descriptors list
-//             them slot after slot (cstart int32[p+1] = first chunk of each
-//             slot), so a wavefront takes one chunk regardless of column length
-//             and reaches its nonzeros through one descriptor load.
+//   order   : per outer iteration, X copied into partition order (pri, pv,
+//             pslot: the nonzeros of slot r at [poff[r], poff[r+1])), built
+//             by kPermW-position ranges of the output: rfirst int32[] = the
+//             slot holding each range's first position, psrc int64[p] = the
+//             first nonzero of each slot's column; and the same nonzeros in
+//             bundle-row order (grouped by bundle, rows ascending).
 //
 // Synchronisation model: on gfx950 a device-scope fence or grid barrier costs
 // far more than a kernel boundary, so every global dependency of the bundle
@@ -34,16 +35,6 @@ constexpr int kQGroup = 4;     // candidates per line-search thread (grid y cove
 constexpr int kSumGrid = 256;  // blocks of the first reduction level
 constexpr int kLogistic = 0;
 constexpr int kL2Svm = 1;
-
-struct Chunk {
-  int64_t klo;   // first nonzero of the chunk
-  int32_t len;   // nonzeros in the chunk (0 for an empty column)
-  int32_t slot;  // slot of the feature in the order
-  int32_t c0;    // first chunk of the feature
-  int32_t nch;   // chunks of the feature
-  int32_t feat;  // feature index
-  int32_t pad;
-};
 
 // Cumulative device-side counters (read back by the host at sync points).
 // Data-dependent counters, updated by one thread per block (never per
@@ -95,8 +86,6 @@ struct SweepArgs {
   const double* cache;
   const double2* rw;          // per-row term weights (row_weights of cache and y)
   const double* w;
-  const Chunk* chunks;        // chunk descriptors of the order
-  const int32_t* cstart;      // slot -> first chunk, p+1 entries
   // X in partition order (bundle sweep): the nonzeros of slot r are
   // pri/pv/pslot[poff[r] .. poff[r+1]), pslot holding r; pw[r] = w[perm[r]]
   const int64_t* poff;
@@ -219,22 +208,24 @@ struct SlotLenArgs {         // column length (and w) in slot order
   int32_t* len;
   const double* w;           // nullable: no copy of w
   double* pw;
+  int64_t* src;              // nullable: first nonzero of the slot's column (cp[perm[r]])
 };
+constexpr int kPermW = 256;  // output positions per wavefront of the copy into partition order
 struct WidenArgs {
   const int32_t* in;
   int64_t m;
   int64_t* out;
+  int32_t* rfirst;           // nullable: slot of each kPermW-range's first position
 };
-// X copied into partition order (one wavefront per chunk of the order):
-// pri/pv[poff[slot] + e] and, if pslot is not null, pslot = the slot.
+// X copied into partition order: pri/pv[poff[slot] + e] = nonzero e of the
+// slot's column and, if pslot is not null, pslot = the slot.
 struct PermuteArgs {
   const int32_t* ri;
   const float* v;
-  const int64_t* cp;
-  const Chunk* chunks;
-  const int32_t* cstart;
+  const int64_t* src;        // slot -> first nonzero of its column
+  const int64_t* poff;       // slot -> first output position (p + 1 entries)
+  const int32_t* rfirst;     // range -> slot holding its first position
   int64_t p;                 // slots
-  const int64_t* poff;
   int32_t* pri;
   float* pv;
   int32_t* pslot;
@@ -273,8 +264,8 @@ struct SumArgs {
   int32_t nb;                // blocks of the first level
 };
 
-// Partition kernels as executor tasks (the launches of launch_perm_keys,
-// launch_radix_sort and launch_chunks, one task per launch).
+// Partition kernels as executor tasks (the launches of launch_perm_keys and
+// launch_radix_sort, one task per launch).
 struct PermKeysArgs {
   const IterState* it;
   uint64_t seed;
@@ -298,15 +289,6 @@ struct ScanArgs {           // exclusive scan of in[0..m) into out (out[m] = tot
   int32_t* tmp;             // block totals
   int64_t m, nb;
 };
-struct ChunkArgs {
-  const int32_t* perm;
-  const int64_t* cp;
-  const int32_t* cstart;
-  int32_t* nch;
-  Chunk* chunks;
-  int64_t p;
-  int32_t chunk;
-};
 
 // One kernel invocation of one problem, as run by the multi-problem
 // executor: the kernel, its arguments, and the grid a launch of its own
@@ -329,8 +311,6 @@ enum TaskKind : int32_t {
   kTaskScanBlocks,
   kTaskScanTotals,
   kTaskScanAdd,
-  kTaskChunkCount,
-  kTaskChunkFill,
   kTaskSlotLen,
   kTaskWiden,
   kTaskIslot,
@@ -357,7 +337,6 @@ struct Task {
     PermKeysArgs pk;
     RadixArgs rx;
     ScanArgs scan;
-    ChunkArgs ch;
   } u;
 };
 
@@ -438,12 +417,6 @@ int64_t scan_tmp_ints(int64_t m);
 int64_t radix_hist_ints(int64_t p);
 // Exclusive scan of in[0..m) into out[0..m], out[m] = total (int32).
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s);
-// Chunk descriptors for a slot order (perm null: identity): every column is
-// cut into ceil(len / chunk) >= 1 pieces of at most `chunk` nonzeros
-// (kChunkMin <= chunk).
-hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
-                         int32_t* nch, int32_t* cstart, Chunk* chunks, int32_t* tmp,
-                         hipStream_t s);
 // The bundle sweep (X in partition order, ranges of kSweepW nonzeros) and
 // its finish over the bundle's slots, with the grids they take for a bundle
 // of `slots` slots and about `nnz_bundle` nonzeros.
@@ -469,8 +442,9 @@ hipError_t launch_rows_apply(int loss, const RowsArgs& a, hipStream_t s);
 // working storage (br_hist_ints(nnz) and scan_tmp_ints of it).
 int br_passes(int64_t p_slots, int64_t P);
 int64_t br_hist_ints(int64_t nnz);
-// The same pass also copies X into partition order (pri, pv, pslot at poff,
-// from the chunk descriptors of the order) and w into slot order (pw).
+// The same pass also copies X into partition order (pri, pv, pslot at poff;
+// psrc and rfirst as working storage, p and nnz / kPermW + 1 entries) and w
+// into slot order (pw).
 struct BrPlan {
   const int32_t* perm;
   int64_t p, p_slots, P;
@@ -481,8 +455,8 @@ struct BrPlan {
   int64_t nnz;
   const int32_t* ri;     // X as loaded (CSC)
   const float* v;
-  const Chunk* chunks;   // chunk descriptors of the order
-  const int32_t* cstart;
+  int64_t* psrc;
+  int32_t* rfirst;
   const double* w;
   int32_t* islot;
   int32_t* len_tmp;
@@ -508,13 +482,12 @@ void bundle_row_tasks(int loss, const BrPlan& b, std::vector<Task>& out);
 // the bundle [a.slot_lo, a.slot_hi) (dense must be zero elsewhere).
 hipError_t launch_rows_scatter(const RowsArgs& a, double* dense, hipStream_t s);
 hipError_t launch_narrow(int loss, const NarrowArgs& a, hipStream_t s);
-// The partition of one outer iteration (launch_perm_keys, launch_radix_sort
-// and launch_chunks on the same buffers) as executor tasks, appended to out;
-// the same permutation and chunk descriptors as those launches.
+// The partition of one outer iteration (launch_perm_keys and
+// launch_radix_sort on the same buffers) as executor tasks, appended to out;
+// the same permutation as those launches.
 void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, const double* act,
                      uint32_t* keys0, int32_t* idx0, uint32_t* keys1, int32_t* idx1,
-                     int32_t* hist, int32_t* scan_tmp, const int64_t* cp, int32_t chunk,
-                     int32_t* nch, int32_t* cstart, Chunk* chunks, std::vector<Task>& out);
+                     int32_t* hist, int32_t* scan_tmp, std::vector<Task>& out);
 // Every task of tasks[0..count) in one launch of `blocks` blocks: task i
 // takes blocks [first[i], first[i+1]) (first[count] = blocks).
 hipError_t launch_exec(const Task* tasks, const int32_t* first, int count, int blocks,
@@ -525,10 +498,11 @@ hipError_t launch_gather(const double* const* src, double* dst, int count, hipSt
 // with its own loss).
 hipError_t launch_narrow_multi(const NarrowArgs* tab, int count, hipStream_t s);
 // X in partition order for the single-workgroup schedule (needs nnz < 2^31),
-// and w in the same slot order (pw).  `chunks`/`cstart` are the chunk
-// descriptors of the same slot order.
-hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
-                          const float* v, const Chunk* chunks, const int32_t* cstart,
+// and w in the same slot order (pw), over the first p slots of perm (their
+// columns hold at most nnz nonzeros); psrc (p) and rfirst (nnz / kPermW + 1)
+// are working storage.
+hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, int64_t nnz,
+                          const int32_t* ri, const float* v, int64_t* psrc, int32_t* rfirst,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, int32_t* pslot, const double* w, double* pw,
                           hipStream_t s);

@@ -34,7 +34,6 @@ hipError_t dalloc(T** p, size_t count) {
 }  // namespace host
 }  // namespace pcdn
 
-using pcdn::Chunk;
 using pcdn::IterState;
 using pcdn::Stats;
 using pcdn::StepState;
@@ -81,8 +80,8 @@ struct pcdn_ctx {
   int32_t* hist = nullptr;
   int32_t* scan_tmp = nullptr;
   int32_t* nch = nullptr;
-  int32_t* cstart = nullptr;
-  Chunk* chunks = nullptr;
+  int32_t* rfirst = nullptr;     // copy into partition order: slot of each range's first position
+  int64_t* psrc = nullptr;       // first nonzero of each slot's column
   int32_t* step_perm = nullptr;
   int64_t max_chunks = 0;
   double2* part = nullptr;

@@ -580,56 +580,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 }
 
 // ---------------------------------------------------------------------------
-// chunk bookkeeping: nch = chunks per slot, cstart = exclusive scan, then one
-// descriptor per chunk
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void chunk_count_body(const int32_t* perm, const int64_t* cp,
-                                                 int64_t p, int32_t chunk, int32_t* nch,
-                                                 int64_t bid) {
-  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
-  if (r < p) {
-    const int32_t j = perm ? perm[r] : (int32_t)r;
-    const int64_t len = cp[j + 1] - cp[j];
-    const int64_t c = (len + chunk - 1) / chunk;
-    nch[r] = (int32_t)(c > 0 ? c : 1);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_chunk_count(const int32_t* perm, const int64_t* cp,
-                                                        int64_t p, int32_t chunk, int32_t* nch) {
-  chunk_count_body(perm, cp, p, chunk, nch, blockIdx.x);
-}
-
-__device__ __forceinline__ void chunk_fill_body(const int32_t* perm, const int64_t* cp,
-                                                const int32_t* cstart, int64_t p, int32_t chunk,
-                                                Chunk* chunks, int64_t bid) {
-  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
-  if (r < p) {
-    const int32_t j = perm ? perm[r] : (int32_t)r;
-    const int64_t k0 = cp[j], len = cp[j + 1] - k0;
-    const int32_t c0 = cstart[r], nch = cstart[r + 1] - c0;
-    for (int32_t q = 0; q < nch; ++q) {
-      Chunk ch;
-      ch.klo = k0 + (int64_t)q * chunk;
-      const int64_t rem = len - (int64_t)q * chunk;
-      ch.len = (int32_t)(rem < chunk ? (rem > 0 ? rem : 0) : chunk);
-      ch.slot = (int32_t)r;
-      ch.c0 = c0;
-      ch.nch = nch;
-      ch.feat = j;
-      ch.pad = 0;
-      chunks[c0 + q] = ch;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_chunk_fill(const int32_t* perm, const int64_t* cp,
-                                                       const int32_t* cstart, int64_t p,
-                                                       int32_t chunk, Chunk* chunks) {
-  chunk_fill_body(perm, cp, cstart, p, chunk, chunks, blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
 // gradient / Hessian sweep of a bundle (eq. (11); SVM: eq. (3) and the
 // generalised Hessian), the direction (eq. (5)) and its Delta term (eq. (7)),
 // over the bundle's nonzeros in partition order (one contiguous range, the
@@ -2520,19 +2470,95 @@ __global__ __launch_bounds__(kNarrowBlock) void k_narrow_multi(const NarrowArgs*
 }
 
 // Copy X into partition order: the nonzeros of slot r land at
-// [poff[r], poff[r+1]) (one wavefront per chunk descriptor).
+// [poff[r], poff[r+1]).  A wavefront takes kPermW consecutive output
+// positions, lane L the positions 4L .. 4L+3.  The slots that cover them
+// are read 64 at a time, from rfirst[range] on (their output offsets and the
+// first nonzero of their columns, one slot per lane); a position finds its
+// slot by a binary search over the 64 slots' ends (exchanged by lane
+// shuffles), gathers its row index and value from the column, and stores
+// them with its slot, so the stores are contiguous and every lane has
+// nonzeros to move however short the columns are.
+constexpr int kPermE = kPermW / kWave;
+
+__device__ inline int64_t shfl64(int64_t x, int src) {
+  const int lo = __shfl((int)(uint32_t)(uint64_t)x, src, kWave);
+  const int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src, kWave);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 __device__ __forceinline__ void permute_body(const PermuteArgs& a, int64_t bid, int64_t nblk) {
   const int lane = lane_id();
   const int64_t wave = uniform((bid * kBlock + threadIdx.x) / kWave);
   const int64_t nwaves = nblk * kWavesPerBlock;
-  const int64_t total = a.cstart[a.p];
-  for (int64_t c = wave; c < total; c += nwaves) {
-    const Chunk ch = a.chunks[c];
-    const int64_t dst = a.poff[ch.slot] + (ch.klo - a.cp[ch.feat]);
-    for (int32_t e = lane; e < ch.len; e += kWave) {
-      a.pri[dst + e] = a.ri[ch.klo + e];
-      a.pv[dst + e] = a.v[ch.klo + e];
-      if (a.pslot) a.pslot[dst + e] = ch.slot;
+  const int64_t N = a.poff[a.p];
+  const int64_t nr = (N + kPermW - 1) / kPermW;
+  const bool vec = ((reinterpret_cast<uintptr_t>(a.pri) | reinterpret_cast<uintptr_t>(a.pv) |
+                     reinterpret_cast<uintptr_t>(a.pslot)) & 15) == 0;
+  for (int64_t m = wave; m < nr; m += nwaves) {
+    const int64_t q0 = m * kPermW + (int64_t)lane * kPermE;
+    int32_t slot[kPermE];
+    int64_t src[kPermE];
+    bool open[kPermE];
+#pragma unroll
+    for (int u = 0; u < kPermE; ++u) {
+      slot[u] = 0;
+      src[u] = 0;
+      open[u] = q0 + u < N;
+    }
+    // windows of 64 slots; a window's slots past the order end nowhere
+    // (INT64_MAX), so every position < N is found
+    for (int64_t s = uniform(a.rfirst[m]);; s += kWave) {
+      const int64_t sw = s + lane;
+      const bool in = sw < a.p;
+      const int64_t st = in ? a.poff[sw] : INT64_MAX;
+      const int64_t en = in ? a.poff[sw + 1] : INT64_MAX;
+      const int64_t cs = in ? a.src[sw] : 0;
+      bool more = false;
+#pragma unroll
+      for (int u = 0; u < kPermE; ++u) {
+        // i = the number of window slots that end at or before q: slot s + i
+        // holds q (its start is <= q, its end > q) unless i == 64
+        const int64_t q = q0 + u;
+        // (the halving steps count the ends <= q among the first 63; the
+        // last end is then tested at i, which is 63 only if all 63 were)
+        int i = 0;
+#pragma unroll
+        for (int step = kWave / 2; step >= 1; step >>= 1)
+          if (shfl64(en, i + step - 1) <= q) i += step;
+        if (shfl64(en, i) <= q) i += 1;
+        const int ic = i < kWave ? i : kWave - 1;
+        const int64_t sti = shfl64(st, ic), csi = shfl64(cs, ic);
+        if (open[u] && i < kWave) {
+          slot[u] = (int32_t)(s + i);
+          src[u] = csi + (q - sti);
+          open[u] = false;
+        }
+        more = more || open[u];
+      }
+      if (__ballot(more) == 0) break;
+    }
+    int32_t row[kPermE];
+    float val[kPermE];
+#pragma unroll
+    for (int u = 0; u < kPermE; ++u) {
+      const bool ok = q0 + u < N;
+      row[u] = ldz(a.ri, ok, src[u], 0);
+      val[u] = ldz(a.v, ok, src[u], 0.0f);
+    }
+    if (vec && q0 + kPermE <= N) {
+      *reinterpret_cast<int4*>(a.pri + q0) = make_int4(row[0], row[1], row[2], row[3]);
+      *reinterpret_cast<float4*>(a.pv + q0) = make_float4(val[0], val[1], val[2], val[3]);
+      if (a.pslot)
+        *reinterpret_cast<int4*>(a.pslot + q0) = make_int4(slot[0], slot[1], slot[2], slot[3]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < kPermE; ++u) {
+        if (q0 + u < N) {
+          a.pri[q0 + u] = row[u];
+          a.pv[q0 + u] = val[u];
+          if (a.pslot) a.pslot[q0 + u] = slot[u];
+        }
+      }
     }
   }
 }
@@ -2546,8 +2572,10 @@ __device__ __forceinline__ void slot_len_body(const SlotLenArgs& a, int64_t bid)
   const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
   if (r < a.p) {
     const int32_t j = a.perm[r];
-    a.len[r] = (int32_t)(a.cp[j + 1] - a.cp[j]);
+    const int64_t k0 = a.cp[j];
+    a.len[r] = (int32_t)(a.cp[j + 1] - k0);
     if (a.w) a.pw[r] = a.w[j];
+    if (a.src) a.src[r] = k0;
   }
 }
 
@@ -2556,6 +2584,10 @@ __global__ __launch_bounds__(kBlock) void k_slot_len(SlotLenArgs a) { slot_len_b
 __device__ __forceinline__ void widen_body(const WidenArgs& a, int64_t bid) {
   const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
   if (r <= a.m) a.out[r] = a.in[r];
+  if (a.rfirst && r < a.m) {  // the ranges whose first position slot r holds
+    const int64_t lo = a.in[r], hi = a.in[r + 1];
+    for (int64_t k = (lo + kPermW - 1) / kPermW; k * kPermW < hi; ++k) a.rfirst[k] = (int32_t)r;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_widen(WidenArgs a) { widen_body(a, blockIdx.x); }
@@ -2708,13 +2740,6 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
       scan_totals_body<kBlock>(t.u.scan.tmp, t.u.scan.nb, t.u.scan.out + t.u.scan.m);
       break;
     case kTaskScanAdd: scan_add_body<kBlock>(t.u.scan.out, t.u.scan.m, t.u.scan.tmp, lb); break;
-    case kTaskChunkCount:
-      chunk_count_body(t.u.ch.perm, t.u.ch.cp, t.u.ch.p, t.u.ch.chunk, t.u.ch.nch, lb);
-      break;
-    case kTaskChunkFill:
-      chunk_fill_body(t.u.ch.perm, t.u.ch.cp, t.u.ch.cstart, t.u.ch.p, t.u.ch.chunk,
-                      t.u.ch.chunks, lb);
-      break;
     default: break;
   }
 }
@@ -2800,7 +2825,7 @@ inline int grid_for(int64_t items, int per_block, int cap) {
   return (int)g;
 }
 
-int permute_grid(int64_t p) { return grid_for(p, kWavesPerBlock, 8192); }
+int permute_grid(int64_t nnz) { return grid_for((nnz + kPermW - 1) / kPermW, kWavesPerBlock, 8192); }
 
 }  // namespace
 
@@ -2867,19 +2892,6 @@ hipError_t launch_radix_sort(uint32_t* keys0, int32_t* idx0, uint32_t* keys1, in
   return hipGetLastError();
 }
 
-hipError_t launch_chunks(const int32_t* perm, const int64_t* cp, int64_t p, int32_t chunk,
-                         int32_t* nch, int32_t* cstart, Chunk* chunks, int32_t* tmp,
-                         hipStream_t s) {
-  if (chunk < kChunkMin) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
-                     cp, p, chunk, nch);
-  hipError_t e = launch_scan(nch, cstart, p, tmp, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chunk_fill, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s, perm,
-                     cp, cstart, p, chunk, chunks);
-  return hipGetLastError();
-}
-
 namespace {
 
 Task partition_task(int kind, int loss, int64_t nblk) {
@@ -2923,8 +2935,7 @@ void scan_tasks(int loss, const int32_t* in, int32_t* out, int64_t m, int32_t* t
 
 void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, const double* act,
                      uint32_t* keys0, int32_t* idx0, uint32_t* keys1, int32_t* idx1,
-                     int32_t* hist, int32_t* scan_tmp, const int64_t* cp, int32_t chunk,
-                     int32_t* nch, int32_t* cstart, Chunk* chunks, std::vector<Task>& out) {
+                     int32_t* hist, int32_t* scan_tmp, std::vector<Task>& out) {
   const int64_t pg = grid_for(p, kBlock, 1 << 30);
   Task t = partition_task(kTaskPermKeys, loss, pg);
   t.u.pk = PermKeysArgs{it, seed, 0, p, act, keys0, idx0};
@@ -2945,13 +2956,6 @@ void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, co
     std::swap(kin, kout);
     std::swap(iin, iout);
   }
-  // launch_chunks
-  t = partition_task(kTaskChunkCount, loss, pg);
-  t.u.ch = ChunkArgs{idx0, cp, cstart, nch, chunks, p, chunk};
-  out.push_back(t);
-  scan_tasks(loss, nch, cstart, p, scan_tmp, out);
-  t.kind = kTaskChunkFill;
-  out.push_back(t);
 }
 
 // One wavefront per range of a bundle of the expected size and at least 256
@@ -3075,7 +3079,7 @@ void br_steps(const BrPlan& bp, F&& f) {
   st = BrStep{};
   st.kind = kTaskSlotLen;
   st.nblk = pg;
-  st.sl = SlotLenArgs{bp.perm, bp.cp, p_slots, bp.len_tmp, bp.w, bp.pw};
+  st.sl = SlotLenArgs{bp.perm, bp.cp, p_slots, bp.len_tmp, bp.w, bp.pw, bp.psrc};
   f(st);
   st = BrStep{};
   st.kind = -1;
@@ -3086,15 +3090,14 @@ void br_steps(const BrPlan& bp, F&& f) {
   st = BrStep{};
   st.kind = kTaskWiden;
   st.nblk = grid_for(p_slots + 1, kBlock, 1 << 30);
-  st.wd = WidenArgs{bp.off32, p_slots, bp.poff};
+  st.wd = WidenArgs{bp.off32, p_slots, bp.poff, bp.rfirst};
   f(st);
   if (nnz == 0) return;
   // X in partition order (the bundle sweep's input)
   st = BrStep{};
   st.kind = kTaskPermute;
-  st.nblk = permute_grid(p_slots);
-  st.pm = PermuteArgs{bp.ri, bp.v, bp.cp, bp.chunks, bp.cstart, p_slots, bp.poff, bp.pri, bp.pv,
-                      bp.pslot};
+  st.nblk = permute_grid(nnz);
+  st.pm = PermuteArgs{bp.ri, bp.v, bp.psrc, bp.poff, bp.rfirst, p_slots, bp.pri, bp.pv, bp.pslot};
   f(st);
   const int passes = br_passes(p_slots, P);
   const int64_t ntiles = (nnz + kBrTile - 1) / kBrTile;
@@ -3198,19 +3201,20 @@ void bundle_row_tasks(int loss, const BrPlan& bp, std::vector<Task>& out) {
   });
 }
 
-hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, const int32_t* ri,
-                          const float* v, const Chunk* chunks, const int32_t* cstart,
+hipError_t launch_permute(const int32_t* perm, const int64_t* cp, int64_t p, int64_t nnz,
+                          const int32_t* ri, const float* v, int64_t* psrc, int32_t* rfirst,
                           int32_t* len_tmp, int32_t* off32, int32_t* scan_tmp, int64_t* poff,
                           int32_t* pri, float* pv, int32_t* pslot, const double* w, double* pw,
                           hipStream_t s) {
   hipLaunchKernelGGL(k_slot_len, dim3(grid_for(p, kBlock, 1 << 30)), dim3(kBlock), 0, s,
-                     SlotLenArgs{perm, cp, p, len_tmp, w, pw});
+                     SlotLenArgs{perm, cp, p, len_tmp, w, pw, psrc});
   hipError_t e = launch_scan(len_tmp, off32, p, scan_tmp, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_widen, dim3(grid_for(p + 1, kBlock, 1 << 30)), dim3(kBlock), 0, s,
-                     WidenArgs{off32, p, poff});
-  hipLaunchKernelGGL(k_permute, dim3(permute_grid(p)), dim3(kBlock), 0, s,
-                     PermuteArgs{ri, v, cp, chunks, cstart, p, poff, pri, pv, pslot});
+                     WidenArgs{off32, p, poff, rfirst});
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_permute, dim3(permute_grid(nnz)), dim3(kBlock), 0, s,
+                       PermuteArgs{ri, v, psrc, poff, rfirst, p, pri, pv, pslot});
   return hipGetLastError();
 }
 

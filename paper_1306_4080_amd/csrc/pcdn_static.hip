@@ -201,8 +201,8 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->hist = k.take<int32_t>(hist_p);
   t->scan_tmp = k.take<int32_t>(scan_m + 1);
   t->nch = k.take<int32_t>(p);
-  t->cstart = k.take<int32_t>(p + 1);
-  t->chunks = k.take<Chunk>(max_chunks);
+  t->rfirst = k.take<int32_t>(nnz / kPermW + 2);
+  t->psrc = k.take<int64_t>(p);
   t->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
   t->part = k.take<double2>(t->part_len);
   t->pri = k.take<int32_t>(nnz);
