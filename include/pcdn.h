@@ -70,10 +70,12 @@ typedef struct {
   int32_t schedule;     /* PCDN_SCHED_*: how bundles map onto the GPU       */
   int32_t shrink;       /* 1: outer-iteration shrinking (below); 0: off     */
   int32_t penalty;      /* PCDN_PENALTY_*: the regulariser (below)          */
-  int32_t chunk;        /* nonzeros per wavefront work item of the WIDE
-                           schedule: a column of L nonzeros is swept by
-                           ceil(L / chunk) wavefronts (0: 128; 64, 128, 256
-                           or 512)                                          */
+  int32_t chunk;        /* nonzeros per wavefront range of the WIDE
+                           schedule's bundle sweep: a bundle's nonzeros in
+                           partition order are cut into ranges of `chunk`
+                           (a column of L nonzeros spans about L / chunk
+                           wavefronts; 0: 256; 64, 128, 256 or 512).  It
+                           fixes the order of the g_j, h_j sums            */
   double l2;            /* ridge weight b of ELASTIC and L2 (> 0); 0 for L1 */
 } pcdn_opts;
 
@@ -143,7 +145,7 @@ typedef struct {
   double min_armijo_margin;
   double min_stop_margin;
   /* The schedule and chunk the solve ran with (PCDN_SCHED_*; nonzeros per
-   * work item): the options' values, or the autotuner's for a batch job
+   * wavefront range of the bundle sweep): the options' values, or the autotuner's for a batch job
    * with P = 0.  Passing them back reproduces the solve bit for bit. */
   int32_t schedule;
   int32_t chunk;
@@ -344,7 +346,7 @@ typedef struct {
   pcdn_tune_point tried[12];
 } pcdn_tune;
 
-/* Choose the bundle size P, the schedule and the wavefronts per column for
+/* Choose the bundle size P, the schedule and the sweep's range width for
  * solving the loaded problem with (loss, C, eps), by the pilot procedure of
  * Sec. 5.1 ("Bundle Size Choice"): the paper starts at about 5% of the
  * features, P0 = 0.05 p, and adjusts P by measured runtime.
@@ -353,8 +355,9 @@ typedef struct {
  *  2. schedule (only if opts->schedule is PCDN_SCHED_AUTO): at the best P,
  *     the schedule the automatic choice did not take (WIDE after a
  *     single-workgroup run; NARROW after a WIDE run when P <= 1024);
- *  3. wavefronts per column (only if opts->chunk is 0, and the best pilot
- *     so far ran WIDE bundles): chunks of 64, 256 and 512 nonzeros.
+ *  3. the bundle sweep's range width (only if opts->chunk is 0, and the
+ *     best pilot so far ran WIDE bundles): 64, 128 and 512 nonzeros per
+ *     wavefront (256 ran in steps 1 and 2).
  * Each pilot is the solve itself through the batch engine (the path
  * pcdn_solve_batch takes), from the start pcdn_solve would use, to the
  * target eps (graphs and task lists built before the clock starts), abandoned as soon as

@@ -197,6 +197,7 @@ SweepArgs sweep_args(pcdn_ctx* c, const Opts& o) {
   a.h = c->h;
   a.d = c->d;
   a.dterm = c->dterm;
+  a.W = o.chunk;
   a.sg = c->tmp_p;
   a.part = c->part;
   a.dtx = c->dtx;
@@ -227,17 +228,17 @@ SweepArgs bundle_sweep_args(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, 
   return a;
 }
 
-// Blocks of a bundle sweep over slots [lo, hi): sized for the bundle's
-// expected nonzeros.
-int bundle_sweep_grid(const pcdn_ctx* c, int64_t lo, int64_t hi) {
-  return sweep_ranges_grid((double)c->nnz * (double)(hi - lo) / (double)c->p);
+// Blocks of a bundle sweep over slots [lo, hi) in ranges of W nonzeros:
+// sized for the bundle's expected nonzeros.
+int bundle_sweep_grid(const pcdn_ctx* c, int64_t lo, int64_t hi, int W) {
+  return sweep_ranges_grid((double)c->nnz * (double)(hi - lo) / (double)c->p, W);
 }
 
 int bundle_sweep(pcdn_ctx* c, const Opts& o, int64_t lo, int64_t hi, bool clip) {
   const SweepArgs a = bundle_sweep_args(c, o, lo, hi, clip);
   {
     ProfScope ps(c, 0);
-    HIPCHK(c, launch_sweep_ranges(c->loss, a, bundle_sweep_grid(c, lo, hi), c->stream));
+    HIPCHK(c, launch_sweep_ranges(c->loss, a, bundle_sweep_grid(c, lo, hi, a.W), c->stream));
   }
   {
     ProfScope ps(c, 1);
@@ -525,9 +526,6 @@ int device_permutation(pcdn_ctx* c, uint64_t seed, int64_t k, const IterState* i
   return PCDN_OK;
 }
 
-bool has_split_columns(const pcdn_ctx* c, int chunk) {
-  return c->top_len.size() < 2 || c->top_len[1] > chunk;
-}
 
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P) {
   if (P > kNarrowMaxP || c->nnz >= ((int64_t)1 << 31)) return false;
@@ -722,7 +720,7 @@ int outer_tasks(pcdn_ctx* c, const Opts& o, int64_t P, std::vector<Task>& out) {
   const int64_t nb = (c->p + P - 1) / P;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t lo = b * P, hi = std::min(lo + P, c->p);
-    Task t = task(kTaskSweepRanges, bundle_sweep_grid(c, lo, hi), 0);
+    Task t = task(kTaskSweepRanges, bundle_sweep_grid(c, lo, hi, o.chunk), 0);
     t.u.sw = bundle_sweep_args(c, o, lo, hi, o.shrink);
     out.push_back(t);
     t.kind = kTaskSweepFinish;

@@ -1116,13 +1116,14 @@ extern "C" int pcdn_autotune(pcdn_ctx* c, int loss, double C, double eps, const 
       rc = pilot(Pb, PCDN_SCHED_NARROW, o.chunk);
     if (rc) return rc;
   }
-  // 3. wavefronts per column, when multi-kernel bundles ran (WIDE, or the
-  //    heavy bundles of the automatic single-workgroup schedule)
+  // 3. the other range widths of the bundle sweep (nonzeros per wavefront),
+  //    when multi-kernel bundles ran (WIDE, or the heavy bundles of the
+  //    automatic single-workgroup schedule)
   Opts ob = o;
   ob.schedule = out->schedule;
   if (tune_chunk && !done && (!best_narrow || use_hybrid(c, ob, Pb))) {
     const int sched = out->schedule;
-    for (const int ch : {64, 256, 512}) {
+    for (const int ch : {64, 128, 512}) {
       rc = pilot(Pb, sched, ch);
       if (rc) return rc;
     }

@@ -28,8 +28,8 @@ namespace pcdn {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kChunk = 128;    // nonzeros per wavefront work item (default)
-constexpr int kChunkMin = 64;  // smallest selectable (descriptor storage is sized for it)
+constexpr int kChunk = 256;    // nonzeros per wavefront range of the bundle sweep (default)
+constexpr int kChunkMin = 64;  // smallest selectable (the partials are sized for it)
 constexpr int kQMax = 32;      // line-search candidates evaluated per pass
 constexpr int kQGroup = 4;     // candidates per line-search thread (grid y covers the rest)
 constexpr int kSumGrid = 256;  // blocks of the first reduction level
@@ -99,7 +99,8 @@ struct SweepArgs {
   double* d;
   double* dterm;              // g d + gamma h d^2 + R_j(w + d) - R_j(w)
   double* sg;                 // stopping mode: |grad^S_j F|
-  double2* part;              // split-column partial sums, per chunk
+  double2* part;              // bundle sweep: the ranges' open-slot partials (2 per range)
+  int32_t W;                  // bundle sweep: nonzeros per wavefront range (64 .. 512)
   double* dtx;                // d^T x accumulator
   Stats* stats;
   const double* Cp;           // C (device scalar: one captured graph serves every C)
@@ -149,7 +150,6 @@ struct StopArgs {
 // and lists them (row, d^T x_i) at u_row/u_dtx[r kRangeW ...], u_cnt[r] of
 // them, rows with d^T x_i = 0 left out.
 constexpr int kRangeW = 256;
-constexpr int kSweepW = 256;  // nonzeros per wavefront range of the bundle sweep
 constexpr int kRowsGridMax = 2048;  // blocks of the d^T x / line-search launch (at most)
 struct RowsArgs {
   const int32_t* br_row;     // bundle-row order: row, slot and value of each nonzero
@@ -417,10 +417,10 @@ int64_t scan_tmp_ints(int64_t m);
 int64_t radix_hist_ints(int64_t p);
 // Exclusive scan of in[0..m) into out[0..m], out[m] = total (int32).
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s);
-// The bundle sweep (X in partition order, ranges of kSweepW nonzeros) and
+// The bundle sweep (X in partition order, ranges of a.W nonzeros) and
 // its finish over the bundle's slots, with the grids they take for a bundle
 // of `slots` slots and about `nnz_bundle` nonzeros.
-int sweep_ranges_grid(double nnz_bundle);
+int sweep_ranges_grid(double nnz_bundle, int W);
 int sweep_finish_grid(int64_t slots);
 hipError_t launch_sweep_ranges(int loss, const SweepArgs& a, int grid, hipStream_t s);
 hipError_t launch_sweep_finish(int loss, const SweepArgs& a, hipStream_t s);

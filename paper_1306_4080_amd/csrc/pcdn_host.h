@@ -233,10 +233,6 @@ uint64_t data_fingerprint(int64_t n, int64_t p, int64_t nnz, const int64_t* cp,
                           const int32_t* ri, const float* v, const int8_t* y);
 // Record the regulariser that the state is being advanced with.
 void note_regulariser(pcdn_ctx* c, const Opts& o);
-// Whether a column has more than `chunk` nonzeros: only then do work items
-// of that size split a column, and only then is k_split launched (with no
-// split column it does nothing).
-bool has_split_columns(const pcdn_ctx* c, int chunk);
 // Whether outer iterations with bundle size P run in one workgroup.
 bool use_narrow(const pcdn_ctx* c, const Opts& o, int64_t P);
 // Whether the batch engine runs this single-workgroup job's bundles of at

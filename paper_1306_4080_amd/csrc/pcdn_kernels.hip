@@ -583,8 +583,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 // gradient / Hessian sweep of a bundle (eq. (11); SVM: eq. (3) and the
 // generalised Hessian), the direction (eq. (5)) and its Delta term (eq. (7)),
 // over the bundle's nonzeros in partition order (one contiguous range, the
-// nonzeros of each slot together).  Wavefront w takes ranges of kSweepW
-// nonzeros, lane L the range's nonzeros 4L .. 4L+3: a lane sums its own
+// nonzeros of each slot together).  Wavefront w takes ranges of W nonzeros
+// (SweepArgs::W: 64, 128, 256 or 512, the chunk option), lane L the range's
+// nonzeros kE L .. kE L + kE - 1 (kE = W / 64): a lane sums its own
 // nonzeros per slot in order and finishes the slots that start and end
 // inside it; one segmented wavefront scan over the lanes' last runs carries
 // runs across lanes, and a slot is finished where it ends.  Slots that cross
@@ -629,19 +630,19 @@ __device__ inline double lane_pick(double v, int src) {
   return __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
 }
 
-template <int LOSS>
+template <int LOSS, int kE>
 __device__ __forceinline__ void sweep_ranges_body(const SweepArgs& a, int64_t bid, int64_t nblk) {
-  constexpr int kE = kSweepW / kWave;  // consecutive nonzeros per lane
+  constexpr int kW = kE * kWave;  // nonzeros per range (a.W); kE consecutive per lane
   const int lane = lane_id();
   const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
   if (hi <= a.slot_lo) return;
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[hi];
-  const int64_t nr = (e1 - e0 + kSweepW - 1) / kSweepW;
+  const int64_t nr = (e1 - e0 + kW - 1) / kW;
   const int64_t nwaves = nblk * kWavesPerBlock;
   const double C = *a.Cp;
   for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
-    const int64_t rb = e0 + m * kSweepW;
-    const int64_t re = rb + kSweepW < e1 ? rb + kSweepW : e1;
+    const int64_t rb = e0 + m * kW;
+    const int64_t re = rb + kW < e1 ? rb + kW : e1;
     const int64_t k0 = rb + (int64_t)lane * kE;
     int32_t sl[kE], row[kE];
     float xv[kE];
@@ -759,9 +760,20 @@ __device__ __forceinline__ void sweep_ranges_body(const SweepArgs& a, int64_t bi
   }
 }
 
-template <int LOSS>
+template <int LOSS, int kE>
 __global__ __launch_bounds__(kBlock) void k_sweep_ranges(SweepArgs a) {
-  sweep_ranges_body<LOSS>(a, blockIdx.x, gridDim.x);
+  sweep_ranges_body<LOSS, kE>(a, blockIdx.x, gridDim.x);
+}
+
+// The body for the range width a.W (64, 128, 256 or 512 nonzeros).
+template <int LOSS>
+__device__ __forceinline__ void sweep_ranges_any(const SweepArgs& a, int64_t bid, int64_t nblk) {
+  switch (a.W) {
+    case 64: sweep_ranges_body<LOSS, 1>(a, bid, nblk); break;
+    case 128: sweep_ranges_body<LOSS, 2>(a, bid, nblk); break;
+    case 512: sweep_ranges_body<LOSS, 8>(a, bid, nblk); break;
+    default: sweep_ranges_body<LOSS, 4>(a, bid, nblk); break;
+  }
 }
 
 // Slots that cross a range boundary and empty slots (g_j = h_j = 0 before
@@ -778,13 +790,14 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& a, int64_t bi
   const int lane = lane_id();
   const int64_t e0 = a.poff[a.slot_lo];
   const double C = *a.Cp;
+  const int wsh = __builtin_ctz((unsigned)a.W);  // range index = offset >> wsh (W a power of 2)
   const int64_t nwaves = nblk * kWavesPerBlock;
   for (int64_t base = a.slot_lo + uniform((bid * kBlock + threadIdx.x) / kWave) * kWave; base < hi;
        base += nwaves * kWave) {
     const int64_t o = base + lane;
     const bool valid = o < hi;
     const int64_t k0 = ldz(a.poff, valid, o, (int64_t)0), k1 = ldz(a.poff, valid, o + 1, (int64_t)0);
-    const int64_t m1 = (k0 - e0) / kSweepW, m2 = k1 > k0 ? (k1 - 1 - e0) / kSweepW : m1;
+    const int64_t m1 = (k0 - e0) >> wsh, m2 = k1 > k0 ? (k1 - 1 - e0) >> wsh : m1;
     const bool empty = valid && k1 == k0;
     const bool crossing = valid && k1 > k0 && m2 > m1;
     const bool longer = crossing && m2 - m1 > kFinishShort;
@@ -2705,7 +2718,7 @@ __device__ inline int task_of_block(const int32_t* first, int count, int b) {
 template <int LOSS>
 __device__ __forceinline__ void exec_task(const Task& t, int lb) {
   switch (t.kind) {
-    case kTaskSweepRanges: sweep_ranges_body<LOSS>(t.u.sw, lb, t.nblk); break;
+    case kTaskSweepRanges: sweep_ranges_any<LOSS>(t.u.sw, lb, t.nblk); break;
     case kTaskStopRanges: stop_ranges_body<LOSS>(t.u.so, lb, t.nblk); break;
     case kTaskSweepFinish: sweep_finish_body<LOSS>(t.u.sw, lb, t.nblk); break;
     case kTaskStopFinish: stop_finish_body<LOSS>(t.u.so, lb, t.nblk); break;
@@ -2961,19 +2974,30 @@ void partition_tasks(int loss, const IterState* it, uint64_t seed, int64_t p, co
 // One wavefront per range of a bundle of the expected size and at least 256
 // wavefronts; a larger bundle (the partition is random) takes several ranges
 // per wavefront.  Which wavefront takes a range changes no sum.
-int sweep_ranges_grid(double nnz_bundle) {
-  const double ranges = nnz_bundle / kSweepW + 1.0;
+int sweep_ranges_grid(double nnz_bundle, int W) {
+  const double ranges = nnz_bundle / W + 1.0;
   const int64_t waves = ranges > 256.0 ? (int64_t)ranges : 256;
   return grid_for(waves, kWavesPerBlock, 8192);
 }
 
 int sweep_finish_grid(int64_t slots) { return grid_for(slots, kBlock, 4096); }
 
+template <int LOSS>
+void launch_sweep_ranges_w(const SweepArgs& a, int grid, hipStream_t s) {
+  switch (a.W) {
+    case 64: hipLaunchKernelGGL((k_sweep_ranges<LOSS, 1>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_sweep_ranges<LOSS, 2>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 512: hipLaunchKernelGGL((k_sweep_ranges<LOSS, 8>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep_ranges<LOSS, 4>), dim3(grid), dim3(kBlock), 0, s, a); break;
+  }
+}
+
 hipError_t launch_sweep_ranges(int loss, const SweepArgs& a, int grid, hipStream_t s) {
+  if (a.W != 64 && a.W != 128 && a.W != 256 && a.W != 512) return hipErrorInvalidValue;
   if (loss == kLogistic)
-    hipLaunchKernelGGL(k_sweep_ranges<kLogistic>, dim3(grid), dim3(kBlock), 0, s, a);
+    launch_sweep_ranges_w<kLogistic>(a, grid, s);
   else
-    hipLaunchKernelGGL(k_sweep_ranges<kL2Svm>, dim3(grid), dim3(kBlock), 0, s, a);
+    launch_sweep_ranges_w<kL2Svm>(a, grid, s);
   return hipGetLastError();
 }
 

@@ -356,8 +356,8 @@ def test_path_svm_wide(pc):
 def test_autotune_ladder_and_choice(pc):
     """The candidates are the paper's pilot start (5% of the features) and
     its factor-4 neighbours, nearest first; then, at the best of those, the
-    schedule the automatic choice did not take, and chunk lengths when
-    multi-kernel bundles won.  The choice is the fastest finished pilot;
+    schedule the automatic choice did not take, and the other sweep range
+    widths (pcdn_opts.chunk) when multi-kernel bundles won.  The choice is the fastest finished pilot;
     solving with it matches the oracle at that P."""
     d = synth.c1()
     s = pc.Solver(device=0).load_data(d)
@@ -373,14 +373,14 @@ def test_autotune_ladder_and_choice(pc):
     for x in tried:
         print("  ", x, flush=True)
     assert [x["P"] for x in tried[:len(ladder)]] == ladder
-    assert all(x["schedule"] == 0 and x["chunk"] == 128 for x in tried[:len(ladder)])
+    assert all(x["schedule"] == 0 and x["chunk"] == 256 for x in tried[:len(ladder)])
     first = [x for x in tried[:len(ladder)] if np.isfinite(x["predicted_seconds"])]
     assert first
     Pb = min(first, key=lambda x: x["predicted_seconds"])["P"]
     rest = tried[len(ladder):]
     assert rest and all(x["P"] == Pb for x in rest)
     assert rest[0]["schedule"] in (1, 2) and rest[0]["narrow"] == (rest[0]["schedule"] == 2)
-    assert {x["chunk"] for x in rest[1:]} <= {64, 256, 512}
+    assert {x["chunk"] for x in rest[1:]} <= {64, 128, 512}
     done = [x for x in tried if np.isfinite(x["predicted_seconds"])]
     best = min(done, key=lambda x: x["predicted_seconds"])
     assert t["predicted_seconds"] == best["predicted_seconds"]

@@ -134,6 +134,34 @@ def test_step_parity_long_columns_c2(pc, loss, schedule):
     s.close()
 
 
+@pytest.mark.parametrize("width", [64, 128, 512])
+@pytest.mark.parametrize("loss", ["lr", "svm"])
+def test_step_parity_range_widths_c2(pc, loss, width):
+    """Every range width of the bundle sweep (pcdn_opts.chunk): g, h, d,
+    d^T x and the step against the oracle on bundles with C2's longest
+    columns (a column then spans up to 300 ranges of 64 nonzeros)."""
+    d = synth.c2()
+    prob = oracle.Problem.from_data(d)
+    C = 4.0
+    par = oracle.Params(loss=loss, C=C)
+    s = _solver(pc, d)
+    rng = np.random.default_rng(11)
+    heavy = np.argsort(d.col_lengths())[::-1][:30]
+    for trial in range(2):
+        w = _random_w(rng, d.p, frac=0.05, scale=0.2) if trial else np.zeros(d.p)
+        s.reset(loss, C, w)
+        cache = oracle.cache_from_w(prob, loss, w)
+        perm = oracle.permutation(13, trial, d.p)
+        bundle = np.concatenate([heavy[trial::2], perm[:2048]])
+        bundle = bundle[np.sort(np.unique(bundle, return_index=True)[1])]
+        w_o = w.copy()
+        s_orc = oracle.step(prob, par, w_o, cache, bundle)
+        s_gpu = s.step(bundle, schedule="wide", chunk=width)
+        _compare_step(d, s_gpu, s_orc, bundle, C)
+        np.testing.assert_allclose(s.w(), w_o, rtol=1e-12, atol=1e-15)
+    s.close()
+
+
 @pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("loss", ["lr", "svm"])
 @pytest.mark.parametrize("zmax", [50.0, 700.0])
@@ -504,11 +532,12 @@ def test_regulariser_argument_errors(pc):
     s.close()
 
 
-@pytest.mark.parametrize("chunk", [64, 256, 512])
+@pytest.mark.parametrize("chunk", [64, 128, 512])
 def test_chunk_lengths_same_trajectory(pc, chunk):
-    """Nonzeros per wavefront work item (pcdn_opts.chunk) change only the work
-    split of the multi-kernel schedule: C2's long columns at P = 1,024 give
-    the oracle's trajectory for every chunk length."""
+    """The bundle sweep's range width (pcdn_opts.chunk, nonzeros per
+    wavefront; 256 by default) changes only the work split and the order of
+    the g_j, h_j sums: C2's long columns at P = 1,024 give the oracle's
+    trajectory for every width."""
     d = _c2_cached()
     prob = oracle.Problem.from_data(d)
     w_o, io, _ = oracle.solve(prob, oracle.Params(loss="lr", C=0.5), P=1024, eps=1e-4, seed=1)
