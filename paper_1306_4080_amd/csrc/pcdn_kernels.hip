@@ -199,13 +199,6 @@ __device__ inline void weighted_terms(double2 rw, double x, double& gs, double& 
   }
 }
 
-// Gradient term alone (the stopping sweep).
-template <int LOSS>
-__device__ inline double weighted_grad(double2 rw, double x) {
-  if (LOSS == kLogistic) return rw.x * x;
-  return rw.y > 0.0 ? rw.x * x : 0.0;
-}
-
 // Loss change of sample i when its margin w^T x_i grows by a (eq. (10)'s
 // summand).  Logistic: log(1+e^{-y(z+a)}) - log(1+e^{-yz}); with m = -y a and
 // tau = tau(y z) it is log(tau + (1 - tau) e^m), written for t = -|m| <= 0 as
@@ -891,28 +884,30 @@ __device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid,
     // columns open at the range's ends
     const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
     const int32_t right = re < a.nnz ? a.ccol[re] : -1;
-    double2 rv[kE];
+    // the rows' gradient weights alone (the first of the two row weights;
+    // zero where an SVM row has no slack, so the product is the term)
+    const double* gw = reinterpret_cast<const double*>(a.rw);
+    double rg[kE];
     double wv[kE];
 #pragma unroll
     for (int u = 0; u < kE; ++u) {
-      rv[u] = ldz(a.rw, col[u] >= 0, row[u], make_double2(0.0, 0.0));
+      rg[u] = ldz(gw, col[u] >= 0, 2 * (int64_t)row[u], 0.0);
       wv[u] = ldz(wsrc, col[u] >= 0 && a.w != nullptr, col[u], 0.0);
     }
     // every operand loaded before the first use (the compiler would sink
     // loads into the finishing branches and wait for each there)
 #pragma unroll
-    for (int u = 0; u < kE; ++u)
-      asm volatile("" ::"v"(rv[u].x), "v"(rv[u].y), "v"(wv[u]), "v"(xv[u]));
+    for (int u = 0; u < kE; ++u) asm volatile("" ::"v"(rg[u]), "v"(wv[u]), "v"(xv[u]));
     // the lane's runs: head (from its first nonzero), complete middles, tail
     const int32_t hk = col[0];
     const double hw = wv[0];
     int32_t rk = col[0];
-    double run = col[0] >= 0 ? weighted_grad<LOSS>(rv[0], (double)xv[0]) : 0.0;
+    double run = col[0] >= 0 ? rg[0] * (double)xv[0] : 0.0;
     double wk = wv[0], hs = 0.0;
     bool whole = true;  // one run covers the lane's nonzeros
 #pragma unroll
     for (int u = 1; u < kE; ++u) {
-      const double t = col[u] >= 0 ? weighted_grad<LOSS>(rv[u], (double)xv[u]) : 0.0;
+      const double t = col[u] >= 0 ? rg[u] * (double)xv[u] : 0.0;
       if (col[u] == rk) {
         run += t;
       } else {
