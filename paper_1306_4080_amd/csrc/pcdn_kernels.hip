@@ -1121,7 +1121,7 @@ __device__ inline int rows_round(RowQueue& qu, int qn, int32_t row, bool owned, 
 // rounds are issued together (rows, slots and values, then the directions
 // and the rows' retained quantities and labels), so a range costs two
 // dependent round trips to memory.
-template <int LOSS>
+template <int LOSS, bool EARLY>
 __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   constexpr int kR = kRangeW / kWave;
   __shared__ RowQueue queue[kWavesPerBlock];
@@ -1135,16 +1135,21 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   const int64_t nwaves = (int64_t)G * kWavesPerBlock;
   RowQueue& qu = queue[wv];
-  // the regulariser terms' operands of this thread's first slot, loaded now
-  // (they depend on nothing the row sums compute; w from its copy in
-  // partition order, which no apply has changed for this bundle's slots)
+  // EARLY: the regulariser terms' operands of this thread's first slot,
+  // loaded now (they depend on nothing the row sums compute; w from its copy
+  // in partition order, which no apply has changed for this bundle's slots).
+  // The executor's copy of this body loads them where they are used: the
+  // registers they hold across the row sums would cost it occupancy.
   const int64_t Pt = hi_act - a.slot_lo;
   const int64_t r0 = (int64_t)bx * kBlock + threadIdx.x;
-  const bool has0 = r0 < Pt;
-  const double wj0 = ldz(a.pw, has0, a.slot_lo + r0, 0.0);
-  const double dj0 = ldz(a.d, has0, a.slot_lo + r0, 0.0);
-  const double dt0 = ldz(a.dterm, has0, a.slot_lo + r0, 0.0);
-  asm volatile("" ::"v"(wj0), "v"(dj0), "v"(dt0));
+  const bool has0 = EARLY && r0 < Pt;
+  double wj0 = 0.0, dj0 = 0.0, dt0 = 0.0;
+  if (EARLY) {
+    wj0 = ldz(a.pw, has0, a.slot_lo + r0, 0.0);
+    dj0 = ldz(a.d, has0, a.slot_lo + r0, 0.0);
+    dt0 = ldz(a.dterm, has0, a.slot_lo + r0, 0.0);
+    asm volatile("" ::"v"(wj0), "v"(dj0), "v"(dt0));
+  }
   double acc[kQGroup], aabs[kQGroup];
 #pragma unroll
   for (int q = 0; q < kQGroup; ++q) acc[q] = aabs[q] = 0.0;
@@ -1289,7 +1294,7 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   for (int q = 0; q < kQGroup; ++q) acc[q] = aabs[q] = 0.0;
   for (int64_t r = r0; r < Pt; r += (int64_t)G * kBlock) {
     const int64_t slot = a.slot_lo + r;
-    const bool pre = r == r0;
+    const bool pre = EARLY && r == r0;
     const double wj = pre ? wj0 : a.pw[slot];
     const double dj = pre ? dj0 : a.d[slot];
     del += pre ? dt0 : a.dterm[slot];
@@ -1334,7 +1339,7 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
 
 template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_rows_dtx(RowsArgs a) {
-  rows_dtx_body<LOSS>(a, blockIdx.x);
+  rows_dtx_body<LOSS, true>(a, blockIdx.x);
 }
 
 // Sum of row v of the line-search partials, same order in every block.
@@ -1448,7 +1453,7 @@ __device__ inline void apply_row(const RowsArgs& a, int32_t row, double s, doubl
                        LOSS == kLogistic ? c * exp(s) : c - (yi > 0 ? s : -s), yi, a.stats);
 }
 
-template <int LOSS>
+template <int LOSS, bool EARLY>
 __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, int64_t nblk) {
   __shared__ double lds4[kWavesPerBlock];
   __shared__ double lds7[7][kWavesPerBlock];
@@ -1459,41 +1464,52 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   constexpr int kR = kRangeW / kWave;
   const int lane = lane_id();
   // Delta, candidate 0's sums and scales, touched rows and nonzeros with
-  // d_j != 0, in one pass over the partials.  Issued with them, before the
-  // decision waits for them (the update's operands depend only on what the
-  // d^T x launch wrote): the bundle's nonzero range, this thread's first slot
-  // of the w update (w from its copy in partition order), then the
+  // d_j != 0, in one pass over the partials.  EARLY: issued with them, before
+  // the decision waits for them (the update's operands depend only on what
+  // the d^T x launch wrote): the bundle's nonzero range, this thread's first
+  // slot of the w update (w from its copy in partition order), then the
   // wavefront's first listed range (count, rows and d^T x, then the rows'
-  // retained quantities and labels).
+  // retained quantities and labels).  The executor's copy loads them after
+  // the decision (registers held across it would cost it occupancy).
   const int first[7] = {2 * a.Q, 0, a.Q, 2 * a.Q + 3, 3 * a.Q + 3, 2 * a.Q + 1, 2 * a.Q + 2};
   double x7[7];
   ls_load(a.part, first, a.G, x7);
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
   const int64_t sl0 = a.slot_lo + bid * kBlock + threadIdx.x;
-  const bool own0 = sl0 < hi_act;
-  const int32_t f0 = ldz(a.perm, own0, sl0, 0);
-  const double d0 = ldz(a.d, own0, sl0, 0.0);
-  const double w0 = ldz(a.pw, own0, sl0, 0.0);
+  const bool own0 = EARLY && sl0 < hi_act;
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   const int64_t gwave = (bid * kBlock + threadIdx.x) / kWave;
-  const int32_t cnt0 = ldz(a.u_cnt, gwave < nr, gwave, 0);
+  int32_t f0 = 0;
+  double d0 = 0.0, w0 = 0.0;
   int32_t row0[kR];
   double sv0[kR], c0[kR];
   int y0[kR];
 #pragma unroll
   for (int u = 0; u < kR; ++u) {
-    const int32_t i = lane + u * kWave;
-    row0[u] = ldz(a.u_row, i < cnt0, gwave * kRangeW + i, -1);
-    sv0[u] = ldz(a.u_dtx, i < cnt0, gwave * kRangeW + i, 0.0);
+    row0[u] = -1;
+    sv0[u] = c0[u] = 0.0;
+    y0[u] = 0;
   }
+  if (EARLY) {
+    f0 = ldz(a.perm, own0, sl0, 0);
+    d0 = ldz(a.d, own0, sl0, 0.0);
+    w0 = ldz(a.pw, own0, sl0, 0.0);
+    const int32_t cnt0 = ldz(a.u_cnt, gwave < nr, gwave, 0);
 #pragma unroll
-  for (int u = 0; u < kR; ++u) {
-    c0[u] = ldz(a.cache, row0[u] >= 0, row0[u], 0.0);
-    y0[u] = (int)ldz(a.y, row0[u] >= 0, row0[u], (int8_t)0);
+    for (int u = 0; u < kR; ++u) {
+      const int32_t i = lane + u * kWave;
+      row0[u] = ldz(a.u_row, i < cnt0, gwave * kRangeW + i, -1);
+      sv0[u] = ldz(a.u_dtx, i < cnt0, gwave * kRangeW + i, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kR; ++u) {
+      c0[u] = ldz(a.cache, row0[u] >= 0, row0[u], 0.0);
+      y0[u] = (int)ldz(a.y, row0[u] >= 0, row0[u], (int8_t)0);
+    }
+    asm volatile("" ::"v"(f0), "v"(d0), "v"(w0));
+#pragma unroll
+    for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(sv0[u]), "v"(c0[u]), "v"(y0[u]));
   }
-  asm volatile("" ::"v"(f0), "v"(d0), "v"(w0));
-#pragma unroll
-  for (int u = 0; u < kR; ++u) asm volatile("" ::"v"(sv0[u]), "v"(c0[u]), "v"(y0[u]));
   double tot[7];
   ls_finish(a.part, first, a.G, x7, tot, lds7);
   const double Delta = tot[0];
@@ -1542,7 +1558,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
   const int64_t wave = alone ? wave_in_block() : gwave;
   const int64_t nwaves = alone ? kWavesPerBlock : nblk * kWavesPerBlock;
   int64_t r = wave;
-  if (!alone && r < nr) {
+  if (EARLY && !alone && r < nr) {
 #pragma unroll
     for (int u = 0; u < kR; ++u)
       if (row0[u] >= 0) apply_row<LOSS>(a, row0[u], sv0[u], c0[u], y0[u], q_acc);
@@ -1582,7 +1598,7 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
 
 template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_rows_apply(RowsArgs a) {
-  rows_apply_body<LOSS>(a, blockIdx.x, gridDim.x);
+  rows_apply_body<LOSS, true>(a, blockIdx.x, gridDim.x);
 }
 
 // d^T x of the listed rows into a dense vector (pcdn_step's read-back).
@@ -2717,8 +2733,8 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskStopRanges: stop_ranges_body<LOSS>(t.u.so, lb, t.nblk); break;
     case kTaskSweepFinish: sweep_finish_body<LOSS>(t.u.sw, lb, t.nblk); break;
     case kTaskStopFinish: stop_finish_body<LOSS>(t.u.so, lb, t.nblk); break;
-    case kTaskRowsDtx: rows_dtx_body<LOSS>(t.u.rw, lb); break;
-    case kTaskRowsApply: rows_apply_body<LOSS>(t.u.rw, lb, t.nblk); break;
+    case kTaskRowsDtx: rows_dtx_body<LOSS, false>(t.u.rw, lb); break;
+    case kTaskRowsApply: rows_apply_body<LOSS, false>(t.u.rw, lb, t.nblk); break;
     case kTaskSlotLen: slot_len_body(t.u.sl, lb); break;
     case kTaskWiden: widen_body(t.u.wd, lb); break;
     case kTaskIslot: islot_body(t.u.is, lb); break;
