@@ -209,6 +209,7 @@ struct SlotLenArgs {         // column length (and w) in slot order
   const double* w;           // nullable: no copy of w
   double* pw;
   int64_t* src;              // nullable: first nonzero of the slot's column (cp[perm[r]])
+  int32_t* islot;            // nullable: islot[perm[r]] = r
 };
 constexpr int kPermW = 256;  // output positions per wavefront of the copy into partition order
 struct WidenArgs {
@@ -231,11 +232,6 @@ struct PermuteArgs {
   int32_t* pslot;
 };
 
-struct IslotArgs {           // islot[perm[r]] = r for r < p
-  const int32_t* perm;
-  int64_t p;
-  int32_t* islot;
-};
 
 
 // Stopping reduction with shrinking: sums ||grad^S F||_1 = sum sg, the
@@ -309,11 +305,9 @@ enum TaskKind : int32_t {
   kTaskRadixScatter,
   kTaskScanSmall,
   kTaskScanBlocks,
-  kTaskScanTotals,
   kTaskScanAdd,
   kTaskSlotLen,
   kTaskWiden,
-  kTaskIslot,
   kTaskBrHist,
   kTaskBrScatter,
   kTaskPermute,
@@ -330,7 +324,6 @@ struct Task {
     BrArgs br;
     SlotLenArgs sl;
     WidenArgs wd;
-    IslotArgs is;
     PermuteArgs pm;
     SumArgs sum;
     StopSumArgs stop;

@@ -351,8 +351,9 @@ __global__ __launch_bounds__(kBlock) void k_perm_keys(const IterState* it, uint6
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan (int32), three launches: per-block scan, scan of block
-// totals, add-back.  A block of THREADS threads covers kScanTile items (PER
+// exclusive scan (int32), two launches: per-block scan with the block
+// totals, then add-back of the sum of the earlier blocks' totals (each block
+// forms its own).  A block of THREADS threads covers kScanTile items (PER
 // = kScanTile / THREADS each): 1024-thread blocks in direct launches,
 // kBlock-thread blocks in the multi-problem executor.  Integer sums, so
 // every block size gives the same result.
@@ -412,25 +413,6 @@ __device__ __forceinline__ void scan_blocks_body(const int32_t* in, int32_t* out
   if (threadIdx.x == 0) block_tot[bid] = tot;
 }
 
-template <int THREADS>
-__device__ __forceinline__ void scan_totals_body(int32_t* block_tot, int64_t nb,
-                                                 int32_t* out_total) {
-  __shared__ int32_t lds[THREADS / kWave + 1];
-  const int64_t per = (nb + THREADS - 1) / THREADS;
-  const int64_t lo = (int64_t)threadIdx.x * per;
-  const int64_t hi = lo + per < nb ? lo + per : nb;
-  int32_t s = 0;
-  for (int64_t k = lo; k < hi; ++k) s += block_tot[k];
-  int32_t tot;
-  int32_t run = block_exclusive_scan<THREADS>(s, lds, &tot);
-  for (int64_t k = lo; k < hi; ++k) {
-    const int32_t t = block_tot[k];
-    block_tot[k] = run;
-    run += t;
-  }
-  if (threadIdx.x == 0) *out_total = tot;
-}
-
 // Whole scan in one block when m <= 16 THREADS: thread t scans a contiguous
 // chunk of ceil(m / THREADS) items (in and out may alias: a thread reads its
 // whole chunk before the block scan's barriers and writes it afterwards).
@@ -457,15 +439,23 @@ __device__ __forceinline__ void scan_small_body(const int32_t* in, int32_t* out,
   if (threadIdx.x == 0) out[m] = tot;
 }
 
+// Tile bid adds the sum of the tiles before it, which it forms itself from
+// the tiles' totals (a few hundred integers: no launch of its own to scan
+// them); the last tile also writes the total at out[m].
 template <int THREADS>
 __device__ __forceinline__ void scan_add_body(int32_t* out, int64_t m, const int32_t* block_tot,
-                                              int64_t bid) {
+                                              int64_t nb, int64_t bid) {
+  __shared__ int32_t lds[THREADS / kWave + 1];
   constexpr int PER = kScanTile / THREADS;
+  int32_t s = 0;
+  for (int64_t k = threadIdx.x; k < bid; k += THREADS) s += block_tot[k];
+  int32_t add;
+  (void)block_exclusive_scan<THREADS>(s, lds, &add);
   const int64_t base = bid * kScanTile + (int64_t)threadIdx.x * PER;
-  const int32_t add = block_tot[bid];
 #pragma unroll
   for (int k = 0; k < PER; ++k)
     if (base + k < m) out[base + k] += add;
+  if (bid == nb - 1 && threadIdx.x == 0) out[m] = add + block_tot[bid];
 }
 
 constexpr int64_t kScanSmall = 16 * kScanThreads;
@@ -475,19 +465,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_blocks(const int32_t* in,
   scan_blocks_body<kScanThreads>(in, out, m, block_tot, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_totals(int32_t* block_tot, int64_t nb,
-                                                              int32_t* out_total) {
-  scan_totals_body<kScanThreads>(block_tot, nb, out_total);
-}
-
 __global__ __launch_bounds__(kScanThreads) void k_scan_small(const int32_t* in, int32_t* out,
                                                              int64_t m) {
   scan_small_body<kScanThreads>(in, out, m);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t m,
-                                                           const int32_t* block_tot) {
-  scan_add_body<kScanThreads>(out, m, block_tot, blockIdx.x);
+                                                           const int32_t* block_tot, int64_t nb) {
+  scan_add_body<kScanThreads>(out, m, block_tot, nb, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1620,13 +1605,6 @@ __global__ __launch_bounds__(kBlock) void k_rows_scatter(RowsArgs a, double* den
 // ---------------------------------------------------------------------------
 constexpr int kBrTile = kSortThreads * kBrRounds;
 
-__device__ __forceinline__ void islot_body(const IslotArgs& a, int64_t bid) {
-  const int64_t r = bid * (int64_t)kBlock + threadIdx.x;
-  if (r < a.p) a.islot[a.perm[r]] = (int32_t)r;
-}
-
-__global__ __launch_bounds__(kBlock) void k_islot(IslotArgs a) { islot_body(a, blockIdx.x); }
-
 __global__ void k_fill_i32(int32_t* a, int32_t v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -2600,6 +2578,7 @@ __device__ __forceinline__ void slot_len_body(const SlotLenArgs& a, int64_t bid)
     a.len[r] = (int32_t)(a.cp[j + 1] - k0);
     if (a.w) a.pw[r] = a.w[j];
     if (a.src) a.src[r] = k0;
+    if (a.islot) a.islot[j] = (int32_t)r;
   }
 }
 
@@ -2737,7 +2716,6 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskRowsApply: rows_apply_body<LOSS, false>(t.u.rw, lb, t.nblk); break;
     case kTaskSlotLen: slot_len_body(t.u.sl, lb); break;
     case kTaskWiden: widen_body(t.u.wd, lb); break;
-    case kTaskIslot: islot_body(t.u.is, lb); break;
     case kTaskPermute: permute_body(t.u.pm, lb, t.nblk); break;
     case kTaskBrHist: br_hist_body(t.u.br, lb); break;
     case kTaskBrScatter: br_scatter_body(t.u.br, lb); break;
@@ -2760,10 +2738,9 @@ __device__ __forceinline__ void exec_task(const Task& t, int lb) {
     case kTaskScanBlocks:
       scan_blocks_body<kBlock>(t.u.scan.in, t.u.scan.out, t.u.scan.m, t.u.scan.tmp, lb);
       break;
-    case kTaskScanTotals:
-      scan_totals_body<kBlock>(t.u.scan.tmp, t.u.scan.nb, t.u.scan.out + t.u.scan.m);
+    case kTaskScanAdd:
+      scan_add_body<kBlock>(t.u.scan.out, t.u.scan.m, t.u.scan.tmp, t.u.scan.nb, lb);
       break;
-    case kTaskScanAdd: scan_add_body<kBlock>(t.u.scan.out, t.u.scan.m, t.u.scan.tmp, lb); break;
     default: break;
   }
 }
@@ -2872,20 +2849,15 @@ int64_t scan_tmp_ints(int64_t m) { return (m + kScanTile - 1) / kScanTile + 1; }
 int64_t radix_hist_ints(int64_t p) { return 256 * ((p + kSortTile - 1) / kSortTile) + 1; }
 
 hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t m, int32_t* tmp, hipStream_t s) {
-  if (m >= 1 && m <= kScanSmall) {
+  if (m < 0) return hipErrorInvalidValue;
+  if (m <= kScanSmall) {
     hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanThreads), 0, s, in, out, m);
     return hipGetLastError();
   }
   const int64_t nb = (m + kScanTile - 1) / kScanTile;
-  if (nb < 1) {
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tmp, (int64_t)0,
-                       out + m);
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, m,
                      tmp);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanThreads), 0, s, tmp, nb, out + m);
-  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, m, tmp);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, m, tmp, nb);
   return hipGetLastError();
 }
 
@@ -2933,22 +2905,14 @@ void scan_tasks(int loss, const int32_t* in, int32_t* out, int64_t m, int32_t* t
                 std::vector<Task>& v) {
   Task t = partition_task(kTaskScanSmall, loss, 1);
   t.u.scan = ScanArgs{in, out, tmp, m, 0};
-  if (m >= 1 && m <= 16 * kBlock) {
+  if (m <= 16 * kBlock) {
     v.push_back(t);
     return;
   }
   const int64_t nb = (m + kScanTile - 1) / kScanTile;
   t.u.scan.nb = nb;
-  if (nb < 1) {
-    t.kind = kTaskScanTotals;
-    v.push_back(t);
-    return;
-  }
   t.kind = kTaskScanBlocks;
   t.nblk = (int32_t)nb;
-  v.push_back(t);
-  t.kind = kTaskScanTotals;
-  t.nblk = 1;
   v.push_back(t);
   t.kind = kTaskScanAdd;
   t.nblk = (int32_t)nb;
@@ -3089,9 +3053,8 @@ namespace {
 // The launches of the bundle-row order, in order: (kernel kind, block count,
 // arguments).  Shared by the direct launcher and the executor's task list.
 struct BrStep {
-  int kind;  // kTaskIslot, kTaskSlotLen, kTaskWiden, kTaskPermute, kTaskBrHist, kTaskBrScatter; -1: scan
+  int kind;  // kTaskSlotLen, kTaskWiden, kTaskPermute, kTaskBrHist, kTaskBrScatter; -1: scan
   int64_t nblk;
-  IslotArgs is;
   SlotLenArgs sl;
   WidenArgs wd;
   PermuteArgs pm;
@@ -3107,14 +3070,9 @@ void br_steps(const BrPlan& bp, F&& f) {
   const int64_t p_slots = bp.p_slots, P = bp.P, nnz = bp.nnz;
   BrStep st{};
   const int64_t pg = grid_for(p_slots, kBlock, 1 << 30);
-  st.kind = kTaskIslot;
-  st.nblk = pg;
-  st.is = IslotArgs{bp.perm, p_slots, bp.islot};
-  f(st);
-  st = BrStep{};
   st.kind = kTaskSlotLen;
   st.nblk = pg;
-  st.sl = SlotLenArgs{bp.perm, bp.cp, p_slots, bp.len_tmp, bp.w, bp.pw, bp.psrc};
+  st.sl = SlotLenArgs{bp.perm, bp.cp, p_slots, bp.len_tmp, bp.w, bp.pw, bp.psrc, bp.islot};
   f(st);
   st = BrStep{};
   st.kind = -1;
@@ -3188,9 +3146,6 @@ hipError_t launch_bundle_row_order(const BrPlan& bp, hipStream_t s) {
     if (err != hipSuccess) return;
     hipError_t e = hipSuccess;
     switch (st.kind) {
-      case kTaskIslot:
-        hipLaunchKernelGGL(k_islot, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.is);
-        break;
       case kTaskSlotLen:
         hipLaunchKernelGGL(k_slot_len, dim3((unsigned)st.nblk), dim3(kBlock), 0, s, st.sl);
         break;
@@ -3226,7 +3181,6 @@ void bundle_row_tasks(int loss, const BrPlan& bp, std::vector<Task>& out) {
     }
     Task t = partition_task(st.kind, loss, st.nblk);
     switch (st.kind) {
-      case kTaskIslot: t.u.is = st.is; break;
       case kTaskSlotLen: t.u.sl = st.sl; break;
       case kTaskWiden: t.u.wd = st.wd; break;
       case kTaskPermute: t.u.pm = st.pm; break;
