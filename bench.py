@@ -548,6 +548,16 @@ def main():
         print("bench: CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(synth.c3(), args.cpu_seconds)
     print(json.dumps(line), flush=True)
+    # every batched and served solve must equal its plain run (the kernels'
+    # sums have fixed orders); a difference is a defect, not noise
+    bad = []
+    if "batched" in line and not line["batched"]["same_results"]:
+        bad.append("batched solves differ from the plain ones")
+    if "serving" in line and line["serving"]["max_rel_objective_gap_converged"] > 1e-6:
+        bad.append("served objectives differ from the plain ones by more than 1e-6")
+    if bad:
+        print("bench.py: " + "; ".join(bad), file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":
