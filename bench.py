@@ -58,7 +58,7 @@ if ROOT not in sys.path:
 
 METRIC = "bundle-sweep nnz/s (HBM GB/s %peak); batched solves/s + p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_CLASSES = ("sweep", "split_columns", "dtx_linesearch", "apply", "stopping_sweep", "narrow")
+KERNEL_CLASSES = ("sweep", "sweep_finish", "dtx_linesearch", "apply", "stopping_sweep", "narrow")
 KERNEL_NAMES = ("k_sweep_ranges (gradient/Hessian sweep and direction over the bundle's "
                 "nonzeros in partition order, 256 per wavefront)",
                 "k_sweep_finish (slots crossing a range boundary, and empty slots)",

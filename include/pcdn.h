@@ -416,12 +416,14 @@ int pcdn_get_cache(pcdn_ctx* ctx, double* cache_out);
  * pcdn_reset). */
 int pcdn_evaluate(pcdn_ctx* ctx, double* objective, double* subgrad);
 
-/* Kernel timing.  Kernel classes: 0 gradient/direction sweep (with the fused
- * d^T x scatter), 1 d^T x scatter of split columns, 2 line search, 3 apply,
- * 4 stopping sweep, 5 single-workgroup kernel (every step of every bundle of
- * an outer iteration, PCDN_SCHED_NARROW).  pcdn_profile(ctx, mask) brackets every launch of each
- * class whose bit (1 << class) is set in mask with HIP events on the
- * context's stream (mask 0: off) and restarts the accumulators;
+/* Kernel timing.  Kernel classes: 0 bundle sweep (g, h and, for the slots
+ * inside one range, d), 1 its finish (the slots across ranges, the empty
+ * ones), 2 d^T x with the first line-search candidates, 3 Armijo decision
+ * and apply, 4 stopping sweep, 5 single-workgroup kernel (every step of
+ * every bundle of an outer iteration, PCDN_SCHED_NARROW).
+ * pcdn_profile(ctx, mask) brackets every launch of each class whose bit
+ * (1 << class) is set in mask with HIP events on the context's stream (mask
+ * 0: off) and restarts the accumulators;
  * pcdn_profile_read() returns for class `which` the summed event time in ms
  * and the launch count since then (bracketed classes only), and the
  * algorithmic bytes all launches of that class moved since then. */
