@@ -454,8 +454,8 @@ const char* pcdn_last_error(const pcdn_ctx* ctx);
  *    while the solve runs.
  * Every other buffer lives in a workspace of 64 MiB per device compiled into
  * the library (each device the library runs on holds it until the process
- * ends); a problem whose buffers do not fit (roughly 130 bytes per nonzero,
- * 200 per feature and 50 per sample) is rejected with PCDN_E_ARG before any
+ * ends); a problem whose buffers do not fit (roughly 70 bytes per nonzero,
+ * 110 per feature and 50 per sample) is rejected with PCDN_E_ARG before any
  * work.  Every call on one device shares that workspace: calls that overlap
  * on one device (two host threads, or two streams) race and must not be
  * made.  Errors are described by pcdn_last_error(NULL). */

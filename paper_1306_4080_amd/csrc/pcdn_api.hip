@@ -913,7 +913,7 @@ double alg_bytes_of(const Stats& s, const Stats& b, const pcdn_ctx::HostCounts& 
   const double d_sweeps = h.stop_sweeps - hb.stop_sweeps;
   switch (cls) {
     case 0: return kBytesPerNnzSweep * d_nnz_gh + kBytesPerSlotSweep * d_slots;
-    case 1: return 0.0;  // finishes the split columns from partials already counted
+    case 1: return 0.0;  // the sweep's finish: from partials already counted
     case 2: return kBytesPerNnzScatter * d_scat + kBytesPerRowLs * d_rows +
                    kBytesPerSlotLs * d_slots;
     case 3: return kBytesPerRowApply * d_rows + kBytesPerSlotApply * d_slots;
@@ -1131,9 +1131,8 @@ namespace host {
 // Device bytes pcdn_load_csc allocates for (n, p, nnz), each buffer rounded
 // up to 4 KiB, plus the context's own small records.
 int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
-  const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   const int64_t hist_m = radix_hist_ints(p);
-  const int64_t part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
+  const int64_t part_len = 2 * ((nnz + kWave - 1) / kWave) + 2;
   const int64_t br_m = br_hist_ints(nnz);
   const int64_t sizes[] = {
       8 * (p + 1), 4 * nnz, 4 * nnz, n,                    // X, y
@@ -1168,8 +1167,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   if (!col_ptr || !y || (nnz > 0 && (!row_idx || !val)))
     return fail(c, PCDN_E_ARG, "null array");
   if (ptr_kind != 0 && ptr_kind != 1) return fail(c, PCDN_E_ARG, "ptr_kind must be 0 or 1");
-  const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
-  if (max_chunks >= ((int64_t)1 << 31) - 1 || nnz > kMaxNnz)
+  if (nnz > kMaxNnz)
     return fail(c, PCDN_E_ARG, "matrix too large (at most 2^31 - 2^16 nonzeros)");
   HIPCHK(c, hipSetDevice(c->device));
 
@@ -1228,7 +1226,6 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   c->n = n;
   c->p = p;
   c->nnz = nnz;
-  c->max_chunks = max_chunks;
   const int64_t hist_m = radix_hist_ints(p);
   ALLOC(c, c->cp, p + 1);
   ALLOC(c, c->ri, nnz);
@@ -1256,7 +1253,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->rfirst, nnz / kPermW + 2);
   ALLOC(c, c->psrc, p);
   ALLOC(c, c->step_perm, p);
-  c->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
+  c->part_len = 2 * ((nnz + kWave - 1) / kWave) + 2;  // two per range of the smallest width
   ALLOC(c, c->part, c->part_len);
   ALLOC(c, c->pri, nnz);
   ALLOC(c, c->pv, nnz);

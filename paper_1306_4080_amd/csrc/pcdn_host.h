@@ -83,7 +83,6 @@ struct pcdn_ctx {
   int32_t* rfirst = nullptr;     // copy into partition order: slot of each range's first position
   int64_t* psrc = nullptr;       // first nonzero of each slot's column
   int32_t* step_perm = nullptr;
-  int64_t max_chunks = 0;
   double2* part = nullptr;
   int64_t part_len = 0;
   // X in partition order (single-workgroup schedule)

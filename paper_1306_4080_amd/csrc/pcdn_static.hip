@@ -1,6 +1,6 @@
 // pcdn_solve_static: pcdn_solve for callers that cannot allocate device
 // memory.  Every buffer a context would allocate (the retained quantities,
-// the per-slot outputs, the partition and its chunk descriptors, the
+// the per-slot outputs, the partition and the copy working arrays, the
 // partition-order and bundle-row-order copies of X, the CSR copy, the
 // reduction partials, the counters) is carved out of one file-scope device
 // array, `scratch`, whose device address is looked up once per device.  The
@@ -173,7 +173,6 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   pcdn_ctx* t = c ? c : &tmp;
   StaticExtra xt;
   StaticExtra* e = x ? x : &xt;
-  const int64_t max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   const int64_t hist_p = radix_hist_ints(p);
   const int64_t hist_nnz = radix_hist_ints(nnz);      // the sort by row
   const int64_t br_m = std::max(br_hist_ints(nnz), hist_nnz);
@@ -203,7 +202,7 @@ size_t carve(unsigned char* base, pcdn_ctx* c, StaticExtra* x, int64_t n, int64_
   t->nch = k.take<int32_t>(p);
   t->rfirst = k.take<int32_t>(nnz / kPermW + 2);
   t->psrc = k.take<int64_t>(p);
-  t->part_len = std::max<int64_t>(max_chunks, 2 * ((nnz + kWave - 1) / kWave) + 2);
+  t->part_len = 2 * ((nnz + kWave - 1) / kWave) + 2;
   t->part = k.take<double2>(t->part_len);
   t->pri = k.take<int32_t>(nnz);
   t->pv = k.take<float>(nnz);
@@ -315,7 +314,6 @@ int solve_static(int device, hipStream_t stream, int64_t n, int64_t p, int64_t n
   c->n = n;
   c->p = p;
   c->nnz = nnz;
-  c->max_chunks = p + (nnz + kChunkMin - 1) / kChunkMin + 1;
   c->cp = const_cast<int64_t*>(col_ptr);
   // without nonzeros the caller's arrays may be NULL: kernels read element 0
   // of every array (see ldz), so point them at workspace buffers
