@@ -477,12 +477,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t
 
 // ---------------------------------------------------------------------------
 // stable LSD radix sort of 32-bit keys with int32 payload, 8-bit digits.
-// A tile is kSortTile = 1024 keys (256 threads x 4 rounds).  Stability inside a round
+// A tile is kSortTile = 4096 keys (256 threads x 16 rounds).  Stability inside a round
 // comes from wavefront peer masks built with ballots, across waves and rounds
 // from per-digit running offsets in LDS.
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 4;
+constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
 static_assert(kSortThreads == kBlock, "the executor runs the sort passes in kBlock-thread blocks");
@@ -493,9 +493,16 @@ __device__ __forceinline__ void radix_hist_body(const uint32_t* keys, int64_t p,
   cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = bid * kSortTile;
+  uint32_t k[kSortRounds];
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int64_t i = base + r * kSortThreads + threadIdx.x;
-    if (i < p) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1);
+    k[r] = ldz(keys, i < p, i, 0u);
+  }
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < p) atomicAdd(&cnt[(k[r] >> shift) & 255u], 1);
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * ntiles + bid] = cnt[threadIdx.x];
@@ -555,6 +562,89 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t* kin, const int32_t* iin, uint32_t* kout, int32_t* iout, int64_t p, int shift,
     const int32_t* offs, int64_t ntiles) {
   radix_scatter_body(kin, iin, kout, iout, p, shift, offs, ntiles, blockIdx.x);
+}
+
+// The scatter pass of a standalone launch with the tile staged in LDS: the
+// tile's keys are ranked as in radix_scatter_body, placed in digit order in
+// LDS and stored from there, so a digit's run (16 keys of a tile on
+// average) is written by consecutive threads.  The same positions, so the
+// same output.  (The executor keeps radix_scatter_body: its LDS is shared by
+// every task body.)
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter_staged(
+    const uint32_t* kin, const int32_t* iin, uint32_t* kout, int32_t* iout, int64_t p, int shift,
+    const int32_t* offs, int64_t ntiles) {
+  __shared__ int32_t gbase[256];  // output position of the tile's first key of each digit
+  __shared__ int32_t lbase[256];  // the same inside the tile's sorted order
+  __shared__ int32_t run_off[256];
+  __shared__ int32_t wcnt[kWavesPerBlock][256];
+  __shared__ int32_t lds_scan[kSortThreads / kWave + 1];
+  __shared__ uint32_t s_key[kSortTile];
+  __shared__ int32_t s_idx[kSortTile];
+  const int64_t bid = blockIdx.x;
+  const int lane = lane_id(), wv = wave_in_block();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile = bid * kSortTile;
+  const int32_t tcount = (int32_t)(p - tile < kSortTile ? p - tile : kSortTile);
+  gbase[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + bid];
+  wcnt[0][threadIdx.x] = 0;
+  uint32_t key[kSortRounds];
+  int32_t idx[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = tile + r * kSortThreads + threadIdx.x;
+    const bool valid = i < p;
+    key[r] = ldz(kin, valid, i, 0u);
+    idx[r] = ldz(iin, valid, i, 0);
+  }
+  __syncthreads();
+  // the tile's digit counts, then their exclusive scan
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r)
+    if (r * kSortThreads + (int)threadIdx.x < tcount)
+      atomicAdd(&wcnt[0][(key[r] >> shift) & 255u], 1);
+  __syncthreads();
+  int32_t total;
+  const int32_t lb = block_exclusive_scan<kSortThreads>(wcnt[0][threadIdx.x], lds_scan, &total);
+  lbase[threadIdx.x] = lb;
+  run_off[threadIdx.x] = lb;
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const bool valid = r * kSortThreads + (int)threadIdx.x < tcount;
+    const uint32_t dig = (key[r] >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (dig >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const int rank = __popcll(peers & lt_mask);
+    const bool leader = valid && ((peers & lt_mask) == 0);
+    if (leader) wcnt[wv][dig] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int32_t pos = run_off[dig] + rank;
+      for (int w = 0; w < wv; ++w) pos += wcnt[w][dig];
+      s_key[pos] = key[r];
+      s_idx[pos] = idx[r];
+    }
+    __syncthreads();
+    int32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kWavesPerBlock; ++w) add += wcnt[w][threadIdx.x];
+    run_off[threadIdx.x] += add;
+  }
+  __syncthreads();
+  for (int32_t e = threadIdx.x; e < tcount; e += kSortThreads) {
+    const uint32_t k = s_key[e];
+    const uint32_t dg = (k >> shift) & 255u;
+    const int64_t g = (int64_t)gbase[dg] + (e - lbase[dg]);
+    kout[g] = k;
+    iout[g] = s_idx[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2875,7 +2965,7 @@ hipError_t launch_radix_sort(uint32_t* keys0, int32_t* idx0, uint32_t* keys1, in
                        shift, hist, ntiles);
     hipError_t e = launch_scan(hist, hist, m, scan_tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, kin,
+    hipLaunchKernelGGL(k_radix_scatter_staged, dim3((unsigned)ntiles), dim3(kSortThreads), 0, s, kin,
                        iin, kout, iout, p, shift, hist, ntiles);
     uint32_t* tk = kin;
     kin = kout;
