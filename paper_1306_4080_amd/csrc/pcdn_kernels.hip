@@ -477,12 +477,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t
 
 // ---------------------------------------------------------------------------
 // stable LSD radix sort of 32-bit keys with int32 payload, 8-bit digits.
-// A tile is kSortTile = 4096 keys (256 threads x 16 rounds).  Stability inside a round
+// A tile is kSortTile = 2048 keys (256 threads x 8 rounds).  Stability inside a round
 // comes from wavefront peer masks built with ballots, across waves and rounds
 // from per-digit running offsets in LDS.
 // ---------------------------------------------------------------------------
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 16;
+constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
 static_assert(kSortThreads == kBlock, "the executor runs the sort passes in kBlock-thread blocks");
@@ -566,8 +566,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 
 // The scatter pass of a standalone launch with the tile staged in LDS: the
 // tile's keys are ranked as in radix_scatter_body, placed in digit order in
-// LDS and stored from there, so a digit's run (16 keys of a tile on
-// average) is written by consecutive threads.  The same positions, so the
+// LDS and stored from there, so a digit's run (8 keys of a tile on average)
+// is written by consecutive threads.  The same positions, so the
 // same output.  (The executor keeps radix_scatter_body: its LDS is shared by
 // every task body.)
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter_staged(
