@@ -268,6 +268,7 @@ RowsArgs rows_args(pcdn_ctx* c, const Opts& o, const int32_t* perm, int64_t lo, 
   r.rw = c->rw;
   r.y = c->y;
   r.u_cnt = c->u_cnt;
+  r.u_cap = (c->nnz + kRangeW - 1) / kRangeW + 1;  // as allocated
   r.u_row = c->u_row;
   r.u_dtx = c->u_dtx;
   r.part = c->ls_part;

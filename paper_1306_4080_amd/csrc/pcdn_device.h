@@ -166,7 +166,9 @@ struct RowsArgs {
   double* cache;
   double2* rw;               // per-row term weights, kept with cache
   const int8_t* y;
-  int32_t* u_cnt;
+  int32_t* u_cnt;            // rows listed per range (u_cap entries; the d^T x launch
+                             // zeroes those of its wavefronts that have no range)
+  int64_t u_cap;
   int32_t* u_row;
   double* u_dtx;
   double* part;              // [v * G + block]: Q loss sums, Q regulariser sums, Delta, touched

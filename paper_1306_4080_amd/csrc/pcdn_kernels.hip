@@ -1209,6 +1209,12 @@ __device__ __forceinline__ void rows_dtx_body(const RowsArgs& a, int bx) {
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[a.slot_hi];
   const int64_t nr = (e1 - e0 + kRangeW - 1) / kRangeW;
   const int64_t nwaves = (int64_t)G * kWavesPerBlock;
+  {
+    // a wavefront without a range lists none there (the apply reads its
+    // count before it knows the bundle's ranges)
+    const int64_t gw = (int64_t)bx * kWavesPerBlock + wv;
+    if (gw >= nr && gw < a.u_cap && lane == 0) a.u_cnt[gw] = 0;
+  }
   RowQueue& qu = queue[wv];
   // EARLY: the regulariser terms' operands of this thread's first slot,
   // loaded now (they depend on nothing the row sums compute; w from its copy
@@ -1569,7 +1575,9 @@ __device__ __forceinline__ void rows_apply_body(const RowsArgs& a, int64_t bid, 
     f0 = ldz(a.perm, own0, sl0, 0);
     d0 = ldz(a.d, own0, sl0, 0.0);
     w0 = ldz(a.pw, own0, sl0, 0.0);
-    const int32_t cnt0 = ldz(a.u_cnt, gwave < nr, gwave, 0);
+    // the count depends on nothing the offsets give: the d^T x launch wrote
+    // one (0 past the bundle's ranges) for every wavefront of this grid
+    const int32_t cnt0 = ldz(a.u_cnt, gwave < a.u_cap, gwave, 0);
 #pragma unroll
     for (int u = 0; u < kR; ++u) {
       const int32_t i = lane + u * kWave;
