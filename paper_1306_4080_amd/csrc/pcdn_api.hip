@@ -64,7 +64,7 @@ void free_data(pcdn_ctx* c) {
   dfree(c->w); dfree(c->cache); dfree(c->rw); dfree(c->dtx); dfree(c->tmp_n); dfree(c->tmp_p);
   dfree(c->g); dfree(c->h); dfree(c->d); dfree(c->dterm);
   dfree(c->keys0); dfree(c->keys1); dfree(c->idx0); dfree(c->idx1);
-  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->rfirst); dfree(c->psrc);
+  dfree(c->hist); dfree(c->scan_tmp); dfree(c->nch); dfree(c->rfirst); dfree(c->psrc); dfree(c->srow); dfree(c->spos);
   dfree(c->step_perm);
   dfree(c->ccol); dfree(c->rr); dfree(c->islot); dfree(c->br_row); dfree(c->br_slot); dfree(c->br_val);
   dfree(c->bt_row); dfree(c->bt_slot); dfree(c->bt_val); dfree(c->br_hist);
@@ -356,6 +356,8 @@ StopArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
   a.ri = c->ri;
   a.v = c->v;
   a.ccol = c->ccol;
+  a.srow = c->srow;
+  a.spos = c->spos;
   a.cp = c->cp;
   a.y = c->y;
   a.cache = c->cache;
@@ -1149,6 +1151,7 @@ int64_t ctx_footprint_bytes(int64_t n, int64_t p, int64_t nnz) {
       8 * (int64_t)kRowsGridMax * (4 * kQMax + 3),         // line-search partials
       8 * p,                                               // active mask (shrinking)
       8 * (n + 1), 4 * nnz, 4 * nnz, 4 * nnz, 4 * nnz,     // CSR copy, column of each nonzero
+      4 * nnz, 2 * nnz,                                    // stopping-sweep tiles in row order
       4 * p, 12 * nnz, 12 * nnz, 4 * br_m,                 // bundle-row order, sort buffers
       4 * ((nnz + kRangeW - 1) / kRangeW + 1), 12 * (nnz + kRangeW)};  // touched rows
   int64_t total = 64 * 1024;
@@ -1271,6 +1274,8 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
   ALLOC(c, c->rr, nnz);
   ALLOC(c, c->rc, nnz);
   ALLOC(c, c->rv, nnz);
+  ALLOC(c, c->srow, nnz);
+  ALLOC(c, c->spos, nnz);
   ALLOC(c, c->islot, p);
   ALLOC(c, c->br_row, nnz);
   ALLOC(c, c->br_slot, nnz);
@@ -1290,7 +1295,7 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
     for (int64_t k = 0; k < nnz; ++k) ++hrp[Hri[k] + 1];
     for (int64_t i = 0; i < n; ++i) hrp[i + 1] += hrp[i];
     std::vector<int64_t> next(hrp.begin(), hrp.end() - 1);
-    std::vector<int32_t> hrr(nnz), hrc(nnz);
+    std::vector<int32_t> hrr(nnz), hrc(nnz), hk(nnz);
     std::vector<float> hrv(nnz);
     std::vector<double> l1(n, 0.0);
     for (int64_t j = 0; j < p; ++j)
@@ -1299,8 +1304,24 @@ extern "C" int pcdn_load_csc(pcdn_ctx* c, int64_t n, int64_t p, int64_t nnz,
         hrr[at] = Hri[k];
         hrc[at] = (int32_t)j;
         hrv[at] = Hv[k];
+        hk[at] = (int32_t)k;
         l1[Hri[k]] += std::fabs((double)Hv[k]);
       }
+    // the stopping sweep's tiles (kStopTile consecutive nonzeros of the CSC
+    // order): each tile's nonzeros in row order, from the CSR order
+    if (nnz) {
+      std::vector<int32_t> hsr(nnz);
+      std::vector<uint16_t> hsp(nnz);
+      std::vector<int64_t> fill((nnz + kStopTile - 1) / kStopTile, 0);
+      for (int64_t at = 0; at < nnz; ++at) {
+        const int64_t t = hk[at] / kStopTile;
+        const int64_t e = t * kStopTile + fill[t]++;
+        hsr[e] = hrr[at];
+        hsp[e] = (uint16_t)(hk[at] - t * kStopTile);
+      }
+      HIPCHK(c, hipMemcpy(c->srow, hsr.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+      HIPCHK(c, hipMemcpy(c->spos, hsp.data(), nnz * sizeof(uint16_t), hipMemcpyHostToDevice));
+    }
     c->xrow = 0.0;
     for (int64_t i = 0; i < n; ++i) c->xrow = std::max(c->xrow, l1[i]);
     HIPCHK(c, hipMemcpy(c->rp, hrp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));

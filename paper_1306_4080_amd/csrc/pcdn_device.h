@@ -123,6 +123,7 @@ struct SweepArgs {
 // begins in m and continues), and k_stop_finish completes those and the empty
 // columns, adding the partials in range order.
 constexpr int kStopW = 256;
+constexpr int kStopTile = 16384;  // nonzeros per workgroup of the tiled stopping sweep
 struct StopArgs {
   const int32_t* ri;
   const float* v;
@@ -139,6 +140,10 @@ struct StopArgs {
   double2* part;             // per range
   const double* Cp;          // C (device scalar)
   double ra, rb;
+  // nullable: per kStopTile tile of consecutive nonzeros, the tile's
+  // nonzeros in row order (row, position in the tile)
+  const int32_t* srow;
+  const uint16_t* spos;
 };
 
 // Multi-kernel bundle after the sweep: the bundle's nonzeros in row order

@@ -81,6 +81,8 @@ struct pcdn_ctx {
   int32_t* scan_tmp = nullptr;
   int32_t* nch = nullptr;
   int32_t* rfirst = nullptr;     // copy into partition order: slot of each range's first position
+  int32_t* srow = nullptr;       // stopping-sweep tiles: each tile's nonzeros in row order
+  uint16_t* spos = nullptr;      //   and their positions in the tile (null: no tiles)
   int64_t* psrc = nullptr;       // first nonzero of each slot's column
   int32_t* step_perm = nullptr;
   double2* part = nullptr;

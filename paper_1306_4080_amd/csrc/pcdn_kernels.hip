@@ -926,131 +926,205 @@ __device__ inline StopScalars stop_scalars(const StopArgs& a) {
   return {*a.Cp, a.act ? *a.thr : 0.0};
 }
 
-// Wavefront w of the launch takes ranges w, w + nwaves, ...; lane L holds
-// the range's nonzeros 4L .. 4L+3.  A lane first sums its own nonzeros per
+// Range m of the stopping sweep (one wavefront); lane L holds the range's
+// nonzeros 4L .. 4L+3.  A lane first sums its own nonzeros per
 // column in order (columns that start and end inside the lane are finished
 // there); one segmented wavefront scan over the lanes' last runs (keys =
 // column) then carries the runs across lanes, and each column is finished by
 // the lane where it ends, in the same left-to-right order of its nonzeros.
-template <int LOSS>
-__device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid, int64_t nblk) {
+template <int LOSS, bool FROM_LDS>
+__device__ inline void stop_one_range(const StopArgs& a, int64_t m, const StopScalars& sc,
+                                      const double* lgw, int64_t lbase) {
   constexpr int kE = kStopW / kWave;  // consecutive nonzeros per lane
   const int lane = lane_id();
-  const int64_t nr = (a.nnz + kStopW - 1) / kStopW;
-  const int64_t nwaves = nblk * kWavesPerBlock;
-  const StopScalars sc = stop_scalars(a);
   // w of a nonzero's column (w = 0 when a.w is null: a load of the always
   // valid cache[0], discarded)
   const double* wsrc = a.w ? a.w : a.cache;
-  for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
-    const int64_t rb = m * kStopW;
-    const int64_t re = rb + kStopW < a.nnz ? rb + kStopW : a.nnz;
-    const int64_t k0 = rb + (int64_t)lane * kE;
-    int32_t col[kE], row[kE];
-    float xv[kE];
+  const int64_t rb = m * kStopW;
+  const int64_t re = rb + kStopW < a.nnz ? rb + kStopW : a.nnz;
+  const int64_t k0 = rb + (int64_t)lane * kE;
+  int32_t col[kE], row[kE];
+  float xv[kE];
+  static_assert(kE == 4, "a lane's nonzeros are one 16-byte vector of each array");
+  const bool aligned = ((reinterpret_cast<uintptr_t>(a.ccol) | reinterpret_cast<uintptr_t>(a.v) |
+                         (FROM_LDS ? 0 : reinterpret_cast<uintptr_t>(a.ri))) & 15) == 0;
+  if (re - rb == kStopW && aligned) {
+    // a whole range: 16-byte loads (rb is a multiple of kStopW, so k0 of 4)
+    const int4 c4 = *reinterpret_cast<const int4*>(a.ccol + k0);
+    const float4 v4 = *reinterpret_cast<const float4*>(a.v + k0);
+    col[0] = c4.x; col[1] = c4.y; col[2] = c4.z; col[3] = c4.w;
+    xv[0] = v4.x; xv[1] = v4.y; xv[2] = v4.z; xv[3] = v4.w;
+    if (FROM_LDS) {
+      row[0] = row[1] = row[2] = row[3] = 0;
+    } else {
+      const int4 r4 = *reinterpret_cast<const int4*>(a.ri + k0);
+      row[0] = r4.x; row[1] = r4.y; row[2] = r4.z; row[3] = r4.w;
+    }
+  } else {
 #pragma unroll
     for (int u = 0; u < kE; ++u) {
       const int64_t k = k0 + u;
       const bool in = k < re;
       col[u] = ldz(a.ccol, in, k, -1);
-      row[u] = ldz(a.ri, in, k, 0);
+      row[u] = FROM_LDS ? 0 : ldz(a.ri, in, k, 0);
       xv[u] = ldz(a.v, in, k, 0.0f);
     }
-    // columns open at the range's ends
-    const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
-    const int32_t right = re < a.nnz ? a.ccol[re] : -1;
-    // the rows' gradient weights alone (the first of the two row weights;
-    // zero where an SVM row has no slack, so the product is the term)
-    const double* gw = reinterpret_cast<const double*>(a.rw);
-    double rg[kE];
-    double wv[kE];
-#pragma unroll
-    for (int u = 0; u < kE; ++u) {
-      rg[u] = ldz(gw, col[u] >= 0, 2 * (int64_t)row[u], 0.0);
-      wv[u] = ldz(wsrc, col[u] >= 0 && a.w != nullptr, col[u], 0.0);
-    }
-    // every operand loaded before the first use (the compiler would sink
-    // loads into the finishing branches and wait for each there)
-#pragma unroll
-    for (int u = 0; u < kE; ++u) asm volatile("" ::"v"(rg[u]), "v"(wv[u]), "v"(xv[u]));
-    // the lane's runs: head (from its first nonzero), complete middles, tail
-    const int32_t hk = col[0];
-    const double hw = wv[0];
-    int32_t rk = col[0];
-    double run = col[0] >= 0 ? rg[0] * (double)xv[0] : 0.0;
-    double wk = wv[0], hs = 0.0;
-    bool whole = true;  // one run covers the lane's nonzeros
-#pragma unroll
-    for (int u = 1; u < kE; ++u) {
-      const double t = col[u] >= 0 ? rg[u] * (double)xv[u] : 0.0;
-      if (col[u] == rk) {
-        run += t;
-      } else {
-        if (whole) {
-          hs = run;  // the head run ends inside the lane
-          whole = false;
-        } else if (rk >= 0) {
-          stop_finish_one<LOSS>(a, rk, run, sc.C, sc.thr, wk);  // starts and ends here
-        }
-        rk = col[u];
-        run = t;
-        wk = wv[u];
-      }
-    }
-    if (whole) hs = run;
-    // tail runs carried over the lanes of equal column
-    const int32_t tk = rk;
-    double S = run;
-    seg_scan1(S, tk);
-    const int32_t pk = __builtin_amdgcn_update_dpp(-1, tk, 0x138, 0xf, 0xf, false);  // lane - 1
-    const double pS = dpp_f64<0x138, 0xf, 0xf>(S);
-    const int32_t nk = next_lane_key(hk);  // the next lane's first column
-    const int last_lane = (int)((re - 1 - rb) / kE);
-    double pf = 0.0, pl = 0.0;
-    if (!whole && hk >= 0) {
-      // the head run ends in this lane: add what the previous lanes carried
-      const double H = hs + (lane > 0 && pk == hk ? pS : 0.0);
-      if (hk == left)
-        pf = H;
-      else
-        stop_finish_one<LOSS>(a, hk, H, sc.C, sc.thr, hw);
-    }
-    if (tk >= 0 && lane <= last_lane) {
-      const bool at_end = lane == last_lane;
-      const bool cont = at_end ? right == tk : nk == tk;
-      if (at_end || !cont) {
-        if (tk == left)
-          pf = S;  // (also when right-open: a column through the whole range)
-        else if (cont)
-          pl = S;
-        else
-          stop_finish_one<LOSS>(a, tk, S, sc.C, sc.thr, wk);
-      }
-    }
-    // the partials (held by the lanes that ended the open runs)
-    const uint64_t mf = __ballot(pf != 0.0), ml = __ballot(pl != 0.0);
-    double2 pr = make_double2(0.0, 0.0);
-    if (mf) {
-      const int src = __builtin_ctzll(mf);
-      const unsigned long long b = (unsigned long long)__double_as_longlong(pf);
-      const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
-      const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
-      pr.x = __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
-    }
-    if (ml) {
-      const int src = __builtin_ctzll(ml);
-      const unsigned long long b = (unsigned long long)__double_as_longlong(pl);
-      const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
-      const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
-      pr.y = __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
-    }
-    if (lane == 0) a.part[m] = pr;
   }
+  // columns open at the range's ends
+  const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
+  const int32_t right = re < a.nnz ? a.ccol[re] : -1;
+  // the rows' gradient weights alone (the first of the two row weights;
+  // zero where an SVM row has no slack, so the product is the term):
+  // gathered, or (FROM_LDS) already placed at the nonzero's position
+  const double* gw = reinterpret_cast<const double*>(a.rw);
+  double rg[kE];
+  double wv[kE];
+#pragma unroll
+  for (int u = 0; u < kE; ++u) {
+    rg[u] = FROM_LDS ? (col[u] >= 0 ? lgw[k0 + u - lbase] : 0.0)
+                     : ldz(gw, col[u] >= 0, 2 * (int64_t)row[u], 0.0);
+    wv[u] = ldz(wsrc, col[u] >= 0 && a.w != nullptr, col[u], 0.0);
+  }
+  // every operand loaded before the first use (the compiler would sink
+  // loads into the finishing branches and wait for each there)
+#pragma unroll
+  for (int u = 0; u < kE; ++u) asm volatile("" ::"v"(rg[u]), "v"(wv[u]), "v"(xv[u]));
+  // the lane's runs: head (from its first nonzero), complete middles, tail
+  const int32_t hk = col[0];
+  const double hw = wv[0];
+  int32_t rk = col[0];
+  double run = col[0] >= 0 ? rg[0] * (double)xv[0] : 0.0;
+  double wk = wv[0], hs = 0.0;
+  bool whole = true;  // one run covers the lane's nonzeros
+#pragma unroll
+  for (int u = 1; u < kE; ++u) {
+    const double t = col[u] >= 0 ? rg[u] * (double)xv[u] : 0.0;
+    if (col[u] == rk) {
+      run += t;
+    } else {
+      if (whole) {
+        hs = run;  // the head run ends inside the lane
+        whole = false;
+      } else if (rk >= 0) {
+        stop_finish_one<LOSS>(a, rk, run, sc.C, sc.thr, wk);  // starts and ends here
+      }
+      rk = col[u];
+      run = t;
+      wk = wv[u];
+    }
+  }
+  if (whole) hs = run;
+  // tail runs carried over the lanes of equal column
+  const int32_t tk = rk;
+  double S = run;
+  seg_scan1(S, tk);
+  const int32_t pk = __builtin_amdgcn_update_dpp(-1, tk, 0x138, 0xf, 0xf, false);  // lane - 1
+  const double pS = dpp_f64<0x138, 0xf, 0xf>(S);
+  const int32_t nk = next_lane_key(hk);  // the next lane's first column
+  const int last_lane = (int)((re - 1 - rb) / kE);
+  double pf = 0.0, pl = 0.0;
+  if (!whole && hk >= 0) {
+    // the head run ends in this lane: add what the previous lanes carried
+    const double H = hs + (lane > 0 && pk == hk ? pS : 0.0);
+    if (hk == left)
+      pf = H;
+    else
+      stop_finish_one<LOSS>(a, hk, H, sc.C, sc.thr, hw);
+  }
+  if (tk >= 0 && lane <= last_lane) {
+    const bool at_end = lane == last_lane;
+    const bool cont = at_end ? right == tk : nk == tk;
+    if (at_end || !cont) {
+      if (tk == left)
+        pf = S;  // (also when right-open: a column through the whole range)
+      else if (cont)
+        pl = S;
+      else
+        stop_finish_one<LOSS>(a, tk, S, sc.C, sc.thr, wk);
+    }
+  }
+  // the partials (held by the lanes that ended the open runs)
+  const uint64_t mf = __ballot(pf != 0.0), ml = __ballot(pl != 0.0);
+  double2 pr = make_double2(0.0, 0.0);
+  if (mf) {
+    const int src = __builtin_ctzll(mf);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(pf);
+    const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+    const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    pr.x = __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
+  }
+  if (ml) {
+    const int src = __builtin_ctzll(ml);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(pl);
+    const unsigned l2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), src);
+    const unsigned h2 = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+    pr.y = __longlong_as_double((long long)(((unsigned long long)h2 << 32) | l2));
+  }
+  if (lane == 0) a.part[m] = pr;
+}
+
+// Wavefront w of the launch takes ranges w, w + nwaves, ... (the rows'
+// weights gathered from global memory).
+template <int LOSS>
+__device__ __forceinline__ void stop_ranges_body(const StopArgs& a, int64_t bid, int64_t nblk) {
+  const int64_t nr = (a.nnz + kStopW - 1) / kStopW;
+  const int64_t nwaves = nblk * kWavesPerBlock;
+  const StopScalars sc = stop_scalars(a);
+  for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves)
+    stop_one_range<LOSS, false>(a, m, sc, nullptr, 0);
 }
 
 template <int LOSS>
 __global__ __launch_bounds__(kBlock) void k_stop_ranges(StopArgs a) {
   stop_ranges_body<LOSS>(a, blockIdx.x, gridDim.x);
+}
+
+// The stopping sweep by tiles of kStopTile consecutive nonzeros (whole
+// ranges), one 1024-thread workgroup each, when the tiles' row-sorted lists
+// exist (a.srow, a.spos: each tile's nonzeros in row order, with their
+// positions in the tile).  The workgroup first gathers the rows' gradient
+// weights in row order, so consecutive threads read neighbouring rows (a
+// tile touches a sixth of the 100,000 rows of the huge sparse workload, so
+// most 128-byte lines serve several nonzeros instead of one), and places
+// each at its nonzero's position in LDS; then its wavefronts run the tile's
+// ranges as stop_ranges_body does, reading the weights from LDS.  The sums
+// and their order are those of stop_ranges_body, so are the results.
+constexpr int kStopTileThreads = 1024;
+constexpr int kStopTileRounds = 16;
+static_assert(kStopTile == kStopTileThreads * kStopTileRounds, "one weight per thread and round");
+template <int LOSS>
+__global__ __launch_bounds__(kStopTileThreads) void k_stop_tiles(StopArgs a) {
+  __shared__ double lgw[kStopTile];
+  const int64_t base = (int64_t)blockIdx.x * kStopTile;
+  const int64_t tcount = a.nnz - base < kStopTile ? a.nnz - base : kStopTile;
+  const double* gw = reinterpret_cast<const double*>(a.rw);
+  {
+    int32_t row[kStopTileRounds];
+    int32_t pos[kStopTileRounds];
+#pragma unroll
+    for (int r = 0; r < kStopTileRounds; ++r) {
+      const int64_t e = (int64_t)r * kStopTileThreads + threadIdx.x;
+      row[r] = ldz(a.srow, e < tcount, base + e, 0);
+      pos[r] = (int32_t)ldz(a.spos, e < tcount, base + e, (uint16_t)0);
+    }
+    double g[kStopTileRounds];
+#pragma unroll
+    for (int r = 0; r < kStopTileRounds; ++r) {
+      const int64_t e = (int64_t)r * kStopTileThreads + threadIdx.x;
+      g[r] = ldz(gw, e < tcount, 2 * (int64_t)row[r], 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < kStopTileRounds; ++r) {
+      const int64_t e = (int64_t)r * kStopTileThreads + threadIdx.x;
+      if (e < tcount) lgw[pos[r]] = g[r];
+    }
+  }
+  __syncthreads();
+  const StopScalars sc = stop_scalars(a);
+  const int64_t nr = (tcount + kStopW - 1) / kStopW;
+  const int64_t m0 = base / kStopW;
+  for (int64_t j = threadIdx.x / kWave; j < nr; j += kStopTileThreads / kWave)
+    stop_one_range<LOSS, true>(a, m0 + uniform(j), sc, lgw, base);
 }
 
 // Columns that cross a range boundary (the partials in range order) and
@@ -3090,11 +3164,19 @@ int stop_finish_grid(int64_t p) { return grid_for(p, kBlock, 4096); }
 
 hipError_t launch_stop_sweep(int loss, const StopArgs& a, hipStream_t s) {
   const dim3 g1(stop_ranges_grid(a.nnz)), g2(stop_finish_grid(a.p));
+  const dim3 gt((unsigned)((a.nnz + kStopTile - 1) / kStopTile));
+  const bool tiles = a.srow && a.spos;
   if (loss == kLogistic) {
-    if (a.nnz > 0) hipLaunchKernelGGL(k_stop_ranges<kLogistic>, g1, dim3(kBlock), 0, s, a);
+    if (a.nnz > 0 && tiles)
+      hipLaunchKernelGGL(k_stop_tiles<kLogistic>, gt, dim3(kStopTileThreads), 0, s, a);
+    else if (a.nnz > 0)
+      hipLaunchKernelGGL(k_stop_ranges<kLogistic>, g1, dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_stop_finish<kLogistic>, g2, dim3(kBlock), 0, s, a);
   } else {
-    if (a.nnz > 0) hipLaunchKernelGGL(k_stop_ranges<kL2Svm>, g1, dim3(kBlock), 0, s, a);
+    if (a.nnz > 0 && tiles)
+      hipLaunchKernelGGL(k_stop_tiles<kL2Svm>, gt, dim3(kStopTileThreads), 0, s, a);
+    else if (a.nnz > 0)
+      hipLaunchKernelGGL(k_stop_ranges<kL2Svm>, g1, dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_stop_finish<kL2Svm>, g2, dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
