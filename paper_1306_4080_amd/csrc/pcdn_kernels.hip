@@ -705,22 +705,47 @@ __device__ __forceinline__ void sweep_ranges_body(const SweepArgs& a, int64_t bi
   const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
   if (hi <= a.slot_lo) return;
   const int64_t e0 = a.poff[a.slot_lo], e1 = a.poff[hi];
-  const int64_t nr = (e1 - e0 + kW - 1) / kW;
+  // ranges start at e0 rounded down to 4 nonzeros (the first range's
+  // nonzeros before e0 belong to the bundle before and are left out), so a
+  // lane's nonzeros of a whole range are one aligned vector of each array
+  const int64_t e0a = e0 & ~(int64_t)3;
+  const int64_t nr = (e1 - e0a + kW - 1) / kW;
   const int64_t nwaves = nblk * kWavesPerBlock;
   const double C = *a.Cp;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(a.pslot) | reinterpret_cast<uintptr_t>(a.pri) |
+                         reinterpret_cast<uintptr_t>(a.pv)) & 15) == 0;
   for (int64_t m = uniform((bid * kBlock + threadIdx.x) / kWave); m < nr; m += nwaves) {
-    const int64_t rb = e0 + m * kW;
+    const int64_t rb = e0a + m * kW;
     const int64_t re = rb + kW < e1 ? rb + kW : e1;
     const int64_t k0 = rb + (int64_t)lane * kE;
     int32_t sl[kE], row[kE];
     float xv[kE];
+    if (kE % 4 == 0 && aligned && rb >= e0 && re - rb == kW) {
 #pragma unroll
-    for (int u = 0; u < kE; ++u) {
-      const int64_t k = k0 + u;
-      const bool in = k < re;
-      sl[u] = ldz(a.pslot, in, k, -1);
-      row[u] = ldz(a.pri, in, k, 0);
-      xv[u] = ldz(a.pv, in, k, 0.0f);
+      for (int q = 0; q < kE / 4; ++q) {
+        const int4 s4 = *reinterpret_cast<const int4*>(a.pslot + k0 + 4 * q);
+        const int4 r4 = *reinterpret_cast<const int4*>(a.pri + k0 + 4 * q);
+        const float4 v4 = *reinterpret_cast<const float4*>(a.pv + k0 + 4 * q);
+        sl[4 * q] = s4.x; sl[4 * q + 1] = s4.y; sl[4 * q + 2] = s4.z; sl[4 * q + 3] = s4.w;
+        row[4 * q] = r4.x; row[4 * q + 1] = r4.y; row[4 * q + 2] = r4.z; row[4 * q + 3] = r4.w;
+        xv[4 * q] = v4.x; xv[4 * q + 1] = v4.y; xv[4 * q + 2] = v4.z; xv[4 * q + 3] = v4.w;
+      }
+    } else if (kE == 2 && aligned && rb >= e0 && re - rb == kW) {
+      const int2 s2 = *reinterpret_cast<const int2*>(a.pslot + k0);
+      const int2 r2 = *reinterpret_cast<const int2*>(a.pri + k0);
+      const float2 v2 = *reinterpret_cast<const float2*>(a.pv + k0);
+      sl[0] = s2.x; sl[kE - 1] = s2.y;
+      row[0] = r2.x; row[kE - 1] = r2.y;
+      xv[0] = v2.x; xv[kE - 1] = v2.y;
+    } else {
+#pragma unroll
+      for (int u = 0; u < kE; ++u) {
+        const int64_t k = k0 + u;
+        const bool in = k >= e0 && k < re;
+        sl[u] = ldz(a.pslot, in, k, -1);
+        row[u] = ldz(a.pri, in, k, 0);
+        xv[u] = ldz(a.pv, in, k, 0.0f);
+      }
     }
     // slots open at the range's ends
     const int32_t left = rb > e0 ? a.pslot[rb - 1] : -1;
@@ -856,7 +881,7 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& a, int64_t bi
   const int64_t hi = clipped_hi(a.slot_hi, a.p_active);
   if (hi <= a.slot_lo) return;
   const int lane = lane_id();
-  const int64_t e0 = a.poff[a.slot_lo];
+  const int64_t e0a = a.poff[a.slot_lo] & ~(int64_t)3;  // where the sweep's ranges start
   const double C = *a.Cp;
   const int wsh = __builtin_ctz((unsigned)a.W);  // range index = offset >> wsh (W a power of 2)
   const int64_t nwaves = nblk * kWavesPerBlock;
@@ -865,7 +890,7 @@ __device__ __forceinline__ void sweep_finish_body(const SweepArgs& a, int64_t bi
     const int64_t o = base + lane;
     const bool valid = o < hi;
     const int64_t k0 = ldz(a.poff, valid, o, (int64_t)0), k1 = ldz(a.poff, valid, o + 1, (int64_t)0);
-    const int64_t m1 = (k0 - e0) >> wsh, m2 = k1 > k0 ? (k1 - 1 - e0) >> wsh : m1;
+    const int64_t m1 = (k0 - e0a) >> wsh, m2 = k1 > k0 ? (k1 - 1 - e0a) >> wsh : m1;
     const bool empty = valid && k1 == k0;
     const bool crossing = valid && k1 > k0 && m2 > m1;
     const bool longer = crossing && m2 - m1 > kFinishShort;
