@@ -952,68 +952,94 @@ __device__ inline StopScalars stop_scalars(const StopArgs& a) {
 }
 
 // Range m of the stopping sweep (one wavefront); lane L holds the range's
-// nonzeros 4L .. 4L+3.  A lane first sums its own nonzeros per
-// column in order (columns that start and end inside the lane are finished
-// there); one segmented wavefront scan over the lanes' last runs (keys =
-// column) then carries the runs across lanes, and each column is finished by
-// the lane where it ends, in the same left-to-right order of its nonzeros.
-template <int LOSS, bool FROM_LDS>
-__device__ inline void stop_one_range(const StopArgs& a, int64_t m, const StopScalars& sc,
-                                      const double* lgw, int64_t lbase) {
-  constexpr int kE = kStopW / kWave;  // consecutive nonzeros per lane
+// nonzeros 4L .. 4L+3.  In three parts, so that a caller can issue the
+// loads of several ranges before it waits for any: the range's columns and
+// values (and rows, for the gather), the rows' gradient weights and the
+// columns' w, then the sums.
+constexpr int kStopE = kStopW / kWave;  // consecutive nonzeros per lane
+static_assert(kStopE == 4, "a lane's nonzeros are one 16-byte vector of each array");
+struct StopOps {
+  int64_t rb, re;
+  int32_t col[kStopE], row[kStopE];
+  float xv[kStopE];
+  double rg[kStopE], wv[kStopE];
+  int32_t left, right;
+};
+
+template <bool FROM_LDS>
+__device__ inline void stop_range_load(const StopArgs& a, int64_t m, StopOps& o) {
+  constexpr int kE = kStopE;
   const int lane = lane_id();
-  // w of a nonzero's column (w = 0 when a.w is null: a load of the always
-  // valid cache[0], discarded)
-  const double* wsrc = a.w ? a.w : a.cache;
-  const int64_t rb = m * kStopW;
-  const int64_t re = rb + kStopW < a.nnz ? rb + kStopW : a.nnz;
+  o.rb = m * kStopW;
+  o.re = o.rb + kStopW < a.nnz ? o.rb + kStopW : a.nnz;
+  const int64_t rb = o.rb, re = o.re;
   const int64_t k0 = rb + (int64_t)lane * kE;
-  int32_t col[kE], row[kE];
-  float xv[kE];
-  static_assert(kE == 4, "a lane's nonzeros are one 16-byte vector of each array");
   const bool aligned = ((reinterpret_cast<uintptr_t>(a.ccol) | reinterpret_cast<uintptr_t>(a.v) |
                          (FROM_LDS ? 0 : reinterpret_cast<uintptr_t>(a.ri))) & 15) == 0;
   if (re - rb == kStopW && aligned) {
     // a whole range: 16-byte loads (rb is a multiple of kStopW, so k0 of 4)
     const int4 c4 = *reinterpret_cast<const int4*>(a.ccol + k0);
     const float4 v4 = *reinterpret_cast<const float4*>(a.v + k0);
-    col[0] = c4.x; col[1] = c4.y; col[2] = c4.z; col[3] = c4.w;
-    xv[0] = v4.x; xv[1] = v4.y; xv[2] = v4.z; xv[3] = v4.w;
+    o.col[0] = c4.x; o.col[1] = c4.y; o.col[2] = c4.z; o.col[3] = c4.w;
+    o.xv[0] = v4.x; o.xv[1] = v4.y; o.xv[2] = v4.z; o.xv[3] = v4.w;
     if (FROM_LDS) {
-      row[0] = row[1] = row[2] = row[3] = 0;
+      o.row[0] = o.row[1] = o.row[2] = o.row[3] = 0;
     } else {
       const int4 r4 = *reinterpret_cast<const int4*>(a.ri + k0);
-      row[0] = r4.x; row[1] = r4.y; row[2] = r4.z; row[3] = r4.w;
+      o.row[0] = r4.x; o.row[1] = r4.y; o.row[2] = r4.z; o.row[3] = r4.w;
     }
   } else {
 #pragma unroll
     for (int u = 0; u < kE; ++u) {
       const int64_t k = k0 + u;
       const bool in = k < re;
-      col[u] = ldz(a.ccol, in, k, -1);
-      row[u] = FROM_LDS ? 0 : ldz(a.ri, in, k, 0);
-      xv[u] = ldz(a.v, in, k, 0.0f);
+      o.col[u] = ldz(a.ccol, in, k, -1);
+      o.row[u] = FROM_LDS ? 0 : ldz(a.ri, in, k, 0);
+      o.xv[u] = ldz(a.v, in, k, 0.0f);
     }
   }
   // columns open at the range's ends
-  const int32_t left = rb > 0 ? a.ccol[rb - 1] : -1;
-  const int32_t right = re < a.nnz ? a.ccol[re] : -1;
-  // the rows' gradient weights alone (the first of the two row weights;
-  // zero where an SVM row has no slack, so the product is the term):
-  // gathered, or (FROM_LDS) already placed at the nonzero's position
+  o.left = rb > 0 ? a.ccol[rb - 1] : -1;
+  o.right = re < a.nnz ? a.ccol[re] : -1;
+}
+
+// The rows' gradient weights alone (the first of the two row weights; zero
+// where an SVM row has no slack, so the product is the term): gathered, or
+// (FROM_LDS) already placed at the nonzero's position; and the columns' w
+// (w = 0 when a.w is null: a load of the always valid cache[0], discarded).
+template <bool FROM_LDS>
+__device__ inline void stop_range_gather(const StopArgs& a, StopOps& o, const double* lgw,
+                                         int64_t lbase) {
+  constexpr int kE = kStopE;
+  const int64_t k0 = o.rb + (int64_t)lane_id() * kE;
   const double* gw = reinterpret_cast<const double*>(a.rw);
-  double rg[kE];
-  double wv[kE];
+  const double* wsrc = a.w ? a.w : a.cache;
 #pragma unroll
   for (int u = 0; u < kE; ++u) {
-    rg[u] = FROM_LDS ? (col[u] >= 0 ? lgw[k0 + u - lbase] : 0.0)
-                     : ldz(gw, col[u] >= 0, 2 * (int64_t)row[u], 0.0);
-    wv[u] = ldz(wsrc, col[u] >= 0 && a.w != nullptr, col[u], 0.0);
+    o.rg[u] = FROM_LDS ? (o.col[u] >= 0 ? lgw[k0 + u - lbase] : 0.0)
+                       : ldz(gw, o.col[u] >= 0, 2 * (int64_t)o.row[u], 0.0);
+    o.wv[u] = ldz(wsrc, o.col[u] >= 0 && a.w != nullptr, o.col[u], 0.0);
   }
-  // every operand loaded before the first use (the compiler would sink
-  // loads into the finishing branches and wait for each there)
+}
+
+// every operand loaded before the first use (the compiler would sink loads
+// into the finishing branches and wait for each there)
+__device__ inline void stop_range_pin(StopOps& o) {
 #pragma unroll
-  for (int u = 0; u < kE; ++u) asm volatile("" ::"v"(rg[u]), "v"(wv[u]), "v"(xv[u]));
+  for (int u = 0; u < kStopE; ++u) asm volatile("" ::"v"(o.rg[u]), "v"(o.wv[u]), "v"(o.xv[u]));
+}
+
+template <int LOSS>
+__device__ inline void stop_range_sums(const StopArgs& a, int64_t m, const StopScalars& sc,
+                                       const StopOps& o) {
+  constexpr int kE = kStopE;
+  const int lane = lane_id();
+  const int64_t rb = o.rb, re = o.re;
+  const int32_t* col = o.col;
+  const float* xv = o.xv;
+  const double* rg = o.rg;
+  const double* wv = o.wv;
+  const int32_t left = o.left, right = o.right;
   // the lane's runs: head (from its first nonzero), complete middles, tail
   const int32_t hk = col[0];
   const double hw = wv[0];
@@ -1088,6 +1114,16 @@ __device__ inline void stop_one_range(const StopArgs& a, int64_t m, const StopSc
   if (lane == 0) a.part[m] = pr;
 }
 
+template <int LOSS, bool FROM_LDS>
+__device__ inline void stop_one_range(const StopArgs& a, int64_t m, const StopScalars& sc,
+                                      const double* lgw, int64_t lbase) {
+  StopOps o;
+  stop_range_load<FROM_LDS>(a, m, o);
+  stop_range_gather<FROM_LDS>(a, o, lgw, lbase);
+  stop_range_pin(o);
+  stop_range_sums<LOSS>(a, m, sc, o);
+}
+
 // Wavefront w of the launch takes ranges w, w + nwaves, ... (the rows'
 // weights gathered from global memory).
 template <int LOSS>
@@ -1148,8 +1184,22 @@ __global__ __launch_bounds__(kStopTileThreads) void k_stop_tiles(StopArgs a) {
   const StopScalars sc = stop_scalars(a);
   const int64_t nr = (tcount + kStopW - 1) / kStopW;
   const int64_t m0 = base / kStopW;
-  for (int64_t j = threadIdx.x / kWave; j < nr; j += kStopTileThreads / kWave)
-    stop_one_range<LOSS, true>(a, m0 + uniform(j), sc, lgw, base);
+  // two ranges at a time, both ranges' loads issued before either is summed
+  // (a missing second range repeats the first's loads and is not summed)
+  constexpr int kWaves = kStopTileThreads / kWave;
+  for (int64_t j = uniform(threadIdx.x / kWave); j < nr; j += 2 * kWaves) {
+    const bool two = j + kWaves < nr;
+    const int64_t jb = two ? j + kWaves : j;
+    StopOps o1, o2;
+    stop_range_load<true>(a, m0 + j, o1);
+    stop_range_load<true>(a, m0 + jb, o2);
+    stop_range_gather<true>(a, o1, lgw, base);
+    stop_range_gather<true>(a, o2, lgw, base);
+    stop_range_pin(o1);
+    stop_range_pin(o2);
+    stop_range_sums<LOSS>(a, m0 + j, sc, o1);
+    if (two) stop_range_sums<LOSS>(a, m0 + jb, sc, o2);
+  }
 }
 
 // Columns that cross a range boundary (the partials in range order) and
