@@ -31,7 +31,7 @@ More objects on the same line:
 - "batched" (skipped with --no-batched): 64 independent LR problems (n
   U[500,20000], p U[1000,100000], density U[0.001,0.02]) solved to
   eps = 1e-4 one pcdn_solve after another and in one pcdn_solve_batch call
-  (bundle size, schedule and chunk length from the autotuner, tuned before
+  (bundle size, schedule and range width from the autotuner, tuned before
   timing);
 - "path": 32 C values on the text-like matrix with warm starts,
   pcdn_solve_path against the same chain of pcdn_solve calls, against the
@@ -64,7 +64,7 @@ KERNEL_NAMES = ("k_sweep_ranges (gradient/Hessian sweep and direction over the b
                 "k_sweep_finish (slots crossing a range boundary, and empty slots)",
                 "k_rows_dtx (d^T x by row and the first line-search candidates)",
                 "k_rows_apply (Armijo decision, w and retained-quantity update)",
-                "k_stop_ranges+k_stop_finish (full-gradient subgradient norm)",
+                "k_stop_tiles+k_stop_finish (full-gradient subgradient norm)",
                 "k_narrow (one workgroup runs every bundle of an outer iteration)")
 C3 = dict(C=1.0, P=16384, eps=1e-3, loss="svm")
 SETTINGS = [(0.5, 64), (0.5, 1024), (0.5, 8192), (4.0, 64), (4.0, 1024), (4.0, 8192)]
@@ -189,7 +189,7 @@ def _chosen_pilot(t: dict) -> dict:
 
 def batched_measurement(pc, synth, scale: float) -> dict:
     """64 independent LR problems (C = 1, eps = 1e-4), bundle size, schedule
-    and chunk length from the autotuner (not timed): one pcdn_solve after
+    and range width (pcdn_opts.chunk) from the autotuner (not timed): one pcdn_solve after
     another ("plain") against one pcdn_solve_batch call; both give the same
     results."""
     import torch
@@ -198,7 +198,7 @@ def batched_measurement(pc, synth, scale: float) -> dict:
     t0 = time.perf_counter()
     tunes = [s.autotune(1.0, 1e-4, "lr", seed=SEED) for s in solvers]
     t_tune = time.perf_counter() - t0
-    # the tuned bundle size, schedule and chunk length of each problem
+    # the tuned bundle size, schedule and range width of each problem
     cfg = [dict(P=t["P"], schedule=t["schedule"], chunk=t["chunk"]) for t in tunes]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
