@@ -498,6 +498,8 @@ def main():
     avg_launch_s = dom_ms / 1e3 / max(dom_n, 1)
     bytes_per_launch = dom_bytes / max(dom_n, 1)
     achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    path_ms = sum(v[0] for v in totals.values())
+    path_gbps = sum(v[2] for v in totals.values()) / (path_ms / 1e3) / 1e9 if path_ms > 0 else 0.0
     line = {
         "metric": METRIC,
         "value": h["value"],
@@ -526,7 +528,11 @@ def main():
                      "frac_of_copy": achieved / cp["copy_GBps"],
                      "measured": "HIP events around each launch on the library's stream in "
                                  "region B (the next steps of the same solve)",
-                     "region_b_ms_per_step": h["region_b_ms_per_step"]},
+                     "region_b_ms_per_step": h["region_b_ms_per_step"],
+                     # the whole path's kernels together: every class's algorithmic
+                     # bytes over every class's event time in region B
+                     "path_alg_GBps": path_gbps,
+                     "path_frac": path_gbps / HBM_PEAK_GBS},
         "kernels": h["kernels"],
         "objective_after": h["objective_after"],
         "subgrad_after": h["subgrad_after"],
