@@ -358,6 +358,8 @@ StopArgs stop_args(pcdn_ctx* c, const Opts& o, const double* w) {
   a.ccol = c->ccol;
   a.srow = c->srow;
   a.spos = c->spos;
+  a.gwc = c->tmp_n;
+  a.n = c->n;
   a.cp = c->cp;
   a.y = c->y;
   a.cache = c->cache;

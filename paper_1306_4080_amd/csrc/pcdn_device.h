@@ -144,6 +144,8 @@ struct StopArgs {
   // nonzeros in row order (row, position in the tile)
   const int32_t* srow;
   const uint16_t* spos;
+  double* gwc;               // with the tiles: n doubles of working storage (the rows'
+  int64_t n;                 //   gradient weights, packed for the tiles' gathers)
 };
 
 // Multi-kernel bundle after the sweep: the bundle's nonzeros in row order

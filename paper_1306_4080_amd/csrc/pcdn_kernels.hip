@@ -1150,6 +1150,15 @@ __global__ __launch_bounds__(kBlock) void k_stop_ranges(StopArgs a) {
 // each at its nonzero's position in LDS; then its wavefronts run the tile's
 // ranges as stop_ranges_body does, reading the weights from LDS.  The sums
 // and their order are those of stop_ranges_body, so are the results.
+// The rows' gradient weights (the first of each row's two) packed into one
+// array for the tiles' gathers.
+__global__ __launch_bounds__(kBlock) void k_pack_gradient_weights(const double2* rw, int64_t n,
+                                                                  double* gwc) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    gwc[i] = rw[i].x;
+}
+
 constexpr int kStopTileThreads = 1024;
 constexpr int kStopTileRounds = 16;
 static_assert(kStopTile == kStopTileThreads * kStopTileRounds, "one weight per thread and round");
@@ -1158,7 +1167,7 @@ __global__ __launch_bounds__(kStopTileThreads) void k_stop_tiles(StopArgs a) {
   __shared__ double lgw[kStopTile];
   const int64_t base = (int64_t)blockIdx.x * kStopTile;
   const int64_t tcount = a.nnz - base < kStopTile ? a.nnz - base : kStopTile;
-  const double* gw = reinterpret_cast<const double*>(a.rw);
+  const double* gw = a.gwc;  // packed: 16 rows a 128-byte line
   {
     int32_t row[kStopTileRounds];
     int32_t pos[kStopTileRounds];
@@ -1172,7 +1181,7 @@ __global__ __launch_bounds__(kStopTileThreads) void k_stop_tiles(StopArgs a) {
 #pragma unroll
     for (int r = 0; r < kStopTileRounds; ++r) {
       const int64_t e = (int64_t)r * kStopTileThreads + threadIdx.x;
-      g[r] = ldz(gw, e < tcount, 2 * (int64_t)row[r], 0.0);
+      g[r] = ldz(gw, e < tcount, (int64_t)row[r], 0.0);
     }
 #pragma unroll
     for (int r = 0; r < kStopTileRounds; ++r) {
@@ -3240,7 +3249,10 @@ int stop_finish_grid(int64_t p) { return grid_for(p, kBlock, 4096); }
 hipError_t launch_stop_sweep(int loss, const StopArgs& a, hipStream_t s) {
   const dim3 g1(stop_ranges_grid(a.nnz)), g2(stop_finish_grid(a.p));
   const dim3 gt((unsigned)((a.nnz + kStopTile - 1) / kStopTile));
-  const bool tiles = a.srow && a.spos;
+  const bool tiles = a.srow && a.spos && a.gwc && a.nnz > 0;
+  if (tiles)
+    hipLaunchKernelGGL(k_pack_gradient_weights, dim3(grid_for(a.n, kBlock, 4096)), dim3(kBlock), 0,
+                       s, a.rw, a.n, a.gwc);
   if (loss == kLogistic) {
     if (a.nnz > 0 && tiles)
       hipLaunchKernelGGL(k_stop_tiles<kLogistic>, gt, dim3(kStopTileThreads), 0, s, a);
